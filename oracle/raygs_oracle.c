@@ -1,0 +1,917 @@
+/*
+ * raygs_oracle.c -- plain, slow FP64 CPU oracle for ray-based Gaussian
+ * splatting ("Hardware-Rasterized Ray-Based Gaussian Splatting", CVPR 2025).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header or constant table with the HIP renderer and must never be used as a
+ * fallback for it.
+ *
+ * What it computes, in the paper's order and notation (every quantity in
+ * double precision; float32 inputs are widened exactly):
+ *   per view, per Gaussian
+ *     mu = W m + t (camera frame, Sec. 3 "Scene representation"),
+ *     Sigma = R_p S^2 R_p^T with R_p = W R(q / |q|), S = diag(exp(l)),
+ *     o = sigmoid(a),
+ *     optional MIP widening and opacity modulation (Sec. 5, eq. 17),
+ *     kappa = -2 log(p_min / o) (eq. 3), skipped when kappa <= 0,
+ *     c^2 = mu^T Sigma^-1 mu (eq. 6), skipped when c^2 <= kappa,
+ *     the 3D quad V_ray = T_ray H(Z_ray) (Sec. 4.1, eqs. 12-15, App. A.1-A.3),
+ *     its pixel bounding box and tile rectangle, the depth key;
+ *   per pixel
+ *     every Gaussian whose box holds the pixel centre, in ascending
+ *     (depth, index) order, with D_ray from its definition (eq. 5),
+ *     omega = o exp(-D/2) (eq. 2), composited front to back (eq. 1).
+ *   backward (not in the paper): the exact adjoint of the above, with the
+ *     derivative of D_ray taken by the envelope theorem at tau (Prop. A.1).
+ *
+ * Readings of points the paper leaves open (shared with the GPU path through
+ * the documented options, not through code):
+ *   p_min = 1/255; alpha = min(omega, alpha_max); a Gaussian contributes iff
+ *   omega >= p_min; compositing stops before a Gaussian whose contribution
+ *   would take the transmittance below t_eps; rays with tau <= 0 get no
+ *   contribution; near-plane culling of centres with mu_z <= near_z; a quad
+ *   with a vertex at z <= 0 bounds the whole view; pixel centres sit at +1/2;
+ *   colour = max(0, SH(view direction) + 0.5); depth key = bits of
+ *   float32(mu_z), ties broken by Gaussian index.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ types */
+typedef struct {
+    double w2c[12]; /* row-major [W | t], world -> camera, OpenCV axes */
+    double fx, fy, cx, cy;
+    int32_t width, height;
+} orc_camera;
+
+typedef struct {
+    double p_min, alpha_max, t_eps, near_z;
+    int32_t mip;
+    double mip_sigma2_px;
+    double background[3];
+    int32_t tile_w, tile_h;
+} orc_options;
+
+typedef struct {
+    const double *means, *log_scales, *quats, *opacity_logits, *sh;
+    int64_t n;
+    int32_t sh_degree;
+} orc_scene;
+
+enum {
+    ORC_VISIBLE = 0,
+    ORC_CULL_INVALID = 1,
+    ORC_CULL_NEAR = 2,
+    ORC_CULL_KAPPA = 3,
+    ORC_CULL_INSIDE = 4,
+    ORC_CULL_OFFSCREEN = 5
+};
+
+enum { /* hazard bits: a decision taken within rounding distance */
+    ORC_HZ_KEY = 1,
+    ORC_HZ_RECT = 2,
+    ORC_HZ_EIGEN = 4,
+    ORC_HZ_CULL = 8,
+    ORC_HZ_FRONT = 16
+};
+
+typedef struct {
+    int32_t cull;     /* ORC_VISIBLE or the reason it was dropped */
+    int32_t hazard;   /* ORC_HZ_* bits */
+    double mu[3];     /* centre, camera frame */
+    double Rp[9];     /* rotation, camera frame, row-major */
+    double s[3];      /* scales (after MIP widening) */
+    double o;         /* opacity (after MIP modulation) */
+    double kappa, c2;
+    double mu_w[3];   /* whitened centre S^-1 R_p^T mu */
+    double b;         /* sqrt(1 - kappa / c^2) */
+    double Rv[9];     /* R_{mu^ <- v}, row-major */
+    double U[4];      /* U_ray = (u0, u1) as columns, row-major 2x2 */
+    double quad[12];  /* 4 vertices x (x, y, z), camera frame */
+    double bbox[4];   /* umin, umax, vmin, vmax of the projected quad */
+    int32_t all_front;
+    int32_t px0, px1, py0, py1; /* covered pixel centres (inclusive) */
+    int32_t tx0, tx1, ty0, ty1; /* covered tiles (inclusive) */
+    uint32_t depth_key;
+    int32_t pad;
+    double rgb[3], rgb_raw[3];
+    double dir[3];    /* unit view direction used for the colour */
+    double dist;      /* |m - camera centre| */
+} orc_splat;
+
+/* --------------------------------------------------------- small helpers */
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* y = M x for a row-major 3x3 M */
+static void mat3_vec(const double *M, const double *x, double *y)
+{
+    for (int r = 0; r < 3; ++r) y[r] = M[3 * r] * x[0] + M[3 * r + 1] * x[1] + M[3 * r + 2] * x[2];
+}
+
+/* y = M^T x */
+static void mat3t_vec(const double *M, const double *x, double *y)
+{
+    for (int c = 0; c < 3; ++c) y[c] = M[c] * x[0] + M[3 + c] * x[1] + M[6 + c] * x[2];
+}
+
+/* C = A B, row-major 3x3 */
+static void mat3_mul(const double *A, const double *B, double *C)
+{
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) C[3 * r + c] = A[3 * r] * B[c] + A[3 * r + 1] * B[3 + c] + A[3 * r + 2] * B[6 + c];
+}
+
+/* Rotation matrix of a unit quaternion (w, x, y, z). */
+static void quat_to_rot(const double *q, double *R)
+{
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+/* ------------------------------------------------ real spherical harmonics
+ * Orthonormal real SH up to degree 3, index k = l^2 + l + m, with the sign
+ * convention common in Gaussian-splatting colour models (Condon-Shortley
+ * phase on the odd-m terms).  Constants are the closed forms of the
+ * normalisation factors. */
+void orc_sh_basis(int degree, const double *d, double *Y, double *dY /* [16][3] or NULL */)
+{
+    const double PI = 3.14159265358979323846;
+    const double c0 = 0.5 / sqrt(PI);
+    const double c1 = 0.5 * sqrt(3.0 / PI);
+    const double c2a = 0.5 * sqrt(15.0 / PI);
+    const double c2b = 0.25 * sqrt(5.0 / PI);
+    const double c2c = 0.25 * sqrt(15.0 / PI);
+    const double c3a = -0.25 * sqrt(35.0 / (2.0 * PI));
+    const double c3b = 0.5 * sqrt(105.0 / PI);
+    const double c3c = -0.25 * sqrt(21.0 / (2.0 * PI));
+    const double c3d = 0.25 * sqrt(7.0 / PI);
+    const double c3e = 0.25 * sqrt(105.0 / PI);
+    double x = d[0], y = d[1], z = d[2];
+    double g[16][3];
+    memset(g, 0, sizeof g);
+    Y[0] = c0;
+    if (degree >= 1) {
+        Y[1] = -c1 * y; g[1][1] = -c1;
+        Y[2] = c1 * z;  g[2][2] = c1;
+        Y[3] = -c1 * x; g[3][0] = -c1;
+    }
+    if (degree >= 2) {
+        Y[4] = c2a * x * y;                     g[4][0] = c2a * y; g[4][1] = c2a * x;
+        Y[5] = -c2a * y * z;                    g[5][1] = -c2a * z; g[5][2] = -c2a * y;
+        Y[6] = c2b * (2 * z * z - x * x - y * y); g[6][0] = -2 * c2b * x; g[6][1] = -2 * c2b * y; g[6][2] = 4 * c2b * z;
+        Y[7] = -c2a * x * z;                    g[7][0] = -c2a * z; g[7][2] = -c2a * x;
+        Y[8] = c2c * (x * x - y * y);           g[8][0] = 2 * c2c * x; g[8][1] = -2 * c2c * y;
+    }
+    if (degree >= 3) {
+        Y[9] = c3a * y * (3 * x * x - y * y);
+        g[9][0] = 6 * c3a * x * y; g[9][1] = c3a * (3 * x * x - 3 * y * y);
+        Y[10] = c3b * x * y * z;
+        g[10][0] = c3b * y * z; g[10][1] = c3b * x * z; g[10][2] = c3b * x * y;
+        Y[11] = c3c * y * (4 * z * z - x * x - y * y);
+        g[11][0] = -2 * c3c * x * y; g[11][1] = c3c * (4 * z * z - x * x - 3 * y * y); g[11][2] = 8 * c3c * y * z;
+        Y[12] = c3d * z * (2 * z * z - 3 * x * x - 3 * y * y);
+        g[12][0] = -6 * c3d * x * z; g[12][1] = -6 * c3d * y * z; g[12][2] = c3d * (6 * z * z - 3 * x * x - 3 * y * y);
+        Y[13] = c3c * x * (4 * z * z - x * x - y * y);
+        g[13][0] = c3c * (4 * z * z - 3 * x * x - y * y); g[13][1] = -2 * c3c * x * y; g[13][2] = 8 * c3c * x * z;
+        Y[14] = c3e * z * (x * x - y * y);
+        g[14][0] = 2 * c3e * x * z; g[14][1] = -2 * c3e * y * z; g[14][2] = c3e * (x * x - y * y);
+        Y[15] = c3a * x * (x * x - 3 * y * y);
+        g[15][0] = c3a * (3 * x * x - 3 * y * y); g[15][1] = -6 * c3a * x * y;
+    }
+    if (dY) {
+        int nk = (degree + 1) * (degree + 1);
+        for (int k = 0; k < nk; ++k)
+            for (int j = 0; j < 3; ++j) dY[3 * k + j] = g[k][j];
+    }
+}
+
+/* ----------------------------------------------------- ray divergence
+ * D_ray(x; mu, Sigma) of eq. (5): tau = x^T Sigma^-1 mu / x^T Sigma^-1 x and
+ * D = (tau x - mu)^T Sigma^-1 (tau x - mu), evaluated in whitened
+ * coordinates (Sigma^-1 = A^T A with A = S^-1 R_p^T).  Returns D; *tau_out
+ * receives tau and e_out (if not NULL) receives tau x - mu. */
+double orc_divergence(const double *mu, const double *Rp, const double *s, const double *x, double *tau_out,
+                      double *e_out)
+{
+    double xl[3], ml[3], xw[3], mw[3];
+    mat3t_vec(Rp, x, xl);
+    mat3t_vec(Rp, mu, ml);
+    for (int k = 0; k < 3; ++k) {
+        xw[k] = xl[k] / s[k];
+        mw[k] = ml[k] / s[k];
+    }
+    double tau = dot3(xw, mw) / dot3(xw, xw);
+    double D = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double e = tau * xw[k] - mw[k];
+        D += e * e;
+    }
+    if (tau_out) *tau_out = tau;
+    if (e_out)
+        for (int k = 0; k < 3; ++k) e_out[k] = tau * x[k] - mu[k];
+    return D;
+}
+
+/* R_{x,y} = 2 (x+y)(x+y)^T / |x+y|^2 - I (App. A.1) */
+static void rot_align(const double *x, const double *y, double *R)
+{
+    double a[3] = {x[0] + y[0], x[1] + y[1], x[2] + y[2]};
+    double n2 = dot3(a, a);
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) R[3 * r + c] = 2.0 * a[r] * a[c] / n2 - (r == c ? 1.0 : 0.0);
+}
+
+/* R_{mu^ <- v}: v = (0,0,1); R_{mu^,v} if mu^.v >= 0, else R_{mu^,-v} P with
+ * P = diag(-1, 1, -1) (App. A.1). */
+void orc_rot_mu_v(const double *muh, double *R)
+{
+    const double v[3] = {0.0, 0.0, 1.0};
+    const double mv[3] = {0.0, 0.0, -1.0};
+    if (muh[2] >= 0.0) {
+        rot_align(muh, v, R);
+    } else {
+        double Rm[9];
+        rot_align(muh, mv, Rm);
+        /* right-multiply by P: negate columns 0 and 2 */
+        for (int r = 0; r < 3; ++r) {
+            R[3 * r + 0] = -Rm[3 * r + 0];
+            R[3 * r + 1] = Rm[3 * r + 1];
+            R[3 * r + 2] = -Rm[3 * r + 2];
+        }
+    }
+}
+
+static int near_integer(double v, double rel)
+{
+    double r = nearbyint(v);
+    return fabs(v - r) <= rel * fmax(1.0, fabs(v));
+}
+
+/* Is the float32 rounding of z decided by rounding noise of size ~tol?  An
+ * exact tie (z exactly on a midpoint) arises only when z was computed without
+ * any rounding, which every implementation then reproduces, so it is not a
+ * hazard. */
+static int depth_key_hazard(double z, double tol)
+{
+    float f = (float)z;
+    float lo = nextafterf(f, 0.0f), hi = nextafterf(f, INFINITY);
+    double mlo = 0.5 * ((double)f + (double)lo), mhi = 0.5 * ((double)f + (double)hi);
+    double dlo = fabs(z - mlo), dhi = fabs(z - mhi);
+    return (dlo > 0.0 && dlo <= tol) || (dhi > 0.0 && dhi <= tol);
+}
+
+/* ------------------------------------------------------ per-Gaussian stage */
+static void preprocess_one(const orc_scene *sc, int64_t i, const orc_camera *cam, const orc_options *opt,
+                           orc_splat *sp)
+{
+    const int64_t n = sc->n;
+    memset(sp, 0, sizeof *sp);
+    sp->cull = ORC_CULL_INVALID;
+    const double *W = cam->w2c;
+    double Wr[9] = {W[0], W[1], W[2], W[4], W[5], W[6], W[8], W[9], W[10]};
+    double t[3] = {W[3], W[7], W[11]};
+
+    double m[3], l[3], q[4], a = sc->opacity_logits[i];
+    for (int k = 0; k < 3; ++k) {
+        m[k] = sc->means[k * n + i];
+        l[k] = sc->log_scales[k * n + i];
+    }
+    for (int k = 0; k < 4; ++k) q[k] = sc->quats[k * n + i];
+    int nk = (sc->sh_degree + 1) * (sc->sh_degree + 1);
+    int finite = isfinite(a);
+    for (int k = 0; k < 3; ++k) finite = finite && isfinite(m[k]) && isfinite(l[k]);
+    for (int k = 0; k < 4; ++k) finite = finite && isfinite(q[k]);
+    for (int k = 0; k < nk * 3; ++k) finite = finite && isfinite(sc->sh[(int64_t)k * n + i]);
+    double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    if (!finite || !(qn > 0.0)) return;
+
+    /* camera-frame centre (Sec. 3 assumes centre and covariance in the camera frame) */
+    double mu[3] = {Wr[0] * m[0] + Wr[1] * m[1] + Wr[2] * m[2] + t[0],
+                    Wr[3] * m[0] + Wr[4] * m[1] + Wr[5] * m[2] + t[1],
+                    Wr[6] * m[0] + Wr[7] * m[1] + Wr[8] * m[2] + t[2]};
+    memcpy(sp->mu, mu, sizeof mu);
+    sp->depth_key = 0;
+    {
+        float fz = (float)mu[2];
+        memcpy(&sp->depth_key, &fz, 4);
+    }
+    if (depth_key_hazard(mu[2], 1e-14 * (fabs(Wr[6] * m[0]) + fabs(Wr[7] * m[1]) + fabs(Wr[8] * m[2]) + fabs(t[2]))))
+        sp->hazard |= ORC_HZ_KEY;
+    if (fabs(mu[2] - opt->near_z) <= 1e-12 * fmax(1.0, fabs(mu[2]))) sp->hazard |= ORC_HZ_CULL;
+    if (!(mu[2] > opt->near_z)) {
+        sp->cull = ORC_CULL_NEAR;
+        return;
+    }
+
+    /* Sigma = R_p S^2 R_p^T with R_p = W R(q^) (Sec. 3) */
+    double qh[4] = {q[0] / qn, q[1] / qn, q[2] / qn, q[3] / qn};
+    double R[9];
+    quat_to_rot(qh, R);
+    mat3_mul(Wr, R, sp->Rp);
+    double s[3] = {exp(l[0]), exp(l[1]), exp(l[2])};
+    double o = 1.0 / (1.0 + exp(-a));
+
+    if (opt->mip) {
+        /* Sec. 5, eq. (17): Sigma^ = Sigma + sigma^2 tau^2 I with a
+         * pixel-invariant tau = |mu| (unit rays) and sigma^2 the pixel area at
+         * unit distance; opacity modulated by sqrt(|Sigma| c^2 / (|Sigma^| c^^2)). */
+        double tb = sqrt(dot3(mu, mu));
+        double sig2 = opt->mip_sigma2_px / (cam->fx * cam->fy);
+        double ml[3];
+        mat3t_vec(sp->Rp, mu, ml);
+        double det = 1.0, deth = 1.0, c2p = 0.0, c2h = 0.0, sh2[3];
+        for (int k = 0; k < 3; ++k) {
+            double s2 = s[k] * s[k];
+            sh2[k] = s2 + sig2 * tb * tb;
+            det *= s2;
+            deth *= sh2[k];
+            c2p += ml[k] * ml[k] / s2;
+            c2h += ml[k] * ml[k] / sh2[k];
+        }
+        o = o * sqrt(det * c2p / (deth * c2h));
+        for (int k = 0; k < 3; ++k) s[k] = sqrt(sh2[k]);
+    }
+    memcpy(sp->s, s, sizeof s);
+    sp->o = o;
+
+    /* kappa = -2 log(p_min / o), eq. (3); skip when kappa <= 0 */
+    double kappa = -2.0 * log(opt->p_min / o);
+    sp->kappa = kappa;
+    if (fabs(kappa) <= 1e-12) sp->hazard |= ORC_HZ_CULL;
+    if (!(kappa > 0.0)) {
+        sp->cull = ORC_CULL_KAPPA;
+        return;
+    }
+
+    /* c^2 = mu^T Sigma^-1 mu, eq. (6); skip when c^2 <= kappa (Prop. A.2) */
+    double ml[3], mw[3];
+    mat3t_vec(sp->Rp, mu, ml);
+    for (int k = 0; k < 3; ++k) mw[k] = ml[k] / s[k];
+    double c2 = dot3(mw, mw);
+    sp->c2 = c2;
+    memcpy(sp->mu_w, mw, sizeof mw);
+    if (fabs(c2 - kappa) <= 1e-12 * c2) sp->hazard |= ORC_HZ_CULL;
+    if (!(c2 > kappa)) {
+        sp->cull = ORC_CULL_INSIDE;
+        return;
+    }
+
+    /* Sec. 4.1: mu^ = S^-1 R_p^T mu / c, b = sqrt(1 - kappa/c^2),
+     * Q = R_p S R_{mu^<-v}, B = Q_{0:2}^T Q_{0:2}. */
+    double c = sqrt(c2);
+    double muh[3] = {mw[0] / c, mw[1] / c, mw[2] / c};
+    double b = sqrt(1.0 - kappa / c2);
+    sp->b = b;
+    orc_rot_mu_v(muh, sp->Rv);
+    double RpS[9];
+    for (int r = 0; r < 3; ++r)
+        for (int cc = 0; cc < 3; ++cc) RpS[3 * r + cc] = sp->Rp[3 * r + cc] * s[cc];
+    double Q[9];
+    mat3_mul(RpS, sp->Rv, Q);
+    double Ba = 0, Bh = 0, Bd = 0;
+    for (int r = 0; r < 3; ++r) {
+        Ba += Q[3 * r] * Q[3 * r];
+        Bh += Q[3 * r] * Q[3 * r + 1];
+        Bd += Q[3 * r + 1] * Q[3 * r + 1];
+    }
+    /* eq. (14): u1 = top eigenvector of the 2x2 B in closed form; u0 is u1
+     * turned 90 degrees anticlockwise.  Near-isotropic B (relative eigen-gap
+     * <= 1e-6) takes u1 = (1, 0). */
+    double mean = 0.5 * (Ba + Bd);
+    double rad = sqrt(0.25 * (Ba - Bd) * (Ba - Bd) + Bh * Bh);
+    double lmax = mean + rad;
+    double gap = 2.0 * rad;
+    double u1[2];
+    if (gap <= 1e-6 * lmax) {
+        u1[0] = 1.0;
+        u1[1] = 0.0;
+    } else {
+        double v1[2] = {Bh, lmax - Ba}, v2[2] = {lmax - Bd, Bh};
+        double n1 = sqrt(v1[0] * v1[0] + v1[1] * v1[1]), n2 = sqrt(v2[0] * v2[0] + v2[1] * v2[1]);
+        if (n1 >= n2) {
+            u1[0] = v1[0] / n1;
+            u1[1] = v1[1] / n1;
+        } else {
+            u1[0] = v2[0] / n2;
+            u1[1] = v2[1] / n2;
+        }
+    }
+    if (gap >= 0.5e-6 * lmax && gap <= 2e-6 * lmax) sp->hazard |= ORC_HZ_EIGEN;
+    double u0[2] = {-u1[1], u1[0]};
+    sp->U[0] = u0[0]; sp->U[1] = u1[0];
+    sp->U[2] = u0[1]; sp->U[3] = u1[1];
+
+    /* eq. (15): V_ray = [Q_{0:2} U_ray, mu] H(Z_ray), Z_ray = (sqrt(kappa)/b) O,
+     * O = [[-1,-1,1,1],[-1,1,1,-1]] (the canonical quad of Sec. 3.3). */
+    const double O[2][4] = {{-1, -1, 1, 1}, {-1, 1, 1, -1}};
+    double hs = sqrt(kappa) / b;
+    double QU[6]; /* 3x2 */
+    for (int r = 0; r < 3; ++r) {
+        QU[2 * r] = Q[3 * r] * u0[0] + Q[3 * r + 1] * u0[1];
+        QU[2 * r + 1] = Q[3 * r] * u1[0] + Q[3 * r + 1] * u1[1];
+    }
+    int all_front = 1;
+    double zmin = INFINITY, zscale = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        double z0 = hs * O[0][k], z1 = hs * O[1][k];
+        for (int r = 0; r < 3; ++r) sp->quad[3 * k + r] = QU[2 * r] * z0 + QU[2 * r + 1] * z1 + mu[r];
+        double vz = sp->quad[3 * k + 2];
+        if (!(vz > 0.0)) all_front = 0;
+        zmin = fmin(zmin, fabs(vz));
+        zscale = fmax(zscale, fabs(mu[2]) + fabs(QU[4] * z0) + fabs(QU[5] * z1));
+    }
+    if (zmin <= 1e-12 * zscale) sp->hazard |= ORC_HZ_FRONT;
+    sp->all_front = all_front;
+
+    /* Bounding box of the projected quad; no near-plane clipping of the quad
+     * (Sec. 4.1): when a vertex lies at z <= 0 the whole view is covered. */
+    int W_ = cam->width, H_ = cam->height;
+    int px0, px1, py0, py1;
+    if (all_front) {
+        double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+        for (int k = 0; k < 4; ++k) {
+            const double *V = &sp->quad[3 * k];
+            double u = cam->fx * V[0] / V[2] + cam->cx;
+            double v = cam->fy * V[1] / V[2] + cam->cy;
+            umin = fmin(umin, u); umax = fmax(umax, u);
+            vmin = fmin(vmin, v); vmax = fmax(vmax, v);
+        }
+        sp->bbox[0] = umin; sp->bbox[1] = umax; sp->bbox[2] = vmin; sp->bbox[3] = vmax;
+        /* pixel x covers centre x + 1/2: the covered centres are those inside the box */
+        double fx0 = ceil(umin - 0.5), fx1 = floor(umax - 0.5);
+        double fy0 = ceil(vmin - 0.5), fy1 = floor(vmax - 0.5);
+        if (near_integer(umin - 0.5, 1e-9) || near_integer(umax - 0.5, 1e-9) || near_integer(vmin - 0.5, 1e-9) ||
+            near_integer(vmax - 0.5, 1e-9))
+            sp->hazard |= ORC_HZ_RECT;
+        px0 = fx0 < 0.0 ? 0 : (fx0 > W_ ? W_ : (int)fx0);
+        px1 = fx1 > W_ - 1 ? W_ - 1 : (fx1 < -1.0 ? -1 : (int)fx1);
+        py0 = fy0 < 0.0 ? 0 : (fy0 > H_ ? H_ : (int)fy0);
+        py1 = fy1 > H_ - 1 ? H_ - 1 : (fy1 < -1.0 ? -1 : (int)fy1);
+    } else {
+        sp->bbox[0] = -INFINITY; sp->bbox[1] = INFINITY; sp->bbox[2] = -INFINITY; sp->bbox[3] = INFINITY;
+        px0 = 0; px1 = W_ - 1; py0 = 0; py1 = H_ - 1;
+    }
+    sp->px0 = px0; sp->px1 = px1; sp->py0 = py0; sp->py1 = py1;
+    if (px0 > px1 || py0 > py1) {
+        sp->cull = ORC_CULL_OFFSCREEN;
+        return;
+    }
+    sp->tx0 = px0 / opt->tile_w; sp->tx1 = px1 / opt->tile_w;
+    sp->ty0 = py0 / opt->tile_h; sp->ty1 = py1 / opt->tile_h;
+
+    /* colour: SH at the unit direction from the camera centre to the mean */
+    double Cw[3]; /* camera centre = -W^T t */
+    mat3t_vec(Wr, t, Cw);
+    double dv[3] = {m[0] + Cw[0], m[1] + Cw[1], m[2] + Cw[2]};
+    double dn = sqrt(dot3(dv, dv));
+    sp->dist = dn;
+    for (int k = 0; k < 3; ++k) sp->dir[k] = dv[k] / dn;
+    double Y[16];
+    orc_sh_basis(sc->sh_degree, sp->dir, Y, NULL);
+    for (int ch = 0; ch < 3; ++ch) {
+        double acc = 0.0;
+        for (int k = 0; k < nk; ++k) acc += Y[k] * sc->sh[((int64_t)k * 3 + ch) * n + i];
+        sp->rgb_raw[ch] = acc + 0.5;
+        sp->rgb[ch] = sp->rgb_raw[ch] > 0.0 ? sp->rgb_raw[ch] : 0.0;
+    }
+    sp->cull = ORC_VISIBLE;
+}
+
+typedef struct {
+    const orc_scene *sc;
+    const orc_camera *cam;
+    const orc_options *opt;
+    orc_splat *out;
+    int64_t begin, end;
+} prep_job;
+
+static void *prep_worker(void *arg)
+{
+    prep_job *j = (prep_job *)arg;
+    for (int64_t i = j->begin; i < j->end; ++i) preprocess_one(j->sc, i, j->cam, j->opt, &j->out[i]);
+    return NULL;
+}
+
+static int clamp_threads(int nthreads)
+{
+    if (nthreads < 1) return 1;
+    return nthreads > 256 ? 256 : nthreads;
+}
+
+int orc_preprocess(const orc_scene *sc, const orc_camera *cam, const orc_options *opt, orc_splat *out, int nthreads)
+{
+    nthreads = clamp_threads(nthreads);
+    pthread_t th[256];
+    prep_job jobs[256];
+    int64_t chunk = (sc->n + nthreads - 1) / nthreads;
+    int used = 0;
+    for (int k = 0; k < nthreads; ++k) {
+        jobs[k] = (prep_job){sc, cam, opt, out, k * chunk, (k + 1) * chunk < sc->n ? (k + 1) * chunk : sc->n};
+        if (jobs[k].begin >= jobs[k].end) break;
+        pthread_create(&th[k], NULL, prep_worker, &jobs[k]);
+        ++used;
+    }
+    for (int k = 0; k < used; ++k) pthread_join(th[k], NULL);
+    return 0;
+}
+
+/* ------------------------------------------------------------- ordering */
+typedef struct {
+    uint32_t key;
+    int64_t idx;
+} key_idx;
+
+static int cmp_key_idx(const void *a, const void *b)
+{
+    const key_idx *x = (const key_idx *)a, *y = (const key_idx *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return x->idx < y->idx ? -1 : (x->idx > y->idx);
+}
+
+/* Visible Gaussians in ascending (depth key, index) order (Sec. 3, eq. 1). */
+static int64_t depth_order(const orc_splat *sp, int64_t n, int64_t *order)
+{
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) m += sp[i].cull == ORC_VISIBLE;
+    key_idx *ki = (key_idx *)malloc(sizeof(key_idx) * (m ? m : 1));
+    m = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (sp[i].cull == ORC_VISIBLE) ki[m++] = (key_idx){sp[i].depth_key, i};
+    qsort(ki, (size_t)m, sizeof(key_idx), cmp_key_idx);
+    for (int64_t k = 0; k < m; ++k) order[k] = ki[k].idx;
+    free(ki);
+    return m;
+}
+
+/* Per-row candidate lists: for each row, the ordered Gaussians whose pixel box
+ * spans it.  A filter that keeps the depth order; no other reordering. */
+typedef struct {
+    int64_t *start; /* [H + 1] */
+    int64_t *items;
+} row_lists;
+
+static void build_rows(const orc_splat *sp, const int64_t *order, int64_t m, int H, row_lists *rl)
+{
+    rl->start = (int64_t *)calloc((size_t)H + 1, sizeof(int64_t));
+    for (int64_t k = 0; k < m; ++k) {
+        const orc_splat *s = &sp[order[k]];
+        for (int y = s->py0; y <= s->py1; ++y) rl->start[y + 1]++;
+    }
+    for (int y = 0; y < H; ++y) rl->start[y + 1] += rl->start[y];
+    rl->items = (int64_t *)malloc(sizeof(int64_t) * (rl->start[H] ? rl->start[H] : 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * ((size_t)H + 1));
+    memcpy(fill, rl->start, sizeof(int64_t) * ((size_t)H + 1));
+    for (int64_t k = 0; k < m; ++k) {
+        const orc_splat *s = &sp[order[k]];
+        for (int y = s->py0; y <= s->py1; ++y) rl->items[fill[y]++] = order[k];
+    }
+    free(fill);
+}
+
+static void free_rows(row_lists *rl)
+{
+    free(rl->start);
+    free(rl->items);
+}
+
+/* Does the ray x hit the 3D quad of splat s in front of the camera?  (The
+ * fragments a rasteriser would shade for this quad.) */
+static int ray_hits_quad(const orc_splat *s, const double *x)
+{
+    double xl[3], xw[3];
+    mat3t_vec(s->Rp, x, xl);
+    for (int k = 0; k < 3; ++k) xw[k] = xl[k] / s->s[k];
+    double den = dot3(xw, s->mu_w);
+    if (!(den > 0.0)) return 0;
+    double tt = s->c2 / den;
+    double r[3] = {tt * xw[0] - s->mu_w[0], tt * xw[1] - s->mu_w[1], tt * xw[2] - s->mu_w[2]};
+    /* plane coordinates in the R_v frame, then in the quad axes U */
+    double p0 = s->Rv[0] * r[0] + s->Rv[3] * r[1] + s->Rv[6] * r[2];
+    double p1 = s->Rv[1] * r[0] + s->Rv[4] * r[1] + s->Rv[7] * r[2];
+    double z0 = s->U[0] * p0 + s->U[2] * p1;
+    double z1 = s->U[1] * p0 + s->U[3] * p1;
+    double hs = sqrt(s->kappa) / s->b;
+    return fabs(z0) <= hs && fabs(z1) <= hs;
+}
+
+/* Margins (relative) inside which a threshold decision is reported as a hazard. */
+#define ORC_MARGIN_OMEGA 1e-4
+#define ORC_MARGIN_T 1e-3
+
+typedef struct {
+    double rgb[3], T;
+    int32_t n_contrib;
+    int32_t hazard;
+    int64_t fragments, in_box, contributions;
+} pixel_result;
+
+/* Composite one pixel (eqs. 1-2) over the candidate list `cand[0..nc)`. */
+static void shade_pixel(const orc_splat *sp, const int64_t *cand, int64_t nc, int px, int py, const orc_camera *cam,
+                        const orc_options *opt, pixel_result *res)
+{
+    double x[3] = {(px + 0.5 - cam->cx) / cam->fx, (py + 0.5 - cam->cy) / cam->fy, 1.0};
+    double T = 1.0, C[3] = {0, 0, 0};
+    int32_t last = 0, hz = 0;
+    int64_t frags = 0, inbox = 0, contrib = 0;
+    int32_t entry = 0;
+    for (int64_t k = 0; k < nc; ++k) {
+        const orc_splat *s = &sp[cand[k]];
+        if (px < s->px0 || px > s->px1 || py < s->py0 || py > s->py1) continue;
+        ++entry;
+        ++inbox;
+        frags += ray_hits_quad(s, x);
+        double tau;
+        double D = orc_divergence(s->mu, s->Rp, s->s, x, &tau, NULL);
+        if (!(tau > 0.0)) continue; /* peak density behind the camera */
+        double w = s->o * exp(-0.5 * D);
+        if (fabs(log(w / opt->p_min)) < ORC_MARGIN_OMEGA) hz = 1;
+        if (!(w >= opt->p_min)) continue;
+        double a = w < opt->alpha_max ? w : opt->alpha_max;
+        double Tn = T * (1.0 - a);
+        if (fabs(log(Tn / opt->t_eps)) < ORC_MARGIN_T) hz = 1;
+        if (Tn < opt->t_eps) break;
+        for (int ch = 0; ch < 3; ++ch) C[ch] += T * a * s->rgb[ch];
+        T = Tn;
+        last = entry;
+        ++contrib;
+    }
+    for (int ch = 0; ch < 3; ++ch) res->rgb[ch] = C[ch] + T * opt->background[ch];
+    res->T = T;
+    res->n_contrib = last;
+    res->hazard = hz;
+    res->fragments = frags;
+    res->in_box = inbox;
+    res->contributions = contrib;
+}
+
+typedef struct {
+    const orc_splat *sp;
+    const row_lists *rl;
+    const orc_camera *cam;
+    const orc_options *opt;
+    int y_begin, y_end, stride, offset;
+    double *rgb, *T;
+    uint8_t *hazard;
+    int32_t *n_contrib;
+    int64_t frags, inbox, contrib;
+} render_job;
+
+static void *render_worker(void *arg)
+{
+    render_job *j = (render_job *)arg;
+    const int W = j->cam->width, H = j->cam->height;
+    for (int y = j->y_begin + j->offset; y < j->y_end; y += j->stride) {
+        const int64_t *cand = j->rl->items + j->rl->start[y];
+        int64_t nc = j->rl->start[y + 1] - j->rl->start[y];
+        for (int x = 0; x < W; ++x) {
+            pixel_result r;
+            shade_pixel(j->sp, cand, nc, x, y, j->cam, j->opt, &r);
+            int64_t p = (int64_t)y * W + x;
+            for (int ch = 0; ch < 3; ++ch) j->rgb[(int64_t)ch * H * W + p] = r.rgb[ch];
+            j->T[p] = r.T;
+            if (j->hazard) j->hazard[p] = (uint8_t)r.hazard;
+            if (j->n_contrib) j->n_contrib[p] = r.n_contrib;
+            j->frags += r.fragments;
+            j->inbox += r.in_box;
+            j->contrib += r.contributions;
+        }
+    }
+    return NULL;
+}
+
+/* Render rows [y_begin, y_end) of one view.  rgb is [3][H][W], T / hazard /
+ * n_contrib are [H][W]; rows outside the range are left untouched.
+ * counters (optional, 5 entries): visible Gaussians, instances (Gaussian-tile
+ * pairs), fragments (pixel centre inside a projected quad), pixel-box pairs,
+ * contributions -- the last three over the rendered rows only. */
+int orc_render(const orc_scene *sc, const orc_camera *cam, const orc_options *opt, int y_begin, int y_end,
+               int nthreads, double *rgb, double *T, uint8_t *hazard, int32_t *n_contrib, int64_t *counters)
+{
+    nthreads = clamp_threads(nthreads);
+    int64_t n = sc->n;
+    orc_splat *sp = (orc_splat *)malloc(sizeof(orc_splat) * (n ? n : 1));
+    orc_preprocess(sc, cam, opt, sp, nthreads);
+    int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (n ? n : 1));
+    int64_t m = depth_order(sp, n, order);
+    row_lists rl;
+    build_rows(sp, order, m, cam->height, &rl);
+    if (y_begin < 0) y_begin = 0;
+    if (y_end > cam->height) y_end = cam->height;
+    pthread_t th[256];
+    render_job jobs[256];
+    for (int k = 0; k < nthreads; ++k) {
+        jobs[k] = (render_job){sp, &rl, cam, opt, y_begin, y_end, nthreads, k, rgb, T, hazard, n_contrib, 0, 0, 0};
+        pthread_create(&th[k], NULL, render_worker, &jobs[k]);
+    }
+    int64_t frags = 0, inbox = 0, contrib = 0;
+    for (int k = 0; k < nthreads; ++k) {
+        pthread_join(th[k], NULL);
+        frags += jobs[k].frags;
+        inbox += jobs[k].inbox;
+        contrib += jobs[k].contrib;
+    }
+    if (counters) {
+        int64_t inst = 0;
+        for (int64_t k = 0; k < m; ++k) {
+            const orc_splat *s = &sp[order[k]];
+            inst += (int64_t)(s->tx1 - s->tx0 + 1) * (s->ty1 - s->ty0 + 1);
+        }
+        counters[0] = m;
+        counters[1] = inst;
+        counters[2] = frags;
+        counters[3] = inbox;
+        counters[4] = contrib;
+    }
+    free_rows(&rl);
+    free(order);
+    free(sp);
+    return 0;
+}
+
+/* Render an arbitrary list of pixels (px[k], py[k]); rgb is [npix][3]. */
+int orc_render_pixels(const orc_scene *sc, const orc_camera *cam, const orc_options *opt, const int32_t *px,
+                      const int32_t *py, int64_t npix, int nthreads, double *rgb, double *T, uint8_t *hazard)
+{
+    int64_t n = sc->n;
+    orc_splat *sp = (orc_splat *)malloc(sizeof(orc_splat) * (n ? n : 1));
+    orc_preprocess(sc, cam, opt, sp, nthreads);
+    int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (n ? n : 1));
+    int64_t m = depth_order(sp, n, order);
+    for (int64_t k = 0; k < npix; ++k) {
+        pixel_result r;
+        shade_pixel(sp, order, m, px[k], py[k], cam, opt, &r);
+        for (int ch = 0; ch < 3; ++ch) rgb[3 * k + ch] = r.rgb[ch];
+        T[k] = r.T;
+        if (hazard) hazard[k] = (uint8_t)r.hazard;
+    }
+    free(order);
+    free(sp);
+    return 0;
+}
+
+/* ------------------------------------------------------------- backward
+ * Gradients of L with respect to every parameter, given dL/dC for each output
+ * pixel (dL_dC is [3][H][W]; pixels whose three entries are zero are skipped).
+ * Results are ADDED into the gradient arrays (same shapes as the inputs).
+ * MIP is not differentiated (returns -1 when opt->mip is set).
+ *
+ * Compositing adjoint of eq. (1): with T_i the transmittance in front of
+ * Gaussian i, dL/d rgb_i = T_i a_i g and
+ *   dL/d a_i = T_i (rgb_i . g) - (sum_{j>i} T_j a_j (rgb_j . g) + T_final (bg . g)) / (1 - a_i).
+ * a = min(omega, alpha_max): the clamp passes no gradient.  omega = o exp(-D/2).
+ * D is the minimum over the ray of the Mahalanobis distance (Prop. A.1), so by
+ * the envelope theorem, with e = tau x - mu:
+ *   dD/dmu = -2 Sigma^-1 e,   dD/dSigma^-1 = e e^T.
+ * Sigma^-1 = R_p diag(s^-2) R_p^T, R_p = W R(q/|q|), s = exp(l), mu = W m + t. */
+typedef struct {
+    double d_mu[3], d_Rp[9], d_l[3], d_o, d_rgb[3];
+} splat_grad;
+
+int orc_backward(const orc_scene *sc, const orc_camera *cam, const orc_options *opt, const double *dL_dC,
+                 double *g_means, double *g_log_scales, double *g_quats, double *g_opacity, double *g_sh)
+{
+    if (opt->mip) return -1;
+    int64_t n = sc->n;
+    const int W = cam->width, H = cam->height;
+    orc_splat *sp = (orc_splat *)malloc(sizeof(orc_splat) * (n ? n : 1));
+    orc_preprocess(sc, cam, opt, sp, 1);
+    int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (n ? n : 1));
+    int64_t m = depth_order(sp, n, order);
+    row_lists rl;
+    build_rows(sp, order, m, H, &rl);
+    splat_grad *gg = (splat_grad *)calloc((size_t)(n ? n : 1), sizeof(splat_grad));
+
+    typedef struct {
+        int64_t idx;
+        double T, a, w, D, tau;
+        int clamped;
+    } contrib_rec;
+    int64_t cap = 1024;
+    contrib_rec *list = (contrib_rec *)malloc(sizeof(contrib_rec) * cap);
+
+    for (int py = 0; py < H; ++py) {
+        const int64_t *cand = rl.items + rl.start[py];
+        int64_t nc = rl.start[py + 1] - rl.start[py];
+        for (int px = 0; px < W; ++px) {
+            int64_t p = (int64_t)py * W + px;
+            double g[3] = {dL_dC[p], dL_dC[(int64_t)H * W + p], dL_dC[2 * (int64_t)H * W + p]};
+            if (g[0] == 0.0 && g[1] == 0.0 && g[2] == 0.0) continue;
+            double x[3] = {(px + 0.5 - cam->cx) / cam->fx, (py + 0.5 - cam->cy) / cam->fy, 1.0};
+            /* forward pass, recording the contributors */
+            double T = 1.0;
+            int64_t nl = 0;
+            for (int64_t k = 0; k < nc; ++k) {
+                const orc_splat *s = &sp[cand[k]];
+                if (px < s->px0 || px > s->px1) continue;
+                double tau;
+                double D = orc_divergence(s->mu, s->Rp, s->s, x, &tau, NULL);
+                if (!(tau > 0.0)) continue;
+                double w = s->o * exp(-0.5 * D);
+                if (!(w >= opt->p_min)) continue;
+                double a = w < opt->alpha_max ? w : opt->alpha_max;
+                double Tn = T * (1.0 - a);
+                if (Tn < opt->t_eps) break;
+                if (nl == cap) {
+                    cap *= 2;
+                    list = (contrib_rec *)realloc(list, sizeof(contrib_rec) * cap);
+                }
+                list[nl++] = (contrib_rec){cand[k], T, a, w, D, tau, !(w < opt->alpha_max)};
+                T = Tn;
+            }
+            /* reverse sweep */
+            double S = T * (opt->background[0] * g[0] + opt->background[1] * g[1] + opt->background[2] * g[2]);
+            for (int64_t k = nl - 1; k >= 0; --k) {
+                const contrib_rec *c = &list[k];
+                const orc_splat *s = &sp[c->idx];
+                splat_grad *G = &gg[c->idx];
+                double rg = s->rgb[0] * g[0] + s->rgb[1] * g[1] + s->rgb[2] * g[2];
+                for (int ch = 0; ch < 3; ++ch) G->d_rgb[ch] += c->T * c->a * g[ch];
+                double dL_da = c->T * rg - S / (1.0 - c->a);
+                S += c->T * c->a * rg;
+                if (c->clamped) continue;
+                double dL_dw = dL_da;
+                G->d_o += dL_dw * c->w / s->o;
+                double dL_dD = -0.5 * c->w * dL_dw;
+                double e[3];
+                orc_divergence(s->mu, s->Rp, s->s, x, NULL, e);
+                double f[3], Pe[3], fs[3];
+                mat3t_vec(s->Rp, e, f); /* f = R_p^T e */
+                for (int k2 = 0; k2 < 3; ++k2) fs[k2] = f[k2] / (s->s[k2] * s->s[k2]);
+                mat3_vec(s->Rp, fs, Pe); /* Sigma^-1 e */
+                for (int k2 = 0; k2 < 3; ++k2) G->d_mu[k2] += dL_dD * (-2.0 * Pe[k2]);
+                /* dD = e^T dSigma^-1 e with dSigma^-1 = dR_p L R_p^T + R_p dL R_p^T + R_p L dR_p^T */
+                for (int r = 0; r < 3; ++r)
+                    for (int cc = 0; cc < 3; ++cc) G->d_Rp[3 * r + cc] += dL_dD * 2.0 * e[r] * fs[cc];
+                for (int k2 = 0; k2 < 3; ++k2) G->d_l[k2] += dL_dD * (-2.0 * f[k2] * f[k2] / (s->s[k2] * s->s[k2]));
+            }
+        }
+    }
+
+    /* chain per Gaussian to the parameters */
+    const double *Wm = cam->w2c;
+    double Wr[9] = {Wm[0], Wm[1], Wm[2], Wm[4], Wm[5], Wm[6], Wm[8], Wm[9], Wm[10]};
+    int nk = (sc->sh_degree + 1) * (sc->sh_degree + 1);
+    for (int64_t i = 0; i < n; ++i) {
+        const orc_splat *s = &sp[i];
+        if (s->cull != ORC_VISIBLE) continue;
+        const splat_grad *G = &gg[i];
+        /* means through mu = W m + t */
+        double dm[3];
+        mat3t_vec(Wr, G->d_mu, dm);
+        /* log-scales (s = exp(l) enters Sigma^-1 only) */
+        for (int k = 0; k < 3; ++k) g_log_scales[k * n + i] += G->d_l[k];
+        /* rotation: dL/dR = W^T dL/dR_p, then the quaternion */
+        double dR[9];
+        for (int r = 0; r < 3; ++r)
+            for (int cc = 0; cc < 3; ++cc)
+                dR[3 * r + cc] = Wr[r] * G->d_Rp[cc] + Wr[3 + r] * G->d_Rp[3 + cc] + Wr[6 + r] * G->d_Rp[6 + cc];
+        double q[4];
+        for (int k = 0; k < 4; ++k) q[k] = sc->quats[k * n + i];
+        double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+        /* partial derivatives of R(w,x,y,z) entry by entry */
+        double dq[4] = {0, 0, 0, 0};
+        const double J[9][4] = {
+            {0, 0, -4 * y, -4 * z},          {-2 * z, 2 * y, 2 * x, -2 * w}, {2 * y, 2 * z, 2 * w, 2 * x},
+            {2 * z, 2 * y, 2 * x, 2 * w},    {0, -4 * x, 0, -4 * z},         {-2 * x, -2 * w, 2 * z, 2 * y},
+            {-2 * y, 2 * z, -2 * w, 2 * x},  {2 * x, 2 * w, 2 * z, 2 * y},   {0, -4 * x, -4 * y, 0}};
+        for (int e = 0; e < 9; ++e)
+            for (int k = 0; k < 4; ++k) dq[k] += dR[e] * J[e][k];
+        double qh[4] = {w, x, y, z};
+        double proj = qh[0] * dq[0] + qh[1] * dq[1] + qh[2] * dq[2] + qh[3] * dq[3];
+        for (int k = 0; k < 4; ++k) g_quats[k * n + i] += (dq[k] - qh[k] * proj) / qn;
+        /* opacity logit */
+        double o = s->o;
+        g_opacity[i] += G->d_o * o * (1.0 - o);
+        /* SH coefficients and the view direction */
+        double Y[16], dY[48];
+        orc_sh_basis(sc->sh_degree, s->dir, Y, dY);
+        double ddir[3] = {0, 0, 0};
+        for (int ch = 0; ch < 3; ++ch) {
+            if (!(s->rgb_raw[ch] > 0.0)) continue;
+            double gc = G->d_rgb[ch];
+            for (int k = 0; k < nk; ++k) {
+                g_sh[((int64_t)k * 3 + ch) * n + i] += Y[k] * gc;
+                double coef = sc->sh[((int64_t)k * 3 + ch) * n + i];
+                for (int j = 0; j < 3; ++j) ddir[j] += gc * coef * dY[3 * k + j];
+            }
+        }
+        double pd = dot3(ddir, s->dir);
+        for (int j = 0; j < 3; ++j) dm[j] += (ddir[j] - s->dir[j] * pd) / s->dist;
+        for (int k = 0; k < 3; ++k) g_means[k * n + i] += dm[k];
+    }
+    free(list);
+    free(gg);
+    free_rows(&rl);
+    free(order);
+    free(sp);
+    return 0;
+}
+
+int orc_splat_size(void) { return (int)sizeof(orc_splat); }

@@ -1,0 +1,67 @@
+"""Pin of the oracle's analytic gradient against FP64 central finite
+differences (h = 1e-6) of the oracle's own forward render, on the 64-Gaussian
+32x32 SH3 subcase.  The loss is linear in the image, L = sum(w * C), so dL/dC = w;
+any loss enters the backward only through dL/dC."""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+
+KEYS = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+def _loss(scene, cam, opts, w):
+    return float((oracle.render(scene, cam, opts, threads=1)["rgb"] * w).sum())
+
+
+def _fd_check(scene, cam, opts, w, h=1e-6, stride=1):
+    base = {k: np.asarray(scene[k], np.float64).copy() for k in KEYS}
+    sc = dict(base, sh_degree=scene["sh_degree"])
+    g = oracle.backward(sc, cam, opts, w)
+    worst = 0.0
+    count = 0
+    for k in KEYS:
+        flat = sc[k].reshape(-1)
+        gflat = g[k].reshape(-1)
+        gmax = np.abs(g[k]).max() + 1e-12
+        for j in range(0, flat.size, stride):
+            v = flat[j]
+            flat[j] = v + h
+            lp = _loss(sc, cam, opts, w)
+            flat[j] = v - h
+            lm = _loss(sc, cam, opts, w)
+            flat[j] = v
+            fd = (lp - lm) / (2 * h)
+            err = abs(fd - gflat[j]) / (abs(gflat[j]) + 1e-3 * gmax)
+            worst = max(worst, err)
+            count += 1
+            assert err < 2e-4, (k, j, fd, gflat[j])
+    return worst, count
+
+
+def test_gradient_matches_central_differences(oracle_lib):
+    scene, cam = scenegen.fd_subcase()
+    opts = scenegen.default_options()
+    out = oracle.render(scene, cam, opts)
+    assert out["hazard"].sum() == 0
+    assert out["counters"]["contributions"] > 1000
+    w = np.random.default_rng(7).normal(0, 1, (3, 32, 32))
+    worst, count = _fd_check(scene, cam, opts, w)
+    assert count == 64 * 59
+
+
+def test_gradient_with_background_and_sparse_pixels(oracle_lib):
+    scene, cam = scenegen.fd_subcase(seed=2003)
+    opts = scenegen.default_options(background=(0.3, 0.1, 0.6))
+    w = np.zeros((3, 32, 32))
+    rng = np.random.default_rng(8)
+    ys, xs = rng.integers(0, 32, 40), rng.integers(0, 32, 40)
+    w[:, ys, xs] = rng.normal(0, 1, (3, 40))
+    _fd_check(scene, cam, opts, w, stride=3)
+
+
+def test_mip_backward_is_rejected(oracle_lib):
+    scene, cam = scenegen.fd_subcase()
+    with pytest.raises(ValueError):
+        oracle.backward(scene, cam, scenegen.default_options(mip=1), np.zeros((3, 32, 32)))

@@ -1,0 +1,516 @@
+"""Pins of the CPU oracle against facts the paper and mathematics fix
+independently of the oracle's own code: brute-force minimisation along rays,
+closed forms, the propositions of the appendix, invariants, an independent
+library for the SH basis, and brute-force rendering of tiny scenes."""
+import math
+
+import numpy as np
+import pytest
+from scipy import special
+
+import oracle
+import scenegen
+
+OPTS = scenegen.default_options()
+
+
+def _rot(rng):
+    a = rng.standard_normal((3, 3))
+    q, r = np.linalg.qr(a)
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] *= -1
+    return q
+
+
+def _sigma_inv(Rp, s):
+    # independent route: invert the covariance R S^2 R^T numerically
+    return np.linalg.inv(Rp @ np.diag(np.asarray(s) ** 2) @ Rp.T)
+
+
+def _brute_min_along_ray(mu, Sinv, x):
+    """min over alpha of (alpha x - mu)^T Sinv (alpha x - mu) by dense sampling
+    plus golden-section refinement (no closed form used)."""
+    f = lambda a: (a * x - mu) @ Sinv @ (a * x - mu)  # noqa: E731
+    scale = np.linalg.norm(mu) / np.linalg.norm(x)
+    grid = np.linspace(-4 * scale, 4 * scale, 20001)
+    vals = np.array([f(a) for a in grid])
+    k = int(np.argmin(vals))
+    lo, hi = grid[max(k - 1, 0)], grid[min(k + 1, len(grid) - 1)]
+    g = (math.sqrt(5) - 1) / 2
+    for _ in range(200):
+        c, d = hi - g * (hi - lo), lo + g * (hi - lo)
+        if f(c) < f(d):
+            hi = d
+        else:
+            lo = c
+    a = 0.5 * (lo + hi)
+    return f(a), a
+
+
+# ----------------------------------------------------------------- D_ray, eq. (5)
+def test_divergence_matches_brute_force_minimum(oracle_lib):
+    """Prop. A.1: tau(x) x is the point of maximum density along the ray and
+    D_ray is the Mahalanobis distance there."""
+    rng = np.random.default_rng(1)
+    for _ in range(40):
+        Rp = _rot(rng)
+        s = np.exp(rng.normal(-1.0, 0.7, 3))
+        mu = rng.normal(0, 1, 3) + np.array([0, 0, 4.0])
+        x = np.array([rng.uniform(-0.6, 0.6), rng.uniform(-0.6, 0.6), 1.0])
+        D, tau, e = oracle.divergence(mu, Rp.reshape(-1), s, x)
+        Db, ab = _brute_min_along_ray(mu, _sigma_inv(Rp, s), x)
+        assert abs(D - Db) <= 1e-9 * max(1.0, Db)
+        assert abs(tau - ab) <= 1e-6 * max(1.0, abs(ab))
+        np.testing.assert_allclose(e, tau * x - mu, rtol=0, atol=1e-12 * np.linalg.norm(mu))
+
+
+def test_divergence_isotropic_closed_form(oracle_lib):
+    """Sigma = s^2 I, unit ray x: D = (|mu|^2 - (x.mu)^2) / s^2."""
+    rng = np.random.default_rng(2)
+    for _ in range(50):
+        s = math.exp(rng.normal(-2, 0.5))
+        mu = rng.normal(0, 1, 3) + [0, 0, 3.0]
+        x = rng.normal(0, 1, 3)
+        x /= np.linalg.norm(x)
+        D, _, _ = oracle.divergence(mu, np.eye(3).reshape(-1), [s, s, s], x)
+        ref = (mu @ mu - (x @ mu) ** 2) / s**2
+        assert abs(D - ref) <= 1e-9 * max(1.0, ref)
+
+
+def test_divergence_on_axis_anisotropic_closed_form(oracle_lib):
+    """mu = (0,0,d), Sigma = diag(sx^2, sy^2, sz^2), x = (px, py, 1):
+    D = d^2 q / (1 + sz^2 q) with q = px^2/sx^2 + py^2/sy^2; tends to the
+    linearised (GS) divergence d^2 q as sz -> 0 (Sec. 3.1)."""
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        d = rng.uniform(1, 10)
+        sx, sy, sz = np.exp(rng.normal(-2, 0.5, 3))
+        px, py = rng.uniform(-0.3, 0.3, 2)
+        q = px**2 / sx**2 + py**2 / sy**2
+        D, _, _ = oracle.divergence([0, 0, d], np.eye(3).reshape(-1), [sx, sy, sz], [px, py, 1.0])
+        ref = d * d * q / (1 + sz * sz * q)
+        assert abs(D - ref) <= 1e-10 * max(1.0, ref)
+    D, _, _ = oracle.divergence([0, 0, 5.0], np.eye(3).reshape(-1), [0.1, 0.2, 1e-9], [0.01, 0.02, 1.0])
+    assert abs(D - 25 * (0.01**2 / 0.01 + 0.02**2 / 0.04)) < 1e-9
+
+
+def test_full_support_when_camera_inside(oracle_lib):
+    """Prop. A.2: c^2 <= kappa implies omega >= p_min on every ray, and the
+    oracle skips such a Gaussian (eq. 6)."""
+    rng = np.random.default_rng(4)
+    mu = np.array([0.1, -0.05, 0.5])
+    s = np.array([0.4, 0.3, 0.5])
+    o = 0.9
+    kappa = -2 * math.log(OPTS["p_min"] / o)
+    c2 = mu @ _sigma_inv(np.eye(3), s) @ mu
+    assert c2 <= kappa
+    for _ in range(200):
+        x = rng.normal(0, 1, 3)
+        D, _, _ = oracle.divergence(mu, np.eye(3).reshape(-1), s, x)
+        assert o * math.exp(-D / 2) >= OPTS["p_min"]
+    scene = dict(means=mu[:, None].astype(np.float32), log_scales=np.log(s)[:, None].astype(np.float32),
+                 quats=np.array([[1.0], [0], [0], [0]], np.float32),
+                 opacity_logits=np.array([math.log(o / (1 - o))], np.float32),
+                 sh=np.zeros((1, 3, 1), np.float32), sh_degree=0)
+    cam = scenegen.pinhole(np.concatenate([np.eye(3), np.zeros((3, 1))], 1), 16, 16, 60)
+    sp = oracle.preprocess(scene, cam, OPTS)
+    assert sp["cull"][0] == oracle.CULL["inside"]
+
+
+# ------------------------------------------------------- quad of Sec. 4.1 / App. A
+def _visible_splats(seed, n=200):
+    sc = scenegen.tiny_scene(seed, n, sh_degree=0, log_scale_mean=-2.5, log_scale_std=0.8)
+    cam = scenegen.pinhole(scenegen.look_at((0, 0, -3.5)), 96, 80, 70)
+    sp = oracle.preprocess(sc, cam, OPTS)
+    return sc, cam, sp[sp["cull"] == 0]
+
+
+def test_rotation_aligning_v_to_mu_hat(oracle_lib):
+    """App. A.1: R v = mu^, R in SO(3), for mu^_z >= 0 and < 0 (incl. mu^ = -v)."""
+    rng = np.random.default_rng(5)
+    cases = [rng.normal(0, 1, 3) for _ in range(100)] + [np.array([0, 0, -1.0]), np.array([0, 0, 1.0])]
+    for m in cases:
+        m = m / np.linalg.norm(m)
+        R = oracle.rot_mu_v(m)
+        np.testing.assert_allclose(R @ [0, 0, 1.0], m, atol=1e-14)
+        np.testing.assert_allclose(R @ R.T, np.eye(3), atol=1e-14)
+        assert abs(np.linalg.det(R) - 1) < 1e-13
+
+
+def test_quad_geometry_identities(oracle_lib):
+    """eq. (8) / Prop. A.5: points e = Phi^-1(u) of the ellipse satisfy
+    e^T Sinv e = e^T Sinv mu = c^2 - kappa, tau(e) = 1 (Prop. A.4) and
+    D(e) = kappa.  App. A.3: V_ray = c^2/(c^2-kappa) Phi^-1(U O).  eq. (14):
+    u1 is the top eigenvector of B.  The quad is a rectangle on the plane
+    p^T Sinv mu = c^2."""
+    O = np.array([[-1, -1, 1, 1], [-1, 1, 1, -1]], float)
+    for seed in (6, 7):
+        _, _, sp = _visible_splats(seed)
+        assert len(sp) > 50
+        for r in sp:
+            Rp, s, mu = r["Rp"].reshape(3, 3), r["s"], r["mu"]
+            Sinv = _sigma_inv(Rp, s)
+            c2 = mu @ Sinv @ mu
+            kappa = r["kappa"]
+            assert abs(c2 - r["c2"]) <= 1e-10 * c2
+            c = math.sqrt(c2)
+            a = math.sqrt(kappa / (c2 - kappa))
+            Q = Rp @ np.diag(s) @ r["Rv"].reshape(3, 3)
+            phi_inv = lambda u: (c2 - kappa) / c * Q @ np.array([a * u[0], a * u[1], 1.0])  # noqa: E731
+            for th in np.linspace(0, 2 * math.pi, 7):
+                e = phi_inv([math.cos(th), math.sin(th)])
+                assert abs(e @ Sinv @ e - (c2 - kappa)) <= 1e-8 * c2
+                assert abs(e @ Sinv @ mu - (c2 - kappa)) <= 1e-8 * c2
+                D, tau, _ = oracle.divergence(mu, Rp.reshape(-1), s, e)
+                assert abs(tau - 1) <= 1e-9
+                assert abs(D - kappa) <= 1e-7 * max(1, kappa)
+            U = r["U"].reshape(2, 2)
+            B = Q[:, :2].T @ Q[:, :2]
+            w, v = np.linalg.eigh(B)
+            if w[1] - w[0] > 1e-5 * w[1]:
+                assert abs(abs(U[:, 1] @ v[:, 1]) - 1) < 1e-9
+            assert abs(U[:, 0] @ U[:, 1]) < 1e-14
+            V = r["quad"].reshape(4, 3).T
+            uo = U @ O
+            # App. A.3: V_ray = c^2 / (c^2 - kappa) * Phi^-1(U O), column by column
+            Vref = np.stack([c2 / (c2 - kappa) * phi_inv(uo[:, k]) for k in range(4)], 1)
+            np.testing.assert_allclose(V, Vref, atol=1e-9 * np.abs(Vref).max())
+            for k in range(4):
+                assert abs(V[:, k] @ Sinv @ mu - c2) <= 1e-8 * c2
+            e01, e12 = V[:, 1] - V[:, 0], V[:, 2] - V[:, 1]
+            assert abs(e01 @ e12) <= 1e-9 * (e01 @ e01 + e12 @ e12)
+
+
+def test_isotropic_on_axis_worked_example(oracle_lib):
+    """Worked example (derived from Sec. 4.1, stored in tests/golden): an
+    isotropic Gaussian on the optical axis; its support radius in pixels,
+    f * tan(asin(s sqrt(kappa) / d)), equals the half-side of the projected
+    quad: the support disk is inscribed in the quad."""
+    import os
+
+    golden = {}
+    path = os.path.join(os.path.dirname(__file__), "golden", "isotropic_on_axis.txt")
+    for line in open(path):
+        line = line.split("#")[0].strip()
+        if line:
+            k, v = line.split("=")
+            golden[k.strip()] = float(v)
+    s, d, o, W = golden["s"], golden["d"], golden["o"], int(golden["width"])
+    cam = scenegen.pinhole(np.concatenate([np.eye(3), np.zeros((3, 1))], 1), W, W, golden["fov_deg"])
+    scene = dict(means=np.array([[0], [0], [d]], np.float32), log_scales=np.full((3, 1), math.log(s), np.float32),
+                 quats=np.array([[1.0], [0], [0], [0]], np.float32),
+                 opacity_logits=np.array([math.log(o / (1 - o))], np.float32),
+                 sh=np.zeros((1, 3, 1), np.float32), sh_degree=0)
+    sp = oracle.preprocess(scene, cam, OPTS)[0]
+    half = 0.5 * (sp["bbox"][1] - sp["bbox"][0])
+    s32, d32, o32 = float(np.float32(s)), float(np.float32(d)), 1 / (1 + math.exp(-float(np.float32(math.log(o / (1 - o))))))
+    kappa = 2 * math.log(o32 / OPTS["p_min"])
+    r = cam["fx"] * math.tan(math.asin(math.exp(float(np.float32(math.log(s)))) * math.sqrt(kappa) / d32))
+    assert abs(half - r) < 1e-9
+    assert abs(half - golden["radius_px"]) < 5e-4
+    # brute force: largest pixel radius along +u with omega >= p_min
+    rr = np.linspace(0, 2 * r, 200001)
+    xs = np.stack([rr / cam["fx"], 0 * rr, 1 + 0 * rr], 1)
+    Dv = np.array([oracle.divergence([0, 0, d32], np.eye(3).reshape(-1), [math.exp(float(np.float32(math.log(s))))] * 3, x)[0] for x in xs[::50]])
+    inside = rr[::50][o32 * np.exp(-Dv / 2) >= OPTS["p_min"]]
+    assert abs(inside.max() - r) < 2 * (rr[50] - rr[0])
+
+
+def test_quad_encloses_support(oracle_lib):
+    """Every pixel centre with omega >= p_min lies inside its Gaussian's
+    projected quad and pixel box (Sec. 4.1); brute force over all pixels with
+    an independent D (c^2 - L^2/Q from a numerically inverted covariance)."""
+    for seed in (8, 9, 10):
+        sc, cam, sp = _visible_splats(seed, 300)
+        H, W = cam["height"], cam["width"]
+        ys, xs = np.mgrid[0:H, 0:W]
+        rays = np.stack([(xs + 0.5 - cam["cx"]) / cam["fx"], (ys + 0.5 - cam["cy"]) / cam["fy"], np.ones_like(xs, float)], -1)
+        hits = 0
+        for r in sp:
+            Sinv = _sigma_inv(r["Rp"].reshape(3, 3), r["s"])
+            L = rays @ (Sinv @ r["mu"])
+            Qd = np.einsum("hwi,ij,hwj->hw", rays, Sinv, rays)
+            D = r["c2"] - L * L / Qd
+            sup = (r["o"] * np.exp(-D / 2) >= OPTS["p_min"] * (1 + 1e-9)) & (L > 0)
+            if not sup.any():
+                continue
+            hits += 1
+            py, px = np.nonzero(sup)
+            assert px.min() >= r["px0"] and px.max() <= r["px1"] and py.min() >= r["py0"] and py.max() <= r["py1"]
+            if r["all_front"]:
+                V = r["quad"].reshape(4, 3)
+                P = np.stack([cam["fx"] * V[:, 0] / V[:, 2] + cam["cx"], cam["fy"] * V[:, 1] / V[:, 2] + cam["cy"]], 1)
+                pts = np.stack([px + 0.5, py + 0.5], 1)
+                sgn = []
+                for k in range(4):
+                    a, b = P[k], P[(k + 1) % 4]
+                    sgn.append((b[0] - a[0]) * (pts[:, 1] - a[1]) - (b[1] - a[1]) * (pts[:, 0] - a[0]))
+                sgn = np.stack(sgn, 1)
+                tol = 1e-9 * np.abs(sgn).max()
+                assert np.all((sgn >= -tol).all(1) | (sgn <= tol).all(1))
+        assert hits > 30
+
+
+# --------------------------------------------------------- compositing, eq. (1)
+def _one_gaussian_scene(mus, scales, opac, rgbs):
+    n = len(mus)
+    sh = np.zeros((1, 3, n))
+    sh[0] = (np.asarray(rgbs, float).T - 0.5) * 2 * math.sqrt(math.pi)
+    return dict(means=np.asarray(mus, np.float32).T.copy(), log_scales=np.log(np.asarray(scales, float)).T.astype(np.float32).copy(),
+                quats=np.tile(np.array([[1.0], [0], [0], [0]], np.float32), (1, n)),
+                opacity_logits=np.array([math.log(o / (1 - o)) for o in opac], np.float32), sh=sh.astype(np.float32), sh_degree=0)
+
+
+def _ident_cam(W=32, H=32, fov=60):
+    return scenegen.pinhole(np.concatenate([np.eye(3), np.zeros((3, 1))], 1), W, H, fov)
+
+
+def test_compositing_closed_forms(oracle_lib):
+    cam = _ident_cam()
+    px, py = 16, 16
+    x = np.array([(px + 0.5 - cam["cx"]) / cam["fx"], (py + 0.5 - cam["cy"]) / cam["fy"], 1.0])
+
+    def alpha(mu, s, o):
+        xn = x / np.linalg.norm(x)
+        D = (mu @ mu - (xn @ mu) ** 2) / s**2
+        return min(o * math.exp(-D / 2), OPTS["alpha_max"])
+
+    f32 = lambda v: float(np.float32(v))  # noqa: E731
+    m1, m2 = np.array([0.0, 0.0, 3.0]), np.array([0.02, -0.01, 5.0])
+    s1, s2 = 0.2, 0.3
+    sc = _one_gaussian_scene([m1], [[s1] * 3], [0.7], [[0.2, 0.5, 0.9]])
+    out = oracle.render(sc, cam, OPTS)
+    o1 = 1 / (1 + math.exp(-f32(math.log(0.7 / 0.3))))
+    rgb1 = np.float32((np.array([0.2, 0.5, 0.9]) - 0.5) * 2 * math.sqrt(math.pi)).astype(float) / (2 * math.sqrt(math.pi)) + 0.5
+    a1 = alpha(m1, math.exp(f32(math.log(s1))), o1)
+    np.testing.assert_allclose(out["rgb"][:, py, px], a1 * rgb1, atol=1e-12)
+    assert abs(out["T"][py, px] - (1 - a1)) < 1e-12
+    sc = _one_gaussian_scene([m2, m1], [[s2] * 3, [s1] * 3], [0.6, 0.7], [[1, 0, 0], [0.2, 0.5, 0.9]])
+    out = oracle.render(sc, cam, OPTS)
+    o2 = 1 / (1 + math.exp(-f32(math.log(0.6 / 0.4))))
+    a2 = alpha(np.array([f32(v) for v in m2]), math.exp(f32(math.log(s2))), o2)
+    rgb2 = np.float32((np.array([1.0, 0, 0]) - 0.5) * 2 * math.sqrt(math.pi)).astype(float) / (2 * math.sqrt(math.pi)) + 0.5
+    np.testing.assert_allclose(out["rgb"][:, py, px], a1 * rgb1 + (1 - a1) * a2 * rgb2, atol=1e-12)
+    # an opaque front Gaussian (alpha clamped at alpha_max) leaks at most 1 - alpha_max
+    sc = _one_gaussian_scene([m1, m2], [[0.5] * 3, [s2] * 3], [0.999999, 0.9], [[0, 0, 0], [1, 1, 1]])
+    out = oracle.render(sc, cam, OPTS)
+    assert out["rgb"][:, py, px].max() <= 1 - OPTS["alpha_max"] + 1e-12
+
+
+def test_order_is_by_depth_not_input(oracle_lib):
+    """eq. (1): permuting the input (distinct depths) leaves the image unchanged."""
+    sc = scenegen.tiny_scene(11, 60, sh_degree=2)
+    cam = scenegen.pinhole(scenegen.look_at((0.3, 0.2, -3.0)), 40, 36, 60)
+    a = oracle.render(sc, cam, OPTS)
+    perm = np.random.default_rng(0).permutation(60)
+    sc2 = {k: (v[..., perm] if isinstance(v, np.ndarray) else v) for k, v in sc.items()}
+    b = oracle.render(sc2, cam, OPTS)
+    assert np.array_equal(a["rgb"], b["rgb"]) and np.array_equal(a["T"], b["T"])
+
+
+def _brute_render(sc, cam, opts):
+    """All pixels x all Gaussians, no boxes: independent rendering of eq. (1)-(2)."""
+    n = sc["opacity_logits"].shape[0]
+    W_ = np.asarray(cam["w2c"])
+    H, Wd = cam["height"], cam["width"]
+    m = sc["means"].astype(np.float64).T
+    mu = m @ W_[:, :3].T + W_[:, 3]
+    q = sc["quats"].astype(np.float64).T
+    s = np.exp(sc["log_scales"].astype(np.float64).T)
+    o = 1 / (1 + np.exp(-sc["opacity_logits"].astype(np.float64)))
+    Cw = -W_[:, :3].T @ W_[:, 3]
+    ys, xs = np.mgrid[0:H, 0:Wd]
+    rays = np.stack([(xs + 0.5 - cam["cx"]) / cam["fx"], (ys + 0.5 - cam["cy"]) / cam["fy"], np.ones((H, Wd))], -1)
+    keys = np.array([np.float32(z).view(np.uint32) for z in mu[:, 2]])
+    order = sorted(range(n), key=lambda i: (keys[i], i))
+    C = np.zeros((H, Wd, 3))
+    T = np.ones((H, Wd))
+    alive = np.ones((H, Wd), bool)
+    deg = sc["sh_degree"]
+    for i in order:
+        qn = q[i] / np.linalg.norm(q[i])
+        w, x, y, z = qn
+        R = np.array([[w * w + x * x - y * y - z * z, 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                      [2 * (x * y + w * z), w * w - x * x + y * y - z * z, 2 * (y * z - w * x)],
+                      [2 * (x * z - w * y), 2 * (y * z + w * x), w * w - x * x - y * y + z * z]])
+        Rp = W_[:, :3] @ R
+        Sinv = np.linalg.inv(Rp @ np.diag(s[i] ** 2) @ Rp.T)
+        if mu[i, 2] <= opts["near_z"]:
+            continue
+        kappa = -2 * math.log(opts["p_min"] / o[i])
+        if kappa <= 0 or mu[i] @ Sinv @ mu[i] <= kappa:
+            continue
+        L = rays @ (Sinv @ mu[i])
+        Qd = np.einsum("hwi,ij,hwj->hw", rays, Sinv, rays)
+        tau = L / Qd
+        e = tau[..., None] * rays - mu[i]
+        D = np.einsum("hwi,ij,hwj->hw", e, Sinv, e)
+        om = o[i] * np.exp(-D / 2)
+        take = alive & (tau > 0) & (om >= opts["p_min"])
+        a = np.minimum(om, opts["alpha_max"])
+        Tn = T * (1 - a)
+        stop = take & (Tn < opts["t_eps"])
+        alive &= ~stop
+        take &= ~stop
+        d = m[i] - Cw
+        d /= np.linalg.norm(d)
+        Y = _scipy_real_sh(deg, d)
+        col = np.maximum(Y @ sc["sh"][:, :, i].astype(np.float64) + 0.5, 0)
+        C[take] += (T[take] * a[take])[:, None] * col
+        T = np.where(take, Tn, T)
+    return C.transpose(2, 0, 1) + T * np.asarray(opts["background"])[:, None, None], T
+
+
+def test_brute_force_rendering_tiny_scenes(oracle_lib):
+    for seed, deg, eye in ((12, 0, (0, 0, -3.0)), (13, 3, (0.5, 0.4, -2.5)), (14, 1, (-0.2, 1.0, -2.2))):
+        sc = scenegen.tiny_scene(seed, 40, sh_degree=deg, log_scale_mean=-2.2, log_scale_std=0.6)
+        cam = scenegen.pinhole(scenegen.look_at(eye), 30, 26, 65)
+        opts = scenegen.default_options(tile_w=8, tile_h=8, background=(0.1, 0.2, 0.3))
+        out = oracle.render(sc, cam, opts)
+        C, T = _brute_render(sc, cam, opts)
+        np.testing.assert_allclose(out["rgb"], C, atol=1e-10)
+        np.testing.assert_allclose(out["T"], T, atol=1e-12)
+
+
+# ---------------------------------------------------------------- SH basis
+def _scipy_real_sh(deg, d):
+    """Real SH from scipy's complex Y_l^m (which carries the Condon-Shortley
+    phase): for m > 0 sqrt2 (-1)^m Re Y_l^m, m < 0 sqrt2 (-1)^m Im Y_l^|m|;
+    the colour-model convention used here is that basis times (-1)^m."""
+    x, y, z = d
+    theta = math.acos(max(-1.0, min(1.0, z)))
+    phi = math.atan2(y, x)
+    out = []
+    for l in range(deg + 1):
+        for m in range(-l, l + 1):
+            Y = special.sph_harm_y(l, abs(m), theta, phi)
+            if m > 0:
+                v = math.sqrt(2) * (-1) ** m * Y.real
+            elif m < 0:
+                v = math.sqrt(2) * (-1) ** m * Y.imag
+            else:
+                v = Y.real
+            out.append(v * (-1) ** m)
+    return np.array(out)
+
+
+def test_sh_basis_against_scipy(oracle_lib):
+    rng = np.random.default_rng(15)
+    for _ in range(50):
+        d = rng.normal(0, 1, 3)
+        d /= np.linalg.norm(d)
+        Y, _ = oracle.sh_basis(3, d)
+        np.testing.assert_allclose(Y, _scipy_real_sh(3, d), atol=1e-12)
+
+
+def test_sh_basis_orthonormal_and_gradient(oracle_lib):
+    # Lebedev-free check: Monte Carlo with many points gives orthonormality to ~1e-2
+    rng = np.random.default_rng(16)
+    d = rng.normal(0, 1, (40000, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    Ys = np.array([oracle.sh_basis(3, v)[0] for v in d[:8000]])
+    G = 4 * math.pi * Ys.T @ Ys / len(Ys)
+    assert np.abs(G - np.eye(16)).max() < 0.12
+    for v in d[:20]:
+        Y, dY = oracle.sh_basis(3, v)
+        for j in range(3):
+            h = np.zeros(3)
+            h[j] = 1e-6
+            fd = (oracle.sh_basis(3, v + h)[0] - oracle.sh_basis(3, v - h)[0]) / 2e-6
+            np.testing.assert_allclose(dY[:, j], fd, atol=1e-8)
+
+
+# --------------------------------------------------------- binning and sort
+def test_tile_lists_brute_force(oracle_lib):
+    sc = scenegen.tiny_scene(17, 150, sh_degree=0, log_scale_mean=-2.5, log_scale_std=0.7)
+    cam = scenegen.pinhole(scenegen.look_at((0.1, -0.2, -3.0)), 53, 41, 60)
+    opts = scenegen.default_options(tile_w=16, tile_h=8)
+    sp = oracle.preprocess(sc, cam, opts)
+    tiles, keys, idx = oracle.tile_lists(sp, cam, opts)
+    tx_n, ty_n = -(-53 // 16), -(-41 // 8)
+    ref = []
+    for ty in range(ty_n):
+        for tx in range(tx_n):
+            xa, xb, ya, yb = tx * 16, min(53, tx * 16 + 16) - 1, ty * 8, min(41, ty * 8 + 8) - 1
+            here = [i for i in range(150) if sp["cull"][i] == 0 and sp["px0"][i] <= xb and sp["px1"][i] >= xa
+                    and sp["py0"][i] <= yb and sp["py1"][i] >= ya]
+            here.sort(key=lambda i: (float(np.float32(sp["mu"][i][2])), i))
+            ref += [(ty * tx_n + tx, i) for i in here]
+    assert list(zip(tiles.tolist(), idx.tolist())) == ref
+    assert np.array_equal(keys, np.array([np.float32(sp["mu"][i][2]).view(np.uint32) for i in idx]))
+
+
+def test_pixel_box_is_centres_inside_bbox(oracle_lib):
+    _, cam, sp = _visible_splats(18, 300)
+    for r in sp[sp["all_front"] == 1]:
+        xs = np.arange(cam["width"]) + 0.5
+        inside = np.nonzero((xs >= r["bbox"][0]) & (xs <= r["bbox"][1]))[0]
+        assert inside.min() == r["px0"] and inside.max() == r["px1"]
+
+
+# --------------------------------------------------------------------- culls
+def test_culls_and_degenerate_inputs(oracle_lib):
+    cam = _ident_cam()
+    mus = [[0, 0, 0.1], [0, 0, -2], [0, 0, 3], [0, 0, 3], [0, 0, 3], [0, 0, 3], [5, 0, 3]]
+    sc = _one_gaussian_scene(mus, [[0.1] * 3] * 7, [0.5, 0.5, 0.5, 0.002, 0.5, 0.5, 0.5], [[0.5] * 3] * 7)
+    sc["quats"][:, 4] = 0.0
+    sc["means"][0, 5] = np.nan
+    sp = oracle.preprocess(sc, cam, OPTS)
+    C = oracle.CULL
+    assert list(sp["cull"]) == [C["near"], C["near"], C["visible"], C["kappa"], C["invalid"], C["invalid"], C["offscreen"]]
+
+
+def test_quad_crossing_camera_plane_covers_view(oracle_lib):
+    """A large Gaussian just beyond the near plane whose quad crosses z <= 0
+    bounds the whole view (no near-plane clipping, Sec. 4.1); the image still
+    matches brute force."""
+    cam = _ident_cam(24, 20, 90)
+    sc = _one_gaussian_scene([[0.3, 0.1, 0.6], [0, 0, 2.0]], [[0.05, 0.5, 0.05], [0.2] * 3], [0.8, 0.6], [[1, 0, 0], [0, 1, 0]])
+    sc["quats"][:, 0] = np.array([0.9, 0.3, 0.2, 0.1], np.float32)
+    sp = oracle.preprocess(sc, cam, OPTS)
+    assert sp["cull"][0] == 0 and sp["all_front"][0] == 0
+    assert (sp["px0"][0], sp["px1"][0], sp["py0"][0], sp["py1"][0]) == (0, 23, 0, 19)
+    out = oracle.render(sc, cam, OPTS)
+    C, T = _brute_render(sc, cam, OPTS)
+    np.testing.assert_allclose(out["rgb"], C, atol=1e-10)
+
+
+# ----------------------------------------------------------------- MIP, eq. (17)
+def test_mip_zero_sigma_is_plain(oracle_lib):
+    sc = scenegen.tiny_scene(19, 80, sh_degree=1)
+    cam = scenegen.pinhole(scenegen.look_at((0, 0, -3)), 40, 40, 60)
+    a = oracle.render(sc, cam, scenegen.default_options(mip=0))
+    b = oracle.render(sc, cam, scenegen.default_options(mip=1, mip_sigma2_px=0.0))
+    assert np.array_equal(a["rgb"], b["rgb"])
+
+
+def test_mip_modulation_matches_determinant_form(oracle_lib):
+    """Opacity after MIP = o sqrt(|Sigma| c^2 / (|Sigma^| c^^2)) with
+    Sigma^ = Sigma + sigma^2 |mu|^2 I (eq. 17, pixel-invariant tau = |mu|);
+    for an isotropic Gaussian this is the area ratio s^2 / (s^2 + sigma^2 |mu|^2)."""
+    sc = scenegen.tiny_scene(20, 100, sh_degree=0, log_scale_mean=-4.0, log_scale_std=1.0)
+    cam = scenegen.pinhole(scenegen.look_at((0, 0, -3)), 64, 64, 60)
+    opts = scenegen.default_options(mip=1)
+    plain = oracle.preprocess(sc, cam, scenegen.default_options())
+    mip = oracle.preprocess(sc, cam, opts)
+    sig2 = opts["mip_sigma2_px"] / (cam["fx"] * cam["fy"])
+    checked = 0
+    for p, m in zip(plain, mip):
+        if p["cull"] == 1 or p["cull"] == 2:
+            continue
+        Sig = p["Rp"].reshape(3, 3) @ np.diag(p["s"] ** 2) @ p["Rp"].reshape(3, 3).T
+        Sh = Sig + sig2 * (p["mu"] @ p["mu"]) * np.eye(3)
+        c2 = p["mu"] @ np.linalg.solve(Sig, p["mu"])
+        ch2 = p["mu"] @ np.linalg.solve(Sh, p["mu"])
+        ref = p["o"] * math.sqrt(np.linalg.det(Sig) * c2 / (np.linalg.det(Sh) * ch2))
+        assert abs(m["o"] - ref) <= 1e-9 * ref
+        np.testing.assert_allclose(m["s"] ** 2, p["s"] ** 2 + sig2 * (p["mu"] @ p["mu"]), rtol=1e-12)
+        checked += 1
+    assert checked > 50
+    iso = _one_gaussian_scene([[0.1, 0.0, 4.0]], [[0.01] * 3], [0.8], [[1, 1, 1]])
+    p = oracle.preprocess(iso, _ident_cam(64, 64), scenegen.default_options())[0]
+    m = oracle.preprocess(iso, _ident_cam(64, 64), opts)[0]
+    f = _ident_cam(64, 64)["fx"]
+    s2 = p["s"][0] ** 2
+    assert abs(m["o"] / p["o"] - s2 / (s2 + opts["mip_sigma2_px"] / f**2 * (p["mu"] @ p["mu"]))) < 1e-12
