@@ -1,0 +1,232 @@
+/*
+ * raygs.h -- C ABI of the MI355X (gfx950) ray-based Gaussian splatting
+ * renderer.
+ *
+ * The method is that of "Hardware-Rasterized Ray-Based Gaussian Splatting"
+ * (Rota Bulo et al., CVPR 2025):
+ *   - a scene is a set of 3D Gaussians (centre, covariance R S^2 R^T, prior
+ *     opacity, colour features) and an image is, per pixel ray x, the front to
+ *     back composition of the rendered opacities (Sec. 3, eqs. 1-2);
+ *   - the rendered opacity uses the ray-based divergence D_ray, the
+ *     Mahalanobis distance of the point of maximum density along the ray
+ *     (Sec. 3.2, eq. 5);
+ *   - each Gaussian's screen support is bounded by the projection of the
+ *     smallest enclosing 3D quad of Sec. 4.1 (eqs. 12-15, App. A.1-A.3), and
+ *     D_ray is evaluated per pixel from the quad-local coordinate of the ray's
+ *     hit on the quad plane, D = (c^-2 + |zeta|^-2)^-1 (Sec. 4.2, eq. 16);
+ *   - optionally, the approximate MIP anti-aliasing of Sec. 5 (eq. 17).
+ * The paper's fixed-function rasteriser and blender are replaced by compute
+ * kernels: tile binning, a stable radix sort, and a persistent per-tile
+ * compositing kernel.  Multi-view batching and the backward pass are
+ * extensions; the paper has neither.
+ *
+ * Conventions shared by every entry point
+ *   - Every pointer named "device" is memory on the context's GPU; the caller
+ *     owns it (allocates, frees) and the library never keeps it past a call,
+ *     except that a plan remembers the pointers it was captured with.
+ *   - Gaussians are structure-of-arrays float32 planes of length n:
+ *       means[3][n] (world), log_scales[3][n] (s = exp), quats[4][n] as
+ *       (w, x, y, z) (normalised inside), opacity_logits[n] (o = sigmoid),
+ *       sh[(d+1)^2][3][n] with d = sh_degree in 0..3, real spherical-harmonic
+ *       coefficients indexed k = l^2 + l + m; colour = max(0, SH(dir) + 0.5)
+ *       with dir the unit vector from the camera centre to the mean.
+ *   - Cameras are pinhole, OpenCV axes (x right, y down, z forward), host
+ *     memory, double precision: world_to_cam is row-major [R | t] (3x4); a
+ *     pixel (x, y) is the ray through ((x + 1/2 - cx)/fx, (y + 1/2 - cy)/fy, 1).
+ *   - Images are float32, planar: rgb[3][H][W]; final_T[H][W] is the
+ *     transmittance left after compositing; n_contrib[H][W] (int32) is the
+ *     1-based position, in the pixel's tile list, of the last Gaussian that
+ *     contributed (0 if none).
+ *   - All work is queued on the caller's HIP stream (hipStream_t passed as
+ *     void*; NULL = the null stream) and is asynchronous unless stated.
+ *   - Errors are returned as rgs_status codes, never by abort; the message
+ *     of the last failure is available from rgs_last_error.  Degenerate
+ *     Gaussians (non-finite values, zero quaternion, prior opacity below
+ *     p_min, camera inside the support, centre at or before the near plane)
+ *     are culled, not errors.
+ *   - A context is not thread-safe; use one per host thread.
+ */
+#ifndef RAYGS_H
+#define RAYGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rgs_context rgs_context;
+typedef struct rgs_plan rgs_plan;
+
+typedef enum {
+    RGS_OK = 0,
+    RGS_EINVAL = -1,       /* invalid argument (null pointer, bad size or option) */
+    RGS_EWORKSPACE = -2,   /* workspace smaller than rgs_workspace_size reports */
+    RGS_EOVERFLOW = -3,    /* more Gaussian-tile instances than the workspace holds */
+    RGS_EHIP = -4,         /* a HIP runtime call failed */
+    RGS_ECAPTURE = -5,     /* HIP graph capture or instantiation failed */
+    RGS_EUNSUPPORTED = -6  /* valid request this build does not implement */
+} rgs_status;
+
+typedef struct {
+    const float *means;          /* device [3][n] */
+    const float *log_scales;     /* device [3][n] */
+    const float *quats;          /* device [4][n], (w, x, y, z) */
+    const float *opacity_logits; /* device [n] */
+    const float *sh;             /* device [(sh_degree+1)^2][3][n] */
+    int64_t n;                   /* >= 0; n * n_views < 2^31 */
+    int32_t sh_degree;           /* 0..3 */
+} rgs_gaussians;
+
+typedef struct {
+    double world_to_cam[12]; /* row-major [R | t], OpenCV axes */
+    double fx, fy, cx, cy;   /* pixels; fx, fy > 0 */
+    int32_t width, height;   /* 1..16384 */
+} rgs_camera;
+
+typedef struct {
+    double p_min;          /* cut-off opacity of the support, eq. 3; in (0, 1); default 1/255 */
+    double alpha_max;      /* opacity clamp, in (p_min, 1); default 0.99 */
+    double t_eps;          /* compositing stops before T would fall below it; [0, 1); default 1e-4 */
+    double near_z;         /* centres with z <= near_z are culled (Sec. 4.1, near plane); default 0.2 */
+    int32_t mip;           /* 1 = approximate MIP of Sec. 5, eq. 17; default 0 */
+    double mip_sigma2_px;  /* MIP pixel variance in px^2 (Sec. 6 uses 0.1); >= 0 */
+    double background[3];  /* added as T_final * background; default 0 */
+    int32_t tile_w, tile_h;/* 8x8, 16x8, 16x16, 32x16 or 32x32; 0, 0 = library default (16x16) */
+} rgs_options;
+
+typedef struct {
+    float *rgb;          /* device [3][H][W] */
+    float *final_T;      /* device [H][W] */
+    int32_t *n_contrib;  /* device [H][W] */
+} rgs_view_out;
+
+typedef struct { /* device, same shapes as rgs_gaussians; gradients are ADDED (+=) */
+    float *means, *log_scales, *quats, *opacity_logits, *sh;
+} rgs_gaussian_grads;
+
+/* Flags of a workspace. */
+#define RGS_WS_BACKWARD 1 /* reserve the per-record gradients used by rgs_render_backward */
+
+/* A caller-owned device workspace.  It holds all intermediate state of a frame
+ * (per Gaussian-view raster records, depth keys and tile rectangles, sort
+ * buffers, tile ranges) and, with RGS_WS_BACKWARD, the per-record gradients.
+ * It needs no initialisation and must stay untouched between rgs_render and
+ * the matching rgs_render_backward.  `capacity` is the number of
+ * Gaussian-tile instances it can hold; `bytes` must be at least what
+ * rgs_workspace_size reports for the same (capacity, flags). */
+typedef struct {
+    void *ptr;         /* device, 256-byte aligned */
+    size_t bytes;
+    int64_t capacity;  /* >= 1 */
+    int32_t flags;     /* RGS_WS_* */
+} rgs_workspace;
+
+/* Create a context on HIP device `device` (queries its compute-unit count).
+ * Returns RGS_EINVAL for a bad device or NULL out, RGS_EHIP on runtime
+ * failure.  The context holds tuning state and timing events only. */
+rgs_status rgs_create(int device, rgs_context **out);
+void rgs_destroy(rgs_context *ctx);
+
+/* Message describing the last error on this context ("" if none).  The string
+ * is owned by the context and valid until the next call on it. */
+const char *rgs_last_error(const rgs_context *ctx);
+
+/* Bytes of device workspace needed to render `n_views` cameras of a scene of
+ * n Gaussians with room for `capacity` Gaussian-tile instances.  Pure host
+ * arithmetic; no GPU work; ctx may be NULL (no error message is kept then).  A capacity of about 8 n n_views instances covers
+ * typical scenes; rgs_render_status reports the count a frame needed. */
+rgs_status rgs_workspace_size(rgs_context *ctx, int64_t n, const rgs_camera *cams, int32_t n_views,
+                              const rgs_options *opts, int64_t capacity, int32_t flags, size_t *bytes);
+
+/* Forward render of n_views cameras in one batch (Sec. 3 eqs. 1-2 with D_ray
+ * of eq. 5, the quad bound of Sec. 4.1 and, if opts->mip, eq. 17).
+ * cams, outs: host arrays of n_views (outs entries hold device pointers);
+ * opts: one struct for the whole batch.  Stream-ordered, no host
+ * synchronisation.  If the frame needs
+ * more instances than ws->capacity, every view is rendered as background and
+ * rgs_render_status reports RGS_EOVERFLOW with the count needed. */
+rgs_status rgs_render(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
+                      const rgs_options *opts, const rgs_workspace *ws, const rgs_view_out *outs, void *stream);
+
+/* Synchronises `stream`, then reads the instance count of the last frame
+ * rendered into `ws` (*instances, may be NULL).  Returns RGS_OK, or
+ * RGS_EOVERFLOW when that count exceeded ws->capacity. */
+rgs_status rgs_render_status(rgs_context *ctx, const rgs_workspace *ws, void *stream, int64_t *instances);
+
+/* Gradients of a loss with respect to the Gaussian parameters, given
+ * dL_drgb[v] (device [3][H][W] per view) for the frame last rendered into
+ * `ws` (which must carry RGS_WS_BACKWARD) with the same g, cams, opts and
+ * outs.  Walks each pixel's list back from n_contrib starting at final_T.
+ * Gradients are added into `grads`.  opts->mip = 1 returns RGS_EUNSUPPORTED.
+ * Uses float atomics: results are order-nondeterministic in the last bits. */
+rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
+                               const rgs_options *opts, const rgs_workspace *ws, const rgs_view_out *outs,
+                               const float *const *dL_drgb, const rgs_gaussian_grads *grads, void *stream);
+
+/* Batched persistent rendering with HIP graphs.  A plan fixes the view
+ * count, resolutions, options, Gaussian count, SH degree and the workspace's
+ * capacity and flags; the first rgs_batch_launch captures the whole frame
+ * (all views, one persistent compositing launch) into one HIP graph and later
+ * launches replay it, re-capturing if the Gaussian, workspace or output
+ * pointers change.  Camera poses and intrinsics may change between launches
+ * (image sizes may not).  rgs_batch_plan reports the workspace size. */
+rgs_status rgs_batch_plan(rgs_context *ctx, int64_t n, int32_t sh_degree, const rgs_camera *cams, int32_t n_views,
+                          const rgs_options *opts, int64_t capacity, int32_t flags, size_t *ws_bytes,
+                          rgs_plan **out);
+rgs_status rgs_batch_launch(rgs_plan *plan, const rgs_gaussians *g, const rgs_camera *cams, const rgs_workspace *ws,
+                            const rgs_view_out *outs, void *stream);
+void rgs_plan_destroy(rgs_plan *plan);
+
+/* Times every supported tile shape on this frame (hipEvent timing, `reps`
+ * renders each after one warm-up, synchronising `stream`) and writes the
+ * fastest into *best (a copy of *opts with tile_w, tile_h set) and its mean
+ * milliseconds into *best_ms.  Shapes whose instances exceed ws->capacity are
+ * skipped. */
+rgs_status rgs_autotune(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
+                        const rgs_options *opts, const rgs_workspace *ws, const rgs_view_out *outs, int32_t reps,
+                        void *stream, rgs_options *best, double *best_ms);
+
+/* Byte offsets of the intermediate buffers inside a workspace (for tests and
+ * profiling tools).  Counts are element counts.  Pure host arithmetic; ctx
+ * may be NULL. */
+typedef struct {
+    size_t counters;       /* int64[8]: [0] instances needed, [1] capacity, [2] two uint32 tile-queue heads */
+    size_t views;          /* per-view device table */
+    size_t records;        /* float[16] per Gaussian-view, index v * n + i */
+    size_t depth_keys;     /* uint32 per Gaussian-view (0xffffffff = culled) */
+    size_t rects;          /* uint16[4] per Gaussian-view: tile x0, y0, x1, y1 (inclusive) */
+    size_t tile_counts;    /* uint32 per Gaussian-view */
+    size_t order;          /* uint32 per Gaussian-view: Gaussian-view ids sorted by (depth, id) */
+    size_t offsets;        /* uint32 per Gaussian-view: first instance of each sorted entry */
+    size_t inst_tiles;     /* uint32 per instance: global tile id, sorted */
+    size_t inst_ids;       /* uint32 per instance: Gaussian-view id, sorted by (tile, depth, id) */
+    size_t tile_ranges;    /* uint32[2] per global tile: [start, end) into the instance arrays */
+    size_t record_grads;   /* float[16] per Gaussian-view (RGS_WS_BACKWARD only, else 0) */
+    size_t total_bytes;    /* what rgs_workspace_size reports */
+    int64_t n_records;     /* n * n_views */
+    int64_t capacity;      /* instances */
+    int64_t total_tiles;   /* over all views */
+    int32_t tile_w, tile_h;
+    int32_t tile_bits;     /* significant bits of a global tile id */
+    int32_t reserved;
+} rgs_workspace_layout;
+
+rgs_status rgs_get_workspace_layout(rgs_context *ctx, int64_t n, const rgs_camera *cams, int32_t n_views,
+                                    const rgs_options *opts, int64_t capacity, int32_t flags,
+                                    rgs_workspace_layout *out);
+
+/* Per-stage GPU timing.  While enabled, rgs_render and rgs_render_backward
+ * record HIP events around each stage on the caller's stream; rgs_stage_times
+ * synchronises, adds the elapsed times of all frames recorded since the last
+ * read into ms[0..n) in the order of rgs_stage_names (a ';'-separated list),
+ * and resets.  Returns the number of stages. */
+rgs_status rgs_set_stage_timing(rgs_context *ctx, int32_t enable);
+int32_t rgs_stage_times(rgs_context *ctx, double *ms, int32_t n, int64_t *frames);
+const char *rgs_stage_names(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RAYGS_H */

@@ -1,0 +1,718 @@
+// Host side of the C ABI: argument validation, workspace layout, the launch
+// sequence of a frame, HIP-graph batch plans, the tile-shape autotuner and
+// per-stage event timing.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace rgs;
+
+namespace {
+
+constexpr int kNumStages = 9;
+const char *const kStageNames =
+    "preprocess;depth_sort;scan;emit;tile_sort;tile_ranges;blend;blend_backward;preprocess_backward";
+enum Stage { ST_PRE, ST_DSORT, ST_SCAN, ST_EMIT, ST_TSORT, ST_RANGES, ST_BLEND, ST_BLEND_BWD, ST_PRE_BWD };
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t counters, views, records, keys_a, keys_b, order_a, order_b, rects, tile_counts, offsets, block_sums;
+    size_t inst_tiles_a, inst_tiles_b, inst_ids_a, inst_ids_b, hist, row_total, ranges, record_grads, total;
+    int64_t nv_records, capacity, total_tiles;
+    int tile_w, tile_h, tile_bits;
+};
+
+struct FrameEvents {
+    hipEvent_t ev[kNumStages + 1];
+    int first, last;  // stages [first, last) were recorded
+};
+
+}  // namespace
+
+struct rgs_context {
+    int device = 0;
+    int num_cus = 256;
+    std::string err;
+    bool timing = false;
+    std::vector<FrameEvents> pending;
+    std::vector<FrameEvents> pool;
+    double stage_ms[kNumStages] = {0};
+    int64_t frames = 0;
+    int grid_fwd[64] = {0}, grid_bwd[64] = {0};
+};
+
+struct rgs_plan {
+    rgs_context *ctx = nullptr;
+    int64_t n = 0;
+    int32_t sh_degree = 0;
+    std::vector<rgs_camera> cams;
+    rgs_options opts{};
+    int64_t capacity = 0;
+    int32_t flags = 0;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool captured = false;
+    rgs_gaussians g{};
+    void *ws_ptr = nullptr;
+    std::vector<rgs_view_out> outs;
+};
+
+namespace {
+
+rgs_status fail(rgs_context *ctx, rgs_status st, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+rgs_status fail(rgs_context *ctx, rgs_status st, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return st;
+}
+
+#define RGS_HIP(ctx, call)                                                                                  \
+    do {                                                                                                    \
+        hipError_t e_ = (call);                                                                             \
+        if (e_ != hipSuccess) return fail((ctx), RGS_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));  \
+    } while (0)
+
+TileShape shape_of(const rgs_options &o)
+{
+    if (o.tile_w == 0 && o.tile_h == 0) return TileShape{16, 16};
+    return TileShape{o.tile_w, o.tile_h};
+}
+
+int shape_index(TileShape s)
+{
+    const int w = s.w == 8 ? 0 : (s.w == 16 ? 1 : 2);
+    const int h = s.h == 8 ? 0 : (s.h == 16 ? 1 : 2);
+    return w * 3 + h;
+}
+
+int bits_for(int64_t count)
+{
+    int b = 1;
+    while (b < 40 && (int64_t(1) << b) < count) ++b;
+    return b;
+}
+
+rgs_status check_cameras(rgs_context *ctx, const rgs_camera *cams, int32_t n_views)
+{
+    if (!cams) return fail(ctx, RGS_EINVAL, "cams is NULL");
+    if (n_views < 1 || n_views > kMaxViews) return fail(ctx, RGS_EINVAL, "n_views=%d outside [1, %d]", n_views, kMaxViews);
+    for (int v = 0; v < n_views; ++v) {
+        const rgs_camera &c = cams[v];
+        if (c.width < 1 || c.width > 16384 || c.height < 1 || c.height > 16384)
+            return fail(ctx, RGS_EINVAL, "view %d: size %dx%d outside [1, 16384]", v, c.width, c.height);
+        bool finite = std::isfinite(c.fx) && std::isfinite(c.fy) && std::isfinite(c.cx) && std::isfinite(c.cy);
+        for (int k = 0; k < 12; ++k) finite = finite && std::isfinite(c.world_to_cam[k]);
+        if (!finite) return fail(ctx, RGS_EINVAL, "view %d: non-finite camera parameter", v);
+        if (!(c.fx > 0.0) || !(c.fy > 0.0)) return fail(ctx, RGS_EINVAL, "view %d: focal lengths must be > 0", v);
+    }
+    return RGS_OK;
+}
+
+rgs_status check_options(rgs_context *ctx, const rgs_options *o)
+{
+    if (!o) return fail(ctx, RGS_EINVAL, "opts is NULL");
+    if (!(o->p_min > 0.0 && o->p_min < 1.0)) return fail(ctx, RGS_EINVAL, "p_min must lie in (0, 1)");
+    if (!(o->alpha_max > o->p_min && o->alpha_max < 1.0))
+        return fail(ctx, RGS_EINVAL, "alpha_max must lie in (p_min, 1)");
+    if (!(o->t_eps >= 0.0 && o->t_eps < 1.0)) return fail(ctx, RGS_EINVAL, "t_eps must lie in [0, 1)");
+    if (!std::isfinite(o->near_z)) return fail(ctx, RGS_EINVAL, "near_z must be finite");
+    if (o->mip != 0 && o->mip != 1) return fail(ctx, RGS_EINVAL, "mip must be 0 or 1");
+    if (!(o->mip_sigma2_px >= 0.0) || !std::isfinite(o->mip_sigma2_px))
+        return fail(ctx, RGS_EINVAL, "mip_sigma2_px must be finite and >= 0");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(o->background[k])) return fail(ctx, RGS_EINVAL, "background must be finite");
+    const TileShape s = shape_of(*o);
+    if (!tile_shape_supported(s.w, s.h))
+        return fail(ctx, RGS_EINVAL, "tile shape %dx%d not supported (8x8, 16x8, 16x16, 32x16, 32x32)", s.w, s.h);
+    return RGS_OK;
+}
+
+rgs_status compute_layout(rgs_context *ctx, int64_t n, const rgs_camera *cams, int32_t n_views,
+                          const rgs_options *opts, int64_t capacity, int32_t flags, Layout &L)
+{
+    rgs_status st = check_cameras(ctx, cams, n_views);
+    if (st != RGS_OK) return st;
+    if ((st = check_options(ctx, opts)) != RGS_OK) return st;
+    if (n < 0) return fail(ctx, RGS_EINVAL, "n=%lld < 0", (long long)n);
+    if (n * (int64_t)n_views >= (int64_t(1) << 31) - 1)
+        return fail(ctx, RGS_EINVAL, "n * n_views must be below 2^31");
+    if (capacity < 1 || capacity > 0xffffffffLL) return fail(ctx, RGS_EINVAL, "capacity must lie in [1, 2^32)");
+    if (flags & ~RGS_WS_BACKWARD) return fail(ctx, RGS_EINVAL, "unknown workspace flags 0x%x", flags);
+    const TileShape s = shape_of(*opts);
+    L.tile_w = s.w;
+    L.tile_h = s.h;
+    int64_t tiles = 0;
+    for (int v = 0; v < n_views; ++v)
+        tiles += (int64_t)((cams[v].width + s.w - 1) / s.w) * ((cams[v].height + s.h - 1) / s.h);
+    if (tiles >= (int64_t(1) << 31)) return fail(ctx, RGS_EINVAL, "too many tiles");
+    L.total_tiles = tiles;
+    L.tile_bits = bits_for(tiles);
+    L.nv_records = n * n_views;
+    L.capacity = capacity;
+    const size_t NV = (size_t)L.nv_records;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    L.counters = take(8 * sizeof(int64_t));
+    L.views = take(sizeof(DevView) * n_views);
+    L.records = take(NV * kRecordFloats * sizeof(float));
+    L.keys_a = take(NV * 4);
+    L.keys_b = take(NV * 4);
+    L.order_a = take(NV * 4);
+    L.order_b = take(NV * 4);
+    L.rects = take(NV * 8);
+    L.tile_counts = take(NV * 4);
+    L.offsets = take(NV * 4);
+    L.block_sums = take(scan_block_entries((int64_t)NV) * 8);
+    L.inst_tiles_a = take((size_t)capacity * 4);
+    L.inst_tiles_b = take((size_t)capacity * 4);
+    L.inst_ids_a = take((size_t)capacity * 4);
+    L.inst_ids_b = take((size_t)capacity * 4);
+    L.hist = take(radix_hist_entries(std::max<int64_t>((int64_t)NV, capacity)) * 4);
+    L.row_total = take(256 * 4);
+    L.ranges = take((size_t)tiles * 8);
+    L.record_grads = (flags & RGS_WS_BACKWARD) ? take(NV * kGradFloats * sizeof(float)) : 0;
+    L.total = off;
+    return RGS_OK;
+}
+
+void fill_public_layout(const Layout &L, rgs_workspace_layout *o)
+{
+    std::memset(o, 0, sizeof *o);
+    o->counters = L.counters;
+    o->views = L.views;
+    o->records = L.records;
+    o->depth_keys = L.keys_a;
+    o->rects = L.rects;
+    o->tile_counts = L.tile_counts;
+    o->order = L.order_a;
+    o->offsets = L.offsets;
+    o->inst_tiles = L.inst_tiles_a;
+    o->inst_ids = L.inst_ids_a;
+    o->tile_ranges = L.ranges;
+    o->record_grads = L.record_grads;
+    o->total_bytes = L.total;
+    o->n_records = L.nv_records;
+    o->capacity = L.capacity;
+    o->total_tiles = L.total_tiles;
+    o->tile_w = L.tile_w;
+    o->tile_h = L.tile_h;
+    o->tile_bits = L.tile_bits;
+}
+
+DevOptions dev_options(const rgs_options &o)
+{
+    DevOptions d{};
+    d.p_min = o.p_min;
+    d.alpha_max = o.alpha_max;
+    d.t_eps = o.t_eps;
+    d.near_z = o.near_z;
+    d.mip_sigma2_px = o.mip_sigma2_px;
+    d.mip = o.mip;
+    const TileShape s = shape_of(o);
+    d.tile_w = s.w;
+    d.tile_h = s.h;
+    for (int k = 0; k < 3; ++k) d.bg[k] = (float)o.background[k];
+    return d;
+}
+
+// Host image of the workspace header: counters followed by the view table.
+std::vector<unsigned char> build_header(const Layout &L, const rgs_camera *cams, int n_views,
+                                        const rgs_view_out *outs, const float *const *dL)
+{
+    std::vector<unsigned char> buf(L.views + sizeof(DevView) * n_views, 0);
+    int64_t *counters = reinterpret_cast<int64_t *>(buf.data() + L.counters);
+    counters[0] = 0;
+    counters[1] = L.capacity;
+    DevView *views = reinterpret_cast<DevView *>(buf.data() + L.views);
+    int base = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const rgs_camera &c = cams[v];
+        DevView &d = views[v];
+        std::memcpy(d.w2c, c.world_to_cam, sizeof d.w2c);
+        d.fx = c.fx;
+        d.fy = c.fy;
+        d.cx = c.cx;
+        d.cy = c.cy;
+        const double *W = c.world_to_cam;
+        for (int k = 0; k < 3; ++k) d.centre[k] = -(W[k] * W[3] + W[4 + k] * W[7] + W[8 + k] * W[11]);
+        d.width = c.width;
+        d.height = c.height;
+        d.tiles_x = (c.width + L.tile_w - 1) / L.tile_w;
+        d.tiles_y = (c.height + L.tile_h - 1) / L.tile_h;
+        d.tile_base = base;
+        base += d.tiles_x * d.tiles_y;
+        d.rgb = outs ? outs[v].rgb : nullptr;
+        d.final_T = outs ? outs[v].final_T : nullptr;
+        d.n_contrib = outs ? outs[v].n_contrib : nullptr;
+        d.dL_drgb = dL ? dL[v] : nullptr;
+    }
+    return buf;
+}
+
+template <typename T>
+T *at(void *ws, size_t off)
+{
+    return reinterpret_cast<T *>(static_cast<unsigned char *>(ws) + off);
+}
+
+struct Timer {
+    rgs_context *ctx;
+    hipStream_t stream;
+    FrameEvents fe{};
+    bool on;
+    Timer(rgs_context *c, hipStream_t s, bool enable, int first) : ctx(c), stream(s), on(enable && c->timing)
+    {
+        if (!on) return;
+        if (!ctx->pool.empty()) {
+            fe = ctx->pool.back();
+            ctx->pool.pop_back();
+        } else {
+            for (auto &e : fe.ev) hipEventCreate(&e);
+        }
+        fe.first = first;
+        fe.last = first;
+        hipEventRecord(fe.ev[first], stream);
+    }
+    void mark(int stage_done)
+    {
+        if (!on) return;
+        hipEventRecord(fe.ev[stage_done + 1], stream);
+        fe.last = stage_done + 1;
+    }
+    ~Timer()
+    {
+        if (on) ctx->pending.push_back(fe);
+    }
+};
+
+void ensure_grids(rgs_context *ctx, TileShape s)
+{
+    const int k = shape_index(s);
+    if (!ctx->grid_fwd[k]) ctx->grid_fwd[k] = blend_grid(s, ctx->num_cus);
+    if (!ctx->grid_bwd[k]) ctx->grid_bwd[k] = blend_backward_grid(s, ctx->num_cus);
+}
+
+// Enqueue the forward pipeline after the header copy.
+rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views, const rgs_options &opts,
+                           const Layout &L, void *ws, hipStream_t stream, bool timing)
+{
+    const DevOptions dopt = dev_options(opts);
+    const TileShape s = shape_of(opts);
+    ensure_grids(ctx, s);
+    const DevView *views = at<DevView>(ws, L.views);
+    int64_t *counters = at<int64_t>(ws, L.counters);
+    const int64_t NV = L.nv_records;
+    // pass parity decides where the producers write so results land in "a"
+    const int dpasses = radix_passes(32);
+    const int tpasses = radix_passes(L.tile_bits);
+    uint32_t *keys_in = at<uint32_t>(ws, dpasses % 2 ? L.keys_b : L.keys_a);
+    uint32_t *keys_alt = at<uint32_t>(ws, dpasses % 2 ? L.keys_a : L.keys_b);
+    uint32_t *ord_in = at<uint32_t>(ws, dpasses % 2 ? L.order_b : L.order_a);
+    uint32_t *ord_alt = at<uint32_t>(ws, dpasses % 2 ? L.order_a : L.order_b);
+    uint32_t *tiles_in = at<uint32_t>(ws, tpasses % 2 ? L.inst_tiles_b : L.inst_tiles_a);
+    uint32_t *tiles_alt = at<uint32_t>(ws, tpasses % 2 ? L.inst_tiles_a : L.inst_tiles_b);
+    uint32_t *ids_in = at<uint32_t>(ws, tpasses % 2 ? L.inst_ids_b : L.inst_ids_a);
+    uint32_t *ids_alt = at<uint32_t>(ws, tpasses % 2 ? L.inst_ids_a : L.inst_ids_b);
+    float4 *records = at<float4>(ws, L.records);
+    uint2 *rects = at<uint2>(ws, L.rects);
+    uint32_t *tile_counts = at<uint32_t>(ws, L.tile_counts);
+    uint32_t *hist = at<uint32_t>(ws, L.hist);
+    uint32_t *row_total = at<uint32_t>(ws, L.row_total);
+    uint2 *ranges = at<uint2>(ws, L.ranges);
+    unsigned int *queues = reinterpret_cast<unsigned int *>(counters + 2);
+
+    Timer tm(ctx, stream, timing, ST_PRE);
+    RGS_HIP(ctx, launch_preprocess(g, views, n_views, dopt, records, keys_in, ord_in, rects, tile_counts, stream));
+    tm.mark(ST_PRE);
+    RGS_HIP(ctx, radix_sort(keys_in, ord_in, keys_alt, ord_alt, NV, nullptr, 32, hist, row_total, stream));
+    tm.mark(ST_DSORT);
+    const uint32_t *order = at<uint32_t>(ws, L.order_a);
+    uint32_t *offsets = at<uint32_t>(ws, L.offsets);
+    RGS_HIP(ctx, exclusive_scan_gather(tile_counts, order, offsets, NV, at<unsigned long long>(ws, L.block_sums),
+                                       counters, stream));
+    tm.mark(ST_SCAN);
+    RGS_HIP(ctx, launch_emit(order, offsets, tile_counts, rects, views, g.n, n_views, L.capacity, tiles_in, ids_in,
+                             stream));
+    tm.mark(ST_EMIT);
+    RGS_HIP(ctx, radix_sort(tiles_in, ids_in, tiles_alt, ids_alt, L.capacity, counters, L.tile_bits, hist, row_total,
+                            stream));
+    tm.mark(ST_TSORT);
+    const uint32_t *inst_tiles = at<uint32_t>(ws, L.inst_tiles_a);
+    const uint32_t *inst_ids = at<uint32_t>(ws, L.inst_ids_a);
+    RGS_HIP(ctx, launch_tile_ranges(inst_tiles, counters, L.capacity, L.total_tiles, ranges, queues, stream));
+    tm.mark(ST_RANGES);
+    RGS_HIP(ctx, launch_blend(s, ranges, inst_ids, records, views, n_views, L.total_tiles, NV, dopt, queues,
+                              ctx->grid_fwd[shape_index(s)], stream));
+    tm.mark(ST_BLEND);
+    return RGS_OK;
+}
+
+rgs_status check_gaussians(rgs_context *ctx, const rgs_gaussians *g)
+{
+    if (!g) return fail(ctx, RGS_EINVAL, "g is NULL");
+    if (g->n < 0) return fail(ctx, RGS_EINVAL, "n < 0");
+    if (g->sh_degree < 0 || g->sh_degree > 3) return fail(ctx, RGS_EINVAL, "sh_degree=%d outside 0..3", g->sh_degree);
+    if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh))
+        return fail(ctx, RGS_EINVAL, "NULL Gaussian parameter pointer");
+    return RGS_OK;
+}
+
+rgs_status check_outs(rgs_context *ctx, const rgs_view_out *outs, int n_views)
+{
+    if (!outs) return fail(ctx, RGS_EINVAL, "outs is NULL");
+    for (int v = 0; v < n_views; ++v)
+        if (!outs[v].rgb || !outs[v].final_T || !outs[v].n_contrib)
+            return fail(ctx, RGS_EINVAL, "view %d: NULL output pointer", v);
+    return RGS_OK;
+}
+
+rgs_status check_workspace(rgs_context *ctx, const rgs_workspace *ws, const Layout &L)
+{
+    if (!ws || !ws->ptr) return fail(ctx, RGS_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws->ptr) % kAlign)
+        return fail(ctx, RGS_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+    if (ws->bytes < L.total)
+        return fail(ctx, RGS_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws->bytes, L.total);
+    return RGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rgs_status rgs_create(int device, rgs_context **out)
+{
+    if (!out) return RGS_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return RGS_EINVAL;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return RGS_EHIP;
+    rgs_context *ctx = new rgs_context();
+    ctx->device = device;
+    ctx->num_cus = cus > 0 ? cus : 256;
+    *out = ctx;
+    return RGS_OK;
+}
+
+void rgs_destroy(rgs_context *ctx)
+{
+    if (!ctx) return;
+    for (auto &fe : ctx->pending)
+        for (auto &e : fe.ev) hipEventDestroy(e);
+    for (auto &fe : ctx->pool)
+        for (auto &e : fe.ev) hipEventDestroy(e);
+    delete ctx;
+}
+
+const char *rgs_last_error(const rgs_context *ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+const char *rgs_stage_names(void) { return kStageNames; }
+
+rgs_status rgs_workspace_size(rgs_context *ctx, int64_t n, const rgs_camera *cams, int32_t n_views,
+                              const rgs_options *opts, int64_t capacity, int32_t flags, size_t *bytes)
+{
+    if (!bytes) return fail(ctx, RGS_EINVAL, "NULL argument");
+    Layout L;
+    const rgs_status st = compute_layout(ctx, n, cams, n_views, opts, capacity, flags, L);
+    if (st != RGS_OK) return st;
+    *bytes = L.total;
+    return RGS_OK;
+}
+
+rgs_status rgs_get_workspace_layout(rgs_context *ctx, int64_t n, const rgs_camera *cams, int32_t n_views,
+                                    const rgs_options *opts, int64_t capacity, int32_t flags,
+                                    rgs_workspace_layout *out)
+{
+    if (!out) return fail(ctx, RGS_EINVAL, "NULL argument");
+    Layout L;
+    const rgs_status st = compute_layout(ctx, n, cams, n_views, opts, capacity, flags, L);
+    if (st != RGS_OK) return st;
+    fill_public_layout(L, out);
+    return RGS_OK;
+}
+
+rgs_status rgs_render(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
+                      const rgs_options *opts, const rgs_workspace *ws, const rgs_view_out *outs, void *stream)
+{
+    if (!ctx) return RGS_EINVAL;
+    ctx->err.clear();
+    rgs_status st = check_gaussians(ctx, g);
+    if (st != RGS_OK) return st;
+    if (!ws) return fail(ctx, RGS_EINVAL, "workspace is NULL");
+    Layout L;
+    if ((st = compute_layout(ctx, g->n, cams, n_views, opts, ws->capacity, ws->flags, L)) != RGS_OK) return st;
+    if ((st = check_workspace(ctx, ws, L)) != RGS_OK) return st;
+    if ((st = check_outs(ctx, outs, n_views)) != RGS_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    RGS_HIP(ctx, hipSetDevice(ctx->device));
+    const std::vector<unsigned char> hdr = build_header(L, cams, n_views, outs, nullptr);
+    RGS_HIP(ctx, hipMemcpyAsync(ws->ptr, hdr.data(), hdr.size(), hipMemcpyHostToDevice, s));
+    st = enqueue_forward(ctx, *g, n_views, *opts, L, ws->ptr, s, true);
+    if (st == RGS_OK) ++ctx->frames;
+    return st;
+}
+
+rgs_status rgs_render_status(rgs_context *ctx, const rgs_workspace *ws, void *stream, int64_t *instances)
+{
+    if (!ctx) return RGS_EINVAL;
+    if (!ws || !ws->ptr) return fail(ctx, RGS_EINVAL, "workspace is NULL");
+    RGS_HIP(ctx, hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    int64_t c[2] = {0, 0};
+    RGS_HIP(ctx, hipMemcpy(c, ws->ptr, sizeof c, hipMemcpyDeviceToHost));
+    if (instances) *instances = c[0];
+    if (c[0] > ws->capacity)
+        return fail(ctx, RGS_EOVERFLOW, "frame needed %lld instances, capacity %lld", (long long)c[0],
+                    (long long)ws->capacity);
+    return RGS_OK;
+}
+
+rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
+                               const rgs_options *opts, const rgs_workspace *ws, const rgs_view_out *outs,
+                               const float *const *dL_drgb, const rgs_gaussian_grads *grads, void *stream)
+{
+    if (!ctx) return RGS_EINVAL;
+    ctx->err.clear();
+    rgs_status st = check_gaussians(ctx, g);
+    if (st != RGS_OK) return st;
+    if (!ws) return fail(ctx, RGS_EINVAL, "workspace is NULL");
+    Layout L;
+    if ((st = compute_layout(ctx, g->n, cams, n_views, opts, ws->capacity, ws->flags, L)) != RGS_OK) return st;
+    if ((st = check_workspace(ctx, ws, L)) != RGS_OK) return st;
+    if ((st = check_outs(ctx, outs, n_views)) != RGS_OK) return st;
+    if (!(ws->flags & RGS_WS_BACKWARD)) return fail(ctx, RGS_EINVAL, "workspace lacks RGS_WS_BACKWARD");
+    if (opts->mip) return fail(ctx, RGS_EUNSUPPORTED, "the MIP transform is not differentiated");
+    if (!dL_drgb) return fail(ctx, RGS_EINVAL, "dL_drgb is NULL");
+    for (int v = 0; v < n_views; ++v)
+        if (!dL_drgb[v]) return fail(ctx, RGS_EINVAL, "dL_drgb[%d] is NULL", v);
+    if (!grads) return fail(ctx, RGS_EINVAL, "grads is NULL");
+    if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh))
+        return fail(ctx, RGS_EINVAL, "NULL gradient pointer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    RGS_HIP(ctx, hipSetDevice(ctx->device));
+    // refresh the view table with the upstream gradients (counters untouched)
+    const std::vector<unsigned char> hdr = build_header(L, cams, n_views, outs, dL_drgb);
+    RGS_HIP(ctx, hipMemcpyAsync(at<unsigned char>(ws->ptr, L.views), hdr.data() + L.views, hdr.size() - L.views,
+                                hipMemcpyHostToDevice, s));
+    const TileShape sh = shape_of(*opts);
+    ensure_grids(ctx, sh);
+    const DevOptions dopt = dev_options(*opts);
+    int64_t *counters = at<int64_t>(ws->ptr, L.counters);
+    unsigned int *queues = reinterpret_cast<unsigned int *>(counters + 2);
+    float *rgrads = at<float>(ws->ptr, L.record_grads);
+    Timer tm(ctx, s, true, ST_BLEND_BWD);
+    RGS_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(rgrads), 0u, L.nv_records * kGradFloats, s));
+    RGS_HIP(ctx, launch_fill_u32(queues + 1, 0u, 1, s));
+    RGS_HIP(ctx, launch_blend_backward(sh, at<uint2>(ws->ptr, L.ranges), at<uint32_t>(ws->ptr, L.inst_ids_a),
+                                       at<float4>(ws->ptr, L.records), at<DevView>(ws->ptr, L.views), n_views,
+                                       L.total_tiles, L.nv_records, dopt, rgrads, queues + 1,
+                                       ctx->grid_bwd[shape_index(sh)], s));
+    tm.mark(ST_BLEND_BWD);
+    RGS_HIP(ctx, launch_preprocess_backward(*g, at<DevView>(ws->ptr, L.views), n_views, dopt,
+                                            at<uint32_t>(ws->ptr, L.tile_counts), rgrads, *grads, s));
+    tm.mark(ST_PRE_BWD);
+    return RGS_OK;
+}
+
+rgs_status rgs_batch_plan(rgs_context *ctx, int64_t n, int32_t sh_degree, const rgs_camera *cams, int32_t n_views,
+                          const rgs_options *opts, int64_t capacity, int32_t flags, size_t *ws_bytes, rgs_plan **out)
+{
+    if (!ctx || !out || !ws_bytes) return fail(ctx, RGS_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (sh_degree < 0 || sh_degree > 3) return fail(ctx, RGS_EINVAL, "sh_degree outside 0..3");
+    Layout L;
+    const rgs_status st = compute_layout(ctx, n, cams, n_views, opts, capacity, flags, L);
+    if (st != RGS_OK) return st;
+    rgs_plan *p = new rgs_plan();
+    p->ctx = ctx;
+    p->n = n;
+    p->sh_degree = sh_degree;
+    p->cams.assign(cams, cams + n_views);
+    p->opts = *opts;
+    p->capacity = capacity;
+    p->flags = flags;
+    if (hipSetDevice(ctx->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete p;
+        return fail(ctx, RGS_EHIP, "cannot create the capture stream");
+    }
+    ensure_grids(ctx, shape_of(*opts));
+    *ws_bytes = L.total;
+    *out = p;
+    return RGS_OK;
+}
+
+void rgs_plan_destroy(rgs_plan *p)
+{
+    if (!p) return;
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->capture_stream) hipStreamDestroy(p->capture_stream);
+    delete p;
+}
+
+rgs_status rgs_batch_launch(rgs_plan *p, const rgs_gaussians *g, const rgs_camera *cams, const rgs_workspace *ws,
+                            const rgs_view_out *outs, void *stream)
+{
+    if (!p) return RGS_EINVAL;
+    rgs_context *ctx = p->ctx;
+    ctx->err.clear();
+    rgs_status st = check_gaussians(ctx, g);
+    if (st != RGS_OK) return st;
+    const int nv = (int)p->cams.size();
+    if (g->n != p->n || g->sh_degree != p->sh_degree)
+        return fail(ctx, RGS_EINVAL, "Gaussian count or SH degree differs from the plan");
+    if (!cams) return fail(ctx, RGS_EINVAL, "cams is NULL");
+    for (int v = 0; v < nv; ++v)
+        if (cams[v].width != p->cams[v].width || cams[v].height != p->cams[v].height)
+            return fail(ctx, RGS_EINVAL, "view %d: image size differs from the plan", v);
+    if (!ws) return fail(ctx, RGS_EINVAL, "workspace is NULL");
+    if (ws->capacity != p->capacity || ws->flags != p->flags)
+        return fail(ctx, RGS_EINVAL, "workspace capacity or flags differ from the plan");
+    Layout L;
+    if ((st = compute_layout(ctx, p->n, cams, nv, &p->opts, p->capacity, p->flags, L)) != RGS_OK) return st;
+    if ((st = check_workspace(ctx, ws, L)) != RGS_OK) return st;
+    if ((st = check_outs(ctx, outs, nv)) != RGS_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    RGS_HIP(ctx, hipSetDevice(ctx->device));
+    bool same = p->captured && ws->ptr == p->ws_ptr && std::memcmp(g, &p->g, sizeof *g) == 0;
+    for (int v = 0; same && v < nv; ++v)
+        same = outs[v].rgb == p->outs[v].rgb && outs[v].final_T == p->outs[v].final_T &&
+               outs[v].n_contrib == p->outs[v].n_contrib;
+    if (!same) {
+        if (p->exec) {
+            hipGraphExecDestroy(p->exec);
+            p->exec = nullptr;
+        }
+        if (p->graph) {
+            hipGraphDestroy(p->graph);
+            p->graph = nullptr;
+        }
+        p->captured = false;
+        RGS_HIP(ctx, hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
+        st = enqueue_forward(ctx, *g, nv, p->opts, L, ws->ptr, p->capture_stream, false);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(p->capture_stream, &graph);
+        if (st != RGS_OK) {
+            if (graph) hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess || !graph) return fail(ctx, RGS_ECAPTURE, "capture failed: %s", hipGetErrorString(e));
+        p->graph = graph;
+        if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+            return fail(ctx, RGS_ECAPTURE, "graph instantiation failed");
+        p->captured = true;
+        p->g = *g;
+        p->ws_ptr = ws->ptr;
+        p->outs.assign(outs, outs + nv);
+    }
+    const std::vector<unsigned char> hdr = build_header(L, cams, nv, outs, nullptr);
+    RGS_HIP(ctx, hipMemcpyAsync(ws->ptr, hdr.data(), hdr.size(), hipMemcpyHostToDevice, s));
+    RGS_HIP(ctx, hipGraphLaunch(p->exec, s));
+    ++ctx->frames;
+    return RGS_OK;
+}
+
+rgs_status rgs_autotune(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
+                        const rgs_options *opts, const rgs_workspace *ws, const rgs_view_out *outs, int32_t reps,
+                        void *stream, rgs_options *best, double *best_ms)
+{
+    if (!ctx || !best || !best_ms || !opts) return fail(ctx, RGS_EINVAL, "NULL argument");
+    if (reps < 1) return fail(ctx, RGS_EINVAL, "reps must be >= 1");
+    static const TileShape shapes[] = {{8, 8}, {16, 8}, {16, 16}, {32, 16}, {32, 32}};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    RGS_HIP(ctx, hipEventCreate(&e0));
+    RGS_HIP(ctx, hipEventCreate(&e1));
+    double best_t = 1e300;
+    rgs_options chosen = *opts;
+    rgs_status result = RGS_EOVERFLOW;
+    const bool timing = ctx->timing;
+    ctx->timing = false;
+    for (const TileShape &sh : shapes) {
+        rgs_options o = *opts;
+        o.tile_w = sh.w;
+        o.tile_h = sh.h;
+        rgs_status st = rgs_render(ctx, g, cams, n_views, &o, ws, outs, stream);
+        if (st == RGS_OK) st = rgs_render_status(ctx, ws, stream, nullptr);
+        if (st == RGS_EOVERFLOW || st == RGS_EWORKSPACE) continue;
+        if (st != RGS_OK) {
+            result = st;
+            break;
+        }
+        hipEventRecord(e0, s);
+        for (int r = 0; r < reps && st == RGS_OK; ++r) st = rgs_render(ctx, g, cams, n_views, &o, ws, outs, stream);
+        hipEventRecord(e1, s);
+        if (st != RGS_OK) {
+            result = st;
+            break;
+        }
+        hipEventSynchronize(e1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        const double t = ms / reps;
+        if (t < best_t) {
+            best_t = t;
+            chosen = o;
+        }
+        result = RGS_OK;
+    }
+    ctx->timing = timing;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (result != RGS_OK)
+        return result == RGS_EOVERFLOW ? fail(ctx, RGS_EOVERFLOW, "no tile shape fits the workspace capacity")
+                                       : result;
+    *best = chosen;
+    *best_ms = best_t;
+    return RGS_OK;
+}
+
+rgs_status rgs_set_stage_timing(rgs_context *ctx, int32_t enable)
+{
+    if (!ctx) return RGS_EINVAL;
+    ctx->timing = enable != 0;
+    return RGS_OK;
+}
+
+int32_t rgs_stage_times(rgs_context *ctx, double *ms, int32_t n, int64_t *frames)
+{
+    if (!ctx) return 0;
+    for (auto &fe : ctx->pending) {
+        hipEventSynchronize(fe.ev[fe.last]);
+        for (int st = fe.first; st < fe.last; ++st) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, fe.ev[st], fe.ev[st + 1]) == hipSuccess) ctx->stage_ms[st] += t;
+        }
+        ctx->pool.push_back(fe);
+    }
+    ctx->pending.clear();
+    if (ms)
+        for (int k = 0; k < n && k < kNumStages; ++k) ms[k] = ctx->stage_ms[k];
+    if (frames) *frames = ctx->frames;
+    for (double &v : ctx->stage_ms) v = 0.0;
+    ctx->frames = 0;
+    return kNumStages;
+}
+
+}  // extern "C"

@@ -1,0 +1,232 @@
+// Per-Gaussian backward: chain rule from the accumulated raster-record
+// gradients to the Gaussian parameters (means, log-scales, quaternions,
+// opacity logits, SH coefficients), summed over the views of the batch.
+//
+// The record's 2x2 map G = R_v[:, 0:2]^T A2 enters the image only through
+// q = |G delta|^2 = delta^T M delta with
+//     M = G^T G = A2^T (I - mu^ mu^^T) A2 = A2^T A2 - w w^T / c^2,
+// where A = S^-1 R_p^T, A2 = A[:, 0:2] diag(1/fx, 1/fy), mu' = A mu and
+// w = A2^T mu' (so g = w / c^2).  The compositing kernel therefore
+// accumulates dL/dM, and this kernel differentiates M, g, k0 = 1/mu_z,
+// ic2 = 1/c^2 and the projected centre with respect to (A, mu) without ever
+// differentiating the rotation R_{mu^ <- v}.  Evaluated in double precision.
+#include "internal.h"
+
+namespace rgs {
+namespace {
+
+// Real SH basis and its gradient with respect to the (unnormalised) direction
+// components, degree <= 3, same convention as the forward kernel.
+template <int DEG>
+__device__ __forceinline__ void sh_basis_grad(double x, double y, double z, double *Y, double (*dY)[3])
+{
+    const double c0 = 0.28209479177387814, c1 = 0.48860251190291992;
+    const double c2a = 1.0925484305920792, c2b = 0.31539156525252005, c2c = 0.54627421529603959;
+    const double c3a = -0.59004358992664352, c3b = 2.8906114426405538, c3c = -0.45704579946446572;
+    const double c3d = 0.37317633259011540, c3e = 1.4453057213202769;
+    for (int k = 0; k < (DEG + 1) * (DEG + 1); ++k) dY[k][0] = dY[k][1] = dY[k][2] = 0.0;
+    Y[0] = c0;
+    if (DEG >= 1) {
+        Y[1] = -c1 * y; dY[1][1] = -c1;
+        Y[2] = c1 * z;  dY[2][2] = c1;
+        Y[3] = -c1 * x; dY[3][0] = -c1;
+    }
+    if (DEG >= 2) {
+        const double xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = c2a * x * y;            dY[4][0] = c2a * y;       dY[4][1] = c2a * x;
+        Y[5] = -c2a * y * z;           dY[5][1] = -c2a * z;      dY[5][2] = -c2a * y;
+        Y[6] = c2b * (2 * zz - xx - yy); dY[6][0] = -2 * c2b * x; dY[6][1] = -2 * c2b * y; dY[6][2] = 4 * c2b * z;
+        Y[7] = -c2a * x * z;           dY[7][0] = -c2a * z;      dY[7][2] = -c2a * x;
+        Y[8] = c2c * (xx - yy);        dY[8][0] = 2 * c2c * x;   dY[8][1] = -2 * c2c * y;
+    }
+    if (DEG >= 3) {
+        const double xx = x * x, yy = y * y, zz = z * z;
+        Y[9] = c3a * y * (3 * xx - yy);
+        dY[9][0] = 6 * c3a * x * y; dY[9][1] = 3 * c3a * (xx - yy);
+        Y[10] = c3b * x * y * z;
+        dY[10][0] = c3b * y * z; dY[10][1] = c3b * x * z; dY[10][2] = c3b * x * y;
+        Y[11] = c3c * y * (4 * zz - xx - yy);
+        dY[11][0] = -2 * c3c * x * y; dY[11][1] = c3c * (4 * zz - xx - 3 * yy); dY[11][2] = 8 * c3c * y * z;
+        Y[12] = c3d * z * (2 * zz - 3 * xx - 3 * yy);
+        dY[12][0] = -6 * c3d * x * z; dY[12][1] = -6 * c3d * y * z; dY[12][2] = 3 * c3d * (2 * zz - xx - yy);
+        Y[13] = c3c * x * (4 * zz - xx - yy);
+        dY[13][0] = c3c * (4 * zz - 3 * xx - yy); dY[13][1] = -2 * c3c * x * y; dY[13][2] = 8 * c3c * x * z;
+        Y[14] = c3e * z * (xx - yy);
+        dY[14][0] = 2 * c3e * x * z; dY[14][1] = -2 * c3e * y * z; dY[14][2] = c3e * (xx - yy);
+        Y[15] = c3a * x * (xx - 3 * yy);
+        dY[15][0] = 3 * c3a * (xx - yy); dY[15][1] = -6 * c3a * x * y;
+    }
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess_bwd(
+    const float *__restrict__ means, const float *__restrict__ log_scales, const float *__restrict__ quats,
+    const float *__restrict__ opacity_logits, const float *__restrict__ sh, int n, const DevView *__restrict__ views,
+    int n_views, const uint32_t *__restrict__ tile_counts, const float *__restrict__ record_grads,
+    float *__restrict__ g_means, float *__restrict__ g_log_scales, float *__restrict__ g_quats,
+    float *__restrict__ g_opacity, float *__restrict__ g_sh)
+{
+    constexpr int NK = (DEG + 1) * (DEG + 1);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool any = false;
+    for (int v = 0; v < n_views; ++v) any = any || tile_counts[(size_t)v * n + i] != 0;
+    if (!any) return;
+
+    const double m[3] = {means[i], means[n + i], means[2 * n + i]};
+    const double q[4] = {quats[i], quats[n + i], quats[2 * n + i], quats[3 * n + i]};
+    const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+    double R[9];
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+    const double s[3] = {exp((double)log_scales[i]), exp((double)log_scales[n + i]), exp((double)log_scales[2 * n + i])};
+    const double o = 1.0 / (1.0 + exp(-(double)opacity_logits[i]));
+    double shc[NK * 3];
+#pragma unroll
+    for (int k = 0; k < NK * 3; ++k) shc[k] = sh[(size_t)k * n + i];
+
+    double dm[3] = {0, 0, 0}, dl[3] = {0, 0, 0}, dR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, da = 0.0;
+    double dsh[NK * 3];
+#pragma unroll
+    for (int k = 0; k < NK * 3; ++k) dsh[k] = 0.0;
+
+    for (int v = 0; v < n_views; ++v) {
+        const size_t idx = (size_t)v * n + i;
+        if (tile_counts[idx] == 0) continue;
+        const DevView &V = views[v];
+        const float *gr = record_grads + idx * kGradFloats;
+        const double gu0 = gr[0], gv0 = gr[1], gM00 = gr[2], gM01 = gr[3], gM11 = gr[4], ggx = gr[5], ggy = gr[6];
+        const double gk0 = gr[7], gic2 = gr[8], go = gr[9], gcol[3] = {gr[10], gr[11], gr[12]};
+        const double *W = V.w2c;
+        const double mu[3] = {W[0] * m[0] + W[1] * m[1] + W[2] * m[2] + W[3],
+                              W[4] * m[0] + W[5] * m[1] + W[6] * m[2] + W[7],
+                              W[8] * m[0] + W[9] * m[1] + W[10] * m[2] + W[11]};
+        double Rp[9];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) Rp[3 * r + c] = W[4 * r] * R[c] + W[4 * r + 1] * R[3 + c] + W[4 * r + 2] * R[6 + c];
+        double A[3][3];  // A = S^-1 R_p^T
+        for (int k = 0; k < 3; ++k)
+            for (int j = 0; j < 3; ++j) A[k][j] = Rp[3 * j + k] / s[k];
+        double mw[3];
+        for (int k = 0; k < 3; ++k) mw[k] = A[k][0] * mu[0] + A[k][1] * mu[1] + A[k][2] * mu[2];
+        const double c2 = mw[0] * mw[0] + mw[1] * mw[1] + mw[2] * mw[2];
+        const double c4 = c2 * c2;
+        double A2[3][2];
+        for (int k = 0; k < 3; ++k) {
+            A2[k][0] = A[k][0] / V.fx;
+            A2[k][1] = A[k][1] / V.fy;
+        }
+        double wv[2];
+        for (int c = 0; c < 2; ++c) wv[c] = A2[0][c] * mw[0] + A2[1][c] * mw[1] + A2[2][c] * mw[2];
+        // symmetric matrix gradient of M (the off-diagonal parameter appears twice)
+        const double Gm[2][2] = {{gM00, 0.5 * gM01}, {0.5 * gM01, gM11}};
+        double dA2[3][2], dw[2], dc2;
+        for (int k = 0; k < 3; ++k)
+            for (int c = 0; c < 2; ++c) dA2[k][c] = 2.0 * (A2[k][0] * Gm[0][c] + A2[k][1] * Gm[1][c]);
+        const double Gw[2] = {Gm[0][0] * wv[0] + Gm[0][1] * wv[1], Gm[1][0] * wv[0] + Gm[1][1] * wv[1]};
+        dw[0] = -2.0 * Gw[0] / c2 + ggx / c2;
+        dw[1] = -2.0 * Gw[1] / c2 + ggy / c2;
+        dc2 = (wv[0] * Gw[0] + wv[1] * Gw[1]) / c4 - (ggx * wv[0] + ggy * wv[1]) / c4 - gic2 / c4;
+        // w = A2^T mu'
+        double dmw[3];
+        for (int k = 0; k < 3; ++k) {
+            dA2[k][0] += mw[k] * dw[0];
+            dA2[k][1] += mw[k] * dw[1];
+            dmw[k] = A2[k][0] * dw[0] + A2[k][1] * dw[1] + 2.0 * mw[k] * dc2;
+        }
+        // mu' = A mu, A2 = A[:, 0:2] diag(1/fx, 1/fy)
+        double dA[3][3], dmu[3];
+        for (int k = 0; k < 3; ++k)
+            for (int j = 0; j < 3; ++j) dA[k][j] = dmw[k] * mu[j];
+        for (int k = 0; k < 3; ++k) {
+            dA[k][0] += dA2[k][0] / V.fx;
+            dA[k][1] += dA2[k][1] / V.fy;
+        }
+        for (int j = 0; j < 3; ++j) dmu[j] = A[0][j] * dmw[0] + A[1][j] * dmw[1] + A[2][j] * dmw[2];
+        // k0 = 1/mu_z, projected centre (u0, v0)
+        const double iz = 1.0 / mu[2];
+        dmu[2] += -gk0 * iz * iz;
+        dmu[0] += gu0 * V.fx * iz;
+        dmu[1] += gv0 * V.fy * iz;
+        dmu[2] += -(gu0 * V.fx * mu[0] + gv0 * V.fy * mu[1]) * iz * iz;
+        // A[k][j] = R_p[j][k] / s_k
+        double dRp[9];
+        for (int k = 0; k < 3; ++k) {
+            double acc = 0.0;
+            for (int j = 0; j < 3; ++j) {
+                dRp[3 * j + k] = dA[k][j] / s[k];
+                acc += dA[k][j] * A[k][j];
+            }
+            dl[k] -= acc;
+        }
+        // R_p = W_rot R, mu = W_rot m + t
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) dR[3 * r + c] += W[r] * dRp[c] + W[4 + r] * dRp[3 + c] + W[8 + r] * dRp[6 + c];
+        for (int c = 0; c < 3; ++c) dm[c] += W[c] * dmu[0] + W[4 + c] * dmu[1] + W[8 + c] * dmu[2];
+        // prior opacity
+        da += go * o * (1.0 - o);
+        // colour: SH coefficients and the view direction
+        const double d0 = m[0] - V.centre[0], d1 = m[1] - V.centre[1], d2 = m[2] - V.centre[2];
+        const double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        const double dir[3] = {d0 / dist, d1 / dist, d2 / dist};
+        double Y[NK], dY[NK][3];
+        sh_basis_grad<DEG>(dir[0], dir[1], dir[2], Y, dY);
+        double ddir[3] = {0, 0, 0};
+        for (int ch = 0; ch < 3; ++ch) {
+            double raw = 0.5;
+            for (int k = 0; k < NK; ++k) raw += Y[k] * shc[3 * k + ch];
+            if (!(raw > 0.0)) continue;
+            for (int k = 0; k < NK; ++k) {
+                dsh[3 * k + ch] += Y[k] * gcol[ch];
+                for (int j = 0; j < 3; ++j) ddir[j] += gcol[ch] * shc[3 * k + ch] * dY[k][j];
+            }
+        }
+        const double pd = ddir[0] * dir[0] + ddir[1] * dir[1] + ddir[2] * dir[2];
+        for (int j = 0; j < 3; ++j) dm[j] += (ddir[j] - dir[j] * pd) / dist;
+    }
+    // quaternion: dR/d(w,x,y,z) of the unit quaternion, then the normalisation
+    const double J[9][4] = {{0, 0, -4 * y, -4 * z},       {-2 * z, 2 * y, 2 * x, -2 * w}, {2 * y, 2 * z, 2 * w, 2 * x},
+                            {2 * z, 2 * y, 2 * x, 2 * w}, {0, -4 * x, 0, -4 * z},         {-2 * x, -2 * w, 2 * z, 2 * y},
+                            {-2 * y, 2 * z, -2 * w, 2 * x}, {2 * x, 2 * w, 2 * z, 2 * y}, {0, -4 * x, -4 * y, 0}};
+    double dqh[4] = {0, 0, 0, 0};
+    for (int e = 0; e < 9; ++e)
+        for (int k = 0; k < 4; ++k) dqh[k] += dR[e] * J[e][k];
+    const double qh[4] = {w, x, y, z};
+    const double proj = qh[0] * dqh[0] + qh[1] * dqh[1] + qh[2] * dqh[2] + qh[3] * dqh[3];
+    for (int k = 0; k < 4; ++k) g_quats[(size_t)k * n + i] += (float)((dqh[k] - qh[k] * proj) / qn);
+    for (int k = 0; k < 3; ++k) {
+        g_means[(size_t)k * n + i] += (float)dm[k];
+        g_log_scales[(size_t)k * n + i] += (float)dl[k];
+    }
+    g_opacity[i] += (float)da;
+#pragma unroll
+    for (int k = 0; k < NK * 3; ++k) g_sh[(size_t)k * n + i] += (float)dsh[k];
+}
+
+}  // namespace
+
+hipError_t launch_preprocess_backward(const rgs_gaussians &g, const DevView *views, int n_views,
+                                      const DevOptions &opt, const uint32_t *tile_counts, const float *record_grads,
+                                      const rgs_gaussian_grads &gr, hipStream_t stream)
+{
+    (void)opt;
+    const int n = (int)g.n;
+    if (n == 0) return hipSuccess;
+    const dim3 grid((n + 255) / 256), block(256);
+#define RGS_BWD(D)                                                                                                  \
+    k_preprocess_bwd<D><<<grid, block, 0, stream>>>(g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, n,      \
+                                                    views, n_views, tile_counts, record_grads, gr.means,            \
+                                                    gr.log_scales, gr.quats, gr.opacity_logits, gr.sh)
+    switch (g.sh_degree) {
+    case 0: RGS_BWD(0); break;
+    case 1: RGS_BWD(1); break;
+    case 2: RGS_BWD(2); break;
+    default: RGS_BWD(3); break;
+    }
+#undef RGS_BWD
+    return hipGetLastError();
+}
+
+}  // namespace rgs

@@ -1,0 +1,381 @@
+// Per-pixel compositing (forward and backward).
+//
+// Work decomposition: one wavefront (64 lanes) owns one screen tile of
+// TW x TH pixels; lane l covers column l % TW and rows l / TW + k * (64 / TW),
+// k < TW * TH / 64.  Waves of a workgroup are independent: each pulls tile ids
+// from a global atomic queue (persistent grid), stages 64 raster records at a
+// time in its own LDS slice and reads them back as broadcasts, and leaves the
+// tile as soon as a ballot shows that no lane has a live pixel (early ray
+// termination).  No workgroup barrier is ever taken.
+//
+// Per fragment (Sec. 4.2, eq. 16): with delta the pixel-centre offset from the
+// projected centre, n = G delta is the quad-plane offset times den and
+// den = k0 + g . delta is proportional to x^T Sigma^-1 mu (> 0 iff tau > 0),
+// so |zeta|^2 = q / den^2 with q = |n|^2 and
+//     D = (c^-2 + |zeta|^-2)^-1 = q / (den^2 + q / c^2),
+// a form without the cancellation of c^2 - (x^T Sigma^-1 mu)^2 / x^T Sigma^-1 x.
+// omega = o exp(-D/2) (eq. 2); a Gaussian contributes iff den > 0 and
+// omega >= p_min; alpha = min(omega, alpha_max); compositing (eq. 1) stops
+// before a Gaussian that would take T below t_eps.
+#include "internal.h"
+
+#pragma clang fp contract(off)
+
+namespace rgs {
+namespace {
+
+struct Rec {
+    float u_hi, v_hi, u_lo, v_lo, G00, G01, G10, G11, gx, gy, k0, ic2, log2o, r, g, b;
+};
+
+struct Frag {
+    float dx, dy, n0, n1, den, q, rt, D, w;
+};
+
+__device__ __forceinline__ Rec load_rec(const float4 *p)
+{
+    const float4 a = p[0], b = p[1], c = p[2], d = p[3];
+    return Rec{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w};
+}
+
+// The single per-fragment instruction sequence shared by the forward and the
+// backward kernel (explicit fma, no contraction), so both take identical
+// decisions.  Returns den > 0.
+__device__ __forceinline__ bool eval_fragment(const Rec &R, float pxc, float pyc, Frag &f)
+{
+    f.dx = (pxc - R.u_hi) - R.u_lo;
+    f.dy = (pyc - R.v_hi) - R.v_lo;
+    f.n0 = __builtin_fmaf(R.G01, f.dy, R.G00 * f.dx);
+    f.n1 = __builtin_fmaf(R.G11, f.dy, R.G10 * f.dx);
+    f.den = __builtin_fmaf(R.gy, f.dy, __builtin_fmaf(R.gx, f.dx, R.k0));
+    f.q = __builtin_fmaf(f.n1, f.n1, f.n0 * f.n0);
+    const float t = __builtin_fmaf(f.q, R.ic2, f.den * f.den);
+    f.rt = __builtin_amdgcn_rcpf(t);
+    f.D = f.q * f.rt;
+    // omega = o * 2^(-D log2(e) / 2)
+    f.w = __builtin_amdgcn_exp2f(__builtin_fmaf(f.D, -0.72134752044448170f, R.log2o));
+    return f.den > 0.0f;
+}
+
+__device__ __forceinline__ void lds_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int find_view(const DevView *views, int n_views, int tile)
+{
+    int v = 0;
+    while (v + 1 < n_views && views[v + 1].tile_base <= tile) ++v;
+    return v;
+}
+
+struct BlendParams {
+    float p_min, alpha_max, t_eps, bg0, bg1, bg2;
+    int n_views, total_tiles;
+    uint32_t n_records;
+};
+
+// Stage one record into LDS; an id outside the record array (never produced
+// by the binning) is replaced by a record whose den is negative everywhere.
+__device__ __forceinline__ void stage_record(float4 *dst, const float4 *__restrict__ records, uint32_t id,
+                                             uint32_t n_records)
+{
+    if (id < n_records) {
+        const float4 *src = records + (size_t)id * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) dst[c] = src[c];
+    } else {
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        dst[0] = z;
+        dst[1] = z;
+        dst[2] = make_float4(0.f, 0.f, -1.f, 0.f);
+        dst[3] = make_float4(-126.f, 0.f, 0.f, 0.f);
+    }
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ inst_ids,
+                                               const float4 *__restrict__ records, const DevView *__restrict__ views,
+                                               BlendParams P, unsigned int *__restrict__ queue)
+{
+    constexpr int LX = TW, LY = 64 / TW, PPL = TH / LY;
+    static_assert(64 % TW == 0 && TH % LY == 0, "tile shape");
+    __shared__ float4 s_rec[4][64][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lx = lane % LX, ly = lane / LX;
+    for (;;) {
+        int tile = 0;
+        if (lane == 0) tile = (int)atomicAdd(queue, 1u);
+        tile = __shfl(tile, 0, 64);
+        if (tile >= P.total_tiles) break;
+        const DevView &V = views[find_view(views, P.n_views, tile)];
+        const int local = tile - V.tile_base;
+        const int tx = local % V.tiles_x, ty = local / V.tiles_x;
+        const int px = tx * TW + lx;
+        const float pxc = (float)px + 0.5f;
+        float T[PPL], C0[PPL], C1[PPL], C2[PPL], pyc[PPL];
+        int last[PPL];
+        bool live[PPL];
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            const int py = ty * TH + ly + k * LY;
+            pyc[k] = (float)py + 0.5f;
+            T[k] = 1.0f;
+            C0[k] = C1[k] = C2[k] = 0.0f;
+            last[k] = 0;
+            live[k] = px < V.width && py < V.height;
+        }
+        const uint2 rg = ranges[tile];
+        bool wave_live = true;
+        for (uint32_t base = rg.x; base < rg.y && wave_live; base += 64) {
+            const uint32_t nb = min(64u, rg.y - base);
+            if ((uint32_t)lane < nb) stage_record(s_rec[wave][lane], records, inst_ids[base + lane], P.n_records);
+            lds_wave_sync();
+            for (uint32_t j = 0; j < nb; ++j) {
+                const Rec R = load_rec(s_rec[wave][j]);
+                bool any = false;
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) {
+                    if (!live[k]) continue;
+                    Frag f;
+                    const bool front = eval_fragment(R, pxc, pyc[k], f);
+                    if (front && f.w >= P.p_min) {
+                        const float a = fminf(f.w, P.alpha_max);
+                        const float Tn = T[k] * (1.0f - a);
+                        if (Tn < P.t_eps) {
+                            live[k] = false;
+                        } else {
+                            const float wt = T[k] * a;
+                            C0[k] += wt * R.r;
+                            C1[k] += wt * R.g;
+                            C2[k] += wt * R.b;
+                            T[k] = Tn;
+                            last[k] = (int)(base - rg.x + j + 1);
+                        }
+                    }
+                    any = any || live[k];
+                }
+                if (__ballot(any) == 0) {
+                    wave_live = false;
+                    break;
+                }
+            }
+            lds_wave_sync();
+        }
+        const size_t plane = (size_t)V.width * V.height;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            const int py = ty * TH + ly + k * LY;
+            if (px < V.width && py < V.height) {
+                const size_t p = (size_t)py * V.width + px;
+                V.rgb[p] = C0[k] + T[k] * P.bg0;
+                V.rgb[plane + p] = C1[k] + T[k] * P.bg1;
+                V.rgb[2 * plane + p] = C2[k] + T[k] * P.bg2;
+                V.final_T[p] = T[k];
+                V.n_contrib[p] = last[k];
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ float wave_sum(float x)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ranges,
+                                                   const uint32_t *__restrict__ inst_ids,
+                                                   const float4 *__restrict__ records,
+                                                   const DevView *__restrict__ views, BlendParams P,
+                                                   float *__restrict__ record_grads, unsigned int *__restrict__ queue)
+{
+    constexpr int LX = TW, LY = 64 / TW, PPL = TH / LY;
+    __shared__ float4 s_rec[4][64][4];
+    __shared__ uint32_t s_id[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lx = lane % LX, ly = lane / LX;
+    for (;;) {
+        int tile = 0;
+        if (lane == 0) tile = (int)atomicAdd(queue, 1u);
+        tile = __shfl(tile, 0, 64);
+        if (tile >= P.total_tiles) break;
+        const DevView &V = views[find_view(views, P.n_views, tile)];
+        const int local = tile - V.tile_base;
+        const int tx = local % V.tiles_x, ty = local / V.tiles_x;
+        const int px = tx * TW + lx;
+        const float pxc = (float)px + 0.5f;
+        const size_t plane = (size_t)V.width * V.height;
+        float T[PPL], S[PPL], g0[PPL], g1[PPL], g2[PPL], pyc[PPL];
+        int last[PPL];
+        int maxlast = 0;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            const int py = ty * TH + ly + k * LY;
+            pyc[k] = (float)py + 0.5f;
+            T[k] = 1.0f;
+            S[k] = 0.0f;
+            g0[k] = g1[k] = g2[k] = 0.0f;
+            last[k] = 0;
+            if (px < V.width && py < V.height) {
+                const size_t p = (size_t)py * V.width + px;
+                T[k] = V.final_T[p];
+                last[k] = V.n_contrib[p];
+                g0[k] = V.dL_drgb[p];
+                g1[k] = V.dL_drgb[plane + p];
+                g2[k] = V.dL_drgb[2 * plane + p];
+                S[k] = T[k] * (P.bg0 * g0[k] + P.bg1 * g1[k] + P.bg2 * g2[k]);
+                maxlast = max(maxlast, last[k]);
+            }
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, d, 64));
+        const uint2 rg = ranges[tile];
+        maxlast = min(maxlast, (int)(rg.y - rg.x));
+        for (int hi = maxlast; hi > 0; hi -= 64) {
+            const int lo = hi > 64 ? hi - 64 : 0;
+            const int nb = hi - lo;
+            if (lane < nb) {
+                const uint32_t id = inst_ids[rg.x + lo + lane];
+                s_id[wave][lane] = id < P.n_records ? id : 0xffffffffu;
+                stage_record(s_rec[wave][lane], records, id, P.n_records);
+            }
+            lds_wave_sync();
+            for (int jj = nb - 1; jj >= 0; --jj) {
+                const int j = lo + jj;
+                const Rec R = load_rec(s_rec[wave][jj]);
+                const float inv_o = __builtin_amdgcn_exp2f(-R.log2o);
+                float du0 = 0, dv0 = 0, dM00 = 0, dM01 = 0, dM11 = 0, dgx = 0, dgy = 0, dk0 = 0, dic2 = 0, dop = 0,
+                      dr = 0, dg = 0, db = 0;
+                bool hit = false;
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) {
+                    if (j >= last[k]) continue;
+                    Frag f;
+                    const bool front = eval_fragment(R, pxc, pyc[k], f);
+                    if (!(front && f.w >= P.p_min)) continue;
+                    hit = true;
+                    const float a = fminf(f.w, P.alpha_max);
+                    const float om = 1.0f - a;
+                    const float Tb = T[k] / om;  // transmittance in front of this Gaussian
+                    const float rgd = R.r * g0[k] + R.g * g1[k] + R.b * g2[k];
+                    const float ta = Tb * a;
+                    dr += ta * g0[k];
+                    dg += ta * g1[k];
+                    db += ta * g2[k];
+                    const float dL_da = Tb * rgd - S[k] / om;
+                    S[k] += ta * rgd;
+                    T[k] = Tb;
+                    if (f.w < P.alpha_max) {
+                        dop += dL_da * f.w * inv_o;
+                        const float dL_dD = -0.5f * f.w * dL_da;
+                        const float rt2 = f.rt * f.rt;
+                        const float dL_dq = dL_dD * (f.den * f.den) * rt2;
+                        const float dL_dden = dL_dD * (-2.0f * f.q * f.den) * rt2;
+                        dic2 += dL_dD * (-(f.q * f.q)) * rt2;
+                        dM00 += dL_dq * (f.dx * f.dx);
+                        dM01 += dL_dq * (2.0f * f.dx * f.dy);
+                        dM11 += dL_dq * (f.dy * f.dy);
+                        dk0 += dL_dden;
+                        dgx += dL_dden * f.dx;
+                        dgy += dL_dden * f.dy;
+                        const float dq_ddx = 2.0f * (R.G00 * f.n0 + R.G10 * f.n1);
+                        const float dq_ddy = 2.0f * (R.G01 * f.n0 + R.G11 * f.n1);
+                        du0 -= dL_dq * dq_ddx + dL_dden * R.gx;
+                        dv0 -= dL_dq * dq_ddy + dL_dden * R.gy;
+                    }
+                }
+                if (__ballot(hit) == 0) continue;
+                float vals[13] = {du0, dv0, dM00, dM01, dM11, dgx, dgy, dk0, dic2, dop, dr, dg, db};
+#pragma unroll
+                for (int c = 0; c < 13; ++c) vals[c] = wave_sum(vals[c]);
+                if (lane == 0 && s_id[wave][jj] != 0xffffffffu) {
+                    float *dst = record_grads + (size_t)s_id[wave][jj] * kGradFloats;
+#pragma unroll
+                    for (int c = 0; c < 13; ++c) atomicAdd(dst + c, vals[c]);
+                }
+            }
+            lds_wave_sync();
+        }
+    }
+}
+
+template <int TW, int TH>
+int occupancy_grid(const void *kernel, int num_cus)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    return per_cu * num_cus;
+}
+
+BlendParams make_params(const DevOptions &opt, int n_views, int64_t total_tiles, int64_t n_records)
+{
+    return BlendParams{(float)opt.p_min, (float)opt.alpha_max, (float)opt.t_eps, opt.bg[0], opt.bg[1], opt.bg[2],
+                       n_views, (int)total_tiles, (uint32_t)n_records};
+}
+
+}  // namespace
+
+bool tile_shape_supported(int w, int h)
+{
+    return (w == 8 && h == 8) || (w == 16 && h == 8) || (w == 16 && h == 16) || (w == 32 && h == 16) ||
+           (w == 32 && h == 32);
+}
+
+#define RGS_SHAPES(X) X(8, 8) X(16, 8) X(16, 16) X(32, 16) X(32, 32)
+
+int blend_grid(TileShape s, int num_cus)
+{
+#define X(W, H) \
+    if (s.w == W && s.h == H) return occupancy_grid<W, H>(reinterpret_cast<const void *>(&k_blend<W, H>), num_cus);
+    RGS_SHAPES(X)
+#undef X
+    return num_cus;
+}
+
+int blend_backward_grid(TileShape s, int num_cus)
+{
+#define X(W, H)                                                                                                  \
+    if (s.w == W && s.h == H)                                                                                    \
+        return occupancy_grid<W, H>(reinterpret_cast<const void *>(&k_blend_bwd<W, H>), num_cus);
+    RGS_SHAPES(X)
+#undef X
+    return num_cus;
+}
+
+hipError_t launch_blend(TileShape s, const uint2 *ranges, const uint32_t *inst_ids, const float4 *records,
+                        const DevView *views, int n_views, int64_t total_tiles, int64_t n_records,
+                        const DevOptions &opt, unsigned int *queue, int grid, hipStream_t stream)
+{
+    const BlendParams P = make_params(opt, n_views, total_tiles, n_records);
+#define X(W, H)                                                                                         \
+    if (s.w == W && s.h == H) {                                                                         \
+        k_blend<W, H><<<grid, 256, 0, stream>>>(ranges, inst_ids, records, views, P, queue);            \
+        return hipGetLastError();                                                                       \
+    }
+    RGS_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_blend_backward(TileShape s, const uint2 *ranges, const uint32_t *inst_ids, const float4 *records,
+                                 const DevView *views, int n_views, int64_t total_tiles, int64_t n_records,
+                                 const DevOptions &opt, float *record_grads, unsigned int *queue, int grid,
+                                 hipStream_t stream)
+{
+    const BlendParams P = make_params(opt, n_views, total_tiles, n_records);
+#define X(W, H)                                                                                                  \
+    if (s.w == W && s.h == H) {                                                                                  \
+        k_blend_bwd<W, H><<<grid, 256, 0, stream>>>(ranges, inst_ids, records, views, P, record_grads, queue);   \
+        return hipGetLastError();                                                                                \
+    }
+    RGS_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+}  // namespace rgs

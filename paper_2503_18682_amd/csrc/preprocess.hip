@@ -1,0 +1,296 @@
+// Per Gaussian-view stage: activation, camera transform, culling, MIP
+// transform, the 3D bounding quad, its pixel/tile rectangle, the depth key and
+// the raster record consumed by the compositing kernel.
+//
+// One thread per Gaussian loops over the views of the batch, so the
+// parameters (236 B per Gaussian at SH degree 3) are read from HBM once per
+// batch with coalesced structure-of-arrays loads.  Everything up to the tile
+// rectangle and the depth key is evaluated in double precision (full rate on
+// CDNA) with FMA contraction disabled, so the integer decisions (culls, tile
+// rectangles, keys) are those of an exact evaluation up to double rounding.
+#include "internal.h"
+
+#pragma clang fp contract(off)
+
+namespace rgs {
+namespace {
+
+// Orthonormal real spherical harmonics up to degree 3 (index l^2 + l + m) in
+// the sign convention of Gaussian-splatting colour models.
+template <int DEG>
+__device__ __forceinline__ void sh_basis(double x, double y, double z, double *Y)
+{
+    Y[0] = 0.28209479177387814;
+    if (DEG >= 1) {
+        Y[1] = -0.48860251190291992 * y;
+        Y[2] = 0.48860251190291992 * z;
+        Y[3] = -0.48860251190291992 * x;
+    }
+    if (DEG >= 2) {
+        const double xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = 1.0925484305920792 * x * y;
+        Y[5] = -1.0925484305920792 * y * z;
+        Y[6] = 0.31539156525252005 * (2.0 * zz - xx - yy);
+        Y[7] = -1.0925484305920792 * x * z;
+        Y[8] = 0.54627421529603959 * (xx - yy);
+    }
+    if (DEG >= 3) {
+        const double xx = x * x, yy = y * y, zz = z * z;
+        Y[9] = -0.59004358992664352 * y * (3.0 * xx - yy);
+        Y[10] = 2.8906114426405538 * x * y * z;
+        Y[11] = -0.45704579946446572 * y * (4.0 * zz - xx - yy);
+        Y[12] = 0.37317633259011540 * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+        Y[13] = -0.45704579946446572 * x * (4.0 * zz - xx - yy);
+        Y[14] = 1.4453057213202769 * z * (xx - yy);
+        Y[15] = -0.59004358992664352 * x * (xx - 3.0 * yy);
+    }
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ means,
+                                                    const float *__restrict__ log_scales,
+                                                    const float *__restrict__ quats,
+                                                    const float *__restrict__ opacity_logits,
+                                                    const float *__restrict__ sh, int n,
+                                                    const DevView *__restrict__ views, int n_views, DevOptions opt,
+                                                    float4 *__restrict__ records, uint32_t *__restrict__ depth_keys,
+                                                    uint32_t *__restrict__ order, uint2 *__restrict__ rects,
+                                                    uint32_t *__restrict__ tile_counts)
+{
+    constexpr int NK = (DEG + 1) * (DEG + 1);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+
+    const double m[3] = {means[i], means[n + i], means[2 * n + i]};
+    const float lf[3] = {log_scales[i], log_scales[n + i], log_scales[2 * n + i]};
+    const float qf[4] = {quats[i], quats[n + i], quats[2 * n + i], quats[3 * n + i]};
+    const float af = opacity_logits[i];
+    float shc[NK * 3];
+    bool ok = isfinite(af);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ok = ok && isfinite((float)m[k]) && isfinite(lf[k]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ok = ok && isfinite(qf[k]);
+#pragma unroll
+    for (int k = 0; k < NK * 3; ++k) {
+        shc[k] = sh[(size_t)k * n + i];
+        ok = ok && isfinite(shc[k]);
+    }
+    const double q[4] = {qf[0], qf[1], qf[2], qf[3]};
+    const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    ok = ok && qn > 0.0;
+
+    // Sigma = R S^2 R^T in the world frame: rotation of the unit quaternion,
+    // s = exp(l), prior opacity o = sigmoid(a).
+    double R[9], s[3], o = 0.0;
+    {
+        const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+        R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+        R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+        R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+        for (int k = 0; k < 3; ++k) s[k] = exp((double)lf[k]);
+        o = 1.0 / (1.0 + exp(-(double)af));
+    }
+
+    for (int v = 0; v < n_views; ++v) {
+        const DevView &V = views[v];
+        const size_t idx = (size_t)v * n + i;
+        order[idx] = (uint32_t)idx;
+        uint32_t key = 0xffffffffu, cnt = 0;
+        uint2 rect = make_uint2(0u, 0u);
+        const double *W = V.w2c;
+        // camera-frame centre
+        const double mu[3] = {W[0] * m[0] + W[1] * m[1] + W[2] * m[2] + W[3],
+                              W[4] * m[0] + W[5] * m[1] + W[6] * m[2] + W[7],
+                              W[8] * m[0] + W[9] * m[1] + W[10] * m[2] + W[11]};
+        do {
+            if (!ok || !(mu[2] > opt.near_z)) break;
+            double Rp[9];  // R_p = W_rot R
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c)
+                    Rp[3 * r + c] = W[4 * r] * R[c] + W[4 * r + 1] * R[3 + c] + W[4 * r + 2] * R[6 + c];
+            double sv[3] = {s[0], s[1], s[2]};
+            double ov = o;
+            double ml[3];  // R_p^T mu: centre in the Gaussian's own axes
+            for (int c = 0; c < 3; ++c) ml[c] = Rp[c] * mu[0] + Rp[3 + c] * mu[1] + Rp[6 + c] * mu[2];
+            if (opt.mip) {
+                // Approximate MIP (Sec. 5, eq. 17): add sigma^2 |mu|^2 to every
+                // variance (pixel-invariant tau = |mu|) and scale the opacity by
+                // sqrt(|Sigma| c^2 / (|Sigma^| c^^2)).
+                const double tb = sqrt(mu[0] * mu[0] + mu[1] * mu[1] + mu[2] * mu[2]);
+                const double sig2 = opt.mip_sigma2_px / (V.fx * V.fy);
+                double det = 1.0, deth = 1.0, c2p = 0.0, c2h = 0.0, sh2[3];
+                for (int k = 0; k < 3; ++k) {
+                    const double s2 = sv[k] * sv[k];
+                    sh2[k] = s2 + sig2 * tb * tb;
+                    det *= s2;
+                    deth *= sh2[k];
+                    c2p += ml[k] * ml[k] / s2;
+                    c2h += ml[k] * ml[k] / sh2[k];
+                }
+                ov = ov * sqrt(det * c2p / (deth * c2h));
+                for (int k = 0; k < 3; ++k) sv[k] = sqrt(sh2[k]);
+            }
+            // support cut-off (eq. 3) and the camera-inside skip (eq. 6)
+            const double kappa = -2.0 * log(opt.p_min / ov);
+            if (!(kappa > 0.0)) break;
+            const double mw[3] = {ml[0] / sv[0], ml[1] / sv[1], ml[2] / sv[2]};
+            const double c2 = mw[0] * mw[0] + mw[1] * mw[1] + mw[2] * mw[2];
+            if (!(c2 > kappa)) break;
+
+            // Sec. 4.1: whitened unit centre, b, R_{mu^ <- v} (App. A.1)
+            const double c = sqrt(c2);
+            const double muh[3] = {mw[0] / c, mw[1] / c, mw[2] / c};
+            const double b = sqrt(1.0 - kappa / c2);
+            double Rv[9];
+            {
+                const double sgn = muh[2] >= 0.0 ? 1.0 : -1.0;  // align to v or to -v
+                const double a3[3] = {muh[0], muh[1], muh[2] + sgn};
+                const double a2 = a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2];
+                for (int r = 0; r < 3; ++r)
+                    for (int cc = 0; cc < 3; ++cc) Rv[3 * r + cc] = 2.0 * a3[r] * a3[cc] / a2 - (r == cc ? 1.0 : 0.0);
+                if (sgn < 0.0)  // right-multiply by P = diag(-1, 1, -1)
+                    for (int r = 0; r < 3; ++r) {
+                        Rv[3 * r] = -Rv[3 * r];
+                        Rv[3 * r + 2] = -Rv[3 * r + 2];
+                    }
+            }
+            // Q = R_p S R_v, B = Q_{0:2}^T Q_{0:2} (eq. 14)
+            double Q[9];
+            for (int r = 0; r < 3; ++r)
+                for (int cc = 0; cc < 3; ++cc)
+                    Q[3 * r + cc] = (Rp[3 * r] * sv[0]) * Rv[cc] + (Rp[3 * r + 1] * sv[1]) * Rv[3 + cc] +
+                                    (Rp[3 * r + 2] * sv[2]) * Rv[6 + cc];
+            double Ba = 0.0, Bh = 0.0, Bd = 0.0;
+            for (int r = 0; r < 3; ++r) {
+                Ba += Q[3 * r] * Q[3 * r];
+                Bh += Q[3 * r] * Q[3 * r + 1];
+                Bd += Q[3 * r + 1] * Q[3 * r + 1];
+            }
+            // closed-form top eigenvector u1 of the 2x2 B; u0 = u1 turned by +90 degrees
+            const double mean = 0.5 * (Ba + Bd);
+            const double rad = sqrt(0.25 * (Ba - Bd) * (Ba - Bd) + Bh * Bh);
+            const double lmax = mean + rad;
+            double u1x = 1.0, u1y = 0.0;
+            if (!(2.0 * rad <= 1e-6 * lmax)) {
+                const double v1x = Bh, v1y = lmax - Ba, v2x = lmax - Bd, v2y = Bh;
+                const double n1 = sqrt(v1x * v1x + v1y * v1y), n2 = sqrt(v2x * v2x + v2y * v2y);
+                if (n1 >= n2) {
+                    u1x = v1x / n1;
+                    u1y = v1y / n1;
+                } else {
+                    u1x = v2x / n2;
+                    u1y = v2y / n2;
+                }
+            }
+            const double u0x = -u1y, u0y = u1x;
+            // quad vertices V_k = mu + Q_{0:2} U (sqrt(kappa)/b) O_k (eq. 15)
+            const double hs = sqrt(kappa) / b;
+            double QU[6];
+            for (int r = 0; r < 3; ++r) {
+                QU[2 * r] = Q[3 * r] * u0x + Q[3 * r + 1] * u0y;
+                QU[2 * r + 1] = Q[3 * r] * u1x + Q[3 * r + 1] * u1y;
+            }
+            const double O0[4] = {-1.0, -1.0, 1.0, 1.0}, O1[4] = {-1.0, 1.0, 1.0, -1.0};
+            bool all_front = true;
+            double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+            for (int k = 0; k < 4; ++k) {
+                const double z0 = hs * O0[k], z1 = hs * O1[k];
+                const double Vx = QU[0] * z0 + QU[1] * z1 + mu[0];
+                const double Vy = QU[2] * z0 + QU[3] * z1 + mu[1];
+                const double Vz = QU[4] * z0 + QU[5] * z1 + mu[2];
+                if (!(Vz > 0.0)) all_front = false;
+                const double u = V.fx * Vx / Vz + V.cx;
+                const double vv = V.fy * Vy / Vz + V.cy;
+                umin = fmin(umin, u);
+                umax = fmax(umax, u);
+                vmin = fmin(vmin, vv);
+                vmax = fmax(vmax, vv);
+            }
+            // pixel centres inside the box; no near-plane clipping of the quad,
+            // so a vertex at z <= 0 makes the box the whole view
+            const int Wd = V.width, Hd = V.height;
+            int px0 = 0, px1 = Wd - 1, py0 = 0, py1 = Hd - 1;
+            if (all_front) {
+                const double fx0 = ceil(umin - 0.5), fx1 = floor(umax - 0.5);
+                const double fy0 = ceil(vmin - 0.5), fy1 = floor(vmax - 0.5);
+                px0 = fx0 < 0.0 ? 0 : (fx0 > Wd ? Wd : (int)fx0);
+                px1 = fx1 > Wd - 1 ? Wd - 1 : (fx1 < -1.0 ? -1 : (int)fx1);
+                py0 = fy0 < 0.0 ? 0 : (fy0 > Hd ? Hd : (int)fy0);
+                py1 = fy1 > Hd - 1 ? Hd - 1 : (fy1 < -1.0 ? -1 : (int)fy1);
+            }
+            if (px0 > px1 || py0 > py1) break;
+            const int tx0 = px0 / opt.tile_w, tx1 = px1 / opt.tile_w;
+            const int ty0 = py0 / opt.tile_h, ty1 = py1 / opt.tile_h;
+            cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+            rect = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
+            key = __float_as_uint((float)mu[2]);
+
+            // ---- raster record (float32) ----
+            // projected centre as a (hi, lo) float pair
+            const double u_c = V.fx * mu[0] / mu[2] + V.cx;
+            const double v_c = V.fy * mu[1] / mu[2] + V.cy;
+            const float u_hi = (float)u_c, v_hi = (float)v_c;
+            const float u_lo = (float)(u_c - (double)u_hi), v_lo = (float)(v_c - (double)v_hi);
+            // A2 = (S^-1 R_p^T)[:, 0:2] diag(1/fx, 1/fy): a pixel offset delta moves
+            // the whitened ray direction by A2 delta.
+            double A2[3][2];
+            for (int k = 0; k < 3; ++k) {
+                A2[k][0] = Rp[k] / sv[k] / V.fx;
+                A2[k][1] = Rp[3 + k] / sv[k] / V.fy;
+            }
+            // G = R_v[:, 0:2]^T A2 maps delta to the quad-plane offset (times den)
+            double G[2][2];
+            for (int r = 0; r < 2; ++r)
+                for (int cc = 0; cc < 2; ++cc)
+                    G[r][cc] = Rv[r] * A2[0][cc] + Rv[3 + r] * A2[1][cc] + Rv[6 + r] * A2[2][cc];
+            const double gx = (A2[0][0] * mw[0] + A2[1][0] * mw[1] + A2[2][0] * mw[2]) / c2;
+            const double gy = (A2[0][1] * mw[0] + A2[1][1] * mw[1] + A2[2][1] * mw[2]) / c2;
+            // colour from the view direction (camera centre -> mean, world frame)
+            const double d0 = m[0] - V.centre[0], d1 = m[1] - V.centre[1], d2 = m[2] - V.centre[2];
+            const double dn = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            double Y[NK];
+            sh_basis<DEG>(d0 / dn, d1 / dn, d2 / dn, Y);
+            double col[3];
+            for (int ch = 0; ch < 3; ++ch) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < NK; ++k) acc += Y[k] * (double)shc[3 * k + ch];
+                acc += 0.5;
+                col[ch] = acc > 0.0 ? acc : 0.0;
+            }
+            float4 *rec = records + idx * 4;
+            rec[0] = make_float4(u_hi, v_hi, u_lo, v_lo);
+            rec[1] = make_float4((float)G[0][0], (float)G[0][1], (float)G[1][0], (float)G[1][1]);
+            rec[2] = make_float4((float)gx, (float)gy, (float)(1.0 / mu[2]), (float)(1.0 / c2));
+            rec[3] = make_float4((float)log2(ov), (float)col[0], (float)col[1], (float)col[2]);
+        } while (false);
+        depth_keys[idx] = cnt ? key : 0xffffffffu;
+        tile_counts[idx] = cnt;
+        rects[idx] = rect;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n_views, const DevOptions &opt,
+                             float4 *records, uint32_t *depth_keys, uint32_t *order, uint2 *rects,
+                             uint32_t *tile_counts, hipStream_t stream)
+{
+    const int n = (int)g.n;
+    if (n == 0) return hipSuccess;
+    const dim3 grid((n + 255) / 256), block(256);
+#define RGS_PRE(D)                                                                                                 \
+    k_preprocess<D><<<grid, block, 0, stream>>>(g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, n, views, \
+                                                n_views, opt, records, depth_keys, order, rects, tile_counts)
+    switch (g.sh_degree) {
+    case 0: RGS_PRE(0); break;
+    case 1: RGS_PRE(1); break;
+    case 2: RGS_PRE(2); break;
+    default: RGS_PRE(3); break;
+    }
+#undef RGS_PRE
+    return hipGetLastError();
+}
+
+}  // namespace rgs

@@ -1,0 +1,247 @@
+"""GPU parity of the HIP renderer (through the C ABI) against the CPU oracle.
+
+Images: max-abs <= 2e-4 in [0, 1] outside the oracle's hazard mask (pixels
+where a threshold decision lies within rounding distance).  Depth keys, tile
+rectangles and tile lists: bit-exact, excluding Gaussians the oracle flags as
+hazards (expected count ~0)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen
+from gpu_helpers import (assert_image_close, instance_lists, oracle_lists_without_hazards, read, render_with_ws, say,
+                         to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def r():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_18682_amd import renderer as R
+
+    rr = R.Renderer(0)
+    yield rr
+    rr.close()
+
+
+def _check_lists(buf, lay, m, sp, cam, opts, label):
+    tiles, ids = instance_lists(buf, lay, m)
+    ot, ok_, oi, bad = oracle_lists_without_hazards(sp, cam, opts)
+    keep = ~np.isin(ids, list(bad)) if bad else np.ones_like(ids, bool)
+    say(f"  {label}: {m} instances, {len(bad)} hazard Gaussians excluded")
+    assert np.array_equal(tiles[keep], ot) and np.array_equal(ids[keep], oi)
+
+
+def test_c0_image_keys_and_lists(r):
+    say("case c0: 1000 Gaussians, 128x128")
+    w = scenegen.make_workload("c0")
+    sc, cam, opts = w["scene"], w["cameras"][0], w["options"]
+    outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
+    assert ok
+    ref = oracle.render(sc, cam, opts)
+    assert m == ref["counters"]["instances"]
+    assert_image_close(outs[0]["rgb"], outs[0]["final_T"], ref, label="c0")
+    sp = oracle.preprocess(sc, cam, opts)
+    assert (sp["hazard"] & oracle.HAZARD["cull"]).sum() == 0
+    # depth keys and tile rectangles of every visible Gaussian
+    n = sc["opacity_logits"].shape[0]
+    keys = read(buf, lay.depth_keys, n, np.uint32)
+    order = read(buf, lay.order, n, np.uint32)
+    gpu_key = np.full(n, 0xFFFFFFFF, np.uint32)
+    gpu_key[order] = keys
+    vis = sp["cull"] == 0
+    assert np.array_equal(gpu_key[vis], sp["depth_key"][vis])
+    assert np.all(gpu_key[~vis] == 0xFFFFFFFF)
+    rects = read(buf, lay.rects, 4 * n, np.uint16).reshape(n, 4)
+    good = vis & (sp["hazard"] == 0)
+    for f, col in (("tx0", 0), ("ty0", 1), ("tx1", 2), ("ty1", 3)):
+        assert np.array_equal(rects[good, col], sp[f][good])
+    _check_lists(buf, lay, m, sp, cam, opts, "c0 lists")
+
+
+def test_lists_rebin_from_gpu_rects_and_keys(r):
+    """The integer stages are exact functions of the GPU's own float outputs:
+    re-binning the GPU's rectangles and keys on the host reproduces its lists."""
+    say("case rebin: 2000 Gaussians, 200x150, 8x8 tiles")
+    sc = scenegen.tiny_scene(31, 2000, sh_degree=1, half_extent=1.5, log_scale_mean=-3.0, log_scale_std=0.8)
+    cam = scenegen.pinhole(scenegen.look_at((0.4, 0.3, -4.0)), 200, 150, 55)
+    opts = scenegen.default_options(tile_w=8, tile_h=8)
+    outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
+    assert ok
+    n = 2000
+    keys = read(buf, lay.depth_keys, n, np.uint32)
+    order = read(buf, lay.order, n, np.uint32).astype(np.int64)
+    rects = read(buf, lay.rects, 4 * n, np.uint16).reshape(n, 4).astype(np.int64)
+    counts = read(buf, lay.tile_counts, n, np.uint32).astype(np.int64)
+    key_of = np.zeros(n, np.uint32)
+    key_of[order] = keys
+    tx = -(-200 // 8)
+    rows = []
+    for i in np.nonzero(counts)[0]:
+        for ty in range(rects[i, 1], rects[i, 3] + 1):
+            for x in range(rects[i, 0], rects[i, 2] + 1):
+                rows.append((ty * tx + x, key_of[i], i))
+    rows = np.array(rows, dtype=np.int64)
+    srt = rows[np.lexsort((rows[:, 2], rows[:, 1], rows[:, 0]))]
+    tiles, ids = instance_lists(buf, lay, m)
+    assert m == len(rows)
+    assert np.array_equal(tiles, srt[:, 0]) and np.array_equal(ids, srt[:, 2])
+    # tile ranges bracket exactly the runs of each tile
+    rng = read(buf, lay.tile_ranges, 2 * lay.total_tiles, np.uint32).reshape(-1, 2)
+    for t in np.unique(tiles):
+        idx = np.nonzero(tiles == t)[0]
+        assert rng[t, 0] == idx[0] and rng[t, 1] == idx[-1] + 1
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (16, 8), (16, 16), (32, 16), (32, 32)])
+def test_ragged_image_all_tile_shapes(r, shape):
+    say(f"case ragged 131x77 tile {shape}")
+    sc = scenegen.tiny_scene(32, 400, sh_degree=2, half_extent=1.2, log_scale_mean=-2.8, log_scale_std=0.7)
+    cam = scenegen.pinhole(scenegen.look_at((-0.3, 0.5, -3.5)), 131, 77, 70)
+    opts = scenegen.default_options(tile_w=shape[0], tile_h=shape[1], background=(0.2, 0.1, 0.05))
+    outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
+    assert ok
+    ref = oracle.render(sc, cam, opts)
+    assert m == ref["counters"]["instances"]
+    assert_image_close(outs[0]["rgb"], outs[0]["final_T"], ref, label=f"ragged {shape}")
+    sp = oracle.preprocess(sc, cam, opts)
+    _check_lists(buf, lay, m, sp, cam, opts, f"ragged {shape} lists")
+    base = scenegen.default_options(tile_w=16, tile_h=16, background=(0.2, 0.1, 0.05))
+    b_outs = render_with_ws(r, sc, [cam], base)[0]
+    # per-pixel arithmetic does not depend on the tiling
+    assert np.array_equal(outs[0]["rgb"], b_outs[0]["rgb"]) and np.array_equal(outs[0]["final_T"], b_outs[0]["final_T"])
+
+
+def _mk(mus, scales, opac, rgbs, quats=None):
+    n = len(mus)
+    sh = np.zeros((1, 3, n))
+    sh[0] = (np.asarray(rgbs, float).T - 0.5) * 2 * np.sqrt(np.pi)
+    q = np.tile(np.array([[1.0], [0], [0], [0]]), (1, n)) if quats is None else np.asarray(quats, float).T
+    return dict(means=np.asarray(mus, np.float32).T.copy(), log_scales=np.log(np.asarray(scales, float)).T.astype(np.float32).copy(),
+                quats=q.astype(np.float32).copy(), opacity_logits=np.log(np.asarray(opac) / (1 - np.asarray(opac))).astype(np.float32),
+                sh=sh.astype(np.float32), sh_degree=0)
+
+
+def test_edge_cases(r):
+    cam = scenegen.pinhole(np.concatenate([np.eye(3), np.zeros((3, 1))], 1), 48, 40, 90)
+    opts = scenegen.default_options(background=(0.1, 0.2, 0.3))
+    cases = {
+        "empty": _mk(np.zeros((0, 3)), np.zeros((0, 3)) + 1, np.zeros(0) + 0.5, np.zeros((0, 3))),
+        "single": _mk([[0.1, 0.05, 2.0]], [[0.1, 0.2, 0.05]], [0.8], [[0.9, 0.3, 0.1]]),
+        "all_culled": _mk([[0, 0, -1.0], [0, 0, 0.1], [0, 0, 3.0]], [[0.1] * 3] * 3, [0.5, 0.5, 0.002], [[1, 1, 1]] * 3),
+        "camera_inside": _mk([[0.05, 0.0, 0.4], [0.0, 0.0, 3.0]], [[0.5] * 3, [0.2] * 3], [0.9, 0.7], [[1, 0, 0], [0, 1, 0]]),
+        "quad_crossing_camera_plane": _mk([[0.3, 0.1, 0.6], [0, 0, 2.0]], [[0.05, 0.5, 0.05], [0.2] * 3], [0.8, 0.6],
+                                          [[1, 0, 0], [0, 1, 0]], quats=[[0.9, 0.3, 0.2, 0.1], [1, 0, 0, 0]]),
+        "offscreen": _mk([[30.0, 0.0, 2.0]], [[0.1] * 3], [0.9], [[1, 1, 1]]),
+    }
+    bad = _mk([[0.0, 0.0, 2.0], [0.1, 0.0, 2.5], [0.0, 0.1, 3.0]], [[0.2] * 3] * 3, [0.7] * 3, [[1, 0, 0]] * 3)
+    bad["means"][0, 0] = np.nan
+    bad["quats"][:, 1] = 0.0
+    bad["sh"][0, 1, 2] = np.inf
+    cases["non_finite_and_zero_quat"] = bad
+    for name, sc in cases.items():
+        say(f"case edge/{name}")
+        outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
+        assert ok
+        ref = oracle.render(sc, cam, opts)
+        assert m == ref["counters"]["instances"], name
+        assert_image_close(outs[0]["rgb"], outs[0]["final_T"], ref, label=name)
+    assert np.allclose(render_with_ws(r, cases["empty"], [cam], opts)[0][0]["rgb"][2], 0.3)
+
+
+def test_overflow_is_reported_and_recovers(r):
+    say("case overflow: capacity 16")
+    w = scenegen.make_workload("c0")
+    sc, cam, opts = w["scene"], w["cameras"][0], w["options"]
+    outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts, capacity=16)
+    assert not ok and m > 16
+    assert np.all(outs[0]["rgb"] == 0.0) and np.all(outs[0]["final_T"] == 1.0)
+    outs2, _, _, _, (ok2, m2) = render_with_ws(r, sc, [cam], opts, capacity=m)
+    assert ok2 and m2 == m
+    assert_image_close(outs2[0]["rgb"], outs2[0]["final_T"], oracle.render(sc, cam, opts), label="after regrow")
+
+
+def test_c1_full_size_sampled_pixels_and_lists(r):
+    """500k Gaussians at 1920x1080 (the benchmark frame): sampled pixels
+    against the oracle pixel by pixel, the full tile list bit-exact."""
+    say("case c1 full size: 500k Gaussians, 1920x1080, pose 0")
+    w = scenegen.make_workload("c1")
+    sc, cam, opts = w["scene"], w["cameras"][0], w["options"]
+    outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
+    assert ok
+    sp = oracle.preprocess(sc, cam, opts)
+    assert (sp["hazard"] & oracle.HAZARD["cull"]).sum() == 0
+    _check_lists(buf, lay, m, sp, cam, opts, "c1 lists")
+    rng = np.random.default_rng(5)
+    px = np.concatenate([rng.integers(0, 1920, 3000), np.arange(1920)])
+    py = np.concatenate([rng.integers(0, 1080, 3000), np.full(1920, 540)])
+    rgb, T, hz = oracle.render_pixels(sc, cam, opts, px, py)
+    g_rgb = outs[0]["rgb"][:, py, px].T
+    g_T = outs[0]["final_T"][py, px]
+    ok_ = hz == 0
+    err = np.abs(g_rgb - rgb)[ok_].max()
+    terr = np.abs(g_T - T)[ok_].max()
+    say(f"  c1 sampled: max|rgb-oracle|={err:.3e} max|T-oracle|={terr:.3e} hazard={int((~ok_).sum())}/{len(px)}")
+    assert (~ok_).mean() < 0.01
+    assert err <= 2e-4 and terr <= 2e-4
+
+
+def test_batched_views_match_single_views_and_oracle(r):
+    """Views of different sizes in one batch (MIP on) equal the same views
+    rendered one at a time, bit for bit, and match the oracle."""
+    sc = scenegen.tiny_scene(33, 3000, sh_degree=3, half_extent=1.5, log_scale_mean=-3.5, log_scale_std=0.8)
+    cams = [scenegen.pinhole(scenegen.look_at((0, 0, -4)), 160, 120, 60),
+            scenegen.pinhole(scenegen.look_at((2, 1, -3.5)), 97, 211, 75),
+            scenegen.pinhole(scenegen.look_at((-3, 0.5, -2)), 64, 64, 40)]
+    opts = scenegen.default_options(mip=1)
+    say("case batch of 3 uneven views, MIP on")
+    outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, cams, opts)
+    assert ok
+    for v, cam in enumerate(cams):
+        single = render_with_ws(r, sc, [cam], opts)[0][0]
+        assert np.array_equal(outs[v]["rgb"], single["rgb"]), v
+        assert np.array_equal(outs[v]["final_T"], single["final_T"]), v
+        assert_image_close(outs[v]["rgb"], outs[v]["final_T"], oracle.render(sc, cam, opts), label=f"batch view {v}")
+
+
+def test_graph_plan_replays_match_eager(r):
+    from paper_2503_18682_amd import renderer as R
+
+    sc = scenegen.tiny_scene(34, 3000, sh_degree=2, half_extent=1.5, log_scale_mean=-3.5, log_scale_std=0.8)
+    cams = [scenegen.pinhole(scenegen.look_at((0, 0, -4)), 160, 120, 60),
+            scenegen.pinhole(scenegen.look_at((0.063, 0, -4)), 160, 120, 60),
+            scenegen.pinhole(scenegen.look_at((1, 1, -3)), 80, 90, 70)]
+    opts = scenegen.default_options(mip=1)
+    g = to_dev(sc)
+    say("case graph plan: 3 views, 4 replays with moving cameras")
+    br = R.BatchRenderer(r, 3000, 2, cams, capacity=200000, options=opts)
+    for rep in range(4):
+        moved = []
+        for c in cams:
+            c2 = dict(c)
+            c2["w2c"] = c["w2c"].copy()
+            c2["w2c"][0, 3] += 0.05 * rep
+            moved.append(c2)
+        outs = br.launch(g, moved)
+        ok, _ = br.status()
+        assert ok
+        eager = render_with_ws(r, sc, moved, opts)[0]
+        for v in range(3):
+            assert np.array_equal(outs[v]["rgb"].cpu().numpy(), eager[v]["rgb"]), (rep, v)
+            assert np.array_equal(outs[v]["final_T"].cpu().numpy(), eager[v]["final_T"]), (rep, v)
+    br.close()
+
+
+def test_autotune_picks_a_supported_shape(r):
+    sc = scenegen.tiny_scene(35, 2000, sh_degree=1)
+    cams = [scenegen.pinhole(scenegen.look_at((0, 0, -4)), 200, 160, 60)]
+    g = to_dev(sc)
+    say("case autotune")
+    buf, ws = r.new_workspace(2000, cams, 500000, 0, r.options)
+    outs = r.allocate_outputs(cams)
+    best, ms = r.autotune(g, cams, ws, outs, reps=2)
+    assert (best["tile_w"], best["tile_h"]) in [(8, 8), (16, 8), (16, 16), (32, 16), (32, 32)]
+    assert ms > 0
