@@ -1,0 +1,60 @@
+"""Write the algorithmic work counts of the benchmark frames, computed by the
+CPU oracle only (TEST / MEASUREMENT INFRASTRUCTURE).
+
+For each view of a workload it records, from a full oracle render:
+  visible        Gaussians passing every cull
+  instances      Gaussian-tile pairs (16x16 tiles)
+  fragments      pixel centres inside a projected quad (what a rasteriser
+                 would shade for the paper's quads), before termination
+  box_pairs      pixel centres inside a Gaussian's pixel box
+  contributions  fragments that were composited (omega >= p_min, before
+                 early termination)
+These are the denominators of the roofline figures (work per launch).
+
+    python -m oracle.work_counts c1 [--out tests/golden/work_counts_c1.json]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import scenegen  # noqa: E402
+
+
+def counts(name: str, views=None):
+    w = scenegen.make_workload(name)
+    sc, cams, opts = w["scene"], w["cameras"], w["options"]
+    out = []
+    for v, cam in enumerate(cams):
+        if views is not None and v not in views:
+            continue
+        t = time.time()
+        r = oracle.render(sc, cam, opts)
+        c = dict(r["counters"], view=v, width=cam["width"], height=cam["height"])
+        out.append(c)
+        print(f"{name} view {v}: {c} ({time.time() - t:.1f} s)", flush=True)
+    return dict(workload=name, n=int(sc["opacity_logits"].shape[0]), options=opts, views=out)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("workload", default="c1", nargs="?")
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    res = counts(a.workload)
+    path = a.out or os.path.join(ROOT, "tests", "golden", f"work_counts_{a.workload}.json")
+    with open(path, "w") as f:
+        json.dump(res, f, indent=1)
+    print("wrote", path)
+
+
+if __name__ == "__main__":
+    main()

@@ -41,6 +41,11 @@ def render_with_ws(r, scene, cams, opts, capacity=None, flags=0):
     outs = r.allocate_outputs(cams)
     r.render_into(g, cams, outs, ws, opts)
     ok, need = r.status(ws)
+    if not ok and capacity is None:  # grow once, as the renderer does
+        cap = need
+        buf, ws = r.new_workspace(n, cams, cap, flags, opts)
+        r.render_into(g, cams, outs, ws, opts)
+        ok, need = r.status(ws)
     lay = r.layout(n, cams, cap, flags, opts)
     host = [{k: v.cpu().numpy() for k, v in o.items()} for o in outs]
     return host, buf, ws, lay, (ok, need)
