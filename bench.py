@@ -62,7 +62,15 @@ def parse():
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of HIP-graph replays")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-steps", type=int, default=32, help="frames of the per-stage timing pass")
+    ap.add_argument("--tile", default="16x16", help="tile shape WxH, each of 8, 16, 32")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB MiB (reference for HBM counters)")
     return ap.parse_args()
+
+
+def tile_opts(args):
+    tw, th = (int(v) for v in args.tile.lower().split("x"))
+    return dict(tile_w=tw, tile_h=th)
 
 
 def work_counts(name):
@@ -134,7 +142,7 @@ def bench_c1(args, torch):
     from paper_2503_18682_amd import renderer as R
 
     w = scenegen.make_workload("c1")
-    sc, cams, opts = w["scene"], w["cameras"], w["options"]
+    sc, cams, opts = w["scene"], w["cameras"], dict(w["options"], **tile_opts(args))
     n = int(sc["opacity_logits"].shape[0])
     g = to_dev(sc, torch)
     r = R.Renderer(0, opts)
@@ -186,7 +194,7 @@ def bench_c1(args, torch):
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "c1: 500k Gaussians (64 clusters, SH3), 1920x1080, 50deg FOV, 16 orbit poses",
-                   "n_gaussians": n, "width": 1920, "height": 1080, "tile": "16x16",
+                   "n_gaussians": n, "width": 1920, "height": 1080, "tile": args.tile,
                    "launch": "eager" if args.eager else "hip_graph", "instance_capacity": capacity},
         "roofline": roof,
         "stages_ms": stages,
@@ -201,7 +209,7 @@ def bench_c2(args, torch):
     from paper_2503_18682_amd import renderer as R
 
     w = scenegen.make_workload("c2")
-    sc, cams, opts = w["scene"], w["cameras"], w["options"]
+    sc, cams, opts = w["scene"], w["cameras"], dict(w["options"], **tile_opts(args))
     n = int(sc["opacity_logits"].shape[0])
     g = to_dev(sc, torch)
     r = R.Renderer(0, opts)
@@ -253,7 +261,7 @@ def bench_c3(args, torch):
     from paper_2503_18682_amd import renderer as R
 
     w = scenegen.make_workload("c3")
-    sc, cams, opts = w["scene"], w["cameras"], w["options"]
+    sc, cams, opts = w["scene"], w["cameras"], dict(w["options"], **tile_opts(args))
     n = int(sc["opacity_logits"].shape[0])
     g = to_dev(sc, torch)
     targets = [torch.from_numpy(t).cuda() for t in w["targets"]]
@@ -320,6 +328,12 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     res = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3}[args.workload](args, torch)
     print(json.dumps(res), flush=True)
 

@@ -93,7 +93,7 @@ typedef struct {
     int32_t mip;           /* 1 = approximate MIP of Sec. 5, eq. 17; default 0 */
     double mip_sigma2_px;  /* MIP pixel variance in px^2 (Sec. 6 uses 0.1); >= 0 */
     double background[3];  /* added as T_final * background; default 0 */
-    int32_t tile_w, tile_h;/* 8x8, 16x8, 16x16, 32x16 or 32x32; 0, 0 = library default (16x16) */
+    int32_t tile_w, tile_h;/* each 8, 16 or 32; 0, 0 = library default (16x16) */
 } rgs_options;
 
 typedef struct {
@@ -192,7 +192,7 @@ rgs_status rgs_autotune(rgs_context *ctx, const rgs_gaussians *g, const rgs_came
  * profiling tools).  Counts are element counts.  Pure host arithmetic; ctx
  * may be NULL. */
 typedef struct {
-    size_t counters;       /* int64[8]: [0] instances needed, [1] capacity, [2] two uint32 tile-queue heads */
+    size_t counters;       /* int64[8]: [0] instances needed, [1] capacity */
     size_t views;          /* per-view device table */
     size_t records;        /* float[16] per Gaussian-view, index v * n + i */
     size_t depth_keys;     /* uint32 per Gaussian-view (0xffffffff = culled) */

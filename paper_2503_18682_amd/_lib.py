@@ -11,7 +11,8 @@ import os
 import torch  # noqa: F401  (loads the HIP runtime before the library)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libraygs.so")
+# RAYGS_LIBRARY may point at another build of the same ABI (e.g. for A/B timing)
+LIB_PATH = os.environ.get("RAYGS_LIBRARY") or os.path.join(_HERE, "libraygs.so")
 
 RGS_OK = 0
 RGS_EINVAL = -1

@@ -25,7 +25,8 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t counters, views, records, keys_a, keys_b, order_a, order_b, rects, tile_counts, offsets, block_sums;
-    size_t inst_tiles_a, inst_tiles_b, inst_ids_a, inst_ids_b, hist, row_total, ranges, record_grads, total;
+    size_t inst_tiles_a, inst_tiles_b, inst_ids_a, inst_ids_b, hist, row_total, ranges, sched, tile_order;
+    size_t record_grads, total;
     int64_t nv_records, capacity, total_tiles;
     int tile_w, tile_h, tile_bits;
 };
@@ -139,7 +140,7 @@ rgs_status check_options(rgs_context *ctx, const rgs_options *o)
         if (!std::isfinite(o->background[k])) return fail(ctx, RGS_EINVAL, "background must be finite");
     const TileShape s = shape_of(*o);
     if (!tile_shape_supported(s.w, s.h))
-        return fail(ctx, RGS_EINVAL, "tile shape %dx%d not supported (8x8, 16x8, 16x16, 32x16, 32x32)", s.w, s.h);
+        return fail(ctx, RGS_EINVAL, "tile shape %dx%d not supported (width and height in {8, 16, 32})", s.w, s.h);
     return RGS_OK;
 }
 
@@ -190,6 +191,8 @@ rgs_status compute_layout(rgs_context *ctx, int64_t n, const rgs_camera *cams, i
     L.hist = take(radix_hist_entries(std::max<int64_t>((int64_t)NV, capacity)) * 4);
     L.row_total = take(256 * 4);
     L.ranges = take((size_t)tiles * 8);
+    L.sched = take(sched_words() * 4);
+    L.tile_order = take((size_t)tiles * 4);
     L.record_grads = (flags & RGS_WS_BACKWARD) ? take(NV * kGradFloats * sizeof(float)) : 0;
     L.total = off;
     return RGS_OK;
@@ -287,16 +290,16 @@ struct Timer {
             fe = ctx->pool.back();
             ctx->pool.pop_back();
         } else {
-            for (auto &e : fe.ev) hipEventCreate(&e);
+            for (auto &e : fe.ev) (void)hipEventCreate(&e);
         }
         fe.first = first;
         fe.last = first;
-        hipEventRecord(fe.ev[first], stream);
+        (void)hipEventRecord(fe.ev[first], stream);
     }
     void mark(int stage_done)
     {
         if (!on) return;
-        hipEventRecord(fe.ev[stage_done + 1], stream);
+        (void)hipEventRecord(fe.ev[stage_done + 1], stream);
         fe.last = stage_done + 1;
     }
     ~Timer()
@@ -339,7 +342,8 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
     uint32_t *hist = at<uint32_t>(ws, L.hist);
     uint32_t *row_total = at<uint32_t>(ws, L.row_total);
     uint2 *ranges = at<uint2>(ws, L.ranges);
-    unsigned int *queues = reinterpret_cast<unsigned int *>(counters + 2);
+    uint32_t *sched = at<uint32_t>(ws, L.sched);
+    const uint32_t *tile_order = at<uint32_t>(ws, L.tile_order);
 
     Timer tm(ctx, stream, timing, ST_PRE);
     RGS_HIP(ctx, launch_preprocess(g, views, n_views, dopt, records, keys_in, ord_in, rects, tile_counts, stream));
@@ -359,10 +363,11 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
     tm.mark(ST_TSORT);
     const uint32_t *inst_tiles = at<uint32_t>(ws, L.inst_tiles_a);
     const uint32_t *inst_ids = at<uint32_t>(ws, L.inst_ids_a);
-    RGS_HIP(ctx, launch_tile_ranges(inst_tiles, counters, L.capacity, L.total_tiles, ranges, queues, stream));
+    RGS_HIP(ctx, launch_tile_ranges(inst_tiles, counters, L.capacity, L.total_tiles, ranges, sched,
+                                    at<uint32_t>(ws, L.tile_order), stream));
     tm.mark(ST_RANGES);
-    RGS_HIP(ctx, launch_blend(s, ranges, inst_ids, records, views, n_views, L.total_tiles, NV, dopt, queues,
-                              ctx->grid_fwd[shape_index(s)], stream));
+    RGS_HIP(ctx, launch_blend(s, ranges, tile_order, inst_ids, records, views, n_views, L.total_tiles, NV, dopt,
+                              sched, ctx->grid_fwd[shape_index(s)], stream));
     tm.mark(ST_BLEND);
     return RGS_OK;
 }
@@ -419,9 +424,9 @@ void rgs_destroy(rgs_context *ctx)
 {
     if (!ctx) return;
     for (auto &fe : ctx->pending)
-        for (auto &e : fe.ev) hipEventDestroy(e);
+        for (auto &e : fe.ev) (void)hipEventDestroy(e);
     for (auto &fe : ctx->pool)
-        for (auto &e : fe.ev) hipEventDestroy(e);
+        for (auto &e : fe.ev) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -517,16 +522,15 @@ rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const r
     const TileShape sh = shape_of(*opts);
     ensure_grids(ctx, sh);
     const DevOptions dopt = dev_options(*opts);
-    int64_t *counters = at<int64_t>(ws->ptr, L.counters);
-    unsigned int *queues = reinterpret_cast<unsigned int *>(counters + 2);
+    uint32_t *sched = at<uint32_t>(ws->ptr, L.sched);
     float *rgrads = at<float>(ws->ptr, L.record_grads);
     Timer tm(ctx, s, true, ST_BLEND_BWD);
     RGS_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(rgrads), 0u, L.nv_records * kGradFloats, s));
-    RGS_HIP(ctx, launch_fill_u32(queues + 1, 0u, 1, s));
-    RGS_HIP(ctx, launch_blend_backward(sh, at<uint2>(ws->ptr, L.ranges), at<uint32_t>(ws->ptr, L.inst_ids_a),
-                                       at<float4>(ws->ptr, L.records), at<DevView>(ws->ptr, L.views), n_views,
-                                       L.total_tiles, L.nv_records, dopt, rgrads, queues + 1,
-                                       ctx->grid_bwd[shape_index(sh)], s));
+    RGS_HIP(ctx, launch_fill_u32(sched + 1, 0u, 1, s));
+    RGS_HIP(ctx, launch_blend_backward(sh, at<uint2>(ws->ptr, L.ranges), at<uint32_t>(ws->ptr, L.tile_order),
+                                       at<uint32_t>(ws->ptr, L.inst_ids_a), at<float4>(ws->ptr, L.records),
+                                       at<DevView>(ws->ptr, L.views), n_views, L.total_tiles, L.nv_records, dopt,
+                                       rgrads, sched + 1, ctx->grid_bwd[shape_index(sh)], s));
     tm.mark(ST_BLEND_BWD);
     RGS_HIP(ctx, launch_preprocess_backward(*g, at<DevView>(ws->ptr, L.views), n_views, dopt,
                                             at<uint32_t>(ws->ptr, L.tile_counts), rgrads, *grads, s));
@@ -565,9 +569,9 @@ rgs_status rgs_batch_plan(rgs_context *ctx, int64_t n, int32_t sh_degree, const 
 void rgs_plan_destroy(rgs_plan *p)
 {
     if (!p) return;
-    if (p->exec) hipGraphExecDestroy(p->exec);
-    if (p->graph) hipGraphDestroy(p->graph);
-    if (p->capture_stream) hipStreamDestroy(p->capture_stream);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
     delete p;
 }
 
@@ -601,11 +605,11 @@ rgs_status rgs_batch_launch(rgs_plan *p, const rgs_gaussians *g, const rgs_camer
                outs[v].n_contrib == p->outs[v].n_contrib;
     if (!same) {
         if (p->exec) {
-            hipGraphExecDestroy(p->exec);
+            (void)hipGraphExecDestroy(p->exec);
             p->exec = nullptr;
         }
         if (p->graph) {
-            hipGraphDestroy(p->graph);
+            (void)hipGraphDestroy(p->graph);
             p->graph = nullptr;
         }
         p->captured = false;
@@ -614,7 +618,7 @@ rgs_status rgs_batch_launch(rgs_plan *p, const rgs_gaussians *g, const rgs_camer
         hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(p->capture_stream, &graph);
         if (st != RGS_OK) {
-            if (graph) hipGraphDestroy(graph);
+            if (graph) (void)hipGraphDestroy(graph);
             return st;
         }
         if (e != hipSuccess || !graph) return fail(ctx, RGS_ECAPTURE, "capture failed: %s", hipGetErrorString(e));
@@ -639,7 +643,7 @@ rgs_status rgs_autotune(rgs_context *ctx, const rgs_gaussians *g, const rgs_came
 {
     if (!ctx || !best || !best_ms || !opts) return fail(ctx, RGS_EINVAL, "NULL argument");
     if (reps < 1) return fail(ctx, RGS_EINVAL, "reps must be >= 1");
-    static const TileShape shapes[] = {{8, 8}, {16, 8}, {16, 16}, {32, 16}, {32, 32}};
+    static const TileShape shapes[] = {{8, 8}, {8, 16}, {8, 32}, {16, 8}, {16, 16}, {16, 32}, {32, 8}, {32, 16}, {32, 32}};
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t e0, e1;
     RGS_HIP(ctx, hipEventCreate(&e0));
@@ -660,16 +664,16 @@ rgs_status rgs_autotune(rgs_context *ctx, const rgs_gaussians *g, const rgs_came
             result = st;
             break;
         }
-        hipEventRecord(e0, s);
+        (void)hipEventRecord(e0, s);
         for (int r = 0; r < reps && st == RGS_OK; ++r) st = rgs_render(ctx, g, cams, n_views, &o, ws, outs, stream);
-        hipEventRecord(e1, s);
+        (void)hipEventRecord(e1, s);
         if (st != RGS_OK) {
             result = st;
             break;
         }
-        hipEventSynchronize(e1);
+        (void)hipEventSynchronize(e1);
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
         const double t = ms / reps;
         if (t < best_t) {
             best_t = t;
@@ -678,8 +682,8 @@ rgs_status rgs_autotune(rgs_context *ctx, const rgs_gaussians *g, const rgs_came
         result = RGS_OK;
     }
     ctx->timing = timing;
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (result != RGS_OK)
         return result == RGS_EOVERFLOW ? fail(ctx, RGS_EOVERFLOW, "no tile shape fits the workspace capacity")
                                        : result;
@@ -699,7 +703,7 @@ int32_t rgs_stage_times(rgs_context *ctx, double *ms, int32_t n, int64_t *frames
 {
     if (!ctx) return 0;
     for (auto &fe : ctx->pending) {
-        hipEventSynchronize(fe.ev[fe.last]);
+        (void)hipEventSynchronize(fe.ev[fe.last]);
         for (int st = fe.first; st < fe.last; ++st) {
             float t = 0.f;
             if (hipEventElapsedTime(&t, fe.ev[st], fe.ev[st + 1]) == hipSuccess) ctx->stage_ms[st] += t;

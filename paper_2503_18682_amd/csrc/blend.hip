@@ -17,6 +17,8 @@
 // omega = o exp(-D/2) (eq. 2); a Gaussian contributes iff den > 0 and
 // omega >= p_min; alpha = min(omega, alpha_max); compositing (eq. 1) stops
 // before a Gaussian that would take T below t_eps.
+#include <hip/hip_fp16.h>
+
 #include "internal.h"
 
 #pragma clang fp contract(off)
@@ -26,22 +28,31 @@ namespace {
 
 struct Rec {
     float u_hi, v_hi, u_lo, v_lo, G00, G01, G10, G11, gx, gy, k0, ic2, log2o, r, g, b;
+    uint32_t rows;  // first | last << 16 covered pixel row
 };
 
 struct Frag {
-    float dx, dy, n0, n1, den, q, rt, D, w;
+    float dx, dy, n0, n1, den, q, t, rt, D, w;
 };
 
 __device__ __forceinline__ Rec load_rec(const float4 *p)
 {
     const float4 a = p[0], b = p[1], c = p[2], d = p[3];
-    return Rec{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w};
+    const uint32_t lo_bits = __float_as_uint(a.z);
+    const float2 lo = __half22float2(*reinterpret_cast<const __half2 *>(&lo_bits));
+    return Rec{a.x, a.y, lo.x, lo.y, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w, __float_as_uint(a.w)};
 }
 
-// The single per-fragment instruction sequence shared by the forward and the
+// The per-fragment instruction sequence shared by the forward and the
 // backward kernel (explicit fma, no contraction), so both take identical
-// decisions.  Returns den > 0.
-__device__ __forceinline__ bool eval_fragment(const Rec &R, float pxc, float pyc, Frag &f)
+// decisions.  frag_test evaluates the quad-plane coordinate and decides
+// whether the Gaussian contributes: den > 0 (tau > 0) and omega >= p_min,
+// i.e. D log2(e) / 2 <= log2(o / p_min) = K, tested as
+// (log2(e)/2) q <= K (den^2 + q / c^2) without a reciprocal or exponential.
+// frag_omega then finishes D and omega for accepted fragments only.
+constexpr float kHalfLog2e = 0.72134752044448170f;
+
+__device__ __forceinline__ bool frag_test(const Rec &R, float K, float pxc, float pyc, Frag &f)
 {
     f.dx = (pxc - R.u_hi) - R.u_lo;
     f.dy = (pyc - R.v_hi) - R.v_lo;
@@ -49,12 +60,28 @@ __device__ __forceinline__ bool eval_fragment(const Rec &R, float pxc, float pyc
     f.n1 = __builtin_fmaf(R.G11, f.dy, R.G10 * f.dx);
     f.den = __builtin_fmaf(R.gy, f.dy, __builtin_fmaf(R.gx, f.dx, R.k0));
     f.q = __builtin_fmaf(f.n1, f.n1, f.n0 * f.n0);
-    const float t = __builtin_fmaf(f.q, R.ic2, f.den * f.den);
-    f.rt = __builtin_amdgcn_rcpf(t);
+    f.t = __builtin_fmaf(f.q, R.ic2, f.den * f.den);
+    return (f.den > 0.0f) & (kHalfLog2e * f.q <= K * f.t);
+}
+
+__device__ __forceinline__ void frag_omega(const Rec &R, Frag &f)
+{
+    f.rt = __builtin_amdgcn_rcpf(f.t);
     f.D = f.q * f.rt;
-    // omega = o * 2^(-D log2(e) / 2)
-    f.w = __builtin_amdgcn_exp2f(__builtin_fmaf(f.D, -0.72134752044448170f, R.log2o));
-    return f.den > 0.0f;
+    f.w = __builtin_amdgcn_exp2f(__builtin_fmaf(f.D, -kHalfLog2e, R.log2o));  // o 2^(-D log2(e)/2)
+}
+
+// Rows of the tile covered by a record, relative to the tile's first row, as
+// wave-uniform (scalar) values: lane l's pixel k lies in row band
+// [k * LY, k * LY + LY), so a band outside [r0, r1] is skipped by the whole wave.
+struct RowSpan {
+    int r0, r1;
+};
+
+__device__ __forceinline__ RowSpan row_span(const Rec &R, int tile_row0)
+{
+    const uint32_t rows = __builtin_amdgcn_readfirstlane(R.rows);
+    return RowSpan{(int)(rows & 0xffffu) - tile_row0, (int)(rows >> 16) - tile_row0};
 }
 
 __device__ __forceinline__ void lds_wave_sync()
@@ -72,7 +99,7 @@ __device__ __forceinline__ int find_view(const DevView *views, int n_views, int 
 }
 
 struct BlendParams {
-    float p_min, alpha_max, t_eps, bg0, bg1, bg2;
+    float log2_pmin, alpha_max, t_eps, bg0, bg1, bg2;
     int n_views, total_tiles;
     uint32_t n_records;
 };
@@ -88,7 +115,7 @@ __device__ __forceinline__ void stage_record(float4 *dst, const float4 *__restri
         for (int c = 0; c < 4; ++c) dst[c] = src[c];
     } else {
         const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-        dst[0] = z;
+        dst[0] = make_float4(0.f, 0.f, 0.f, __uint_as_float(1u));  // rows [1, 0]: empty
         dst[1] = z;
         dst[2] = make_float4(0.f, 0.f, -1.f, 0.f);
         dst[3] = make_float4(-126.f, 0.f, 0.f, 0.f);
@@ -96,7 +123,9 @@ __device__ __forceinline__ void stage_record(float4 *dst, const float4 *__restri
 }
 
 template <int TW, int TH>
-__global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ inst_ids,
+__global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
+                                               const uint32_t *__restrict__ tile_order,
+                                               const uint32_t *__restrict__ inst_ids,
                                                const float4 *__restrict__ records, const DevView *__restrict__ views,
                                                BlendParams P, unsigned int *__restrict__ queue)
 {
@@ -106,10 +135,11 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lx = lane % LX, ly = lane / LX;
     for (;;) {
-        int tile = 0;
-        if (lane == 0) tile = (int)atomicAdd(queue, 1u);
-        tile = __shfl(tile, 0, 64);
-        if (tile >= P.total_tiles) break;
+        int slot = 0;
+        if (lane == 0) slot = (int)atomicAdd(queue, 1u);
+        slot = __builtin_amdgcn_readfirstlane(slot);
+        if (slot >= P.total_tiles) break;
+        const int tile = (int)tile_order[slot];
         const DevView &V = views[find_view(views, P.n_views, tile)];
         const int local = tile - V.tile_base;
         const int tx = local % V.tiles_x, ty = local / V.tiles_x;
@@ -129,19 +159,27 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
         }
         const uint2 rg = ranges[tile];
         bool wave_live = true;
+        // batch 0 goes straight to LDS; batch b+1 is prefetched into registers
+        // while batch b is composited
+        if (rg.x + lane < rg.y) stage_record(s_rec[wave][lane], records, inst_ids[rg.x + lane], P.n_records);
         for (uint32_t base = rg.x; base < rg.y && wave_live; base += 64) {
             const uint32_t nb = min(64u, rg.y - base);
-            if ((uint32_t)lane < nb) stage_record(s_rec[wave][lane], records, inst_ids[base + lane], P.n_records);
+            const uint32_t next = base + 64 + lane;
+            const bool have_next = next < rg.y;
+            float4 pre[4];
+            if (have_next) stage_record(pre, records, inst_ids[next], P.n_records);
             lds_wave_sync();
             for (uint32_t j = 0; j < nb; ++j) {
                 const Rec R = load_rec(s_rec[wave][j]);
-                bool any = false;
+                const float K = R.log2o - P.log2_pmin;
+                const RowSpan span = row_span(R, ty * TH);
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) {
+                    if (span.r1 < k * LY || span.r0 >= (k + 1) * LY) continue;
                     if (!live[k]) continue;
                     Frag f;
-                    const bool front = eval_fragment(R, pxc, pyc[k], f);
-                    if (front && f.w >= P.p_min) {
+                    if (frag_test(R, K, pxc, pyc[k], f)) {
+                        frag_omega(R, f);
                         const float a = fminf(f.w, P.alpha_max);
                         const float Tn = T[k] * (1.0f - a);
                         if (Tn < P.t_eps) {
@@ -155,14 +193,20 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
                             last[k] = (int)(base - rg.x + j + 1);
                         }
                     }
-                    any = any || live[k];
                 }
+                bool any = false;
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) any = any || live[k];
                 if (__ballot(any) == 0) {
                     wave_live = false;
                     break;
                 }
             }
             lds_wave_sync();
+            if (have_next) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) s_rec[wave][lane][c] = pre[c];
+            }
         }
         const size_t plane = (size_t)V.width * V.height;
 #pragma unroll
@@ -189,6 +233,7 @@ __device__ __forceinline__ float wave_sum(float x)
 
 template <int TW, int TH>
 __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ranges,
+                                                   const uint32_t *__restrict__ tile_order,
                                                    const uint32_t *__restrict__ inst_ids,
                                                    const float4 *__restrict__ records,
                                                    const DevView *__restrict__ views, BlendParams P,
@@ -200,10 +245,11 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lx = lane % LX, ly = lane / LX;
     for (;;) {
-        int tile = 0;
-        if (lane == 0) tile = (int)atomicAdd(queue, 1u);
-        tile = __shfl(tile, 0, 64);
-        if (tile >= P.total_tiles) break;
+        int slot = 0;
+        if (lane == 0) slot = (int)atomicAdd(queue, 1u);
+        slot = __builtin_amdgcn_readfirstlane(slot);
+        if (slot >= P.total_tiles) break;
+        const int tile = (int)tile_order[slot];
         const DevView &V = views[find_view(views, P.n_views, tile)];
         const int local = tile - V.tile_base;
         const int tx = local % V.tiles_x, ty = local / V.tiles_x;
@@ -248,16 +294,19 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
             for (int jj = nb - 1; jj >= 0; --jj) {
                 const int j = lo + jj;
                 const Rec R = load_rec(s_rec[wave][jj]);
+                const float K = R.log2o - P.log2_pmin;
+                const RowSpan span = row_span(R, ty * TH);
                 const float inv_o = __builtin_amdgcn_exp2f(-R.log2o);
                 float du0 = 0, dv0 = 0, dM00 = 0, dM01 = 0, dM11 = 0, dgx = 0, dgy = 0, dk0 = 0, dic2 = 0, dop = 0,
                       dr = 0, dg = 0, db = 0;
                 bool hit = false;
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) {
+                    if (span.r1 < k * LY || span.r0 >= (k + 1) * LY) continue;
                     if (j >= last[k]) continue;
                     Frag f;
-                    const bool front = eval_fragment(R, pxc, pyc[k], f);
-                    if (!(front && f.w >= P.p_min)) continue;
+                    if (!frag_test(R, K, pxc, pyc[k], f)) continue;
+                    frag_omega(R, f);
                     hit = true;
                     const float a = fminf(f.w, P.alpha_max);
                     const float om = 1.0f - a;
@@ -314,7 +363,7 @@ int occupancy_grid(const void *kernel, int num_cus)
 
 BlendParams make_params(const DevOptions &opt, int n_views, int64_t total_tiles, int64_t n_records)
 {
-    return BlendParams{(float)opt.p_min, (float)opt.alpha_max, (float)opt.t_eps, opt.bg[0], opt.bg[1], opt.bg[2],
+    return BlendParams{(float)log2(opt.p_min), (float)opt.alpha_max, (float)opt.t_eps, opt.bg[0], opt.bg[1], opt.bg[2],
                        n_views, (int)total_tiles, (uint32_t)n_records};
 }
 
@@ -322,11 +371,10 @@ BlendParams make_params(const DevOptions &opt, int n_views, int64_t total_tiles,
 
 bool tile_shape_supported(int w, int h)
 {
-    return (w == 8 && h == 8) || (w == 16 && h == 8) || (w == 16 && h == 16) || (w == 32 && h == 16) ||
-           (w == 32 && h == 32);
+    return (w == 8 || w == 16 || w == 32) && (h == 8 || h == 16 || h == 32);
 }
 
-#define RGS_SHAPES(X) X(8, 8) X(16, 8) X(16, 16) X(32, 16) X(32, 32)
+#define RGS_SHAPES(X) X(8, 8) X(8, 16) X(8, 32) X(16, 8) X(16, 16) X(16, 32) X(32, 8) X(32, 16) X(32, 32)
 
 int blend_grid(TileShape s, int num_cus)
 {
@@ -347,14 +395,15 @@ int blend_backward_grid(TileShape s, int num_cus)
     return num_cus;
 }
 
-hipError_t launch_blend(TileShape s, const uint2 *ranges, const uint32_t *inst_ids, const float4 *records,
+hipError_t launch_blend(TileShape s, const uint2 *ranges, const uint32_t *tile_order, const uint32_t *inst_ids,
+                        const float4 *records,
                         const DevView *views, int n_views, int64_t total_tiles, int64_t n_records,
                         const DevOptions &opt, unsigned int *queue, int grid, hipStream_t stream)
 {
     const BlendParams P = make_params(opt, n_views, total_tiles, n_records);
 #define X(W, H)                                                                                         \
     if (s.w == W && s.h == H) {                                                                         \
-        k_blend<W, H><<<grid, 256, 0, stream>>>(ranges, inst_ids, records, views, P, queue);            \
+        k_blend<W, H><<<grid, 256, 0, stream>>>(ranges, tile_order, inst_ids, records, views, P, queue); \
         return hipGetLastError();                                                                       \
     }
     RGS_SHAPES(X)
@@ -362,7 +411,8 @@ hipError_t launch_blend(TileShape s, const uint2 *ranges, const uint32_t *inst_i
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_blend_backward(TileShape s, const uint2 *ranges, const uint32_t *inst_ids, const float4 *records,
+hipError_t launch_blend_backward(TileShape s, const uint2 *ranges, const uint32_t *tile_order,
+                                 const uint32_t *inst_ids, const float4 *records,
                                  const DevView *views, int n_views, int64_t total_tiles, int64_t n_records,
                                  const DevOptions &opt, float *record_grads, unsigned int *queue, int grid,
                                  hipStream_t stream)
@@ -370,7 +420,8 @@ hipError_t launch_blend_backward(TileShape s, const uint2 *ranges, const uint32_
     const BlendParams P = make_params(opt, n_views, total_tiles, n_records);
 #define X(W, H)                                                                                                  \
     if (s.w == W && s.h == H) {                                                                                  \
-        k_blend_bwd<W, H><<<grid, 256, 0, stream>>>(ranges, inst_ids, records, views, P, record_grads, queue);   \
+        k_blend_bwd<W, H><<<grid, 256, 0, stream>>>(ranges, tile_order, inst_ids, records, views, P,          \
+                                                    record_grads, queue);                                        \
         return hipGetLastError();                                                                                \
     }
     RGS_SHAPES(X)

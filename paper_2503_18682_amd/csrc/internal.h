@@ -34,7 +34,9 @@ struct DevOptions {
 
 // Raster record of one Gaussian-view, 16 floats (64 B), written by the
 // preprocess kernel and read by the compositing kernels:
-//   [0] u_hi, v_hi, u_lo, v_lo   projected centre pi(mu) as a float pair
+//   [0] u_hi, v_hi, lo, rows     projected centre pi(mu) = (u_hi, v_hi) + lo where
+//                                lo = (u_lo, v_lo) as an fp16 pair (bits); rows =
+//                                first | last << 16 covered pixel row (bits)
 //   [1] G00, G01, G10, G11       pixel offset -> quad-plane coordinate (whitened)
 //   [2] gx, gy, k0, ic2          den = k0 + g . delta, ic2 = 1 / c^2
 //   [3] log2o, r, g, b           log2 of the prior opacity, colour
@@ -75,15 +77,22 @@ hipError_t launch_emit(const uint32_t *order, const uint32_t *offsets, const uin
                        const DevView *views, int64_t n, int n_views, int64_t capacity, uint32_t *inst_tiles,
                        uint32_t *inst_ids, hipStream_t stream);
 
+// Tile ranges of the sorted instances plus the compositing work order
+// (tile ids by decreasing list length).  `sched` holds sched_words() uint32:
+// [0] forward queue head, [1] backward queue head, [4..) bucket histograms.
+size_t sched_words();
 hipError_t launch_tile_ranges(const uint32_t *inst_tiles, const int64_t *counters, int64_t capacity,
-                              int64_t total_tiles, uint2 *ranges, unsigned int *queues, hipStream_t stream);
+                              int64_t total_tiles, uint2 *ranges, uint32_t *sched, uint32_t *tile_order,
+                              hipStream_t stream);
 
-hipError_t launch_blend(TileShape shape, const uint2 *ranges, const uint32_t *inst_ids, const float4 *records,
+hipError_t launch_blend(TileShape shape, const uint2 *ranges, const uint32_t *tile_order, const uint32_t *inst_ids,
+                        const float4 *records,
                         const DevView *views, int n_views, int64_t total_tiles, int64_t n_records,
                         const DevOptions &opt, unsigned int *queue, int grid, hipStream_t stream);
 int blend_grid(TileShape shape, int num_cus);
 
-hipError_t launch_blend_backward(TileShape shape, const uint2 *ranges, const uint32_t *inst_ids,
+hipError_t launch_blend_backward(TileShape shape, const uint2 *ranges, const uint32_t *tile_order,
+                                 const uint32_t *inst_ids,
                                  const float4 *records, const DevView *views, int n_views, int64_t total_tiles,
                                  int64_t n_records, const DevOptions &opt, float *record_grads, unsigned int *queue,
                                  int grid, hipStream_t stream);

@@ -8,6 +8,8 @@
 // rectangle and the depth key is evaluated in double precision (full rate on
 // CDNA) with FMA contraction disabled, so the integer decisions (culls, tile
 // rectangles, keys) are those of an exact evaluation up to double rounding.
+#include <hip/hip_fp16.h>
+
 #include "internal.h"
 
 #pragma clang fp contract(off)
@@ -259,8 +261,14 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                 acc += 0.5;
                 col[ch] = acc > 0.0 ? acc : 0.0;
             }
+            // the residuals of the centre go into one fp16 pair (|residual| <= half an
+            // fp32 ulp of the centre, so fp16 keeps it to ~1e-7 px); the freed slot
+            // holds the covered pixel rows for in-tile culling
+            const __half2 lo = __floats2half2_rn(u_lo, v_lo);
+            const uint32_t lo_bits = *reinterpret_cast<const uint32_t *>(&lo);
+            const uint32_t rows = (uint32_t)py0 | ((uint32_t)py1 << 16);
             float4 *rec = records + idx * 4;
-            rec[0] = make_float4(u_hi, v_hi, u_lo, v_lo);
+            rec[0] = make_float4(u_hi, v_hi, __uint_as_float(lo_bits), __uint_as_float(rows));
             rec[1] = make_float4((float)G[0][0], (float)G[0][1], (float)G[1][0], (float)G[1][1]);
             rec[2] = make_float4((float)gx, (float)gy, (float)(1.0 / mu[2]), (float)(1.0 / c2));
             rec[3] = make_float4((float)log2(ov), (float)col[0], (float)col[1], (float)col[2]);

@@ -266,6 +266,12 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t *__restr
 }
 
 // ---------------------------------------------------------------- emission
+// One lane per sorted Gaussian-view writes its (tile, id) instances in
+// row-major tile order at its scanned offset.  Rectangles of more than
+// kEmitSolo tiles are queued in LDS and written by the whole wave, 64 tiles
+// per step, so one large Gaussian does not serialise a lane.
+constexpr uint32_t kEmitSolo = 16;
+
 __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ order,
                                                    const uint32_t *__restrict__ offsets,
                                                    const uint32_t *__restrict__ tile_counts,
@@ -273,23 +279,56 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
                                                    int64_t n, int64_t n_total, int64_t capacity,
                                                    uint32_t *__restrict__ inst_tiles, uint32_t *__restrict__ inst_ids)
 {
+    __shared__ uint32_t big[kWaves][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (k >= n_total) return;
-    const uint32_t id = order[k];
-    const uint32_t cnt = tile_counts[id];
-    if (cnt == 0) return;
-    const int v = (int)(id / (uint32_t)n);
-    const uint2 r = rects[id];
-    const int tx0 = r.x & 0xffff, ty0 = r.x >> 16, tx1 = r.y & 0xffff, ty1 = r.y >> 16;
-    const int tiles_x = views[v].tiles_x;
-    const uint32_t tbase = (uint32_t)views[v].tile_base;
-    int64_t pos = offsets[k];
-    if (pos + cnt > capacity) return;  // overflow: the scan total reports it
-    for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx, ++pos) {
-            inst_tiles[pos] = tbase + (uint32_t)(ty * tiles_x + tx);
-            inst_ids[pos] = id;
+    uint32_t id = 0, cnt = 0;
+    if (k < n_total) {
+        id = order[k];
+        cnt = tile_counts[id];
+    }
+    const bool solo = cnt > 0 && cnt <= kEmitSolo;
+    if (solo) {
+        const int v = (int)(id / (uint32_t)n);
+        const uint2 r = rects[id];
+        const int tx0 = r.x & 0xffff, ty0 = r.x >> 16, tx1 = r.y & 0xffff, ty1 = r.y >> 16;
+        const int tiles_x = views[v].tiles_x;
+        const uint32_t tbase = (uint32_t)views[v].tile_base;
+        int64_t pos = offsets[k];
+        if (pos + cnt <= capacity) {  // overflow: the scan total reports it
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx, ++pos) {
+                    inst_tiles[pos] = tbase + (uint32_t)(ty * tiles_x + tx);
+                    inst_ids[pos] = id;
+                }
         }
+    }
+    // queue the large rectangles of this wave and write them cooperatively
+    const bool large = cnt > kEmitSolo;
+    const unsigned long long mask = __ballot(large);
+    if (large) big[wave][__popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)(k - (int64_t)blockIdx.x * kThreads);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int nbig = __popcll(mask);
+    for (int b = 0; b < nbig; ++b) {
+        const int64_t kk = (int64_t)blockIdx.x * kThreads + big[wave][b];
+        const uint32_t bid = order[kk];
+        const uint32_t bcnt = tile_counts[bid];
+        const int64_t base = offsets[kk];
+        if (base + bcnt > capacity) continue;
+        const int v = (int)(bid / (uint32_t)n);
+        const uint2 r = rects[bid];
+        const int tx0 = r.x & 0xffff, ty0 = r.x >> 16, tx1 = r.y & 0xffff;
+        const uint32_t nx = (uint32_t)(tx1 - tx0 + 1);
+        const int tiles_x = views[v].tiles_x;
+        const uint32_t tbase = (uint32_t)views[v].tile_base;
+        for (uint32_t j = lane; j < bcnt; j += 64) {
+            const int ty = ty0 + (int)(j / nx), tx = tx0 + (int)(j % nx);
+            inst_tiles[base + j] = tbase + (uint32_t)(ty * tiles_x + tx);
+            inst_ids[base + j] = bid;
+        }
+    }
 }
 
 // ------------------------------------------------------------ tile ranges
@@ -310,6 +349,57 @@ __global__ __launch_bounds__(kThreads) void k_tile_ranges(const uint32_t *__rest
     if (t >= total_tiles) return;
     if (p == 0 || inst_tiles[p - 1] != t) ranges[t].x = (uint32_t)p;
     if (p == m - 1 || inst_tiles[p + 1] != t) ranges[t].y = (uint32_t)(p + 1);
+}
+
+// -------------------------------------------------------- tile scheduling
+// Work order of the compositing kernels: tiles sorted by decreasing list
+// length (coarse buckets of 4 entries, order inside a bucket arbitrary), so
+// the longest tiles start first and the persistent grid drains evenly.
+constexpr int kSchedBuckets = 256;
+
+__device__ __forceinline__ uint32_t work_bucket(uint2 r)
+{
+    const uint32_t len = r.y - r.x;
+    return min(len >> 2, (uint32_t)(kSchedBuckets - 1));
+}
+
+__global__ __launch_bounds__(kThreads) void k_sched_hist(const uint2 *__restrict__ ranges, int64_t total_tiles,
+                                                         uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t cnt[kSchedBuckets];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (t < total_tiles) atomicAdd(&cnt[work_bucket(ranges[t])], 1u);
+    __syncthreads();
+    if (cnt[threadIdx.x]) atomicAdd(&hist[threadIdx.x], cnt[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_sched_scatter(const uint2 *__restrict__ ranges, int64_t total_tiles,
+                                                            const uint32_t *__restrict__ hist,
+                                                            uint32_t *__restrict__ cursor,
+                                                            uint32_t *__restrict__ tile_order)
+{
+    __shared__ uint32_t smem[kWaves];
+    __shared__ uint32_t base[kSchedBuckets];
+    __shared__ uint32_t cnt[kSchedBuckets];
+    // buckets in decreasing order: bucket b starts after all tiles of buckets > b
+    const uint32_t hb = hist[kSchedBuckets - 1 - threadIdx.x];
+    uint32_t tot;
+    const uint32_t before = block_inclusive_scan(hb, smem, &tot) - hb;
+    base[kSchedBuckets - 1 - threadIdx.x] = before;
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    uint32_t b = 0, rank = 0;
+    if (t < total_tiles) {
+        b = work_bucket(ranges[t]);
+        rank = atomicAdd(&cnt[b], 1u);
+    }
+    __syncthreads();
+    if (cnt[threadIdx.x]) base[threadIdx.x] += atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
+    __syncthreads();
+    if (t < total_tiles) tile_order[base[b] + rank] = (uint32_t)t;
 }
 
 }  // namespace
@@ -375,17 +465,24 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t s
     return hipGetLastError();
 }
 
+size_t sched_words() { return 4 + 2 * kSchedBuckets; }
+
 hipError_t launch_tile_ranges(const uint32_t *inst_tiles, const int64_t *counters, int64_t capacity,
-                              int64_t total_tiles, uint2 *ranges, unsigned int *queues, hipStream_t stream)
+                              int64_t total_tiles, uint2 *ranges, uint32_t *sched, uint32_t *tile_order,
+                              hipStream_t stream)
 {
-    // empty ranges and the two work-queue heads (forward, backward) start at zero
+    // empty ranges; the work-queue heads and scheduling histograms start at zero
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * total_tiles, stream);
     if (e != hipSuccess) return e;
-    e = launch_fill_u32(queues, 0u, 2, stream);
+    e = launch_fill_u32(sched, 0u, (int64_t)sched_words(), stream);
     if (e != hipSuccess) return e;
     if (capacity > 0)
         k_tile_ranges<<<(unsigned)((capacity + kThreads - 1) / kThreads), kThreads, 0, stream>>>(inst_tiles, counters,
                                                                                                  capacity, total_tiles, ranges);
+    const unsigned nb = (unsigned)((total_tiles + kThreads - 1) / kThreads);
+    uint32_t *hist = sched + 4, *cursor = sched + 4 + kSchedBuckets;
+    k_sched_hist<<<nb, kThreads, 0, stream>>>(ranges, total_tiles, hist);
+    k_sched_scatter<<<nb, kThreads, 0, stream>>>(ranges, total_tiles, hist, cursor, tile_order);
     return hipGetLastError();
 }
 

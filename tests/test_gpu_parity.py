@@ -96,7 +96,7 @@ def test_lists_rebin_from_gpu_rects_and_keys(r):
         assert rng[t, 0] == idx[0] and rng[t, 1] == idx[-1] + 1
 
 
-@pytest.mark.parametrize("shape", [(8, 8), (16, 8), (16, 16), (32, 16), (32, 32)])
+@pytest.mark.parametrize("shape", [(8, 8), (8, 16), (8, 32), (16, 8), (16, 16), (16, 32), (32, 8), (32, 16), (32, 32)])
 def test_ragged_image_all_tile_shapes(r, shape):
     say(f"case ragged 131x77 tile {shape}")
     sc = scenegen.tiny_scene(32, 400, sh_degree=2, half_extent=1.2, log_scale_mean=-2.8, log_scale_std=0.7)
@@ -243,5 +243,5 @@ def test_autotune_picks_a_supported_shape(r):
     buf, ws = r.new_workspace(2000, cams, 500000, 0, r.options)
     outs = r.allocate_outputs(cams)
     best, ms = r.autotune(g, cams, ws, outs, reps=2)
-    assert (best["tile_w"], best["tile_h"]) in [(8, 8), (16, 8), (16, 16), (32, 16), (32, 32)]
+    assert best["tile_w"] in (8, 16, 32) and best["tile_h"] in (8, 16, 32)
     assert ms > 0
