@@ -75,7 +75,7 @@ typedef struct {
     const float *quats;          /* device [4][n], (w, x, y, z) */
     const float *opacity_logits; /* device [n] */
     const float *sh;             /* device [(sh_degree+1)^2][3][n] */
-    int64_t n;                   /* >= 0; n * n_views < 2^31 */
+    int64_t n;                   /* >= 0; n * n_views < 2^28 */
     int32_t sh_degree;           /* 0..3 */
 } rgs_gaussians;
 
@@ -192,16 +192,19 @@ rgs_status rgs_autotune(rgs_context *ctx, const rgs_gaussians *g, const rgs_came
  * profiling tools).  Counts are element counts.  Pure host arithmetic; ctx
  * may be NULL. */
 typedef struct {
-    size_t counters;       /* int64[8]: [0] instances needed, [1] capacity */
+    size_t counters;       /* int64[8]: [0] instances needed, [1] capacity, [2] tile rows of all boxes */
     size_t views;          /* per-view device table */
     size_t records;        /* float[16] per Gaussian-view, index v * n + i */
     size_t depth_keys;     /* uint32 per Gaussian-view (0xffffffff = culled) */
-    size_t rects;          /* uint16[4] per Gaussian-view: tile x0, y0, x1, y1 (inclusive) */
-    size_t tile_counts;    /* uint32 per Gaussian-view */
+    size_t boxes;          /* uint16[4] per Gaussian-view: pixel box x0, x1, y0, y1 (inclusive) */
+    size_t conics;         /* double[8] per Gaussian-view: support ellipse P00, P01, P11, h0, h1, f0, u0, v0 */
+    size_t tile_counts;    /* uint32 per Gaussian-view: tiles of its pixel box (0 = culled) */
     size_t order;          /* uint32 per Gaussian-view: Gaussian-view ids sorted by (depth, id) */
     size_t offsets;        /* uint32 per Gaussian-view: first instance of each sorted entry */
-    size_t inst_tiles;     /* uint32 per instance: global tile id, sorted */
-    size_t inst_ids;       /* uint32 per instance: Gaussian-view id, sorted by (tile, depth, id) */
+    size_t inst_tiles;     /* uint32 per instance: global tile id, sorted; a box tile whose row bands all
+                              miss the support holds 2^tile_bits - 1 (> every tile id) and sorts last */
+    size_t inst_ids;       /* uint32 per instance: Gaussian-view id (low 28 bits) sorted by (tile, depth, id);
+                              the top 4 bits flag the tile's row bands that meet the support */
     size_t tile_ranges;    /* uint32[2] per global tile: [start, end) into the instance arrays */
     size_t record_grads;   /* float[16] per Gaussian-view (RGS_WS_BACKWARD only, else 0) */
     size_t total_bytes;    /* what rgs_workspace_size reports */
@@ -209,7 +212,7 @@ typedef struct {
     int64_t capacity;      /* instances */
     int64_t total_tiles;   /* over all views */
     int32_t tile_w, tile_h;
-    int32_t tile_bits;     /* significant bits of a global tile id */
+    int32_t tile_bits;     /* sorted bits of a tile id: 2^tile_bits > total_tiles */
     int32_t reserved;
 } rgs_workspace_layout;
 

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "raygs_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-CULL = dict(visible=0, invalid=1, near=2, kappa=3, inside=4, offscreen=5)
+CULL = dict(visible=0, invalid=1, near=2, kappa=3, inside=4, offscreen=5, notile=6)
 HAZARD = dict(key=1, rect=2, eigen=4, cull=8, front=16)
 
 
@@ -55,7 +55,7 @@ SPLAT_DTYPE = np.dtype(
      ("all_front", np.int32), ("px0", np.int32), ("px1", np.int32), ("py0", np.int32), ("py1", np.int32),
      ("tx0", np.int32), ("tx1", np.int32), ("ty0", np.int32), ("ty1", np.int32), ("depth_key", np.uint32),
      ("pad", np.int32), ("rgb", np.float64, 3), ("rgb_raw", np.float64, 3), ("dir", np.float64, 3),
-     ("dist", np.float64)],
+     ("dist", np.float64), ("cq", np.float64, 6), ("bounded", np.int32), ("listed", np.int32)],
     align=True,
 )
 
@@ -78,6 +78,8 @@ def load():
         lib.orc_divergence.restype = C.c_double
         lib.orc_rot_mu_v.argtypes = [P, P]
         lib.orc_splat_size.restype = C.c_int
+        lib.orc_list_tiles.argtypes = [P, C.c_int64, P, C.c_int32, P, P, C.c_int64]
+        lib.orc_list_tiles.restype = C.c_int64
         if lib.orc_splat_size() != SPLAT_DTYPE.itemsize:
             raise RuntimeError("oracle splat layout mismatch")
         _lib = lib
@@ -183,26 +185,24 @@ def backward(scene, cam, opts, dL_dC):
 
 
 def tile_lists(splats, cam, opts, tile_base=0):
-    """Tile binning by definition: for every visible Gaussian and every tile of
-    its rectangle, the pair (tile id, Gaussian index), ordered by
+    """Tile binning by definition: for every visible Gaussian and every listed
+    tile (a row band of the tile meets the support ellipse, see
+    raygs_oracle.c), the pair (tile id, Gaussian index), ordered by
     (tile, depth key, Gaussian index).  Returns (tile ids int64, depth keys
     uint32, Gaussian indices int64)."""
+    lib = load()
     tiles_x = -(-int(cam["width"]) // int(opts["tile_w"]))
-    vis = np.nonzero(splats["cull"] == CULL["visible"])[0]
-    sv = splats[vis]
-    nx = (sv["tx1"] - sv["tx0"] + 1).astype(np.int64)
-    ny = (sv["ty1"] - sv["ty0"] + 1).astype(np.int64)
-    cnt = nx * ny
-    g = np.repeat(vis.astype(np.int64), cnt)
-    start = np.repeat(np.cumsum(cnt) - cnt, cnt)
-    local = np.arange(g.shape[0], dtype=np.int64) - start
-    rep_nx = np.repeat(nx, cnt)
-    tx = np.repeat(sv["tx0"].astype(np.int64), cnt) + local % rep_nx
-    ty = np.repeat(sv["ty0"].astype(np.int64), cnt) + local // rep_nx
-    tile = tile_base + ty * tiles_x + tx
-    key = np.repeat(sv["depth_key"], cnt)
-    order = np.lexsort((g, key, tile))
-    return tile[order], key[order], g[order]
+    sp = np.ascontiguousarray(splats)
+    total = int(sp["listed"][sp["cull"] == CULL["visible"]].sum())
+    tiles = np.zeros(max(total, 1), np.int64)
+    ids = np.zeros(max(total, 1), np.int64)
+    o = _options(opts)
+    w = lib.orc_list_tiles(_ptr(sp), sp.shape[0], C.byref(o), tiles_x, _ptr(tiles), _ptr(ids), total)
+    assert w == total
+    tiles, ids = tiles[:w] + tile_base, ids[:w]
+    key = sp["depth_key"][ids]
+    order = np.lexsort((ids, key, tiles))
+    return tiles[order], key[order], ids[order]
 
 
 def sh_basis(degree, d):

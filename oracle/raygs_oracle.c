@@ -68,7 +68,8 @@ enum {
     ORC_CULL_NEAR = 2,
     ORC_CULL_KAPPA = 3,
     ORC_CULL_INSIDE = 4,
-    ORC_CULL_OFFSCREEN = 5
+    ORC_CULL_OFFSCREEN = 5,
+    ORC_CULL_NOTILE = 6
 };
 
 enum { /* hazard bits: a decision taken within rounding distance */
@@ -101,6 +102,9 @@ typedef struct {
     double rgb[3], rgb_raw[3];
     double dir[3];    /* unit view direction used for the colour */
     double dist;      /* |m - camera centre| */
+    double cq[6];     /* support conic in pixel coordinates: A00, A01, A11, b0, b1, c */
+    int32_t bounded;  /* the conic is an ellipse (A positive definite) */
+    int32_t listed;   /* tiles listed for this Gaussian */
 } orc_splat;
 
 /* --------------------------------------------------------- small helpers */
@@ -264,6 +268,94 @@ static int depth_key_hazard(double z, double tol)
     double mlo = 0.5 * ((double)f + (double)lo), mhi = 0.5 * ((double)f + (double)hi);
     double dlo = fabs(z - mlo), dhi = fabs(z - mhi);
     return (dlo > 0.0 && dlo <= tol) || (dhi > 0.0 && dhi <= tol);
+}
+
+/* ------------------------------------------------------ tile listing
+ * The pixels p whose ray x(p) = ((p_x - c_x)/f_x, (p_y - c_y)/f_y, 1) meets the
+ * support satisfy D <= kappa, i.e. (c^2 - kappa) x^T Sigma^-1 x <= (x^T Sigma^-1 mu)^2
+ * (eqs. 3, 5), a conic [p;1]^T C [p;1] <= 0 with
+ * C = K^-T ((c^2 - kappa) Sigma^-1 - Sigma^-1 mu mu^T Sigma^-1) K^-1.  When its
+ * 2x2 block is positive definite the region is one ellipse around pi(mu).  A
+ * tile is listed when, for one of its row bands (64 / tile_w rows), the
+ * rectangle spanned by the band's pixel centres inside the Gaussian's pixel
+ * box meets that ellipse (every tile of the box when it is unbounded); a tile
+ * that would have more than 4 such bands is tested as one band. */
+static void support_conic(orc_splat *sp, const orc_camera *cam)
+{
+    double Sinv[9], tmp[9], Lam[9] = {0};
+    for (int k = 0; k < 3; ++k) Lam[4 * k] = 1.0 / (sp->s[k] * sp->s[k]);
+    mat3_mul(sp->Rp, Lam, tmp);
+    double RpT[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) RpT[3 * r + c] = sp->Rp[3 * c + r];
+    mat3_mul(tmp, RpT, Sinv);
+    double Sm[3];
+    mat3_vec(Sinv, sp->mu, Sm);
+    double N[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) N[3 * r + c] = (sp->c2 - sp->kappa) * Sinv[3 * r + c] - Sm[r] * Sm[c];
+    const double Ki[9] = {1.0 / cam->fx, 0.0, -cam->cx / cam->fx, 0.0, 1.0 / cam->fy, -cam->cy / cam->fy, 0, 0, 1};
+    double KiT[9], NK[9], C[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) KiT[3 * r + c] = Ki[3 * c + r];
+    mat3_mul(N, Ki, NK);
+    mat3_mul(KiT, NK, C);
+    sp->cq[0] = C[0]; sp->cq[1] = 0.5 * (C[1] + C[3]); sp->cq[2] = C[4];
+    sp->cq[3] = 0.5 * (C[2] + C[6]); sp->cq[4] = 0.5 * (C[5] + C[7]); sp->cq[5] = C[8];
+    double det = sp->cq[0] * sp->cq[2] - sp->cq[1] * sp->cq[1];
+    sp->bounded = sp->cq[0] > 0.0 && det > 0.0;
+    if (fabs(det) <= 1e-9 * (fabs(sp->cq[0] * sp->cq[2]) + sp->cq[1] * sp->cq[1])) sp->hazard |= ORC_HZ_RECT;
+}
+
+static double conic_at(const double *q, double x, double y)
+{
+    return q[0] * x * x + 2.0 * q[1] * x * y + q[2] * y * y + 2.0 * (q[3] * x + q[4] * y) + q[5];
+}
+
+/* minimum of the conic over the rectangle of pixel centres [x0, x1] x [y0, y1] */
+static double conic_rect_min(const double *q, int x0, int x1, int y0, int y1)
+{
+    double xa = x0 + 0.5, xb = x1 + 0.5, ya = y0 + 0.5, yb = y1 + 0.5;
+    double det = q[0] * q[2] - q[1] * q[1];
+    double px = (q[1] * q[4] - q[2] * q[3]) / det, py = (q[1] * q[3] - q[0] * q[4]) / det;
+    if (px >= xa && px <= xb && py >= ya && py <= yb) return conic_at(q, px, py);
+    double best = INFINITY;
+    double xe[2] = {xa, xb}, ye[2] = {ya, yb};
+    for (int e = 0; e < 2; ++e) {
+        double y = -(q[1] * xe[e] + q[4]) / q[2];
+        y = y < ya ? ya : (y > yb ? yb : y);
+        best = fmin(best, conic_at(q, xe[e], y));
+        double x = -(q[1] * ye[e] + q[3]) / q[0];
+        x = x < xa ? xa : (x > xb ? xb : x);
+        best = fmin(best, conic_at(q, x, ye[e]));
+    }
+    return best;
+}
+
+/* Is tile (tx, ty) listed for splat sp?  Flags a hazard when a decision is
+ * within rounding of the boundary. */
+static int tile_listed(orc_splat *sp, const orc_options *opt, int tx, int ty)
+{
+    /* bands of 64 / tile_w rows, or the whole tile when that makes more than 4 */
+    int TW = opt->tile_w, TH = opt->tile_h, LY = 64 / TW;
+    if (TH / LY > 4) LY = TH;
+    int cx0 = tx * TW > sp->px0 ? tx * TW : sp->px0;
+    int cx1 = tx * TW + TW - 1 < sp->px1 ? tx * TW + TW - 1 : sp->px1;
+    if (cx0 > cx1) return 0;
+    if (!sp->bounded) return 1;
+    /* scale: |conic| at the projected centre = kappa c^2 / mu_z^2 */
+    double scale = sp->kappa * sp->c2 / (sp->mu[2] * sp->mu[2]);
+    int listed = 0;
+    for (int b = 0; b < TH / LY; ++b) {
+        int r0 = ty * TH + b * LY, r1 = r0 + LY - 1;
+        if (r0 < sp->py0) r0 = sp->py0;
+        if (r1 > sp->py1) r1 = sp->py1;
+        if (r0 > r1) continue;
+        double m = conic_rect_min(sp->cq, cx0, cx1, r0, r1);
+        if (fabs(m) <= 1e-9 * scale) sp->hazard |= ORC_HZ_RECT;
+        if (m <= 0.0) listed = 1;
+    }
+    return listed;
 }
 
 /* ------------------------------------------------------ per-Gaussian stage */
@@ -464,6 +556,14 @@ static void preprocess_one(const orc_scene *sc, int64_t i, const orc_camera *cam
     }
     sp->tx0 = px0 / opt->tile_w; sp->tx1 = px1 / opt->tile_w;
     sp->ty0 = py0 / opt->tile_h; sp->ty1 = py1 / opt->tile_h;
+    support_conic(sp, cam);
+    sp->listed = 0;
+    for (int ty = sp->ty0; ty <= sp->ty1; ++ty)
+        for (int tx = sp->tx0; tx <= sp->tx1; ++tx) sp->listed += tile_listed(sp, opt, tx, ty);
+    if (sp->listed == 0) {
+        sp->cull = ORC_CULL_NOTILE;
+        return;
+    }
 
     /* colour: SH at the unit direction from the camera centre to the mean */
     double Cw[3]; /* camera centre = -W^T t */
@@ -718,10 +818,7 @@ int orc_render(const orc_scene *sc, const orc_camera *cam, const orc_options *op
     }
     if (counters) {
         int64_t inst = 0;
-        for (int64_t k = 0; k < m; ++k) {
-            const orc_splat *s = &sp[order[k]];
-            inst += (int64_t)(s->tx1 - s->tx0 + 1) * (s->ty1 - s->ty0 + 1);
-        }
+        for (int64_t k = 0; k < m; ++k) inst += sp[order[k]].listed;
         counters[0] = m;
         counters[1] = inst;
         counters[2] = frags;
@@ -912,6 +1009,27 @@ int orc_backward(const orc_scene *sc, const orc_camera *cam, const orc_options *
     free(order);
     free(sp);
     return 0;
+}
+
+/* (tile, Gaussian) pairs of every listed tile of the visible splats, in
+ * Gaussian index order and row-major tile order; tiles[] receives
+ * ty * tiles_x + tx.  Returns the number of pairs written (at most cap). */
+int64_t orc_list_tiles(orc_splat *sp, int64_t n, const orc_options *opt, int32_t tiles_x, int64_t *tiles,
+                       int64_t *ids, int64_t cap)
+{
+    int64_t w = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        orc_splat *s = &sp[i];
+        if (s->cull != ORC_VISIBLE) continue;
+        for (int ty = s->ty0; ty <= s->ty1; ++ty)
+            for (int tx = s->tx0; tx <= s->tx1; ++tx)
+                if (tile_listed(s, opt, tx, ty) && w < cap) {
+                    tiles[w] = (int64_t)ty * tiles_x + tx;
+                    ids[w] = i;
+                    ++w;
+                }
+    }
+    return w;
 }
 
 int orc_splat_size(void) { return (int)sizeof(orc_splat); }

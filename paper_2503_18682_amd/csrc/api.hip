@@ -24,8 +24,9 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t counters, views, records, keys_a, keys_b, order_a, order_b, rects, tile_counts, offsets, block_sums;
+    size_t counters, views, records, keys_a, keys_b, order_a, order_b, boxes, conics, tile_counts, offsets, block_sums;
     size_t inst_tiles_a, inst_tiles_b, inst_ids_a, inst_ids_b, hist, row_total, ranges, sched, tile_order;
+    size_t row_offsets, row_owner;
     size_t record_grads, total;
     int64_t nv_records, capacity, total_tiles;
     int tile_w, tile_h, tile_bits;
@@ -151,8 +152,8 @@ rgs_status compute_layout(rgs_context *ctx, int64_t n, const rgs_camera *cams, i
     if (st != RGS_OK) return st;
     if ((st = check_options(ctx, opts)) != RGS_OK) return st;
     if (n < 0) return fail(ctx, RGS_EINVAL, "n=%lld < 0", (long long)n);
-    if (n * (int64_t)n_views >= (int64_t(1) << 31) - 1)
-        return fail(ctx, RGS_EINVAL, "n * n_views must be below 2^31");
+    if (n * (int64_t)n_views > (int64_t)kIdMask)
+        return fail(ctx, RGS_EINVAL, "n * n_views must be below 2^28");
     if (capacity < 1 || capacity > 0xffffffffLL) return fail(ctx, RGS_EINVAL, "capacity must lie in [1, 2^32)");
     if (flags & ~RGS_WS_BACKWARD) return fail(ctx, RGS_EINVAL, "unknown workspace flags 0x%x", flags);
     const TileShape s = shape_of(*opts);
@@ -163,7 +164,7 @@ rgs_status compute_layout(rgs_context *ctx, int64_t n, const rgs_camera *cams, i
         tiles += (int64_t)((cams[v].width + s.w - 1) / s.w) * ((cams[v].height + s.h - 1) / s.h);
     if (tiles >= (int64_t(1) << 31)) return fail(ctx, RGS_EINVAL, "too many tiles");
     L.total_tiles = tiles;
-    L.tile_bits = bits_for(tiles);
+    L.tile_bits = bits_for(tiles + 1);  // 2^tile_bits - 1 (the empty-instance tile) >= tiles
     L.nv_records = n * n_views;
     L.capacity = capacity;
     const size_t NV = (size_t)L.nv_records;
@@ -180,9 +181,11 @@ rgs_status compute_layout(rgs_context *ctx, int64_t n, const rgs_camera *cams, i
     L.keys_b = take(NV * 4);
     L.order_a = take(NV * 4);
     L.order_b = take(NV * 4);
-    L.rects = take(NV * 8);
+    L.boxes = take(NV * 8);
+    L.conics = take(NV * sizeof(Conic));
     L.tile_counts = take(NV * 4);
     L.offsets = take(NV * 4);
+    L.row_offsets = take(NV * 4);
     L.block_sums = take(scan_block_entries((int64_t)NV) * 8);
     L.inst_tiles_a = take((size_t)capacity * 4);
     L.inst_tiles_b = take((size_t)capacity * 4);
@@ -193,6 +196,7 @@ rgs_status compute_layout(rgs_context *ctx, int64_t n, const rgs_camera *cams, i
     L.ranges = take((size_t)tiles * 8);
     L.sched = take(sched_words() * 4);
     L.tile_order = take((size_t)tiles * 4);
+    L.row_owner = take((size_t)capacity * 4);
     L.record_grads = (flags & RGS_WS_BACKWARD) ? take(NV * kGradFloats * sizeof(float)) : 0;
     L.total = off;
     return RGS_OK;
@@ -205,7 +209,8 @@ void fill_public_layout(const Layout &L, rgs_workspace_layout *o)
     o->views = L.views;
     o->records = L.records;
     o->depth_keys = L.keys_a;
-    o->rects = L.rects;
+    o->boxes = L.boxes;
+    o->conics = L.conics;
     o->tile_counts = L.tile_counts;
     o->order = L.order_a;
     o->offsets = L.offsets;
@@ -337,7 +342,8 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
     uint32_t *ids_in = at<uint32_t>(ws, tpasses % 2 ? L.inst_ids_b : L.inst_ids_a);
     uint32_t *ids_alt = at<uint32_t>(ws, tpasses % 2 ? L.inst_ids_a : L.inst_ids_b);
     float4 *records = at<float4>(ws, L.records);
-    uint2 *rects = at<uint2>(ws, L.rects);
+    uint2 *boxes = at<uint2>(ws, L.boxes);
+    Conic *conics = at<Conic>(ws, L.conics);
     uint32_t *tile_counts = at<uint32_t>(ws, L.tile_counts);
     uint32_t *hist = at<uint32_t>(ws, L.hist);
     uint32_t *row_total = at<uint32_t>(ws, L.row_total);
@@ -346,17 +352,21 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
     const uint32_t *tile_order = at<uint32_t>(ws, L.tile_order);
 
     Timer tm(ctx, stream, timing, ST_PRE);
-    RGS_HIP(ctx, launch_preprocess(g, views, n_views, dopt, records, keys_in, ord_in, rects, tile_counts, stream));
+    RGS_HIP(ctx, launch_preprocess(g, views, n_views, dopt, records, keys_in, ord_in, boxes, conics, tile_counts,
+                                   stream));
     tm.mark(ST_PRE);
     RGS_HIP(ctx, radix_sort(keys_in, ord_in, keys_alt, ord_alt, NV, nullptr, 32, hist, row_total, stream));
     tm.mark(ST_DSORT);
     const uint32_t *order = at<uint32_t>(ws, L.order_a);
     uint32_t *offsets = at<uint32_t>(ws, L.offsets);
-    RGS_HIP(ctx, exclusive_scan_gather(tile_counts, order, offsets, NV, at<unsigned long long>(ws, L.block_sums),
-                                       counters, stream));
+    uint32_t *row_offsets = at<uint32_t>(ws, L.row_offsets);
+    uint32_t *row_owner = at<uint32_t>(ws, L.row_owner);
+    RGS_HIP(ctx, binning_scan(tile_counts, boxes, order, NV, s.h, L.capacity, offsets, row_offsets, row_owner,
+                              at<unsigned long long>(ws, L.block_sums), counters, stream));
     tm.mark(ST_SCAN);
-    RGS_HIP(ctx, launch_emit(order, offsets, tile_counts, rects, views, g.n, n_views, L.capacity, tiles_in, ids_in,
-                             stream));
+    const uint32_t empty_tile = (uint32_t)((int64_t(1) << L.tile_bits) - 1);
+    RGS_HIP(ctx, launch_emit(order, offsets, row_offsets, row_owner, boxes, conics, views, g.n, n_views, counters,
+                             L.capacity, s.w, s.h, empty_tile, tiles_in, ids_in, emit_grid(ctx->num_cus), stream));
     tm.mark(ST_EMIT);
     RGS_HIP(ctx, radix_sort(tiles_in, ids_in, tiles_alt, ids_alt, L.capacity, counters, L.tile_bits, hist, row_total,
                             stream));
@@ -526,11 +536,12 @@ rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const r
     float *rgrads = at<float>(ws->ptr, L.record_grads);
     Timer tm(ctx, s, true, ST_BLEND_BWD);
     RGS_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(rgrads), 0u, L.nv_records * kGradFloats, s));
-    RGS_HIP(ctx, launch_fill_u32(sched + 1, 0u, 1, s));
+    uint32_t *bwd_heads = sched + sched_backward_heads();
+    RGS_HIP(ctx, launch_fill_u32(bwd_heads, 0u, (int64_t)kQueues * kQueueStride, s));
     RGS_HIP(ctx, launch_blend_backward(sh, at<uint2>(ws->ptr, L.ranges), at<uint32_t>(ws->ptr, L.tile_order),
                                        at<uint32_t>(ws->ptr, L.inst_ids_a), at<float4>(ws->ptr, L.records),
                                        at<DevView>(ws->ptr, L.views), n_views, L.total_tiles, L.nv_records, dopt,
-                                       rgrads, sched + 1, ctx->grid_bwd[shape_index(sh)], s));
+                                       rgrads, bwd_heads, ctx->grid_bwd[shape_index(sh)], s));
     tm.mark(ST_BLEND_BWD);
     RGS_HIP(ctx, launch_preprocess_backward(*g, at<DevView>(ws->ptr, L.views), n_views, dopt,
                                             at<uint32_t>(ws->ptr, L.tile_counts), rgrads, *grads, s));

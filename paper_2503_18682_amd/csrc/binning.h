@@ -1,0 +1,185 @@
+// Exact support-versus-tile test shared by the preprocess kernel (which
+// counts the listed tiles of each Gaussian-view) and the emission kernel
+// (which writes them): both evaluate the same double-precision code on the
+// same stored values, so they take identical decisions.
+//
+// In pixel offsets delta = p - pi(mu) the support omega >= p_min, tau > 0 of a
+// Gaussian whose quad lies in front of the camera is the ellipse
+//     F(delta) = delta^T P delta - 2 h . delta - f0 <= 0,
+// P = b^2 G^T G - kappa g g^T, h = kappa k0 g, f0 = kappa k0^2
+// (from q b^2 <= kappa den^2 with q = |G delta|^2, den = k0 + g . delta,
+// b^2 = 1 - kappa / c^2).  When P is not positive definite the support is
+// unbounded on the image plane and every tile of the bounding rectangle is
+// kept.  A row band of a tile is listed when the continuous rectangle
+// spanned by its pixel centres (clipped to the Gaussian's pixel box) meets
+// the ellipse; a tile is listed when one of its bands is.  The test is done
+// per tile row: the ellipse's x-extent over each band's heights is computed in
+// closed form, then each tile of the row is an interval comparison.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rgs {
+
+struct Conic {
+    double P00, P01, P11, h0, h1, f0, u0, v0;  // u0, v0: projected centre (pixels)
+};
+
+// Pixel box of a Gaussian-view: x0 | x1 << 16, y0 | y1 << 16 (inclusive).
+struct PixelBox {
+    int x0, x1, y0, y1;
+};
+
+__host__ __device__ inline PixelBox unpack_box(uint2 b)
+{
+    return PixelBox{(int)(b.x & 0xffffu), (int)(b.x >> 16), (int)(b.y & 0xffffu), (int)(b.y >> 16)};
+}
+
+// Quantities of the ellipse derived once per Gaussian-view (delta units):
+// centre c = P^-1 h, R^2 = f0 + h . c (so the ellipse is
+// (d - c)^T P (d - c) <= R^2), its extents and the heights of its leftmost
+// and rightmost points.
+struct ConicFrame {
+    double cx, cy, xmin, xmax, ymin, ymax, yleft, yright, inv_p00;
+    bool bounded;
+};
+
+__device__ inline ConicFrame conic_frame(const Conic &C)
+{
+#pragma clang fp contract(off)
+    ConicFrame F{};
+    const double det = C.P00 * C.P11 - C.P01 * C.P01;
+    F.bounded = C.P00 > 0.0 && det > 0.0;
+    if (!F.bounded) return F;
+    F.cx = (C.P11 * C.h0 - C.P01 * C.h1) / det;
+    F.cy = (C.P00 * C.h1 - C.P01 * C.h0) / det;
+    const double R2 = C.f0 + C.h0 * F.cx + C.h1 * F.cy;
+    const double hx = sqrt(R2 * C.P11 / det), hy = sqrt(R2 * C.P00 / det);
+    const double sy = C.P01 * sqrt(R2 / (C.P11 * det));
+    F.xmin = F.cx - hx;
+    F.xmax = F.cx + hx;
+    F.ymin = F.cy - hy;
+    F.ymax = F.cy + hy;
+    F.yleft = F.cy + sy;
+    F.yright = F.cy - sy;
+    F.inv_p00 = 1.0 / C.P00;
+    return F;
+}
+
+// x-extent [xl, xr] of the ellipse over heights y in [ya, yb]; false if the
+// ellipse does not reach that height range.  The left boundary is convex and
+// the right one concave in y, so off their extreme points the extent is set
+// by the chord at an end of the (clipped) range.
+__device__ inline bool conic_xrange(const Conic &C, const ConicFrame &F, double ya, double yb, double &xl, double &xr)
+{
+#pragma clang fp contract(off)
+    ya = fmax(ya, F.ymin);
+    yb = fmin(yb, F.ymax);
+    if (ya > yb) return false;
+    const double ys[2] = {ya, yb};
+    double lo = INFINITY, hi = -INFINITY;
+    for (int e = 0; e < 2; ++e) {
+        const double y = ys[e];
+        const double bq = C.P01 * y - C.h0;
+        const double disc = fmax(bq * bq - C.P00 * (C.P11 * y * y - 2.0 * C.h1 * y - C.f0), 0.0);
+        const double r = sqrt(disc);
+        lo = fmin(lo, (-bq - r) * F.inv_p00);
+        hi = fmax(hi, (-bq + r) * F.inv_p00);
+    }
+    xl = (F.yleft >= ya && F.yleft <= yb) ? F.xmin : lo;
+    xr = (F.yright >= ya && F.yright <= yb) ? F.xmax : hi;
+    return true;
+}
+
+// Row bands used for culling: rows [k*LY, (k+1)*LY) of a tile with
+// LY = 64 / TW (the rows one pixel slot of a compositing wave spans) when a
+// tile has at most 4 of them; a taller tile is tested as one band of TH rows.
+constexpr int kMaxBands = 4;
+
+__device__ inline int cull_band_rows(int TW, int TH)
+{
+    const int LY = 64 / TW;
+    return TH / LY <= kMaxBands ? LY : TH;
+}
+
+// x-extent of the ellipse over each culling band of tile row ty, in pixels.
+struct BandRanges {
+    double xl[kMaxBands], xr[kMaxBands];
+    uint32_t valid;
+};
+
+__device__ inline void band_ranges(const Conic &C, const ConicFrame &F, const PixelBox &box, int ty, int TW, int TH,
+                                   BandRanges &B)
+{
+#pragma clang fp contract(off)
+    const int LY = cull_band_rows(TW, TH), nb = TH / LY;
+    B.valid = 0u;
+#pragma unroll
+    for (int k = 0; k < kMaxBands; ++k) {
+        B.xl[k] = -INFINITY;
+        B.xr[k] = INFINITY;
+        if (k >= nb) continue;
+        const int r0 = max(ty * TH + k * LY, box.y0), r1 = min(ty * TH + k * LY + LY - 1, box.y1);
+        if (r0 > r1) continue;
+        if (!F.bounded) {
+            B.valid |= 1u << k;
+            continue;
+        }
+        double xl, xr;
+        if (conic_xrange(C, F, (double)r0 + 0.5 - C.v0, (double)r1 + 0.5 - C.v0, xl, xr)) {
+            B.valid |= 1u << k;
+            B.xl[k] = xl;
+            B.xr[k] = xr;
+        }
+    }
+}
+
+// Culling bands of tile (tx, .) that meet the support: the band's
+// pixel-centre rectangle (clipped to the box) overlaps the band's x-extent.
+// 0 = tile not listed.
+__device__ inline uint32_t tile_bands(const Conic &C, const BandRanges &B, const PixelBox &box, int tx, int TW)
+{
+#pragma clang fp contract(off)
+    const int cx0 = max(tx * TW, box.x0), cx1 = min(tx * TW + TW - 1, box.x1);
+    if (cx0 > cx1) return 0u;
+    const double xa = (double)cx0 + 0.5 - C.u0, xb = (double)cx1 + 0.5 - C.u0;
+    uint32_t bands = 0u;
+#pragma unroll
+    for (int k = 0; k < kMaxBands; ++k)
+        if (((B.valid >> k) & 1u) && xa <= B.xr[k] && xb >= B.xl[k]) bands |= 1u << k;
+    return bands;
+}
+
+// Number of listed tiles in a tile row whose band ranges are B.
+__device__ inline uint32_t row_listed(const Conic &C, const BandRanges &B, const PixelBox &box, int TW)
+{
+    if (!B.valid) return 0u;
+    uint32_t n = 0u;
+    for (int tx = box.x0 / TW; tx <= box.x1 / TW; ++tx) n += tile_bands(C, B, box, tx, TW) != 0u;
+    return n;
+}
+
+// Boxes with at most this many tile rows and tiles are listed by one lane;
+// larger ones by a whole wave, one lane per tile row.
+constexpr int kSoloRows = 4, kSoloTiles = 16;
+
+__device__ inline bool solo_box(const PixelBox &b, int TW, int TH)
+{
+    const int rows = b.y1 / TH - b.y0 / TH + 1;
+    return rows <= kSoloRows && rows * (b.x1 / TW - b.x0 / TW + 1) <= kSoloTiles;
+}
+
+// Instance values carry the culling-band bits of their tile in the top 4
+// bits (a tile tested as one band carries none; its rows are then bounded by
+// the record's pixel rows).
+constexpr uint32_t kIdBits = 28;
+constexpr uint32_t kIdMask = (1u << kIdBits) - 1u;
+
+__device__ inline uint32_t pack_instance(uint32_t id, uint32_t bands, int TW, int TH)
+{
+    return cull_band_rows(TW, TH) == 64 / TW ? id | (bands << kIdBits) : id;
+}
+
+}  // namespace rgs

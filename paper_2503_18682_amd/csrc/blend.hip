@@ -3,7 +3,9 @@
 // Work decomposition: one wavefront (64 lanes) owns one screen tile of
 // TW x TH pixels; lane l covers column l % TW and rows l / TW + k * (64 / TW),
 // k < TW * TH / 64.  Waves of a workgroup are independent: each pulls tile ids
-// from a global atomic queue (persistent grid), stages 64 raster records at a
+// from one of kQueues atomic queues (persistent grid; the queues interleave
+// the heavy-first work order, and splitting the head keeps one memory
+// address from serialising every take), stages 64 raster records at a
 // time in its own LDS slice and reads them back as broadcasts, and leaves the
 // tile as soon as a ballot shows that no lane has a live pixel (early ray
 // termination).  No workgroup barrier is ever taken.
@@ -132,12 +134,13 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
     constexpr int LX = TW, LY = 64 / TW, PPL = TH / LY;
     static_assert(64 % TW == 0 && TH % LY == 0, "tile shape");
     __shared__ float4 s_rec[4][64][4];
+    __shared__ uint32_t s_bands[4][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lx = lane % LX, ly = lane / LX;
+    const int nq = min((int)gridDim.x, kQueues), q = (int)blockIdx.x % nq;
+    unsigned int *const head = queue + q * kQueueStride;
     for (;;) {
-        int slot = 0;
-        if (lane == 0) slot = (int)atomicAdd(queue, 1u);
-        slot = __builtin_amdgcn_readfirstlane(slot);
+        const int64_t slot = q + (int64_t)nq * wave_fetch_add(head, 1u);
         if (slot >= P.total_tiles) break;
         const int tile = (int)tile_order[slot];
         const DevView &V = views[find_view(views, P.n_views, tile)];
@@ -161,21 +164,31 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
         bool wave_live = true;
         // batch 0 goes straight to LDS; batch b+1 is prefetched into registers
         // while batch b is composited
-        if (rg.x + lane < rg.y) stage_record(s_rec[wave][lane], records, inst_ids[rg.x + lane], P.n_records);
+        if (rg.x + lane < rg.y) {
+            const uint32_t v = inst_ids[rg.x + lane];
+            stage_record(s_rec[wave][lane], records, v & kIdMask, P.n_records);
+            s_bands[wave][lane] = v >> kIdBits;
+        }
         for (uint32_t base = rg.x; base < rg.y && wave_live; base += 64) {
             const uint32_t nb = min(64u, rg.y - base);
             const uint32_t next = base + 64 + lane;
             const bool have_next = next < rg.y;
             float4 pre[4];
-            if (have_next) stage_record(pre, records, inst_ids[next], P.n_records);
+            uint32_t pre_bands = 0u;
+            if (have_next) {
+                const uint32_t v = inst_ids[next];
+                stage_record(pre, records, v & kIdMask, P.n_records);
+                pre_bands = v >> kIdBits;
+            }
             lds_wave_sync();
             for (uint32_t j = 0; j < nb; ++j) {
                 const Rec R = load_rec(s_rec[wave][j]);
                 const float K = R.log2o - P.log2_pmin;
                 const RowSpan span = row_span(R, ty * TH);
+                const uint32_t bands = __builtin_amdgcn_readfirstlane(s_bands[wave][j]);
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) {
-                    if (span.r1 < k * LY || span.r0 >= (k + 1) * LY) continue;
+                    if (PPL <= 4 ? !((bands >> k) & 1u) : (span.r1 < k * LY || span.r0 >= (k + 1) * LY)) continue;
                     if (!live[k]) continue;
                     Frag f;
                     if (frag_test(R, K, pxc, pyc[k], f)) {
@@ -206,6 +219,7 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
             if (have_next) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) s_rec[wave][lane][c] = pre[c];
+                s_bands[wave][lane] = pre_bands;
             }
         }
         const size_t plane = (size_t)V.width * V.height;
@@ -242,12 +256,13 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
     constexpr int LX = TW, LY = 64 / TW, PPL = TH / LY;
     __shared__ float4 s_rec[4][64][4];
     __shared__ uint32_t s_id[4][64];
+    __shared__ uint32_t s_bands[4][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lx = lane % LX, ly = lane / LX;
+    const int nq = min((int)gridDim.x, kQueues), q = (int)blockIdx.x % nq;
+    unsigned int *const head = queue + q * kQueueStride;
     for (;;) {
-        int slot = 0;
-        if (lane == 0) slot = (int)atomicAdd(queue, 1u);
-        slot = __builtin_amdgcn_readfirstlane(slot);
+        const int64_t slot = q + (int64_t)nq * wave_fetch_add(head, 1u);
         if (slot >= P.total_tiles) break;
         const int tile = (int)tile_order[slot];
         const DevView &V = views[find_view(views, P.n_views, tile)];
@@ -286,8 +301,10 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
             const int lo = hi > 64 ? hi - 64 : 0;
             const int nb = hi - lo;
             if (lane < nb) {
-                const uint32_t id = inst_ids[rg.x + lo + lane];
+                const uint32_t v = inst_ids[rg.x + lo + lane];
+                const uint32_t id = v & kIdMask;
                 s_id[wave][lane] = id < P.n_records ? id : 0xffffffffu;
+                s_bands[wave][lane] = v >> kIdBits;
                 stage_record(s_rec[wave][lane], records, id, P.n_records);
             }
             lds_wave_sync();
@@ -296,13 +313,14 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                 const Rec R = load_rec(s_rec[wave][jj]);
                 const float K = R.log2o - P.log2_pmin;
                 const RowSpan span = row_span(R, ty * TH);
+                const uint32_t bands = __builtin_amdgcn_readfirstlane(s_bands[wave][jj]);
                 const float inv_o = __builtin_amdgcn_exp2f(-R.log2o);
                 float du0 = 0, dv0 = 0, dM00 = 0, dM01 = 0, dM11 = 0, dgx = 0, dgy = 0, dk0 = 0, dic2 = 0, dop = 0,
                       dr = 0, dg = 0, db = 0;
                 bool hit = false;
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) {
-                    if (span.r1 < k * LY || span.r0 >= (k + 1) * LY) continue;
+                    if (PPL <= 4 ? !((bands >> k) & 1u) : (span.r1 < k * LY || span.r0 >= (k + 1) * LY)) continue;
                     if (j >= last[k]) continue;
                     Frag f;
                     if (!frag_test(R, K, pxc, pyc[k], f)) continue;

@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "binning.h"
 #include "raygs.h"
 
 namespace rgs {
@@ -55,9 +56,12 @@ struct TileShape {
 };
 
 // ---- launchers (each enqueues on `stream`, returns hipError_t) -----------
+// Writes per Gaussian-view: record, depth key (0xffffffff when culled), the
+// identity order, pixel box, support conic, and the number of tiles of the
+// box (0 when culled).
 hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n_views, const DevOptions &opt,
-                             float4 *records, uint32_t *depth_keys, uint32_t *order, uint2 *rects,
-                             uint32_t *tile_counts, hipStream_t stream);
+                             float4 *records, uint32_t *depth_keys, uint32_t *order, uint2 *boxes,
+                             Conic *conics, uint32_t *tile_counts, hipStream_t stream);
 
 // Stable LSD radix sort of (key, value) pairs on bits [0, bits).  n_dev (may
 // be null) holds a device-side element count, clamped to n_max.  Ping-pongs
@@ -68,19 +72,39 @@ hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32
                       const int64_t *n_dev, int bits, uint32_t *hist, uint32_t *row_total, hipStream_t stream);
 size_t radix_hist_entries(int64_t n_max);
 
-// offsets[k] = sum_{j<k} counts[gather[k]], counters[0] = total (int64).
-hipError_t exclusive_scan_gather(const uint32_t *counts, const uint32_t *gather, uint32_t *offsets, int64_t n,
-                                 unsigned long long *block_sums, int64_t *total, hipStream_t stream);
+// Binning scan over the depth order (Gaussian-view order[k] at position k):
+// offsets[k] = box tiles and row_offsets[k] = box tile rows of the positions
+// before k; counters[0] = all box tiles (instances), counters[2] = all tile
+// rows (int64); row_owner[r] = k for each tile row r of position k, written
+// when the instances fit `capacity` (row_owner holds capacity entries).
+// block_sums holds scan_block_entries(n) uint64.
+hipError_t binning_scan(const uint32_t *tile_counts, const uint2 *boxes, const uint32_t *order, int64_t n,
+                        int tile_h, int64_t capacity, uint32_t *offsets, uint32_t *row_offsets, uint32_t *row_owner,
+                        unsigned long long *block_sums, int64_t *counters, hipStream_t stream);
 size_t scan_block_entries(int64_t n);
 
-hipError_t launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *tile_counts, const uint2 *rects,
-                       const DevView *views, int64_t n, int n_views, int64_t capacity, uint32_t *inst_tiles,
-                       uint32_t *inst_ids, hipStream_t stream);
+// Instances of every tile row (one lane per row, `grid` workgroups looping
+// over counters[2] rows): (tile id, id | band bits) for listed tiles and
+// (empty_tile, id) for the other tiles of the box.
+int emit_grid(int num_cus);
+hipError_t launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *row_offsets,
+                       const uint32_t *row_owner, const uint2 *boxes, const Conic *conics, const DevView *views,
+                       int64_t n, int n_views, const int64_t *counters, int64_t capacity, int tile_w, int tile_h,
+                       uint32_t empty_tile, uint32_t *inst_tiles, uint32_t *inst_ids, int grid, hipStream_t stream);
+
+// Compositing work queues: kQueues heads per pass, kQueueStride words apart
+// (separate memory lines, so their atomics do not serialise on one
+// address); workgroup b takes queue b % min(grid, kQueues) and queue q hands
+// out the work-order slots q, q + nq, q + 2 nq, ...
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 1024;
 
 // Tile ranges of the sorted instances plus the compositing work order
 // (tile ids by decreasing list length).  `sched` holds sched_words() uint32:
-// [0] forward queue head, [1] backward queue head, [4..) bucket histograms.
+// the forward queue heads from word 0, the backward heads from
+// kQueues * kQueueStride (sched_backward_heads), then bucket histograms.
 size_t sched_words();
+size_t sched_backward_heads();
 hipError_t launch_tile_ranges(const uint32_t *inst_tiles, const int64_t *counters, int64_t capacity,
                               int64_t total_tiles, uint2 *ranges, uint32_t *sched, uint32_t *tile_order,
                               hipStream_t stream);
@@ -105,5 +129,18 @@ hipError_t launch_preprocess_backward(const rgs_gaussians &g, const DevView *vie
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t stream);
 
 bool tile_shape_supported(int w, int h);
+
+// Adds `amount` to a global counter once per wave and returns the previous
+// value in every lane.  Only the first active lane contributes, selected by
+// value rather than by a branch: a lane-0 branch in front of the convergent
+// read-first-lane inside a persistent loop is loop invariant, and the
+// compiler may thread it into the back edge, leaving lanes 1..63 in a loop
+// of their own that re-reads a stale value and never exits.
+__device__ __forceinline__ uint32_t wave_fetch_add(uint32_t *counter, uint32_t amount)
+{
+    const unsigned long long active = __ballot(1);
+    const bool first = (threadIdx.x & 63u) == (unsigned)__builtin_ctzll(active);
+    return __builtin_amdgcn_readfirstlane(atomicAdd(counter, first ? amount : 0u));
+}
 
 }  // namespace rgs

@@ -10,6 +10,7 @@
 // rectangles, keys) are those of an exact evaluation up to double rounding.
 #include <hip/hip_fp16.h>
 
+#include "binning.h"
 #include "internal.h"
 
 #pragma clang fp contract(off)
@@ -18,33 +19,34 @@ namespace rgs {
 namespace {
 
 // Orthonormal real spherical harmonics up to degree 3 (index l^2 + l + m) in
-// the sign convention of Gaussian-splatting colour models.
+// the sign convention of Gaussian-splatting colour models, evaluated in
+// float32 (the colour is stored as float32).
 template <int DEG>
-__device__ __forceinline__ void sh_basis(double x, double y, double z, double *Y)
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float *Y)
 {
-    Y[0] = 0.28209479177387814;
+    Y[0] = 0.28209479177387814f;
     if (DEG >= 1) {
-        Y[1] = -0.48860251190291992 * y;
-        Y[2] = 0.48860251190291992 * z;
-        Y[3] = -0.48860251190291992 * x;
+        Y[1] = -0.48860251190291992f * y;
+        Y[2] = 0.48860251190291992f * z;
+        Y[3] = -0.48860251190291992f * x;
     }
     if (DEG >= 2) {
-        const double xx = x * x, yy = y * y, zz = z * z;
-        Y[4] = 1.0925484305920792 * x * y;
-        Y[5] = -1.0925484305920792 * y * z;
-        Y[6] = 0.31539156525252005 * (2.0 * zz - xx - yy);
-        Y[7] = -1.0925484305920792 * x * z;
-        Y[8] = 0.54627421529603959 * (xx - yy);
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = 1.0925484305920792f * x * y;
+        Y[5] = -1.0925484305920792f * y * z;
+        Y[6] = 0.31539156525252005f * (2.0f * zz - xx - yy);
+        Y[7] = -1.0925484305920792f * x * z;
+        Y[8] = 0.54627421529603959f * (xx - yy);
     }
     if (DEG >= 3) {
-        const double xx = x * x, yy = y * y, zz = z * z;
-        Y[9] = -0.59004358992664352 * y * (3.0 * xx - yy);
-        Y[10] = 2.8906114426405538 * x * y * z;
-        Y[11] = -0.45704579946446572 * y * (4.0 * zz - xx - yy);
-        Y[12] = 0.37317633259011540 * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
-        Y[13] = -0.45704579946446572 * x * (4.0 * zz - xx - yy);
-        Y[14] = 1.4453057213202769 * z * (xx - yy);
-        Y[15] = -0.59004358992664352 * x * (xx - 3.0 * yy);
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[9] = -0.59004358992664352f * y * (3.0f * xx - yy);
+        Y[10] = 2.8906114426405538f * x * y * z;
+        Y[11] = -0.45704579946446572f * y * (4.0f * zz - xx - yy);
+        Y[12] = 0.37317633259011540f * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+        Y[13] = -0.45704579946446572f * x * (4.0f * zz - xx - yy);
+        Y[14] = 1.4453057213202769f * z * (xx - yy);
+        Y[15] = -0.59004358992664352f * x * (xx - 3.0f * yy);
     }
 }
 
@@ -56,8 +58,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                                                     const float *__restrict__ sh, int n,
                                                     const DevView *__restrict__ views, int n_views, DevOptions opt,
                                                     float4 *__restrict__ records, uint32_t *__restrict__ depth_keys,
-                                                    uint32_t *__restrict__ order, uint2 *__restrict__ rects,
-                                                    uint32_t *__restrict__ tile_counts)
+                                                    uint32_t *__restrict__ order, uint2 *__restrict__ boxes,
+                                                    Conic *__restrict__ conics, uint32_t *__restrict__ tile_counts)
 {
     constexpr int NK = (DEG + 1) * (DEG + 1);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -67,17 +69,13 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
     const float lf[3] = {log_scales[i], log_scales[n + i], log_scales[2 * n + i]};
     const float qf[4] = {quats[i], quats[n + i], quats[2 * n + i], quats[3 * n + i]};
     const float af = opacity_logits[i];
-    float shc[NK * 3];
     bool ok = isfinite(af);
 #pragma unroll
     for (int k = 0; k < 3; ++k) ok = ok && isfinite((float)m[k]) && isfinite(lf[k]);
 #pragma unroll
     for (int k = 0; k < 4; ++k) ok = ok && isfinite(qf[k]);
-#pragma unroll
-    for (int k = 0; k < NK * 3; ++k) {
-        shc[k] = sh[(size_t)k * n + i];
-        ok = ok && isfinite(shc[k]);
-    }
+    // colour coefficients are read (and checked) only once a view keeps the
+    // Gaussian; a non-finite coefficient culls it in every view
     const double q[4] = {qf[0], qf[1], qf[2], qf[3]};
     const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     ok = ok && qn > 0.0;
@@ -99,7 +97,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
         const size_t idx = (size_t)v * n + i;
         order[idx] = (uint32_t)idx;
         uint32_t key = 0xffffffffu, cnt = 0;
-        uint2 rect = make_uint2(0u, 0u);
+        uint2 box = make_uint2(0u, 0u);
         const double *W = V.w2c;
         // camera-frame centre
         const double mu[3] = {W[0] * m[0] + W[1] * m[1] + W[2] * m[2] + W[3],
@@ -222,10 +220,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                 py1 = fy1 > Hd - 1 ? Hd - 1 : (fy1 < -1.0 ? -1 : (int)fy1);
             }
             if (px0 > px1 || py0 > py1) break;
-            const int tx0 = px0 / opt.tile_w, tx1 = px1 / opt.tile_w;
-            const int ty0 = py0 / opt.tile_h, ty1 = py1 / opt.tile_h;
-            cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-            rect = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
+            box = make_uint2((uint32_t)px0 | ((uint32_t)px1 << 16), (uint32_t)py0 | ((uint32_t)py1 << 16));
             key = __float_as_uint((float)mu[2]);
 
             // ---- raster record (float32) ----
@@ -248,19 +243,45 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                     G[r][cc] = Rv[r] * A2[0][cc] + Rv[3 + r] * A2[1][cc] + Rv[6 + r] * A2[2][cc];
             const double gx = (A2[0][0] * mw[0] + A2[1][0] * mw[1] + A2[2][0] * mw[2]) / c2;
             const double gy = (A2[0][1] * mw[0] + A2[1][1] * mw[1] + A2[2][1] * mw[2]) / c2;
+            // support ellipse in pixel offsets; list the tiles whose row bands meet it
+            Conic C;
+            {
+                const double k0 = 1.0 / mu[2];
+                const double M00 = G[0][0] * G[0][0] + G[1][0] * G[1][0];
+                const double M01 = G[0][0] * G[0][1] + G[1][0] * G[1][1];
+                const double M11 = G[0][1] * G[0][1] + G[1][1] * G[1][1];
+                C.P00 = b * b * M00 - kappa * gx * gx;
+                C.P01 = b * b * M01 - kappa * gx * gy;
+                C.P11 = b * b * M11 - kappa * gy * gy;
+                C.h0 = kappa * k0 * gx;
+                C.h1 = kappa * k0 * gy;
+                C.f0 = kappa * k0 * k0;
+                C.u0 = u_c;
+                C.v0 = v_c;
+            }
+            // tiles of the box; the emission kernel lists those whose row bands
+            // meet the support and marks the others empty
+            cnt = (uint32_t)((px1 / opt.tile_w - px0 / opt.tile_w + 1) * (py1 / opt.tile_h - py0 / opt.tile_h + 1));
             // colour from the view direction (camera centre -> mean, world frame)
             const double d0 = m[0] - V.centre[0], d1 = m[1] - V.centre[1], d2 = m[2] - V.centre[2];
             const double dn = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            double Y[NK];
-            sh_basis<DEG>(d0 / dn, d1 / dn, d2 / dn, Y);
-            double col[3];
-            for (int ch = 0; ch < 3; ++ch) {
-                double acc = 0.0;
+            float Y[NK];
+            sh_basis<DEG>((float)(d0 / dn), (float)(d1 / dn), (float)(d2 / dn), Y);
+            float col[3] = {0.5f, 0.5f, 0.5f};
+            bool sh_ok = true;
 #pragma unroll
-                for (int k = 0; k < NK; ++k) acc += Y[k] * (double)shc[3 * k + ch];
-                acc += 0.5;
-                col[ch] = acc > 0.0 ? acc : 0.0;
+            for (int k = 0; k < NK; ++k)
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    const float c = sh[(size_t)(3 * k + ch) * n + i];
+                    sh_ok = sh_ok && isfinite(c);
+                    col[ch] += Y[k] * c;
+                }
+            if (!sh_ok) {
+                cnt = 0;
+                break;
             }
+            for (int ch = 0; ch < 3; ++ch) col[ch] = col[ch] > 0.0f ? col[ch] : 0.0f;
             // the residuals of the centre go into one fp16 pair (|residual| <= half an
             // fp32 ulp of the centre, so fp16 keeps it to ~1e-7 px); the freed slot
             // holds the covered pixel rows for in-tile culling
@@ -271,26 +292,27 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
             rec[0] = make_float4(u_hi, v_hi, __uint_as_float(lo_bits), __uint_as_float(rows));
             rec[1] = make_float4((float)G[0][0], (float)G[0][1], (float)G[1][0], (float)G[1][1]);
             rec[2] = make_float4((float)gx, (float)gy, (float)(1.0 / mu[2]), (float)(1.0 / c2));
-            rec[3] = make_float4((float)log2(ov), (float)col[0], (float)col[1], (float)col[2]);
+            rec[3] = make_float4((float)log2(ov), col[0], col[1], col[2]);
+            conics[idx] = C;
         } while (false);
         depth_keys[idx] = cnt ? key : 0xffffffffu;
         tile_counts[idx] = cnt;
-        rects[idx] = rect;
+        boxes[idx] = box;
     }
 }
 
 }  // namespace
 
 hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n_views, const DevOptions &opt,
-                             float4 *records, uint32_t *depth_keys, uint32_t *order, uint2 *rects,
-                             uint32_t *tile_counts, hipStream_t stream)
+                             float4 *records, uint32_t *depth_keys, uint32_t *order, uint2 *boxes,
+                             Conic *conics, uint32_t *tile_counts, hipStream_t stream)
 {
     const int n = (int)g.n;
     if (n == 0) return hipSuccess;
     const dim3 grid((n + 255) / 256), block(256);
 #define RGS_PRE(D)                                                                                                 \
     k_preprocess<D><<<grid, block, 0, stream>>>(g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, n, views, \
-                                                n_views, opt, records, depth_keys, order, rects, tile_counts)
+                                                n_views, opt, records, depth_keys, order, boxes, conics, tile_counts)
     switch (g.sh_degree) {
     case 0: RGS_PRE(0); break;
     case 1: RGS_PRE(1); break;

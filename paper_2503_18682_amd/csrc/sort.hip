@@ -190,143 +190,186 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
 }
 
 // ---------------------------------------------------------------------- scan
-__global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__restrict__ counts,
-                                                          const uint32_t *__restrict__ gather, int64_t n,
+// Binning scan over the depth-sorted Gaussian-views: each item carries two
+// counts, the tiles of its pixel box (instances) and the tile rows of that
+// box; both are scanned at once (block sums hold the pair as two uint64).
+__device__ __forceinline__ void scan_item(const uint32_t *__restrict__ tile_counts, const uint2 *__restrict__ boxes,
+                                          const uint32_t *__restrict__ order, int64_t idx, int TH, uint32_t &tiles,
+                                          uint32_t &rows)
+{
+    const uint32_t id = order[idx];
+    tiles = tile_counts[id];
+    rows = 0u;
+    if (tiles) {
+        const PixelBox pb = unpack_box(boxes[id]);
+        rows = (uint32_t)(pb.y1 / TH - pb.y0 / TH + 1);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__restrict__ tile_counts,
+                                                          const uint2 *__restrict__ boxes,
+                                                          const uint32_t *__restrict__ order, int64_t n, int TH,
                                                           unsigned long long *__restrict__ block_sums)
 {
-    __shared__ unsigned long long part[kWaves];
+    __shared__ unsigned long long part[2][kWaves];
     const int64_t base = (int64_t)blockIdx.x * kTile;
-    unsigned long long acc = 0;
+    unsigned long long at = 0, ar = 0;
 #pragma unroll
     for (int j = 0; j < kItemsPerThread; ++j) {
         const int64_t idx = base + (int64_t)j * kThreads + threadIdx.x;
-        if (idx < n) acc += counts[gather ? gather[idx] : idx];
+        if (idx < n) {
+            uint32_t t, r;
+            scan_item(tile_counts, boxes, order, idx, TH, t, r);
+            at += t;
+            ar += r;
+        }
     }
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    for (int d = 32; d >= 1; d >>= 1) {
+        at += __shfl_xor(at, d, 64);
+        ar += __shfl_xor(ar, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        part[0][threadIdx.x >> 6] = at;
+        part[1][threadIdx.x >> 6] = ar;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+    if (threadIdx.x < 2) {
+        const unsigned long long *p = part[threadIdx.x];
+        block_sums[2 * blockIdx.x + threadIdx.x] = p[0] + p[1] + p[2] + p[3];
+    }
 }
 
-// Single-block exclusive scan of the block sums; writes the grand total.
+// Single-block exclusive scan of the block-sum pairs; writes the two totals
+// to counters[0] (instances) and counters[2] (tile rows).
 __global__ __launch_bounds__(1024) void k_scan_top(unsigned long long *__restrict__ block_sums, int nb,
-                                                   int64_t *__restrict__ total)
+                                                   int64_t *__restrict__ counters)
 {
-    __shared__ unsigned long long wsum[16];
+    __shared__ unsigned long long wsum[2][16];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    unsigned long long carry = 0;
+    unsigned long long carry[2] = {0, 0};
     for (int base = 0; base < nb; base += 1024) {
         const int i = base + threadIdx.x;
-        const unsigned long long x = i < nb ? block_sums[i] : 0ull;
-        unsigned long long v = x;
+        unsigned long long x[2], v[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            x[c] = i < nb ? block_sums[2 * i + c] : 0ull;
+            v[c] = x[c];
+        }
         for (int d = 1; d < 64; d <<= 1) {
-            const unsigned long long y = __shfl_up(v, d, 64);
-            if (lane >= d) v += y;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const unsigned long long y = __shfl_up(v[c], d, 64);
+                if (lane >= d) v[c] += y;
+            }
         }
-        if (lane == 63) wsum[wave] = v;
-        __syncthreads();
-        unsigned long long before = 0, all = 0;
-        for (int w = 0; w < 16; ++w) {
-            if (w < wave) before += wsum[w];
-            all += wsum[w];
+        if (lane == 63) {
+            wsum[0][wave] = v[0];
+            wsum[1][wave] = v[1];
         }
         __syncthreads();
-        if (i < nb) block_sums[i] = carry + before + v - x;
-        carry += all;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            unsigned long long before = 0, all = 0;
+            for (int w = 0; w < 16; ++w) {
+                if (w < wave) before += wsum[c][w];
+                all += wsum[c][w];
+            }
+            if (i < nb) block_sums[2 * i + c] = carry[c] + before + v[c] - x[c];
+            carry[c] += all;
+        }
+        __syncthreads();
     }
-    if (threadIdx.x == 0) *total = (int64_t)carry;
+    if (threadIdx.x == 0) {
+        counters[0] = (int64_t)carry[0];
+        counters[2] = (int64_t)carry[1];
+    }
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t *__restrict__ counts,
-                                                         const uint32_t *__restrict__ gather, int64_t n,
+// Offsets of every sorted item, plus the owner map of the tile rows
+// (row_owner[r] = sorted position owning row r) when the instances fit.
+__global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t *__restrict__ tile_counts,
+                                                         const uint2 *__restrict__ boxes,
+                                                         const uint32_t *__restrict__ order, int64_t n, int TH,
+                                                         int64_t capacity,
                                                          const unsigned long long *__restrict__ block_sums,
-                                                         uint32_t *__restrict__ offsets)
+                                                         const int64_t *__restrict__ counters,
+                                                         uint32_t *__restrict__ offsets,
+                                                         uint32_t *__restrict__ row_offsets,
+                                                         uint32_t *__restrict__ row_owner)
 {
     __shared__ uint32_t smem[kWaves];
     // blocked arrangement: thread t owns items base + t*8 .. +7
     const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItemsPerThread;
-    uint32_t c[kItemsPerThread];
-    uint32_t local = 0;
+    uint32_t c[kItemsPerThread], r[kItemsPerThread];
+    uint32_t lt = 0, lr = 0;
 #pragma unroll
     for (int j = 0; j < kItemsPerThread; ++j) {
-        const int64_t idx = base + j;
-        c[j] = idx < n ? counts[gather ? gather[idx] : idx] : 0u;
-        local += c[j];
+        c[j] = r[j] = 0u;
+        if (base + j < n) scan_item(tile_counts, boxes, order, base + j, TH, c[j], r[j]);
+        lt += c[j];
+        lr += r[j];
     }
     uint32_t tot;
-    const uint32_t before = block_inclusive_scan(local, smem, &tot) - local;
-    unsigned long long run = block_sums[blockIdx.x] + before;
+    const uint32_t bt = block_inclusive_scan(lt, smem, &tot) - lt;
+    const uint32_t br = block_inclusive_scan(lr, smem, &tot) - lr;
+    const bool fits = counters[0] <= capacity;
+    unsigned long long rt = block_sums[2 * blockIdx.x] + bt;
+    unsigned long long rr = block_sums[2 * blockIdx.x + 1] + br;
 #pragma unroll
     for (int j = 0; j < kItemsPerThread; ++j) {
         const int64_t idx = base + j;
-        if (idx < n) offsets[idx] = run > 0xffffffffull ? 0xffffffffu : (uint32_t)run;
-        run += c[j];
+        if (idx < n) {
+            offsets[idx] = rt > 0xffffffffull ? 0xffffffffu : (uint32_t)rt;
+            row_offsets[idx] = rr > 0xffffffffull ? 0xffffffffu : (uint32_t)rr;
+            // rows <= instances, so every row index lies below capacity
+            if (fits)
+                for (uint32_t q = 0; q < r[j]; ++q) row_owner[rr + q] = (uint32_t)idx;
+        }
+        rt += c[j];
+        rr += r[j];
     }
 }
 
 // ---------------------------------------------------------------- emission
-// One lane per sorted Gaussian-view writes its (tile, id) instances in
-// row-major tile order at its scanned offset.  Rectangles of more than
-// kEmitSolo tiles are queued in LDS and written by the whole wave, 64 tiles
-// per step, so one large Gaussian does not serialise a lane.
-constexpr uint32_t kEmitSolo = 16;
-
+// One lane per tile row of the sorted Gaussian-views (a grid-stride loop
+// over the row count the scan produced): the lane computes the support's
+// x-extent over the row's culling bands and writes every tile of the box row
+// at its scanned position, as (tile id, id | band bits) when a band meets the
+// support and as the empty marker `empty_tile` otherwise.  Instances end up
+// grouped by Gaussian-view in depth order, so a stable sort on the tile id
+// alone leaves every tile's list in depth order.
 __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ order,
                                                    const uint32_t *__restrict__ offsets,
-                                                   const uint32_t *__restrict__ tile_counts,
-                                                   const uint2 *__restrict__ rects, const DevView *__restrict__ views,
-                                                   int64_t n, int64_t n_total, int64_t capacity,
-                                                   uint32_t *__restrict__ inst_tiles, uint32_t *__restrict__ inst_ids)
+                                                   const uint32_t *__restrict__ row_offsets,
+                                                   const uint32_t *__restrict__ row_owner,
+                                                   const uint2 *__restrict__ boxes, const Conic *__restrict__ conics,
+                                                   const DevView *__restrict__ views, int64_t n,
+                                                   const int64_t *__restrict__ counters, int64_t capacity, int TW,
+                                                   int TH, uint32_t empty_tile, uint32_t *__restrict__ inst_tiles,
+                                                   uint32_t *__restrict__ inst_ids)
 {
-    __shared__ uint32_t big[kWaves][64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    uint32_t id = 0, cnt = 0;
-    if (k < n_total) {
-        id = order[k];
-        cnt = tile_counts[id];
-    }
-    const bool solo = cnt > 0 && cnt <= kEmitSolo;
-    if (solo) {
+    if (counters[0] > capacity) return;  // overflow: the instance total reports it
+    const int64_t rows = counters[2];
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < rows; r += stride) {
+        const uint32_t k = row_owner[r];
+        const uint32_t id = order[k];
+        const PixelBox pb = unpack_box(boxes[id]);
         const int v = (int)(id / (uint32_t)n);
-        const uint2 r = rects[id];
-        const int tx0 = r.x & 0xffff, ty0 = r.x >> 16, tx1 = r.y & 0xffff, ty1 = r.y >> 16;
-        const int tiles_x = views[v].tiles_x;
-        const uint32_t tbase = (uint32_t)views[v].tile_base;
-        int64_t pos = offsets[k];
-        if (pos + cnt <= capacity) {  // overflow: the scan total reports it
-            for (int ty = ty0; ty <= ty1; ++ty)
-                for (int tx = tx0; tx <= tx1; ++tx, ++pos) {
-                    inst_tiles[pos] = tbase + (uint32_t)(ty * tiles_x + tx);
-                    inst_ids[pos] = id;
-                }
-        }
-    }
-    // queue the large rectangles of this wave and write them cooperatively
-    const bool large = cnt > kEmitSolo;
-    const unsigned long long mask = __ballot(large);
-    if (large) big[wave][__popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)(k - (int64_t)blockIdx.x * kThreads);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int nbig = __popcll(mask);
-    for (int b = 0; b < nbig; ++b) {
-        const int64_t kk = (int64_t)blockIdx.x * kThreads + big[wave][b];
-        const uint32_t bid = order[kk];
-        const uint32_t bcnt = tile_counts[bid];
-        const int64_t base = offsets[kk];
-        if (base + bcnt > capacity) continue;
-        const int v = (int)(bid / (uint32_t)n);
-        const uint2 r = rects[bid];
-        const int tx0 = r.x & 0xffff, ty0 = r.x >> 16, tx1 = r.y & 0xffff;
-        const uint32_t nx = (uint32_t)(tx1 - tx0 + 1);
-        const int tiles_x = views[v].tiles_x;
-        const uint32_t tbase = (uint32_t)views[v].tile_base;
-        for (uint32_t j = lane; j < bcnt; j += 64) {
-            const int ty = ty0 + (int)(j / nx), tx = tx0 + (int)(j % nx);
-            inst_tiles[base + j] = tbase + (uint32_t)(ty * tiles_x + tx);
-            inst_ids[base + j] = bid;
+        const int row = (int)(r - row_offsets[k]);
+        const int ty = pb.y0 / TH + row;
+        const int tx0 = pb.x0 / TW, tx1 = pb.x1 / TW;
+        int64_t pos = (int64_t)offsets[k] + (int64_t)row * (tx1 - tx0 + 1);
+        const Conic C = conics[id];
+        const ConicFrame F = conic_frame(C);
+        BandRanges B;
+        band_ranges(C, F, pb, ty, TW, TH, B);
+        const uint32_t row_base = (uint32_t)views[v].tile_base + (uint32_t)(ty * views[v].tiles_x);
+        for (int tx = tx0; tx <= tx1; ++tx, ++pos) {
+            const uint32_t bands = B.valid ? tile_bands(C, B, pb, tx, TW) : 0u;
+            inst_tiles[pos] = bands ? row_base + (uint32_t)tx : empty_tile;
+            inst_ids[pos] = pack_instance(id, bands, TW, TH);
         }
     }
 }
@@ -431,30 +474,36 @@ hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32
     return hipGetLastError();
 }
 
-size_t scan_block_entries(int64_t n) { return (size_t)((n + kTile - 1) / kTile + 1); }
+size_t scan_block_entries(int64_t n) { return 2 * (size_t)((n + kTile - 1) / kTile + 1); }
 
-hipError_t exclusive_scan_gather(const uint32_t *counts, const uint32_t *gather, uint32_t *offsets, int64_t n,
-                                 unsigned long long *block_sums, int64_t *total, hipStream_t stream)
+hipError_t binning_scan(const uint32_t *tile_counts, const uint2 *boxes, const uint32_t *order, int64_t n,
+                        int tile_h, int64_t capacity, uint32_t *offsets, uint32_t *row_offsets, uint32_t *row_owner,
+                        unsigned long long *block_sums, int64_t *counters, hipStream_t stream)
 {
     const int nb = (int)((n + kTile - 1) / kTile);
     if (nb == 0) {
-        k_fill_u32<<<1, kThreads, 0, stream>>>(reinterpret_cast<uint32_t *>(total), 0u, 2);
+        // counters[0] and counters[2] (int64) = 0, counters[1] (capacity) kept
+        k_fill_u32<<<1, kThreads, 0, stream>>>(reinterpret_cast<uint32_t *>(counters), 0u, 2);
+        k_fill_u32<<<1, kThreads, 0, stream>>>(reinterpret_cast<uint32_t *>(counters + 2), 0u, 2);
         return hipGetLastError();
     }
-    k_scan_reduce<<<nb, kThreads, 0, stream>>>(counts, gather, n, block_sums);
-    k_scan_top<<<1, 1024, 0, stream>>>(block_sums, nb, total);
-    k_scan_apply<<<nb, kThreads, 0, stream>>>(counts, gather, n, block_sums, offsets);
+    k_scan_reduce<<<nb, kThreads, 0, stream>>>(tile_counts, boxes, order, n, tile_h, block_sums);
+    k_scan_top<<<1, 1024, 0, stream>>>(block_sums, nb, counters);
+    k_scan_apply<<<nb, kThreads, 0, stream>>>(tile_counts, boxes, order, n, tile_h, capacity, block_sums, counters,
+                                              offsets, row_offsets, row_owner);
     return hipGetLastError();
 }
 
-hipError_t launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *tile_counts, const uint2 *rects,
-                       const DevView *views, int64_t n, int n_views, int64_t capacity, uint32_t *inst_tiles,
-                       uint32_t *inst_ids, hipStream_t stream)
+int emit_grid(int num_cus) { return 8 * num_cus; }
+
+hipError_t launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *row_offsets,
+                       const uint32_t *row_owner, const uint2 *boxes, const Conic *conics, const DevView *views,
+                       int64_t n, int n_views, const int64_t *counters, int64_t capacity, int tile_w, int tile_h,
+                       uint32_t empty_tile, uint32_t *inst_tiles, uint32_t *inst_ids, int grid, hipStream_t stream)
 {
-    const int64_t total = n * n_views;
-    if (total == 0) return hipSuccess;
-    k_emit<<<(unsigned)((total + kThreads - 1) / kThreads), kThreads, 0, stream>>>(
-        order, offsets, tile_counts, rects, views, n, total, capacity, inst_tiles, inst_ids);
+    if (n * n_views == 0) return hipSuccess;
+    k_emit<<<grid, kThreads, 0, stream>>>(order, offsets, row_offsets, row_owner, boxes, conics, views, n, counters,
+                                          capacity, tile_w, tile_h, empty_tile, inst_tiles, inst_ids);
     return hipGetLastError();
 }
 
@@ -465,7 +514,8 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t s
     return hipGetLastError();
 }
 
-size_t sched_words() { return 4 + 2 * kSchedBuckets; }
+size_t sched_backward_heads() { return (size_t)kQueues * kQueueStride; }
+size_t sched_words() { return 2 * sched_backward_heads() + 2 * kSchedBuckets; }
 
 hipError_t launch_tile_ranges(const uint32_t *inst_tiles, const int64_t *counters, int64_t capacity,
                               int64_t total_tiles, uint2 *ranges, uint32_t *sched, uint32_t *tile_order,
@@ -480,7 +530,7 @@ hipError_t launch_tile_ranges(const uint32_t *inst_tiles, const int64_t *counter
         k_tile_ranges<<<(unsigned)((capacity + kThreads - 1) / kThreads), kThreads, 0, stream>>>(inst_tiles, counters,
                                                                                                  capacity, total_tiles, ranges);
     const unsigned nb = (unsigned)((total_tiles + kThreads - 1) / kThreads);
-    uint32_t *hist = sched + 4, *cursor = sched + 4 + kSchedBuckets;
+    uint32_t *hist = sched + 2 * sched_backward_heads(), *cursor = hist + kSchedBuckets;
     k_sched_hist<<<nb, kThreads, 0, stream>>>(ranges, total_tiles, hist);
     k_sched_scatter<<<nb, kThreads, 0, stream>>>(ranges, total_tiles, hist, cursor, tile_order);
     return hipGetLastError();

@@ -51,10 +51,31 @@ def render_with_ws(r, scene, cams, opts, capacity=None, flags=0):
     return host, buf, ws, lay, (ok, need)
 
 
-def instance_lists(buf, lay, m):
+ID_MASK = (1 << 28) - 1
+
+
+def instance_lists(buf, lay, m, with_bands=False, keep_empty=False):
+    """Sorted instances (tile ids, Gaussian-view ids[, band bits]).  Box tiles
+    whose bands all miss the support carry the empty tile id
+    2^tile_bits - 1 and sort last; they are dropped unless keep_empty."""
     tiles = read(buf, lay.inst_tiles, m, np.uint32).astype(np.int64)
-    ids = read(buf, lay.inst_ids, m, np.uint32).astype(np.int64)
+    raw = read(buf, lay.inst_ids, m, np.uint32).astype(np.int64)
+    if not keep_empty:
+        listed = tiles != (1 << lay.tile_bits) - 1
+        tiles, raw = tiles[listed], raw[listed]
+    ids = raw & ID_MASK
+    if with_bands:
+        return tiles, ids, raw >> 28
     return tiles, ids
+
+
+def oracle_box_tiles(sp):
+    """(kept, tiles): the Gaussians the GPU keeps -- the oracle's visible ones
+    plus those whose support meets no tile, whose instances the GPU marks
+    empty -- and the tile count of each one's pixel box (0 if not kept)."""
+    kept = np.isin(sp["cull"], [oracle.CULL["visible"], oracle.CULL["notile"]])
+    tiles = (sp["tx1"].astype(np.int64) - sp["tx0"] + 1) * (sp["ty1"].astype(np.int64) - sp["ty0"] + 1)
+    return kept, np.where(kept, tiles, 0)
 
 
 def assert_image_close(rgb, T, ref, tol=IMAGE_TOL, max_hazard_frac=0.01, label=""):

@@ -101,11 +101,11 @@ def test_workspace_size_validation(lib):
     w[1, 2] = np.inf
     _, a2, _, o2 = _args(cams=[scenegen.pinhole(w, 64, 48, 60)])
     assert _size(lib, n, a2, 1, o2)[0] == _lib.RGS_EINVAL
-    # n * n_views must stay below 2^31
-    assert _size(lib, 2**30, arr, nv, opts)[0] == _lib.RGS_OK
+    # n * n_views must stay below 2^28
+    assert _size(lib, 2**27, arr, nv, opts)[0] == _lib.RGS_OK
     cams = [scenegen.pinhole(scenegen.look_at((0, 0, -4)), 64, 48, 60)] * 2
     _, a2, _, o2 = _args(cams=cams)
-    assert _size(lib, 2**30, a2, 2, o2)[0] == _lib.RGS_EINVAL
+    assert _size(lib, 2**27, a2, 2, o2)[0] == _lib.RGS_EINVAL
 
 
 def test_workspace_layout(lib):
@@ -119,8 +119,8 @@ def test_workspace_layout(lib):
     assert lay.n_records == 2000 and lay.capacity == 5000
     assert lay.total_tiles == 9 * 5 + 3 * 3 and lay.tile_bits == 6
     assert lay.record_grads == 0
-    offs = [getattr(lay, k) for k in ("counters", "views", "records", "depth_keys", "rects", "tile_counts", "order",
-                                      "offsets", "inst_tiles", "inst_ids", "tile_ranges")]
+    offs = [getattr(lay, k) for k in ("counters", "views", "records", "depth_keys", "boxes", "conics", "tile_counts",
+                                      "order", "offsets", "inst_tiles", "inst_ids", "tile_ranges")]
     assert all(o % 256 == 0 for o in offs) and len(set(offs)) == len(offs)
     assert max(offs) < lay.total_bytes
     assert _size(lib, n, arr, nv, opts, 5000)[1] == lay.total_bytes

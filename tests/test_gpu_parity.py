@@ -1,17 +1,17 @@
 """GPU parity of the HIP renderer (through the C ABI) against the CPU oracle.
 
 Images: max-abs <= 2e-4 in [0, 1] outside the oracle's hazard mask (pixels
-where a threshold decision lies within rounding distance).  Depth keys, tile
-rectangles and tile lists: bit-exact, excluding Gaussians the oracle flags as
-hazards (expected count ~0)."""
+where a threshold decision lies within rounding distance).  Depth keys, pixel
+boxes, box tile counts and tile lists: bit-exact, excluding Gaussians the
+oracle flags as hazards (expected count ~0)."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 import scenegen
-from gpu_helpers import (assert_image_close, instance_lists, oracle_lists_without_hazards, read, render_with_ws, say,
-                         to_dev)
+from gpu_helpers import (assert_image_close, instance_lists, oracle_box_tiles, oracle_lists_without_hazards, read,
+                         render_with_ws, say, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -42,54 +42,62 @@ def test_c0_image_keys_and_lists(r):
     outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
     assert ok
     ref = oracle.render(sc, cam, opts)
-    assert m == ref["counters"]["instances"]
     assert_image_close(outs[0]["rgb"], outs[0]["final_T"], ref, label="c0")
     sp = oracle.preprocess(sc, cam, opts)
     assert (sp["hazard"] & oracle.HAZARD["cull"]).sum() == 0
-    # depth keys and tile rectangles of every visible Gaussian
+    kept, box_tiles = oracle_box_tiles(sp)
+    assert m == box_tiles.sum()
+    # depth keys, pixel boxes and box tile counts of every kept Gaussian
     n = sc["opacity_logits"].shape[0]
     keys = read(buf, lay.depth_keys, n, np.uint32)
     order = read(buf, lay.order, n, np.uint32)
     gpu_key = np.full(n, 0xFFFFFFFF, np.uint32)
     gpu_key[order] = keys
-    vis = sp["cull"] == 0
-    assert np.array_equal(gpu_key[vis], sp["depth_key"][vis])
-    assert np.all(gpu_key[~vis] == 0xFFFFFFFF)
-    rects = read(buf, lay.rects, 4 * n, np.uint16).reshape(n, 4)
-    good = vis & (sp["hazard"] == 0)
-    for f, col in (("tx0", 0), ("ty0", 1), ("tx1", 2), ("ty1", 3)):
-        assert np.array_equal(rects[good, col], sp[f][good])
+    assert np.array_equal(gpu_key[kept], sp["depth_key"][kept])
+    assert np.all(gpu_key[~kept] == 0xFFFFFFFF)
+    boxes = read(buf, lay.boxes, 4 * n, np.uint16).reshape(n, 4)
+    good = kept & (sp["hazard"] == 0)
+    for f, col in (("px0", 0), ("px1", 1), ("py0", 2), ("py1", 3)):
+        assert np.array_equal(boxes[good, col], sp[f][good])
+    counts = read(buf, lay.tile_counts, n, np.uint32)
+    assert np.array_equal(counts[good], box_tiles[good])
     _check_lists(buf, lay, m, sp, cam, opts, "c0 lists")
 
 
-def test_lists_rebin_from_gpu_rects_and_keys(r):
-    """The integer stages are exact functions of the GPU's own float outputs:
-    re-binning the GPU's rectangles and keys on the host reproduces its lists."""
-    say("case rebin: 2000 Gaussians, 200x150, 8x8 tiles")
+def test_lists_are_consistent_with_gpu_counts_boxes_and_keys(r):
+    """The integer stages are exact functions of the GPU's own outputs: every
+    Gaussian has exactly its counted number of instances; the listed ones lie
+    in its box's tile rectangle and carry band bits, the empty ones carry
+    none; re-sorting the GPU's instances on the host by (tile, depth key, id)
+    reproduces its order; tile ranges bracket exactly the runs of each
+    listed tile."""
+    say("case consistency: 2000 Gaussians, 200x150, 8x16 tiles")
     sc = scenegen.tiny_scene(31, 2000, sh_degree=1, half_extent=1.5, log_scale_mean=-3.0, log_scale_std=0.8)
     cam = scenegen.pinhole(scenegen.look_at((0.4, 0.3, -4.0)), 200, 150, 55)
-    opts = scenegen.default_options(tile_w=8, tile_h=8)
+    opts = scenegen.default_options(tile_w=8, tile_h=16)
     outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
     assert ok
     n = 2000
     keys = read(buf, lay.depth_keys, n, np.uint32)
     order = read(buf, lay.order, n, np.uint32).astype(np.int64)
-    rects = read(buf, lay.rects, 4 * n, np.uint16).reshape(n, 4).astype(np.int64)
+    boxes = read(buf, lay.boxes, 4 * n, np.uint16).reshape(n, 4).astype(np.int64)
     counts = read(buf, lay.tile_counts, n, np.uint32).astype(np.int64)
     key_of = np.zeros(n, np.uint32)
     key_of[order] = keys
-    tx = -(-200 // 8)
-    rows = []
-    for i in np.nonzero(counts)[0]:
-        for ty in range(rects[i, 1], rects[i, 3] + 1):
-            for x in range(rects[i, 0], rects[i, 2] + 1):
-                rows.append((ty * tx + x, key_of[i], i))
-    rows = np.array(rows, dtype=np.int64)
-    srt = rows[np.lexsort((rows[:, 2], rows[:, 1], rows[:, 0]))]
-    tiles, ids = instance_lists(buf, lay, m)
-    assert m == len(rows)
-    assert np.array_equal(tiles, srt[:, 0]) and np.array_equal(ids, srt[:, 2])
-    # tile ranges bracket exactly the runs of each tile
+    tiles, ids, bands = instance_lists(buf, lay, m, with_bands=True, keep_empty=True)
+    assert m == counts.sum()
+    assert np.array_equal(np.bincount(ids, minlength=n), counts)
+    srt = np.lexsort((ids, key_of[ids], tiles))
+    assert np.array_equal(srt, np.arange(m))
+    empty = tiles == (1 << lay.tile_bits) - 1
+    assert (1 << lay.tile_bits) - 1 >= lay.total_tiles and np.all(bands[empty] == 0)
+    say(f"  {m} box instances, {int(empty.sum())} empty")
+    tiles, ids, bands = tiles[~empty], ids[~empty], bands[~empty]
+    tx_n = -(-200 // 8)
+    ty, tx = tiles // tx_n, tiles % tx_n
+    b = boxes[ids]
+    assert np.all((tx >= b[:, 0] // 8) & (tx <= b[:, 1] // 8) & (ty >= b[:, 2] // 16) & (ty <= b[:, 3] // 16))
+    assert np.all((bands & 3) > 0)  # 2 row bands per 8x16 tile (all 4 bits for an unbounded support)
     rng = read(buf, lay.tile_ranges, 2 * lay.total_tiles, np.uint32).reshape(-1, 2)
     for t in np.unique(tiles):
         idx = np.nonzero(tiles == t)[0]
@@ -105,9 +113,9 @@ def test_ragged_image_all_tile_shapes(r, shape):
     outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
     assert ok
     ref = oracle.render(sc, cam, opts)
-    assert m == ref["counters"]["instances"]
     assert_image_close(outs[0]["rgb"], outs[0]["final_T"], ref, label=f"ragged {shape}")
     sp = oracle.preprocess(sc, cam, opts)
+    assert m == oracle_box_tiles(sp)[1].sum()
     _check_lists(buf, lay, m, sp, cam, opts, f"ragged {shape} lists")
     base = scenegen.default_options(tile_w=16, tile_h=16, background=(0.2, 0.1, 0.05))
     b_outs = render_with_ws(r, sc, [cam], base)[0]
@@ -147,7 +155,7 @@ def test_edge_cases(r):
         outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
         assert ok
         ref = oracle.render(sc, cam, opts)
-        assert m == ref["counters"]["instances"], name
+        assert m == oracle_box_tiles(oracle.preprocess(sc, cam, opts))[1].sum(), name
         assert_image_close(outs[0]["rgb"], outs[0]["final_T"], ref, label=name)
     assert np.allclose(render_with_ws(r, cases["empty"], [cam], opts)[0][0]["rgb"][2], 0.3)
 

@@ -422,23 +422,80 @@ def test_sh_basis_orthonormal_and_gradient(oracle_lib):
 
 
 # --------------------------------------------------------- binning and sort
-def test_tile_lists_brute_force(oracle_lib):
+def _support_mask(r, cam, xs, ys):
+    """omega >= p_min and tau > 0 at pixel positions (xs, ys), with D from a
+    numerically inverted covariance (independent of the oracle's conic)."""
+    Sinv = _sigma_inv(r["Rp"].reshape(3, 3), r["s"])
+    x = np.stack([(xs - cam["cx"]) / cam["fx"], (ys - cam["cy"]) / cam["fy"], np.ones_like(xs, float)], -1)
+    L = x @ (Sinv @ r["mu"])
+    Q = np.einsum("...i,ij,...j->...", x, Sinv, x)
+    D = r["c2"] - L * L / Q
+    return (L > 0) & (r["o"] * np.exp(-D / 2) >= OPTS["p_min"]), D
+
+
+def _min_D_over_rect(r, cam, x0, x1, y0, y1):
+    from scipy.optimize import minimize
+
+    Sinv = _sigma_inv(r["Rp"].reshape(3, 3), r["s"])
+
+    def D(p):
+        x = np.array([(p[0] - cam["cx"]) / cam["fx"], (p[1] - cam["cy"]) / cam["fy"], 1.0])
+        L = x @ Sinv @ r["mu"]
+        return r["c2"] - L * L / (x @ Sinv @ x) if L > 0 else r["c2"]
+
+    best = np.inf
+    for sx in np.linspace(x0, x1, 3):
+        for sy in np.linspace(y0, y1, 3):
+            res = minimize(D, [sx, sy], bounds=[(x0, x1), (y0, y1)], method="L-BFGS-B")
+            best = min(best, res.fun)
+    return best
+
+
+def test_tile_lists_by_definition(oracle_lib):
+    """A tile is listed for a Gaussian iff one of its row bands (64 / tile_w
+    rows, clipped to the pixel box) meets the support: checked from below by
+    pixel centres inside the support, from above by minimising D over the band
+    rectangle; the list of a tile is ordered by (float32 depth, index)."""
     sc = scenegen.tiny_scene(17, 150, sh_degree=0, log_scale_mean=-2.5, log_scale_std=0.7)
     cam = scenegen.pinhole(scenegen.look_at((0.1, -0.2, -3.0)), 53, 41, 60)
     opts = scenegen.default_options(tile_w=16, tile_h=8)
     sp = oracle.preprocess(sc, cam, opts)
     tiles, keys, idx = oracle.tile_lists(sp, cam, opts)
-    tx_n, ty_n = -(-53 // 16), -(-41 // 8)
-    ref = []
-    for ty in range(ty_n):
-        for tx in range(tx_n):
-            xa, xb, ya, yb = tx * 16, min(53, tx * 16 + 16) - 1, ty * 8, min(41, ty * 8 + 8) - 1
-            here = [i for i in range(150) if sp["cull"][i] == 0 and sp["px0"][i] <= xb and sp["px1"][i] >= xa
-                    and sp["py0"][i] <= yb and sp["py1"][i] >= ya]
-            here.sort(key=lambda i: (float(np.float32(sp["mu"][i][2])), i))
-            ref += [(ty * tx_n + tx, i) for i in here]
-    assert list(zip(tiles.tolist(), idx.tolist())) == ref
-    assert np.array_equal(keys, np.array([np.float32(sp["mu"][i][2]).view(np.uint32) for i in idx]))
+    tx_n = -(-53 // 16)
+    listed = set(zip(tiles.tolist(), idx.tolist()))
+    LY = 64 // 16
+    checked_above = 0
+    for i in np.nonzero(sp["cull"] == 0)[0]:
+        r = sp[i]
+        ys, xs = np.mgrid[r["py0"]:r["py1"] + 1, r["px0"]:r["px1"] + 1]
+        sup, _ = _support_mask(r, cam, xs + 0.5, ys + 0.5)
+        for y, x in zip(ys[sup], xs[sup]):
+            assert ((y // 8) * tx_n + x // 16, i) in listed
+        mine = [t for (t, j) in listed if j == i]
+        for t in mine[:6]:
+            ty, tx = divmod(t, tx_n)
+            ok = False
+            for b in range(8 // LY):
+                r0, r1 = max(ty * 8 + b * LY, r["py0"]), min(ty * 8 + b * LY + LY - 1, r["py1"])
+                c0, c1 = max(tx * 16, r["px0"]), min(tx * 16 + 15, r["px1"])
+                if r0 > r1 or c0 > c1:
+                    continue
+                if _min_D_over_rect(r, cam, c0 + 0.5, c1 + 0.5, r0 + 0.5, r1 + 0.5) <= r["kappa"] + 1e-7:
+                    ok = True
+                    break
+            assert ok, (i, t)
+            checked_above += 1
+    assert checked_above > 100
+    # every listed tile lies in the Gaussian's tile rectangle, lists are (depth, index) ordered
+    for t, k, i in zip(tiles, keys, idx):
+        ty, tx = divmod(int(t), tx_n)
+        assert sp["tx0"][i] <= tx <= sp["tx1"][i] and sp["ty0"][i] <= ty <= sp["ty1"][i]
+        assert k == np.float32(sp["mu"][i][2]).view(np.uint32)
+    for t in np.unique(tiles):
+        sel = tiles == t
+        pairs = list(zip(keys[sel].tolist(), idx[sel].tolist()))
+        assert pairs == sorted(pairs)
+    assert len(listed) == len(tiles)
 
 
 def test_pixel_box_is_centres_inside_bbox(oracle_lib):
