@@ -44,7 +44,7 @@ FLOP_PER_FRAGMENT = 25
 FLOP_PER_CONTRIBUTION = 10
 # Algorithmic bytes of the other stages (per unit):
 PARAM_BYTES = {0: 56, 1: 92, 2: 152, 3: 236}   # Gaussian parameters read once per batch
-RECORD_BYTES = 64 + 4 + 8 + 4                  # record + depth key + rect + tile count per visible Gaussian-view
+RECORD_BYTES = 64 + 4 + 8 + 64 + 4             # record, depth key, pixel box, support conic, tile count per visible Gaussian-view
 INSTANCE_BYTES = 8                             # (tile id, Gaussian id) written once
 PIXEL_BYTES = 20                               # rgb + final T + n_contrib
 
@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of HIP-graph replays")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-steps", type=int, default=32, help="frames of the per-stage timing pass")
-    ap.add_argument("--tile", default="16x16", help="tile shape WxH, each of 8, 16, 32")
+    ap.add_argument("--tile", default="8x16", help="tile shape WxH, each of 8, 16, 32")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference for HBM counters)")
     return ap.parse_args()
@@ -103,11 +103,22 @@ def stage_pass(r, g, cams_seq, opts, ws, outs, frames):
     return {k: v / max(n, 1) for k, v in ms.items()}, n
 
 
-def roofline_for(stage, ms, *, flops=None, nbytes=None):
+def pmc_traffic(stage, workload):
+    """HBM bytes per launch of the compositing kernel from the committed
+    counter summary (profiles/), or None when there is none for this
+    workload or the kernel's sources changed since it was taken."""
+    if stage != "blend":
+        return None
+    from paper_2503_18682_amd.prof_summary import read_traffic
+
+    return read_traffic(os.path.join(ROOT, "profiles", f"blend_{workload}_pmc_traffic.txt"), "k_blend")
+
+
+def roofline_for(stage, ms, *, flops=None, nbytes=None, traffic=None):
     if stage.startswith("blend"):
         achieved = flops / (ms * 1e-3) / 1e12 if flops else None
         return {"bound": "alu", "kernel": stage, "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS if achieved else None, "traffic": None,
+                "frac": achieved / PEAK_FP32_TFLOPS if achieved else None, "traffic": traffic,
                 "avg_ms": ms, "algorithmic_flop": flops}
     achieved = nbytes / (ms * 1e-3) / 1e9 if nbytes else None
     return {"bound": "hbm", "kernel": stage, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -188,7 +199,8 @@ def bench_c1(args, torch):
         flops = FLOP_PER_FRAGMENT * frag + FLOP_PER_CONTRIBUTION * contrib
         nbytes = {"preprocess": PARAM_BYTES[3] * n + RECORD_BYTES * vis,
                   "tile_sort": 2 * 2 * INSTANCE_BYTES * inst}.get(dom)
-    roof = roofline_for(dom, fwd[dom], flops=flops, nbytes=nbytes)
+    tag = "c1_1080p_500k_" + args.tile
+    roof = roofline_for(dom, fwd[dom], flops=flops, nbytes=nbytes, traffic=pmc_traffic(dom, tag))
     res = {
         "metric": METRIC, "value": 1e3 / ms, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
