@@ -3,7 +3,7 @@ CPU oracle only (TEST / MEASUREMENT INFRASTRUCTURE).
 
 For each view of a workload it records, from a full oracle render:
   visible        Gaussians passing every cull
-  instances      Gaussian-tile pairs (16x16 tiles)
+  instances      listed (Gaussian, tile) pairs at the recorded tile shape
   fragments      pixel centres inside a projected quad (what a rasteriser
                  would shade for the paper's quads), before termination
   box_pairs      pixel centres inside a Gaussian's pixel box
@@ -11,7 +11,7 @@ For each view of a workload it records, from a full oracle render:
                  early termination)
 These are the denominators of the roofline figures (work per launch).
 
-    python -m oracle.work_counts c1 [--out tests/golden/work_counts_c1.json]
+    python -m oracle.work_counts c1 [--tile 8x16] [--out tests/golden/work_counts_c1.json]
 """
 from __future__ import annotations
 
@@ -29,9 +29,11 @@ import oracle  # noqa: E402
 import scenegen  # noqa: E402
 
 
-def counts(name: str, views=None):
+def counts(name: str, views=None, tile=None):
     w = scenegen.make_workload(name)
-    sc, cams, opts = w["scene"], w["cameras"], w["options"]
+    sc, cams, opts = w["scene"], w["cameras"], dict(w["options"])
+    if tile:
+        opts["tile_w"], opts["tile_h"] = (int(x) for x in tile.lower().split("x"))
     out = []
     for v, cam in enumerate(cams):
         if views is not None and v not in views:
@@ -48,8 +50,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("workload", default="c1", nargs="?")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--tile", default=None, help="tile shape WxH (default: the workload's)")
     a = ap.parse_args()
-    res = counts(a.workload)
+    res = counts(a.workload, tile=a.tile)
     path = a.out or os.path.join(ROOT, "tests", "golden", f"work_counts_{a.workload}.json")
     with open(path, "w") as f:
         json.dump(res, f, indent=1)
