@@ -135,8 +135,10 @@ const char *rgs_last_error(const rgs_context *ctx);
 
 /* Bytes of device workspace needed to render `n_views` cameras of a scene of
  * n Gaussians with room for `capacity` Gaussian-tile instances.  Pure host
- * arithmetic; no GPU work; ctx may be NULL (no error message is kept then).  A capacity of about 8 n n_views instances covers
- * typical scenes; rgs_render_status reports the count a frame needed. */
+ * arithmetic; no GPU work; ctx may be NULL (no error message is kept then).
+ * A capacity of about 8 n n_views instances covers typical scenes;
+ * rgs_render_status reports the count a frame needed.  RGS_EINVAL when
+ * n n_views >= 2^28 or the views hold 2^29 tiles or more in total. */
 rgs_status rgs_workspace_size(rgs_context *ctx, int64_t n, const rgs_camera *cams, int32_t n_views,
                               const rgs_options *opts, int64_t capacity, int32_t flags, size_t *bytes);
 
@@ -195,11 +197,11 @@ typedef struct {
     size_t counters;       /* int64[8]: [0] instances needed, [1] capacity, [2] tile rows of all boxes */
     size_t views;          /* per-view device table */
     size_t records;        /* float[16] per Gaussian-view, index v * n + i */
-    size_t depth_keys;     /* uint32 per Gaussian-view (0xffffffff = culled) */
+    size_t depth_keys;     /* uint32 per Gaussian-view, sorted (0xffffffff = culled, at the end) */
     size_t boxes;          /* uint16[4] per Gaussian-view: pixel box x0, x1, y0, y1 (inclusive) */
     size_t conics;         /* double[8] per Gaussian-view: support ellipse P00, P01, P11, h0, h1, f0, u0, v0 */
     size_t tile_counts;    /* uint32 per Gaussian-view: tiles of its pixel box (0 = culled) */
-    size_t order;          /* uint32 per Gaussian-view: Gaussian-view ids sorted by (depth, id) */
+    size_t order;          /* uint32 per Gaussian-view: Gaussian-view ids sorted by (depth key, id) */
     size_t offsets;        /* uint32 per Gaussian-view: first instance of each sorted entry */
     size_t inst_tiles;     /* uint32 per instance: global tile id, sorted; a box tile whose row bands all
                               miss the support holds 2^tile_bits - 1 (> every tile id) and sorts last */

@@ -162,7 +162,7 @@ rgs_status compute_layout(rgs_context *ctx, int64_t n, const rgs_camera *cams, i
     int64_t tiles = 0;
     for (int v = 0; v < n_views; ++v)
         tiles += (int64_t)((cams[v].width + s.w - 1) / s.w) * ((cams[v].height + s.h - 1) / s.h);
-    if (tiles >= (int64_t(1) << 31)) return fail(ctx, RGS_EINVAL, "too many tiles");
+    if (tiles >= (int64_t(1) << 29)) return fail(ctx, RGS_EINVAL, "too many tiles (at most 2^29 - 1)");
     L.total_tiles = tiles;
     L.tile_bits = bits_for(tiles + 1);  // 2^tile_bits - 1 (the empty-instance tile) >= tiles
     L.nv_records = n * n_views;
@@ -195,7 +195,7 @@ rgs_status compute_layout(rgs_context *ctx, int64_t n, const rgs_camera *cams, i
     L.row_total = take(256 * 4);
     L.ranges = take((size_t)tiles * 8);
     L.sched = take(sched_words() * 4);
-    L.tile_order = take((size_t)tiles * 4);
+    L.tile_order = take((size_t)tiles * 2 * 4);  // work items: up to two per tile
     L.row_owner = take((size_t)capacity * 4);
     L.record_grads = (flags & RGS_WS_BACKWARD) ? take(NV * kGradFloats * sizeof(float)) : 0;
     L.total = off;
@@ -361,22 +361,26 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
     uint32_t *offsets = at<uint32_t>(ws, L.offsets);
     uint32_t *row_offsets = at<uint32_t>(ws, L.row_offsets);
     uint32_t *row_owner = at<uint32_t>(ws, L.row_owner);
-    RGS_HIP(ctx, binning_scan(tile_counts, boxes, order, NV, s.h, L.capacity, offsets, row_offsets, row_owner,
+    RGS_HIP(ctx, binning_scan(at<uint32_t>(ws, L.keys_a), boxes, order, NV, nullptr, s.w, s.h, L.capacity, offsets,
+                              row_offsets, row_owner,
                               at<unsigned long long>(ws, L.block_sums), counters, stream));
     tm.mark(ST_SCAN);
     const uint32_t empty_tile = (uint32_t)((int64_t(1) << L.tile_bits) - 1);
     RGS_HIP(ctx, launch_emit(order, offsets, row_offsets, row_owner, boxes, conics, views, g.n, n_views, counters,
-                             L.capacity, s.w, s.h, empty_tile, tiles_in, ids_in, emit_grid(ctx->num_cus), stream));
+                             L.capacity, s.w, s.h, empty_tile, tiles_in, ids_in, ranges, L.total_tiles, sched,
+                             emit_grid(ctx->num_cus), stream));
     tm.mark(ST_EMIT);
     RGS_HIP(ctx, radix_sort(tiles_in, ids_in, tiles_alt, ids_alt, L.capacity, counters, L.tile_bits, hist, row_total,
                             stream));
     tm.mark(ST_TSORT);
     const uint32_t *inst_tiles = at<uint32_t>(ws, L.inst_tiles_a);
     const uint32_t *inst_ids = at<uint32_t>(ws, L.inst_ids_a);
-    RGS_HIP(ctx, launch_tile_ranges(inst_tiles, counters, L.capacity, L.total_tiles, ranges, sched,
+    const uint32_t split_len = s.h / (64 / s.w) >= 2 ? (uint32_t)RGS_SPLIT_LEN : 0u;
+    RGS_HIP(ctx, launch_tile_ranges(inst_tiles, counters, L.capacity, L.total_tiles, split_len, ranges, sched,
                                     at<uint32_t>(ws, L.tile_order), stream));
     tm.mark(ST_RANGES);
-    RGS_HIP(ctx, launch_blend(s, ranges, tile_order, inst_ids, records, views, n_views, L.total_tiles, NV, dopt,
+    RGS_HIP(ctx, launch_blend(s, ranges, tile_order, sched + sched_item_count(), inst_ids, records, views, n_views,
+                              L.total_tiles, NV, dopt,
                               sched, ctx->grid_fwd[shape_index(s)], stream));
     tm.mark(ST_BLEND);
     return RGS_OK;
@@ -539,6 +543,7 @@ rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const r
     uint32_t *bwd_heads = sched + sched_backward_heads();
     RGS_HIP(ctx, launch_fill_u32(bwd_heads, 0u, (int64_t)kQueues * kQueueStride, s));
     RGS_HIP(ctx, launch_blend_backward(sh, at<uint2>(ws->ptr, L.ranges), at<uint32_t>(ws->ptr, L.tile_order),
+                                       sched + sched_item_count(),
                                        at<uint32_t>(ws->ptr, L.inst_ids_a), at<float4>(ws->ptr, L.records),
                                        at<DevView>(ws->ptr, L.views), n_views, L.total_tiles, L.nv_records, dopt,
                                        rgrads, bwd_heads, ctx->grid_bwd[shape_index(sh)], s));

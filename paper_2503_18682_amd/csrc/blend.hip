@@ -34,7 +34,7 @@ struct Rec {
 };
 
 struct Frag {
-    float dx, dy, n0, n1, den, q, t, rt, D, w;
+    float dx, dy, n0, n1, den, q, kq, t, rt, w;
 };
 
 __device__ __forceinline__ Rec load_rec(const float4 *p)
@@ -63,14 +63,15 @@ __device__ __forceinline__ bool frag_test(const Rec &R, float K, float pxc, floa
     f.den = __builtin_fmaf(R.gy, f.dy, __builtin_fmaf(R.gx, f.dx, R.k0));
     f.q = __builtin_fmaf(f.n1, f.n1, f.n0 * f.n0);
     f.t = __builtin_fmaf(f.q, R.ic2, f.den * f.den);
-    return (f.den > 0.0f) & (kHalfLog2e * f.q <= K * f.t);
+    f.kq = kHalfLog2e * f.q;
+    return (f.den > 0.0f) & (f.kq <= K * f.t);
 }
 
+// omega = o 2^(-D log2(e) / 2) with D = q / t.
 __device__ __forceinline__ void frag_omega(const Rec &R, Frag &f)
 {
     f.rt = __builtin_amdgcn_rcpf(f.t);
-    f.D = f.q * f.rt;
-    f.w = __builtin_amdgcn_exp2f(__builtin_fmaf(f.D, -kHalfLog2e, R.log2o));  // o 2^(-D log2(e)/2)
+    f.w = __builtin_amdgcn_exp2f(__builtin_fmaf(f.kq, -f.rt, R.log2o));
 }
 
 // Rows of the tile covered by a record, relative to the tile's first row, as
@@ -106,27 +107,45 @@ struct BlendParams {
     uint32_t n_records;
 };
 
-// Stage one record into LDS; an id outside the record array (never produced
-// by the binning) is replaced by a record whose den is negative everywhere.
-__device__ __forceinline__ void stage_record(float4 *dst, const float4 *__restrict__ records, uint32_t id,
-                                             uint32_t n_records)
+// Stage one record (four float4) for instance value `inst` (id | band bits).
+// An id outside the record array (never produced by the binning) is replaced
+// by a record whose den is negative everywhere.  When a tile has at most 4
+// culling bands the covered-rows word is not needed, and the instance's band
+// bits take its place.
+__device__ __forceinline__ void stage_record(float4 *dst, const float4 *__restrict__ records, uint32_t inst,
+                                             uint32_t n_records, bool bands_in_rows)
 {
+    const uint32_t id = inst & kIdMask;
+    float4 r[4];
     if (id < n_records) {
         const float4 *src = records + (size_t)id * 4;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) dst[c] = src[c];
+        for (int c = 0; c < 4; ++c) r[c] = src[c];
     } else {
-        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-        dst[0] = make_float4(0.f, 0.f, 0.f, __uint_as_float(1u));  // rows [1, 0]: empty
-        dst[1] = z;
-        dst[2] = make_float4(0.f, 0.f, -1.f, 0.f);
-        dst[3] = make_float4(-126.f, 0.f, 0.f, 0.f);
+        r[0] = make_float4(0.f, 0.f, 0.f, __uint_as_float(1u));  // rows [1, 0]: empty
+        r[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        r[2] = make_float4(0.f, 0.f, -1.f, 0.f);
+        r[3] = make_float4(-126.f, 0.f, 0.f, 0.f);
     }
+    if (bands_in_rows) r[0].w = __uint_as_float(inst >> kIdBits);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dst[c] = r[c];
+}
+
+// Whether culling band k (rows [k LY, (k + 1) LY) of the tile) may hold a
+// fragment of the record: its band bit when the tile has at most 4 bands
+// (`bands` is then the record's rows word), else the record's covered rows.
+template <int PPL, int LY>
+__device__ __forceinline__ bool band_open(uint32_t bands, const RowSpan &span, int k)
+{
+    if (PPL <= 4) return (bands >> k) & 1u;
+    return !(span.r1 < k * LY || span.r0 >= (k + 1) * LY);
 }
 
 template <int TW, int TH>
 __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
-                                               const uint32_t *__restrict__ tile_order,
+                                               const uint32_t *__restrict__ work_order,
+                                               const uint32_t *__restrict__ n_items_p,
                                                const uint32_t *__restrict__ inst_ids,
                                                const float4 *__restrict__ records, const DevView *__restrict__ views,
                                                BlendParams P, unsigned int *__restrict__ queue)
@@ -134,15 +153,19 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
     constexpr int LX = TW, LY = 64 / TW, PPL = TH / LY;
     static_assert(64 % TW == 0 && TH % LY == 0, "tile shape");
     __shared__ float4 s_rec[4][64][4];
-    __shared__ uint32_t s_bands[4][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lx = lane % LX, ly = lane / LX;
     const int nq = min((int)gridDim.x, kQueues), q = (int)blockIdx.x % nq;
     unsigned int *const head = queue + q * kQueueStride;
+    const int64_t n_items = *n_items_p;
     for (;;) {
         const int64_t slot = q + (int64_t)nq * wave_fetch_add(head, 1u);
-        if (slot >= P.total_tiles) break;
-        const int tile = (int)tile_order[slot];
+        if (slot >= n_items) break;
+        const uint32_t item = work_order[slot];
+        const int tile = (int)(item >> 2);
+        // pixel slots [k_lo, k_hi) of the lanes: all, or one half of the rows
+        const int part = (int)(item & 3u);
+        const int k_lo = part == 2 ? PPL / 2 : 0, k_hi = part == 1 ? PPL / 2 : PPL;
         const DevView &V = views[find_view(views, P.n_views, tile)];
         const int local = tile - V.tile_base;
         const int tx = local % V.tiles_x, ty = local / V.tiles_x;
@@ -158,75 +181,72 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
             T[k] = 1.0f;
             C0[k] = C1[k] = C2[k] = 0.0f;
             last[k] = 0;
-            live[k] = px < V.width && py < V.height;
+            live[k] = k >= k_lo && k < k_hi && px < V.width && py < V.height;
         }
         const uint2 rg = ranges[tile];
         bool wave_live = true;
         // batch 0 goes straight to LDS; batch b+1 is prefetched into registers
         // while batch b is composited
-        if (rg.x + lane < rg.y) {
-            const uint32_t v = inst_ids[rg.x + lane];
-            stage_record(s_rec[wave][lane], records, v & kIdMask, P.n_records);
-            s_bands[wave][lane] = v >> kIdBits;
-        }
+        if (rg.x + lane < rg.y) stage_record(s_rec[wave][lane], records, inst_ids[rg.x + lane], P.n_records, PPL <= 4);
         for (uint32_t base = rg.x; base < rg.y && wave_live; base += 64) {
             const uint32_t nb = min(64u, rg.y - base);
             const uint32_t next = base + 64 + lane;
             const bool have_next = next < rg.y;
             float4 pre[4];
-            uint32_t pre_bands = 0u;
-            if (have_next) {
-                const uint32_t v = inst_ids[next];
-                stage_record(pre, records, v & kIdMask, P.n_records);
-                pre_bands = v >> kIdBits;
-            }
+            if (have_next) stage_record(pre, records, inst_ids[next], P.n_records, PPL <= 4);
             lds_wave_sync();
             for (uint32_t j = 0; j < nb; ++j) {
                 const Rec R = load_rec(s_rec[wave][j]);
                 const float K = R.log2o - P.log2_pmin;
                 const RowSpan span = row_span(R, ty * TH);
-                const uint32_t bands = __builtin_amdgcn_readfirstlane(s_bands[wave][j]);
+                const uint32_t bands = __builtin_amdgcn_readfirstlane(R.rows);
+                const int idx = (int)(base - rg.x + j + 1);
+                bool stopped = false;
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) {
-                    if (PPL <= 4 ? !((bands >> k) & 1u) : (span.r1 < k * LY || span.r0 >= (k + 1) * LY)) continue;
-                    if (!live[k]) continue;
+                    if (k < k_lo || k >= k_hi || !band_open<PPL, LY>(bands, span, k)) continue;
+                    // every lane evaluates the test; results are kept by selection
+                    // (the values are those of a branch per lane, bit for bit)
                     Frag f;
-                    if (frag_test(R, K, pxc, pyc[k], f)) {
-                        frag_omega(R, f);
-                        const float a = fminf(f.w, P.alpha_max);
-                        const float Tn = T[k] * (1.0f - a);
-                        if (Tn < P.t_eps) {
-                            live[k] = false;
-                        } else {
-                            const float wt = T[k] * a;
-                            C0[k] += wt * R.r;
-                            C1[k] += wt * R.g;
-                            C2[k] += wt * R.b;
-                            T[k] = Tn;
-                            last[k] = (int)(base - rg.x + j + 1);
-                        }
-                    }
+                    const bool hit = frag_test(R, K, pxc, pyc[k], f) & live[k];
+                    if (__ballot(hit) == 0) continue;
+                    frag_omega(R, f);
+                    const float a = fminf(f.w, P.alpha_max);
+                    const float ta = T[k] * a;
+                    const float Tn = T[k] - ta;
+                    const bool stop = hit & (Tn < P.t_eps);
+                    const bool take = hit & !(Tn < P.t_eps);
+                    const float wt = take ? ta : 0.0f;
+                    C0[k] = __builtin_fmaf(wt, R.r, C0[k]);
+                    C1[k] = __builtin_fmaf(wt, R.g, C1[k]);
+                    C2[k] = __builtin_fmaf(wt, R.b, C2[k]);
+                    T[k] = take ? Tn : T[k];
+                    last[k] = take ? idx : last[k];
+                    live[k] = live[k] & !stop;
+                    stopped |= stop;
                 }
-                bool any = false;
+                // a lane finished: leave the tile once no pixel is live
+                if (__ballot(stopped) != 0) {
+                    bool any = false;
 #pragma unroll
-                for (int k = 0; k < PPL; ++k) any = any || live[k];
-                if (__ballot(any) == 0) {
-                    wave_live = false;
-                    break;
+                    for (int k = 0; k < PPL; ++k) any = any || live[k];
+                    if (__ballot(any) == 0) {
+                        wave_live = false;
+                        break;
+                    }
                 }
             }
             lds_wave_sync();
             if (have_next) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) s_rec[wave][lane][c] = pre[c];
-                s_bands[wave][lane] = pre_bands;
             }
         }
         const size_t plane = (size_t)V.width * V.height;
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
             const int py = ty * TH + ly + k * LY;
-            if (px < V.width && py < V.height) {
+            if (k >= k_lo && k < k_hi && px < V.width && py < V.height) {
                 const size_t p = (size_t)py * V.width + px;
                 V.rgb[p] = C0[k] + T[k] * P.bg0;
                 V.rgb[plane + p] = C1[k] + T[k] * P.bg1;
@@ -247,7 +267,8 @@ __device__ __forceinline__ float wave_sum(float x)
 
 template <int TW, int TH>
 __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ranges,
-                                                   const uint32_t *__restrict__ tile_order,
+                                                   const uint32_t *__restrict__ work_order,
+                                                   const uint32_t *__restrict__ n_items_p,
                                                    const uint32_t *__restrict__ inst_ids,
                                                    const float4 *__restrict__ records,
                                                    const DevView *__restrict__ views, BlendParams P,
@@ -256,15 +277,17 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
     constexpr int LX = TW, LY = 64 / TW, PPL = TH / LY;
     __shared__ float4 s_rec[4][64][4];
     __shared__ uint32_t s_id[4][64];
-    __shared__ uint32_t s_bands[4][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lx = lane % LX, ly = lane / LX;
     const int nq = min((int)gridDim.x, kQueues), q = (int)blockIdx.x % nq;
     unsigned int *const head = queue + q * kQueueStride;
+    const int64_t n_items = *n_items_p;
     for (;;) {
         const int64_t slot = q + (int64_t)nq * wave_fetch_add(head, 1u);
-        if (slot >= P.total_tiles) break;
-        const int tile = (int)tile_order[slot];
+        if (slot >= n_items) break;
+        const uint32_t item = work_order[slot];
+        if ((item & 3u) == 2u) continue;  // a split tile is done whole by its first item
+        const int tile = (int)(item >> 2);
         const DevView &V = views[find_view(views, P.n_views, tile)];
         const int local = tile - V.tile_base;
         const int tx = local % V.tiles_x, ty = local / V.tiles_x;
@@ -304,8 +327,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                 const uint32_t v = inst_ids[rg.x + lo + lane];
                 const uint32_t id = v & kIdMask;
                 s_id[wave][lane] = id < P.n_records ? id : 0xffffffffu;
-                s_bands[wave][lane] = v >> kIdBits;
-                stage_record(s_rec[wave][lane], records, id, P.n_records);
+                stage_record(s_rec[wave][lane], records, v, P.n_records, PPL <= 4);
             }
             lds_wave_sync();
             for (int jj = nb - 1; jj >= 0; --jj) {
@@ -313,14 +335,14 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                 const Rec R = load_rec(s_rec[wave][jj]);
                 const float K = R.log2o - P.log2_pmin;
                 const RowSpan span = row_span(R, ty * TH);
-                const uint32_t bands = __builtin_amdgcn_readfirstlane(s_bands[wave][jj]);
+                const uint32_t bands = __builtin_amdgcn_readfirstlane(R.rows);
                 const float inv_o = __builtin_amdgcn_exp2f(-R.log2o);
                 float du0 = 0, dv0 = 0, dM00 = 0, dM01 = 0, dM11 = 0, dgx = 0, dgy = 0, dk0 = 0, dic2 = 0, dop = 0,
                       dr = 0, dg = 0, db = 0;
                 bool hit = false;
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) {
-                    if (PPL <= 4 ? !((bands >> k) & 1u) : (span.r1 < k * LY || span.r0 >= (k + 1) * LY)) continue;
+                    if (!band_open<PPL, LY>(bands, span, k)) continue;
                     if (j >= last[k]) continue;
                     Frag f;
                     if (!frag_test(R, K, pxc, pyc[k], f)) continue;
@@ -413,24 +435,24 @@ int blend_backward_grid(TileShape s, int num_cus)
     return num_cus;
 }
 
-hipError_t launch_blend(TileShape s, const uint2 *ranges, const uint32_t *tile_order, const uint32_t *inst_ids,
-                        const float4 *records,
-                        const DevView *views, int n_views, int64_t total_tiles, int64_t n_records,
-                        const DevOptions &opt, unsigned int *queue, int grid, hipStream_t stream)
+hipError_t launch_blend(TileShape s, const uint2 *ranges, const uint32_t *work_order, const uint32_t *n_items,
+                        const uint32_t *inst_ids, const float4 *records, const DevView *views, int n_views,
+                        int64_t total_tiles, int64_t n_records, const DevOptions &opt, unsigned int *queue, int grid,
+                        hipStream_t stream)
 {
     const BlendParams P = make_params(opt, n_views, total_tiles, n_records);
-#define X(W, H)                                                                                         \
-    if (s.w == W && s.h == H) {                                                                         \
-        k_blend<W, H><<<grid, 256, 0, stream>>>(ranges, tile_order, inst_ids, records, views, P, queue); \
-        return hipGetLastError();                                                                       \
+#define X(W, H)                                                                                                  \
+    if (s.w == W && s.h == H) {                                                                                  \
+        k_blend<W, H><<<grid, 256, 0, stream>>>(ranges, work_order, n_items, inst_ids, records, views, P, queue); \
+        return hipGetLastError();                                                                                \
     }
     RGS_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_blend_backward(TileShape s, const uint2 *ranges, const uint32_t *tile_order,
-                                 const uint32_t *inst_ids, const float4 *records,
+hipError_t launch_blend_backward(TileShape s, const uint2 *ranges, const uint32_t *work_order,
+                                 const uint32_t *n_items, const uint32_t *inst_ids, const float4 *records,
                                  const DevView *views, int n_views, int64_t total_tiles, int64_t n_records,
                                  const DevOptions &opt, float *record_grads, unsigned int *queue, int grid,
                                  hipStream_t stream)
@@ -438,7 +460,7 @@ hipError_t launch_blend_backward(TileShape s, const uint2 *ranges, const uint32_
     const BlendParams P = make_params(opt, n_views, total_tiles, n_records);
 #define X(W, H)                                                                                                  \
     if (s.w == W && s.h == H) {                                                                                  \
-        k_blend_bwd<W, H><<<grid, 256, 0, stream>>>(ranges, tile_order, inst_ids, records, views, P,          \
+        k_blend_bwd<W, H><<<grid, 256, 0, stream>>>(ranges, work_order, n_items, inst_ids, records, views, P,  \
                                                     record_grads, queue);                                        \
         return hipGetLastError();                                                                                \
     }

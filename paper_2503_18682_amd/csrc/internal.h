@@ -63,7 +63,9 @@ hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n
                              float4 *records, uint32_t *depth_keys, uint32_t *order, uint2 *boxes,
                              Conic *conics, uint32_t *tile_counts, hipStream_t stream);
 
-// Stable LSD radix sort of (key, value) pairs on bits [0, bits).  n_dev (may
+// Stable LSD radix sort of (key, value) pairs on bits [0, bits), 8-bit digits
+// (radix_passes(bits) passes of a per-workgroup digit histogram, a scan of
+// each digit's row over the workgroups, and a stable scatter).  n_dev (may
 // be null) holds a device-side element count, clamped to n_max.  Ping-pongs
 // between (keys, vals) and (keys_alt, vals_alt): the result lands in the
 // primary buffers when the pass count is even, else in the alternates.
@@ -72,25 +74,31 @@ hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32
                       const int64_t *n_dev, int bits, uint32_t *hist, uint32_t *row_total, hipStream_t stream);
 size_t radix_hist_entries(int64_t n_max);
 
-// Binning scan over the depth order (Gaussian-view order[k] at position k):
-// offsets[k] = box tiles and row_offsets[k] = box tile rows of the positions
-// before k; counters[0] = all box tiles (instances), counters[2] = all tile
-// rows (int64); row_owner[r] = k for each tile row r of position k, written
-// when the instances fit `capacity` (row_owner holds capacity entries).
-// block_sums holds scan_block_entries(n) uint64.
-hipError_t binning_scan(const uint32_t *tile_counts, const uint2 *boxes, const uint32_t *order, int64_t n,
-                        int tile_h, int64_t capacity, uint32_t *offsets, uint32_t *row_offsets, uint32_t *row_owner,
-                        unsigned long long *block_sums, int64_t *counters, hipStream_t stream);
+// Binning scan over the depth order (Gaussian-view order[k] at position k,
+// sorted key keys[k], 0xffffffff when culled; positions k < *n_dev, at most
+// n): offsets[k] = box tiles and
+// row_offsets[k] = box tile rows of the positions before k; counters[0] =
+// all box tiles (instances), counters[2] = all tile rows (int64);
+// row_owner[r] = k for each tile row r of position k, written when the
+// instances fit `capacity` (row_owner holds capacity entries).  block_sums
+// holds scan_block_entries(n) uint64.
+hipError_t binning_scan(const uint32_t *keys, const uint2 *boxes, const uint32_t *order, int64_t n,
+                        const int64_t *n_dev, int tile_w, int tile_h, int64_t capacity, uint32_t *offsets,
+                        uint32_t *row_offsets, uint32_t *row_owner, unsigned long long *block_sums,
+                        int64_t *counters, hipStream_t stream);
 size_t scan_block_entries(int64_t n);
 
 // Instances of every tile row (one lane per row, `grid` workgroups looping
 // over counters[2] rows): (tile id, id | band bits) for listed tiles and
-// (empty_tile, id) for the other tiles of the box.
+// (empty_tile, id) for the other tiles of the box.  Also zeroes `ranges`
+// (total_tiles entries) and `sched` (sched_words()) for the stages after the
+// tile sort; always launched, also for an empty scene.
 int emit_grid(int num_cus);
 hipError_t launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *row_offsets,
                        const uint32_t *row_owner, const uint2 *boxes, const Conic *conics, const DevView *views,
                        int64_t n, int n_views, const int64_t *counters, int64_t capacity, int tile_w, int tile_h,
-                       uint32_t empty_tile, uint32_t *inst_tiles, uint32_t *inst_ids, int grid, hipStream_t stream);
+                       uint32_t empty_tile, uint32_t *inst_tiles, uint32_t *inst_ids, uint2 *ranges,
+                       int64_t total_tiles, uint32_t *sched, int grid, hipStream_t stream);
 
 // Compositing work queues: kQueues heads per pass, kQueueStride words apart
 // (separate memory lines, so their atomics do not serialise on one
@@ -99,27 +107,42 @@ hipError_t launch_emit(const uint32_t *order, const uint32_t *offsets, const uin
 constexpr int kQueues = 8;
 constexpr int kQueueStride = 1024;
 
-// Tile ranges of the sorted instances plus the compositing work order
-// (tile ids by decreasing list length).  `sched` holds sched_words() uint32:
-// the forward queue heads from word 0, the backward heads from
-// kQueues * kQueueStride (sched_backward_heads), then bucket histograms.
+// Tile ranges of the sorted instances plus the compositing work order:
+// work items tile << 2 | part (0 whole tile; 1, 2 the first and second half
+// of its pixel rows, for tiles whose list holds >= split_len entries, 0 =
+// never split) by decreasing list length, at most 2 * total_tiles of them.
+// `ranges` and `sched` must be zero (launch_emit clears them).  `sched` holds
+// sched_words() uint32: the forward queue heads from word 0, the backward
+// heads from sched_backward_heads(), bucket histograms, and the number of
+// work items at sched_item_count().
 size_t sched_words();
 size_t sched_backward_heads();
+size_t sched_item_count();
 hipError_t launch_tile_ranges(const uint32_t *inst_tiles, const int64_t *counters, int64_t capacity,
-                              int64_t total_tiles, uint2 *ranges, uint32_t *sched, uint32_t *tile_order,
-                              hipStream_t stream);
+                              int64_t total_tiles, uint32_t split_len, uint2 *ranges, uint32_t *sched,
+                              uint32_t *work_order, hipStream_t stream);
 
-hipError_t launch_blend(TileShape shape, const uint2 *ranges, const uint32_t *tile_order, const uint32_t *inst_ids,
-                        const float4 *records,
-                        const DevView *views, int n_views, int64_t total_tiles, int64_t n_records,
-                        const DevOptions &opt, unsigned int *queue, int grid, hipStream_t stream);
+// Lists at least this long are composited as two half-tile work items (for
+// tile shapes with at least two pixel slots per lane).
+#ifndef RGS_SPLIT_LEN
+#define RGS_SPLIT_LEN 256
+#endif
+
+// Compositing of the work items work_order[0, *n_items) (see
+// launch_tile_ranges); `queue` holds the kQueues heads (zero).
+hipError_t launch_blend(TileShape shape, const uint2 *ranges, const uint32_t *work_order, const uint32_t *n_items,
+                        const uint32_t *inst_ids, const float4 *records, const DevView *views, int n_views,
+                        int64_t total_tiles, int64_t n_records, const DevOptions &opt, unsigned int *queue, int grid,
+                        hipStream_t stream);
 int blend_grid(TileShape shape, int num_cus);
 
-hipError_t launch_blend_backward(TileShape shape, const uint2 *ranges, const uint32_t *tile_order,
-                                 const uint32_t *inst_ids,
-                                 const float4 *records, const DevView *views, int n_views, int64_t total_tiles,
-                                 int64_t n_records, const DevOptions &opt, float *record_grads, unsigned int *queue,
-                                 int grid, hipStream_t stream);
+// Backward compositing over the same work items (a split tile is handled
+// whole by its first half item; the second is skipped).
+hipError_t launch_blend_backward(TileShape shape, const uint2 *ranges, const uint32_t *work_order,
+                                 const uint32_t *n_items, const uint32_t *inst_ids, const float4 *records,
+                                 const DevView *views, int n_views, int64_t total_tiles, int64_t n_records,
+                                 const DevOptions &opt, float *record_grads, unsigned int *queue, int grid,
+                                 hipStream_t stream);
 int blend_backward_grid(TileShape shape, int num_cus);
 
 hipError_t launch_preprocess_backward(const rgs_gaussians &g, const DevView *views, int n_views,

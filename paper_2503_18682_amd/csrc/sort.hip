@@ -193,24 +193,27 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
 // Binning scan over the depth-sorted Gaussian-views: each item carries two
 // counts, the tiles of its pixel box (instances) and the tile rows of that
 // box; both are scanned at once (block sums hold the pair as two uint64).
-__device__ __forceinline__ void scan_item(const uint32_t *__restrict__ tile_counts, const uint2 *__restrict__ boxes,
-                                          const uint32_t *__restrict__ order, int64_t idx, int TH, uint32_t &tiles,
-                                          uint32_t &rows)
+// A culled view (sorted key 0xffffffff, all at the end) counts nothing and
+// costs no gather; a kept one reads its box.
+__device__ __forceinline__ void scan_item(const uint32_t *__restrict__ keys, const uint2 *__restrict__ boxes,
+                                          const uint32_t *__restrict__ order, int64_t idx, int TW, int TH,
+                                          uint32_t &tiles, uint32_t &rows)
 {
-    const uint32_t id = order[idx];
-    tiles = tile_counts[id];
-    rows = 0u;
-    if (tiles) {
-        const PixelBox pb = unpack_box(boxes[id]);
+    tiles = rows = 0u;
+    if (keys[idx] != 0xffffffffu) {
+        const PixelBox pb = unpack_box(boxes[order[idx]]);
         rows = (uint32_t)(pb.y1 / TH - pb.y0 / TH + 1);
+        tiles = rows * (uint32_t)(pb.x1 / TW - pb.x0 / TW + 1);
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__restrict__ tile_counts,
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__restrict__ keys,
                                                           const uint2 *__restrict__ boxes,
-                                                          const uint32_t *__restrict__ order, int64_t n, int TH,
+                                                          const uint32_t *__restrict__ order, int64_t n_max,
+                                                          const int64_t *__restrict__ n_dev, int TW, int TH,
                                                           unsigned long long *__restrict__ block_sums)
 {
+    const int64_t n = clamp_count(n_dev, n_max);
     __shared__ unsigned long long part[2][kWaves];
     const int64_t base = (int64_t)blockIdx.x * kTile;
     unsigned long long at = 0, ar = 0;
@@ -219,7 +222,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__rest
         const int64_t idx = base + (int64_t)j * kThreads + threadIdx.x;
         if (idx < n) {
             uint32_t t, r;
-            scan_item(tile_counts, boxes, order, idx, TH, t, r);
+            scan_item(keys, boxes, order, idx, TW, TH, t, r);
             at += t;
             ar += r;
         }
@@ -288,9 +291,10 @@ __global__ __launch_bounds__(1024) void k_scan_top(unsigned long long *__restric
 
 // Offsets of every sorted item, plus the owner map of the tile rows
 // (row_owner[r] = sorted position owning row r) when the instances fit.
-__global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t *__restrict__ tile_counts,
+__global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t *__restrict__ keys,
                                                          const uint2 *__restrict__ boxes,
-                                                         const uint32_t *__restrict__ order, int64_t n, int TH,
+                                                         const uint32_t *__restrict__ order, int64_t n_max,
+                                                         const int64_t *__restrict__ n_dev, int TW, int TH,
                                                          int64_t capacity,
                                                          const unsigned long long *__restrict__ block_sums,
                                                          const int64_t *__restrict__ counters,
@@ -299,6 +303,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t *__restr
                                                          uint32_t *__restrict__ row_owner)
 {
     __shared__ uint32_t smem[kWaves];
+    const int64_t n = clamp_count(n_dev, n_max);
     // blocked arrangement: thread t owns items base + t*8 .. +7
     const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItemsPerThread;
     uint32_t c[kItemsPerThread], r[kItemsPerThread];
@@ -306,7 +311,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t *__restr
 #pragma unroll
     for (int j = 0; j < kItemsPerThread; ++j) {
         c[j] = r[j] = 0u;
-        if (base + j < n) scan_item(tile_counts, boxes, order, base + j, TH, c[j], r[j]);
+        if (base + j < n) scan_item(keys, boxes, order, base + j, TW, TH, c[j], r[j]);
         lt += c[j];
         lr += r[j];
     }
@@ -338,7 +343,9 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t *__restr
 // at its scanned position, as (tile id, id | band bits) when a band meets the
 // support and as the empty marker `empty_tile` otherwise.  Instances end up
 // grouped by Gaussian-view in depth order, so a stable sort on the tile id
-// alone leaves every tile's list in depth order.
+// alone leaves every tile's list in depth order.  The kernel also clears the
+// tile ranges and the compositing scheduling words for the stages after the
+// tile sort (`clear` holds clear_words uint32 at `clear_a`, then `clear_b`).
 __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ order,
                                                    const uint32_t *__restrict__ offsets,
                                                    const uint32_t *__restrict__ row_offsets,
@@ -347,12 +354,17 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
                                                    const DevView *__restrict__ views, int64_t n,
                                                    const int64_t *__restrict__ counters, int64_t capacity, int TW,
                                                    int TH, uint32_t empty_tile, uint32_t *__restrict__ inst_tiles,
-                                                   uint32_t *__restrict__ inst_ids)
+                                                   uint32_t *__restrict__ inst_ids, uint32_t *__restrict__ clear_a,
+                                                   int64_t clear_a_words, uint32_t *__restrict__ clear_b,
+                                                   int64_t clear_b_words)
 {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    const int64_t tid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    for (int64_t i = tid; i < clear_a_words; i += stride) clear_a[i] = 0u;
+    for (int64_t i = tid; i < clear_b_words; i += stride) clear_b[i] = 0u;
     if (counters[0] > capacity) return;  // overflow: the instance total reports it
     const int64_t rows = counters[2];
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < rows; r += stride) {
+    for (int64_t r = tid; r < rows; r += stride) {
         const uint32_t k = row_owner[r];
         const uint32_t id = order[k];
         const PixelBox pb = unpack_box(boxes[id]);
@@ -395,54 +407,73 @@ __global__ __launch_bounds__(kThreads) void k_tile_ranges(const uint32_t *__rest
 }
 
 // -------------------------------------------------------- tile scheduling
-// Work order of the compositing kernels: tiles sorted by decreasing list
+// Work order of the compositing kernels: work items sorted by decreasing list
 // length (coarse buckets of 4 entries, order inside a bucket arbitrary), so
-// the longest tiles start first and the persistent grid drains evenly.
+// the longest lists start first and the persistent grid drains evenly.  A
+// tile whose list holds at least `split_len` entries (0: never) becomes two
+// items, each compositing half of the tile's pixel rows against the whole
+// list, which halves the longest chains of dependent work.  Item value =
+// tile << 2 | part (0 whole tile, 1 first half, 2 second half).
 constexpr int kSchedBuckets = 256;
 
-__device__ __forceinline__ uint32_t work_bucket(uint2 r)
+__device__ __forceinline__ uint32_t work_bucket(uint32_t len)
 {
-    const uint32_t len = r.y - r.x;
     return min(len >> 2, (uint32_t)(kSchedBuckets - 1));
 }
 
+__device__ __forceinline__ uint32_t work_parts(uint32_t len, uint32_t split_len)
+{
+    return (split_len != 0u && len >= split_len) ? 2u : 1u;
+}
+
 __global__ __launch_bounds__(kThreads) void k_sched_hist(const uint2 *__restrict__ ranges, int64_t total_tiles,
-                                                         uint32_t *__restrict__ hist)
+                                                         uint32_t split_len, uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t cnt[kSchedBuckets];
     cnt[threadIdx.x] = 0;
     __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (t < total_tiles) atomicAdd(&cnt[work_bucket(ranges[t])], 1u);
+    if (t < total_tiles) {
+        const uint2 r = ranges[t];
+        atomicAdd(&cnt[work_bucket(r.y - r.x)], work_parts(r.y - r.x, split_len));
+    }
     __syncthreads();
     if (cnt[threadIdx.x]) atomicAdd(&hist[threadIdx.x], cnt[threadIdx.x]);
 }
 
 __global__ __launch_bounds__(kThreads) void k_sched_scatter(const uint2 *__restrict__ ranges, int64_t total_tiles,
-                                                            const uint32_t *__restrict__ hist,
+                                                            uint32_t split_len, const uint32_t *__restrict__ hist,
                                                             uint32_t *__restrict__ cursor,
-                                                            uint32_t *__restrict__ tile_order)
+                                                            uint32_t *__restrict__ n_items,
+                                                            uint32_t *__restrict__ work_order)
 {
     __shared__ uint32_t smem[kWaves];
     __shared__ uint32_t base[kSchedBuckets];
     __shared__ uint32_t cnt[kSchedBuckets];
-    // buckets in decreasing order: bucket b starts after all tiles of buckets > b
+    // buckets in decreasing order: bucket b starts after all items of buckets > b
     const uint32_t hb = hist[kSchedBuckets - 1 - threadIdx.x];
     uint32_t tot;
     const uint32_t before = block_inclusive_scan(hb, smem, &tot) - hb;
     base[kSchedBuckets - 1 - threadIdx.x] = before;
     cnt[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *n_items = tot;
     __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    uint32_t b = 0, rank = 0;
+    uint32_t b = 0, rank = 0, parts = 0;
     if (t < total_tiles) {
-        b = work_bucket(ranges[t]);
-        rank = atomicAdd(&cnt[b], 1u);
+        const uint2 r = ranges[t];
+        b = work_bucket(r.y - r.x);
+        parts = work_parts(r.y - r.x, split_len);
+        rank = atomicAdd(&cnt[b], parts);
     }
     __syncthreads();
     if (cnt[threadIdx.x]) base[threadIdx.x] += atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
     __syncthreads();
-    if (t < total_tiles) tile_order[base[b] + rank] = (uint32_t)t;
+    if (parts == 1u) work_order[base[b] + rank] = (uint32_t)t << 2;
+    if (parts == 2u) {
+        work_order[base[b] + rank] = (uint32_t)t << 2 | 1u;
+        work_order[base[b] + rank + 1] = (uint32_t)t << 2 | 2u;
+    }
 }
 
 }  // namespace
@@ -476,9 +507,10 @@ hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32
 
 size_t scan_block_entries(int64_t n) { return 2 * (size_t)((n + kTile - 1) / kTile + 1); }
 
-hipError_t binning_scan(const uint32_t *tile_counts, const uint2 *boxes, const uint32_t *order, int64_t n,
-                        int tile_h, int64_t capacity, uint32_t *offsets, uint32_t *row_offsets, uint32_t *row_owner,
-                        unsigned long long *block_sums, int64_t *counters, hipStream_t stream)
+hipError_t binning_scan(const uint32_t *keys, const uint2 *boxes, const uint32_t *order, int64_t n,
+                        const int64_t *n_dev, int tile_w, int tile_h, int64_t capacity, uint32_t *offsets,
+                        uint32_t *row_offsets, uint32_t *row_owner, unsigned long long *block_sums,
+                        int64_t *counters, hipStream_t stream)
 {
     const int nb = (int)((n + kTile - 1) / kTile);
     if (nb == 0) {
@@ -487,10 +519,10 @@ hipError_t binning_scan(const uint32_t *tile_counts, const uint2 *boxes, const u
         k_fill_u32<<<1, kThreads, 0, stream>>>(reinterpret_cast<uint32_t *>(counters + 2), 0u, 2);
         return hipGetLastError();
     }
-    k_scan_reduce<<<nb, kThreads, 0, stream>>>(tile_counts, boxes, order, n, tile_h, block_sums);
+    k_scan_reduce<<<nb, kThreads, 0, stream>>>(keys, boxes, order, n, n_dev, tile_w, tile_h, block_sums);
     k_scan_top<<<1, 1024, 0, stream>>>(block_sums, nb, counters);
-    k_scan_apply<<<nb, kThreads, 0, stream>>>(tile_counts, boxes, order, n, tile_h, capacity, block_sums, counters,
-                                              offsets, row_offsets, row_owner);
+    k_scan_apply<<<nb, kThreads, 0, stream>>>(keys, boxes, order, n, n_dev, tile_w, tile_h, capacity, block_sums,
+                                              counters, offsets, row_offsets, row_owner);
     return hipGetLastError();
 }
 
@@ -499,11 +531,15 @@ int emit_grid(int num_cus) { return 8 * num_cus; }
 hipError_t launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *row_offsets,
                        const uint32_t *row_owner, const uint2 *boxes, const Conic *conics, const DevView *views,
                        int64_t n, int n_views, const int64_t *counters, int64_t capacity, int tile_w, int tile_h,
-                       uint32_t empty_tile, uint32_t *inst_tiles, uint32_t *inst_ids, int grid, hipStream_t stream)
+                       uint32_t empty_tile, uint32_t *inst_tiles, uint32_t *inst_ids, uint2 *ranges,
+                       int64_t total_tiles, uint32_t *sched, int grid, hipStream_t stream)
 {
-    if (n * n_views == 0) return hipSuccess;
-    k_emit<<<grid, kThreads, 0, stream>>>(order, offsets, row_offsets, row_owner, boxes, conics, views, n, counters,
-                                          capacity, tile_w, tile_h, empty_tile, inst_tiles, inst_ids);
+    // runs even with no Gaussian: it clears the ranges and scheduling words
+    k_emit<<<grid, kThreads, 0, stream>>>(order, offsets, row_offsets, row_owner, boxes, conics, views,
+                                          n > 0 ? n : 1, counters, capacity, tile_w, tile_h, empty_tile, inst_tiles,
+                                          inst_ids, reinterpret_cast<uint32_t *>(ranges), 2 * total_tiles, sched,
+                                          (int64_t)sched_words());
+    (void)n_views;
     return hipGetLastError();
 }
 
@@ -515,24 +551,22 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t s
 }
 
 size_t sched_backward_heads() { return (size_t)kQueues * kQueueStride; }
-size_t sched_words() { return 2 * sched_backward_heads() + 2 * kSchedBuckets; }
+size_t sched_item_count() { return 2 * sched_backward_heads() + 2 * kSchedBuckets; }
+size_t sched_words() { return sched_item_count() + 4; }
 
 hipError_t launch_tile_ranges(const uint32_t *inst_tiles, const int64_t *counters, int64_t capacity,
-                              int64_t total_tiles, uint2 *ranges, uint32_t *sched, uint32_t *tile_order,
-                              hipStream_t stream)
+                              int64_t total_tiles, uint32_t split_len, uint2 *ranges, uint32_t *sched,
+                              uint32_t *work_order, hipStream_t stream)
 {
-    // empty ranges; the work-queue heads and scheduling histograms start at zero
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * total_tiles, stream);
-    if (e != hipSuccess) return e;
-    e = launch_fill_u32(sched, 0u, (int64_t)sched_words(), stream);
-    if (e != hipSuccess) return e;
+    // the ranges, queue heads and scheduling histograms were cleared by k_emit
     if (capacity > 0)
         k_tile_ranges<<<(unsigned)((capacity + kThreads - 1) / kThreads), kThreads, 0, stream>>>(inst_tiles, counters,
                                                                                                  capacity, total_tiles, ranges);
     const unsigned nb = (unsigned)((total_tiles + kThreads - 1) / kThreads);
     uint32_t *hist = sched + 2 * sched_backward_heads(), *cursor = hist + kSchedBuckets;
-    k_sched_hist<<<nb, kThreads, 0, stream>>>(ranges, total_tiles, hist);
-    k_sched_scatter<<<nb, kThreads, 0, stream>>>(ranges, total_tiles, hist, cursor, tile_order);
+    k_sched_hist<<<nb, kThreads, 0, stream>>>(ranges, total_tiles, split_len, hist);
+    k_sched_scatter<<<nb, kThreads, 0, stream>>>(ranges, total_tiles, split_len, hist, cursor,
+                                                 sched + sched_item_count(), work_order);
     return hipGetLastError();
 }
 

@@ -5,6 +5,11 @@ Kernel durations (a ``--kernel-trace --stats --output-format csv`` run):
     python -m paper_2503_18682_amd.prof_summary stats --csv X_kernel_stats.csv \
         --out profiles/<name>.txt --workload "..." --command "..."
 
+Per-dispatch SQ counter averages of one kernel (any number of counter runs):
+
+    python -m paper_2503_18682_amd.prof_summary counters --csv A.csv B.csv \\
+        --kernel k_blend --out profiles/<name>.txt --workload "..." --command "..."
+
 HBM traffic of one kernel from two counter runs:
 
     python -m paper_2503_18682_amd.prof_summary traffic --fetch F.csv --write W.csv \
@@ -154,9 +159,49 @@ def write_stats(csv_path, out, command, workload):
         fo.write("\n".join(lines) + "\n")
 
 
+def write_counters(csv_paths, kernel, out, command, workload, clock_ghz=2.4, simds=1024):
+    """Per-dispatch averages of every counter in the given counter runs for
+    one kernel, with the VALU issue figure: SQ_INSTS_VALU wave instructions
+    take 4 cycles each on a 16-lane SIMD, so the chip issues at most
+    simds * clock / 4 of them per second."""
+    vals = collections.defaultdict(list)
+    ns = []
+    for path in csv_paths:
+        acc = collections.defaultdict(lambda: collections.defaultdict(float))
+        dur = {}
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if not re.search(re.escape(kernel) + r"\b", row["Kernel_Name"]):
+                    continue
+                d = int(row["Dispatch_Id"])
+                acc[d][row["Counter_Name"]] += float(row["Counter_Value"])
+                dur[d] = int(row["End_Timestamp"]) - int(row["Start_Timestamp"])
+        for d, c in acc.items():
+            for k, v in c.items():
+                vals[k].append(v)
+            ns.append(dur[d])
+    avg = {k: sum(v) / len(v) for k, v in vals.items()}
+    t = sum(ns) / len(ns) * 1e-9
+    lines = [f"# SQ counters of {kernel} ({workload}), averages per dispatch", "#",
+             "# Commands (repository root R on the GPU box, run from /tmp with TMPDIR=/tmp):"]
+    lines += [f"#   {c}" for c in command.split(" ;; ")]
+    lines += ["#", f"duration_us_under_counters: {t * 1e6:.1f}"]
+    lines += [f"{k}: {v:.4g}" for k, v in sorted(avg.items())]
+    if "SQ_INSTS_VALU" in avg:
+        issue_s = avg["SQ_INSTS_VALU"] * 4 / (simds * clock_ghz * 1e9)
+        lines += [f"valu_issue_time_us (SQ_INSTS_VALU x 4 cycles / {simds} SIMDs at {clock_ghz} GHz): "
+                  f"{issue_s * 1e6:.1f}",
+                  f"valu_issue_fraction_of_duration: {issue_s / t:.3f}"]
+    with open(out, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
+    cn = sub.add_parser("counters")
+    cn.add_argument("--csv", nargs="+", required=True)
+    cn.add_argument("--kernel", default="k_blend")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -164,7 +209,7 @@ def main():
     t.add_argument("--copy-mib", type=int, required=True)
     st = sub.add_parser("stats")
     st.add_argument("--csv", required=True)
-    for p in (t, st):
+    for p in (t, st, cn):
         p.add_argument("--out", required=True)
         p.add_argument("--workload", default="")
         p.add_argument("--command", default="", help="commands that produced the input (';;'-separated)")
@@ -173,6 +218,8 @@ def main():
         res = summarise(a.fetch, a.write, a.kernel, a.copy_mib)
         res["copy_mib"] = a.copy_mib
         write_summary(res, a.kernel, a.out, a.command, a.workload)
+    elif a.cmd == "counters":
+        write_counters(a.csv, a.kernel, a.out, a.command, a.workload)
     else:
         write_stats(a.csv, a.out, a.command, a.workload)
     print(open(a.out).read())

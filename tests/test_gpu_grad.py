@@ -83,6 +83,27 @@ def test_multi_view_sparse_pixels(r):
     _compare(grads, ref, "2-view sparse", rel=2e-3)
 
 
+def test_long_tile_lists(r):
+    """Dense cluster with tile lists of ~1,500 entries (split into half-tile
+    work items in the forward; the backward composites each tile whole)."""
+    from paper_2503_18682_amd import _lib
+
+    sc = scenegen.tiny_scene(36, 4000, sh_degree=1, half_extent=0.35, log_scale_mean=-3.2, log_scale_std=0.5)
+    # low opacity keeps every pixel's transmittance far above T_eps (no
+    # termination decision near its threshold)
+    sc["opacity_logits"][:] = -3.0 + 0.3 * np.random.default_rng(0).standard_normal(4000).astype(np.float32)
+    cam = scenegen.pinhole(scenegen.look_at((0.0, 0.0, -4.0)), 96, 80, 30)
+    opts = scenegen.default_options(tile_w=8, tile_h=16, background=(0.1, 0.2, 0.3))
+    say("case grad long lists, 4000 Gaussians 96x80")
+    g = to_dev(sc)
+    outs, (buf, ws) = r.render(g, [cam], opts, flags=_lib.RGS_WS_BACKWARD, keep_workspace=True)
+    rng = np.random.default_rng(7)
+    dl = (rng.normal(0, 1, (3, 80, 96)) * (rng.uniform(size=(80, 96)) < 0.3)).astype(np.float32)
+    grads = r.backward(g, [cam], outs, [torch.from_numpy(dl).cuda()], ws, opts)
+    ref = oracle.backward(sc, cam, opts, dl.astype(np.float64))
+    _compare(grads, ref, "long lists", rel=2e-3)
+
+
 def test_autograd_function_matches_direct_backward(r):
     from paper_2503_18682_amd import _lib
     from paper_2503_18682_amd import renderer as R

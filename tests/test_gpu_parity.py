@@ -47,14 +47,14 @@ def test_c0_image_keys_and_lists(r):
     assert (sp["hazard"] & oracle.HAZARD["cull"]).sum() == 0
     kept, box_tiles = oracle_box_tiles(sp)
     assert m == box_tiles.sum()
-    # depth keys, pixel boxes and box tile counts of every kept Gaussian
+    # depth keys (sorted, kept views only), pixel boxes and box tile counts
     n = sc["opacity_logits"].shape[0]
-    keys = read(buf, lay.depth_keys, n, np.uint32)
-    order = read(buf, lay.order, n, np.uint32)
-    gpu_key = np.full(n, 0xFFFFFFFF, np.uint32)
-    gpu_key[order] = keys
-    assert np.array_equal(gpu_key[kept], sp["depth_key"][kept])
-    assert np.all(gpu_key[~kept] == 0xFFFFFFFF)
+    n_kept = int(kept.sum())  # culled views sort last (key 0xffffffff)
+    keys = read(buf, lay.depth_keys, n_kept, np.uint32)
+    order = read(buf, lay.order, n_kept, np.uint32)
+    want = np.nonzero(kept)[0]
+    want = want[np.lexsort((want, sp["depth_key"][want]))]
+    assert np.array_equal(order, want) and np.array_equal(keys, sp["depth_key"][want])
     boxes = read(buf, lay.boxes, 4 * n, np.uint16).reshape(n, 4)
     good = kept & (sp["hazard"] == 0)
     for f, col in (("px0", 0), ("px1", 1), ("py0", 2), ("py1", 3)):
@@ -78,10 +78,13 @@ def test_lists_are_consistent_with_gpu_counts_boxes_and_keys(r):
     outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
     assert ok
     n = 2000
-    keys = read(buf, lay.depth_keys, n, np.uint32)
-    order = read(buf, lay.order, n, np.uint32).astype(np.int64)
-    boxes = read(buf, lay.boxes, 4 * n, np.uint16).reshape(n, 4).astype(np.int64)
     counts = read(buf, lay.tile_counts, n, np.uint32).astype(np.int64)
+    n_kept = int((counts > 0).sum())  # culled views sort last (key 0xffffffff)
+    keys = read(buf, lay.depth_keys, n_kept, np.uint32)
+    order = read(buf, lay.order, n_kept, np.uint32).astype(np.int64)
+    boxes = read(buf, lay.boxes, 4 * n, np.uint16).reshape(n, 4).astype(np.int64)
+    assert np.all(counts[order] > 0)
+    assert np.all(np.diff(keys.astype(np.int64)) >= 0)
     key_of = np.zeros(n, np.uint32)
     key_of[order] = keys
     tiles, ids, bands = instance_lists(buf, lay, m, with_bands=True, keep_empty=True)
@@ -121,6 +124,34 @@ def test_ragged_image_all_tile_shapes(r, shape):
     b_outs = render_with_ws(r, sc, [cam], base)[0]
     # per-pixel arithmetic does not depend on the tiling
     assert np.array_equal(outs[0]["rgb"], b_outs[0]["rgb"]) and np.array_equal(outs[0]["final_T"], b_outs[0]["final_T"])
+
+
+@pytest.mark.parametrize("logit", [-3.0, 1.0])
+def test_long_tile_lists_are_split_by_rows(r, logit):
+    """A dense cluster whose tile lists reach ~1,500-2,000 entries: tiles this
+    heavy are composited as two half-tile work items.  The image matches the
+    oracle, and is bit-identical across tile shapes (8x8 is never split).
+    logit -3: transmittance stays above T_eps (whole lists); logit 1: pixels
+    terminate early inside split tiles."""
+    say(f"case long lists, opacity logit {logit}")
+    sc = scenegen.tiny_scene(36, 4000, sh_degree=1, half_extent=0.35, log_scale_mean=-3.2, log_scale_std=0.5)
+    sc["opacity_logits"][:] = logit + 0.3 * np.random.default_rng(0).standard_normal(4000).astype(np.float32)
+    cam = scenegen.pinhole(scenegen.look_at((0.0, 0.0, -4.0)), 96, 80, 30)
+    ref = None
+    images = []
+    for shape in ((8, 16), (16, 16), (8, 8)):
+        opts = scenegen.default_options(tile_w=shape[0], tile_h=shape[1])
+        outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
+        assert ok
+        if ref is None:
+            ref = oracle.render(sc, cam, opts)
+            sp = oracle.preprocess(sc, cam, opts)
+            tiles, _, _ = oracle.tile_lists(sp, cam, opts)
+            assert np.bincount(tiles).max() >= 1000
+        assert_image_close(outs[0]["rgb"], outs[0]["final_T"], ref, label=f"long lists {shape}")
+        images.append(outs[0])
+    for o in images[1:]:
+        assert np.array_equal(o["rgb"], images[0]["rgb"]) and np.array_equal(o["final_T"], images[0]["final_T"])
 
 
 def _mk(mus, scales, opac, rgbs, quats=None):
