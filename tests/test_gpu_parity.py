@@ -228,6 +228,48 @@ def test_c1_full_size_sampled_pixels_and_lists(r):
     assert err <= 2e-4 and terr <= 2e-4
 
 
+def _sampled_pixels(outs_v, sc, cam, opts, n_px, rng, label):
+    """GPU pixels against the oracle's per-pixel evaluation at n_px random pixels."""
+    px = rng.integers(0, cam["width"], n_px)
+    py = rng.integers(0, cam["height"], n_px)
+    rgb, T, hz = oracle.render_pixels(sc, cam, opts, px, py)
+    g_rgb = outs_v["rgb"][:, py, px].T
+    g_T = outs_v["final_T"][py, px]
+    ok_ = hz == 0
+    err = np.abs(g_rgb - rgb)[ok_].max()
+    terr = np.abs(g_T - T)[ok_].max()
+    say(f"  {label}: max|rgb-oracle|={err:.3e} max|T-oracle|={terr:.3e} hazard={int((~ok_).sum())}/{n_px}")
+    assert (~ok_).mean() <= 0.02
+    assert err <= 2e-4 and terr <= 2e-4
+
+
+def test_c2_full_size_stereo_batch_sampled_pixels(r):
+    """3M Gaussians, 4 stereo pairs (8 views from 1032x1104 to 4128x4416 per
+    eye), MIP on, all 8 views in one HIP-graph replay with the benchmark's
+    8x16 tiles: sampled pixels of a 4128x4416 and a 1032x1104 eye."""
+    from paper_2503_18682_amd import renderer as R
+
+    w = scenegen.make_workload("c2")
+    sc, cams = w["scene"], w["cameras"]
+    opts = dict(w["options"], tile_w=8, tile_h=16)
+    n = int(sc["opacity_logits"].shape[0])
+    say("case c2 full size: 3M Gaussians, 8 stereo views, MIP, one graph replay")
+    g = to_dev(sc)
+    _, (buf, ws) = r.render(g, cams, opts, keep_workspace=True)
+    need = r.status(ws)[1]
+    del buf, ws
+    br = R.BatchRenderer(r, n, sc["sh_degree"], cams, int(need * 1.1) + 4096, options=opts)
+    outs = br.launch(g, cams)
+    ok, _ = br.status()
+    assert ok
+    rng = np.random.default_rng(8)
+    for v in (2, 5):
+        assert (cams[v]["width"], cams[v]["height"]) in ((4128, 4416), (1032, 1104))
+        host = {k: t.cpu().numpy() for k, t in outs[v].items()}
+        _sampled_pixels(host, sc, cams[v], opts, 150, rng, f"c2 view {v} {cams[v]['width']}x{cams[v]['height']}")
+    br.close()
+
+
 def test_batched_views_match_single_views_and_oracle(r):
     """Views of different sizes in one batch (MIP on) equal the same views
     rendered one at a time, bit for bit, and match the oracle."""
