@@ -50,18 +50,16 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, float *Y)
     }
 }
 
-template <int DEG>
 __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ means,
                                                     const float *__restrict__ log_scales,
                                                     const float *__restrict__ quats,
                                                     const float *__restrict__ opacity_logits,
-                                                    const float *__restrict__ sh, int n,
+                                                    int n,
                                                     const DevView *__restrict__ views, int n_views, DevOptions opt,
                                                     float4 *__restrict__ records, uint32_t *__restrict__ depth_keys,
                                                     uint32_t *__restrict__ order, uint2 *__restrict__ boxes,
                                                     Conic *__restrict__ conics, uint32_t *__restrict__ tile_counts)
 {
-    constexpr int NK = (DEG + 1) * (DEG + 1);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
 
@@ -74,8 +72,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
     for (int k = 0; k < 3; ++k) ok = ok && isfinite((float)m[k]) && isfinite(lf[k]);
 #pragma unroll
     for (int k = 0; k < 4; ++k) ok = ok && isfinite(qf[k]);
-    // colour coefficients are read (and checked) only once a view keeps the
-    // Gaussian; a non-finite coefficient culls it in every view
+    // colour coefficients are read (and checked) by k_colour once a view keeps
+    // the Gaussian; a non-finite coefficient culls it in every view
     const double q[4] = {qf[0], qf[1], qf[2], qf[3]};
     const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     ok = ok && qn > 0.0;
@@ -262,26 +260,6 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
             // tiles of the box; the emission kernel lists those whose row bands
             // meet the support and marks the others empty
             cnt = (uint32_t)((px1 / opt.tile_w - px0 / opt.tile_w + 1) * (py1 / opt.tile_h - py0 / opt.tile_h + 1));
-            // colour from the view direction (camera centre -> mean, world frame)
-            const double d0 = m[0] - V.centre[0], d1 = m[1] - V.centre[1], d2 = m[2] - V.centre[2];
-            const double dn = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            float Y[NK];
-            sh_basis<DEG>((float)(d0 / dn), (float)(d1 / dn), (float)(d2 / dn), Y);
-            float col[3] = {0.5f, 0.5f, 0.5f};
-            bool sh_ok = true;
-#pragma unroll
-            for (int k = 0; k < NK; ++k)
-#pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    const float c = sh[(size_t)(3 * k + ch) * n + i];
-                    sh_ok = sh_ok && isfinite(c);
-                    col[ch] += Y[k] * c;
-                }
-            if (!sh_ok) {
-                cnt = 0;
-                break;
-            }
-            for (int ch = 0; ch < 3; ++ch) col[ch] = col[ch] > 0.0f ? col[ch] : 0.0f;
             // the residuals of the centre go into one fp16 pair (|residual| <= half an
             // fp32 ulp of the centre, so fp16 keeps it to ~1e-7 px); the freed slot
             // holds the covered pixel rows for in-tile culling
@@ -292,12 +270,63 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
             rec[0] = make_float4(u_hi, v_hi, __uint_as_float(lo_bits), __uint_as_float(rows));
             rec[1] = make_float4((float)G[0][0], (float)G[0][1], (float)G[1][0], (float)G[1][1]);
             rec[2] = make_float4((float)gx, (float)gy, (float)(1.0 / mu[2]), (float)(1.0 / c2));
-            rec[3] = make_float4((float)log2(ov), col[0], col[1], col[2]);
+            rec[3] = make_float4((float)log2(ov), 0.0f, 0.0f, 0.0f);  // colour: k_colour
             conics[idx] = C;
         } while (false);
         depth_keys[idx] = cnt ? key : 0xffffffffu;
         tile_counts[idx] = cnt;
         boxes[idx] = box;
+    }
+}
+
+// View-dependent colour of every kept Gaussian-view (one thread per
+// Gaussian; its coefficients are read once, coalesced across the wave):
+// max(0, SH(direction camera centre -> mean) + 1/2) into the record.  A
+// Gaussian with a non-finite coefficient is culled in every view (its key
+// and tile count are cleared before the depth sort).
+template <int DEG>
+__global__ __launch_bounds__(256) void k_colour(const float *__restrict__ means, const float *__restrict__ sh, int n,
+                                                const DevView *__restrict__ views, int n_views,
+                                                float4 *__restrict__ records, uint32_t *__restrict__ depth_keys,
+                                                uint32_t *__restrict__ tile_counts)
+{
+    constexpr int NK = (DEG + 1) * (DEG + 1);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool any = false;
+    for (int v = 0; v < n_views; ++v) any = any || tile_counts[(size_t)v * n + i] != 0u;
+    if (!any) return;
+    float c[NK * 3];
+    bool sh_ok = true;
+#pragma unroll
+    for (int k = 0; k < NK * 3; ++k) {
+        c[k] = sh[(size_t)k * n + i];
+        sh_ok = sh_ok && isfinite(c[k]);
+    }
+    if (!sh_ok) {
+        for (int v = 0; v < n_views; ++v) {
+            const size_t idx = (size_t)v * n + i;
+            depth_keys[idx] = 0xffffffffu;
+            tile_counts[idx] = 0u;
+        }
+        return;
+    }
+    const double m[3] = {means[i], means[n + i], means[2 * n + i]};
+    for (int v = 0; v < n_views; ++v) {
+        const size_t idx = (size_t)v * n + i;
+        if (tile_counts[idx] == 0u) continue;
+        const DevView &V = views[v];
+        const double d0 = m[0] - V.centre[0], d1 = m[1] - V.centre[1], d2 = m[2] - V.centre[2];
+        const double dn = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        float Y[NK];
+        sh_basis<DEG>((float)(d0 / dn), (float)(d1 / dn), (float)(d2 / dn), Y);
+        float col[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
+        for (int k = 0; k < NK; ++k)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) col[ch] += Y[k] * c[3 * k + ch];
+        float *rec = reinterpret_cast<float *>(records + idx * 4);
+        for (int ch = 0; ch < 3; ++ch) rec[13 + ch] = col[ch] > 0.0f ? col[ch] : 0.0f;
     }
 }
 
@@ -310,16 +339,17 @@ hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n
     const int n = (int)g.n;
     if (n == 0) return hipSuccess;
     const dim3 grid((n + 255) / 256), block(256);
-#define RGS_PRE(D)                                                                                                 \
-    k_preprocess<D><<<grid, block, 0, stream>>>(g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, n, views, \
-                                                n_views, opt, records, depth_keys, order, boxes, conics, tile_counts)
+    k_preprocess<<<grid, block, 0, stream>>>(g.means, g.log_scales, g.quats, g.opacity_logits, n, views, n_views, opt,
+                                             records, depth_keys, order, boxes, conics, tile_counts);
+#define RGS_COL(D) \
+    k_colour<D><<<grid, block, 0, stream>>>(g.means, g.sh, n, views, n_views, records, depth_keys, tile_counts)
     switch (g.sh_degree) {
-    case 0: RGS_PRE(0); break;
-    case 1: RGS_PRE(1); break;
-    case 2: RGS_PRE(2); break;
-    default: RGS_PRE(3); break;
+    case 0: RGS_COL(0); break;
+    case 1: RGS_COL(1); break;
+    case 2: RGS_COL(2); break;
+    default: RGS_COL(3); break;
     }
-#undef RGS_PRE
+#undef RGS_COL
     return hipGetLastError();
 }
 
