@@ -307,6 +307,7 @@ def bench_c3(args, torch):
         bwd += ev[1].elapsed_time(ev[2])
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
+    r.stage_times()  # reset
     r.set_stage_timing(True)
     for _ in range(4):
         step()

@@ -194,17 +194,20 @@ rgs_status rgs_autotune(rgs_context *ctx, const rgs_gaussians *g, const rgs_came
  * profiling tools).  Counts are element counts.  Pure host arithmetic; ctx
  * may be NULL. */
 typedef struct {
-    size_t counters;       /* int64[8]: [0] instances needed, [1] capacity, [2] tile rows of all boxes */
+    size_t counters;       /* int64[8]: [0] instances needed (tiles of all pixel boxes), [1] capacity,
+                              [2] tile rows of all boxes, [3] listed instances (sorted; the rest are
+                              empty), [4] kept (not culled) Gaussian-views */
     size_t views;          /* per-view device table */
     size_t records;        /* float[16] per Gaussian-view, index v * n + i */
-    size_t depth_keys;     /* uint32 per Gaussian-view, sorted (0xffffffff = culled, at the end) */
+    size_t depth_keys;     /* uint32 per Gaussian-view: the kept views' keys, sorted, in [0, counters[4]) */
     size_t boxes;          /* uint16[4] per Gaussian-view: pixel box x0, x1, y0, y1 (inclusive) */
     size_t conics;         /* double[8] per Gaussian-view: support ellipse P00, P01, P11, h0, h1, f0, u0, v0 */
     size_t tile_counts;    /* uint32 per Gaussian-view: tiles of its pixel box (0 = culled) */
-    size_t order;          /* uint32 per Gaussian-view: Gaussian-view ids sorted by (depth key, id) */
+    size_t order;          /* uint32 per Gaussian-view: the kept views' ids sorted by (depth key, id), in
+                              [0, counters[4]) */
     size_t offsets;        /* uint32 per Gaussian-view: first instance of each sorted entry */
-    size_t inst_tiles;     /* uint32 per instance: global tile id, sorted; a box tile whose row bands all
-                              miss the support holds 2^tile_bits - 1 (> every tile id) and sorts last */
+    size_t inst_tiles;     /* uint32 per instance: global tile id, sorted, [0, counters[3]) (box tiles
+                              whose row bands all miss the support are dropped by the sort) */
     size_t inst_ids;       /* uint32 per instance: Gaussian-view id (low 28 bits) sorted by (tile, depth, id);
                               the top 4 bits flag the tile's row bands that meet the support */
     size_t tile_ranges;    /* uint32[2] per global tile: [start, end) into the instance arrays */
@@ -223,10 +226,12 @@ rgs_status rgs_get_workspace_layout(rgs_context *ctx, int64_t n, const rgs_camer
                                     rgs_workspace_layout *out);
 
 /* Per-stage GPU timing.  While enabled, rgs_render and rgs_render_backward
- * record HIP events around each stage on the caller's stream; rgs_stage_times
- * synchronises, adds the elapsed times of all frames recorded since the last
- * read into ms[0..n) in the order of rgs_stage_names (a ';'-separated list),
- * and resets.  Returns the number of stages. */
+ * record HIP events around each stage on the caller's stream (graph replays
+ * are not timed); rgs_stage_times synchronises, adds the elapsed times of all
+ * frames recorded since the last read into ms[0..n) in the order of
+ * rgs_stage_names (a ';'-separated list), sets *frames to the number of
+ * forward renders timed since then, and resets.  Returns the number of
+ * stages. */
 rgs_status rgs_set_stage_timing(rgs_context *ctx, int32_t enable);
 int32_t rgs_stage_times(rgs_context *ctx, double *ms, int32_t n, int64_t *frames);
 const char *rgs_stage_names(void);

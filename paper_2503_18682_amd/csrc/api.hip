@@ -355,13 +355,16 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
     RGS_HIP(ctx, launch_preprocess(g, views, n_views, dopt, records, keys_in, ord_in, boxes, conics, tile_counts,
                                    stream));
     tm.mark(ST_PRE);
-    RGS_HIP(ctx, radix_sort(keys_in, ord_in, keys_alt, ord_alt, NV, nullptr, 32, hist, row_total, stream));
+    // counters: [0] box instances, [1] capacity, [2] tile rows, [3] listed instances, [4] kept views
+    int64_t *listed = counters + 3, *kept = counters + 4;
+    RGS_HIP(ctx, radix_sort(keys_in, ord_in, keys_alt, ord_alt, NV, nullptr, 32, true, 0xffffffffu, kept, hist,
+                            row_total, stream));
     tm.mark(ST_DSORT);
     const uint32_t *order = at<uint32_t>(ws, L.order_a);
     uint32_t *offsets = at<uint32_t>(ws, L.offsets);
     uint32_t *row_offsets = at<uint32_t>(ws, L.row_offsets);
     uint32_t *row_owner = at<uint32_t>(ws, L.row_owner);
-    RGS_HIP(ctx, binning_scan(at<uint32_t>(ws, L.keys_a), boxes, order, NV, nullptr, s.w, s.h, L.capacity, offsets,
+    RGS_HIP(ctx, binning_scan(at<uint32_t>(ws, L.keys_a), boxes, order, NV, kept, s.w, s.h, L.capacity, offsets,
                               row_offsets, row_owner,
                               at<unsigned long long>(ws, L.block_sums), counters, stream));
     tm.mark(ST_SCAN);
@@ -370,13 +373,14 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
                              L.capacity, s.w, s.h, empty_tile, tiles_in, ids_in, ranges, L.total_tiles, sched,
                              emit_grid(ctx->num_cus), stream));
     tm.mark(ST_EMIT);
-    RGS_HIP(ctx, radix_sort(tiles_in, ids_in, tiles_alt, ids_alt, L.capacity, counters, L.tile_bits, hist, row_total,
-                            stream));
+    RGS_HIP(ctx, radix_sort(tiles_in, ids_in, tiles_alt, ids_alt, L.capacity, counters, L.tile_bits, true, empty_tile,
+                            listed, hist, row_total, stream));
     tm.mark(ST_TSORT);
     const uint32_t *inst_tiles = at<uint32_t>(ws, L.inst_tiles_a);
     const uint32_t *inst_ids = at<uint32_t>(ws, L.inst_ids_a);
-    const uint32_t split_len = s.h / (64 / s.w) >= 2 ? (uint32_t)RGS_SPLIT_LEN : 0u;
-    RGS_HIP(ctx, launch_tile_ranges(inst_tiles, counters, L.capacity, L.total_tiles, split_len, ranges, sched,
+    const uint32_t split_min = s.h / (64 / s.w) >= 2 ? (uint32_t)RGS_SPLIT_LEN : 0u;
+    const uint32_t waves = (uint32_t)(4 * ctx->grid_fwd[shape_index(s)]);
+    RGS_HIP(ctx, launch_tile_ranges(inst_tiles, listed, L.capacity, L.total_tiles, split_min, waves, ranges, sched,
                                     at<uint32_t>(ws, L.tile_order), stream));
     tm.mark(ST_RANGES);
     RGS_HIP(ctx, launch_blend(s, ranges, tile_order, sched + sched_item_count(), inst_ids, records, views, n_views,
@@ -488,7 +492,7 @@ rgs_status rgs_render(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera
     const std::vector<unsigned char> hdr = build_header(L, cams, n_views, outs, nullptr);
     RGS_HIP(ctx, hipMemcpyAsync(ws->ptr, hdr.data(), hdr.size(), hipMemcpyHostToDevice, s));
     st = enqueue_forward(ctx, *g, n_views, *opts, L, ws->ptr, s, true);
-    if (st == RGS_OK) ++ctx->frames;
+    if (st == RGS_OK && ctx->timing) ++ctx->frames;  // frames whose stages were timed
     return st;
 }
 
@@ -649,7 +653,6 @@ rgs_status rgs_batch_launch(rgs_plan *p, const rgs_gaussians *g, const rgs_camer
     const std::vector<unsigned char> hdr = build_header(L, cams, nv, outs, nullptr);
     RGS_HIP(ctx, hipMemcpyAsync(ws->ptr, hdr.data(), hdr.size(), hipMemcpyHostToDevice, s));
     RGS_HIP(ctx, hipGraphLaunch(p->exec, s));
-    ++ctx->frames;
     return RGS_OK;
 }
 

@@ -258,11 +258,45 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
     }
 }
 
-__device__ __forceinline__ float wave_sum(float x)
+// Sums of 16 per-lane values over the wave by transposing while reducing:
+// at each butterfly step a lane keeps one half of its values and sends the
+// other half to its partner, so the 16 sums take 8 + 4 + 2 + 1 + 1 + 1 = 17
+// exchanges instead of 16 * 6.  On return, lane l holds the sum of value
+// index ((l >> 5) & 1) * 8 + ((l >> 4) & 1) * 4 + ((l >> 3) & 1) * 2 +
+// ((l >> 2) & 1) (the same in the four lanes l & ~3 .. l | 3).
+__device__ __forceinline__ float wave_sum16(const float (&v)[16], int lane)
 {
+    float a[8];
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    for (int i = 0; i < 8; ++i) {
+        const bool up = lane & 32;
+        const float send = up ? v[i] : v[8 + i];
+        a[i] = (up ? v[8 + i] : v[i]) + __shfl_xor(send, 32, 64);
+    }
+    float b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const bool up = lane & 16;
+        const float send = up ? a[i] : a[4 + i];
+        b[i] = (up ? a[4 + i] : a[i]) + __shfl_xor(send, 16, 64);
+    }
+    float c[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const bool up = lane & 8;
+        const float send = up ? b[i] : b[2 + i];
+        c[i] = (up ? b[2 + i] : b[i]) + __shfl_xor(send, 8, 64);
+    }
+    const bool up = lane & 4;
+    float x = (up ? c[1] : c[0]) + __shfl_xor(up ? c[0] : c[1], 4, 64);
+    x += __shfl_xor(x, 2, 64);
+    x += __shfl_xor(x, 1, 64);
     return x;
+}
+
+__device__ __forceinline__ int wave_sum16_index(int lane)
+{
+    return ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
 }
 
 template <int TW, int TH>
@@ -286,8 +320,10 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
         const int64_t slot = q + (int64_t)nq * wave_fetch_add(head, 1u);
         if (slot >= n_items) break;
         const uint32_t item = work_order[slot];
-        if ((item & 3u) == 2u) continue;  // a split tile is done whole by its first item
         const int tile = (int)(item >> 2);
+        // pixel slots [k_lo, k_hi) of the lanes: all, or one half of the rows
+        const int part = (int)(item & 3u);
+        const int k_lo = part == 2 ? PPL / 2 : 0, k_hi = part == 1 ? PPL / 2 : PPL;
         const DevView &V = views[find_view(views, P.n_views, tile)];
         const int local = tile - V.tile_base;
         const int tx = local % V.tiles_x, ty = local / V.tiles_x;
@@ -305,7 +341,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
             S[k] = 0.0f;
             g0[k] = g1[k] = g2[k] = 0.0f;
             last[k] = 0;
-            if (px < V.width && py < V.height) {
+            if (k >= k_lo && k < k_hi && px < V.width && py < V.height) {
                 const size_t p = (size_t)py * V.width + px;
                 T[k] = V.final_T[p];
                 last[k] = V.n_contrib[p];
@@ -342,21 +378,21 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                 bool hit = false;
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) {
-                    if (!band_open<PPL, LY>(bands, span, k)) continue;
+                    if (k < k_lo || k >= k_hi || !band_open<PPL, LY>(bands, span, k)) continue;
                     if (j >= last[k]) continue;
                     Frag f;
                     if (!frag_test(R, K, pxc, pyc[k], f)) continue;
                     frag_omega(R, f);
                     hit = true;
                     const float a = fminf(f.w, P.alpha_max);
-                    const float om = 1.0f - a;
-                    const float Tb = T[k] / om;  // transmittance in front of this Gaussian
+                    const float rom = __builtin_amdgcn_rcpf(1.0f - a);  // 1 / (1 - alpha), alpha <= alpha_max
+                    const float Tb = T[k] * rom;  // transmittance in front of this Gaussian
                     const float rgd = R.r * g0[k] + R.g * g1[k] + R.b * g2[k];
                     const float ta = Tb * a;
                     dr += ta * g0[k];
                     dg += ta * g1[k];
                     db += ta * g2[k];
-                    const float dL_da = Tb * rgd - S[k] / om;
+                    const float dL_da = Tb * rgd - S[k] * rom;
                     S[k] += ta * rgd;
                     T[k] = Tb;
                     if (f.w < P.alpha_max) {
@@ -379,14 +415,13 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                     }
                 }
                 if (__ballot(hit) == 0) continue;
-                float vals[13] = {du0, dv0, dM00, dM01, dM11, dgx, dgy, dk0, dic2, dop, dr, dg, db};
-#pragma unroll
-                for (int c = 0; c < 13; ++c) vals[c] = wave_sum(vals[c]);
-                if (lane == 0 && s_id[wave][jj] != 0xffffffffu) {
-                    float *dst = record_grads + (size_t)s_id[wave][jj] * kGradFloats;
-#pragma unroll
-                    for (int c = 0; c < 13; ++c) atomicAdd(dst + c, vals[c]);
-                }
+                const float vals[16] = {du0, dv0, dM00, dM01, dM11, dgx, dgy, dk0, dic2, dop, dr, dg, db, 0.f, 0.f, 0.f};
+                const float sum = wave_sum16(vals, lane);
+                const int c = wave_sum16_index(lane);
+                const uint32_t rid = s_id[wave][jj];
+                // one lane per gradient component adds it to the record's accumulators
+                if ((lane & 3) == 0 && c < 13 && rid != 0xffffffffu)
+                    atomicAdd(record_grads + (size_t)rid * kGradFloats + c, sum);
             }
             lds_wave_sync();
         }

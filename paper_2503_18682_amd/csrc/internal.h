@@ -66,12 +66,16 @@ hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n
 // Stable LSD radix sort of (key, value) pairs on bits [0, bits), 8-bit digits
 // (radix_passes(bits) passes of a per-workgroup digit histogram, a scan of
 // each digit's row over the workgroups, and a stable scatter).  n_dev (may
-// be null) holds a device-side element count, clamped to n_max.  Ping-pongs
-// between (keys, vals) and (keys_alt, vals_alt): the result lands in the
-// primary buffers when the pass count is even, else in the alternates.
+// be null) holds a device-side element count, clamped to n_max.  With
+// `drop`, elements whose key equals drop_key leave the sort in the first
+// pass; the kept elements end up sorted in [0, *kept_out) (int64, device,
+// written).  Ping-pongs between (keys, vals) and (keys_alt, vals_alt): the
+// result lands in the primary buffers when the pass count is even, else in
+// the alternates.
 int radix_passes(int bits);
 hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt, int64_t n_max,
-                      const int64_t *n_dev, int bits, uint32_t *hist, uint32_t *row_total, hipStream_t stream);
+                      const int64_t *n_dev, int bits, bool drop, uint32_t drop_key, int64_t *kept_out,
+                      uint32_t *hist, uint32_t *row_total, hipStream_t stream);
 size_t radix_hist_entries(int64_t n_max);
 
 // Binning scan over the depth order (Gaussian-view order[k] at position k,
@@ -107,10 +111,11 @@ hipError_t launch_emit(const uint32_t *order, const uint32_t *offsets, const uin
 constexpr int kQueues = 8;
 constexpr int kQueueStride = 1024;
 
-// Tile ranges of the sorted instances plus the compositing work order:
-// work items tile << 2 | part (0 whole tile; 1, 2 the first and second half
-// of its pixel rows, for tiles whose list holds >= split_len entries, 0 =
-// never split) by decreasing list length, at most 2 * total_tiles of them.
+// Tile ranges of the `*counters` sorted instances plus the compositing work
+// order: work items tile << 2 | part (0 whole tile; 1, 2 the first and
+// second half of its pixel rows, for tiles whose list is longer than
+// max(split_min, *counters / waves), split_min 0 = never split) by
+// decreasing list length, at most 2 * total_tiles of them.
 // `ranges` and `sched` must be zero (launch_emit clears them).  `sched` holds
 // sched_words() uint32: the forward queue heads from word 0, the backward
 // heads from sched_backward_heads(), bucket histograms, and the number of
@@ -119,11 +124,11 @@ size_t sched_words();
 size_t sched_backward_heads();
 size_t sched_item_count();
 hipError_t launch_tile_ranges(const uint32_t *inst_tiles, const int64_t *counters, int64_t capacity,
-                              int64_t total_tiles, uint32_t split_len, uint2 *ranges, uint32_t *sched,
-                              uint32_t *work_order, hipStream_t stream);
+                              int64_t total_tiles, uint32_t split_min, uint32_t waves, uint2 *ranges,
+                              uint32_t *sched, uint32_t *work_order, hipStream_t stream);
 
-// Lists at least this long are composited as two half-tile work items (for
-// tile shapes with at least two pixel slots per lane).
+// Shortest list composited as two half-tile work items (for tile shapes with
+// at least two pixel slots per lane).
 #ifndef RGS_SPLIT_LEN
 #define RGS_SPLIT_LEN 256
 #endif
@@ -136,8 +141,7 @@ hipError_t launch_blend(TileShape shape, const uint2 *ranges, const uint32_t *wo
                         hipStream_t stream);
 int blend_grid(TileShape shape, int num_cus);
 
-// Backward compositing over the same work items (a split tile is handled
-// whole by its first half item; the second is skipped).
+// Backward compositing over the same work items (whole tiles and halves).
 hipError_t launch_blend_backward(TileShape shape, const uint2 *ranges, const uint32_t *work_order,
                                  const uint32_t *n_items, const uint32_t *inst_ids, const float4 *records,
                                  const DevView *views, int n_views, int64_t total_tiles, int64_t n_records,

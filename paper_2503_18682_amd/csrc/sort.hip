@@ -16,7 +16,15 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kItemsPerThread = 8;
-constexpr int kTile = kThreads * kItemsPerThread;  // items per block
+constexpr int kTile = kThreads * kItemsPerThread;  // items per block (scans)
+// radix sort: items per lane and per workgroup (a smaller tile shortens the
+// serial ranking chain of each workgroup; the digit histograms grow with the
+// number of tiles)
+#ifndef RGS_RADIX_ITEMS
+#define RGS_RADIX_ITEMS 8
+#endif
+constexpr int kRadixItems = RGS_RADIX_ITEMS;
+constexpr int kRadixTile = kThreads * kRadixItems;
 constexpr int kBins = 256;                         // 8-bit digits
 
 // Element count of a device-sized array: a frame whose instance count
@@ -55,9 +63,12 @@ __device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t x, uint32_t *s
 }
 
 // ---------------------------------------------------------------- radix sort
+// Digit histogram of one block's items; with `drop`, keys equal to drop_key
+// are left out (they leave the sort in this pass).
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restrict__ keys, int64_t n_max,
                                                          const int64_t *__restrict__ n_dev, int shift, int bits,
-                                                         uint32_t *__restrict__ hist, int nblocks)
+                                                         bool drop, uint32_t drop_key, uint32_t *__restrict__ hist,
+                                                         int nblocks)
 {
     __shared__ uint32_t cnt[kWaves][kBins];
     const int tid = threadIdx.x, wave = tid >> 6;
@@ -65,13 +76,16 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restr
     for (int w = 0; w < kWaves; ++w) cnt[w][tid] = 0;
     __syncthreads();
     const int64_t n = clamp_count(n_dev, n_max);
-    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
     const uint32_t mask = (1u << bits) - 1u;
     if (base < n) {
 #pragma unroll
-        for (int j = 0; j < kItemsPerThread; ++j) {
+        for (int j = 0; j < kRadixItems; ++j) {
             const int64_t idx = base + (int64_t)j * kThreads + tid;
-            if (idx < n) atomicAdd(&cnt[wave][(keys[idx] >> shift) & mask], 1u);
+            if (idx < n) {
+                const uint32_t key = keys[idx];
+                if (!(drop && key == drop_key)) atomicAdd(&cnt[wave][(key >> shift) & mask], 1u);
+            }
         }
     }
     __syncthreads();
@@ -101,39 +115,47 @@ __global__ __launch_bounds__(kThreads) void k_radix_scan_rows(uint32_t *__restri
 // per digit bit, ranked by popcount of the lower peers, and a per-wave LDS
 // counter per digit carries the rank across rounds.  Items are then staged in
 // LDS in block-local sorted order and written out in runs of equal digits.
+// With `drop`, keys equal to drop_key are not written, and block 0 stores
+// the number of items kept (the sum of the digit totals) in *kept_out.
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
     uint32_t *__restrict__ vals_out, int64_t n_max, const int64_t *__restrict__ n_dev, int shift, int bits,
-    const uint32_t *__restrict__ hist, const uint32_t *__restrict__ row_total, int nblocks)
+    bool drop, uint32_t drop_key, int64_t *__restrict__ kept_out, const uint32_t *__restrict__ hist,
+    const uint32_t *__restrict__ row_total, int nblocks)
 {
     __shared__ uint32_t wave_cnt[kWaves][kBins];
     __shared__ uint32_t block_start[kBins];
     __shared__ uint32_t out_base[kBins];
-    __shared__ uint32_t s_keys[kTile];
-    __shared__ uint32_t s_vals[kTile];
+    __shared__ uint32_t s_keys[kRadixTile];
+    __shared__ uint32_t s_vals[kRadixTile];
     __shared__ uint32_t smem[kWaves];
+    __shared__ uint32_t block_valid;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t n = clamp_count(n_dev, n_max);
-    const int64_t base = (int64_t)blockIdx.x * kTile;
-    if (base >= n) return;  // uniform per block
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    if (base >= n) {  // uniform per block
+        if (drop && blockIdx.x == 0 && tid == 0) *kept_out = 0;
+        return;
+    }
     const uint32_t mask = (1u << bits) - 1u;
 
     // digit bases: exclusive scan of the row totals (thread = digit)
     uint32_t dig_total;
     const uint32_t rt = row_total[tid];
     const uint32_t dig_base = block_inclusive_scan(rt, smem, &dig_total) - rt;
+    if (drop && blockIdx.x == 0 && tid == 0) *kept_out = (int64_t)dig_total;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) wave_cnt[w][tid] = 0;
     __syncthreads();
 
-    uint32_t my_key[kItemsPerThread], my_val[kItemsPerThread], my_rank[kItemsPerThread];
+    uint32_t my_key[kRadixItems], my_val[kRadixItems], my_rank[kRadixItems];
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
 #pragma unroll
-    for (int r = 0; r < kItemsPerThread; ++r) {
-        const int64_t idx = base + (int64_t)wave * (kTile / kWaves) + r * 64 + lane;
-        const bool valid = idx < n;
-        const uint32_t key = valid ? keys_in[idx] : 0u;
+    for (int r = 0; r < kRadixItems; ++r) {
+        const int64_t idx = base + (int64_t)wave * (kRadixTile / kWaves) + r * 64 + lane;
+        const uint32_t key = idx < n ? keys_in[idx] : 0u;
+        const bool valid = idx < n && !(drop && key == drop_key);
         my_key[r] = key;
         my_val[r] = valid ? vals_in[idx] : 0u;
         const uint32_t d = (key >> shift) & mask;
@@ -165,11 +187,12 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
         uint32_t tot;
         const uint32_t start = block_inclusive_scan(run, smem, &tot) - run;
         block_start[tid] = start;
+        if (tid == 0) block_valid = tot;
         out_base[tid] = dig_base + hist[(size_t)tid * nblocks + blockIdx.x] - start;
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kItemsPerThread; ++r) {
+    for (int r = 0; r < kRadixItems; ++r) {
         if (my_rank[r] == 0xffffffffu) continue;
         const uint32_t d = (my_key[r] >> shift) & mask;
         const uint32_t pos = block_start[d] + wave_cnt[wave][d] + my_rank[r];
@@ -177,7 +200,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
         s_vals[pos] = my_val[r];
     }
     __syncthreads();
-    const int count = (int)((n - base) < kTile ? (n - base) : kTile);
+    const int count = (int)block_valid;  // items of this block that stay in the sort
     for (int p = tid; p < count; p += kThreads) {
         const uint32_t key = s_keys[p];
         const uint32_t d = (key >> shift) & mask;
@@ -410,15 +433,23 @@ __global__ __launch_bounds__(kThreads) void k_tile_ranges(const uint32_t *__rest
 // Work order of the compositing kernels: work items sorted by decreasing list
 // length (coarse buckets of 4 entries, order inside a bucket arbitrary), so
 // the longest lists start first and the persistent grid drains evenly.  A
-// tile whose list holds at least `split_len` entries (0: never) becomes two
-// items, each compositing half of the tile's pixel rows against the whole
-// list, which halves the longest chains of dependent work.  Item value =
-// tile << 2 | part (0 whole tile, 1 first half, 2 second half).
+// tile whose list is longer than the average work of a compositing wave
+// (listed instances / waves, at least split_min; split_min 0: never split)
+// becomes two items, each compositing half of the tile's pixel rows against
+// the whole list, which halves the longest chains of dependent work.  Item
+// value = tile << 2 | part (0 whole tile, 1 first half, 2 second half).
 constexpr int kSchedBuckets = 256;
 
 __device__ __forceinline__ uint32_t work_bucket(uint32_t len)
 {
     return min(len >> 2, (uint32_t)(kSchedBuckets - 1));
+}
+
+__device__ __forceinline__ uint32_t split_length(const int64_t *listed, uint32_t split_min, uint32_t waves)
+{
+    if (split_min == 0u) return 0u;
+    const int64_t share = (*listed + waves - 1) / waves;
+    return (uint32_t)max((int64_t)split_min, share);
 }
 
 __device__ __forceinline__ uint32_t work_parts(uint32_t len, uint32_t split_len)
@@ -427,8 +458,10 @@ __device__ __forceinline__ uint32_t work_parts(uint32_t len, uint32_t split_len)
 }
 
 __global__ __launch_bounds__(kThreads) void k_sched_hist(const uint2 *__restrict__ ranges, int64_t total_tiles,
-                                                         uint32_t split_len, uint32_t *__restrict__ hist)
+                                                         const int64_t *__restrict__ listed, uint32_t split_min,
+                                                         uint32_t waves, uint32_t *__restrict__ hist)
 {
+    const uint32_t split_len = split_length(listed, split_min, waves);
     __shared__ uint32_t cnt[kSchedBuckets];
     cnt[threadIdx.x] = 0;
     __syncthreads();
@@ -442,7 +475,8 @@ __global__ __launch_bounds__(kThreads) void k_sched_hist(const uint2 *__restrict
 }
 
 __global__ __launch_bounds__(kThreads) void k_sched_scatter(const uint2 *__restrict__ ranges, int64_t total_tiles,
-                                                            uint32_t split_len, const uint32_t *__restrict__ hist,
+                                                            const int64_t *__restrict__ listed, uint32_t split_min,
+                                                            uint32_t waves, const uint32_t *__restrict__ hist,
                                                             uint32_t *__restrict__ cursor,
                                                             uint32_t *__restrict__ n_items,
                                                             uint32_t *__restrict__ work_order)
@@ -450,6 +484,7 @@ __global__ __launch_bounds__(kThreads) void k_sched_scatter(const uint2 *__restr
     __shared__ uint32_t smem[kWaves];
     __shared__ uint32_t base[kSchedBuckets];
     __shared__ uint32_t cnt[kSchedBuckets];
+    const uint32_t split_len = split_length(listed, split_min, waves);
     // buckets in decreasing order: bucket b starts after all items of buckets > b
     const uint32_t hb = hist[kSchedBuckets - 1 - threadIdx.x];
     uint32_t tot;
@@ -480,23 +515,30 @@ __global__ __launch_bounds__(kThreads) void k_sched_scatter(const uint2 *__restr
 
 int radix_passes(int bits) { return bits <= 0 ? 0 : (bits + 7) / 8; }
 
-size_t radix_hist_entries(int64_t n_max) { return (size_t)kBins * (size_t)((n_max + kTile - 1) / kTile + 1); }
+size_t radix_hist_entries(int64_t n_max) { return (size_t)kBins * (size_t)((n_max + kRadixTile - 1) / kRadixTile + 1); }
 
 hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt, int64_t n_max,
-                      const int64_t *n_dev, int bits, uint32_t *hist, uint32_t *row_total, hipStream_t stream)
+                      const int64_t *n_dev, int bits, bool drop, uint32_t drop_key, int64_t *kept_out,
+                      uint32_t *hist, uint32_t *row_total, hipStream_t stream)
 {
-    const int nblocks = (int)((n_max + kTile - 1) / kTile);
-    if (nblocks == 0 || bits <= 0) return hipSuccess;
+    const int nblocks = (int)((n_max + kRadixTile - 1) / kRadixTile);
     const int passes = radix_passes(bits);
+    if (nblocks == 0 || passes == 0) {
+        if (drop) k_fill_u32<<<1, kThreads, 0, stream>>>(reinterpret_cast<uint32_t *>(kept_out), 0u, 2);
+        return hipGetLastError();
+    }
     uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
     int shift = 0;
     for (int p = 0; p < passes; ++p) {
-        // spread the bits evenly over the passes (each <= 8)
+        // spread the bits evenly over the passes (each <= 8); the first pass
+        // drops, the later ones sort the kept items
         const int pbits = (bits - shift + (passes - p) - 1) / (passes - p);
-        k_radix_hist<<<nblocks, kThreads, 0, stream>>>(ki, n_max, n_dev, shift, pbits, hist, nblocks);
+        const bool pdrop = drop && p == 0;
+        const int64_t *pn = drop && p > 0 ? kept_out : n_dev;
+        k_radix_hist<<<nblocks, kThreads, 0, stream>>>(ki, n_max, pn, shift, pbits, pdrop, drop_key, hist, nblocks);
         k_radix_scan_rows<<<kBins, kThreads, 0, stream>>>(hist, nblocks, row_total);
-        k_radix_scatter<<<nblocks, kThreads, 0, stream>>>(ki, vi, ko, vo, n_max, n_dev, shift, pbits, hist,
-                                                          row_total, nblocks);
+        k_radix_scatter<<<nblocks, kThreads, 0, stream>>>(ki, vi, ko, vo, n_max, pn, shift, pbits, pdrop, drop_key,
+                                                          kept_out, hist, row_total, nblocks);
         shift += pbits;
         uint32_t *t;
         t = ki; ki = ko; ko = t;
@@ -555,8 +597,8 @@ size_t sched_item_count() { return 2 * sched_backward_heads() + 2 * kSchedBucket
 size_t sched_words() { return sched_item_count() + 4; }
 
 hipError_t launch_tile_ranges(const uint32_t *inst_tiles, const int64_t *counters, int64_t capacity,
-                              int64_t total_tiles, uint32_t split_len, uint2 *ranges, uint32_t *sched,
-                              uint32_t *work_order, hipStream_t stream)
+                              int64_t total_tiles, uint32_t split_min, uint32_t waves, uint2 *ranges,
+                              uint32_t *sched, uint32_t *work_order, hipStream_t stream)
 {
     // the ranges, queue heads and scheduling histograms were cleared by k_emit
     if (capacity > 0)
@@ -564,8 +606,8 @@ hipError_t launch_tile_ranges(const uint32_t *inst_tiles, const int64_t *counter
                                                                                                  capacity, total_tiles, ranges);
     const unsigned nb = (unsigned)((total_tiles + kThreads - 1) / kThreads);
     uint32_t *hist = sched + 2 * sched_backward_heads(), *cursor = hist + kSchedBuckets;
-    k_sched_hist<<<nb, kThreads, 0, stream>>>(ranges, total_tiles, split_len, hist);
-    k_sched_scatter<<<nb, kThreads, 0, stream>>>(ranges, total_tiles, split_len, hist, cursor,
+    k_sched_hist<<<nb, kThreads, 0, stream>>>(ranges, total_tiles, counters, split_min, waves, hist);
+    k_sched_scatter<<<nb, kThreads, 0, stream>>>(ranges, total_tiles, counters, split_min, waves, hist, cursor,
                                                  sched + sched_item_count(), work_order);
     return hipGetLastError();
 }

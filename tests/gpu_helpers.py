@@ -54,15 +54,17 @@ def render_with_ws(r, scene, cams, opts, capacity=None, flags=0):
 ID_MASK = (1 << 28) - 1
 
 
-def instance_lists(buf, lay, m, with_bands=False, keep_empty=False):
-    """Sorted instances (tile ids, Gaussian-view ids[, band bits]).  Box tiles
-    whose bands all miss the support carry the empty tile id
-    2^tile_bits - 1 and sort last; they are dropped unless keep_empty."""
+def listed_count(buf, lay):
+    """Instances left after the tile sort (box tiles whose row bands all miss
+    the support leave the sort)."""
+    return int(read(buf, lay.counters, 8, np.int64)[3])
+
+
+def instance_lists(buf, lay, with_bands=False):
+    """Sorted listed instances (tile ids, Gaussian-view ids[, band bits])."""
+    m = listed_count(buf, lay)
     tiles = read(buf, lay.inst_tiles, m, np.uint32).astype(np.int64)
     raw = read(buf, lay.inst_ids, m, np.uint32).astype(np.int64)
-    if not keep_empty:
-        listed = tiles != (1 << lay.tile_bits) - 1
-        tiles, raw = tiles[listed], raw[listed]
     ids = raw & ID_MASK
     if with_bands:
         return tiles, ids, raw >> 28
