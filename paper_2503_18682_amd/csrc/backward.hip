@@ -9,64 +9,21 @@
 // w = A2^T mu' (so g = w / c^2).  The compositing kernel therefore
 // accumulates dL/dM, and this kernel differentiates M, g, k0 = 1/mu_z,
 // ic2 = 1/c^2 and the projected centre with respect to (A, mu) without ever
-// differentiating the rotation R_{mu^ <- v}.  Evaluated in double precision.
+// differentiating the rotation R_{mu^ <- v}.  Geometry is evaluated in double
+// precision; the colour part in float32, as the forward computed it.
 #include "internal.h"
+#include "sh.h"
 
 namespace rgs {
 namespace {
 
-// Real SH basis and its gradient with respect to the (unnormalised) direction
-// components, degree <= 3, same convention as the forward kernel.
-template <int DEG>
-__device__ __forceinline__ void sh_basis_grad(double x, double y, double z, double *Y, double (*dY)[3])
-{
-    const double c0 = 0.28209479177387814, c1 = 0.48860251190291992;
-    const double c2a = 1.0925484305920792, c2b = 0.31539156525252005, c2c = 0.54627421529603959;
-    const double c3a = -0.59004358992664352, c3b = 2.8906114426405538, c3c = -0.45704579946446572;
-    const double c3d = 0.37317633259011540, c3e = 1.4453057213202769;
-    for (int k = 0; k < (DEG + 1) * (DEG + 1); ++k) dY[k][0] = dY[k][1] = dY[k][2] = 0.0;
-    Y[0] = c0;
-    if (DEG >= 1) {
-        Y[1] = -c1 * y; dY[1][1] = -c1;
-        Y[2] = c1 * z;  dY[2][2] = c1;
-        Y[3] = -c1 * x; dY[3][0] = -c1;
-    }
-    if (DEG >= 2) {
-        const double xx = x * x, yy = y * y, zz = z * z;
-        Y[4] = c2a * x * y;            dY[4][0] = c2a * y;       dY[4][1] = c2a * x;
-        Y[5] = -c2a * y * z;           dY[5][1] = -c2a * z;      dY[5][2] = -c2a * y;
-        Y[6] = c2b * (2 * zz - xx - yy); dY[6][0] = -2 * c2b * x; dY[6][1] = -2 * c2b * y; dY[6][2] = 4 * c2b * z;
-        Y[7] = -c2a * x * z;           dY[7][0] = -c2a * z;      dY[7][2] = -c2a * x;
-        Y[8] = c2c * (xx - yy);        dY[8][0] = 2 * c2c * x;   dY[8][1] = -2 * c2c * y;
-    }
-    if (DEG >= 3) {
-        const double xx = x * x, yy = y * y, zz = z * z;
-        Y[9] = c3a * y * (3 * xx - yy);
-        dY[9][0] = 6 * c3a * x * y; dY[9][1] = 3 * c3a * (xx - yy);
-        Y[10] = c3b * x * y * z;
-        dY[10][0] = c3b * y * z; dY[10][1] = c3b * x * z; dY[10][2] = c3b * x * y;
-        Y[11] = c3c * y * (4 * zz - xx - yy);
-        dY[11][0] = -2 * c3c * x * y; dY[11][1] = c3c * (4 * zz - xx - 3 * yy); dY[11][2] = 8 * c3c * y * z;
-        Y[12] = c3d * z * (2 * zz - 3 * xx - 3 * yy);
-        dY[12][0] = -6 * c3d * x * z; dY[12][1] = -6 * c3d * y * z; dY[12][2] = 3 * c3d * (2 * zz - xx - yy);
-        Y[13] = c3c * x * (4 * zz - xx - yy);
-        dY[13][0] = c3c * (4 * zz - 3 * xx - yy); dY[13][1] = -2 * c3c * x * y; dY[13][2] = 8 * c3c * x * z;
-        Y[14] = c3e * z * (xx - yy);
-        dY[14][0] = 2 * c3e * x * z; dY[14][1] = -2 * c3e * y * z; dY[14][2] = c3e * (xx - yy);
-        Y[15] = c3a * x * (xx - 3 * yy);
-        dY[15][0] = 3 * c3a * (xx - yy); dY[15][1] = -6 * c3a * x * y;
-    }
-}
-
-template <int DEG>
+// Geometry and opacity (the colour part is k_colour_bwd).
 __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const float *__restrict__ means, const float *__restrict__ log_scales, const float *__restrict__ quats,
-    const float *__restrict__ opacity_logits, const float *__restrict__ sh, int n, const DevView *__restrict__ views,
-    int n_views, const uint32_t *__restrict__ tile_counts, const float *__restrict__ record_grads,
-    float *__restrict__ g_means, float *__restrict__ g_log_scales, float *__restrict__ g_quats,
-    float *__restrict__ g_opacity, float *__restrict__ g_sh)
+    const float *__restrict__ opacity_logits, int n, const DevView *__restrict__ views, int n_views,
+    const uint32_t *__restrict__ tile_counts, const float *__restrict__ record_grads, float *__restrict__ g_means,
+    float *__restrict__ g_log_scales, float *__restrict__ g_quats, float *__restrict__ g_opacity)
 {
-    constexpr int NK = (DEG + 1) * (DEG + 1);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     bool any = false;
@@ -83,14 +40,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
     const double s[3] = {exp((double)log_scales[i]), exp((double)log_scales[n + i]), exp((double)log_scales[2 * n + i])};
     const double o = 1.0 / (1.0 + exp(-(double)opacity_logits[i]));
-    double shc[NK * 3];
-#pragma unroll
-    for (int k = 0; k < NK * 3; ++k) shc[k] = sh[(size_t)k * n + i];
 
     double dm[3] = {0, 0, 0}, dl[3] = {0, 0, 0}, dR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, da = 0.0;
-    double dsh[NK * 3];
-#pragma unroll
-    for (int k = 0; k < NK * 3; ++k) dsh[k] = 0.0;
 
     for (int v = 0; v < n_views; ++v) {
         const size_t idx = (size_t)v * n + i;
@@ -98,7 +49,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         const DevView &V = views[v];
         const float *gr = record_grads + idx * kGradFloats;
         const double gu0 = gr[0], gv0 = gr[1], gM00 = gr[2], gM01 = gr[3], gM11 = gr[4], ggx = gr[5], ggy = gr[6];
-        const double gk0 = gr[7], gic2 = gr[8], go = gr[9], gcol[3] = {gr[10], gr[11], gr[12]};
+        const double gk0 = gr[7], gic2 = gr[8], go = gr[9];
         const double *W = V.w2c;
         const double mu[3] = {W[0] * m[0] + W[1] * m[1] + W[2] * m[2] + W[3],
                               W[4] * m[0] + W[5] * m[1] + W[6] * m[2] + W[7],
@@ -167,24 +118,6 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         for (int c = 0; c < 3; ++c) dm[c] += W[c] * dmu[0] + W[4 + c] * dmu[1] + W[8 + c] * dmu[2];
         // prior opacity
         da += go * o * (1.0 - o);
-        // colour: SH coefficients and the view direction
-        const double d0 = m[0] - V.centre[0], d1 = m[1] - V.centre[1], d2 = m[2] - V.centre[2];
-        const double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        const double dir[3] = {d0 / dist, d1 / dist, d2 / dist};
-        double Y[NK], dY[NK][3];
-        sh_basis_grad<DEG>(dir[0], dir[1], dir[2], Y, dY);
-        double ddir[3] = {0, 0, 0};
-        for (int ch = 0; ch < 3; ++ch) {
-            double raw = 0.5;
-            for (int k = 0; k < NK; ++k) raw += Y[k] * shc[3 * k + ch];
-            if (!(raw > 0.0)) continue;
-            for (int k = 0; k < NK; ++k) {
-                dsh[3 * k + ch] += Y[k] * gcol[ch];
-                for (int j = 0; j < 3; ++j) ddir[j] += gcol[ch] * shc[3 * k + ch] * dY[k][j];
-            }
-        }
-        const double pd = ddir[0] * dir[0] + ddir[1] * dir[1] + ddir[2] * dir[2];
-        for (int j = 0; j < 3; ++j) dm[j] += (ddir[j] - dir[j] * pd) / dist;
     }
     // quaternion: dR/d(w,x,y,z) of the unit quaternion, then the normalisation
     const double J[9][4] = {{0, 0, -4 * y, -4 * z},       {-2 * z, 2 * y, 2 * x, -2 * w}, {2 * y, 2 * z, 2 * w, 2 * x},
@@ -201,8 +134,66 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         g_log_scales[(size_t)k * n + i] += (float)dl[k];
     }
     g_opacity[i] += (float)da;
+}
+
+// Colour: the SH coefficients and, through the view direction d = (m - C) /
+// |m - C|, the means.  The colour is recomputed in float32 as the forward
+// kernel computed it, so a channel clamped at zero there passes no gradient
+// here either.
+template <int DEG>
+__global__ __launch_bounds__(256) void k_colour_bwd(const float *__restrict__ means, const float *__restrict__ sh,
+                                                    int n, const DevView *__restrict__ views, int n_views,
+                                                    const uint32_t *__restrict__ tile_counts,
+                                                    const float *__restrict__ record_grads,
+                                                    float *__restrict__ g_means, float *__restrict__ g_sh)
+{
+    constexpr int NK = (DEG + 1) * (DEG + 1);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool any = false;
+    for (int v = 0; v < n_views; ++v) any = any || tile_counts[(size_t)v * n + i] != 0;
+    if (!any) return;
+    float c[NK * 3], dsh[NK * 3];
 #pragma unroll
-    for (int k = 0; k < NK * 3; ++k) g_sh[(size_t)k * n + i] += (float)dsh[k];
+    for (int k = 0; k < NK * 3; ++k) {
+        c[k] = sh[(size_t)k * n + i];
+        dsh[k] = 0.0f;
+    }
+    const double m[3] = {means[i], means[n + i], means[2 * n + i]};
+    double dm[3] = {0, 0, 0};
+    for (int v = 0; v < n_views; ++v) {
+        const size_t idx = (size_t)v * n + i;
+        if (tile_counts[idx] == 0) continue;
+        const DevView &V = views[v];
+        const float *gr = record_grads + idx * kGradFloats;
+        const double d0 = m[0] - V.centre[0], d1 = m[1] - V.centre[1], d2 = m[2] - V.centre[2];
+        const double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        const float dir[3] = {(float)(d0 / dist), (float)(d1 / dist), (float)(d2 / dist)};
+        float Y[NK], col[3];
+        sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
+        sh_colour<DEG>(Y, c, col);
+        // channels clamped at zero in the forward pass no gradient
+        float gcol[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) gcol[ch] = col[ch] > 0.0f ? gr[10 + ch] : 0.0f;
+        float wk[NK];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            wk[k] = 0.0f;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                dsh[3 * k + ch] += Y[k] * gcol[ch];
+                wk[k] += gcol[ch] * c[3 * k + ch];
+            }
+        }
+        float ddir[3];
+        sh_dir_grad<DEG>(dir[0], dir[1], dir[2], wk, ddir);
+        const double pd = (double)ddir[0] * dir[0] + (double)ddir[1] * dir[1] + (double)ddir[2] * dir[2];
+        for (int j = 0; j < 3; ++j) dm[j] += ((double)ddir[j] - dir[j] * pd) / dist;
+    }
+    for (int k = 0; k < 3; ++k) g_means[(size_t)k * n + i] += (float)dm[k];
+#pragma unroll
+    for (int k = 0; k < NK * 3; ++k) g_sh[(size_t)k * n + i] += dsh[k];
 }
 
 }  // namespace
@@ -215,10 +206,13 @@ hipError_t launch_preprocess_backward(const rgs_gaussians &g, const DevView *vie
     const int n = (int)g.n;
     if (n == 0) return hipSuccess;
     const dim3 grid((n + 255) / 256), block(256);
+    k_preprocess_bwd<<<grid, block, 0, stream>>>(g.means, g.log_scales, g.quats, g.opacity_logits, n, views, n_views,
+                                                 tile_counts, record_grads, gr.means, gr.log_scales, gr.quats,
+                                                 gr.opacity_logits);
+    // after k_preprocess_bwd on the same stream: both add into gr.means
 #define RGS_BWD(D)                                                                                                  \
-    k_preprocess_bwd<D><<<grid, block, 0, stream>>>(g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, n,      \
-                                                    views, n_views, tile_counts, record_grads, gr.means,            \
-                                                    gr.log_scales, gr.quats, gr.opacity_logits, gr.sh)
+    k_colour_bwd<D><<<grid, block, 0, stream>>>(g.means, g.sh, n, views, n_views, tile_counts, record_grads,        \
+                                                gr.means, gr.sh)
     switch (g.sh_degree) {
     case 0: RGS_BWD(0); break;
     case 1: RGS_BWD(1); break;

@@ -12,43 +12,13 @@
 
 #include "binning.h"
 #include "internal.h"
+#include "sh.h"
 
 #pragma clang fp contract(off)
 
 namespace rgs {
 namespace {
 
-// Orthonormal real spherical harmonics up to degree 3 (index l^2 + l + m) in
-// the sign convention of Gaussian-splatting colour models, evaluated in
-// float32 (the colour is stored as float32).
-template <int DEG>
-__device__ __forceinline__ void sh_basis(float x, float y, float z, float *Y)
-{
-    Y[0] = 0.28209479177387814f;
-    if (DEG >= 1) {
-        Y[1] = -0.48860251190291992f * y;
-        Y[2] = 0.48860251190291992f * z;
-        Y[3] = -0.48860251190291992f * x;
-    }
-    if (DEG >= 2) {
-        const float xx = x * x, yy = y * y, zz = z * z;
-        Y[4] = 1.0925484305920792f * x * y;
-        Y[5] = -1.0925484305920792f * y * z;
-        Y[6] = 0.31539156525252005f * (2.0f * zz - xx - yy);
-        Y[7] = -1.0925484305920792f * x * z;
-        Y[8] = 0.54627421529603959f * (xx - yy);
-    }
-    if (DEG >= 3) {
-        const float xx = x * x, yy = y * y, zz = z * z;
-        Y[9] = -0.59004358992664352f * y * (3.0f * xx - yy);
-        Y[10] = 2.8906114426405538f * x * y * z;
-        Y[11] = -0.45704579946446572f * y * (4.0f * zz - xx - yy);
-        Y[12] = 0.37317633259011540f * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
-        Y[13] = -0.45704579946446572f * x * (4.0f * zz - xx - yy);
-        Y[14] = 1.4453057213202769f * z * (xx - yy);
-        Y[15] = -0.59004358992664352f * x * (xx - 3.0f * yy);
-    }
-}
 
 __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ means,
                                                     const float *__restrict__ log_scales,
@@ -318,13 +288,9 @@ __global__ __launch_bounds__(256) void k_colour(const float *__restrict__ means,
         const DevView &V = views[v];
         const double d0 = m[0] - V.centre[0], d1 = m[1] - V.centre[1], d2 = m[2] - V.centre[2];
         const double dn = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        float Y[NK];
+        float Y[NK], col[3];
         sh_basis<DEG>((float)(d0 / dn), (float)(d1 / dn), (float)(d2 / dn), Y);
-        float col[3] = {0.5f, 0.5f, 0.5f};
-#pragma unroll
-        for (int k = 0; k < NK; ++k)
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) col[ch] += Y[k] * c[3 * k + ch];
+        sh_colour<DEG>(Y, c, col);
         float *rec = reinterpret_cast<float *>(records + idx * 4);
         for (int ch = 0; ch < 3; ++ch) rec[13 + ch] = col[ch] > 0.0f ? col[ch] : 0.0f;
     }
