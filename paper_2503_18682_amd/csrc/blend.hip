@@ -19,6 +19,11 @@
 // omega = o exp(-D/2) (eq. 2); a Gaussian contributes iff den > 0 and
 // omega >= p_min; alpha = min(omega, alpha_max); compositing (eq. 1) stops
 // before a Gaussian that would take T below t_eps.
+//
+// The loops read each record in a test form made when it is staged: with
+// K = log2(o / p_min) and s^2 = log2(e) / (2 K), H = s G and j = ic2 / s^2,
+// qs = |H delta|^2 = s^2 q and t = den^2 + qs j = den^2 + q / c^2, so the
+// exponent D log2(e) / 2 equals K qs / t and omega >= p_min reads qs <= t.
 #include <hip/hip_fp16.h>
 
 #include "internal.h"
@@ -28,50 +33,57 @@
 namespace rgs {
 namespace {
 
-struct Rec {
-    float u_hi, v_hi, u_lo, v_lo, G00, G01, G10, G11, gx, gy, k0, ic2, log2o, r, g, b;
-    uint32_t rows;  // first | last << 16 covered pixel row
+// Test form of a raster record for one tile (four float4 in LDS).  Positions
+// are taken relative to the corner of the 32 x 32 pixel block that holds the
+// tile: a tile of any supported shape lies inside one such block, so every
+// pixel gets the same arithmetic whatever the tile shape, and offsets from
+// the corner are small exact integers.
+//   [0] cx, cy, K, rows   projected centre minus the block corner;
+//                          K = log2(o / p_min); covered rows or band bits
+//   [1] H00 H01 H10 H11   H = s G
+//   [2] gx, gy, k0, j     j = ic2 / s^2
+//   [3] log2o, r, g, b
+struct TRec {
+    float cx, cy, K, H00, H01, H10, H11, gx, gy, k0, j, log2o, r, g, b;
+    uint32_t rows;  // first | last << 16 covered pixel row, or band bits
 };
 
 struct Frag {
-    float dx, dy, n0, n1, den, q, kq, t, rt, w;
+    float dx, dy, n0, n1, den, q, t, rt, w;
 };
 
-__device__ __forceinline__ Rec load_rec(const float4 *p)
+__device__ __forceinline__ TRec load_trec(const float4 *p)
 {
     const float4 a = p[0], b = p[1], c = p[2], d = p[3];
-    const uint32_t lo_bits = __float_as_uint(a.z);
-    const float2 lo = __half22float2(*reinterpret_cast<const __half2 *>(&lo_bits));
-    return Rec{a.x, a.y, lo.x, lo.y, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w, __float_as_uint(a.w)};
+    return TRec{a.x, a.y, a.z, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w, __float_as_uint(a.w)};
 }
+
+constexpr float kHalfLog2e = 0.72134752044448170f;  // log2(e) / 2
+constexpr float kTwoLn2 = 1.38629436111989061f;     // 2 / log2(e)
 
 // The per-fragment instruction sequence shared by the forward and the
 // backward kernel (explicit fma, no contraction), so both take identical
-// decisions.  frag_test evaluates the quad-plane coordinate and decides
-// whether the Gaussian contributes: den > 0 (tau > 0) and omega >= p_min,
-// i.e. D log2(e) / 2 <= log2(o / p_min) = K, tested as
-// (log2(e)/2) q <= K (den^2 + q / c^2) without a reciprocal or exponential.
-// frag_omega then finishes D and omega for accepted fragments only.
-constexpr float kHalfLog2e = 0.72134752044448170f;
-
-__device__ __forceinline__ bool frag_test(const Rec &R, float K, float pxc, float pyc, Frag &f)
+// decisions.  (pxr, pyr) is the pixel centre relative to the block corner;
+// a NaN pyr (a pixel that is done) fails every comparison.
+// frag_test decides whether the Gaussian contributes: den > 0 (tau > 0) and
+// omega >= p_min, i.e. qs <= t, without a reciprocal or exponential.
+// frag_omega then finishes omega = o 2^(-K qs / t) for accepted fragments.
+__device__ __forceinline__ bool frag_test(const TRec &R, float pxr, float pyr, Frag &f)
 {
-    f.dx = (pxc - R.u_hi) - R.u_lo;
-    f.dy = (pyc - R.v_hi) - R.v_lo;
-    f.n0 = __builtin_fmaf(R.G01, f.dy, R.G00 * f.dx);
-    f.n1 = __builtin_fmaf(R.G11, f.dy, R.G10 * f.dx);
+    f.dx = pxr - R.cx;
+    f.dy = pyr - R.cy;
+    f.n0 = __builtin_fmaf(R.H01, f.dy, R.H00 * f.dx);
+    f.n1 = __builtin_fmaf(R.H11, f.dy, R.H10 * f.dx);
     f.den = __builtin_fmaf(R.gy, f.dy, __builtin_fmaf(R.gx, f.dx, R.k0));
     f.q = __builtin_fmaf(f.n1, f.n1, f.n0 * f.n0);
-    f.t = __builtin_fmaf(f.q, R.ic2, f.den * f.den);
-    f.kq = kHalfLog2e * f.q;
-    return (f.den > 0.0f) & (f.kq <= K * f.t);
+    f.t = __builtin_fmaf(f.q, R.j, f.den * f.den);
+    return (f.den > 0.0f) & (f.q <= f.t);
 }
 
-// omega = o 2^(-D log2(e) / 2) with D = q / t.
-__device__ __forceinline__ void frag_omega(const Rec &R, Frag &f)
+__device__ __forceinline__ void frag_omega(const TRec &R, Frag &f)
 {
     f.rt = __builtin_amdgcn_rcpf(f.t);
-    f.w = __builtin_amdgcn_exp2f(__builtin_fmaf(f.kq, -f.rt, R.log2o));
+    f.w = __builtin_amdgcn_exp2f(__builtin_fmaf(R.K * f.q, -f.rt, R.log2o));
 }
 
 // Rows of the tile covered by a record, relative to the tile's first row, as
@@ -81,7 +93,7 @@ struct RowSpan {
     int r0, r1;
 };
 
-__device__ __forceinline__ RowSpan row_span(const Rec &R, int tile_row0)
+__device__ __forceinline__ RowSpan row_span(const TRec &R, int tile_row0)
 {
     const uint32_t rows = __builtin_amdgcn_readfirstlane(R.rows);
     return RowSpan{(int)(rows & 0xffffu) - tile_row0, (int)(rows >> 16) - tile_row0};
@@ -107,16 +119,15 @@ struct BlendParams {
     uint32_t n_records;
 };
 
-// Stage one record (four float4) for instance value `inst` (id | band bits).
-// An id outside the record array (never produced by the binning) is replaced
-// by a record whose den is negative everywhere.  When a tile has at most 4
-// culling bands the covered-rows word is not needed, and the instance's band
-// bits take its place.
-__device__ __forceinline__ void stage_record(float4 *dst, const float4 *__restrict__ records, uint32_t inst,
+// Raw record (four float4) of instance value `inst` (id | band bits),
+// fetched ahead of its conversion.  An id outside the record array (never
+// produced by the binning) gets a placeholder that cannot reach p_min.  When
+// a tile has at most 4 culling bands the covered-rows word is not needed,
+// and the instance's band bits take its place.
+__device__ __forceinline__ void fetch_record(float4 (&r)[4], const float4 *__restrict__ records, uint32_t inst,
                                              uint32_t n_records, bool bands_in_rows)
 {
     const uint32_t id = inst & kIdMask;
-    float4 r[4];
     if (id < n_records) {
         const float4 *src = records + (size_t)id * 4;
 #pragma unroll
@@ -128,8 +139,29 @@ __device__ __forceinline__ void stage_record(float4 *dst, const float4 *__restri
         r[3] = make_float4(-126.f, 0.f, 0.f, 0.f);
     }
     if (bands_in_rows) r[0].w = __uint_as_float(inst >> kIdBits);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) dst[c] = r[c];
+}
+
+// Writes the test form of raw record r for the tile whose block corner is
+// (x0, y0).  A record with K <= 0 in FP32 (which includes the
+// placeholder) cannot reach p_min and gets den = -1 everywhere.
+__device__ __forceinline__ void put_test_form(float4 *dst, const float4 (&r)[4], float x0, float y0,
+                                              float log2_pmin)
+{
+    const uint32_t lo_bits = __float_as_uint(r[0].z);
+    const float2 lo = __half22float2(*reinterpret_cast<const __half2 *>(&lo_bits));
+    const float K = r[3].x - log2_pmin;
+    const float rows = r[0].w;
+    if (K > 0.0f) {
+        const float s = __builtin_amdgcn_sqrtf(kHalfLog2e * __builtin_amdgcn_rcpf(K));
+        dst[0] = make_float4((r[0].x - x0) + lo.x, (r[0].y - y0) + lo.y, K, rows);
+        dst[1] = make_float4(s * r[1].x, s * r[1].y, s * r[1].z, s * r[1].w);
+        dst[2] = make_float4(r[2].x, r[2].y, r[2].z, (K * kTwoLn2) * r[2].w);
+    } else {
+        dst[0] = make_float4(0.f, 0.f, 1.f, rows);
+        dst[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        dst[2] = make_float4(0.f, 0.f, -1.f, 0.f);
+    }
+    dst[3] = r[3];
 }
 
 // Whether culling band k (rows [k LY, (k + 1) LY) of the tile) may hold a
@@ -170,34 +202,45 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
         const int local = tile - V.tile_base;
         const int tx = local % V.tiles_x, ty = local / V.tiles_x;
         const int px = tx * TW + lx;
-        const float pxc = (float)px + 0.5f;
-        float T[PPL], C0[PPL], C1[PPL], C2[PPL], pyc[PPL];
+        const int ox = (tx * TW) & ~31, oy = (ty * TH) & ~31;
+        const float x0 = (float)ox, y0 = (float)oy;
+        // pixel centres relative to the block corner; NaN marks a pixel that
+        // is outside the image, outside the work item, or done
+        const float pxr = (float)(px - ox) + 0.5f;
+        float T[PPL], C0[PPL], C1[PPL], C2[PPL], pyr[PPL];
         int last[PPL];
-        bool live[PPL];
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
             const int py = ty * TH + ly + k * LY;
-            pyc[k] = (float)py + 0.5f;
+            const bool on = k >= k_lo && k < k_hi && px < V.width && py < V.height;
+            pyr[k] = on ? (float)(py - oy) + 0.5f : __builtin_nanf("");
             T[k] = 1.0f;
             C0[k] = C1[k] = C2[k] = 0.0f;
             last[k] = 0;
-            live[k] = k >= k_lo && k < k_hi && px < V.width && py < V.height;
         }
         const uint2 rg = ranges[tile];
         bool wave_live = true;
-        // batch 0 goes straight to LDS; batch b+1 is prefetched into registers
+        // batch 0 goes straight to LDS; batch b+1 is fetched into registers
         // while batch b is composited
-        if (rg.x + lane < rg.y) stage_record(s_rec[wave][lane], records, inst_ids[rg.x + lane], P.n_records, PPL <= 4);
+        if (rg.x + lane < rg.y) {
+            const uint32_t inst = inst_ids[rg.x + lane];
+            float4 r[4];
+            fetch_record(r, records, inst, P.n_records, PPL <= 4);
+            put_test_form(s_rec[wave][lane], r, x0, y0, P.log2_pmin);
+        }
         for (uint32_t base = rg.x; base < rg.y && wave_live; base += 64) {
             const uint32_t nb = min(64u, rg.y - base);
             const uint32_t next = base + 64 + lane;
             const bool have_next = next < rg.y;
             float4 pre[4];
-            if (have_next) stage_record(pre, records, inst_ids[next], P.n_records, PPL <= 4);
+            if (have_next) {
+                float4 r[4];
+                fetch_record(r, records, inst_ids[next], P.n_records, PPL <= 4);
+                put_test_form(pre, r, x0, y0, P.log2_pmin);
+            }
             lds_wave_sync();
             for (uint32_t j = 0; j < nb; ++j) {
-                const Rec R = load_rec(s_rec[wave][j]);
-                const float K = R.log2o - P.log2_pmin;
+                const TRec R = load_trec(s_rec[wave][j]);
                 const RowSpan span = row_span(R, ty * TH);
                 const uint32_t bands = __builtin_amdgcn_readfirstlane(R.rows);
                 const int idx = (int)(base - rg.x + j + 1);
@@ -208,7 +251,7 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
                     // every lane evaluates the test; results are kept by selection
                     // (the values are those of a branch per lane, bit for bit)
                     Frag f;
-                    const bool hit = frag_test(R, K, pxc, pyc[k], f) & live[k];
+                    const bool hit = frag_test(R, pxr, pyr[k], f);
                     if (__ballot(hit) == 0) continue;
                     frag_omega(R, f);
                     const float a = fminf(f.w, P.alpha_max);
@@ -222,14 +265,14 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
                     C2[k] = __builtin_fmaf(wt, R.b, C2[k]);
                     T[k] = take ? Tn : T[k];
                     last[k] = take ? idx : last[k];
-                    live[k] = live[k] & !stop;
+                    pyr[k] = stop ? __builtin_nanf("") : pyr[k];
                     stopped |= stop;
                 }
                 // a lane finished: leave the tile once no pixel is live
                 if (__ballot(stopped) != 0) {
                     bool any = false;
 #pragma unroll
-                    for (int k = 0; k < PPL; ++k) any = any || live[k];
+                    for (int k = 0; k < PPL; ++k) any = any || (pyr[k] == pyr[k]);
                     if (__ballot(any) == 0) {
                         wave_live = false;
                         break;
@@ -328,15 +371,17 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
         const int local = tile - V.tile_base;
         const int tx = local % V.tiles_x, ty = local / V.tiles_x;
         const int px = tx * TW + lx;
-        const float pxc = (float)px + 0.5f;
+        const int ox = (tx * TW) & ~31, oy = (ty * TH) & ~31;
+        const float x0 = (float)ox, y0 = (float)oy;
+        const float pxr = (float)(px - ox) + 0.5f;
         const size_t plane = (size_t)V.width * V.height;
-        float T[PPL], S[PPL], g0[PPL], g1[PPL], g2[PPL], pyc[PPL];
+        float T[PPL], S[PPL], g0[PPL], g1[PPL], g2[PPL], pyr[PPL];
         int last[PPL];
         int maxlast = 0;
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
             const int py = ty * TH + ly + k * LY;
-            pyc[k] = (float)py + 0.5f;
+            pyr[k] = (float)(py - oy) + 0.5f;
             T[k] = 1.0f;
             S[k] = 0.0f;
             g0[k] = g1[k] = g2[k] = 0.0f;
@@ -363,13 +408,14 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                 const uint32_t v = inst_ids[rg.x + lo + lane];
                 const uint32_t id = v & kIdMask;
                 s_id[wave][lane] = id < P.n_records ? id : 0xffffffffu;
-                stage_record(s_rec[wave][lane], records, v, P.n_records, PPL <= 4);
+                float4 r[4];
+                fetch_record(r, records, v, P.n_records, PPL <= 4);
+                put_test_form(s_rec[wave][lane], r, x0, y0, P.log2_pmin);
             }
             lds_wave_sync();
             for (int jj = nb - 1; jj >= 0; --jj) {
                 const int j = lo + jj;
-                const Rec R = load_rec(s_rec[wave][jj]);
-                const float K = R.log2o - P.log2_pmin;
+                const TRec R = load_trec(s_rec[wave][jj]);
                 const RowSpan span = row_span(R, ty * TH);
                 const uint32_t bands = __builtin_amdgcn_readfirstlane(R.rows);
                 const float inv_o = __builtin_amdgcn_exp2f(-R.log2o);
@@ -381,7 +427,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                     if (k < k_lo || k >= k_hi || !band_open<PPL, LY>(bands, span, k)) continue;
                     if (j >= last[k]) continue;
                     Frag f;
-                    if (!frag_test(R, K, pxc, pyc[k], f)) continue;
+                    if (!frag_test(R, pxr, pyr[k], f)) continue;
                     frag_omega(R, f);
                     hit = true;
                     const float a = fminf(f.w, P.alpha_max);
@@ -399,6 +445,10 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                         dop += dL_da * f.w * inv_o;
                         const float dL_dD = -0.5f * f.w * dL_da;
                         const float rt2 = f.rt * f.rt;
+                        // with the test form's qs = s^2 q in place of q, dL/dden
+                        // and the sums through it (dk0, dg, du0, dv0) come out
+                        // times s^2 and dic2 times s^4; they are rescaled once per
+                        // record below
                         const float dL_dq = dL_dD * (f.den * f.den) * rt2;
                         const float dL_dden = dL_dD * (-2.0f * f.q * f.den) * rt2;
                         dic2 += dL_dD * (-(f.q * f.q)) * rt2;
@@ -408,8 +458,10 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                         dk0 += dL_dden;
                         dgx += dL_dden * f.dx;
                         dgy += dL_dden * f.dy;
-                        const float dq_ddx = 2.0f * (R.G00 * f.n0 + R.G10 * f.n1);
-                        const float dq_ddy = 2.0f * (R.G01 * f.n0 + R.G11 * f.n1);
+                        // dq/ddelta = 2 G^T G delta = 2 H^T n / s^2 (the 1 / s^2 is
+                        // part of the rescaling)
+                        const float dq_ddx = 2.0f * (R.H00 * f.n0 + R.H10 * f.n1);
+                        const float dq_ddy = 2.0f * (R.H01 * f.n0 + R.H11 * f.n1);
                         du0 -= dL_dq * dq_ddx + dL_dden * R.gx;
                         dv0 -= dL_dq * dq_ddy + dL_dden * R.gy;
                     }
@@ -419,9 +471,11 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                 const float sum = wave_sum16(vals, lane);
                 const int c = wave_sum16_index(lane);
                 const uint32_t rid = s_id[wave][jj];
+                const float is2 = R.K * kTwoLn2;  // 1 / s^2
+                const float unit = c == 8 ? is2 * is2 : (c <= 1 || (c >= 5 && c <= 7)) ? is2 : 1.0f;
                 // one lane per gradient component adds it to the record's accumulators
                 if ((lane & 3) == 0 && c < 13 && rid != 0xffffffffu)
-                    atomicAdd(record_grads + (size_t)rid * kGradFloats + c, sum);
+                    atomicAdd(record_grads + (size_t)rid * kGradFloats + c, sum * unit);
             }
             lds_wave_sync();
         }
