@@ -50,15 +50,27 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
 
     // Sigma = R S^2 R^T in the world frame: rotation of the unit quaternion,
     // s = exp(l), prior opacity o = sigmoid(a).
-    double R[9], s[3], o = 0.0;
+    // Divisions are taken as products with one reciprocal wherever a value is
+    // divided more than once: a double division is a long instruction sequence,
+    // and the extra rounding (a few units in the last place of a double) is
+    // far below every decision margin of the integer outputs.
+    double R[9], s[3], is[3], o = 0.0;
     {
-        const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+        const double iq = 1.0 / qn;
+        const double w = q[0] * iq, x = q[1] * iq, y = q[2] * iq, z = q[3] * iq;
         R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
         R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
         R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
-        for (int k = 0; k < 3; ++k) s[k] = exp((double)lf[k]);
+        for (int k = 0; k < 3; ++k) {
+            s[k] = exp((double)lf[k]);
+            is[k] = 1.0 / s[k];
+        }
         o = 1.0 / (1.0 + exp(-(double)af));
     }
+    // support cut-off (eq. 3) and the record's log2 opacity; the MIP transform
+    // changes the opacity per view and recomputes them
+    const double kappa_o = -2.0 * log(opt.p_min / o);
+    const float log2o_o = (float)log2(o);
 
     for (int v = 0; v < n_views; ++v) {
         const DevView &V = views[v];
@@ -77,8 +89,9 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
             for (int r = 0; r < 3; ++r)
                 for (int c = 0; c < 3; ++c)
                     Rp[3 * r + c] = W[4 * r] * R[c] + W[4 * r + 1] * R[3 + c] + W[4 * r + 2] * R[6 + c];
-            double sv[3] = {s[0], s[1], s[2]};
-            double ov = o;
+            double sv[3] = {s[0], s[1], s[2]}, isv[3] = {is[0], is[1], is[2]};
+            double kappa = kappa_o;
+            float log2o = log2o_o;
             double ml[3];  // R_p^T mu: centre in the Gaussian's own axes
             for (int c = 0; c < 3; ++c) ml[c] = Rp[c] * mu[0] + Rp[3 + c] * mu[1] + Rp[6 + c] * mu[2];
             if (opt.mip) {
@@ -87,36 +100,43 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                 // sqrt(|Sigma| c^2 / (|Sigma^| c^^2)).
                 const double tb = sqrt(mu[0] * mu[0] + mu[1] * mu[1] + mu[2] * mu[2]);
                 const double sig2 = opt.mip_sigma2_px / (V.fx * V.fy);
-                double det = 1.0, deth = 1.0, c2p = 0.0, c2h = 0.0, sh2[3];
+                double det = 1.0, deth = 1.0, c2p = 0.0, c2h = 0.0, sh2[3], ish2[3];
                 for (int k = 0; k < 3; ++k) {
                     const double s2 = sv[k] * sv[k];
                     sh2[k] = s2 + sig2 * tb * tb;
+                    ish2[k] = 1.0 / sh2[k];
                     det *= s2;
                     deth *= sh2[k];
-                    c2p += ml[k] * ml[k] / s2;
-                    c2h += ml[k] * ml[k] / sh2[k];
+                    c2p += ml[k] * ml[k] * (isv[k] * isv[k]);
+                    c2h += ml[k] * ml[k] * ish2[k];
                 }
-                ov = ov * sqrt(det * c2p / (deth * c2h));
-                for (int k = 0; k < 3; ++k) sv[k] = sqrt(sh2[k]);
+                const double ov = o * sqrt(det * c2p / (deth * c2h));
+                for (int k = 0; k < 3; ++k) {
+                    sv[k] = sqrt(sh2[k]);
+                    isv[k] = sv[k] * ish2[k];
+                }
+                kappa = -2.0 * log(opt.p_min / ov);
+                log2o = (float)log2(ov);
             }
             // support cut-off (eq. 3) and the camera-inside skip (eq. 6)
-            const double kappa = -2.0 * log(opt.p_min / ov);
             if (!(kappa > 0.0)) break;
-            const double mw[3] = {ml[0] / sv[0], ml[1] / sv[1], ml[2] / sv[2]};
+            const double mw[3] = {ml[0] * isv[0], ml[1] * isv[1], ml[2] * isv[2]};
             const double c2 = mw[0] * mw[0] + mw[1] * mw[1] + mw[2] * mw[2];
             if (!(c2 > kappa)) break;
 
             // Sec. 4.1: whitened unit centre, b, R_{mu^ <- v} (App. A.1)
             const double c = sqrt(c2);
-            const double muh[3] = {mw[0] / c, mw[1] / c, mw[2] / c};
-            const double b = sqrt(1.0 - kappa / c2);
+            const double ic = 1.0 / c, ic2 = 1.0 / c2;
+            const double muh[3] = {mw[0] * ic, mw[1] * ic, mw[2] * ic};
+            const double b = sqrt(1.0 - kappa * ic2);
             double Rv[9];
             {
                 const double sgn = muh[2] >= 0.0 ? 1.0 : -1.0;  // align to v or to -v
                 const double a3[3] = {muh[0], muh[1], muh[2] + sgn};
                 const double a2 = a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2];
+                const double t2 = 2.0 / a2;
                 for (int r = 0; r < 3; ++r)
-                    for (int cc = 0; cc < 3; ++cc) Rv[3 * r + cc] = 2.0 * a3[r] * a3[cc] / a2 - (r == cc ? 1.0 : 0.0);
+                    for (int cc = 0; cc < 3; ++cc) Rv[3 * r + cc] = t2 * a3[r] * a3[cc] - (r == cc ? 1.0 : 0.0);
                 if (sgn < 0.0)  // right-multiply by P = diag(-1, 1, -1)
                     for (int r = 0; r < 3; ++r) {
                         Rv[3 * r] = -Rv[3 * r];
@@ -143,13 +163,10 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
             if (!(2.0 * rad <= 1e-6 * lmax)) {
                 const double v1x = Bh, v1y = lmax - Ba, v2x = lmax - Bd, v2y = Bh;
                 const double n1 = sqrt(v1x * v1x + v1y * v1y), n2 = sqrt(v2x * v2x + v2y * v2y);
-                if (n1 >= n2) {
-                    u1x = v1x / n1;
-                    u1y = v1y / n1;
-                } else {
-                    u1x = v2x / n2;
-                    u1y = v2y / n2;
-                }
+                const bool first = n1 >= n2;
+                const double inv = 1.0 / (first ? n1 : n2);
+                u1x = (first ? v1x : v2x) * inv;
+                u1y = (first ? v1y : v2y) * inv;
             }
             const double u0x = -u1y, u0y = u1x;
             // quad vertices V_k = mu + Q_{0:2} U (sqrt(kappa)/b) O_k (eq. 15)
@@ -168,8 +185,9 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                 const double Vy = QU[2] * z0 + QU[3] * z1 + mu[1];
                 const double Vz = QU[4] * z0 + QU[5] * z1 + mu[2];
                 if (!(Vz > 0.0)) all_front = false;
-                const double u = V.fx * Vx / Vz + V.cx;
-                const double vv = V.fy * Vy / Vz + V.cy;
+                const double iz = 1.0 / Vz;
+                const double u = V.fx * Vx * iz + V.cx;
+                const double vv = V.fy * Vy * iz + V.cy;
                 umin = fmin(umin, u);
                 umax = fmax(umax, u);
                 vmin = fmin(vmin, vv);
@@ -193,28 +211,29 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
 
             // ---- raster record (float32) ----
             // projected centre as a (hi, lo) float pair
-            const double u_c = V.fx * mu[0] / mu[2] + V.cx;
-            const double v_c = V.fy * mu[1] / mu[2] + V.cy;
+            const double k0 = 1.0 / mu[2];
+            const double u_c = V.fx * mu[0] * k0 + V.cx;
+            const double v_c = V.fy * mu[1] * k0 + V.cy;
             const float u_hi = (float)u_c, v_hi = (float)v_c;
             const float u_lo = (float)(u_c - (double)u_hi), v_lo = (float)(v_c - (double)v_hi);
             // A2 = (S^-1 R_p^T)[:, 0:2] diag(1/fx, 1/fy): a pixel offset delta moves
             // the whitened ray direction by A2 delta.
             double A2[3][2];
+            const double ifx = 1.0 / V.fx, ify = 1.0 / V.fy;
             for (int k = 0; k < 3; ++k) {
-                A2[k][0] = Rp[k] / sv[k] / V.fx;
-                A2[k][1] = Rp[3 + k] / sv[k] / V.fy;
+                A2[k][0] = Rp[k] * isv[k] * ifx;
+                A2[k][1] = Rp[3 + k] * isv[k] * ify;
             }
             // G = R_v[:, 0:2]^T A2 maps delta to the quad-plane offset (times den)
             double G[2][2];
             for (int r = 0; r < 2; ++r)
                 for (int cc = 0; cc < 2; ++cc)
                     G[r][cc] = Rv[r] * A2[0][cc] + Rv[3 + r] * A2[1][cc] + Rv[6 + r] * A2[2][cc];
-            const double gx = (A2[0][0] * mw[0] + A2[1][0] * mw[1] + A2[2][0] * mw[2]) / c2;
-            const double gy = (A2[0][1] * mw[0] + A2[1][1] * mw[1] + A2[2][1] * mw[2]) / c2;
+            const double gx = (A2[0][0] * mw[0] + A2[1][0] * mw[1] + A2[2][0] * mw[2]) * ic2;
+            const double gy = (A2[0][1] * mw[0] + A2[1][1] * mw[1] + A2[2][1] * mw[2]) * ic2;
             // support ellipse in pixel offsets; list the tiles whose row bands meet it
             Conic C;
             {
-                const double k0 = 1.0 / mu[2];
                 const double M00 = G[0][0] * G[0][0] + G[1][0] * G[1][0];
                 const double M01 = G[0][0] * G[0][1] + G[1][0] * G[1][1];
                 const double M11 = G[0][1] * G[0][1] + G[1][1] * G[1][1];
@@ -239,8 +258,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
             float4 *rec = records + idx * 4;
             rec[0] = make_float4(u_hi, v_hi, __uint_as_float(lo_bits), __uint_as_float(rows));
             rec[1] = make_float4((float)G[0][0], (float)G[0][1], (float)G[1][0], (float)G[1][1]);
-            rec[2] = make_float4((float)gx, (float)gy, (float)(1.0 / mu[2]), (float)(1.0 / c2));
-            rec[3] = make_float4((float)log2(ov), 0.0f, 0.0f, 0.0f);  // colour: k_colour
+            rec[2] = make_float4((float)gx, (float)gy, (float)k0, (float)ic2);
+            rec[3] = make_float4(log2o, 0.0f, 0.0f, 0.0f);  // colour: k_colour
             conics[idx] = C;
         } while (false);
         depth_keys[idx] = cnt ? key : 0xffffffffu;
