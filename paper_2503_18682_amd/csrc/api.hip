@@ -24,7 +24,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t counters, views, records, keys_a, keys_b, order_a, order_b, boxes, conics, tile_counts, offsets, block_sums;
+    size_t counters, views, colours, records, keys_a, keys_b, order_a, order_b, boxes, conics, tile_counts, offsets, block_sums;
     size_t inst_tiles_a, inst_tiles_b, inst_ids_a, inst_ids_b, hist, row_total, ranges, sched, tile_order;
     size_t row_offsets, row_owner;
     size_t record_grads, total;
@@ -176,6 +176,7 @@ rgs_status compute_layout(rgs_context *ctx, int64_t n, const rgs_camera *cams, i
     };
     L.counters = take(8 * sizeof(int64_t));
     L.views = take(sizeof(DevView) * n_views);
+    L.colours = take(NV * sizeof(float4));
     L.records = take(NV * kRecordFloats * sizeof(float));
     L.keys_a = take(NV * 4);
     L.keys_b = take(NV * 4);
@@ -341,6 +342,7 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
     uint32_t *tiles_alt = at<uint32_t>(ws, tpasses % 2 ? L.inst_tiles_a : L.inst_tiles_b);
     uint32_t *ids_in = at<uint32_t>(ws, tpasses % 2 ? L.inst_ids_b : L.inst_ids_a);
     uint32_t *ids_alt = at<uint32_t>(ws, tpasses % 2 ? L.inst_ids_a : L.inst_ids_b);
+    float4 *colours = at<float4>(ws, L.colours);
     float4 *records = at<float4>(ws, L.records);
     uint2 *boxes = at<uint2>(ws, L.boxes);
     Conic *conics = at<Conic>(ws, L.conics);
@@ -352,8 +354,8 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
     const uint32_t *tile_order = at<uint32_t>(ws, L.tile_order);
 
     Timer tm(ctx, stream, timing, ST_PRE);
-    RGS_HIP(ctx, launch_preprocess(g, views, n_views, dopt, records, keys_in, ord_in, boxes, conics, tile_counts,
-                                   stream));
+    RGS_HIP(ctx, launch_preprocess(g, views, n_views, dopt, colours, records, keys_in, ord_in, boxes, conics,
+                                   tile_counts, stream));
     tm.mark(ST_PRE);
     // counters: [0] box instances, [1] capacity, [2] tile rows, [3] listed instances, [4] kept views
     int64_t *listed = counters + 3, *kept = counters + 4;

@@ -166,9 +166,9 @@ __global__ __launch_bounds__(256) void k_colour_bwd(const float *__restrict__ me
         if (tile_counts[idx] == 0) continue;
         const DevView &V = views[v];
         const float *gr = record_grads + idx * kGradFloats;
-        const double d0 = m[0] - V.centre[0], d1 = m[1] - V.centre[1], d2 = m[2] - V.centre[2];
-        const double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        const float dir[3] = {(float)(d0 / dist), (float)(d1 / dist), (float)(d2 / dist)};
+        float dir[3];
+        double dist;
+        view_dir(m, V.centre, dir, &dist);
         float Y[NK], col[3];
         sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
         sh_colour<DEG>(Y, c, col);

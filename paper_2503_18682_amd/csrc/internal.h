@@ -56,11 +56,12 @@ struct TileShape {
 };
 
 // ---- launchers (each enqueues on `stream`, returns hipError_t) -----------
-// Writes per Gaussian-view: record, depth key (0xffffffff when culled), the
-// identity order, pixel box, support conic, and the number of tiles of the
-// box (0 when culled).
+// Writes per Gaussian-view: the colour staging entry (colours, float4: r, g,
+// b, non-finite-coefficient flag), record, depth key (0xffffffff when
+// culled), the identity order, pixel box, support conic, and the number of
+// tiles of the box (0 when culled).
 hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n_views, const DevOptions &opt,
-                             float4 *records, uint32_t *depth_keys, uint32_t *order, uint2 *boxes,
+                             float4 *colours, float4 *records, uint32_t *depth_keys, uint32_t *order, uint2 *boxes,
                              Conic *conics, uint32_t *tile_counts, hipStream_t stream);
 
 // Stable LSD radix sort of (key, value) pairs on bits [0, bits), 8-bit digits

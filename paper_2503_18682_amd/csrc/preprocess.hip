@@ -26,6 +26,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                                                     const float *__restrict__ opacity_logits,
                                                     int n,
                                                     const DevView *__restrict__ views, int n_views, DevOptions opt,
+                                                    const float4 *__restrict__ colours,
                                                     float4 *__restrict__ records, uint32_t *__restrict__ depth_keys,
                                                     uint32_t *__restrict__ order, uint2 *__restrict__ boxes,
                                                     Conic *__restrict__ conics, uint32_t *__restrict__ tile_counts)
@@ -42,8 +43,9 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
     for (int k = 0; k < 3; ++k) ok = ok && isfinite((float)m[k]) && isfinite(lf[k]);
 #pragma unroll
     for (int k = 0; k < 4; ++k) ok = ok && isfinite(qf[k]);
-    // colour coefficients are read (and checked) by k_colour once a view keeps
-    // the Gaussian; a non-finite coefficient culls it in every view
+    // the colour kernel flags a non-finite colour coefficient (culled in
+    // every view)
+    ok = ok && colours[i].w == 0.0f;
     const double q[4] = {qf[0], qf[1], qf[2], qf[3]};
     const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     ok = ok && qn > 0.0;
@@ -259,7 +261,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
             rec[0] = make_float4(u_hi, v_hi, __uint_as_float(lo_bits), __uint_as_float(rows));
             rec[1] = make_float4((float)G[0][0], (float)G[0][1], (float)G[1][0], (float)G[1][1]);
             rec[2] = make_float4((float)gx, (float)gy, (float)k0, (float)ic2);
-            rec[3] = make_float4(log2o, 0.0f, 0.0f, 0.0f);  // colour: k_colour
+            const float4 col = colours[idx];
+            rec[3] = make_float4(log2o, col.x, col.y, col.z);
             conics[idx] = C;
         } while (false);
         depth_keys[idx] = cnt ? key : 0xffffffffu;
@@ -268,23 +271,21 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
     }
 }
 
-// View-dependent colour of every kept Gaussian-view (one thread per
-// Gaussian; its coefficients are read once, coalesced across the wave):
-// max(0, SH(direction camera centre -> mean) + 1/2) into the record.  A
-// Gaussian with a non-finite coefficient is culled in every view (its key
-// and tile count are cleared before the depth sort).
+// View-dependent colour of every Gaussian-view (one thread per Gaussian; its
+// coefficients are read once, coalesced across the wave), run before the
+// geometry: colours[v n + i] = (max(0, SH(direction camera centre -> mean) +
+// 1/2), flag) with flag 0, or NaN when a coefficient is not finite (the
+// Gaussian is then culled in every view).  The geometry kernel copies the
+// colour of each kept view into its record, so every record is written as
+// whole 64-byte lines.
 template <int DEG>
 __global__ __launch_bounds__(256) void k_colour(const float *__restrict__ means, const float *__restrict__ sh, int n,
                                                 const DevView *__restrict__ views, int n_views,
-                                                float4 *__restrict__ records, uint32_t *__restrict__ depth_keys,
-                                                uint32_t *__restrict__ tile_counts)
+                                                float4 *__restrict__ colours)
 {
     constexpr int NK = (DEG + 1) * (DEG + 1);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    bool any = false;
-    for (int v = 0; v < n_views; ++v) any = any || tile_counts[(size_t)v * n + i] != 0u;
-    if (!any) return;
     float c[NK * 3];
     bool sh_ok = true;
 #pragma unroll
@@ -292,42 +293,28 @@ __global__ __launch_bounds__(256) void k_colour(const float *__restrict__ means,
         c[k] = sh[(size_t)k * n + i];
         sh_ok = sh_ok && isfinite(c[k]);
     }
-    if (!sh_ok) {
-        for (int v = 0; v < n_views; ++v) {
-            const size_t idx = (size_t)v * n + i;
-            depth_keys[idx] = 0xffffffffu;
-            tile_counts[idx] = 0u;
-        }
-        return;
-    }
+    const float flag = sh_ok ? 0.0f : __builtin_nanf("");
     const double m[3] = {means[i], means[n + i], means[2 * n + i]};
     for (int v = 0; v < n_views; ++v) {
-        const size_t idx = (size_t)v * n + i;
-        if (tile_counts[idx] == 0u) continue;
-        const DevView &V = views[v];
-        const double d0 = m[0] - V.centre[0], d1 = m[1] - V.centre[1], d2 = m[2] - V.centre[2];
-        const double dn = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        float Y[NK], col[3];
-        sh_basis<DEG>((float)(d0 / dn), (float)(d1 / dn), (float)(d2 / dn), Y);
+        float dir[3], Y[NK], col[3];
+        double dist;
+        view_dir(m, views[v].centre, dir, &dist);
+        sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
         sh_colour<DEG>(Y, c, col);
-        float *rec = reinterpret_cast<float *>(records + idx * 4);
-        for (int ch = 0; ch < 3; ++ch) rec[13 + ch] = col[ch] > 0.0f ? col[ch] : 0.0f;
+        colours[(size_t)v * n + i] = make_float4(fmaxf(col[0], 0.0f), fmaxf(col[1], 0.0f), fmaxf(col[2], 0.0f), flag);
     }
 }
 
 }  // namespace
 
 hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n_views, const DevOptions &opt,
-                             float4 *records, uint32_t *depth_keys, uint32_t *order, uint2 *boxes,
+                             float4 *colours, float4 *records, uint32_t *depth_keys, uint32_t *order, uint2 *boxes,
                              Conic *conics, uint32_t *tile_counts, hipStream_t stream)
 {
     const int n = (int)g.n;
     if (n == 0) return hipSuccess;
     const dim3 grid((n + 255) / 256), block(256);
-    k_preprocess<<<grid, block, 0, stream>>>(g.means, g.log_scales, g.quats, g.opacity_logits, n, views, n_views, opt,
-                                             records, depth_keys, order, boxes, conics, tile_counts);
-#define RGS_COL(D) \
-    k_colour<D><<<grid, block, 0, stream>>>(g.means, g.sh, n, views, n_views, records, depth_keys, tile_counts)
+#define RGS_COL(D) k_colour<D><<<grid, block, 0, stream>>>(g.means, g.sh, n, views, n_views, colours)
     switch (g.sh_degree) {
     case 0: RGS_COL(0); break;
     case 1: RGS_COL(1); break;
@@ -335,6 +322,8 @@ hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n
     default: RGS_COL(3); break;
     }
 #undef RGS_COL
+    k_preprocess<<<grid, block, 0, stream>>>(g.means, g.log_scales, g.quats, g.opacity_logits, n, views, n_views, opt,
+                                             colours, records, depth_keys, order, boxes, conics, tile_counts);
     return hipGetLastError();
 }
 

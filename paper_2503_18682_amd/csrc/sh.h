@@ -6,6 +6,22 @@
 
 namespace rgs {
 
+// Unit view direction camera centre -> mean as float32 (difference and norm
+// in double, one reciprocal); *dist receives the distance.  Shared by the
+// colour kernel and its backward so both evaluate the same colour.
+__device__ __forceinline__ void view_dir(const double (&m)[3], const double (&centre)[3], float (&dir)[3],
+                                         double *dist)
+{
+#pragma clang fp contract(off)
+    const double d0 = m[0] - centre[0], d1 = m[1] - centre[1], d2 = m[2] - centre[2];
+    const double dn = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    const double inv = 1.0 / dn;
+    dir[0] = (float)(d0 * inv);
+    dir[1] = (float)(d1 * inv);
+    dir[2] = (float)(d2 * inv);
+    *dist = dn;
+}
+
 // Orthonormal real spherical harmonics up to degree 3 (index l^2 + l + m) in
 // the sign convention of Gaussian-splatting colour models, evaluated in
 // float32 (the colour is stored as float32).
