@@ -8,6 +8,8 @@
 // depth key (stable, so equal depths keep id order), instances are emitted in
 // that order, and a stable radix sort on the tile id alone (13-20 bits) groups
 // them by tile without disturbing the depth order inside a tile.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace rgs {
@@ -64,7 +66,9 @@ __device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t x, uint32_t *s
 
 // ---------------------------------------------------------------- radix sort
 // Digit histogram of one block's items; with `drop`, keys equal to drop_key
-// are left out (they leave the sort in this pass).
+// are left out (they leave the sort in this pass).  Blocks past the
+// device-side count write nothing: the row scan and the scatter only look at
+// the first ceil(n / kRadixTile) blocks.
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restrict__ keys, int64_t n_max,
                                                          const int64_t *__restrict__ n_dev, int shift, int bits,
                                                          bool drop, uint32_t drop_key, uint32_t *__restrict__ hist,
@@ -72,13 +76,14 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restr
 {
     __shared__ uint32_t cnt[kWaves][kBins];
     const int tid = threadIdx.x, wave = tid >> 6;
+    const int64_t n = clamp_count(n_dev, n_max);
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    if (base >= n) return;  // uniform per block
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) cnt[w][tid] = 0;
     __syncthreads();
-    const int64_t n = clamp_count(n_dev, n_max);
-    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
     const uint32_t mask = (1u << bits) - 1u;
-    if (base < n) {
+    {
 #pragma unroll
         for (int j = 0; j < kRadixItems; ++j) {
             const int64_t idx = base + (int64_t)j * kThreads + tid;
@@ -92,19 +97,23 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restr
     hist[(size_t)tid * nblocks + blockIdx.x] = cnt[0][tid] + cnt[1][tid] + cnt[2][tid] + cnt[3][tid];
 }
 
-// Exclusive scan of each digit's row hist[d][0..nblocks) (one block per digit).
+// Exclusive scan of each digit's row hist[d][0..nb) (one block per digit)
+// over the nb = ceil(n / kRadixTile) blocks that hold items.
 __global__ __launch_bounds__(kThreads) void k_radix_scan_rows(uint32_t *__restrict__ hist, int nblocks,
+                                                              int64_t n_max, const int64_t *__restrict__ n_dev,
                                                               uint32_t *__restrict__ row_total)
 {
     __shared__ uint32_t smem[kWaves];
+    const int64_t n = clamp_count(n_dev, n_max);
+    const int nb = (int)std::min<int64_t>((n + kRadixTile - 1) / kRadixTile, nblocks);
     uint32_t *row = hist + (size_t)blockIdx.x * nblocks;
     uint32_t carry = 0;
-    for (int base = 0; base < nblocks; base += kThreads) {
+    for (int base = 0; base < nb; base += kThreads) {
         const int i = base + threadIdx.x;
-        const uint32_t x = i < nblocks ? row[i] : 0u;
+        const uint32_t x = i < nb ? row[i] : 0u;
         uint32_t tot;
         const uint32_t inc = block_inclusive_scan(x, smem, &tot);
-        if (i < nblocks) row[i] = carry + inc - x;
+        if (i < nb) row[i] = carry + inc - x;
         carry += tot;
     }
     if (threadIdx.x == 0) row_total[blockIdx.x] = carry;
@@ -230,10 +239,13 @@ __device__ __forceinline__ void scan_item(const uint32_t *__restrict__ keys, con
     }
 }
 
+// Gathers each sorted item's two counts once (into `tiles` and `rows`, read
+// back by k_scan_apply, which scans them in place) and reduces them per block.
 __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__restrict__ keys,
                                                           const uint2 *__restrict__ boxes,
                                                           const uint32_t *__restrict__ order, int64_t n_max,
                                                           const int64_t *__restrict__ n_dev, int TW, int TH,
+                                                          uint32_t *__restrict__ tiles, uint32_t *__restrict__ rows,
                                                           unsigned long long *__restrict__ block_sums)
 {
     const int64_t n = clamp_count(n_dev, n_max);
@@ -246,6 +258,8 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__rest
         if (idx < n) {
             uint32_t t, r;
             scan_item(keys, boxes, order, idx, TW, TH, t, r);
+            tiles[idx] = t;
+            rows[idx] = r;
             at += t;
             ar += r;
         }
@@ -312,12 +326,11 @@ __global__ __launch_bounds__(1024) void k_scan_top(unsigned long long *__restric
     }
 }
 
-// Offsets of every sorted item, plus the owner map of the tile rows
-// (row_owner[r] = sorted position owning row r) when the instances fit.
-__global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t *__restrict__ keys,
-                                                         const uint2 *__restrict__ boxes,
-                                                         const uint32_t *__restrict__ order, int64_t n_max,
-                                                         const int64_t *__restrict__ n_dev, int TW, int TH,
+// Offsets of every sorted item, scanned in place over the counts k_scan_reduce
+// left in `offsets` (box tiles) and `row_offsets` (tile rows), plus the owner
+// map of the tile rows (row_owner[r] = sorted position owning row r) when the
+// instances fit.
+__global__ __launch_bounds__(kThreads) void k_scan_apply(int64_t n_max, const int64_t *__restrict__ n_dev,
                                                          int64_t capacity,
                                                          const unsigned long long *__restrict__ block_sums,
                                                          const int64_t *__restrict__ counters,
@@ -325,16 +338,29 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t *__restr
                                                          uint32_t *__restrict__ row_offsets,
                                                          uint32_t *__restrict__ row_owner)
 {
+    static_assert(kItemsPerThread == 8, "two 16-byte loads per thread");
     __shared__ uint32_t smem[kWaves];
     const int64_t n = clamp_count(n_dev, n_max);
-    // blocked arrangement: thread t owns items base + t*8 .. +7
+    // blocked arrangement: thread t owns items base + t*8 .. +7 (32 aligned bytes)
     const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItemsPerThread;
     uint32_t c[kItemsPerThread], r[kItemsPerThread];
+    if (base + kItemsPerThread <= n) {
+        const uint4 *pc = reinterpret_cast<const uint4 *>(offsets + base);
+        const uint4 *pr = reinterpret_cast<const uint4 *>(row_offsets + base);
+        const uint4 c0 = pc[0], c1 = pc[1], r0 = pr[0], r1 = pr[1];
+        c[0] = c0.x; c[1] = c0.y; c[2] = c0.z; c[3] = c0.w; c[4] = c1.x; c[5] = c1.y; c[6] = c1.z; c[7] = c1.w;
+        r[0] = r0.x; r[1] = r0.y; r[2] = r0.z; r[3] = r0.w; r[4] = r1.x; r[5] = r1.y; r[6] = r1.z; r[7] = r1.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < kItemsPerThread; ++j) {
+            const bool in = base + j < n;
+            c[j] = in ? offsets[base + j] : 0u;
+            r[j] = in ? row_offsets[base + j] : 0u;
+        }
+    }
     uint32_t lt = 0, lr = 0;
 #pragma unroll
     for (int j = 0; j < kItemsPerThread; ++j) {
-        c[j] = r[j] = 0u;
-        if (base + j < n) scan_item(keys, boxes, order, base + j, TW, TH, c[j], r[j]);
         lt += c[j];
         lr += r[j];
     }
@@ -421,12 +447,13 @@ __global__ __launch_bounds__(kThreads) void k_tile_ranges(const uint32_t *__rest
                                                           int64_t total_tiles, uint2 *__restrict__ ranges)
 {
     const int64_t m = clamp_count(counters, capacity);
-    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (p >= m) return;
-    const uint32_t t = inst_tiles[p];
-    if (t >= total_tiles) return;
-    if (p == 0 || inst_tiles[p - 1] != t) ranges[t].x = (uint32_t)p;
-    if (p == m - 1 || inst_tiles[p + 1] != t) ranges[t].y = (uint32_t)(p + 1);
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < m; p += stride) {
+        const uint32_t t = inst_tiles[p];
+        if (t >= total_tiles) continue;
+        if (p == 0 || inst_tiles[p - 1] != t) ranges[t].x = (uint32_t)p;
+        if (p == m - 1 || inst_tiles[p + 1] != t) ranges[t].y = (uint32_t)(p + 1);
+    }
 }
 
 // -------------------------------------------------------- tile scheduling
@@ -439,6 +466,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_ranges(const uint32_t *__rest
 // the whole list, which halves the longest chains of dependent work.  Item
 // value = tile << 2 | part (0 whole tile, 1 first half, 2 second half).
 constexpr int kSchedBuckets = 256;
+constexpr int64_t kRangeBlocks = 4096;
 
 __device__ __forceinline__ uint32_t work_bucket(uint32_t len)
 {
@@ -536,7 +564,7 @@ hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32
         const bool pdrop = drop && p == 0;
         const int64_t *pn = drop && p > 0 ? kept_out : n_dev;
         k_radix_hist<<<nblocks, kThreads, 0, stream>>>(ki, n_max, pn, shift, pbits, pdrop, drop_key, hist, nblocks);
-        k_radix_scan_rows<<<kBins, kThreads, 0, stream>>>(hist, nblocks, row_total);
+        k_radix_scan_rows<<<kBins, kThreads, 0, stream>>>(hist, nblocks, n_max, pn, row_total);
         k_radix_scatter<<<nblocks, kThreads, 0, stream>>>(ki, vi, ko, vo, n_max, pn, shift, pbits, pdrop, drop_key,
                                                           kept_out, hist, row_total, nblocks);
         shift += pbits;
@@ -561,10 +589,11 @@ hipError_t binning_scan(const uint32_t *keys, const uint2 *boxes, const uint32_t
         k_fill_u32<<<1, kThreads, 0, stream>>>(reinterpret_cast<uint32_t *>(counters + 2), 0u, 2);
         return hipGetLastError();
     }
-    k_scan_reduce<<<nb, kThreads, 0, stream>>>(keys, boxes, order, n, n_dev, tile_w, tile_h, block_sums);
+    k_scan_reduce<<<nb, kThreads, 0, stream>>>(keys, boxes, order, n, n_dev, tile_w, tile_h, offsets, row_offsets,
+                                               block_sums);
     k_scan_top<<<1, 1024, 0, stream>>>(block_sums, nb, counters);
-    k_scan_apply<<<nb, kThreads, 0, stream>>>(keys, boxes, order, n, n_dev, tile_w, tile_h, capacity, block_sums,
-                                              counters, offsets, row_offsets, row_owner);
+    k_scan_apply<<<nb, kThreads, 0, stream>>>(n, n_dev, capacity, block_sums, counters, offsets, row_offsets,
+                                              row_owner);
     return hipGetLastError();
 }
 
@@ -601,9 +630,12 @@ hipError_t launch_tile_ranges(const uint32_t *inst_tiles, const int64_t *counter
                               uint32_t *sched, uint32_t *work_order, hipStream_t stream)
 {
     // the ranges, queue heads and scheduling histograms were cleared by k_emit
-    if (capacity > 0)
-        k_tile_ranges<<<(unsigned)((capacity + kThreads - 1) / kThreads), kThreads, 0, stream>>>(inst_tiles, counters,
-                                                                                                 capacity, total_tiles, ranges);
+    // a grid-stride loop over the listed instances (a grid sized for the whole
+    // capacity would mostly launch idle workgroups)
+    if (capacity > 0) {
+        const unsigned grid = (unsigned)std::min<int64_t>((capacity + kThreads - 1) / kThreads, kRangeBlocks);
+        k_tile_ranges<<<grid, kThreads, 0, stream>>>(inst_tiles, counters, capacity, total_tiles, ranges);
+    }
     const unsigned nb = (unsigned)((total_tiles + kThreads - 1) / kThreads);
     uint32_t *hist = sched + 2 * sched_backward_heads(), *cursor = hist + kSchedBuckets;
     k_sched_hist<<<nb, kThreads, 0, stream>>>(ranges, total_tiles, counters, split_min, waves, hist);
