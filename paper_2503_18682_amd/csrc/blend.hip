@@ -421,16 +421,21 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                 const float inv_o = __builtin_amdgcn_exp2f(-R.log2o);
                 float du0 = 0, dv0 = 0, dM00 = 0, dM01 = 0, dM11 = 0, dgx = 0, dgy = 0, dk0 = 0, dic2 = 0, dop = 0,
                       dr = 0, dg = 0, db = 0;
-                bool hit = false;
+                bool wave_hit = false;
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) {
                     if (k < k_lo || k >= k_hi || !band_open<PPL, LY>(bands, span, k)) continue;
-                    if (j >= last[k]) continue;
+                    // every lane evaluates the fragment; a lane that does not hit
+                    // takes omega = 0 and 1/t = 0, so every term it adds is zero
+                    // and its state is unchanged (1 / (1 - 0) = 1 exactly)
                     Frag f;
-                    if (!frag_test(R, pxr, pyr[k], f)) continue;
+                    const bool hit = (j < last[k]) & frag_test(R, pxr, pyr[k], f);
+                    if (__ballot(hit) == 0) continue;
+                    wave_hit = true;
                     frag_omega(R, f);
-                    hit = true;
-                    const float a = fminf(f.w, P.alpha_max);
+                    const float w = hit ? f.w : 0.0f;
+                    const float rt = hit ? f.rt : 0.0f;
+                    const float a = fminf(w, P.alpha_max);
                     const float rom = __builtin_amdgcn_rcpf(1.0f - a);  // 1 / (1 - alpha), alpha <= alpha_max
                     const float Tb = T[k] * rom;  // transmittance in front of this Gaussian
                     const float rgd = R.r * g0[k] + R.g * g1[k] + R.b * g2[k];
@@ -441,32 +446,31 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                     const float dL_da = Tb * rgd - S[k] * rom;
                     S[k] += ta * rgd;
                     T[k] = Tb;
-                    if (f.w < P.alpha_max) {
-                        dop += dL_da * f.w * inv_o;
-                        const float dL_dD = -0.5f * f.w * dL_da;
-                        const float rt2 = f.rt * f.rt;
-                        // with the test form's qs = s^2 q in place of q, dL/dden
-                        // and the sums through it (dk0, dg, du0, dv0) come out
-                        // times s^2 and dic2 times s^4; they are rescaled once per
-                        // record below
-                        const float dL_dq = dL_dD * (f.den * f.den) * rt2;
-                        const float dL_dden = dL_dD * (-2.0f * f.q * f.den) * rt2;
-                        dic2 += dL_dD * (-(f.q * f.q)) * rt2;
-                        dM00 += dL_dq * (f.dx * f.dx);
-                        dM01 += dL_dq * (2.0f * f.dx * f.dy);
-                        dM11 += dL_dq * (f.dy * f.dy);
-                        dk0 += dL_dden;
-                        dgx += dL_dden * f.dx;
-                        dgy += dL_dden * f.dy;
-                        // dq/ddelta = 2 G^T G delta = 2 H^T n / s^2 (the 1 / s^2 is
-                        // part of the rescaling)
-                        const float dq_ddx = 2.0f * (R.H00 * f.n0 + R.H10 * f.n1);
-                        const float dq_ddy = 2.0f * (R.H01 * f.n0 + R.H11 * f.n1);
-                        du0 -= dL_dq * dq_ddx + dL_dden * R.gx;
-                        dv0 -= dL_dq * dq_ddy + dL_dden * R.gy;
-                    }
+                    // alpha clamped at alpha_max passes no gradient to omega
+                    const float dL_dw = w < P.alpha_max ? dL_da : 0.0f;
+                    dop += dL_dw * w * inv_o;
+                    const float dL_dD = -0.5f * w * dL_dw;
+                    const float rt2 = rt * rt;
+                    // with the test form's qs = s^2 q in place of q, dL/dden and
+                    // the sums through it (dk0, dg, du0, dv0) come out times s^2
+                    // and dic2 times s^4; they are rescaled once per record below
+                    const float dL_dq = dL_dD * (f.den * f.den) * rt2;
+                    const float dL_dden = dL_dD * (-2.0f * f.q * f.den) * rt2;
+                    dic2 += dL_dD * (-(f.q * f.q)) * rt2;
+                    dM00 += dL_dq * (f.dx * f.dx);
+                    dM01 += dL_dq * (2.0f * f.dx * f.dy);
+                    dM11 += dL_dq * (f.dy * f.dy);
+                    dk0 += dL_dden;
+                    dgx += dL_dden * f.dx;
+                    dgy += dL_dden * f.dy;
+                    // dq/ddelta = 2 G^T G delta = 2 H^T n / s^2 (the 1 / s^2 is part
+                    // of the rescaling)
+                    const float dq_ddx = 2.0f * (R.H00 * f.n0 + R.H10 * f.n1);
+                    const float dq_ddy = 2.0f * (R.H01 * f.n0 + R.H11 * f.n1);
+                    du0 -= dL_dq * dq_ddx + dL_dden * R.gx;
+                    dv0 -= dL_dq * dq_ddy + dL_dden * R.gy;
                 }
-                if (__ballot(hit) == 0) continue;
+                if (!wave_hit) continue;
                 const float vals[16] = {du0, dv0, dM00, dM01, dM11, dgx, dgy, dk0, dic2, dop, dr, dg, db, 0.f, 0.f, 0.f};
                 const float sum = wave_sum16(vals, lane);
                 const int c = wave_sum16_index(lane);
