@@ -13,6 +13,10 @@ Workloads (synthetic, seeded; see scenegen/scenes.py):
                 graph replay.  Metric: views/s (8 single-view renders reported too).
   c3            1M Gaussians, 4 views at 1600x1060; a step is forward + L1 loss
                 gradient + backward.  Metric: backward ms/view.
+  c4            6M Gaussians, 16 cameras of uneven size (256..2560 x 256..1440)
+                and FOV, autotuned tile shape; a step is forward + L1 loss gradient
+                + backward over all 16 views.  Metric: megapixels/s of the step;
+                per-view forward latency p50/p99 from device completion clocks.
 
 Prints ONE JSON line.  Inputs are resident in HBM before the timed region.
 The roofline object covers the dominant kernel of the step, timed with HIP
@@ -58,7 +62,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=160)
     ap.add_argument("--warmup", type=int, default=16)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of HIP-graph replays")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-steps", type=int, default=32, help="frames of the per-stage timing pass")
@@ -328,6 +332,95 @@ def bench_c3(args, torch):
     }
 
 
+def bench_c4(args, torch):
+    import scenegen
+    from paper_2503_18682_amd import _lib
+    from paper_2503_18682_amd import renderer as R
+
+    w = scenegen.make_workload("c4")
+    sc, cams, opts0 = w["scene"], w["cameras"], w["options"]
+    n = int(sc["opacity_logits"].shape[0])
+    g = to_dev(sc, torch)
+    targets = [torch.from_numpy(t).cuda() for t in w["targets"]]
+    r = R.Renderer(0, opts0)
+    # autotune the tile shape in a workspace with room for the finest tiles
+    _, (buf, ws) = r.render(g, cams, opts0, keep_workspace=True)
+    need = r.status(ws)[1]
+    del buf, ws
+    buf, ws = r.new_workspace(n, cams, int(need * 3) + 4096, 0, opts0)
+    outs = r.allocate_outputs(cams)
+    opts, tune_ms = r.autotune(g, cams, ws, outs, reps=2)
+    log(f"c4: autotuned tile {opts['tile_w']}x{opts['tile_h']} ({tune_ms:.2f} ms per forward batch)")
+    del buf, ws
+    _, (buf, ws) = r.render(g, cams, opts, flags=_lib.RGS_WS_BACKWARD, keep_workspace=True)
+    need = r.status(ws)[1]
+    del buf, ws
+    capacity = int(need * 1.1) + 4096
+    buf, ws = r.new_workspace(n, cams, capacity, _lib.RGS_WS_BACKWARD, opts)
+    grads = {k: torch.zeros_like(g[k]) for k in R.PARAM_KEYS}
+    total = sum(t.numel() for t in targets)
+    pixels = sum(c["width"] * c["height"] for c in cams)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def step():
+        ev[0].record()
+        r.render_into(g, cams, outs, ws, opts)
+        dls = [torch.sign(o["rgb"] - t) / total for o, t in zip(outs, targets)]
+        ev[1].record()
+        r.backward(g, cams, outs, dls, ws, opts, grads=grads)
+        ev[2].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    steps = max(args.steps // 8, 20)
+    fwd = bwd = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+        ev[2].synchronize()
+        fwd += ev[0].elapsed_time(ev[1])
+        bwd += ev[1].elapsed_time(ev[2])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    assert r.status(ws)[0], "instance capacity overflow in the timed region"
+    # per-view forward latency: device clocks of the frame start and of each
+    # view's last finished compositing work item, over separate renders
+    stamps = torch.zeros(len(cams) + 1, dtype=torch.int64, device="cuda")
+    r.set_view_clocks(stamps)
+    lat = []
+    for _ in range(steps):
+        r.render_into(g, cams, outs, ws, opts)
+        torch.cuda.synchronize()
+        lat.append(r.view_latencies_ms(stamps, len(cams)))
+    r.set_view_clocks(None)
+    lat = np.asarray(lat)
+    r.stage_times()  # reset
+    r.set_stage_timing(True)
+    for _ in range(4):
+        step()
+    torch.cuda.synchronize()
+    stages, frames = r.stage_times()
+    r.set_stage_timing(False)
+    stages = {k: v / max(frames, 1) for k, v in stages.items()}
+    dom = max(stages, key=stages.get)
+    return {
+        "metric": METRIC, "value": pixels / 1e6 / (ms * 1e-3), "unit": "megapixels/s (forward + backward)",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c4: 6M Gaussians (SH3), 16 uneven cameras, autotuned, forward + L1 + backward",
+                   "views": [[c["width"], c["height"]] for c in cams], "megapixels": pixels / 1e6,
+                   "tile": [opts["tile_w"], opts["tile_h"]], "instance_capacity": capacity},
+        "forward_ms": fwd / steps, "backward_ms": bwd / steps,
+        "forward_megapixels_per_s": pixels / 1e6 / (fwd / steps * 1e-3),
+        "view_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                            "per_view_median": [float(x) for x in np.median(lat, axis=0)],
+                            "samples": int(lat.size)},
+        "roofline": roofline_for(dom, stages[dom]),
+        "stages_ms": stages,
+    }
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -347,7 +440,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    res = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3}[args.workload](args, torch)
+    res = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4}[args.workload](args, torch)
     print(json.dumps(res), flush=True)
 
 

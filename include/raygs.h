@@ -225,6 +225,18 @@ rgs_status rgs_get_workspace_layout(rgs_context *ctx, int64_t n, const rgs_camer
                                     const rgs_options *opts, int64_t capacity, int32_t flags,
                                     rgs_workspace_layout *out);
 
+/* Per-view completion clocks, for latency measurement of batched renders.
+ * While `stamps` is non-null, every rgs_render on this context (not batch
+ * plans or rgs_autotune) also writes, in stream order, stamps[0] = the
+ * device wall clock when the frame starts and stamps[1 + v] = the wall clock
+ * when the last compositing work item of view v finished; ticks are
+ * 1 / rgs_wall_clock_hz seconds.  `stamps` is caller-owned device memory of
+ * max_views + 1 uint64, 8-byte aligned, max_views in 1..256; a render with
+ * more views fails with RGS_EINVAL.  Passing NULL turns the clocks off.  The
+ * clocks add one store per work item and a small reduction kernel. */
+rgs_status rgs_set_view_clocks(rgs_context *ctx, uint64_t *stamps, int32_t max_views);
+double rgs_wall_clock_hz(rgs_context *ctx);
+
 /* Per-stage GPU timing.  While enabled, rgs_render and rgs_render_backward
  * record HIP events around each stage on the caller's stream (graph replays
  * are not timed); rgs_stage_times synchronises, adds the elapsed times of all

@@ -87,6 +87,8 @@ EXPORTS = {
                                C.POINTER(C.c_double)]),
     "rgs_get_workspace_layout": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(Camera), C.c_int32, C.POINTER(Options),
                                            C.c_int64, C.c_int32, C.POINTER(WorkspaceLayout)]),
+    "rgs_set_view_clocks": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "rgs_wall_clock_hz": (C.c_double, [C.c_void_p]),
     "rgs_set_stage_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "rgs_stage_times": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int64)]),
     "rgs_stage_names": (C.c_char_p, []),

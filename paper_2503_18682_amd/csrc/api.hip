@@ -26,7 +26,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
     size_t counters, views, colours, records, keys_a, keys_b, order_a, order_b, boxes, conics, tile_counts, offsets, block_sums;
     size_t inst_tiles_a, inst_tiles_b, inst_ids_a, inst_ids_b, hist, row_total, ranges, sched, tile_order;
-    size_t row_offsets, row_owner;
+    size_t row_offsets, row_owner, item_clock;
     size_t record_grads, total;
     int64_t nv_records, capacity, total_tiles;
     int tile_w, tile_h, tile_bits;
@@ -49,6 +49,8 @@ struct rgs_context {
     double stage_ms[kNumStages] = {0};
     int64_t frames = 0;
     int grid_fwd[64] = {0}, grid_bwd[64] = {0};
+    unsigned long long *view_stamps = nullptr;  // rgs_set_view_clocks (caller-owned device memory)
+    int view_stamps_views = 0;
 };
 
 struct rgs_plan {
@@ -198,6 +200,7 @@ rgs_status compute_layout(rgs_context *ctx, int64_t n, const rgs_camera *cams, i
     L.sched = take(sched_words() * 4);
     L.tile_order = take((size_t)tiles * 2 * 4);  // work items: up to two per tile
     L.row_owner = take((size_t)capacity * 4);
+    L.item_clock = take((size_t)tiles * 2 * 8);  // per work item, for per-view completion clocks
     L.record_grads = (flags & RGS_WS_BACKWARD) ? take(NV * kGradFloats * sizeof(float)) : 0;
     L.total = off;
     return RGS_OK;
@@ -323,7 +326,8 @@ void ensure_grids(rgs_context *ctx, TileShape s)
 
 // Enqueue the forward pipeline after the header copy.
 rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views, const rgs_options &opts,
-                           const Layout &L, void *ws, hipStream_t stream, bool timing)
+                           const Layout &L, void *ws, hipStream_t stream, bool timing,
+                           unsigned long long *view_stamps = nullptr)
 {
     const DevOptions dopt = dev_options(opts);
     const TileShape s = shape_of(opts);
@@ -353,6 +357,8 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
     uint32_t *sched = at<uint32_t>(ws, L.sched);
     const uint32_t *tile_order = at<uint32_t>(ws, L.tile_order);
 
+    if (view_stamps) RGS_HIP(ctx, launch_view_clock_start(view_stamps, n_views, stream));
+    unsigned long long *item_clock = view_stamps ? at<unsigned long long>(ws, L.item_clock) : nullptr;
     Timer tm(ctx, stream, timing, ST_PRE);
     RGS_HIP(ctx, launch_preprocess(g, views, n_views, dopt, colours, records, keys_in, ord_in, boxes, conics,
                                    tile_counts, stream));
@@ -386,9 +392,11 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
                                     at<uint32_t>(ws, L.tile_order), stream));
     tm.mark(ST_RANGES);
     RGS_HIP(ctx, launch_blend(s, ranges, tile_order, sched + sched_item_count(), inst_ids, records, views, n_views,
-                              L.total_tiles, NV, dopt,
-                              sched, ctx->grid_fwd[shape_index(s)], stream));
+                              L.total_tiles, NV, dopt, sched, ctx->grid_fwd[shape_index(s)], item_clock, stream));
     tm.mark(ST_BLEND);
+    if (view_stamps)
+        RGS_HIP(ctx, launch_view_clock_max(item_clock, tile_order, sched + sched_item_count(), 2 * L.total_tiles,
+                                           views, n_views, view_stamps, stream));
     return RGS_OK;
 }
 
@@ -493,7 +501,10 @@ rgs_status rgs_render(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera
     RGS_HIP(ctx, hipSetDevice(ctx->device));
     const std::vector<unsigned char> hdr = build_header(L, cams, n_views, outs, nullptr);
     RGS_HIP(ctx, hipMemcpyAsync(ws->ptr, hdr.data(), hdr.size(), hipMemcpyHostToDevice, s));
-    st = enqueue_forward(ctx, *g, n_views, *opts, L, ws->ptr, s, true);
+    if (ctx->view_stamps && n_views > ctx->view_stamps_views)
+        return fail(ctx, RGS_EINVAL, "%d views exceed the %d of the view clock buffer", n_views,
+                    ctx->view_stamps_views);
+    st = enqueue_forward(ctx, *g, n_views, *opts, L, ws->ptr, s, true, ctx->view_stamps);
     if (st == RGS_OK && ctx->timing) ++ctx->frames;  // frames whose stages were timed
     return st;
 }
@@ -673,7 +684,9 @@ rgs_status rgs_autotune(rgs_context *ctx, const rgs_gaussians *g, const rgs_came
     rgs_options chosen = *opts;
     rgs_status result = RGS_EOVERFLOW;
     const bool timing = ctx->timing;
+    unsigned long long *const view_stamps = ctx->view_stamps;
     ctx->timing = false;
+    ctx->view_stamps = nullptr;
     for (const TileShape &sh : shapes) {
         rgs_options o = *opts;
         o.tile_w = sh.w;
@@ -703,6 +716,7 @@ rgs_status rgs_autotune(rgs_context *ctx, const rgs_gaussians *g, const rgs_came
         result = RGS_OK;
     }
     ctx->timing = timing;
+    ctx->view_stamps = view_stamps;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (result != RGS_OK)
@@ -711,6 +725,25 @@ rgs_status rgs_autotune(rgs_context *ctx, const rgs_gaussians *g, const rgs_came
     *best = chosen;
     *best_ms = best_t;
     return RGS_OK;
+}
+
+rgs_status rgs_set_view_clocks(rgs_context *ctx, uint64_t *stamps, int32_t max_views)
+{
+    if (!ctx) return RGS_EINVAL;
+    if (stamps && (max_views < 1 || max_views > kMaxViews))
+        return fail(ctx, RGS_EINVAL, "max_views=%d outside 1..%d", max_views, kMaxViews);
+    if (reinterpret_cast<uintptr_t>(stamps) % 8) return fail(ctx, RGS_EINVAL, "stamps must be 8-byte aligned");
+    ctx->view_stamps = reinterpret_cast<unsigned long long *>(stamps);
+    ctx->view_stamps_views = stamps ? max_views : 0;
+    return RGS_OK;
+}
+
+double rgs_wall_clock_hz(rgs_context *ctx)
+{
+    if (!ctx) return 0.0;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess) return 0.0;
+    return 1e3 * khz;
 }
 
 rgs_status rgs_set_stage_timing(rgs_context *ctx, int32_t enable)

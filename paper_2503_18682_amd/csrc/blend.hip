@@ -26,6 +26,8 @@
 // exponent D log2(e) / 2 equals K qs / t and omega >= p_min reads qs <= t.
 #include <hip/hip_fp16.h>
 
+#include <algorithm>
+
 #include "internal.h"
 
 #pragma clang fp contract(off)
@@ -117,6 +119,7 @@ struct BlendParams {
     float log2_pmin, alpha_max, t_eps, bg0, bg1, bg2;
     int n_views, total_tiles;
     uint32_t n_records;
+    unsigned long long *item_clock;  // per work-order slot: wall clock at the item's end (may be null)
 };
 
 // Raw record (four float4) of instance value `inst` (id | band bits),
@@ -298,6 +301,8 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
                 V.n_contrib[p] = last[k];
             }
         }
+        // completion clock of the item (every lane stores the same value)
+        if (P.item_clock != nullptr) P.item_clock[slot] = wall_clock64();
     }
 }
 
@@ -494,10 +499,39 @@ int occupancy_grid(const void *kernel, int num_cus)
     return per_cu * num_cus;
 }
 
-BlendParams make_params(const DevOptions &opt, int n_views, int64_t total_tiles, int64_t n_records)
+BlendParams make_params(const DevOptions &opt, int n_views, int64_t total_tiles, int64_t n_records,
+                        unsigned long long *item_clock)
 {
     return BlendParams{(float)log2(opt.p_min), (float)opt.alpha_max, (float)opt.t_eps, opt.bg[0], opt.bg[1], opt.bg[2],
-                       n_views, (int)total_tiles, (uint32_t)n_records};
+                       n_views, (int)total_tiles, (uint32_t)n_records, item_clock};
+}
+
+// Frame start clock and cleared per-view completion clocks.
+__global__ void k_view_clock_start(unsigned long long *__restrict__ stamps, int n_views)
+{
+    const int i = threadIdx.x;
+    if (i == 0) stamps[0] = wall_clock64();
+    for (int v = i; v < n_views; v += blockDim.x) stamps[1 + v] = 0ull;
+}
+
+// stamps[1 + v] = the latest completion clock over the work items of view v.
+__global__ __launch_bounds__(256) void k_view_clock_max(const unsigned long long *__restrict__ item_clock,
+                                                         const uint32_t *__restrict__ work_order,
+                                                         const uint32_t *__restrict__ n_items_p,
+                                                         const DevView *__restrict__ views, int n_views,
+                                                         unsigned long long *__restrict__ stamps)
+{
+    __shared__ unsigned long long best[kMaxViews];
+    for (int v = threadIdx.x; v < n_views; v += blockDim.x) best[v] = 0ull;
+    __syncthreads();
+    const int64_t n_items = *n_items_p;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n_items; s += (int64_t)gridDim.x * blockDim.x) {
+        const int v = find_view(views, n_views, (int)(work_order[s] >> 2));
+        atomicMax(&best[v], item_clock[s]);
+    }
+    __syncthreads();
+    for (int v = threadIdx.x; v < n_views; v += blockDim.x)
+        if (best[v]) atomicMax(&stamps[1 + v], best[v]);
 }
 
 }  // namespace
@@ -531,9 +565,9 @@ int blend_backward_grid(TileShape s, int num_cus)
 hipError_t launch_blend(TileShape s, const uint2 *ranges, const uint32_t *work_order, const uint32_t *n_items,
                         const uint32_t *inst_ids, const float4 *records, const DevView *views, int n_views,
                         int64_t total_tiles, int64_t n_records, const DevOptions &opt, unsigned int *queue, int grid,
-                        hipStream_t stream)
+                        unsigned long long *item_clock, hipStream_t stream)
 {
-    const BlendParams P = make_params(opt, n_views, total_tiles, n_records);
+    const BlendParams P = make_params(opt, n_views, total_tiles, n_records, item_clock);
 #define X(W, H)                                                                                                  \
     if (s.w == W && s.h == H) {                                                                                  \
         k_blend<W, H><<<grid, 256, 0, stream>>>(ranges, work_order, n_items, inst_ids, records, views, P, queue); \
@@ -550,7 +584,7 @@ hipError_t launch_blend_backward(TileShape s, const uint2 *ranges, const uint32_
                                  const DevOptions &opt, float *record_grads, unsigned int *queue, int grid,
                                  hipStream_t stream)
 {
-    const BlendParams P = make_params(opt, n_views, total_tiles, n_records);
+    const BlendParams P = make_params(opt, n_views, total_tiles, n_records, nullptr);
 #define X(W, H)                                                                                                  \
     if (s.w == W && s.h == H) {                                                                                  \
         k_blend_bwd<W, H><<<grid, 256, 0, stream>>>(ranges, work_order, n_items, inst_ids, records, views, P,  \
@@ -560,6 +594,21 @@ hipError_t launch_blend_backward(TileShape s, const uint2 *ranges, const uint32_
     RGS_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_view_clock_start(unsigned long long *stamps, int n_views, hipStream_t stream)
+{
+    k_view_clock_start<<<1, 256, 0, stream>>>(stamps, n_views);
+    return hipGetLastError();
+}
+
+hipError_t launch_view_clock_max(const unsigned long long *item_clock, const uint32_t *work_order,
+                                 const uint32_t *n_items, int64_t max_items, const DevView *views, int n_views,
+                                 unsigned long long *stamps, hipStream_t stream)
+{
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_items + 255) / 256, 1024));
+    k_view_clock_max<<<grid, 256, 0, stream>>>(item_clock, work_order, n_items, views, n_views, stamps);
+    return hipGetLastError();
 }
 
 }  // namespace rgs

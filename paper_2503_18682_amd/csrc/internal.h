@@ -136,10 +136,21 @@ hipError_t launch_tile_ranges(const uint32_t *inst_tiles, const int64_t *counter
 
 // Compositing of the work items work_order[0, *n_items) (see
 // launch_tile_ranges); `queue` holds the kQueues heads (zero).
+// item_clock (may be null): per work-order slot, the device wall clock when
+// the item finished.
 hipError_t launch_blend(TileShape shape, const uint2 *ranges, const uint32_t *work_order, const uint32_t *n_items,
                         const uint32_t *inst_ids, const float4 *records, const DevView *views, int n_views,
                         int64_t total_tiles, int64_t n_records, const DevOptions &opt, unsigned int *queue, int grid,
-                        hipStream_t stream);
+                        unsigned long long *item_clock, hipStream_t stream);
+
+// Per-view completion clocks: stamps[0] = frame start (written by
+// launch_view_clock_start, which also clears stamps[1..n_views]), stamps[1 + v]
+// = max item clock over view v's work items (launch_view_clock_max, after the
+// compositing kernel).
+hipError_t launch_view_clock_start(unsigned long long *stamps, int n_views, hipStream_t stream);
+hipError_t launch_view_clock_max(const unsigned long long *item_clock, const uint32_t *work_order,
+                                 const uint32_t *n_items, int64_t max_items, const DevView *views, int n_views,
+                                 unsigned long long *stamps, hipStream_t stream);
 int blend_grid(TileShape shape, int num_cus);
 
 // Backward compositing over the same work items (whole tiles and halves).

@@ -235,6 +235,24 @@ class Renderer:
         self.lib.rgs_stage_times(self.ctx, ms, len(names), C.byref(frames))
         return dict(zip(names, list(ms))), frames.value
 
+    def set_view_clocks(self, stamps: Optional[torch.Tensor]):
+        """Per-view completion clocks of later render_into calls: `stamps` is
+        an int64 device tensor of max_views + 1 entries (None turns them off);
+        see view_latencies_ms."""
+        if stamps is None:
+            _check(self.lib, self.ctx, self.lib.rgs_set_view_clocks(self.ctx, None, 0))
+            return
+        assert stamps.dtype == torch.int64 and stamps.is_cuda and stamps.is_contiguous()
+        _check(self.lib, self.ctx, self.lib.rgs_set_view_clocks(self.ctx, C.c_void_p(stamps.data_ptr()),
+                                                                stamps.numel() - 1))
+
+    def view_latencies_ms(self, stamps: torch.Tensor, n_views: int):
+        """Milliseconds from the frame start to each view's last finished
+        compositing work item, from a stamps tensor written by a render."""
+        hz = self.lib.rgs_wall_clock_hz(self.ctx)
+        s = stamps[: n_views + 1].cpu().numpy().astype("float64")
+        return list((s[1:] - s[0]) * 1e3 / hz)
+
 
 class BatchRenderer:
     """A fixed batch of views rendered by one HIP-graph replay per frame."""

@@ -325,3 +325,43 @@ def test_autotune_picks_a_supported_shape(r):
     best, ms = r.autotune(g, cams, ws, outs, reps=2)
     assert best["tile_w"] in (8, 16, 32) and best["tile_h"] in (8, 16, 32)
     assert ms > 0
+
+
+def test_view_clocks_leave_images_unchanged_and_order_in_time(r):
+    """Per-view completion clocks: enabling them changes no output bit; every
+    view's clock lies after the frame start and within the frame's host-side
+    duration; a batch with more views than the clock buffer is rejected."""
+    import time
+
+    sc = scenegen.tiny_scene(36, 3000, sh_degree=1, half_extent=1.5, log_scale_mean=-3.5, log_scale_std=0.8)
+    cams = [scenegen.pinhole(scenegen.look_at((0, 0, -4)), 160, 120, 60),
+            scenegen.pinhole(scenegen.look_at((1, 0.5, -3.5)), 96, 200, 70)]
+    opts = scenegen.default_options()
+    say("case view clocks: 2 uneven views")
+    g = to_dev(sc)
+    buf, ws = r.new_workspace(3000, cams, 200000, 0, opts)
+    plain = r.allocate_outputs(cams)
+    r.render_into(g, cams, plain, ws, opts)
+    stamps = torch.zeros(len(cams) + 1, dtype=torch.int64, device="cuda")
+    r.set_view_clocks(stamps)
+    try:
+        clocked = r.allocate_outputs(cams)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r.render_into(g, cams, clocked, ws, opts)
+        torch.cuda.synchronize()
+        host_ms = (time.perf_counter() - t0) * 1e3
+        lat = r.view_latencies_ms(stamps, len(cams))
+        s = stamps.cpu().numpy()
+        say(f"  latencies {[round(x, 4) for x in lat]} ms, host {host_ms:.3f} ms")
+        assert s[0] > 0 and all(s[1:] >= s[0])
+        assert all(0.0 < x <= host_ms + 1.0 for x in lat)
+        for v in range(len(cams)):
+            for key in ("rgb", "final_T", "n_contrib"):
+                assert torch.equal(plain[v][key], clocked[v][key]), (v, key)
+        small = torch.zeros(2, dtype=torch.int64, device="cuda")
+        r.set_view_clocks(small)  # room for one view only
+        with pytest.raises(RuntimeError):
+            r.render_into(g, cams, clocked, ws, opts)
+    finally:
+        r.set_view_clocks(None)
