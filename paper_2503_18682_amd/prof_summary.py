@@ -15,6 +15,12 @@ HBM traffic of one kernel from two counter runs:
     python -m paper_2503_18682_amd.prof_summary traffic --fetch F.csv --write W.csv \
         --kernel k_blend --copy-mib 1024 --out profiles/<name>.txt [--command "..."]
 
+HBM traffic and bandwidth per frame of every kernel of the path (the same two
+counter runs plus the kernel-trace statistics for durations):
+
+    python -m paper_2503_18682_amd.prof_summary traffic-table --fetch F.csv --write W.csv \
+        --stats X_kernel_stats.csv --copy-mib 1024 --out profiles/<name>.txt
+
 F.csv / W.csv are the ``*_counter_collection.csv`` files of two runs of the
 same program with ``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE``.  Both runs
 must also execute one plain device copy of ``--copy-mib`` MiB (bench.py
@@ -136,6 +142,57 @@ def read_traffic(path, kernel):
     return float(vals["traffic_bytes_per_dispatch"])
 
 
+def write_traffic_table(fetch_csv, write_csv, stats_csv, copy_mib, out, command, workload,
+                        frame_kernel="k_preprocess"):
+    """Per frame: dispatches, HBM bytes (scaled counters) and trace duration of
+    every kernel, and the bandwidth they imply.  Frames are counted by the
+    dispatches of `frame_kernel` (one per frame) in each run."""
+    copy_bytes = copy_mib * (1 << 20)
+    per_frame = {}
+    scales = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        per = _per_dispatch(path, counter)
+        copies = _pick(per, r"copyBuffer|elementwise|CopyKernel")
+        scale = copy_bytes / (max(max(v) for v in copies.values()) * 1024.0)
+        scales[counter] = scale
+        frames = sum(len(v) for k, v in per.items() if re.search(re.escape(frame_kernel) + r"\b", k))
+        for name, v in per.items():
+            m = re.search(r"(k_\w+)", name)
+            if not m:
+                continue
+            e = per_frame.setdefault(m.group(1), {})
+            e[counter] = sum(v) * 1024.0 * scale / max(frames, 1)
+            e["calls_" + counter] = len(v) / max(frames, 1)
+    with open(stats_csv) as f:
+        rows = list(csv.DictReader(f))
+    calls = collections.defaultdict(float)
+    total_ns = collections.defaultdict(float)
+    for r in rows:
+        m = re.search(r"(k_\w+)", r["Name"])
+        if m:
+            calls[m.group(1)] += float(r["Calls"])
+            total_ns[m.group(1)] += float(r["TotalDurationNs"])
+    trace_frames = calls.get(frame_kernel, 1.0)
+    lines = [f"# HBM traffic and bandwidth per frame, every kernel ({workload})", "#",
+             "# Commands (repository root R on the GPU box, run from /tmp with TMPDIR=/tmp):"]
+    lines += [f"#   {c}" for c in command.split(" ;; ")]
+    lines += ["#",
+              f"# bytes = FETCH_SIZE x 1024 x {scales['FETCH_SIZE']:.4f} + WRITE_SIZE x 1024 x "
+              f"{scales['WRITE_SIZE']:.4f} (a {copy_mib} MiB device copy calibrates both), per frame;",
+              "# duration = kernel-trace total per frame; GB/s = bytes / duration",
+              "#",
+              "# kernel | dispatches per frame | fetch MB | write MB | us per frame | GB/s"]
+    for k in sorted(per_frame, key=lambda k: -total_ns.get(k, 0.0)):
+        e = per_frame[k]
+        fb, wb = e.get("FETCH_SIZE", 0.0), e.get("WRITE_SIZE", 0.0)
+        us = total_ns.get(k, 0.0) / trace_frames / 1e3
+        gbs = (fb + wb) / (us * 1e-6) / 1e9 if us > 0 else 0.0
+        lines.append(f"{k} | {e.get('calls_FETCH_SIZE', 0.0):.0f} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {us:.1f} | "
+                     f"{gbs:.0f}")
+    with open(out, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+
+
 def short_name(name: str) -> str:
     m = re.search(r"(k_\w+)(<[^>(]*>)?", name)
     if not m:
@@ -209,7 +266,12 @@ def main():
     t.add_argument("--copy-mib", type=int, required=True)
     st = sub.add_parser("stats")
     st.add_argument("--csv", required=True)
-    for p in (t, st, cn):
+    tt = sub.add_parser("traffic-table")
+    tt.add_argument("--fetch", required=True)
+    tt.add_argument("--write", required=True)
+    tt.add_argument("--stats", required=True)
+    tt.add_argument("--copy-mib", type=int, required=True)
+    for p in (t, st, cn, tt):
         p.add_argument("--out", required=True)
         p.add_argument("--workload", default="")
         p.add_argument("--command", default="", help="commands that produced the input (';;'-separated)")
@@ -220,6 +282,8 @@ def main():
         write_summary(res, a.kernel, a.out, a.command, a.workload)
     elif a.cmd == "counters":
         write_counters(a.csv, a.kernel, a.out, a.command, a.workload)
+    elif a.cmd == "traffic-table":
+        write_traffic_table(a.fetch, a.write, a.stats, a.copy_mib, a.out, a.command, a.workload)
     else:
         write_stats(a.csv, a.out, a.command, a.workload)
     print(open(a.out).read())
