@@ -19,6 +19,7 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kItemsPerThread = 8;
 constexpr int kTile = kThreads * kItemsPerThread;  // items per block (scans)
+constexpr int kScanSelfPrefixBlocks = 1024;
 // radix sort: items per lane and per workgroup (a smaller tile shortens the
 // serial ranking chain of each workgroup; the digit histograms grow with the
 // number of tiles)
@@ -326,14 +327,48 @@ __global__ __launch_bounds__(1024) void k_scan_top(unsigned long long *__restric
     }
 }
 
+// Sums of the (tiles, rows) block-sum pairs of the blocks before `block`
+// (pre) and of all nb blocks (all), the same in every thread.
+__device__ void block_prefix_pairs(const unsigned long long *__restrict__ block_sums, int nb, int block,
+                                   unsigned long long (&pre)[2], unsigned long long (&all)[2])
+{
+    __shared__ unsigned long long part[4][kWaves];
+    unsigned long long v[4] = {0, 0, 0, 0};
+    for (int i = threadIdx.x; i < nb; i += kThreads) {
+        const unsigned long long t = block_sums[2 * i], r = block_sums[2 * i + 1];
+        v[2] += t;
+        v[3] += r;
+        if (i < block) {
+            v[0] += t;
+            v[1] += r;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        for (int d = 32; d >= 1; d >>= 1) v[c] += __shfl_xor(v[c], d, 64);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) part[c][threadIdx.x >> 6] = v[c];
+    __syncthreads();
+    pre[0] = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+    pre[1] = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+    all[0] = part[2][0] + part[2][1] + part[2][2] + part[2][3];
+    all[1] = part[3][0] + part[3][1] + part[3][2] + part[3][3];
+}
+
 // Offsets of every sorted item, scanned in place over the counts k_scan_reduce
 // left in `offsets` (box tiles) and `row_offsets` (tile rows), plus the owner
 // map of the tile rows (row_owner[r] = sorted position owning row r) when the
 // instances fit.
+// With `self_prefix` (few blocks), block_sums still holds every block's raw
+// pair: each block sums the pairs before its own and all of them, block 0
+// writes the totals to counters[0] and counters[2], and k_scan_top is not
+// launched.  Otherwise k_scan_top has turned block_sums into exclusive
+// prefixes and written the totals.
 __global__ __launch_bounds__(kThreads) void k_scan_apply(int64_t n_max, const int64_t *__restrict__ n_dev,
                                                          int64_t capacity,
                                                          const unsigned long long *__restrict__ block_sums,
-                                                         const int64_t *__restrict__ counters,
+                                                         int64_t *__restrict__ counters, bool self_prefix,
                                                          uint32_t *__restrict__ offsets,
                                                          uint32_t *__restrict__ row_offsets,
                                                          uint32_t *__restrict__ row_owner)
@@ -367,9 +402,21 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(int64_t n_max, const in
     uint32_t tot;
     const uint32_t bt = block_inclusive_scan(lt, smem, &tot) - lt;
     const uint32_t br = block_inclusive_scan(lr, smem, &tot) - lr;
-    const bool fits = counters[0] <= capacity;
-    unsigned long long rt = block_sums[2 * blockIdx.x] + bt;
-    unsigned long long rr = block_sums[2 * blockIdx.x + 1] + br;
+    unsigned long long pre[2], all[2];
+    if (self_prefix) {
+        block_prefix_pairs(block_sums, (int)gridDim.x, (int)blockIdx.x, pre, all);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            counters[0] = (int64_t)all[0];
+            counters[2] = (int64_t)all[1];
+        }
+    } else {
+        pre[0] = block_sums[2 * blockIdx.x];
+        pre[1] = block_sums[2 * blockIdx.x + 1];
+        all[0] = (unsigned long long)counters[0];
+    }
+    const bool fits = all[0] <= (unsigned long long)capacity;
+    unsigned long long rt = pre[0] + bt;
+    unsigned long long rr = pre[1] + br;
 #pragma unroll
     for (int j = 0; j < kItemsPerThread; ++j) {
         const int64_t idx = base + j;
@@ -591,9 +638,12 @@ hipError_t binning_scan(const uint32_t *keys, const uint2 *boxes, const uint32_t
     }
     k_scan_reduce<<<nb, kThreads, 0, stream>>>(keys, boxes, order, n, n_dev, tile_w, tile_h, offsets, row_offsets,
                                                block_sums);
-    k_scan_top<<<1, 1024, 0, stream>>>(block_sums, nb, counters);
-    k_scan_apply<<<nb, kThreads, 0, stream>>>(n, n_dev, capacity, block_sums, counters, offsets, row_offsets,
-                                              row_owner);
+    // up to kScanSelfPrefixBlocks blocks, each apply block sums the block
+    // pairs before it (at most that many loads) instead of a separate scan
+    const bool self_prefix = nb <= kScanSelfPrefixBlocks;
+    if (!self_prefix) k_scan_top<<<1, 1024, 0, stream>>>(block_sums, nb, counters);
+    k_scan_apply<<<nb, kThreads, 0, stream>>>(n, n_dev, capacity, block_sums, counters, self_prefix, offsets,
+                                              row_offsets, row_owner);
     return hipGetLastError();
 }
 
