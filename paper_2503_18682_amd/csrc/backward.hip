@@ -33,12 +33,16 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const double m[3] = {means[i], means[n + i], means[2 * n + i]};
     const double q[4] = {quats[i], quats[n + i], quats[2 * n + i], quats[3 * n + i]};
     const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+    // repeated divisors are applied as one reciprocal each (a double division
+    // is a long instruction sequence; gradients need no exact rounding)
+    const double iq = 1.0 / qn;
+    const double w = q[0] * iq, x = q[1] * iq, y = q[2] * iq, z = q[3] * iq;
     double R[9];
     R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
     R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
     R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
     const double s[3] = {exp((double)log_scales[i]), exp((double)log_scales[n + i]), exp((double)log_scales[2 * n + i])};
+    const double is[3] = {1.0 / s[0], 1.0 / s[1], 1.0 / s[2]};
     const double o = 1.0 / (1.0 + exp(-(double)opacity_logits[i]));
 
     double dm[3] = {0, 0, 0}, dl[3] = {0, 0, 0}, dR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, da = 0.0;
@@ -59,15 +63,16 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
             for (int c = 0; c < 3; ++c) Rp[3 * r + c] = W[4 * r] * R[c] + W[4 * r + 1] * R[3 + c] + W[4 * r + 2] * R[6 + c];
         double A[3][3];  // A = S^-1 R_p^T
         for (int k = 0; k < 3; ++k)
-            for (int j = 0; j < 3; ++j) A[k][j] = Rp[3 * j + k] / s[k];
+            for (int j = 0; j < 3; ++j) A[k][j] = Rp[3 * j + k] * is[k];
         double mw[3];
         for (int k = 0; k < 3; ++k) mw[k] = A[k][0] * mu[0] + A[k][1] * mu[1] + A[k][2] * mu[2];
         const double c2 = mw[0] * mw[0] + mw[1] * mw[1] + mw[2] * mw[2];
-        const double c4 = c2 * c2;
+        const double ic2 = 1.0 / c2, ic4 = ic2 * ic2;
+        const double ifx = 1.0 / V.fx, ify = 1.0 / V.fy;
         double A2[3][2];
         for (int k = 0; k < 3; ++k) {
-            A2[k][0] = A[k][0] / V.fx;
-            A2[k][1] = A[k][1] / V.fy;
+            A2[k][0] = A[k][0] * ifx;
+            A2[k][1] = A[k][1] * ify;
         }
         double wv[2];
         for (int c = 0; c < 2; ++c) wv[c] = A2[0][c] * mw[0] + A2[1][c] * mw[1] + A2[2][c] * mw[2];
@@ -77,9 +82,9 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         for (int k = 0; k < 3; ++k)
             for (int c = 0; c < 2; ++c) dA2[k][c] = 2.0 * (A2[k][0] * Gm[0][c] + A2[k][1] * Gm[1][c]);
         const double Gw[2] = {Gm[0][0] * wv[0] + Gm[0][1] * wv[1], Gm[1][0] * wv[0] + Gm[1][1] * wv[1]};
-        dw[0] = -2.0 * Gw[0] / c2 + ggx / c2;
-        dw[1] = -2.0 * Gw[1] / c2 + ggy / c2;
-        dc2 = (wv[0] * Gw[0] + wv[1] * Gw[1]) / c4 - (ggx * wv[0] + ggy * wv[1]) / c4 - gic2 / c4;
+        dw[0] = (-2.0 * Gw[0] + ggx) * ic2;
+        dw[1] = (-2.0 * Gw[1] + ggy) * ic2;
+        dc2 = ((wv[0] * Gw[0] + wv[1] * Gw[1]) - (ggx * wv[0] + ggy * wv[1]) - gic2) * ic4;
         // w = A2^T mu'
         double dmw[3];
         for (int k = 0; k < 3; ++k) {
@@ -92,8 +97,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         for (int k = 0; k < 3; ++k)
             for (int j = 0; j < 3; ++j) dA[k][j] = dmw[k] * mu[j];
         for (int k = 0; k < 3; ++k) {
-            dA[k][0] += dA2[k][0] / V.fx;
-            dA[k][1] += dA2[k][1] / V.fy;
+            dA[k][0] += dA2[k][0] * ifx;
+            dA[k][1] += dA2[k][1] * ify;
         }
         for (int j = 0; j < 3; ++j) dmu[j] = A[0][j] * dmw[0] + A[1][j] * dmw[1] + A[2][j] * dmw[2];
         // k0 = 1/mu_z, projected centre (u0, v0)
@@ -107,7 +112,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         for (int k = 0; k < 3; ++k) {
             double acc = 0.0;
             for (int j = 0; j < 3; ++j) {
-                dRp[3 * j + k] = dA[k][j] / s[k];
+                dRp[3 * j + k] = dA[k][j] * is[k];
                 acc += dA[k][j] * A[k][j];
             }
             dl[k] -= acc;
@@ -128,7 +133,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         for (int k = 0; k < 4; ++k) dqh[k] += dR[e] * J[e][k];
     const double qh[4] = {w, x, y, z};
     const double proj = qh[0] * dqh[0] + qh[1] * dqh[1] + qh[2] * dqh[2] + qh[3] * dqh[3];
-    for (int k = 0; k < 4; ++k) g_quats[(size_t)k * n + i] += (float)((dqh[k] - qh[k] * proj) / qn);
+    for (int k = 0; k < 4; ++k) g_quats[(size_t)k * n + i] += (float)((dqh[k] - qh[k] * proj) * iq);
     for (int k = 0; k < 3; ++k) {
         g_means[(size_t)k * n + i] += (float)dm[k];
         g_log_scales[(size_t)k * n + i] += (float)dl[k];
@@ -189,7 +194,8 @@ __global__ __launch_bounds__(256) void k_colour_bwd(const float *__restrict__ me
         float ddir[3];
         sh_dir_grad<DEG>(dir[0], dir[1], dir[2], wk, ddir);
         const double pd = (double)ddir[0] * dir[0] + (double)ddir[1] * dir[1] + (double)ddir[2] * dir[2];
-        for (int j = 0; j < 3; ++j) dm[j] += ((double)ddir[j] - dir[j] * pd) / dist;
+        const double idist = 1.0 / dist;
+        for (int j = 0; j < 3; ++j) dm[j] += ((double)ddir[j] - dir[j] * pd) * idist;
     }
     for (int k = 0; k < 3; ++k) g_means[(size_t)k * n + i] += (float)dm[k];
 #pragma unroll
