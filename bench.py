@@ -343,15 +343,19 @@ def bench_c4(args, torch):
     g = to_dev(sc, torch)
     targets = [torch.from_numpy(t).cuda() for t in w["targets"]]
     r = R.Renderer(0, opts0)
-    # autotune the tile shape in a workspace with room for the finest tiles
-    _, (buf, ws) = r.render(g, cams, opts0, keep_workspace=True)
+    # autotune the tile shape of the whole training step (render + backward) in
+    # a workspace with room for the finest tiles
+    fine = dict(opts0, tile_w=8, tile_h=8)
+    _, (buf, ws) = r.render(g, cams, fine, keep_workspace=True)
     need = r.status(ws)[1]
     del buf, ws
-    buf, ws = r.new_workspace(n, cams, int(need * 3) + 4096, 0, opts0)
+    buf, ws = r.new_workspace(n, cams, int(need * 1.1) + 4096, _lib.RGS_WS_BACKWARD, fine)
     outs = r.allocate_outputs(cams)
-    opts, tune_ms = r.autotune(g, cams, ws, outs, reps=2)
-    log(f"c4: autotuned tile {opts['tile_w']}x{opts['tile_h']} ({tune_ms:.2f} ms per forward batch)")
-    del buf, ws
+    r.render_into(g, cams, outs, ws, fine)
+    dls = [torch.sign(o["rgb"] - t) / sum(t.numel() for t in targets) for o, t in zip(outs, targets)]
+    opts, tune_ms = r.autotune_training(g, cams, ws, outs, dls, reps=3)
+    log(f"c4: autotuned tile {opts['tile_w']}x{opts['tile_h']} ({tune_ms:.2f} ms per render + backward)")
+    del buf, ws, dls
     _, (buf, ws) = r.render(g, cams, opts, flags=_lib.RGS_WS_BACKWARD, keep_workspace=True)
     need = r.status(ws)[1]
     del buf, ws
@@ -410,7 +414,8 @@ def bench_c4(args, torch):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "c4: 6M Gaussians (SH3), 16 uneven cameras, autotuned, forward + L1 + backward",
                    "views": [[c["width"], c["height"]] for c in cams], "megapixels": pixels / 1e6,
-                   "tile": [opts["tile_w"], opts["tile_h"]], "instance_capacity": capacity},
+                   "tile": [opts["tile_w"], opts["tile_h"]], "tile_from": "rgs_autotune_training",
+                   "instance_capacity": capacity},
         "forward_ms": fwd / steps, "backward_ms": bwd / steps,
         "forward_megapixels_per_s": pixels / 1e6 / (fwd / steps * 1e-3),
         "view_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),

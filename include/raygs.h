@@ -184,11 +184,22 @@ void rgs_plan_destroy(rgs_plan *plan);
 /* Times every supported tile shape on this frame (hipEvent timing, `reps`
  * renders each after one warm-up, synchronising `stream`) and writes the
  * fastest into *best (a copy of *opts with tile_w, tile_h set) and its mean
- * milliseconds into *best_ms.  Shapes whose instances exceed ws->capacity are
- * skipped. */
+ * milliseconds into *best_ms.  Shapes whose instances exceed ws->capacity, or
+ * whose tile tables exceed the workspace, are skipped: a workspace sized for
+ * 8x8 tiles (the most tiles and instances) lets every shape run. */
 rgs_status rgs_autotune(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
                         const rgs_options *opts, const rgs_workspace *ws, const rgs_view_out *outs, int32_t reps,
                         void *stream, rgs_options *best, double *best_ms);
+
+/* As rgs_autotune for a training step: each timed step is a render followed
+ * by rgs_render_backward with the upstream gradients dL_drgb[v] (device
+ * [3][H][W] per view); `ws` must carry RGS_WS_BACKWARD and opts->mip be 0.
+ * Every backward pass adds into `grads`, so pass scratch buffers.  *best_ms
+ * is the mean forward + backward milliseconds of the chosen shape. */
+rgs_status rgs_autotune_training(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
+                                 const rgs_options *opts, const rgs_workspace *ws, const rgs_view_out *outs,
+                                 const float *const *dL_drgb, const rgs_gaussian_grads *grads, int32_t reps,
+                                 void *stream, rgs_options *best, double *best_ms);
 
 /* Byte offsets of the intermediate buffers inside a workspace (for tests and
  * profiling tools).  Counts are element counts.  Pure host arithmetic; ctx

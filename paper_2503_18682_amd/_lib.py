@@ -85,6 +85,10 @@ EXPORTS = {
     "rgs_autotune": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.POINTER(Camera), C.c_int32, C.POINTER(Options),
                                C.POINTER(Workspace), C.POINTER(ViewOut), C.c_int32, C.c_void_p, C.POINTER(Options),
                                C.POINTER(C.c_double)]),
+    "rgs_autotune_training": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.POINTER(Camera), C.c_int32,
+                                        C.POINTER(Options), C.POINTER(Workspace), C.POINTER(ViewOut),
+                                        C.POINTER(C.c_void_p), C.POINTER(GaussianGrads), C.c_int32, C.c_void_p,
+                                        C.POINTER(Options), C.POINTER(C.c_double)]),
     "rgs_get_workspace_layout": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(Camera), C.c_int32, C.POINTER(Options),
                                            C.c_int64, C.c_int32, C.POINTER(WorkspaceLayout)]),
     "rgs_set_view_clocks": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),

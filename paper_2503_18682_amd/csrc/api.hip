@@ -669,9 +669,17 @@ rgs_status rgs_batch_launch(rgs_plan *p, const rgs_gaussians *g, const rgs_camer
     return RGS_OK;
 }
 
-rgs_status rgs_autotune(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
-                        const rgs_options *opts, const rgs_workspace *ws, const rgs_view_out *outs, int32_t reps,
-                        void *stream, rgs_options *best, double *best_ms)
+}  // extern "C"
+
+namespace {
+
+// Times every supported tile shape: `reps` forward renders (each followed by
+// a backward pass when dL_drgb is given) after one untimed step; shapes whose
+// instances exceed the workspace capacity are skipped.
+rgs_status autotune_shapes(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
+                           const rgs_options *opts, const rgs_workspace *ws, const rgs_view_out *outs,
+                           const float *const *dL_drgb, const rgs_gaussian_grads *grads, int32_t reps, void *stream,
+                           rgs_options *best, double *best_ms)
 {
     if (!ctx || !best || !best_ms || !opts) return fail(ctx, RGS_EINVAL, "NULL argument");
     if (reps < 1) return fail(ctx, RGS_EINVAL, "reps must be >= 1");
@@ -691,15 +699,22 @@ rgs_status rgs_autotune(rgs_context *ctx, const rgs_gaussians *g, const rgs_came
         rgs_options o = *opts;
         o.tile_w = sh.w;
         o.tile_h = sh.h;
+        auto step = [&]() {
+            rgs_status st = rgs_render(ctx, g, cams, n_views, &o, ws, outs, stream);
+            if (st == RGS_OK && dL_drgb)
+                st = rgs_render_backward(ctx, g, cams, n_views, &o, ws, outs, dL_drgb, grads, stream);
+            return st;
+        };
         rgs_status st = rgs_render(ctx, g, cams, n_views, &o, ws, outs, stream);
         if (st == RGS_OK) st = rgs_render_status(ctx, ws, stream, nullptr);
         if (st == RGS_EOVERFLOW || st == RGS_EWORKSPACE) continue;
+        if (st == RGS_OK && dL_drgb) st = rgs_render_backward(ctx, g, cams, n_views, &o, ws, outs, dL_drgb, grads, stream);
         if (st != RGS_OK) {
             result = st;
             break;
         }
         (void)hipEventRecord(e0, s);
-        for (int r = 0; r < reps && st == RGS_OK; ++r) st = rgs_render(ctx, g, cams, n_views, &o, ws, outs, stream);
+        for (int r = 0; r < reps && st == RGS_OK; ++r) st = step();
         (void)hipEventRecord(e1, s);
         if (st != RGS_OK) {
             result = st;
@@ -725,6 +740,26 @@ rgs_status rgs_autotune(rgs_context *ctx, const rgs_gaussians *g, const rgs_came
     *best = chosen;
     *best_ms = best_t;
     return RGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rgs_status rgs_autotune(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
+                        const rgs_options *opts, const rgs_workspace *ws, const rgs_view_out *outs, int32_t reps,
+                        void *stream, rgs_options *best, double *best_ms)
+{
+    return autotune_shapes(ctx, g, cams, n_views, opts, ws, outs, nullptr, nullptr, reps, stream, best, best_ms);
+}
+
+rgs_status rgs_autotune_training(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
+                                 const rgs_options *opts, const rgs_workspace *ws, const rgs_view_out *outs,
+                                 const float *const *dL_drgb, const rgs_gaussian_grads *grads, int32_t reps,
+                                 void *stream, rgs_options *best, double *best_ms)
+{
+    if (!dL_drgb) return fail(ctx, RGS_EINVAL, "dL_drgb is NULL");
+    return autotune_shapes(ctx, g, cams, n_views, opts, ws, outs, dL_drgb, grads, reps, stream, best, best_ms);
 }
 
 rgs_status rgs_set_view_clocks(rgs_context *ctx, uint64_t *stamps, int32_t max_views)

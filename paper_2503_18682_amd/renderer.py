@@ -224,6 +224,23 @@ class Renderer:
                                                          _stream(self.device), C.byref(best), C.byref(ms)))
         return options_dict(best), ms.value
 
+    def autotune_training(self, g, cams, ws, outs, dL_drgb: List[torch.Tensor], reps=3, options=None):
+        """Tile shape of the fastest render + backward step (ws must carry
+        RGS_WS_BACKWARD); the timed backward passes go into scratch gradients."""
+        G = make_gaussians(g)
+        arr = make_cameras(cams)
+        o = make_options(options or self.options)
+        scratch = {k: torch.zeros_like(g[k]) for k in PARAM_KEYS}
+        GG = L.GaussianGrads(*(_ptr(scratch[k]) for k in PARAM_KEYS))
+        dl = [t.contiguous() for t in dL_drgb]
+        ptrs = (C.c_void_p * len(dl))(*[t.data_ptr() for t in dl])
+        best = L.Options()
+        ms = C.c_double()
+        _check(self.lib, self.ctx, self.lib.rgs_autotune_training(
+            self.ctx, C.byref(G), arr, len(cams), C.byref(o), C.byref(ws), self._view_outs(outs), ptrs, C.byref(GG),
+            int(reps), _stream(self.device), C.byref(best), C.byref(ms)))
+        return options_dict(best), ms.value
+
     # ------------------------------------------------------------------ timing
     def set_stage_timing(self, enable: bool):
         _check(self.lib, self.ctx, self.lib.rgs_set_stage_timing(self.ctx, 1 if enable else 0))

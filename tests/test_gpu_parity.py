@@ -327,6 +327,32 @@ def test_autotune_picks_a_supported_shape(r):
     assert ms > 0
 
 
+def test_training_autotune_picks_a_supported_shape_and_keeps_gradients_valid(r):
+    """The render + backward autotuner returns a supported shape, and a
+    backward pass at that shape still matches the default shape's."""
+    from paper_2503_18682_amd import _lib
+
+    sc = scenegen.tiny_scene(37, 2000, sh_degree=1)
+    cams = [scenegen.pinhole(scenegen.look_at((0, 0, -4)), 120, 100, 60)]
+    g = to_dev(sc)
+    say("case training autotune")
+    opts = scenegen.default_options()
+    buf, ws = r.new_workspace(2000, cams, 500000, _lib.RGS_WS_BACKWARD, opts)
+    outs = r.allocate_outputs(cams)
+    rng = np.random.default_rng(5)
+    dl = [torch.from_numpy(rng.normal(0, 1, (3, 100, 120)).astype(np.float32)).cuda()]
+    r.render_into(g, cams, outs, ws, opts)
+    best, ms = r.autotune_training(g, cams, ws, outs, dl, reps=2)
+    assert best["tile_w"] in (8, 16, 32) and best["tile_h"] in (8, 16, 32) and ms > 0
+    grads = {}
+    for label, o in (("default", opts), ("tuned", best)):
+        r.render_into(g, cams, outs, ws, o)
+        grads[label] = r.backward(g, cams, outs, dl, ws, o)
+    for k in grads["default"]:
+        a, b = grads["default"][k].cpu().numpy(), grads["tuned"][k].cpu().numpy()
+        assert np.abs(a - b).max() <= 1e-4 * max(np.abs(a).max(), 1e-6), k
+
+
 def test_view_clocks_leave_images_unchanged_and_order_in_time(r):
     """Per-view completion clocks: enabling them changes no output bit; every
     view's clock lies after the frame start and within the frame's host-side
