@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-steps", type=int, default=32, help="frames of the per-stage timing pass")
     ap.add_argument("--tile", default="8x16", help="tile shape WxH, each of 8, 16, 32")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="c4: use --tile instead of the training autotuner (for profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference for HBM counters)")
     return ap.parse_args()
@@ -351,11 +353,16 @@ def bench_c4(args, torch):
     del buf, ws
     buf, ws = r.new_workspace(n, cams, int(need * 1.1) + 4096, _lib.RGS_WS_BACKWARD, fine)
     outs = r.allocate_outputs(cams)
-    r.render_into(g, cams, outs, ws, fine)
-    dls = [torch.sign(o["rgb"] - t) / sum(t.numel() for t in targets) for o, t in zip(outs, targets)]
-    opts, tune_ms = r.autotune_training(g, cams, ws, outs, dls, reps=3)
-    log(f"c4: autotuned tile {opts['tile_w']}x{opts['tile_h']} ({tune_ms:.2f} ms per render + backward)")
-    del buf, ws, dls
+    if args.no_autotune:
+        opts, tile_from = dict(opts0, **tile_opts(args)), "--tile"
+    else:
+        r.render_into(g, cams, outs, ws, fine)
+        dls = [torch.sign(o["rgb"] - t) / sum(t.numel() for t in targets) for o, t in zip(outs, targets)]
+        opts, tune_ms = r.autotune_training(g, cams, ws, outs, dls, reps=3)
+        tile_from = "rgs_autotune_training"
+        log(f"c4: autotuned tile {opts['tile_w']}x{opts['tile_h']} ({tune_ms:.2f} ms per render + backward)")
+        del dls
+    del buf, ws
     _, (buf, ws) = r.render(g, cams, opts, flags=_lib.RGS_WS_BACKWARD, keep_workspace=True)
     need = r.status(ws)[1]
     del buf, ws
@@ -414,7 +421,7 @@ def bench_c4(args, torch):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "c4: 6M Gaussians (SH3), 16 uneven cameras, autotuned, forward + L1 + backward",
                    "views": [[c["width"], c["height"]] for c in cams], "megapixels": pixels / 1e6,
-                   "tile": [opts["tile_w"], opts["tile_h"]], "tile_from": "rgs_autotune_training",
+                   "tile": [opts["tile_w"], opts["tile_h"]], "tile_from": tile_from,
                    "instance_capacity": capacity},
         "forward_ms": fwd / steps, "backward_ms": bwd / steps,
         "forward_megapixels_per_s": pixels / 1e6 / (fwd / steps * 1e-3),

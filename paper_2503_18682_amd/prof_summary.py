@@ -187,7 +187,7 @@ def write_traffic_table(fetch_csv, write_csv, stats_csv, copy_mib, out, command,
         fb, wb = e.get("FETCH_SIZE", 0.0), e.get("WRITE_SIZE", 0.0)
         us = total_ns.get(k, 0.0) / trace_frames / 1e3
         gbs = (fb + wb) / (us * 1e-6) / 1e9 if us > 0 else 0.0
-        lines.append(f"{k} | {e.get('calls_FETCH_SIZE', 0.0):.0f} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {us:.1f} | "
+        lines.append(f"{k} | {e.get('calls_FETCH_SIZE', 0.0):.2g} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {us:.1f} | "
                      f"{gbs:.0f}")
     with open(out, "w") as fo:
         fo.write("\n".join(lines) + "\n")
