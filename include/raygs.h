@@ -93,7 +93,11 @@ typedef struct {
     int32_t mip;           /* 1 = approximate MIP of Sec. 5, eq. 17; default 0 */
     double mip_sigma2_px;  /* MIP pixel variance in px^2 (Sec. 6 uses 0.1); >= 0 */
     double background[3];  /* added as T_final * background; default 0 */
-    int32_t tile_w, tile_h;/* each 8, 16 or 32; 0, 0 = library default (16x16) */
+    int32_t tile_w, tile_h;/* each 8, 16 or 32; 0, 0 = the shape rgs_autotune_training or rgs_autotune
+                              last chose on this context for the same configuration class (render or
+                              training step, MIP, Gaussian count in octaves, each view's pixel count in
+                              half-octaves), training choices first, else 8x16; resolved at every call,
+                              so query workspace sizes again after an autotune */
 } rgs_options;
 
 typedef struct {

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -51,6 +52,7 @@ struct rgs_context {
     int grid_fwd[64] = {0}, grid_bwd[64] = {0};
     unsigned long long *view_stamps = nullptr;  // rgs_set_view_clocks (caller-owned device memory)
     int view_stamps_views = 0;
+    std::map<std::string, TileShape> tune_cache;  // autotuned tile shapes by configuration class
 };
 
 struct rgs_plan {
@@ -92,10 +94,50 @@ rgs_status fail(rgs_context *ctx, rgs_status st, const char *fmt, ...)
         if (e_ != hipSuccess) return fail((ctx), RGS_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));  \
     } while (0)
 
+constexpr TileShape kDefaultTile{8, 16};
+
 TileShape shape_of(const rgs_options &o)
 {
-    if (o.tile_w == 0 && o.tile_h == 0) return TileShape{16, 16};
+    if (o.tile_w == 0 && o.tile_h == 0) return kDefaultTile;
     return TileShape{o.tile_w, o.tile_h};
+}
+
+// Configuration class of the tile-shape cache: render or training step,
+// MIP, the Gaussian count in octaves and each view's pixel count in
+// half-octaves (sorted).
+std::string tune_class(bool training, int64_t n, const rgs_camera *cams, int32_t n_views, const rgs_options &o)
+{
+    std::vector<int> px;
+    for (int v = 0; v < n_views; ++v)
+        px.push_back((int)std::lround(2.0 * std::log2(std::max(1.0, (double)cams[v].width * (double)cams[v].height))));
+    std::sort(px.begin(), px.end());
+    std::string k = std::string(training ? "t" : "r") + std::to_string(o.mip) + "/" +
+                    std::to_string((int)std::floor(std::log2((double)n + 1.0)));
+    for (int x : px) k += "," + std::to_string(x);
+    return k;
+}
+
+// Options with tile_w = tile_h = 0 resolved: the shape the autotuners last
+// chose on this context for the same configuration class (a training-step
+// choice first), else the default.
+rgs_options resolve_tiles(const rgs_context *ctx, int64_t n, const rgs_camera *cams, int32_t n_views,
+                          const rgs_options *opts)
+{
+    rgs_options o = *opts;
+    if (o.tile_w != 0 || o.tile_h != 0) return o;
+    TileShape s = kDefaultTile;
+    if (ctx && cams && n_views > 0 && n >= 0) {
+        for (const bool training : {true, false}) {
+            const auto it = ctx->tune_cache.find(tune_class(training, n, cams, n_views, o));
+            if (it != ctx->tune_cache.end()) {
+                s = it->second;
+                break;
+            }
+        }
+    }
+    o.tile_w = s.w;
+    o.tile_h = s.h;
+    return o;
 }
 
 int shape_index(TileShape s)
@@ -465,9 +507,10 @@ const char *rgs_stage_names(void) { return kStageNames; }
 rgs_status rgs_workspace_size(rgs_context *ctx, int64_t n, const rgs_camera *cams, int32_t n_views,
                               const rgs_options *opts, int64_t capacity, int32_t flags, size_t *bytes)
 {
-    if (!bytes) return fail(ctx, RGS_EINVAL, "NULL argument");
+    if (!bytes || !opts) return fail(ctx, RGS_EINVAL, "NULL argument");
+    const rgs_options ro = resolve_tiles(ctx, n, cams, n_views, opts);
     Layout L;
-    const rgs_status st = compute_layout(ctx, n, cams, n_views, opts, capacity, flags, L);
+    const rgs_status st = compute_layout(ctx, n, cams, n_views, &ro, capacity, flags, L);
     if (st != RGS_OK) return st;
     *bytes = L.total;
     return RGS_OK;
@@ -477,9 +520,10 @@ rgs_status rgs_get_workspace_layout(rgs_context *ctx, int64_t n, const rgs_camer
                                     const rgs_options *opts, int64_t capacity, int32_t flags,
                                     rgs_workspace_layout *out)
 {
-    if (!out) return fail(ctx, RGS_EINVAL, "NULL argument");
+    if (!out || !opts) return fail(ctx, RGS_EINVAL, "NULL argument");
+    const rgs_options ro = resolve_tiles(ctx, n, cams, n_views, opts);
     Layout L;
-    const rgs_status st = compute_layout(ctx, n, cams, n_views, opts, capacity, flags, L);
+    const rgs_status st = compute_layout(ctx, n, cams, n_views, &ro, capacity, flags, L);
     if (st != RGS_OK) return st;
     fill_public_layout(L, out);
     return RGS_OK;
@@ -493,17 +537,20 @@ rgs_status rgs_render(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera
     rgs_status st = check_gaussians(ctx, g);
     if (st != RGS_OK) return st;
     if (!ws) return fail(ctx, RGS_EINVAL, "workspace is NULL");
+    if (!opts) return fail(ctx, RGS_EINVAL, "opts is NULL");
+    const rgs_options ro = resolve_tiles(ctx, g->n, cams, n_views, opts);
+    opts = &ro;
     Layout L;
     if ((st = compute_layout(ctx, g->n, cams, n_views, opts, ws->capacity, ws->flags, L)) != RGS_OK) return st;
     if ((st = check_workspace(ctx, ws, L)) != RGS_OK) return st;
     if ((st = check_outs(ctx, outs, n_views)) != RGS_OK) return st;
+    if (ctx->view_stamps && n_views > ctx->view_stamps_views)
+        return fail(ctx, RGS_EINVAL, "%d views exceed the %d of the view clock buffer", n_views,
+                    ctx->view_stamps_views);
     hipStream_t s = static_cast<hipStream_t>(stream);
     RGS_HIP(ctx, hipSetDevice(ctx->device));
     const std::vector<unsigned char> hdr = build_header(L, cams, n_views, outs, nullptr);
     RGS_HIP(ctx, hipMemcpyAsync(ws->ptr, hdr.data(), hdr.size(), hipMemcpyHostToDevice, s));
-    if (ctx->view_stamps && n_views > ctx->view_stamps_views)
-        return fail(ctx, RGS_EINVAL, "%d views exceed the %d of the view clock buffer", n_views,
-                    ctx->view_stamps_views);
     st = enqueue_forward(ctx, *g, n_views, *opts, L, ws->ptr, s, true, ctx->view_stamps);
     if (st == RGS_OK && ctx->timing) ++ctx->frames;  // frames whose stages were timed
     return st;
@@ -532,6 +579,9 @@ rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const r
     rgs_status st = check_gaussians(ctx, g);
     if (st != RGS_OK) return st;
     if (!ws) return fail(ctx, RGS_EINVAL, "workspace is NULL");
+    if (!opts) return fail(ctx, RGS_EINVAL, "opts is NULL");
+    const rgs_options ro = resolve_tiles(ctx, g->n, cams, n_views, opts);
+    opts = &ro;
     Layout L;
     if ((st = compute_layout(ctx, g->n, cams, n_views, opts, ws->capacity, ws->flags, L)) != RGS_OK) return st;
     if ((st = check_workspace(ctx, ws, L)) != RGS_OK) return st;
@@ -577,6 +627,9 @@ rgs_status rgs_batch_plan(rgs_context *ctx, int64_t n, int32_t sh_degree, const 
     if (!ctx || !out || !ws_bytes) return fail(ctx, RGS_EINVAL, "NULL argument");
     *out = nullptr;
     if (sh_degree < 0 || sh_degree > 3) return fail(ctx, RGS_EINVAL, "sh_degree outside 0..3");
+    if (!opts) return fail(ctx, RGS_EINVAL, "opts is NULL");
+    const rgs_options ro = resolve_tiles(ctx, n, cams, n_views, opts);
+    opts = &ro;
     Layout L;
     const rgs_status st = compute_layout(ctx, n, cams, n_views, opts, capacity, flags, L);
     if (st != RGS_OK) return st;
@@ -739,6 +792,7 @@ rgs_status autotune_shapes(rgs_context *ctx, const rgs_gaussians *g, const rgs_c
                                        : result;
     *best = chosen;
     *best_ms = best_t;
+    ctx->tune_cache[tune_class(dL_drgb != nullptr, g->n, cams, n_views, *opts)] = shape_of(chosen);
     return RGS_OK;
 }
 

@@ -19,7 +19,7 @@ from . import _lib as L
 PARAM_KEYS = ("means", "log_scales", "quats", "opacity_logits", "sh")
 
 DEFAULT_OPTIONS = dict(p_min=1.0 / 255.0, alpha_max=0.99, t_eps=1e-4, near_z=0.2, mip=0, mip_sigma2_px=0.1,
-                       background=(0.0, 0.0, 0.0), tile_w=16, tile_h=16)
+                       background=(0.0, 0.0, 0.0), tile_w=0, tile_h=0)  # 0, 0: tuned shape or 8x16
 
 
 def _check(lib, ctx, status):
@@ -168,11 +168,21 @@ class Renderer:
             _check(self.lib, self.ctx, st)
         return st == L.RGS_OK, inst.value
 
+    def resolve_options(self, n, cams, options=None) -> dict:
+        """Options with tile (0, 0) replaced by the shape the library resolves
+        for this configuration now (the context's tuned shape, else 8x16)."""
+        o = dict(options or self.options)
+        if int(o.get("tile_w", 0)) == 0 and int(o.get("tile_h", 0)) == 0:
+            lay = self.layout(n, cams, 1, 0, o)
+            o["tile_w"], o["tile_h"] = int(lay.tile_w), int(lay.tile_h)
+        return o
+
     def render(self, g, cams, options=None, flags=0, check=True, keep_workspace=False):
         """Render every camera; returns a list of dicts (rgb [3,H,W], final_T, n_contrib).
         With check=True the instance count is verified (host sync) and the
         workspace grows and the frame is re-rendered on overflow."""
         n = int(g["opacity_logits"].shape[0])
+        options = self.resolve_options(n, cams, options)
         key = (n, tuple((int(c["width"]), int(c["height"])) for c in cams), flags,
                tuple(sorted((options or self.options).items())) if isinstance(options or self.options, dict) else None)
         cap = self._capacity.get(key) or self.default_capacity(n, len(cams))
@@ -320,6 +330,8 @@ class RenderFunction(torch.autograd.Function):
     def forward(ctx, renderer: Renderer, cams, options, sh_degree, means, log_scales, quats, opacity_logits, sh):
         g = dict(means=means.contiguous(), log_scales=log_scales.contiguous(), quats=quats.contiguous(),
                  opacity_logits=opacity_logits.contiguous(), sh=sh.contiguous(), sh_degree=sh_degree)
+        # the backward must see the forward's tile shape
+        options = renderer.resolve_options(int(means.shape[1]), cams, options)
         outs, (buf, ws) = renderer.render(g, cams, options, flags=L.RGS_WS_BACKWARD, check=True, keep_workspace=True)
         ctx.renderer, ctx.cams, ctx.options, ctx.g, ctx.outs, ctx.ws_buf, ctx.ws = renderer, cams, options, g, outs, buf, ws
         return tuple(o["rgb"] for o in outs)

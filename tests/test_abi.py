@@ -129,11 +129,11 @@ def test_workspace_layout(lib):
     assert lay2.record_grads >= lay.total_bytes - 256 and lay2.total_bytes >= lay.total_bytes + 2000 * 64
     big = _size(lib, n, arr, nv, opts, 50000)[1]
     assert big - lay.total_bytes >= 45000 * 16
-    # default tile shape (0, 0) is 16x16
+    # tile shape (0, 0) with no tuned shape (no context) is the default 8x16
     _, a3, _, o3 = _args(n=10, tile_w=0, tile_h=0)
     lay3 = _lib.WorkspaceLayout()
     lib.rgs_get_workspace_layout(None, 10, a3, 1, C.byref(o3), 100, 0, C.byref(lay3))
-    assert (lay3.tile_w, lay3.tile_h, lay3.total_tiles) == (16, 16, 4 * 3)
+    assert (lay3.tile_w, lay3.tile_h, lay3.total_tiles) == (8, 16, 8 * 3)
 
 
 def test_create_without_gpu_fails_cleanly(lib):

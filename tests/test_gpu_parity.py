@@ -344,6 +344,9 @@ def test_training_autotune_picks_a_supported_shape_and_keeps_gradients_valid(r):
     r.render_into(g, cams, outs, ws, opts)
     best, ms = r.autotune_training(g, cams, ws, outs, dl, reps=2)
     assert best["tile_w"] in (8, 16, 32) and best["tile_h"] in (8, 16, 32) and ms > 0
+    # tile (0, 0) now resolves to the tuned shape on this context
+    lay = r.layout(2000, cams, 500000, _lib.RGS_WS_BACKWARD, dict(opts, tile_w=0, tile_h=0))
+    assert (lay.tile_w, lay.tile_h) == (best["tile_w"], best["tile_h"])
     grads = {}
     for label, o in (("default", opts), ("tuned", best)):
         r.render_into(g, cams, outs, ws, o)
