@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the MI355X ray-based Gaussian splatting renderer.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c2|c3]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c2|c3|c4]
 
 Workloads (synthetic, seeded; see scenegen/scenes.py):
   c1 (default)  500k Gaussians (64 clusters, SH3), one 1920x1080 camera at 50 deg

@@ -165,7 +165,8 @@ rgs_status rgs_render_status(rgs_context *ctx, const rgs_workspace *ws, void *st
  * dL_drgb[v] (device [3][H][W] per view) for the frame last rendered into
  * `ws` (which must carry RGS_WS_BACKWARD) with the same g, cams, opts and
  * outs.  Walks each pixel's list back from n_contrib starting at final_T.
- * Gradients are added into `grads`.  opts->mip = 1 returns RGS_EUNSUPPORTED.
+ * Gradients are added into `grads`.  With opts->mip = 1 they also flow
+ * through the MIP widening and opacity modulation (eq. 17).
  * Uses float atomics: results are order-nondeterministic in the last bits. */
 rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
                                const rgs_options *opts, const rgs_workspace *ws, const rgs_view_out *outs,

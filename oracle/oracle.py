@@ -180,7 +180,7 @@ def backward(scene, cam, opts, dL_dC):
     rc = lib.orc_backward(C.byref(s.struct), C.byref(c), C.byref(o), _ptr(dl), _ptr(g["means"]),
                           _ptr(g["log_scales"]), _ptr(g["quats"]), _ptr(g["opacity_logits"]), _ptr(g["sh"]))
     if rc != 0:
-        raise ValueError("oracle backward does not differentiate the MIP transform")
+        raise ValueError(f"oracle backward failed ({rc})")
     return g
 
 

@@ -856,7 +856,9 @@ int orc_render_pixels(const orc_scene *sc, const orc_camera *cam, const orc_opti
  * Gradients of L with respect to every parameter, given dL/dC for each output
  * pixel (dL_dC is [3][H][W]; pixels whose three entries are zero are skipped).
  * Results are ADDED into the gradient arrays (same shapes as the inputs).
- * MIP is not differentiated (returns -1 when opt->mip is set).
+ * With MIP (Sec. 5, eq. 17) the rendered scales and opacity are functions of
+ * the parameters and of mu (through tau = |mu|); their gradients are chained
+ * through that transform per Gaussian (see mip_chain below).
  *
  * Compositing adjoint of eq. (1): with T_i the transmittance in front of
  * Gaussian i, dL/d rgb_i = T_i a_i g and
@@ -870,10 +872,56 @@ typedef struct {
     double d_mu[3], d_Rp[9], d_l[3], d_o, d_rgb[3];
 } splat_grad;
 
+/* Chain through the eq. (17) transform.  With s0 = exp(l), o0 = sigmoid(a),
+ * ml = R_p^T mu, sigma^2 the pixel area at unit distance and tau^2 = |mu|^2:
+ *   s_k^2 = s0_k^2 + sigma^2 tau^2,
+ *   log o = log o0 + log|S0| + (1/2) log c2p - log|S| - (1/2) log c2h,
+ *   c2p = sum_k ml_k^2 / s0_k^2,  c2h = sum_k ml_k^2 / s_k^2.
+ * Given dL/dlog s_k (d_l) and dL/do (d_o) of the rendered values, adds the
+ * gradients with respect to log s0 (d_l0), mu (d_mu) and R_p (d_Rp) and
+ * returns dL/dlog o0. */
+static double mip_chain(const double *mu, const double *Rp, const double *s0, const double *s, double sigma2,
+                        const double *d_l, double d_o, double o, double *d_l0, double *d_mu, double *d_Rp)
+{
+    double ml[3];
+    mat3t_vec(Rp, mu, ml);
+    double c2p = 0.0, c2h = 0.0, ml2s4 = 0.0, inv_s2sum = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        c2p += ml[k] * ml[k] / (s0[k] * s0[k]);
+        c2h += ml[k] * ml[k] / (s[k] * s[k]);
+        ml2s4 += ml[k] * ml[k] / (s[k] * s[k] * s[k] * s[k]);
+        inv_s2sum += 1.0 / (s[k] * s[k]);
+    }
+    const double Lo = d_o * o; /* dL/dlog o */
+    double gmu[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k) {
+        const double r = s0[k] * s0[k] / (s[k] * s[k]); /* dlog s_k / dlog s0_k */
+        /* through log s_k directly and through log o (|S0|, c2p, |S|, c2h) */
+        d_l0[k] += d_l[k] * r +
+                   Lo * (1.0 - ml[k] * ml[k] / (s0[k] * s0[k]) / c2p - r + ml[k] * ml[k] / (s[k] * s[k]) * r / c2h);
+        /* dlog s_k / dmu = sigma^2 mu / s_k^2 */
+        for (int j = 0; j < 3; ++j) gmu[j] += d_l[k] * sigma2 * mu[j] / (s[k] * s[k]);
+    }
+    /* log o through ml (c2p, c2h) and through tau (|S| and c2h) */
+    double a0[3], a1[3], v0[3], v1[3];
+    for (int k = 0; k < 3; ++k) {
+        a0[k] = ml[k] / (s0[k] * s0[k]);
+        a1[k] = ml[k] / (s[k] * s[k]);
+    }
+    mat3_vec(Rp, a0, v0);
+    mat3_vec(Rp, a1, v1);
+    for (int j = 0; j < 3; ++j)
+        gmu[j] += Lo * (v0[j] / c2p - v1[j] / c2h - sigma2 * mu[j] * inv_s2sum + sigma2 * mu[j] * ml2s4 / c2h);
+    for (int j = 0; j < 3; ++j) d_mu[j] += gmu[j];
+    /* ml_k = sum_r R_p[r][k] mu_r */
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) d_Rp[3 * r + k] += Lo * mu[r] * (a0[k] / c2p - a1[k] / c2h);
+    return Lo;
+}
+
 int orc_backward(const orc_scene *sc, const orc_camera *cam, const orc_options *opt, const double *dL_dC,
                  double *g_means, double *g_log_scales, double *g_quats, double *g_opacity, double *g_sh)
 {
-    if (opt->mip) return -1;
     int64_t n = sc->n;
     const int W = cam->width, H = cam->height;
     orc_splat *sp = (orc_splat *)malloc(sizeof(orc_splat) * (n ? n : 1));
@@ -958,16 +1006,29 @@ int orc_backward(const orc_scene *sc, const orc_camera *cam, const orc_options *
         const orc_splat *s = &sp[i];
         if (s->cull != ORC_VISIBLE) continue;
         const splat_grad *G = &gg[i];
+        double d_mu[3], d_Rp[9], d_l0[3], Lo;
+        const double o0 = 1.0 / (1.0 + exp(-sc->opacity_logits[i]));
+        memcpy(d_mu, G->d_mu, sizeof d_mu);
+        memcpy(d_Rp, G->d_Rp, sizeof d_Rp);
+        if (opt->mip) {
+            const double s0[3] = {exp(sc->log_scales[i]), exp(sc->log_scales[n + i]), exp(sc->log_scales[2 * n + i])};
+            for (int k = 0; k < 3; ++k) d_l0[k] = 0.0;
+            Lo = mip_chain(s->mu, s->Rp, s0, s->s, opt->mip_sigma2_px / (cam->fx * cam->fy), G->d_l, G->d_o, s->o,
+                           d_l0, d_mu, d_Rp);
+        } else {
+            /* log-scales (s = exp(l) enters Sigma^-1 only) */
+            for (int k = 0; k < 3; ++k) d_l0[k] = G->d_l[k];
+            Lo = G->d_o * s->o;
+        }
         /* means through mu = W m + t */
         double dm[3];
-        mat3t_vec(Wr, G->d_mu, dm);
-        /* log-scales (s = exp(l) enters Sigma^-1 only) */
-        for (int k = 0; k < 3; ++k) g_log_scales[k * n + i] += G->d_l[k];
+        mat3t_vec(Wr, d_mu, dm);
+        for (int k = 0; k < 3; ++k) g_log_scales[k * n + i] += d_l0[k];
         /* rotation: dL/dR = W^T dL/dR_p, then the quaternion */
         double dR[9];
         for (int r = 0; r < 3; ++r)
             for (int cc = 0; cc < 3; ++cc)
-                dR[3 * r + cc] = Wr[r] * G->d_Rp[cc] + Wr[3 + r] * G->d_Rp[3 + cc] + Wr[6 + r] * G->d_Rp[6 + cc];
+                dR[3 * r + cc] = Wr[r] * d_Rp[cc] + Wr[3 + r] * d_Rp[3 + cc] + Wr[6 + r] * d_Rp[6 + cc];
         double q[4];
         for (int k = 0; k < 4; ++k) q[k] = sc->quats[k * n + i];
         double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
@@ -983,9 +1044,8 @@ int orc_backward(const orc_scene *sc, const orc_camera *cam, const orc_options *
         double qh[4] = {w, x, y, z};
         double proj = qh[0] * dq[0] + qh[1] * dq[1] + qh[2] * dq[2] + qh[3] * dq[3];
         for (int k = 0; k < 4; ++k) g_quats[k * n + i] += (dq[k] - qh[k] * proj) / qn;
-        /* opacity logit */
-        double o = s->o;
-        g_opacity[i] += G->d_o * o * (1.0 - o);
+        /* opacity logit: dlog o0 / da = 1 - o0 */
+        g_opacity[i] += Lo * (1.0 - o0);
         /* SH coefficients and the view direction */
         double Y[16], dY[48];
         orc_sh_basis(sc->sh_degree, s->dir, Y, dY);

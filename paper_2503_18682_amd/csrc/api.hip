@@ -587,7 +587,6 @@ rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const r
     if ((st = check_workspace(ctx, ws, L)) != RGS_OK) return st;
     if ((st = check_outs(ctx, outs, n_views)) != RGS_OK) return st;
     if (!(ws->flags & RGS_WS_BACKWARD)) return fail(ctx, RGS_EINVAL, "workspace lacks RGS_WS_BACKWARD");
-    if (opts->mip) return fail(ctx, RGS_EUNSUPPORTED, "the MIP transform is not differentiated");
     if (!dL_drgb) return fail(ctx, RGS_EINVAL, "dL_drgb is NULL");
     for (int v = 0; v < n_views; ++v)
         if (!dL_drgb[v]) return fail(ctx, RGS_EINVAL, "dL_drgb[%d] is NULL", v);

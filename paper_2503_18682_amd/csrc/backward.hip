@@ -17,12 +17,56 @@
 namespace rgs {
 namespace {
 
+// Chain through the MIP transform (Sec. 5, eq. 17).  With s0 the scales,
+// o0 the prior opacity, ml = R_p^T mu and tau^2 = |mu|^2:
+//   s_k^2 = s0_k^2 + sigma^2 tau^2,
+//   log o = log o0 + log|S0| + (1/2) log c2p - log|S| - (1/2) log c2h,
+//   c2p = sum_k ml_k^2 / s0_k^2,  c2h = sum_k ml_k^2 / s_k^2.
+// Given dL/dlog s_k (dls) and dL/dlog o (Lo) of the rendered values, adds
+// the gradients with respect to log s0 (dl), mu (dmu) and R_p (dRp).
+__device__ void mip_chain(const double (&mu)[3], const double (&Rp)[9], const double (&s0)[3], const double (&s)[3],
+                          double sigma2, const double (&dls)[3], double Lo, double (&dl)[3], double (&dmu)[3],
+                          double (&dRp)[9])
+{
+    double ml[3], is0[3], is[3];
+    for (int k = 0; k < 3; ++k) {
+        ml[k] = Rp[k] * mu[0] + Rp[3 + k] * mu[1] + Rp[6 + k] * mu[2];
+        is0[k] = 1.0 / (s0[k] * s0[k]);
+        is[k] = 1.0 / (s[k] * s[k]);
+    }
+    double c2p = 0.0, c2h = 0.0, ml2s4 = 0.0, is_sum = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        c2p += ml[k] * ml[k] * is0[k];
+        c2h += ml[k] * ml[k] * is[k];
+        ml2s4 += ml[k] * ml[k] * is[k] * is[k];
+        is_sum += is[k];
+    }
+    const double ic2p = 1.0 / c2p, ic2h = 1.0 / c2h;
+    double tau_term = 0.0;  // dL/dlog s_k summed against dlog s_k / d(tau^2)
+    for (int k = 0; k < 3; ++k) {
+        const double r = s0[k] * s0[k] * is[k];  // dlog s_k / dlog s0_k
+        dl[k] += dls[k] * r + Lo * (1.0 - ml[k] * ml[k] * is0[k] * ic2p - r + ml[k] * ml[k] * is[k] * r * ic2h);
+        tau_term += dls[k] * is[k];
+    }
+    double a0[3], a1[3];
+    for (int k = 0; k < 3; ++k) {
+        a0[k] = ml[k] * is0[k] * ic2p - ml[k] * is[k] * ic2h;  // dlog o / d ml_k
+        a1[k] = Lo * a0[k];
+    }
+    const double mu_coef = sigma2 * (tau_term + Lo * (ml2s4 * ic2h - is_sum));
+    for (int j = 0; j < 3; ++j)
+        dmu[j] += mu_coef * mu[j] + Rp[3 * j] * a1[0] + Rp[3 * j + 1] * a1[1] + Rp[3 * j + 2] * a1[2];
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) dRp[3 * r + k] += a1[k] * mu[r];
+}
+
 // Geometry and opacity (the colour part is k_colour_bwd).
 __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const float *__restrict__ means, const float *__restrict__ log_scales, const float *__restrict__ quats,
     const float *__restrict__ opacity_logits, int n, const DevView *__restrict__ views, int n_views,
-    const uint32_t *__restrict__ tile_counts, const float *__restrict__ record_grads, float *__restrict__ g_means,
-    float *__restrict__ g_log_scales, float *__restrict__ g_quats, float *__restrict__ g_opacity)
+    const uint32_t *__restrict__ tile_counts, const float *__restrict__ record_grads, DevOptions opt,
+    float *__restrict__ g_means, float *__restrict__ g_log_scales, float *__restrict__ g_quats,
+    float *__restrict__ g_opacity)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -61,9 +105,28 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         double Rp[9];
         for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c) Rp[3 * r + c] = W[4 * r] * R[c] + W[4 * r + 1] * R[3 + c] + W[4 * r + 2] * R[6 + c];
+        // rendered scales and opacity: widened by the MIP transform when it is on
+        double sv[3] = {s[0], s[1], s[2]}, isv[3] = {is[0], is[1], is[2]};
+        double ov = o;
+        const double sig2 = opt.mip ? opt.mip_sigma2_px / (V.fx * V.fy) : 0.0;
+        if (opt.mip) {
+            const double tb2 = mu[0] * mu[0] + mu[1] * mu[1] + mu[2] * mu[2];
+            double det = 1.0, deth = 1.0, c2p = 0.0, c2h = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const double ml = Rp[k] * mu[0] + Rp[3 + k] * mu[1] + Rp[6 + k] * mu[2];
+                const double s2 = s[k] * s[k], sh2 = s2 + sig2 * tb2;
+                det *= s2;
+                deth *= sh2;
+                c2p += ml * ml / s2;
+                c2h += ml * ml / sh2;
+                sv[k] = sqrt(sh2);
+                isv[k] = 1.0 / sv[k];
+            }
+            ov = o * sqrt(det * c2p / (deth * c2h));
+        }
         double A[3][3];  // A = S^-1 R_p^T
         for (int k = 0; k < 3; ++k)
-            for (int j = 0; j < 3; ++j) A[k][j] = Rp[3 * j + k] * is[k];
+            for (int j = 0; j < 3; ++j) A[k][j] = Rp[3 * j + k] * isv[k];
         double mw[3];
         for (int k = 0; k < 3; ++k) mw[k] = A[k][0] * mu[0] + A[k][1] * mu[1] + A[k][2] * mu[2];
         const double c2 = mw[0] * mw[0] + mw[1] * mw[1] + mw[2] * mw[2];
@@ -108,21 +171,27 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         dmu[1] += gv0 * V.fy * iz;
         dmu[2] += -(gu0 * V.fx * mu[0] + gv0 * V.fy * mu[1]) * iz * iz;
         // A[k][j] = R_p[j][k] / s_k
-        double dRp[9];
+        double dRp[9], dls[3];
         for (int k = 0; k < 3; ++k) {
             double acc = 0.0;
             for (int j = 0; j < 3; ++j) {
-                dRp[3 * j + k] = dA[k][j] * is[k];
+                dRp[3 * j + k] = dA[k][j] * isv[k];
                 acc += dA[k][j] * A[k][j];
             }
-            dl[k] -= acc;
+            dls[k] = -acc;
+        }
+        // the record's opacity is ov: dL/dlog ov = go ov
+        if (opt.mip) {
+            mip_chain(mu, Rp, s, sv, sig2, dls, go * ov, dl, dmu, dRp);
+        } else {
+            for (int k = 0; k < 3; ++k) dl[k] += dls[k];
         }
         // R_p = W_rot R, mu = W_rot m + t
         for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c) dR[3 * r + c] += W[r] * dRp[c] + W[4 + r] * dRp[3 + c] + W[8 + r] * dRp[6 + c];
         for (int c = 0; c < 3; ++c) dm[c] += W[c] * dmu[0] + W[4 + c] * dmu[1] + W[8 + c] * dmu[2];
-        // prior opacity
-        da += go * o * (1.0 - o);
+        // prior opacity: dlog o / da = 1 - o
+        da += go * ov * (1.0 - o);
     }
     // quaternion: dR/d(w,x,y,z) of the unit quaternion, then the normalisation
     const double J[9][4] = {{0, 0, -4 * y, -4 * z},       {-2 * z, 2 * y, 2 * x, -2 * w}, {2 * y, 2 * z, 2 * w, 2 * x},
@@ -208,12 +277,11 @@ hipError_t launch_preprocess_backward(const rgs_gaussians &g, const DevView *vie
                                       const DevOptions &opt, const uint32_t *tile_counts, const float *record_grads,
                                       const rgs_gaussian_grads &gr, hipStream_t stream)
 {
-    (void)opt;
     const int n = (int)g.n;
     if (n == 0) return hipSuccess;
     const dim3 grid((n + 255) / 256), block(256);
     k_preprocess_bwd<<<grid, block, 0, stream>>>(g.means, g.log_scales, g.quats, g.opacity_logits, n, views, n_views,
-                                                 tile_counts, record_grads, gr.means, gr.log_scales, gr.quats,
+                                                 tile_counts, record_grads, opt, gr.means, gr.log_scales, gr.quats,
                                                  gr.opacity_logits);
     // after k_preprocess_bwd on the same stream: both add into gr.means
 #define RGS_BWD(D)                                                                                                  \

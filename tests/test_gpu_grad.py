@@ -125,16 +125,50 @@ def test_autograd_function_matches_direct_backward(r):
         assert torch.allclose(a, b, rtol=1e-4, atol=1e-7 * float(b.abs().max() + 1e-30)), k
 
 
-def test_mip_backward_is_unsupported(r):
+def test_mip_fd_subcase_l1(r):
+    """MIP on (eq. 17) with a large pixel filter: gradients through the
+    widening and the opacity modulation against the oracle's (pinned to
+    finite differences)."""
     from paper_2503_18682_amd import _lib
 
-    scene, cam = scenegen.fd_subcase()
-    opts = scenegen.default_options(mip=1)
+    scene, cam = scenegen.fd_subcase(seed=2004)
+    opts = scenegen.default_options(mip=1, mip_sigma2_px=4.0)
+    say("case grad MIP fd-subcase 64 Gaussians 32x32")
     g = to_dev(scene)
     outs, (buf, ws) = r.render(g, [cam], opts, flags=_lib.RGS_WS_BACKWARD, keep_workspace=True)
-    with pytest.raises(_lib.RayGSError) as e:
-        r.backward(g, [cam], outs, [torch.zeros_like(outs[0]["rgb"])], ws, opts)
-    assert e.value.status == _lib.RGS_EUNSUPPORTED
+    img = outs[0]["rgb"].cpu().numpy()
+    target = np.random.default_rng(6).uniform(0, 1, img.shape)
+    dl = _l1_grad(img, target, img.size).astype(np.float32)
+    grads = r.backward(g, [cam], outs, [torch.from_numpy(dl).cuda()], ws, opts)
+    ref = oracle.backward(scene, cam, opts, dl.astype(np.float64))
+    _compare(grads, ref, "MIP fd-subcase")
+
+
+def test_mip_multi_view_sparse_pixels(r):
+    """Two views with MIP at the default pixel filter (0.1 px^2)."""
+    from paper_2503_18682_amd import _lib
+
+    sc = scenegen.tiny_scene(42, 20000, sh_degree=2, half_extent=1.5, log_scale_mean=-4.0, log_scale_std=0.6)
+    cams = [scenegen.pinhole(scenegen.look_at((0, 0.5, -4)), 320, 212, 50),
+            scenegen.pinhole(scenegen.look_at((2.5, 0.0, -3)), 160, 240, 60)]
+    opts = scenegen.default_options(mip=1)
+    say("case grad MIP 2 views, 20000 Gaussians, sparse pixels")
+    g = to_dev(sc)
+    outs, (buf, ws) = r.render(g, cams, opts, flags=_lib.RGS_WS_BACKWARD, keep_workspace=True)
+    rng = np.random.default_rng(5)
+    dls = []
+    ref = {k: np.zeros(sc[k].shape) for k in PARAM_KEYS}
+    for v, cam in enumerate(cams):
+        H, W = cam["height"], cam["width"]
+        dl = np.zeros((3, H, W), np.float32)
+        ys, xs = rng.integers(0, H, 300), rng.integers(0, W, 300)
+        dl[:, ys, xs] = rng.normal(0, 1, (3, 300)).astype(np.float32)
+        dls.append(torch.from_numpy(dl).cuda())
+        rv = oracle.backward(sc, cam, opts, dl.astype(np.float64))
+        for k in PARAM_KEYS:
+            ref[k] += rv[k]
+    grads = r.backward(g, cams, outs, dls, ws, opts)
+    _compare(grads, ref, "MIP 2-view sparse", rel=2e-3)
 
 
 def test_c3_full_size_sampled_gradients(r):

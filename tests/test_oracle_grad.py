@@ -3,8 +3,6 @@ differences (h = 1e-6) of the oracle's own forward render, on the 64-Gaussian
 32x32 SH3 subcase.  The loss is linear in the image, L = sum(w * C), so dL/dC = w;
 any loss enters the backward only through dL/dC."""
 import numpy as np
-import pytest
-
 import oracle
 import scenegen
 
@@ -61,7 +59,16 @@ def test_gradient_with_background_and_sparse_pixels(oracle_lib):
     _fd_check(scene, cam, opts, w, stride=3)
 
 
-def test_mip_backward_is_rejected(oracle_lib):
-    scene, cam = scenegen.fd_subcase()
-    with pytest.raises(ValueError):
-        oracle.backward(scene, cam, scenegen.default_options(mip=1), np.zeros((3, 32, 32)))
+def test_mip_gradient_matches_central_differences(oracle_lib):
+    """With the MIP transform (eq. 17) the rendered scales and opacity depend
+    on the scales, the opacity, the rotation and the mean (through |mu|); a
+    large pixel filter makes every one of those paths matter."""
+    scene, cam = scenegen.fd_subcase(seed=2004)
+    opts = scenegen.default_options(mip=1, mip_sigma2_px=4.0)
+    out = oracle.render(scene, cam, opts)
+    assert out["hazard"].sum() == 0
+    plain = oracle.render(scene, cam, scenegen.default_options())
+    assert np.abs(out["rgb"] - plain["rgb"]).max() > 1e-2  # the transform changes the image
+    w = np.random.default_rng(9).normal(0, 1, (3, 32, 32))
+    worst, count = _fd_check(scene, cam, opts, w)
+    assert count == 64 * 59
