@@ -14,6 +14,7 @@ from .oracle import (  # noqa: F401
     sh_basis,
     divergence,
     rot_mu_v,
+    mip_exact_weight,
     CULL,
     HAZARD,
 )

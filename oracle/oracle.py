@@ -55,7 +55,8 @@ SPLAT_DTYPE = np.dtype(
      ("all_front", np.int32), ("px0", np.int32), ("px1", np.int32), ("py0", np.int32), ("py1", np.int32),
      ("tx0", np.int32), ("tx1", np.int32), ("ty0", np.int32), ("ty1", np.int32), ("depth_key", np.uint32),
      ("pad", np.int32), ("rgb", np.float64, 3), ("rgb_raw", np.float64, 3), ("dir", np.float64, 3),
-     ("dist", np.float64), ("cq", np.float64, 6), ("bounded", np.int32), ("listed", np.int32)],
+     ("dist", np.float64), ("cq", np.float64, 6), ("bounded", np.int32), ("listed", np.int32),
+     ("s0", np.float64, 3), ("sig2", np.float64), ("exact", np.int32), ("whole", np.int32)],
     align=True,
 )
 
@@ -77,6 +78,8 @@ def load():
         lib.orc_divergence.argtypes = [P, P, P, P, P, P]
         lib.orc_divergence.restype = C.c_double
         lib.orc_rot_mu_v.argtypes = [P, P]
+        lib.orc_mip_exact_weight.argtypes = [P, P, P, C.c_double, C.c_double, P, P]
+        lib.orc_mip_exact_weight.restype = C.c_double
         lib.orc_splat_size.restype = C.c_int
         lib.orc_list_tiles.argtypes = [P, C.c_int64, P, C.c_int32, P, P, C.c_int64]
         lib.orc_list_tiles.restype = C.c_int64
@@ -223,6 +226,17 @@ def divergence(mu, Rp, s, x):
     e = np.zeros(3)
     D = lib.orc_divergence(_ptr(mu), _ptr(Rp), _ptr(s), _ptr(x), _ptr(tau), _ptr(e))
     return D, float(tau[0]), e
+
+
+def mip_exact_weight(mu, Rp, s, o, sig2, xbar):
+    """(omega, tau^) of the exact MIP density for the ray through xbar =
+    (u, v, 1) (normalised camera coordinates); sig2 is the pixel area at unit
+    distance at the principal point."""
+    lib = load()
+    mu, Rp, s, xbar = (np.ascontiguousarray(a, np.float64) for a in (mu, Rp, s, xbar))
+    tau = np.zeros(1)
+    w = lib.orc_mip_exact_weight(_ptr(mu), _ptr(Rp), _ptr(s), float(o), float(sig2), _ptr(xbar), _ptr(tau))
+    return w, float(tau[0])
 
 
 def rot_mu_v(muh):

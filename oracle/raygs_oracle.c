@@ -14,6 +14,8 @@
  *     Sigma = R_p S^2 R_p^T with R_p = W R(q / |q|), S = diag(exp(l)),
  *     o = sigmoid(a),
  *     optional MIP widening and opacity modulation (Sec. 5, eq. 17),
+ *     or, for the exact MIP density of Sec. 5 / App. B, a widened Gaussian
+ *     that bounds its support (see mip_exact_bound),
  *     kappa = -2 log(p_min / o) (eq. 3), skipped when kappa <= 0,
  *     c^2 = mu^T Sigma^-1 mu (eq. 6), skipped when c^2 <= kappa,
  *     the 3D quad V_ray = T_ray H(Z_ray) (Sec. 4.1, eqs. 12-15, App. A.1-A.3),
@@ -21,7 +23,8 @@
  *   per pixel
  *     every Gaussian whose box holds the pixel centre, in ascending
  *     (depth, index) order, with D_ray from its definition (eq. 5),
- *     omega = o exp(-D/2) (eq. 2), composited front to back (eq. 1).
+ *     omega = o exp(-D/2) (eq. 2), composited front to back (eq. 1);
+ *     with exact MIP, omega is the per-ray MIP weight (orc_mip_exact_weight).
  *   backward (not in the paper): the exact adjoint of the above, with the
  *     derivative of D_ray taken by the envelope theorem at tau (Prop. A.1).
  *
@@ -105,6 +108,10 @@ typedef struct {
     double cq[6];     /* support conic in pixel coordinates: A00, A01, A11, b0, b1, c */
     int32_t bounded;  /* the conic is an ellipse (A positive definite) */
     int32_t listed;   /* tiles listed for this Gaussian */
+    double s0[3];     /* exact MIP: scales of the Gaussian itself (s holds the bound's) */
+    double sig2;      /* exact MIP: sigma^2 at the principal point, per unit distance */
+    int32_t exact;    /* exact MIP weight per ray */
+    int32_t whole;    /* exact MIP without a bounding Gaussian: the whole view */
 } orc_splat;
 
 /* --------------------------------------------------------- small helpers */
@@ -220,6 +227,68 @@ double orc_divergence(const double *mu, const double *Rp, const double *s, const
     if (e_out)
         for (int k = 0; k < 3; ++k) e_out[k] = tau * x[k] - mu[k];
     return D;
+}
+
+/* Exact MIP weight of one ray (Sec. 5 and its derivation in App. B).
+ * xbar = (u, v, 1) is the ray through a pixel centre in normalised camera
+ * coordinates and x = xbar / |xbar| the unit ray.  With tau(x) the peak of the
+ * Gaussian's own density along x (eq. 5) and sigma_x^2 the area that one pixel
+ * subtends at unit distance along x (sigma^2 cos^3 theta, cos theta = 1/|xbar|,
+ * sigma^2 its value at the principal point):
+ *   Sigma^_x = Sigma + sigma_x^2 tau(x)^2 I   (the same rotation, variances
+ *              s_k^2 + sigma_x^2 tau^2),
+ *   omega = o m(x) exp(-D_ray(x; mu, Sigma^_x) / 2),
+ *   m(x)^2 = |Sigma| x^T Sigma^-1 x / (|Sigma^_x| x^T Sigma^_x^-1 x).
+ * m(x) is the ratio of the ray density's normalising factor with and without
+ * the widening (both written through the determinant identity of App. B), so
+ * it is 1 when sigma = 0 and equals the modulation of eq. (17) on the ray
+ * through mu.  *tau_h receives the peak of the widened density along x; the
+ * ray gets no contribution unless it is positive. */
+double orc_mip_exact_weight(const double *mu, const double *Rp, const double *s0, double o, double sig2,
+                            const double *xbar, double *tau_h)
+{
+    /* D_ray, the sign of the peak and the modulation do not depend on the
+     * length of the ray vector; tau of the unit ray is |xbar| tau(xbar) */
+    double nx = sqrt(dot3(xbar, xbar));
+    double tau;
+    orc_divergence(mu, Rp, s0, xbar, &tau, NULL);
+    tau *= nx;
+    double sx2 = sig2 / (nx * nx * nx);
+    double a = sx2 * tau * tau;
+    double sh[3], det = 1.0, deth = 1.0, xp = 0.0, xh = 0.0, xl[3];
+    mat3t_vec(Rp, xbar, xl);
+    for (int k = 0; k < 3; ++k) {
+        double s2 = s0[k] * s0[k];
+        sh[k] = sqrt(s2 + a);
+        det *= s2;
+        deth *= s2 + a;
+        xp += xl[k] * xl[k] / s2;
+        xh += xl[k] * xl[k] / (s2 + a);
+    }
+    double D = orc_divergence(mu, Rp, sh, xbar, tau_h, NULL);
+    return o * sqrt(det * xp / (deth * xh)) * exp(-0.5 * D);
+}
+
+/* Bound of the exact MIP support.  A ray contributes only if
+ * D_ray(x; mu, Sigma^_x) <= kappa (m <= 1, since det(F^T Sigma^_x F) >=
+ * det(F^T Sigma F) on the tangent plane of App. B).  For such a ray, with
+ * e = mu - tau^ x (tau^ the peak of the widened density), |e|^2 <= kappa
+ * (s_max^2 + a) and the plain peak differs from tau^ by at most
+ * |e| s_max / s_min, so |tau| <= |mu| + sqrt(kappa) (s_max + sigma |tau|)
+ * (1 + rho), rho = s_max / s_min.  With beta = sqrt(kappa) sigma (1 + rho) < 1
+ * this gives |tau| <= tau_max = (|mu| + sqrt(kappa) s_max (1 + rho)) / (1 - beta),
+ * hence sigma_x^2 tau^2 <= a_max = sigma^2 tau_max^2, and D_ray decreases as
+ * the covariance grows: the support lies inside the plain support (opacity o)
+ * of the Gaussian widened by a_max.  Returns a_max, or -1 when beta >= 1 (no
+ * bound: the whole view is listed; so it is when the bound holds the camera). */
+static double mip_exact_bound(const double *mu, const double *s, double kappa, double sig2)
+{
+    double smax = fmax(s[0], fmax(s[1], s[2])), smin = fmin(s[0], fmin(s[1], s[2]));
+    double rho = smax / smin;
+    double beta = sqrt(kappa * sig2) * (1.0 + rho);
+    if (!(beta < 1.0)) return -1.0;
+    double tmax = (sqrt(dot3(mu, mu)) + sqrt(kappa) * smax * (1.0 + rho)) / (1.0 - beta);
+    return sig2 * tmax * tmax;
 }
 
 /* R_{x,y} = 2 (x+y)(x+y)^T / |x+y|^2 - I (App. A.1) */
@@ -409,7 +478,7 @@ static void preprocess_one(const orc_scene *sc, int64_t i, const orc_camera *cam
     double s[3] = {exp(l[0]), exp(l[1]), exp(l[2])};
     double o = 1.0 / (1.0 + exp(-a));
 
-    if (opt->mip) {
+    if (opt->mip == 1) {
         /* Sec. 5, eq. (17): Sigma^ = Sigma + sigma^2 tau^2 I with a
          * pixel-invariant tau = |mu| (unit rays) and sigma^2 the pixel area at
          * unit distance; opacity modulated by sqrt(|Sigma| c^2 / (|Sigma^| c^^2)). */
@@ -430,6 +499,7 @@ static void preprocess_one(const orc_scene *sc, int64_t i, const orc_camera *cam
         for (int k = 0; k < 3; ++k) s[k] = sqrt(sh2[k]);
     }
     memcpy(sp->s, s, sizeof s);
+    memcpy(sp->s0, s, sizeof s);
     sp->o = o;
 
     /* kappa = -2 log(p_min / o), eq. (3); skip when kappa <= 0 */
@@ -439,6 +509,33 @@ static void preprocess_one(const orc_scene *sc, int64_t i, const orc_camera *cam
     if (!(kappa > 0.0)) {
         sp->cull = ORC_CULL_KAPPA;
         return;
+    }
+
+    if (opt->mip == 2) {
+        /* exact MIP: the quad, box and tiles below are those of the bounding
+         * Gaussian; the weight is evaluated per ray with the scales s0 */
+        sp->exact = 1;
+        sp->sig2 = opt->mip_sigma2_px / (cam->fx * cam->fy);
+        /* the camera-inside skip (eq. 6) applies to the Gaussian itself, as
+         * without MIP; a bound that holds the camera gives no quad, and
+         * then, as when there is no bound, the whole view is listed */
+        double ml0[3], c2g = 0.0, c2b = 0.0;
+        mat3t_vec(sp->Rp, mu, ml0);
+        for (int k = 0; k < 3; ++k) c2g += ml0[k] * ml0[k] / (s[k] * s[k]);
+        if (fabs(c2g - kappa) <= 1e-12 * c2g) sp->hazard |= ORC_HZ_CULL;
+        if (!(c2g > kappa)) {
+            sp->c2 = c2g;
+            sp->cull = ORC_CULL_INSIDE;
+            return;
+        }
+        double amax = mip_exact_bound(mu, s, kappa, sp->sig2);
+        for (int k = 0; k < 3; ++k) c2b += ml0[k] * ml0[k] / (s[k] * s[k] + amax);
+        if (amax < 0.0 || !(c2b > kappa)) {
+            sp->whole = 1;
+        } else {
+            for (int k = 0; k < 3; ++k) s[k] = sqrt(s[k] * s[k] + amax);
+            memcpy(sp->s, s, sizeof s);
+        }
     }
 
     /* c^2 = mu^T Sigma^-1 mu, eq. (6); skip when c^2 <= kappa (Prop. A.2) */
@@ -452,6 +549,17 @@ static void preprocess_one(const orc_scene *sc, int64_t i, const orc_camera *cam
     if (!(c2 > kappa)) {
         sp->cull = ORC_CULL_INSIDE;
         return;
+    }
+    if (sp->whole) {
+        /* no bounding Gaussian: every tile of the view is listed */
+        sp->all_front = 0;
+        sp->bbox[0] = -INFINITY; sp->bbox[1] = INFINITY; sp->bbox[2] = -INFINITY; sp->bbox[3] = INFINITY;
+        sp->px0 = 0; sp->px1 = cam->width - 1; sp->py0 = 0; sp->py1 = cam->height - 1;
+        sp->tx0 = 0; sp->tx1 = sp->px1 / opt->tile_w;
+        sp->ty0 = 0; sp->ty1 = sp->py1 / opt->tile_h;
+        sp->bounded = 0;
+        sp->listed = (sp->tx1 + 1) * (sp->ty1 + 1);
+        goto colour;
     }
 
     /* Sec. 4.1: mu^ = S^-1 R_p^T mu / c, b = sqrt(1 - kappa/c^2),
@@ -565,6 +673,7 @@ static void preprocess_one(const orc_scene *sc, int64_t i, const orc_camera *cam
         return;
     }
 
+colour:;
     /* colour: SH at the unit direction from the camera centre to the mean */
     double Cw[3]; /* camera centre = -W^T t */
     mat3t_vec(Wr, t, Cw);
@@ -685,6 +794,7 @@ static void free_rows(row_lists *rl)
 static int ray_hits_quad(const orc_splat *s, const double *x)
 {
     double xl[3], xw[3];
+    if (s->whole) return 1;
     mat3t_vec(s->Rp, x, xl);
     for (int k = 0; k < 3; ++k) xw[k] = xl[k] / s->s[k];
     double den = dot3(xw, s->mu_w);
@@ -726,10 +836,14 @@ static void shade_pixel(const orc_splat *sp, const int64_t *cand, int64_t nc, in
         ++entry;
         ++inbox;
         frags += ray_hits_quad(s, x);
-        double tau;
-        double D = orc_divergence(s->mu, s->Rp, s->s, x, &tau, NULL);
+        double tau, w;
+        if (s->exact) {
+            w = orc_mip_exact_weight(s->mu, s->Rp, s->s0, s->o, s->sig2, x, &tau);
+        } else {
+            double D = orc_divergence(s->mu, s->Rp, s->s, x, &tau, NULL);
+            w = s->o * exp(-0.5 * D);
+        }
         if (!(tau > 0.0)) continue; /* peak density behind the camera */
-        double w = s->o * exp(-0.5 * D);
         if (fabs(log(w / opt->p_min)) < ORC_MARGIN_OMEGA) hz = 1;
         if (!(w >= opt->p_min)) continue;
         double a = w < opt->alpha_max ? w : opt->alpha_max;
@@ -922,6 +1036,7 @@ static double mip_chain(const double *mu, const double *Rp, const double *s0, co
 int orc_backward(const orc_scene *sc, const orc_camera *cam, const orc_options *opt, const double *dL_dC,
                  double *g_means, double *g_log_scales, double *g_quats, double *g_opacity, double *g_sh)
 {
+    if (opt->mip == 2) return -2; /* the exact MIP weight is not differentiated */
     int64_t n = sc->n;
     const int W = cam->width, H = cam->height;
     orc_splat *sp = (orc_splat *)malloc(sizeof(orc_splat) * (n ? n : 1));

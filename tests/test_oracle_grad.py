@@ -3,6 +3,7 @@ differences (h = 1e-6) of the oracle's own forward render, on the 64-Gaussian
 32x32 SH3 subcase.  The loss is linear in the image, L = sum(w * C), so dL/dC = w;
 any loss enters the backward only through dL/dC."""
 import numpy as np
+import pytest
 import oracle
 import scenegen
 
@@ -72,3 +73,11 @@ def test_mip_gradient_matches_central_differences(oracle_lib):
     w = np.random.default_rng(9).normal(0, 1, (3, 32, 32))
     worst, count = _fd_check(scene, cam, opts, w)
     assert count == 64 * 59
+
+
+def test_exact_mip_backward_is_rejected(oracle_lib):
+    sc, cam = scenegen.fd_subcase(2004)
+    opts = scenegen.default_options(mip=2, mip_sigma2_px=1.0)
+    dl = np.ones((3, cam["height"], cam["width"]))
+    with pytest.raises(ValueError):
+        oracle.backward(sc, cam, opts, dl)

@@ -571,3 +571,170 @@ def test_mip_modulation_matches_determinant_form(oracle_lib):
     f = _ident_cam(64, 64)["fx"]
     s2 = p["s"][0] ** 2
     assert abs(m["o"] / p["o"] - s2 / (s2 + opts["mip_sigma2_px"] / f**2 * (p["mu"] @ p["mu"]))) < 1e-12
+
+
+# ------------------------------------------------- exact MIP (Sec. 5, App. B)
+def _tangent_frame(x):
+    """Orthonormal F (3x2) with F^T x = 0, from the SVD of x^T."""
+    _, _, vt = np.linalg.svd(x[None, :])
+    return vt[1:].T
+
+
+def _pixel_solid_angle(cam, px, py):
+    """Solid angle of pixel (px, py) from its four corners on the unit sphere
+    (two spherical triangles, Van Oosterom-Strackee formula)."""
+    def ray(u, v):
+        r = np.array([(u - cam["cx"]) / cam["fx"], (v - cam["cy"]) / cam["fy"], 1.0])
+        return r / np.linalg.norm(r)
+
+    a, b, c, d = ray(px, py), ray(px + 1, py), ray(px + 1, py + 1), ray(px, py + 1)
+
+    def tri(p, q, r):
+        num = abs(p @ np.cross(q, r))
+        den = 1 + p @ q + q @ r + r @ p
+        return 2 * math.atan2(num, den)
+
+    return tri(a, b, c) + tri(a, c, d)
+
+
+def _mip_exact_by_tangent_plane(mu, Rp, s, o, sig2_px, cam, px, py):
+    """The per-ray MIP weight from the tangent-plane Gaussian of App. B,
+    before any of its identities: tau(x) by brute-force minimisation along the
+    unit ray, sigma_x^2 = sigma_px^2 times the pixel's solid angle (the area it
+    subtends at unit distance), Sigma^ = Sigma + sigma_x^2 tau^2 I, the exponent
+    mu^T F (F^T Sigma^ F)^-1 F^T mu and the modulation
+    sqrt(det(F^T Sigma F) / det(F^T Sigma^ F)) (the 2D density's normaliser
+    with and without the smoothing)."""
+    xb = np.array([(px + 0.5 - cam["cx"]) / cam["fx"], (py + 0.5 - cam["cy"]) / cam["fy"], 1.0])
+    x = xb / np.linalg.norm(xb)
+    Sig = Rp @ np.diag(np.asarray(s) ** 2) @ Rp.T
+    _, tau = _brute_min_along_ray(mu, np.linalg.inv(Sig), x)
+    sx2 = sig2_px * _pixel_solid_angle(cam, px, py)
+    Sh = Sig + sx2 * tau * tau * np.eye(3)
+    F = _tangent_frame(x)
+    A, A0 = F.T @ Sh @ F, F.T @ Sig @ F
+    e = F.T @ mu
+    D = e @ np.linalg.solve(A, e)
+    return o * math.sqrt(np.linalg.det(A0) / np.linalg.det(A)) * math.exp(-0.5 * D)
+
+
+def test_mip_exact_weight_matches_tangent_plane_form(oracle_lib):
+    """The oracle's per-ray exact MIP weight (Rp^T-frame scales, D_ray of the
+    widened covariance, determinant-identity modulation) equals the weight
+    written on the ray's tangent plane (App. B before equalities (a)-(d)),
+    with tau found by search and the pixel footprint as a solid angle."""
+    rng = np.random.default_rng(31)
+    # a long focal length keeps the pixel-centre footprint within ~1e-6 of
+    # the pixel's solid angle (their difference is second order in 1/f)
+    cam = scenegen.pinhole(np.concatenate([np.eye(3), np.zeros((3, 1))], 1), 480, 400, 50)
+    sig2_px = 2.0
+    sig2 = sig2_px / (cam["fx"] * cam["fy"])
+    checked = 0
+    for _ in range(40):
+        Rp = _rot(rng)
+        s = np.exp(rng.normal(-5.0, 0.8, 3))
+        mu = np.array([rng.uniform(-0.5, 0.5), rng.uniform(-0.4, 0.4), 1.0]) * rng.uniform(1.5, 6.0)
+        o = rng.uniform(0.2, 0.95)
+        u0 = cam["fx"] * mu[0] / mu[2] + cam["cx"]
+        v0 = cam["fy"] * mu[1] / mu[2] + cam["cy"]
+        for _ in range(3):
+            px = int(np.clip(u0 + rng.normal(0, 3), 0, cam["width"] - 1))
+            py = int(np.clip(v0 + rng.normal(0, 3), 0, cam["height"] - 1))
+            xb = [(px + 0.5 - cam["cx"]) / cam["fx"], (py + 0.5 - cam["cy"]) / cam["fy"], 1.0]
+            w, tau_h = oracle.mip_exact_weight(mu, Rp.reshape(-1), s, o, sig2, xb)
+            ref = _mip_exact_by_tangent_plane(mu, Rp, s, o, sig2_px, cam, px, py)
+            assert tau_h > 0
+            # relative error of the exponent's size (D about 30 in the far tail)
+            assert abs(math.log(w / ref)) <= 2e-6 * (1 + abs(math.log(ref / o))), (w, ref)
+            checked += ref > 1e-3
+    assert checked > 30
+
+
+def test_mip_exact_on_axis_ray_matches_eq17(oracle_lib):
+    """On the ray through the centre of a Gaussian on the optical axis the
+    exact weight is the opacity of eq. (17): tau = |mu| there, the footprint is
+    the principal point's, and x^T Sigma^-1 x / x^T Sigma^^-1 x = c^2 / c^^2."""
+    rng = np.random.default_rng(32)
+    for _ in range(10):
+        z = rng.uniform(2.0, 8.0)
+        q = rng.standard_normal(4)
+        q /= np.linalg.norm(q)
+        sc = dict(means=np.array([[0.0], [0.0], [z]], np.float32),
+                  log_scales=rng.normal(-3.5, 0.7, (3, 1)).astype(np.float32),
+                  quats=q.reshape(4, 1).astype(np.float32), opacity_logits=np.array([1.3], np.float32),
+                  sh=np.zeros((1, 3, 1), np.float32), sh_degree=0)
+        cam = _ident_cam(64, 64)
+        opts = scenegen.default_options(mip=1, mip_sigma2_px=3.0)
+        approx = oracle.preprocess(sc, cam, opts)[0]
+        plain = oracle.preprocess(sc, cam, scenegen.default_options())[0]
+        sig2 = opts["mip_sigma2_px"] / (cam["fx"] * cam["fy"])
+        w, _ = oracle.mip_exact_weight(plain["mu"], plain["Rp"], plain["s"], plain["o"], sig2, [0.0, 0.0, 1.0])
+        assert abs(w - approx["o"]) <= 1e-12 * approx["o"]
+
+
+def test_mip_exact_zero_sigma_is_plain(oracle_lib):
+    sc = scenegen.tiny_scene(33, 80, sh_degree=1)
+    cam = scenegen.pinhole(scenegen.look_at((0, 0, -3)), 40, 36, 60)
+    a = oracle.render(sc, cam, scenegen.default_options(mip=0))
+    b = oracle.render(sc, cam, scenegen.default_options(mip=2, mip_sigma2_px=0.0))
+    assert np.array_equal(a["rgb"], b["rgb"]) and np.array_equal(a["n_contrib"], b["n_contrib"])
+    assert a["counters"] == b["counters"]
+
+
+def _exact_weights_all_pixels(r, cam, sig2_px):
+    """Exact MIP weight and tau^ at every pixel centre, vectorised: plain tau
+    in closed form, then D_ray of the per-pixel widened covariance as
+    mu^T S^-1 mu - (mu^T S^-1 x)^2 / x^T S^-1 x."""
+    H, W = cam["height"], cam["width"]
+    ys, xs = np.mgrid[0:H, 0:W]
+    xb = np.stack([(xs + 0.5 - cam["cx"]) / cam["fx"], (ys + 0.5 - cam["cy"]) / cam["fy"], np.ones((H, W))], -1)
+    nrm = np.linalg.norm(xb, axis=-1)
+    x = xb / nrm[..., None]
+    Rp = r["Rp"].reshape(3, 3)
+    xl = x @ Rp
+    ml = Rp.T @ r["mu"]
+    s2 = r["s0"] ** 2
+    tau = (xl * (ml / s2)).sum(-1) / (xl * xl / s2).sum(-1)
+    a = sig2_px / (cam["fx"] * cam["fy"]) / nrm**3 * tau**2
+    sh2 = s2 + a[..., None]
+    L = (xl * (ml / sh2)).sum(-1)
+    Q = (xl * xl / sh2).sum(-1)
+    D = (ml * ml / sh2).sum(-1) - L * L / Q
+    m2 = np.prod(s2) * (xl * xl / s2).sum(-1) / (np.prod(sh2, -1) * Q)
+    return r["o"] * np.sqrt(m2) * np.exp(-0.5 * D), L / Q
+
+
+def test_mip_exact_support_inside_listed_tiles(oracle_lib):
+    """Every pixel whose exact MIP weight reaches p_min lies in a listed tile
+    of its Gaussian (the bound of the widened Gaussian is conservative), over
+    scenes with strongly anisotropic Gaussians and a footprint large enough
+    that some have no bound (whole view)."""
+    sig2_px = 1.5
+    opts = scenegen.default_options(mip=2, mip_sigma2_px=sig2_px, tile_w=8, tile_h=8)
+    whole = bounded_hits = widened = 0
+    for seed in (34, 35):
+        sc = scenegen.tiny_scene(seed, 150, log_scale_mean=-4.0, log_scale_std=1.0)
+        cam = scenegen.pinhole(scenegen.look_at((0, 0, -2.5)), 72, 56, 60)
+        sp = oracle.preprocess(sc, cam, opts)
+        plain = oracle.preprocess(sc, cam, scenegen.default_options(tile_w=8, tile_h=8))
+        tiles, _, ids = oracle.tile_lists(sp, cam, opts)
+        tiles_x = -(-cam["width"] // 8)
+        for i, r in enumerate(sp):
+            if r["cull"] in (1, 2, 3):
+                continue
+            w, th = _exact_weights_all_pixels(r, cam, sig2_px)
+            sup = (w >= opts["p_min"] * (1 + 1e-9)) & (th > 0)
+            if not sup.any():
+                continue
+            assert r["cull"] == 0, (seed, i, r["cull"])
+            py, px = np.nonzero(sup)
+            listed = set(tiles[ids == i].tolist())
+            need = set(((py // 8) * tiles_x + px // 8).tolist())
+            assert need <= listed, (seed, i)
+            if r["whole"]:
+                whole += 1
+                assert len(listed) == tiles_x * (-(-cam["height"] // 8))
+            else:
+                bounded_hits += 1
+                widened += plain[i]["cull"] != 0 or np.any(px < plain[i]["px0"]) or np.any(px > plain[i]["px1"])
+    assert whole > 0 and bounded_hits > 50 and widened > 5
