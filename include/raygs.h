@@ -90,8 +90,11 @@ typedef struct {
     double alpha_max;      /* opacity clamp, in (p_min, 1); default 0.99 */
     double t_eps;          /* compositing stops before T would fall below it; [0, 1); default 1e-4 */
     double near_z;         /* centres with z <= near_z are culled (Sec. 4.1, near plane); default 0.2 */
-    int32_t mip;           /* 1 = approximate MIP of Sec. 5, eq. 17; default 0 */
-    double mip_sigma2_px;  /* MIP pixel variance in px^2 (Sec. 6 uses 0.1); >= 0 */
+    int32_t mip;           /* 0 = none (default); 1 = approximate MIP of Sec. 5, eq. 17; 2 = exact MIP of
+                              Sec. 5 / App. B: per ray, Sigma + sigma_x^2 tau(x)^2 I with sigma_x^2 the
+                              pixel's area at unit distance along the ray, opacity times
+                              sqrt(|Sigma| x.Sigma^-1 x / (|Sigma^_x| x.Sigma^_x^-1 x)); forward only */
+    double mip_sigma2_px;  /* MIP pixel variance in px^2 at the principal point (Sec. 6 uses 0.1); >= 0 */
     double background[3];  /* added as T_final * background; default 0 */
     int32_t tile_w, tile_h;/* each 8, 16 or 32; 0, 0 = the shape rgs_autotune_training or rgs_autotune
                               last chose on this context for the same configuration class (render or
@@ -147,7 +150,10 @@ rgs_status rgs_workspace_size(rgs_context *ctx, int64_t n, const rgs_camera *cam
                               const rgs_options *opts, int64_t capacity, int32_t flags, size_t *bytes);
 
 /* Forward render of n_views cameras in one batch (Sec. 3 eqs. 1-2 with D_ray
- * of eq. 5, the quad bound of Sec. 4.1 and, if opts->mip, eq. 17).
+ * of eq. 5, the quad bound of Sec. 4.1 and, with opts->mip = 1, eq. 17; with
+ * opts->mip = 2 the exact MIP weight of Sec. 5 per pixel, binned by the quad
+ * of a widened Gaussian that bounds its support, or by the whole view where
+ * no such bound exists).
  * cams, outs: host arrays of n_views (outs entries hold device pointers);
  * opts: one struct for the whole batch.  Stream-ordered, no host
  * synchronisation.  If the frame needs
@@ -166,7 +172,8 @@ rgs_status rgs_render_status(rgs_context *ctx, const rgs_workspace *ws, void *st
  * `ws` (which must carry RGS_WS_BACKWARD) with the same g, cams, opts and
  * outs.  Walks each pixel's list back from n_contrib starting at final_T.
  * Gradients are added into `grads`.  With opts->mip = 1 they also flow
- * through the MIP widening and opacity modulation (eq. 17).
+ * through the MIP widening and opacity modulation (eq. 17); opts->mip = 2
+ * returns RGS_EUNSUPPORTED.
  * Uses float atomics: results are order-nondeterministic in the last bits. */
 rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
                                const rgs_options *opts, const rgs_workspace *ws, const rgs_view_out *outs,
@@ -198,7 +205,7 @@ rgs_status rgs_autotune(rgs_context *ctx, const rgs_gaussians *g, const rgs_came
 
 /* As rgs_autotune for a training step: each timed step is a render followed
  * by rgs_render_backward with the upstream gradients dL_drgb[v] (device
- * [3][H][W] per view); `ws` must carry RGS_WS_BACKWARD and opts->mip be 0.
+ * [3][H][W] per view); `ws` must carry RGS_WS_BACKWARD and opts->mip be 0 or 1.
  * Every backward pass adds into `grads`, so pass scratch buffers.  *best_ms
  * is the mean forward + backward milliseconds of the chosen shape. */
 rgs_status rgs_autotune_training(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
@@ -214,7 +221,7 @@ typedef struct {
                               [2] tile rows of all boxes, [3] listed instances (sorted; the rest are
                               empty), [4] kept (not culled) Gaussian-views */
     size_t views;          /* per-view device table */
-    size_t records;        /* float[16] per Gaussian-view, index v * n + i */
+    size_t records;        /* float[16] per Gaussian-view (float[28] with mip = 2), index v * n + i */
     size_t depth_keys;     /* uint32 per Gaussian-view: the kept views' keys, sorted, in [0, counters[4]) */
     size_t boxes;          /* uint16[4] per Gaussian-view: pixel box x0, x1, y0, y1 (inclusive) */
     size_t conics;         /* double[8] per Gaussian-view: support ellipse P00, P01, P11, h0, h1, f0, u0, v0 */

@@ -49,7 +49,7 @@ struct rgs_context {
     std::vector<FrameEvents> pool;
     double stage_ms[kNumStages] = {0};
     int64_t frames = 0;
-    int grid_fwd[64] = {0}, grid_bwd[64] = {0};
+    int grid_fwd[64] = {0}, grid_fwd_exact[64] = {0}, grid_bwd[64] = {0};
     unsigned long long *view_stamps = nullptr;  // rgs_set_view_clocks (caller-owned device memory)
     int view_stamps_views = 0;
     std::map<std::string, TileShape> tune_cache;  // autotuned tile shapes by configuration class
@@ -178,7 +178,7 @@ rgs_status check_options(rgs_context *ctx, const rgs_options *o)
         return fail(ctx, RGS_EINVAL, "alpha_max must lie in (p_min, 1)");
     if (!(o->t_eps >= 0.0 && o->t_eps < 1.0)) return fail(ctx, RGS_EINVAL, "t_eps must lie in [0, 1)");
     if (!std::isfinite(o->near_z)) return fail(ctx, RGS_EINVAL, "near_z must be finite");
-    if (o->mip != 0 && o->mip != 1) return fail(ctx, RGS_EINVAL, "mip must be 0 or 1");
+    if (o->mip < 0 || o->mip > 2) return fail(ctx, RGS_EINVAL, "mip must be 0, 1 or 2");
     if (!(o->mip_sigma2_px >= 0.0) || !std::isfinite(o->mip_sigma2_px))
         return fail(ctx, RGS_EINVAL, "mip_sigma2_px must be finite and >= 0");
     for (int k = 0; k < 3; ++k)
@@ -221,7 +221,7 @@ rgs_status compute_layout(rgs_context *ctx, int64_t n, const rgs_camera *cams, i
     L.counters = take(8 * sizeof(int64_t));
     L.views = take(sizeof(DevView) * n_views);
     L.colours = take(NV * sizeof(float4));
-    L.records = take(NV * kRecordFloats * sizeof(float));
+    L.records = take(NV * record_floats(opts->mip) * sizeof(float));
     L.keys_a = take(NV * 4);
     L.keys_b = take(NV * 4);
     L.order_a = take(NV * 4);
@@ -362,7 +362,8 @@ struct Timer {
 void ensure_grids(rgs_context *ctx, TileShape s)
 {
     const int k = shape_index(s);
-    if (!ctx->grid_fwd[k]) ctx->grid_fwd[k] = blend_grid(s, ctx->num_cus);
+    if (!ctx->grid_fwd[k]) ctx->grid_fwd[k] = blend_grid(s, false, ctx->num_cus);
+    if (!ctx->grid_fwd_exact[k]) ctx->grid_fwd_exact[k] = blend_grid(s, true, ctx->num_cus);
     if (!ctx->grid_bwd[k]) ctx->grid_bwd[k] = blend_backward_grid(s, ctx->num_cus);
 }
 
@@ -429,12 +430,13 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
     const uint32_t *inst_tiles = at<uint32_t>(ws, L.inst_tiles_a);
     const uint32_t *inst_ids = at<uint32_t>(ws, L.inst_ids_a);
     const uint32_t split_min = s.h / (64 / s.w) >= 2 ? (uint32_t)RGS_SPLIT_LEN : 0u;
-    const uint32_t waves = (uint32_t)(4 * ctx->grid_fwd[shape_index(s)]);
+    const int blend_blocks = opts.mip == 2 ? ctx->grid_fwd_exact[shape_index(s)] : ctx->grid_fwd[shape_index(s)];
+    const uint32_t waves = (uint32_t)(4 * blend_blocks);
     RGS_HIP(ctx, launch_tile_ranges(inst_tiles, listed, L.capacity, L.total_tiles, split_min, waves, ranges, sched,
                                     at<uint32_t>(ws, L.tile_order), stream));
     tm.mark(ST_RANGES);
     RGS_HIP(ctx, launch_blend(s, ranges, tile_order, sched + sched_item_count(), inst_ids, records, views, n_views,
-                              L.total_tiles, NV, dopt, sched, ctx->grid_fwd[shape_index(s)], item_clock, stream));
+                              L.total_tiles, NV, dopt, sched, blend_blocks, item_clock, stream));
     tm.mark(ST_BLEND);
     if (view_stamps)
         RGS_HIP(ctx, launch_view_clock_max(item_clock, tile_order, sched + sched_item_count(), 2 * L.total_tiles,
@@ -591,6 +593,7 @@ rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const r
     for (int v = 0; v < n_views; ++v)
         if (!dL_drgb[v]) return fail(ctx, RGS_EINVAL, "dL_drgb[%d] is NULL", v);
     if (!grads) return fail(ctx, RGS_EINVAL, "grads is NULL");
+    if (opts->mip == 2) return fail(ctx, RGS_EUNSUPPORTED, "the exact MIP weight (mip = 2) is not differentiated");
     if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh))
         return fail(ctx, RGS_EINVAL, "NULL gradient pointer");
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -95,9 +95,9 @@ struct RowSpan {
     int r0, r1;
 };
 
-__device__ __forceinline__ RowSpan row_span(const TRec &R, int tile_row0)
+__device__ __forceinline__ RowSpan row_span(uint32_t rows_word, int tile_row0)
 {
-    const uint32_t rows = __builtin_amdgcn_readfirstlane(R.rows);
+    const uint32_t rows = __builtin_amdgcn_readfirstlane(rows_word);
     return RowSpan{(int)(rows & 0xffffu) - tile_row0, (int)(rows >> 16) - tile_row0};
 }
 
@@ -167,6 +167,149 @@ __device__ __forceinline__ void put_test_form(float4 *dst, const float4 (&r)[4],
     dst[3] = r[3];
 }
 
+// Record model of the forward kernel: how a raw record is fetched, staged
+// in LDS for one tile, read back, and tested per fragment.  PlainModel is the
+// record above (with or without the approximate MIP of eq. 17, which only
+// changes the record's values); ExactMipModel evaluates the exact MIP weight.
+struct PlainModel {
+    static constexpr int kRaw = 4, kStaged = 4;
+    using Rec = TRec;
+    using F = Frag;
+    __device__ static float pixel_aux(const DevView &, int, int) { return 0.0f; }
+    __device__ static void fetch(float4 (&r)[kRaw], const float4 *__restrict__ records, uint32_t inst,
+                                 uint32_t n_records, bool bands_in_rows)
+    {
+        fetch_record(r, records, inst, n_records, bands_in_rows);
+    }
+    __device__ static void stage(float4 *dst, const float4 (&r)[kRaw], float x0, float y0, float log2_pmin)
+    {
+        put_test_form(dst, r, x0, y0, log2_pmin);
+    }
+    __device__ static Rec load(const float4 *p) { return load_trec(p); }
+    __device__ static bool test(const Rec &R, float pxr, float pyr, float, float, F &f)
+    {
+        return frag_test(R, pxr, pyr, f);
+    }
+    __device__ static float omega(const Rec &R, F &f)
+    {
+        frag_omega(R, f);
+        return f.w;
+    }
+};
+
+// Exact MIP (mip = 2).  The record (seven float4, written by the preprocess
+// kernel) describes the Gaussian in its own axes, scaled so that the largest
+// variance is 1 (lam = s_max^2):
+//   [0] u_hi, v_hi, lo, rows      projected centre and covered rows, as above
+//   [1] P0 (3), e                 P0 = R_p^T e_x / f_x;  e = sigma^2 mu_z^2 / lam
+//   [2] P1 (3), log2o             P1 = R_p^T e_y / f_y;  log2o = log2 o + log2 sqrt(prod s'^2)
+//   [3] Q0 (3), r                 Q0 = R_p^T (0, 1, -v0) mu_z / (f_x sqrt(lam))
+//   [4] Q1 (3), g                 Q1 = R_p^T (-1, 0, u0) mu_z / (f_y sqrt(lam))
+//   [5] rho (3), b                rho = R_p^T mu / mu_z
+//   [6] s'^2 (3), 0               s'^2 = s^2 / lam
+// For a pixel offset delta from the projected centre, the ray xbar = (u, v, 1)
+// has r = R_p^T xbar = rho + P0 dx + P1 dy, and w = Q0 dx + Q1 dy is
+// R_p^T (mu x xbar) (scaled), linear in delta with no cancellation.  With
+// A = sum rho_k r_k / s'_k^2 and B = sum r_k^2 / s'_k^2, the widening of
+// this ray is a = e |xbar|^-1 (A / B)^2 (sigma_x^2 tau(x)^2 over lam), the
+// widened variances S_k = s'_k^2 + a, and with
+//   den = sum_k r_k^2 prod_{j != k} S_j,   num = sum_k S_k w_k^2,
+// D_ray(x; mu, Sigma^_x) = num / den (the cross-product form of
+// c^2 - (x.mu)^2 / x.x in the widened metric), the modulation is
+// m^2 = prod s'^2 B / den, and the peak of the widened density lies in front
+// iff sum_k rho_k r_k prod_{j != k} S_j > 0.  Every sum has positive terms
+// except A, which only sets the widening.  omega = 2^L with
+// L = log2o + log2(B / den) / 2 - num log2(e) / (2 den).
+struct XRec {
+    float cx, cy, e, P0x, P0y, P0z, P1x, P1y, P1z, Q0x, Q0y, Q0z, Q1x, Q1y, Q1z;
+    float rx, ry, rz, log2o, ix_, iy_, iz_, r, isx, isy, isz, g, s0, s1, s2, b;
+    uint32_t rows;
+};
+
+struct XFrag {
+    float L;
+};
+
+struct ExactMipModel {
+    static constexpr int kRaw = 7, kStaged = 8;
+    using Rec = XRec;
+    using F = XFrag;
+    // 1 / |xbar| of the pixel-centre ray (the footprint's cos(theta))
+    __device__ static float pixel_aux(const DevView &V, int px, int py)
+    {
+        const float u = ((float)px + 0.5f - (float)V.cx) * (float)(1.0 / V.fx);
+        const float v = ((float)py + 0.5f - (float)V.cy) * (float)(1.0 / V.fy);
+        return __builtin_amdgcn_rsqf(__builtin_fmaf(v, v, __builtin_fmaf(u, u, 1.0f)));
+    }
+    __device__ static void fetch(float4 (&r)[kRaw], const float4 *__restrict__ records, uint32_t inst,
+                                 uint32_t n_records, bool bands_in_rows)
+    {
+        const uint32_t id = inst & kIdMask;
+        if (id < n_records) {
+            const float4 *src = records + (size_t)id * kRaw;
+#pragma unroll
+            for (int c = 0; c < kRaw; ++c) r[c] = src[c];
+        } else {
+            // rows [1, 0]: empty; a ray in front with omega = 2^-126
+            r[0] = make_float4(0.f, 0.f, 0.f, __uint_as_float(1u));
+            r[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            r[2] = make_float4(0.f, 0.f, 0.f, -126.f);
+            r[3] = make_float4(0.f, 0.f, 0.f, 0.f);
+            r[4] = make_float4(0.f, 0.f, 0.f, 0.f);
+            r[5] = make_float4(0.f, 0.f, 1.f, 0.f);
+            r[6] = make_float4(1.f, 1.f, 1.f, 0.f);
+        }
+        if (bands_in_rows) r[0].w = __uint_as_float(inst >> kIdBits);
+    }
+    // staged: [0] cx cy e rows [1] P0 P1x [2] P1yz Q0xy [3] Q0z Q1 [4] rho log2o
+    //         [5] rho/s'^2 r [6] 1/s'^2 g [7] s'^2 b
+    __device__ static void stage(float4 *dst, const float4 (&r)[kRaw], float x0, float y0, float)
+    {
+        const uint32_t lo_bits = __float_as_uint(r[0].z);
+        const float2 lo = __half22float2(*reinterpret_cast<const __half2 *>(&lo_bits));
+        const float isx = 1.0f / r[6].x, isy = 1.0f / r[6].y, isz = 1.0f / r[6].z;
+        dst[0] = make_float4((r[0].x - x0) + lo.x, (r[0].y - y0) + lo.y, r[1].w, r[0].w);
+        dst[1] = make_float4(r[1].x, r[1].y, r[1].z, r[2].x);
+        dst[2] = make_float4(r[2].y, r[2].z, r[3].x, r[3].y);
+        dst[3] = make_float4(r[3].z, r[4].x, r[4].y, r[4].z);
+        dst[4] = make_float4(r[5].x, r[5].y, r[5].z, r[2].w);
+        dst[5] = make_float4(r[5].x * isx, r[5].y * isy, r[5].z * isz, r[3].w);
+        dst[6] = make_float4(isx, isy, isz, r[4].w);
+        dst[7] = make_float4(r[6].x, r[6].y, r[6].z, r[5].w);
+    }
+    __device__ static Rec load(const float4 *p)
+    {
+        const float4 a = p[0], b = p[1], c = p[2], d = p[3], e = p[4], f = p[5], g = p[6], h = p[7];
+        return XRec{a.x, a.y, a.z, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w,
+                    e.x, e.y, e.z, e.w, f.x, f.y, f.z, f.w, g.x, g.y, g.z, g.w, h.x, h.y, h.z, h.w,
+                    __float_as_uint(a.w)};
+    }
+    __device__ static bool test(const Rec &R, float pxr, float pyr, float inv_norm, float log2_pmin, F &f)
+    {
+        const float dx = pxr - R.cx, dy = pyr - R.cy;
+        const float r0 = __builtin_fmaf(R.P1x, dy, __builtin_fmaf(R.P0x, dx, R.rx));
+        const float r1 = __builtin_fmaf(R.P1y, dy, __builtin_fmaf(R.P0y, dx, R.ry));
+        const float r2 = __builtin_fmaf(R.P1z, dy, __builtin_fmaf(R.P0z, dx, R.rz));
+        const float w0 = __builtin_fmaf(R.Q1x, dy, R.Q0x * dx);
+        const float w1 = __builtin_fmaf(R.Q1y, dy, R.Q0y * dx);
+        const float w2 = __builtin_fmaf(R.Q1z, dy, R.Q0z * dx);
+        const float A = __builtin_fmaf(R.iz_, r2, __builtin_fmaf(R.iy_, r1, R.ix_ * r0));
+        const float q0 = r0 * r0, q1 = r1 * r1, q2 = r2 * r2;
+        const float B = __builtin_fmaf(R.isz, q2, __builtin_fmaf(R.isy, q1, R.isx * q0));
+        const float t = A * __builtin_amdgcn_rcpf(B);
+        const float a = (R.e * inv_norm) * (t * t);
+        const float S0 = R.s0 + a, S1 = R.s1 + a, S2 = R.s2 + a;
+        const float p12 = S1 * S2, p02 = S0 * S2, p01 = S0 * S1;
+        const float den = __builtin_fmaf(q2, p01, __builtin_fmaf(q1, p02, q0 * p12));
+        const float num = __builtin_fmaf(S2, w2 * w2, __builtin_fmaf(S1, w1 * w1, S0 * (w0 * w0)));
+        const float th = __builtin_fmaf(R.rz * r2, p01, __builtin_fmaf(R.ry * r1, p02, (R.rx * r0) * p12));
+        const float rd = __builtin_amdgcn_rcpf(den);
+        f.L = __builtin_fmaf(-kHalfLog2e * num, rd, __builtin_fmaf(0.5f, __builtin_amdgcn_logf(B * rd), R.log2o));
+        return (th > 0.0f) & (f.L >= log2_pmin);
+    }
+    __device__ static float omega(const Rec &, F &f) { return __builtin_amdgcn_exp2f(f.L); }
+};
+
 // Whether culling band k (rows [k LY, (k + 1) LY) of the tile) may hold a
 // fragment of the record: its band bit when the tile has at most 4 bands
 // (`bands` is then the record's rows word), else the record's covered rows.
@@ -177,7 +320,7 @@ __device__ __forceinline__ bool band_open(uint32_t bands, const RowSpan &span, i
     return !(span.r1 < k * LY || span.r0 >= (k + 1) * LY);
 }
 
-template <int TW, int TH>
+template <int TW, int TH, class M>
 __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
                                                const uint32_t *__restrict__ work_order,
                                                const uint32_t *__restrict__ n_items_p,
@@ -187,7 +330,7 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
 {
     constexpr int LX = TW, LY = 64 / TW, PPL = TH / LY;
     static_assert(64 % TW == 0 && TH % LY == 0, "tile shape");
-    __shared__ float4 s_rec[4][64][4];
+    __shared__ float4 s_rec[4][64][M::kStaged];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lx = lane % LX, ly = lane / LX;
     const int nq = min((int)gridDim.x, kQueues), q = (int)blockIdx.x % nq;
@@ -210,13 +353,14 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
         // pixel centres relative to the block corner; NaN marks a pixel that
         // is outside the image, outside the work item, or done
         const float pxr = (float)(px - ox) + 0.5f;
-        float T[PPL], C0[PPL], C1[PPL], C2[PPL], pyr[PPL];
+        float T[PPL], C0[PPL], C1[PPL], C2[PPL], pyr[PPL], aux[PPL];
         int last[PPL];
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
             const int py = ty * TH + ly + k * LY;
             const bool on = k >= k_lo && k < k_hi && px < V.width && py < V.height;
             pyr[k] = on ? (float)(py - oy) + 0.5f : __builtin_nanf("");
+            aux[k] = M::pixel_aux(V, px, py);
             T[k] = 1.0f;
             C0[k] = C1[k] = C2[k] = 0.0f;
             last[k] = 0;
@@ -227,24 +371,24 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
         // while batch b is composited
         if (rg.x + lane < rg.y) {
             const uint32_t inst = inst_ids[rg.x + lane];
-            float4 r[4];
-            fetch_record(r, records, inst, P.n_records, PPL <= 4);
-            put_test_form(s_rec[wave][lane], r, x0, y0, P.log2_pmin);
+            float4 r[M::kRaw];
+            M::fetch(r, records, inst, P.n_records, PPL <= 4);
+            M::stage(s_rec[wave][lane], r, x0, y0, P.log2_pmin);
         }
         for (uint32_t base = rg.x; base < rg.y && wave_live; base += 64) {
             const uint32_t nb = min(64u, rg.y - base);
             const uint32_t next = base + 64 + lane;
             const bool have_next = next < rg.y;
-            float4 pre[4];
+            float4 pre[M::kStaged];
             if (have_next) {
-                float4 r[4];
-                fetch_record(r, records, inst_ids[next], P.n_records, PPL <= 4);
-                put_test_form(pre, r, x0, y0, P.log2_pmin);
+                float4 r[M::kRaw];
+                M::fetch(r, records, inst_ids[next], P.n_records, PPL <= 4);
+                M::stage(pre, r, x0, y0, P.log2_pmin);
             }
             lds_wave_sync();
             for (uint32_t j = 0; j < nb; ++j) {
-                const TRec R = load_trec(s_rec[wave][j]);
-                const RowSpan span = row_span(R, ty * TH);
+                const typename M::Rec R = M::load(s_rec[wave][j]);
+                const RowSpan span = row_span(R.rows, ty * TH);
                 const uint32_t bands = __builtin_amdgcn_readfirstlane(R.rows);
                 const int idx = (int)(base - rg.x + j + 1);
                 bool stopped = false;
@@ -253,11 +397,10 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
                     if (k < k_lo || k >= k_hi || !band_open<PPL, LY>(bands, span, k)) continue;
                     // every lane evaluates the test; results are kept by selection
                     // (the values are those of a branch per lane, bit for bit)
-                    Frag f;
-                    const bool hit = frag_test(R, pxr, pyr[k], f);
+                    typename M::F f;
+                    const bool hit = M::test(R, pxr, pyr[k], aux[k], P.log2_pmin, f);
                     if (__ballot(hit) == 0) continue;
-                    frag_omega(R, f);
-                    const float a = fminf(f.w, P.alpha_max);
+                    const float a = fminf(M::omega(R, f), P.alpha_max);
                     const float ta = T[k] * a;
                     const float Tn = T[k] - ta;
                     const bool stop = hit & (Tn < P.t_eps);
@@ -285,7 +428,7 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
             lds_wave_sync();
             if (have_next) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) s_rec[wave][lane][c] = pre[c];
+                for (int c = 0; c < M::kStaged; ++c) s_rec[wave][lane][c] = pre[c];
             }
         }
         const size_t plane = (size_t)V.width * V.height;
@@ -421,7 +564,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
             for (int jj = nb - 1; jj >= 0; --jj) {
                 const int j = lo + jj;
                 const TRec R = load_trec(s_rec[wave][jj]);
-                const RowSpan span = row_span(R, ty * TH);
+                const RowSpan span = row_span(R.rows, ty * TH);
                 const uint32_t bands = __builtin_amdgcn_readfirstlane(R.rows);
                 const float inv_o = __builtin_amdgcn_exp2f(-R.log2o);
                 float du0 = 0, dv0 = 0, dM00 = 0, dM01 = 0, dM11 = 0, dgx = 0, dgy = 0, dk0 = 0, dic2 = 0, dop = 0,
@@ -543,10 +686,12 @@ bool tile_shape_supported(int w, int h)
 
 #define RGS_SHAPES(X) X(8, 8) X(8, 16) X(8, 32) X(16, 8) X(16, 16) X(16, 32) X(32, 8) X(32, 16) X(32, 32)
 
-int blend_grid(TileShape s, int num_cus)
+int blend_grid(TileShape s, bool exact_mip, int num_cus)
 {
-#define X(W, H) \
-    if (s.w == W && s.h == H) return occupancy_grid<W, H>(reinterpret_cast<const void *>(&k_blend<W, H>), num_cus);
+#define X(W, H)                                                                                                  \
+    if (s.w == W && s.h == H)                                                                                    \
+        return exact_mip ? occupancy_grid<W, H>(reinterpret_cast<const void *>(&k_blend<W, H, ExactMipModel>), num_cus) \
+                         : occupancy_grid<W, H>(reinterpret_cast<const void *>(&k_blend<W, H, PlainModel>), num_cus);
     RGS_SHAPES(X)
 #undef X
     return num_cus;
@@ -570,7 +715,12 @@ hipError_t launch_blend(TileShape s, const uint2 *ranges, const uint32_t *work_o
     const BlendParams P = make_params(opt, n_views, total_tiles, n_records, item_clock);
 #define X(W, H)                                                                                                  \
     if (s.w == W && s.h == H) {                                                                                  \
-        k_blend<W, H><<<grid, 256, 0, stream>>>(ranges, work_order, n_items, inst_ids, records, views, P, queue); \
+        if (opt.mip == 2)                                                                                        \
+            k_blend<W, H, ExactMipModel><<<grid, 256, 0, stream>>>(ranges, work_order, n_items, inst_ids, records, \
+                                                                   views, P, queue);                             \
+        else                                                                                                     \
+            k_blend<W, H, PlainModel><<<grid, 256, 0, stream>>>(ranges, work_order, n_items, inst_ids, records,   \
+                                                                views, P, queue);                                \
         return hipGetLastError();                                                                                \
     }
     RGS_SHAPES(X)

@@ -43,6 +43,12 @@ struct DevOptions {
 //   [3] log2o, r, g, b           log2 of the prior opacity, colour
 constexpr int kRecordFloats = 16;
 
+// With exact MIP (mip = 2) the record is 28 floats (seven float4, 112 B): the
+// Gaussian in its own axes, for the per-ray widening (layout in blend.hip).
+constexpr int kRecordFloatsExactMip = 28;
+
+inline int record_floats(int mip) { return mip == 2 ? kRecordFloatsExactMip : kRecordFloats; }
+
 // Gradient of one record as accumulated by the backward compositing kernel:
 //   du0, dv0, dM00, dM01, dM11, dgx, dgy, dk0, dic2, do, dr, dg, db (13 used)
 // where M = G^T G (q = delta^T M delta; dM01 is the derivative with respect to
@@ -151,7 +157,7 @@ hipError_t launch_view_clock_start(unsigned long long *stamps, int n_views, hipS
 hipError_t launch_view_clock_max(const unsigned long long *item_clock, const uint32_t *work_order,
                                  const uint32_t *n_items, int64_t max_items, const DevView *views, int n_views,
                                  unsigned long long *stamps, hipStream_t stream);
-int blend_grid(TileShape shape, int num_cus);
+int blend_grid(TileShape shape, bool exact_mip, int num_cus);
 
 // Backward compositing over the same work items (whole tiles and halves).
 hipError_t launch_blend_backward(TileShape shape, const uint2 *ranges, const uint32_t *work_order,

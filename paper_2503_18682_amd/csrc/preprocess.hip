@@ -19,6 +19,59 @@
 namespace rgs {
 namespace {
 
+// Exact MIP record (mip = 2; layout and per-ray arithmetic in blend.hip):
+// the Gaussian in its own axes with its variances divided by lam = s_max^2.
+__device__ void write_exact_mip_record(float4 *rec, const double mu[3], const double Rp[9], const double s[3],
+                                       double o, double sig2, const DevView &V, float u_hi, float v_hi,
+                                       uint32_t lo_bits, uint32_t rows, float4 col)
+{
+    const double smax = fmax(s[0], fmax(s[1], s[2]));
+    const double ilam = 1.0 / (smax * smax), iz = 1.0 / mu[2];
+    const double u0 = mu[0] * iz, v0 = mu[1] * iz;
+    const double qx = mu[2] / (V.fx * smax), qy = mu[2] / (V.fy * smax);
+    const double ifx = 1.0 / V.fx, ify = 1.0 / V.fy;
+    double P0[3], P1[3], Q0[3], Q1[3], rho[3], s2[3];
+    for (int k = 0; k < 3; ++k) {
+        // (R_p^T e_r)_k = R_p[r][k]
+        P0[k] = Rp[k] * ifx;
+        P1[k] = Rp[3 + k] * ify;
+        Q0[k] = (Rp[3 + k] - v0 * Rp[6 + k]) * qx;
+        Q1[k] = (u0 * Rp[6 + k] - Rp[k]) * qy;
+        rho[k] = (Rp[k] * mu[0] + Rp[3 + k] * mu[1] + Rp[6 + k] * mu[2]) * iz;
+        s2[k] = s[k] * s[k] * ilam;
+    }
+    const double e = sig2 * mu[2] * mu[2] * ilam;
+    const double log2o = log2(o) + 0.5 * log2(s2[0] * s2[1] * s2[2]);
+    rec[0] = make_float4(u_hi, v_hi, __uint_as_float(lo_bits), __uint_as_float(rows));
+    rec[1] = make_float4((float)P0[0], (float)P0[1], (float)P0[2], (float)e);
+    rec[2] = make_float4((float)P1[0], (float)P1[1], (float)P1[2], (float)log2o);
+    rec[3] = make_float4((float)Q0[0], (float)Q0[1], (float)Q0[2], col.x);
+    rec[4] = make_float4((float)Q1[0], (float)Q1[1], (float)Q1[2], col.y);
+    rec[5] = make_float4((float)rho[0], (float)rho[1], (float)rho[2], col.z);
+    rec[6] = make_float4((float)s2[0], (float)s2[1], (float)s2[2], 0.0f);
+}
+
+// Projected centre pi(mu) in pixels as a (hi, lo) float pair, lo as fp16 bits
+// (|lo| <= half an fp32 ulp of the centre, so fp16 keeps it to ~1e-7 px).
+struct Centre {
+    double u, v;
+    float u_hi, v_hi;
+    uint32_t lo_bits;
+};
+
+__device__ inline Centre projected_centre(const double mu[3], const DevView &V)
+{
+    Centre c;
+    const double k0 = 1.0 / mu[2];
+    c.u = V.fx * mu[0] * k0 + V.cx;
+    c.v = V.fy * mu[1] * k0 + V.cy;
+    c.u_hi = (float)c.u;
+    c.v_hi = (float)c.v;
+    const __half2 lo = __floats2half2_rn((float)(c.u - (double)c.u_hi), (float)(c.v - (double)c.v_hi));
+    c.lo_bits = *reinterpret_cast<const uint32_t *>(&lo);
+    return c;
+}
+
 
 __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ means,
                                                     const float *__restrict__ log_scales,
@@ -96,7 +149,55 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
             float log2o = log2o_o;
             double ml[3];  // R_p^T mu: centre in the Gaussian's own axes
             for (int c = 0; c < 3; ++c) ml[c] = Rp[c] * mu[0] + Rp[3 + c] * mu[1] + Rp[6 + c] * mu[2];
-            if (opt.mip) {
+            bool whole = false;  // exact MIP without a bounding Gaussian
+            if (opt.mip == 2) {
+                // Exact MIP: the camera-inside skip applies to the Gaussian
+                // itself; the quad, box and tiles are those of the Gaussian
+                // widened by a_max = sigma^2 tau_max^2, which bounds the
+                // per-ray widening sigma_x^2 tau(x)^2 of every ray that can
+                // reach p_min (m <= 1): |tau| <= (|mu| + sqrt(kappa) s_max
+                // (1 + rho)) / (1 - beta), rho = s_max / s_min, beta =
+                // sqrt(kappa) sigma (1 + rho).  Without such a bound (beta >= 1,
+                // or the widened Gaussian holds the camera) the whole view is
+                // listed.
+                if (!(kappa > 0.0)) break;
+                double c2g = 0.0;
+                for (int k = 0; k < 3; ++k) c2g += ml[k] * ml[k] * (isv[k] * isv[k]);
+                if (!(c2g > kappa)) break;
+                const double sig2 = opt.mip_sigma2_px / (V.fx * V.fy);
+                const double smax = fmax(sv[0], fmax(sv[1], sv[2])), smin = fmin(sv[0], fmin(sv[1], sv[2]));
+                const double rho = smax / smin;
+                const double beta = sqrt(kappa * sig2) * (1.0 + rho);
+                whole = !(beta < 1.0);
+                if (!whole) {
+                    const double tb = sqrt(mu[0] * mu[0] + mu[1] * mu[1] + mu[2] * mu[2]);
+                    const double tmax = (tb + sqrt(kappa) * smax * (1.0 + rho)) / (1.0 - beta);
+                    const double amax = sig2 * tmax * tmax;
+                    double sh2[3], c2b = 0.0;
+                    for (int k = 0; k < 3; ++k) {
+                        sh2[k] = sv[k] * sv[k] + amax;
+                        c2b += ml[k] * ml[k] / sh2[k];
+                    }
+                    whole = !(c2b > kappa);
+                    if (!whole)
+                        for (int k = 0; k < 3; ++k) {
+                            sv[k] = sqrt(sh2[k]);
+                            isv[k] = 1.0 / sv[k];
+                        }
+                }
+                if (whole) {
+                    const int Wd = V.width, Hd = V.height;
+                    box = make_uint2((uint32_t)(Wd - 1) << 16, (uint32_t)(Hd - 1) << 16);
+                    key = __float_as_uint((float)mu[2]);
+                    cnt = (uint32_t)(((Wd - 1) / opt.tile_w + 1) * ((Hd - 1) / opt.tile_h + 1));
+                    const Centre pc = projected_centre(mu, V);
+                    write_exact_mip_record(records + idx * (kRecordFloatsExactMip / 4), mu, Rp, s, o, sig2, V,
+                                           pc.u_hi, pc.v_hi, pc.lo_bits, (uint32_t)(Hd - 1) << 16, colours[idx]);
+                    // P00 = 0: not an ellipse, so every tile of the box is listed
+                    conics[idx] = Conic{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, pc.u, pc.v};
+                    break;
+                }
+            } else if (opt.mip == 1) {
                 // Approximate MIP (Sec. 5, eq. 17): add sigma^2 |mu|^2 to every
                 // variance (pixel-invariant tau = |mu|) and scale the opacity by
                 // sqrt(|Sigma| c^2 / (|Sigma^| c^^2)).
@@ -212,12 +313,9 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
             key = __float_as_uint((float)mu[2]);
 
             // ---- raster record (float32) ----
-            // projected centre as a (hi, lo) float pair
+            const Centre pc = projected_centre(mu, V);
             const double k0 = 1.0 / mu[2];
-            const double u_c = V.fx * mu[0] * k0 + V.cx;
-            const double v_c = V.fy * mu[1] * k0 + V.cy;
-            const float u_hi = (float)u_c, v_hi = (float)v_c;
-            const float u_lo = (float)(u_c - (double)u_hi), v_lo = (float)(v_c - (double)v_hi);
+            const double u_c = pc.u, v_c = pc.v;
             // A2 = (S^-1 R_p^T)[:, 0:2] diag(1/fx, 1/fy): a pixel offset delta moves
             // the whitened ray direction by A2 delta.
             double A2[3][2];
@@ -251,18 +349,20 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
             // tiles of the box; the emission kernel lists those whose row bands
             // meet the support and marks the others empty
             cnt = (uint32_t)((px1 / opt.tile_w - px0 / opt.tile_w + 1) * (py1 / opt.tile_h - py0 / opt.tile_h + 1));
-            // the residuals of the centre go into one fp16 pair (|residual| <= half an
-            // fp32 ulp of the centre, so fp16 keeps it to ~1e-7 px); the freed slot
+            // the residuals of the centre go into one fp16 pair; the freed slot
             // holds the covered pixel rows for in-tile culling
-            const __half2 lo = __floats2half2_rn(u_lo, v_lo);
-            const uint32_t lo_bits = *reinterpret_cast<const uint32_t *>(&lo);
             const uint32_t rows = (uint32_t)py0 | ((uint32_t)py1 << 16);
-            float4 *rec = records + idx * 4;
-            rec[0] = make_float4(u_hi, v_hi, __uint_as_float(lo_bits), __uint_as_float(rows));
-            rec[1] = make_float4((float)G[0][0], (float)G[0][1], (float)G[1][0], (float)G[1][1]);
-            rec[2] = make_float4((float)gx, (float)gy, (float)k0, (float)ic2);
             const float4 col = colours[idx];
-            rec[3] = make_float4(log2o, col.x, col.y, col.z);
+            if (opt.mip == 2) {
+                write_exact_mip_record(records + idx * (kRecordFloatsExactMip / 4), mu, Rp, s, o,
+                                       opt.mip_sigma2_px / (V.fx * V.fy), V, pc.u_hi, pc.v_hi, pc.lo_bits, rows, col);
+            } else {
+                float4 *rec = records + idx * 4;
+                rec[0] = make_float4(pc.u_hi, pc.v_hi, __uint_as_float(pc.lo_bits), __uint_as_float(rows));
+                rec[1] = make_float4((float)G[0][0], (float)G[0][1], (float)G[1][0], (float)G[1][1]);
+                rec[2] = make_float4((float)gx, (float)gy, (float)k0, (float)ic2);
+                rec[3] = make_float4(log2o, col.x, col.y, col.z);
+            }
             conics[idx] = C;
         } while (false);
         depth_keys[idx] = cnt ? key : 0xffffffffu;

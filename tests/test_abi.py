@@ -88,10 +88,15 @@ def test_workspace_size_validation(lib):
     assert _size(lib, n, arr, nv, opts, capacity=0)[0] == _lib.RGS_EINVAL
     assert _size(lib, n, arr, nv, opts, flags=8)[0] == _lib.RGS_EINVAL
     for bad in (dict(p_min=0.0), dict(p_min=1.0), dict(alpha_max=0.001), dict(alpha_max=1.0), dict(t_eps=-1.0),
-                dict(mip=2), dict(mip_sigma2_px=-0.1), dict(tile_w=12, tile_h=12), dict(tile_w=64, tile_h=64),
+                dict(mip=3), dict(mip=-1), dict(mip_sigma2_px=-0.1), dict(tile_w=12, tile_h=12), dict(tile_w=64, tile_h=64),
                 dict(near_z=float("nan")), dict(background=(0, float("inf"), 0))):
         _, a2, _, o2 = _args(**bad)
         assert _size(lib, n, a2, nv, o2)[0] == _lib.RGS_EINVAL, bad
+    # exact MIP records are 112 B instead of 64 B per Gaussian-view
+    st0, b0 = _size(lib, n, arr, nv, opts)
+    _, a3, _, o3 = _args(mip=2)
+    st2, b2 = _size(lib, n, a3, nv, o3)
+    assert st0 == st2 == _lib.RGS_OK and b2 > b0
     for cam_bad in (dict(width=0), dict(height=20000), dict(fx=0.0), dict(fy=-1.0), dict(cx=float("nan"))):
         c = scenegen.pinhole(scenegen.look_at((0, 0, -4)), 64, 48, 60)
         c.update(cam_bad)
