@@ -11,6 +11,7 @@ Workloads (synthetic, seeded; see scenegen/scenes.py):
   c2            3M Gaussians, 4 stereo pairs (8 views, 2064x2208 per eye x
                 {0.5,1,2} per pair), MIP on; a step renders all 8 views in one
                 graph replay.  Metric: views/s (8 single-view renders reported too).
+                --mip exact renders the same frame with the exact per-ray MIP.
   c3            1M Gaussians, 4 views at 1600x1060; a step is forward + L1 loss
                 gradient + backward.  Metric: backward ms/view.
   c4            6M Gaussians, 16 cameras of uneven size (256..2560 x 256..1440)
@@ -63,6 +64,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=160)
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--mip", default="approx", choices=["approx", "exact"],
+                    help="c2: the approximate MIP of eq. 17 (the paper's renderer) or the exact per-ray MIP")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of HIP-graph replays")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-steps", type=int, default=32, help="frames of the per-stage timing pass")
@@ -228,6 +231,8 @@ def bench_c2(args, torch):
 
     w = scenegen.make_workload("c2")
     sc, cams, opts = w["scene"], w["cameras"], dict(w["options"], **tile_opts(args))
+    if args.mip == "exact":
+        opts["mip"] = 2
     n = int(sc["opacity_logits"].shape[0])
     g = to_dev(sc, torch)
     r = R.Renderer(0, opts)
@@ -265,7 +270,8 @@ def bench_c2(args, torch):
         "metric": METRIC, "value": 8e3 / ms, "unit": "views/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "c2: 3M Gaussians, 4 stereo pairs (8 views), MIP on, one HIP-graph replay",
+        "config": {"workload": "c2: 3M Gaussians, 4 stereo pairs (8 views), MIP on, one HIP-graph replay"
+                   + (" (exact per-ray MIP)" if args.mip == "exact" else ""),
                    "views": [[c["width"], c["height"]] for c in cams], "instance_capacity": capacity},
         "plain_launches_views_per_s": 8e3 / plain_ms,
         "roofline": roofline_for(dom, fwd[dom]),
