@@ -40,7 +40,7 @@ class Camera(C.Structure):
 class Options(C.Structure):
     _fields_ = [("p_min", C.c_double), ("alpha_max", C.c_double), ("t_eps", C.c_double), ("near_z", C.c_double),
                 ("mip", C.c_int32), ("mip_sigma2_px", C.c_double), ("background", C.c_double * 3),
-                ("tile_w", C.c_int32), ("tile_h", C.c_int32)]
+                ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("divergence", C.c_int32)]
 
 
 class Scene(C.Structure):
@@ -56,7 +56,8 @@ SPLAT_DTYPE = np.dtype(
      ("tx0", np.int32), ("tx1", np.int32), ("ty0", np.int32), ("ty1", np.int32), ("depth_key", np.uint32),
      ("pad", np.int32), ("rgb", np.float64, 3), ("rgb_raw", np.float64, 3), ("dir", np.float64, 3),
      ("dist", np.float64), ("cq", np.float64, 6), ("bounded", np.int32), ("listed", np.int32),
-     ("s0", np.float64, 3), ("sig2", np.float64), ("exact", np.int32), ("whole", np.int32)],
+     ("s0", np.float64, 3), ("sig2", np.float64), ("exact", np.int32), ("whole", np.int32), ("gs", np.int32),
+     ("pad2", np.int32), ("gs_A", np.float64, 3), ("gs_c", np.float64, 2)],
     align=True,
 )
 
@@ -120,6 +121,7 @@ def _options(opts):
     o.mip_sigma2_px = float(opts["mip_sigma2_px"])
     o.background[:] = [float(v) for v in opts["background"]]
     o.tile_w, o.tile_h = int(opts["tile_w"]), int(opts["tile_h"])
+    o.divergence = int(opts.get("divergence", 0))
     return o
 
 

@@ -37,6 +37,13 @@
  *   with a vertex at z <= 0 bounds the whole view; pixel centres sit at +1/2;
  *   colour = max(0, SH(view direction) + 0.5); depth key = bits of
  *   float32(mu_z), ties broken by Gaussian index.
+ *
+ * The linearised divergence of Sec. 3.1 (divergence = 1) replaces D_ray by
+ * D_gs(x) = (pi(x) - pi(mu))^T Sigma_pi^-1 (pi(x) - pi(mu)), Sigma_pi =
+ * J Sigma J^T with J the Jacobian of the pinhole projection at mu (pixel
+ * units), no low-pass term; its support D_gs <= kappa is an ellipse in the
+ * image, bounded by its axis-aligned box; no MIP; the near-plane and kappa
+ * culls apply, the camera-inside skip does not.
  */
 #include <math.h>
 #include <pthread.h>
@@ -57,6 +64,7 @@ typedef struct {
     double mip_sigma2_px;
     double background[3];
     int32_t tile_w, tile_h;
+    int32_t divergence; /* 0 = D_ray (eq. 5), 1 = D_gs of the linearised projection (Sec. 3.1) */
 } orc_options;
 
 typedef struct {
@@ -112,6 +120,10 @@ typedef struct {
     double sig2;      /* exact MIP: sigma^2 at the principal point, per unit distance */
     int32_t exact;    /* exact MIP weight per ray */
     int32_t whole;    /* exact MIP without a bounding Gaussian: the whole view */
+    int32_t gs;       /* D_gs: the pixel-space Gaussian below */
+    int32_t pad2;
+    double gs_A[3];   /* Sigma_pi^-1 (A00, A01, A11), pixel units */
+    double gs_c[2];   /* pi(mu), pixels */
 } orc_splat;
 
 /* --------------------------------------------------------- small helpers */
@@ -412,8 +424,8 @@ static int tile_listed(orc_splat *sp, const orc_options *opt, int tx, int ty)
     int cx1 = tx * TW + TW - 1 < sp->px1 ? tx * TW + TW - 1 : sp->px1;
     if (cx0 > cx1) return 0;
     if (!sp->bounded) return 1;
-    /* scale: |conic| at the projected centre = kappa c^2 / mu_z^2 */
-    double scale = sp->kappa * sp->c2 / (sp->mu[2] * sp->mu[2]);
+    /* scale: |conic| at the projected centre = kappa c^2 / mu_z^2 (kappa for D_gs) */
+    double scale = sp->gs ? sp->kappa : sp->kappa * sp->c2 / (sp->mu[2] * sp->mu[2]);
     int listed = 0;
     for (int b = 0; b < TH / LY; ++b) {
         int r0 = ty * TH + b * LY, r1 = r0 + LY - 1;
@@ -425,6 +437,23 @@ static int tile_listed(orc_splat *sp, const orc_options *opt, int tx, int ty)
         if (m <= 0.0) listed = 1;
     }
     return listed;
+}
+
+/* Pixel centres inside the bounding box [umin, umax] x [vmin, vmax] (pixel x
+ * covers centre x + 1/2), clipped to the view. */
+static void box_to_pixels(orc_splat *sp, const orc_camera *cam, double umin, double umax, double vmin, double vmax)
+{
+    int W_ = cam->width, H_ = cam->height;
+    sp->bbox[0] = umin; sp->bbox[1] = umax; sp->bbox[2] = vmin; sp->bbox[3] = vmax;
+    double fx0 = ceil(umin - 0.5), fx1 = floor(umax - 0.5);
+    double fy0 = ceil(vmin - 0.5), fy1 = floor(vmax - 0.5);
+    if (near_integer(umin - 0.5, 1e-9) || near_integer(umax - 0.5, 1e-9) || near_integer(vmin - 0.5, 1e-9) ||
+        near_integer(vmax - 0.5, 1e-9))
+        sp->hazard |= ORC_HZ_RECT;
+    sp->px0 = fx0 < 0.0 ? 0 : (fx0 > W_ ? W_ : (int)fx0);
+    sp->px1 = fx1 > W_ - 1 ? W_ - 1 : (fx1 < -1.0 ? -1 : (int)fx1);
+    sp->py0 = fy0 < 0.0 ? 0 : (fy0 > H_ ? H_ : (int)fy0);
+    sp->py1 = fy1 > H_ - 1 ? H_ - 1 : (fy1 < -1.0 ? -1 : (int)fy1);
 }
 
 /* ------------------------------------------------------ per-Gaussian stage */
@@ -477,6 +506,72 @@ static void preprocess_one(const orc_scene *sc, int64_t i, const orc_camera *cam
     mat3_mul(Wr, R, sp->Rp);
     double s[3] = {exp(l[0]), exp(l[1]), exp(l[2])};
     double o = 1.0 / (1.0 + exp(-a));
+
+    if (opt->divergence == 1) {
+        /* Sec. 3.1: the 2D Gaussian of the projection linearised at mu */
+        memcpy(sp->s, s, sizeof s);
+        memcpy(sp->s0, s, sizeof s);
+        sp->o = o;
+        sp->gs = 1;
+        double kappa = -2.0 * log(opt->p_min / o);
+        sp->kappa = kappa;
+        if (fabs(kappa) <= 1e-12) sp->hazard |= ORC_HZ_CULL;
+        if (!(kappa > 0.0)) {
+            sp->cull = ORC_CULL_KAPPA;
+            return;
+        }
+        double iz = 1.0 / mu[2];
+        double J[6] = {cam->fx * iz, 0.0, -cam->fx * mu[0] * iz * iz, 0.0, cam->fy * iz, -cam->fy * mu[1] * iz * iz};
+        double Sig[9], RS[9], RpT[9];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                RS[3 * r + c] = sp->Rp[3 * r + c] * s[c] * s[c];
+                RpT[3 * r + c] = sp->Rp[3 * c + r];
+            }
+        mat3_mul(RS, RpT, Sig);
+        double JS[6];
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 3; ++c)
+                JS[3 * r + c] = J[3 * r] * Sig[c] + J[3 * r + 1] * Sig[3 + c] + J[3 * r + 2] * Sig[6 + c];
+        double P00 = JS[0] * J[0] + JS[1] * J[1] + JS[2] * J[2];
+        double P01 = JS[0] * J[3] + JS[1] * J[4] + JS[2] * J[5];
+        double P11 = JS[3] * J[3] + JS[4] * J[4] + JS[5] * J[5];
+        double det = P00 * P11 - P01 * P01;
+        if (!(det > 0.0)) {
+            sp->cull = ORC_CULL_INVALID;
+            return;
+        }
+        sp->gs_A[0] = P11 / det;
+        sp->gs_A[1] = -P01 / det;
+        sp->gs_A[2] = P00 / det;
+        double uc = cam->fx * mu[0] * iz + cam->cx, vc = cam->fy * mu[1] * iz + cam->cy;
+        sp->gs_c[0] = uc;
+        sp->gs_c[1] = vc;
+        /* the support ellipse (d^T Sigma_pi^-1 d <= kappa) and its box */
+        double eu = sqrt(kappa * P00), ev = sqrt(kappa * P11);
+        sp->all_front = 1;
+        box_to_pixels(sp, cam, uc - eu, uc + eu, vc - ev, vc + ev);
+        if (sp->px0 > sp->px1 || sp->py0 > sp->py1) {
+            sp->cull = ORC_CULL_OFFSCREEN;
+            return;
+        }
+        sp->tx0 = sp->px0 / opt->tile_w; sp->tx1 = sp->px1 / opt->tile_w;
+        sp->ty0 = sp->py0 / opt->tile_h; sp->ty1 = sp->py1 / opt->tile_h;
+        const double *A = sp->gs_A;
+        sp->cq[0] = A[0]; sp->cq[1] = A[1]; sp->cq[2] = A[2];
+        sp->cq[3] = -(A[0] * uc + A[1] * vc);
+        sp->cq[4] = -(A[1] * uc + A[2] * vc);
+        sp->cq[5] = A[0] * uc * uc + 2.0 * A[1] * uc * vc + A[2] * vc * vc - kappa;
+        sp->bounded = 1;
+        sp->listed = 0;
+        for (int ty = sp->ty0; ty <= sp->ty1; ++ty)
+            for (int tx = sp->tx0; tx <= sp->tx1; ++tx) sp->listed += tile_listed(sp, opt, tx, ty);
+        if (sp->listed == 0) {
+            sp->cull = ORC_CULL_NOTILE;
+            return;
+        }
+        goto colour;
+    }
 
     if (opt->mip == 1) {
         /* Sec. 5, eq. (17): Sigma^ = Sigma + sigma^2 tau^2 I with a
@@ -642,17 +737,8 @@ static void preprocess_one(const orc_scene *sc, int64_t i, const orc_camera *cam
             umin = fmin(umin, u); umax = fmax(umax, u);
             vmin = fmin(vmin, v); vmax = fmax(vmax, v);
         }
-        sp->bbox[0] = umin; sp->bbox[1] = umax; sp->bbox[2] = vmin; sp->bbox[3] = vmax;
-        /* pixel x covers centre x + 1/2: the covered centres are those inside the box */
-        double fx0 = ceil(umin - 0.5), fx1 = floor(umax - 0.5);
-        double fy0 = ceil(vmin - 0.5), fy1 = floor(vmax - 0.5);
-        if (near_integer(umin - 0.5, 1e-9) || near_integer(umax - 0.5, 1e-9) || near_integer(vmin - 0.5, 1e-9) ||
-            near_integer(vmax - 0.5, 1e-9))
-            sp->hazard |= ORC_HZ_RECT;
-        px0 = fx0 < 0.0 ? 0 : (fx0 > W_ ? W_ : (int)fx0);
-        px1 = fx1 > W_ - 1 ? W_ - 1 : (fx1 < -1.0 ? -1 : (int)fx1);
-        py0 = fy0 < 0.0 ? 0 : (fy0 > H_ ? H_ : (int)fy0);
-        py1 = fy1 > H_ - 1 ? H_ - 1 : (fy1 < -1.0 ? -1 : (int)fy1);
+        box_to_pixels(sp, cam, umin, umax, vmin, vmax);
+        px0 = sp->px0; px1 = sp->px1; py0 = sp->py0; py1 = sp->py1;
     } else {
         sp->bbox[0] = -INFINITY; sp->bbox[1] = INFINITY; sp->bbox[2] = -INFINITY; sp->bbox[3] = INFINITY;
         px0 = 0; px1 = W_ - 1; py0 = 0; py1 = H_ - 1;
@@ -794,7 +880,7 @@ static void free_rows(row_lists *rl)
 static int ray_hits_quad(const orc_splat *s, const double *x)
 {
     double xl[3], xw[3];
-    if (s->whole) return 1;
+    if (s->whole || s->gs) return 1; /* no quad: every pixel of the box */
     mat3t_vec(s->Rp, x, xl);
     for (int k = 0; k < 3; ++k) xw[k] = xl[k] / s->s[k];
     double den = dot3(xw, s->mu_w);
@@ -837,7 +923,12 @@ static void shade_pixel(const orc_splat *sp, const int64_t *cand, int64_t nc, in
         ++inbox;
         frags += ray_hits_quad(s, x);
         double tau, w;
-        if (s->exact) {
+        if (s->gs) {
+            double du = px + 0.5 - s->gs_c[0], dv = py + 0.5 - s->gs_c[1];
+            double D = s->gs_A[0] * du * du + 2.0 * s->gs_A[1] * du * dv + s->gs_A[2] * dv * dv;
+            w = s->o * exp(-0.5 * D);
+            tau = 1.0;
+        } else if (s->exact) {
             w = orc_mip_exact_weight(s->mu, s->Rp, s->s0, s->o, s->sig2, x, &tau);
         } else {
             double D = orc_divergence(s->mu, s->Rp, s->s, x, &tau, NULL);
@@ -1036,7 +1127,7 @@ static double mip_chain(const double *mu, const double *Rp, const double *s0, co
 int orc_backward(const orc_scene *sc, const orc_camera *cam, const orc_options *opt, const double *dL_dC,
                  double *g_means, double *g_log_scales, double *g_quats, double *g_opacity, double *g_sh)
 {
-    if (opt->mip == 2) return -2; /* the exact MIP weight is not differentiated */
+    if (opt->mip == 2 || opt->divergence == 1) return -2; /* exact MIP and D_gs: forward only */
     int64_t n = sc->n;
     const int W = cam->width, H = cam->height;
     orc_splat *sp = (orc_splat *)malloc(sizeof(orc_splat) * (n ? n : 1));

@@ -46,6 +46,7 @@ def default_options(**kw):
         background=(0.0, 0.0, 0.0),
         tile_w=16,
         tile_h=16,
+        divergence=0,
     )
     opts.update(kw)
     return opts

@@ -738,3 +738,77 @@ def test_mip_exact_support_inside_listed_tiles(oracle_lib):
                 bounded_hits += 1
                 widened += plain[i]["cull"] != 0 or np.any(px < plain[i]["px0"]) or np.any(px > plain[i]["px1"])
     assert whole > 0 and bounded_hits > 50 and widened > 5
+
+
+# ------------------------------------------- linearised divergence (Sec. 3.1)
+GS = scenegen.default_options(divergence=1, tile_w=8, tile_h=8)
+
+
+def _numeric_sigma_pi(mu, Sig, cam, h=1e-6):
+    """J Sigma J^T with J from central differences of the pinhole projection."""
+    def pi(p):
+        return np.array([cam["fx"] * p[0] / p[2] + cam["cx"], cam["fy"] * p[1] / p[2] + cam["cy"]])
+
+    J = np.stack([(pi(mu + h * e) - pi(mu - h * e)) / (2 * h) for e in np.eye(3)], 1)
+    return J @ Sig @ J.T, pi(mu)
+
+
+def test_gs_on_axis_isotropic_closed_form(oracle_lib):
+    """An isotropic Gaussian of scale s on the optical axis at depth z
+    projects to the pixel-space Gaussian of standard deviation f s / z."""
+    cam = _ident_cam(40, 40, 60)
+    z, s, o = 4.0, 0.05, 0.8
+    sc = _one_gaussian_scene([[0.0, 0.0, z]], [[s] * 3], [o], [[0.9, 0.5, 0.2]])
+    out = oracle.render(sc, cam, GS)
+    ys, xs = np.mgrid[0:40, 0:40]
+    d2 = (xs + 0.5 - cam["cx"]) ** 2 + (ys + 0.5 - cam["cy"]) ** 2
+    w = o * np.exp(-0.5 * d2 / (cam["fx"] * s / z) ** 2)
+    a = np.where(w >= GS["p_min"], np.minimum(w, GS["alpha_max"]), 0.0)
+    np.testing.assert_allclose(out["T"], 1 - a, atol=1e-12)
+    np.testing.assert_allclose(out["rgb"][0], 0.9 * a, atol=1e-6)  # colour stored as float32 SH
+
+
+def test_gs_projected_covariance_and_support(oracle_lib):
+    """Sigma_pi^-1 of the oracle equals the inverse of J Sigma J^T with J by
+    central differences of the projection, and every pixel whose D_gs (from
+    that independent Sigma_pi) gives omega >= p_min lies in a listed tile."""
+    hits = 0
+    for seed in (42, 43):
+        sc = scenegen.tiny_scene(seed, 200, log_scale_mean=-2.8, log_scale_std=0.7)
+        cam = scenegen.pinhole(scenegen.look_at((0.3, -0.2, -3.0)), 72, 56, 70)
+        sp = oracle.preprocess(sc, cam, GS)
+        tiles, _, ids = oracle.tile_lists(sp, cam, GS)
+        tiles_x = -(-cam["width"] // 8)
+        ys, xs = np.mgrid[0:cam["height"], 0:cam["width"]]
+        for i, r in enumerate(sp):
+            if r["cull"] in (1, 2, 3):
+                continue
+            Rp = r["Rp"].reshape(3, 3)
+            Sp, c = _numeric_sigma_pi(r["mu"], Rp @ np.diag(r["s"] ** 2) @ Rp.T, cam)
+            A = np.linalg.inv(Sp)
+            np.testing.assert_allclose(r["gs_A"], [A[0, 0], A[0, 1], A[1, 1]], rtol=1e-6, atol=1e-9 * abs(A).max())
+            du, dv = xs + 0.5 - c[0], ys + 0.5 - c[1]
+            D = A[0, 0] * du * du + 2 * A[0, 1] * du * dv + A[1, 1] * dv * dv
+            sup = r["o"] * np.exp(-0.5 * D) >= GS["p_min"] * (1 + 1e-6)
+            if not sup.any():
+                continue
+            assert r["cull"] == 0
+            hits += 1
+            py, px = np.nonzero(sup)
+            need = set(((py // 8) * tiles_x + px // 8).tolist())
+            assert need <= set(tiles[ids == i].tolist()), (seed, i)
+    assert hits > 50
+
+
+def test_gs_approaches_ray_for_small_gaussians(oracle_lib):
+    """The linearisation error vanishes with the Gaussian's angular size: the
+    D_gs and D_ray images of a scene converge as the scales shrink."""
+    cam = scenegen.pinhole(scenegen.look_at((0, 0, -4)), 64, 64, 40)
+    errs = []
+    for lsm in (-3.0, -4.5, -6.0):
+        sc = scenegen.tiny_scene(44, 60, log_scale_mean=lsm, log_scale_std=0.3)
+        sc["opacity_logits"][:] = 3.0  # bright enough to stay above p_min when small
+        a = oracle.render(sc, cam, scenegen.default_options(tile_w=8, tile_h=8))
+        b = oracle.render(sc, cam, GS)
+        errs.append(np.abs(a["rgb"] - b["rgb"]).max())
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 0.05 * errs[0], errs
