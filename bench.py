@@ -12,6 +12,8 @@ Workloads (synthetic, seeded; see scenegen/scenes.py):
                 {0.5,1,2} per pair), MIP on; a step renders all 8 views in one
                 graph replay.  Metric: views/s (8 single-view renders reported too).
                 --mip exact renders the same frame with the exact per-ray MIP.
+  --divergence gs  c1 with the linearised divergence of 3DGS (Sec. 3.1) in the same
+                pipeline: the same-model speed comparison of GS and RayGS.
   c3            1M Gaussians, 4 views at 1600x1060; a step is forward + L1 loss
                 gradient + backward.  Metric: backward ms/view.
   c4            6M Gaussians, 16 cameras of uneven size (256..2560 x 256..1440)
@@ -66,6 +68,8 @@ def parse():
     ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--mip", default="approx", choices=["approx", "exact"],
                     help="c2: the approximate MIP of eq. 17 (the paper's renderer) or the exact per-ray MIP")
+    ap.add_argument("--divergence", default="ray", choices=["ray", "gs"],
+                    help="c1: the ray-based divergence (the paper's renderer) or the linearised one of 3DGS")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of HIP-graph replays")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-steps", type=int, default=32, help="frames of the per-stage timing pass")
@@ -163,6 +167,9 @@ def bench_c1(args, torch):
 
     w = scenegen.make_workload("c1")
     sc, cams, opts = w["scene"], w["cameras"], dict(w["options"], **tile_opts(args))
+    gs = args.divergence == "gs"
+    if gs:
+        opts["divergence"] = 1
     n = int(sc["opacity_logits"].shape[0])
     g = to_dev(sc, torch)
     r = R.Renderer(0, opts)
@@ -194,7 +201,7 @@ def bench_c1(args, torch):
     assert ok, "instance capacity overflow in the timed region"
     ms = (t1 - t0) * 1e3 / args.steps
     stages, frames = stage_pass(r, g, lambda k: [cams[k % 16]], opts, br.ws, br.outs, args.stage_steps)
-    wc = work_counts("c1")
+    wc = work_counts("c1_gs" if gs else "c1")
     fwd = {k: v for k, v in stages.items() if not k.endswith("backward")}
     dom = max(fwd, key=fwd.get)
     flops = nbytes = None
@@ -208,13 +215,14 @@ def bench_c1(args, torch):
         flops = FLOP_PER_FRAGMENT * frag + FLOP_PER_CONTRIBUTION * contrib
         nbytes = {"preprocess": PARAM_BYTES[3] * n + RECORD_BYTES * vis,
                   "tile_sort": 2 * 2 * INSTANCE_BYTES * inst}.get(dom)
-    tag = "c1_1080p_500k_" + args.tile
+    tag = "c1_1080p_500k_" + args.tile + ("_gs" if gs else "")
     roof = roofline_for(dom, fwd[dom], flops=flops, nbytes=nbytes, traffic=pmc_traffic(dom, tag))
     res = {
         "metric": METRIC, "value": 1e3 / ms, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "c1: 500k Gaussians (64 clusters, SH3), 1920x1080, 50deg FOV, 16 orbit poses",
+        "config": {"workload": "c1: 500k Gaussians (64 clusters, SH3), 1920x1080, 50deg FOV, 16 orbit poses"
+                   + (" (linearised GS divergence)" if gs else ""),
                    "n_gaussians": n, "width": 1920, "height": 1080, "tile": args.tile,
                    "launch": "eager" if args.eager else "hip_graph", "instance_capacity": capacity},
         "roofline": roof,

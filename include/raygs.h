@@ -85,6 +85,10 @@ typedef struct {
     int32_t width, height;   /* 1..16384 */
 } rgs_camera;
 
+/* Divergences (rgs_options.divergence). */
+#define RGS_DIVERGENCE_RAY 0
+#define RGS_DIVERGENCE_GS 1
+
 typedef struct {
     double p_min;          /* cut-off opacity of the support, eq. 3; in (0, 1); default 1/255 */
     double alpha_max;      /* opacity clamp, in (p_min, 1); default 0.99 */
@@ -101,6 +105,9 @@ typedef struct {
                               training step, MIP, Gaussian count in octaves, each view's pixel count in
                               half-octaves), training choices first, else 8x16; resolved at every call,
                               so query workspace sizes again after an autotune */
+    int32_t divergence;    /* RGS_DIVERGENCE_RAY (default): D_ray of eq. 5; RGS_DIVERGENCE_GS: the
+                              linearised D_gs of Sec. 3.1, (p - pi(mu))^T (J Sigma J^T)^-1 (p - pi(mu))
+                              with J the projection's Jacobian at mu (no MIP; forward only) */
 } rgs_options;
 
 typedef struct {

@@ -11,7 +11,11 @@ For each view of a workload it records, from a full oracle render:
                  early termination)
 These are the denominators of the roofline figures (work per launch).
 
-    python -m oracle.work_counts c1 [--tile 8x16] [--out tests/golden/work_counts_c1.json]
+    python -m oracle.work_counts c1 [--tile 8x16] [--divergence ray|gs] [--out tests/golden/work_counts_c1.json]
+
+With --divergence gs the frames are rendered with the linearised divergence
+(written to work_counts_<workload>_gs.json); its fragments are the pixel
+centres inside each splat's box.
 """
 from __future__ import annotations
 
@@ -29,9 +33,11 @@ import oracle  # noqa: E402
 import scenegen  # noqa: E402
 
 
-def counts(name: str, views=None, tile=None):
+def counts(name: str, views=None, tile=None, divergence="ray"):
     w = scenegen.make_workload(name)
     sc, cams, opts = w["scene"], w["cameras"], dict(w["options"])
+    if divergence == "gs":
+        opts["divergence"], opts["mip"] = 1, 0
     if tile:
         opts["tile_w"], opts["tile_h"] = (int(x) for x in tile.lower().split("x"))
     out = []
@@ -51,9 +57,11 @@ def main():
     ap.add_argument("workload", default="c1", nargs="?")
     ap.add_argument("--out", default=None)
     ap.add_argument("--tile", default=None, help="tile shape WxH (default: the workload's)")
+    ap.add_argument("--divergence", default="ray", choices=["ray", "gs"])
     a = ap.parse_args()
-    res = counts(a.workload, tile=a.tile)
-    path = a.out or os.path.join(ROOT, "tests", "golden", f"work_counts_{a.workload}.json")
+    res = counts(a.workload, tile=a.tile, divergence=a.divergence)
+    suffix = "_gs" if a.divergence == "gs" else ""
+    path = a.out or os.path.join(ROOT, "tests", "golden", f"work_counts_{a.workload}{suffix}.json")
     with open(path, "w") as f:
         json.dump(res, f, indent=1)
     print("wrote", path)

@@ -40,7 +40,7 @@ class Camera(C.Structure):
 class Options(C.Structure):
     _fields_ = [("p_min", C.c_double), ("alpha_max", C.c_double), ("t_eps", C.c_double), ("near_z", C.c_double),
                 ("mip", C.c_int32), ("mip_sigma2_px", C.c_double), ("background", C.c_double * 3),
-                ("tile_w", C.c_int32), ("tile_h", C.c_int32)]
+                ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("divergence", C.c_int32)]
 
 
 class ViewOut(C.Structure):

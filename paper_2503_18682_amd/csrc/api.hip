@@ -111,7 +111,7 @@ std::string tune_class(bool training, int64_t n, const rgs_camera *cams, int32_t
     for (int v = 0; v < n_views; ++v)
         px.push_back((int)std::lround(2.0 * std::log2(std::max(1.0, (double)cams[v].width * (double)cams[v].height))));
     std::sort(px.begin(), px.end());
-    std::string k = std::string(training ? "t" : "r") + std::to_string(o.mip) + "/" +
+    std::string k = std::string(training ? "t" : "r") + std::to_string(o.mip) + "d" + std::to_string(o.divergence) + "/" +
                     std::to_string((int)std::floor(std::log2((double)n + 1.0)));
     for (int x : px) k += "," + std::to_string(x);
     return k;
@@ -179,6 +179,10 @@ rgs_status check_options(rgs_context *ctx, const rgs_options *o)
     if (!(o->t_eps >= 0.0 && o->t_eps < 1.0)) return fail(ctx, RGS_EINVAL, "t_eps must lie in [0, 1)");
     if (!std::isfinite(o->near_z)) return fail(ctx, RGS_EINVAL, "near_z must be finite");
     if (o->mip < 0 || o->mip > 2) return fail(ctx, RGS_EINVAL, "mip must be 0, 1 or 2");
+    if (o->divergence != RGS_DIVERGENCE_RAY && o->divergence != RGS_DIVERGENCE_GS)
+        return fail(ctx, RGS_EINVAL, "divergence must be RGS_DIVERGENCE_RAY or RGS_DIVERGENCE_GS");
+    if (o->divergence == RGS_DIVERGENCE_GS && o->mip != 0)
+        return fail(ctx, RGS_EINVAL, "MIP applies to the ray-based divergence only");
     if (!(o->mip_sigma2_px >= 0.0) || !std::isfinite(o->mip_sigma2_px))
         return fail(ctx, RGS_EINVAL, "mip_sigma2_px must be finite and >= 0");
     for (int k = 0; k < 3; ++k)
@@ -282,6 +286,7 @@ DevOptions dev_options(const rgs_options &o)
     d.near_z = o.near_z;
     d.mip_sigma2_px = o.mip_sigma2_px;
     d.mip = o.mip;
+    d.divergence = o.divergence;
     const TileShape s = shape_of(o);
     d.tile_w = s.w;
     d.tile_h = s.h;
@@ -594,6 +599,8 @@ rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const r
         if (!dL_drgb[v]) return fail(ctx, RGS_EINVAL, "dL_drgb[%d] is NULL", v);
     if (!grads) return fail(ctx, RGS_EINVAL, "grads is NULL");
     if (opts->mip == 2) return fail(ctx, RGS_EUNSUPPORTED, "the exact MIP weight (mip = 2) is not differentiated");
+    if (opts->divergence == RGS_DIVERGENCE_GS)
+        return fail(ctx, RGS_EUNSUPPORTED, "the linearised divergence is not differentiated");
     if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh))
         return fail(ctx, RGS_EINVAL, "NULL gradient pointer");
     hipStream_t s = static_cast<hipStream_t>(stream);

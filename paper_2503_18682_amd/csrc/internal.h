@@ -30,6 +30,7 @@ struct DevOptions {
     double p_min, alpha_max, t_eps, near_z, mip_sigma2_px;
     int32_t mip;
     int32_t tile_w, tile_h;
+    int32_t divergence;  // RGS_DIVERGENCE_*
     float bg[3];
 };
 

@@ -149,6 +149,54 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
             float log2o = log2o_o;
             double ml[3];  // R_p^T mu: centre in the Gaussian's own axes
             for (int c = 0; c < 3; ++c) ml[c] = Rp[c] * mu[0] + Rp[3 + c] * mu[1] + Rp[6 + c] * mu[2];
+            if (opt.divergence == RGS_DIVERGENCE_GS) {
+                // Linearised divergence (Sec. 3.1): the pixel-space Gaussian of
+                // covariance Sigma_pi = J Sigma J^T, J the Jacobian of the
+                // projection at mu; support D_gs <= kappa, an ellipse bounded
+                // by its axis-aligned box.  Its record is the plain one with
+                // den = 1 (k0 = 1, g = 0, 1/c^2 = 0) and G the Cholesky factor
+                // of Sigma_pi^-1, so the compositing kernel evaluates
+                // q = |G delta|^2 = D_gs.
+                if (!(kappa > 0.0)) break;
+                const double iz = 1.0 / mu[2];
+                const double J0[3] = {V.fx * iz, 0.0, -V.fx * mu[0] * iz * iz};
+                const double J1[3] = {0.0, V.fy * iz, -V.fy * mu[1] * iz * iz};
+                double M0[3], M1[3];  // J R_p S
+                for (int c = 0; c < 3; ++c) {
+                    M0[c] = (J0[0] * Rp[c] + J0[1] * Rp[3 + c] + J0[2] * Rp[6 + c]) * sv[c];
+                    M1[c] = (J1[0] * Rp[c] + J1[1] * Rp[3 + c] + J1[2] * Rp[6 + c]) * sv[c];
+                }
+                const double P00 = M0[0] * M0[0] + M0[1] * M0[1] + M0[2] * M0[2];
+                const double P01 = M0[0] * M1[0] + M0[1] * M1[1] + M0[2] * M1[2];
+                const double P11 = M1[0] * M1[0] + M1[1] * M1[1] + M1[2] * M1[2];
+                const double det = P00 * P11 - P01 * P01;
+                if (!(det > 0.0)) break;
+                const double idet = 1.0 / det;
+                const double A00 = P11 * idet, A01 = -P01 * idet, A11 = P00 * idet;
+                const Centre pc = projected_centre(mu, V);
+                const double eu = sqrt(kappa * P00), ev = sqrt(kappa * P11);
+                const int Wd = V.width, Hd = V.height;
+                const double fx0 = ceil(pc.u - eu - 0.5), fx1 = floor(pc.u + eu - 0.5);
+                const double fy0 = ceil(pc.v - ev - 0.5), fy1 = floor(pc.v + ev - 0.5);
+                const int px0 = fx0 < 0.0 ? 0 : (fx0 > Wd ? Wd : (int)fx0);
+                const int px1 = fx1 > Wd - 1 ? Wd - 1 : (fx1 < -1.0 ? -1 : (int)fx1);
+                const int py0 = fy0 < 0.0 ? 0 : (fy0 > Hd ? Hd : (int)fy0);
+                const int py1 = fy1 > Hd - 1 ? Hd - 1 : (fy1 < -1.0 ? -1 : (int)fy1);
+                if (px0 > px1 || py0 > py1) break;
+                box = make_uint2((uint32_t)px0 | ((uint32_t)px1 << 16), (uint32_t)py0 | ((uint32_t)py1 << 16));
+                key = __float_as_uint((float)mu[2]);
+                cnt = (uint32_t)((px1 / opt.tile_w - px0 / opt.tile_w + 1) * (py1 / opt.tile_h - py0 / opt.tile_h + 1));
+                const double G00 = sqrt(A00), G01 = A01 / G00, G11 = sqrt(A11 - G01 * G01);
+                float4 *rec = records + idx * 4;
+                rec[0] = make_float4(pc.u_hi, pc.v_hi, __uint_as_float(pc.lo_bits),
+                                     __uint_as_float((uint32_t)py0 | ((uint32_t)py1 << 16)));
+                rec[1] = make_float4((float)G00, (float)G01, 0.0f, (float)G11);
+                rec[2] = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
+                const float4 col = colours[idx];
+                rec[3] = make_float4(log2o, col.x, col.y, col.z);
+                conics[idx] = Conic{A00, A01, A11, 0.0, 0.0, kappa, pc.u, pc.v};
+                break;
+            }
             bool whole = false;  // exact MIP without a bounding Gaussian
             if (opt.mip == 2) {
                 // Exact MIP: the camera-inside skip applies to the Gaussian

@@ -19,7 +19,8 @@ from . import _lib as L
 PARAM_KEYS = ("means", "log_scales", "quats", "opacity_logits", "sh")
 
 DEFAULT_OPTIONS = dict(p_min=1.0 / 255.0, alpha_max=0.99, t_eps=1e-4, near_z=0.2, mip=0, mip_sigma2_px=0.1,
-                       background=(0.0, 0.0, 0.0), tile_w=0, tile_h=0)  # 0, 0: tuned shape or 8x16
+                       background=(0.0, 0.0, 0.0), tile_w=0, tile_h=0,  # 0, 0: tuned shape or 8x16
+                       divergence=0)
 
 
 def _check(lib, ctx, status):
@@ -38,12 +39,14 @@ def make_options(opts: Optional[dict] = None) -> L.Options:
     s.mip_sigma2_px = float(o["mip_sigma2_px"])
     s.background[:] = [float(v) for v in o["background"]]
     s.tile_w, s.tile_h = int(o["tile_w"]), int(o["tile_h"])
+    s.divergence = int(o["divergence"])
     return s
 
 
 def options_dict(s: L.Options) -> dict:
     return dict(p_min=s.p_min, alpha_max=s.alpha_max, t_eps=s.t_eps, near_z=s.near_z, mip=s.mip,
-                mip_sigma2_px=s.mip_sigma2_px, background=tuple(s.background), tile_w=s.tile_w, tile_h=s.tile_h)
+                mip_sigma2_px=s.mip_sigma2_px, background=tuple(s.background), tile_w=s.tile_w, tile_h=s.tile_h,
+                divergence=s.divergence)
 
 
 def make_cameras(cams: Sequence[dict]):

@@ -1,0 +1,116 @@
+"""GPU parity of the linearised divergence (divergence = 1, Sec. 3.1) against
+the CPU oracle, through the C ABI: images within 2e-4 outside the hazard mask,
+keys, boxes and tile lists bit-exact.  Only the preprocess differs from the
+ray-based path; compositing and binning are shared."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen
+from gpu_helpers import (assert_image_close, instance_lists, oracle_box_tiles, oracle_lists_without_hazards, read,
+                         render_with_ws, say, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def r():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_18682_amd import renderer as R
+
+    rr = R.Renderer(0)
+    yield rr
+    rr.close()
+
+
+def _lists_match(buf, lay, sp, cam, opts, label):
+    tiles, ids = instance_lists(buf, lay)
+    ot, _, oi, bad = oracle_lists_without_hazards(sp, cam, opts)
+    keep = ~np.isin(ids, list(bad)) if bad else np.ones_like(ids, bool)
+    say(f"  {label}: {len(ids)} listed, {len(bad)} hazard Gaussians excluded")
+    assert np.array_equal(tiles[keep], ot) and np.array_equal(ids[keep], oi)
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (16, 16), (32, 8)])
+def test_gs_ragged_image_keys_boxes_and_lists(r, shape):
+    say(f"case GS divergence ragged 131x77 tile {shape}")
+    sc = scenegen.tiny_scene(45, 400, sh_degree=2, half_extent=1.2, log_scale_mean=-2.8, log_scale_std=0.7)
+    cam = scenegen.pinhole(scenegen.look_at((-0.3, 0.5, -3.5)), 131, 77, 70)
+    opts = scenegen.default_options(divergence=1, tile_w=shape[0], tile_h=shape[1], background=(0.2, 0.1, 0.05))
+    outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
+    assert ok
+    assert_image_close(outs[0]["rgb"], outs[0]["final_T"], oracle.render(sc, cam, opts), label=f"GS {shape}")
+    sp = oracle.preprocess(sc, cam, opts)
+    kept, box_tiles = oracle_box_tiles(sp)
+    assert m == box_tiles.sum()
+    n = 400
+    good = kept & (sp["hazard"] == 0)
+    boxes = read(buf, lay.boxes, 4 * n, np.uint16).reshape(n, 4)
+    for f, col in (("px0", 0), ("px1", 1), ("py0", 2), ("py1", 3)):
+        assert np.array_equal(boxes[good, col], sp[f][good])
+    _lists_match(buf, lay, sp, cam, opts, f"GS {shape} lists")
+    b_outs = render_with_ws(r, sc, [cam], dict(opts, tile_w=8, tile_h=16))[0]
+    assert np.array_equal(outs[0]["rgb"], b_outs[0]["rgb"]) and np.array_equal(outs[0]["final_T"], b_outs[0]["final_T"])
+
+
+def test_gs_c1_full_size_sampled_pixels_and_lists(r):
+    say("case GS divergence c1 full size: 500k Gaussians, 1920x1080")
+    w = scenegen.make_workload("c1")
+    sc, cam = w["scene"], w["cameras"][0]
+    opts = dict(w["options"], divergence=1)
+    outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
+    assert ok
+    sp = oracle.preprocess(sc, cam, opts)
+    _lists_match(buf, lay, sp, cam, opts, "GS c1 lists")
+    rng = np.random.default_rng(6)
+    px = rng.integers(0, 1920, 2000)
+    py = rng.integers(0, 1080, 2000)
+    rgb, T, hz = oracle.render_pixels(sc, cam, opts, px, py)
+    ok_ = hz == 0
+    err = np.abs(outs[0]["rgb"][:, py, px].T - rgb)[ok_].max()
+    terr = np.abs(outs[0]["final_T"][py, px] - T)[ok_].max()
+    say(f"  GS c1 sampled: max|rgb-oracle|={err:.3e} max|T-oracle|={terr:.3e} hazard={int((~ok_).sum())}/2000")
+    assert (~ok_).mean() < 0.01
+    assert err <= 2e-4 and terr <= 2e-4
+
+
+def test_gs_graph_replays_match_eager(r):
+    from paper_2503_18682_amd import renderer as R
+
+    sc = scenegen.tiny_scene(46, 3000, sh_degree=2, half_extent=1.5, log_scale_mean=-3.5, log_scale_std=0.8)
+    cams = [scenegen.pinhole(scenegen.look_at((0, 0, -4)), 160, 120, 60),
+            scenegen.pinhole(scenegen.look_at((1, 1, -3)), 80, 90, 70)]
+    opts = scenegen.default_options(divergence=1)
+    g = to_dev(sc)
+    say("case GS divergence graph plan: 2 views, 3 replays")
+    br = R.BatchRenderer(r, 3000, 2, cams, capacity=200000, options=opts)
+    for rep in range(3):
+        moved = []
+        for c in cams:
+            c2 = dict(c)
+            c2["w2c"] = c["w2c"].copy()
+            c2["w2c"][0, 3] += 0.05 * rep
+            moved.append(c2)
+        outs = br.launch(g, moved)
+        assert br.status()[0]
+        eager = render_with_ws(r, sc, moved, opts)[0]
+        for v in range(2):
+            assert np.array_equal(outs[v]["rgb"].cpu().numpy(), eager[v]["rgb"]), (rep, v)
+            assert np.array_equal(outs[v]["final_T"].cpu().numpy(), eager[v]["final_T"]), (rep, v)
+    assert_image_close(eager[0]["rgb"], eager[0]["final_T"], oracle.render(sc, moved[0], opts), label="GS batch view 0")
+    br.close()
+
+
+def test_gs_backward_is_unsupported(r):
+    from paper_2503_18682_amd import _lib
+    from paper_2503_18682_amd import renderer as R
+
+    sc = scenegen.tiny_scene(47, 200, sh_degree=1)
+    cam = scenegen.pinhole(scenegen.look_at((0, 0, -3)), 48, 40, 60)
+    g = to_dev(sc, requires_grad=True)
+    img = R.render(r, g, [cam], scenegen.default_options(divergence=1))[0]
+    with pytest.raises(_lib.RayGSError) as ei:
+        img.sum().backward()
+    assert ei.value.status == _lib.RGS_EUNSUPPORTED
