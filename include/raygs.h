@@ -97,7 +97,9 @@ typedef struct {
     int32_t mip;           /* 0 = none (default); 1 = approximate MIP of Sec. 5, eq. 17; 2 = exact MIP of
                               Sec. 5 / App. B: per ray, Sigma + sigma_x^2 tau(x)^2 I with sigma_x^2 the
                               pixel's area at unit distance along the ray, opacity times
-                              sqrt(|Sigma| x.Sigma^-1 x / (|Sigma^_x| x.Sigma^_x^-1 x)); forward only */
+                              sqrt(|Sigma| x.Sigma^-1 x / (|Sigma^_x| x.Sigma^_x^-1 x)); forward only;
+                              3 = the widening of eq. 17 without its opacity modulation (the dilation-only
+                              ablation of Sec. 6.2); forward only */
     double mip_sigma2_px;  /* MIP pixel variance in px^2 at the principal point (Sec. 6 uses 0.1); >= 0 */
     double background[3];  /* added as T_final * background; default 0 */
     int32_t tile_w, tile_h;/* each 8, 16 or 32; 0, 0 = the shape rgs_autotune_training or rgs_autotune
@@ -180,7 +182,7 @@ rgs_status rgs_render_status(rgs_context *ctx, const rgs_workspace *ws, void *st
  * outs.  Walks each pixel's list back from n_contrib starting at final_T.
  * Gradients are added into `grads`.  With opts->mip = 1 they also flow
  * through the MIP widening and opacity modulation (eq. 17); opts->mip = 2
- * returns RGS_EUNSUPPORTED.
+ * or 3 returns RGS_EUNSUPPORTED.
  * Uses float atomics: results are order-nondeterministic in the last bits. */
 rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
                                const rgs_options *opts, const rgs_workspace *ws, const rgs_view_out *outs,
@@ -277,6 +279,19 @@ double rgs_wall_clock_hz(rgs_context *ctx);
 rgs_status rgs_set_stage_timing(rgs_context *ctx, int32_t enable);
 int32_t rgs_stage_times(rgs_context *ctx, double *ms, int32_t n, int64_t *frames);
 const char *rgs_stage_names(void);
+
+/* Box downsampling for anti-aliasing evaluation (Sec. 6.2 compares against
+ * 4-ray multisampling): dst[p][y][x] = the mean of the factor x factor block
+ * src[p][y factor + r][x factor + c], r, c < factor.  A view rendered with
+ * its focal lengths, principal point and size multiplied by `factor` has
+ * factor^2 rays per output pixel on an ordered grid, so this gives
+ * multisampled (factor 2) or supersampled images.  src: device
+ * [planes][height factor][width factor] floats; dst: device
+ * [planes][height][width]; both caller-owned, not overlapping.  factor in
+ * 1..16, width and height in 1..16384, planes in 1..4; RGS_EINVAL otherwise
+ * or for NULL pointers.  Stream-ordered. */
+rgs_status rgs_downsample_box(rgs_context *ctx, const float *src, int32_t width, int32_t height, int32_t factor,
+                              int32_t planes, float *dst, void *stream);
 
 #ifdef __cplusplus
 }

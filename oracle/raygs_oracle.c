@@ -573,7 +573,7 @@ static void preprocess_one(const orc_scene *sc, int64_t i, const orc_camera *cam
         goto colour;
     }
 
-    if (opt->mip == 1) {
+    if (opt->mip == 1 || opt->mip == 3) {
         /* Sec. 5, eq. (17): Sigma^ = Sigma + sigma^2 tau^2 I with a
          * pixel-invariant tau = |mu| (unit rays) and sigma^2 the pixel area at
          * unit distance; opacity modulated by sqrt(|Sigma| c^2 / (|Sigma^| c^^2)). */
@@ -590,7 +590,8 @@ static void preprocess_one(const orc_scene *sc, int64_t i, const orc_camera *cam
             c2p += ml[k] * ml[k] / s2;
             c2h += ml[k] * ml[k] / sh2[k];
         }
-        o = o * sqrt(det * c2p / (deth * c2h));
+        /* mip = 3: the widening alone (the dilation-only ablation of Sec. 6.2) */
+        if (opt->mip == 1) o = o * sqrt(det * c2p / (deth * c2h));
         for (int k = 0; k < 3; ++k) s[k] = sqrt(sh2[k]);
     }
     memcpy(sp->s, s, sizeof s);
@@ -1127,7 +1128,7 @@ static double mip_chain(const double *mu, const double *Rp, const double *s0, co
 int orc_backward(const orc_scene *sc, const orc_camera *cam, const orc_options *opt, const double *dL_dC,
                  double *g_means, double *g_log_scales, double *g_quats, double *g_opacity, double *g_sh)
 {
-    if (opt->mip == 2 || opt->divergence == 1) return -2; /* exact MIP and D_gs: forward only */
+    if (opt->mip >= 2 || opt->divergence == 1) return -2; /* exact MIP, dilation only, D_gs: forward only */
     int64_t n = sc->n;
     const int W = cam->width, H = cam->height;
     orc_splat *sp = (orc_splat *)malloc(sizeof(orc_splat) * (n ? n : 1));

@@ -178,7 +178,7 @@ rgs_status check_options(rgs_context *ctx, const rgs_options *o)
         return fail(ctx, RGS_EINVAL, "alpha_max must lie in (p_min, 1)");
     if (!(o->t_eps >= 0.0 && o->t_eps < 1.0)) return fail(ctx, RGS_EINVAL, "t_eps must lie in [0, 1)");
     if (!std::isfinite(o->near_z)) return fail(ctx, RGS_EINVAL, "near_z must be finite");
-    if (o->mip < 0 || o->mip > 2) return fail(ctx, RGS_EINVAL, "mip must be 0, 1 or 2");
+    if (o->mip < 0 || o->mip > 3) return fail(ctx, RGS_EINVAL, "mip must be 0, 1, 2 or 3");
     if (o->divergence != RGS_DIVERGENCE_RAY && o->divergence != RGS_DIVERGENCE_GS)
         return fail(ctx, RGS_EINVAL, "divergence must be RGS_DIVERGENCE_RAY or RGS_DIVERGENCE_GS");
     if (o->divergence == RGS_DIVERGENCE_GS && o->mip != 0)
@@ -598,7 +598,8 @@ rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const r
     for (int v = 0; v < n_views; ++v)
         if (!dL_drgb[v]) return fail(ctx, RGS_EINVAL, "dL_drgb[%d] is NULL", v);
     if (!grads) return fail(ctx, RGS_EINVAL, "grads is NULL");
-    if (opts->mip == 2) return fail(ctx, RGS_EUNSUPPORTED, "the exact MIP weight (mip = 2) is not differentiated");
+    if (opts->mip == 2 || opts->mip == 3)
+        return fail(ctx, RGS_EUNSUPPORTED, "mip = %d (exact MIP, dilation only) is not differentiated", opts->mip);
     if (opts->divergence == RGS_DIVERGENCE_GS)
         return fail(ctx, RGS_EUNSUPPORTED, "the linearised divergence is not differentiated");
     if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh))
@@ -842,6 +843,21 @@ double rgs_wall_clock_hz(rgs_context *ctx)
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess) return 0.0;
     return 1e3 * khz;
+}
+
+rgs_status rgs_downsample_box(rgs_context *ctx, const float *src, int32_t width, int32_t height, int32_t factor,
+                              int32_t planes, float *dst, void *stream)
+{
+    if (!ctx) return RGS_EINVAL;
+    ctx->err.clear();
+    if (!src || !dst) return fail(ctx, RGS_EINVAL, "src or dst is NULL");
+    if (factor < 1 || factor > 16) return fail(ctx, RGS_EINVAL, "factor=%d outside [1, 16]", factor);
+    if (width < 1 || width > 16384 || height < 1 || height > 16384)
+        return fail(ctx, RGS_EINVAL, "size %dx%d outside [1, 16384]", width, height);
+    if (planes < 1 || planes > 4) return fail(ctx, RGS_EINVAL, "planes=%d outside [1, 4]", planes);
+    RGS_HIP(ctx, hipSetDevice(ctx->device));
+    RGS_HIP(ctx, launch_downsample_box(src, width, height, factor, planes, dst, static_cast<hipStream_t>(stream)));
+    return RGS_OK;
 }
 
 rgs_status rgs_set_stage_timing(rgs_context *ctx, int32_t enable)

@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                     conics[idx] = Conic{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, pc.u, pc.v};
                     break;
                 }
-            } else if (opt.mip == 1) {
+            } else if (opt.mip == 1 || opt.mip == 3) {
                 // Approximate MIP (Sec. 5, eq. 17): add sigma^2 |mu|^2 to every
                 // variance (pixel-invariant tau = |mu|) and scale the opacity by
                 // sqrt(|Sigma| c^2 / (|Sigma^| c^^2)).
@@ -261,7 +261,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                     c2p += ml[k] * ml[k] * (isv[k] * isv[k]);
                     c2h += ml[k] * ml[k] * ish2[k];
                 }
-                const double ov = o * sqrt(det * c2p / (deth * c2h));
+                // mip = 3: the widening without the modulation (dilation only)
+                const double ov = opt.mip == 3 ? o : o * sqrt(det * c2p / (deth * c2h));
                 for (int k = 0; k < 3; ++k) {
                     sv[k] = sqrt(sh2[k]);
                     isv[k] = sv[k] * ish2[k];

@@ -265,6 +265,19 @@ class Renderer:
         self.lib.rgs_stage_times(self.ctx, ms, len(names), C.byref(frames))
         return dict(zip(names, list(ms))), frames.value
 
+    def downsample(self, img: torch.Tensor, factor: int) -> torch.Tensor:
+        """Box average of factor x factor blocks of a [P][H f][W f] float32
+        device image (rgs_downsample_box): [P][H][W]."""
+        assert img.dtype == torch.float32 and img.is_cuda and img.dim() == 3
+        img = img.contiguous()
+        p, hs, ws = img.shape
+        assert hs % factor == 0 and ws % factor == 0
+        out = torch.empty((p, hs // factor, ws // factor), dtype=torch.float32, device=img.device)
+        _check(self.lib, self.ctx, self.lib.rgs_downsample_box(self.ctx, C.c_void_p(img.data_ptr()), ws // factor,
+                                                               hs // factor, int(factor), p,
+                                                               C.c_void_p(out.data_ptr()), _stream(self.device)))
+        return out
+
     def set_view_clocks(self, stamps: Optional[torch.Tensor]):
         """Per-view completion clocks of later render_into calls: `stamps` is
         an int64 device tensor of max_views + 1 entries (None turns them off);

@@ -12,6 +12,7 @@ from .scenes import (  # noqa: F401
     make_cameras,
     make_workload,
     tiny_scene,
+    thin_structure_scene,
     default_options,
     fd_subcase,
 )

@@ -163,6 +163,22 @@ def tiny_scene(seed, n, *, sh_degree=0, half_extent=1.0, log_scale_mean=-2.0, lo
     )
 
 
+def thin_structure_scene(seed, n, *, half_extent=1.0, long_log_scale=-2.5, thin_log_scale=-6.5, sh_degree=0):
+    """Thin elongated Gaussians (grass- or wire-like: one axis ~e^-2.5, two
+    ~e^-6.5, i.e. a few pixels long and well under a pixel wide at the
+    evaluation views), the structures on which rendering at a coarser scale
+    than training aliases."""
+    rng = np.random.default_rng(seed)
+    sc = make_scene(rng, n, sh_degree=sh_degree, half_extent=half_extent, log_scale_mean=0.0, log_scale_std=0.3,
+                    logit_std=0.5)
+    ls = sc["log_scales"].astype(np.float64)
+    ls[0] += long_log_scale
+    ls[1:] += thin_log_scale
+    sc["log_scales"] = np.ascontiguousarray(ls, dtype=np.float32)
+    sc["opacity_logits"] = np.ascontiguousarray(sc["opacity_logits"] + 1.5, dtype=np.float32)
+    return sc
+
+
 def make_cameras(name, rng):
     if name == "c0":
         return [pinhole(look_at((0.0, 0.0, -4.0)), 128, 128, 60.0)]

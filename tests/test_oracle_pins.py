@@ -812,3 +812,18 @@ def test_gs_approaches_ray_for_small_gaussians(oracle_lib):
         b = oracle.render(sc, cam, GS)
         errs.append(np.abs(a["rgb"] - b["rgb"]).max())
     assert errs[0] > errs[1] > errs[2] and errs[2] < 0.05 * errs[0], errs
+
+
+def test_mip_dilation_only_widens_without_modulation(oracle_lib):
+    """mip = 3 (the dilation-only ablation): the scales of eq. (17) with the
+    prior opacity unchanged."""
+    sc = scenegen.tiny_scene(48, 100, sh_degree=0, log_scale_mean=-4.0, log_scale_std=1.0)
+    cam = scenegen.pinhole(scenegen.look_at((0, 0, -3)), 64, 64, 60)
+    plain = oracle.preprocess(sc, cam, scenegen.default_options())
+    full = oracle.preprocess(sc, cam, scenegen.default_options(mip=1))
+    dil = oracle.preprocess(sc, cam, scenegen.default_options(mip=3))
+    ok = (plain["cull"] != 1) & (plain["cull"] != 2)
+    assert ok.sum() > 50
+    np.testing.assert_array_equal(dil["s"][ok], full["s"][ok])
+    np.testing.assert_array_equal(dil["o"][ok], plain["o"][ok])
+    assert np.all(dil["o"][ok] >= full["o"][ok])
