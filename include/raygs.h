@@ -109,7 +109,7 @@ typedef struct {
                               so query workspace sizes again after an autotune */
     int32_t divergence;    /* RGS_DIVERGENCE_RAY (default): D_ray of eq. 5; RGS_DIVERGENCE_GS: the
                               linearised D_gs of Sec. 3.1, (p - pi(mu))^T (J Sigma J^T)^-1 (p - pi(mu))
-                              with J the projection's Jacobian at mu (no MIP; forward only) */
+                              with J the projection's Jacobian at mu (no MIP; differentiable) */
 } rgs_options;
 
 typedef struct {
@@ -182,7 +182,8 @@ rgs_status rgs_render_status(rgs_context *ctx, const rgs_workspace *ws, void *st
  * outs.  Walks each pixel's list back from n_contrib starting at final_T.
  * Gradients are added into `grads`.  With opts->mip = 1 they also flow
  * through the MIP widening and opacity modulation (eq. 17); opts->mip = 2
- * or 3 returns RGS_EUNSUPPORTED.
+ * or 3 returns RGS_EUNSUPPORTED.  With RGS_DIVERGENCE_GS they flow through
+ * pi(mu), the projection's Jacobian J(mu) and Sigma_pi = J Sigma J^T.
  * Uses float atomics: results are order-nondeterministic in the last bits. */
 rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
                                const rgs_options *opts, const rgs_workspace *ws, const rgs_view_out *outs,

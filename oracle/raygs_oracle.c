@@ -1076,7 +1076,77 @@ int orc_render_pixels(const orc_scene *sc, const orc_camera *cam, const orc_opti
  * Sigma^-1 = R_p diag(s^-2) R_p^T, R_p = W R(q/|q|), s = exp(l), mu = W m + t. */
 typedef struct {
     double d_mu[3], d_Rp[9], d_l[3], d_o, d_rgb[3];
+    double d_c[2], d_A[4]; /* D_gs: dL/d pi(mu) and dL/d Sigma_pi^-1 (2x2, row-major) */
 } splat_grad;
+
+/* D_gs (Sec. 3.1) of splat s at pixel (px, py); d receives p - pi(mu). */
+static double gs_divergence(const orc_splat *s, int px, int py, double *d)
+{
+    d[0] = px + 0.5 - s->gs_c[0];
+    d[1] = py + 0.5 - s->gs_c[1];
+    return s->gs_A[0] * d[0] * d[0] + 2.0 * s->gs_A[1] * d[0] * d[1] + s->gs_A[2] * d[1] * d[1];
+}
+
+/* Chain of the linearised divergence: from dL/d pi(mu) (d_c) and
+ * dL/d Sigma_pi^-1 (d_A) to dL/d mu, dL/d R_p and dL/d log s (added).
+ * Sigma_pi = J Sigma J^T with J(mu) the pinhole Jacobian and
+ * Sigma = R_p S^2 R_p^T: dL/dSigma_pi = -A d_A A (A = Sigma_pi^-1),
+ * dL/dSigma = J^T (dL/dSigma_pi) J, dL/dJ = 2 (dL/dSigma_pi) J Sigma, and
+ * pi(mu) has Jacobian J. */
+static void gs_chain(const orc_splat *s, const orc_camera *cam, const double *d_c, const double *d_A, double *d_mu,
+                     double *d_Rp, double *d_l)
+{
+    const double *mu = s->mu;
+    double iz = 1.0 / mu[2];
+    double J[6] = {cam->fx * iz, 0.0, -cam->fx * mu[0] * iz * iz, 0.0, cam->fy * iz, -cam->fy * mu[1] * iz * iz};
+    double A[4] = {s->gs_A[0], s->gs_A[1], s->gs_A[1], s->gs_A[2]};
+    double T[4], GP[4];
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) T[2 * r + c] = d_A[2 * r] * A[c] + d_A[2 * r + 1] * A[2 + c];
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) GP[2 * r + c] = -(A[2 * r] * T[c] + A[2 * r + 1] * T[2 + c]);
+    double Sig[9], RS[9], RpT[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            RS[3 * r + c] = s->Rp[3 * r + c] * s->s[c] * s->s[c];
+            RpT[3 * r + c] = s->Rp[3 * c + r];
+        }
+    mat3_mul(RS, RpT, Sig);
+    double GS[9], GJ[6];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0.0;
+            for (int r = 0; r < 2; ++r)
+                for (int c = 0; c < 2; ++c) acc += J[3 * r + a] * GP[2 * r + c] * J[3 * c + b];
+            GS[3 * a + b] = acc;
+        }
+    for (int r = 0; r < 2; ++r)
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0.0;
+            for (int c = 0; c < 2; ++c)
+                for (int a = 0; a < 3; ++a) acc += GP[2 * r + c] * J[3 * c + a] * Sig[3 * a + b];
+            GJ[3 * r + b] = 2.0 * acc;
+        }
+    /* pi(mu) and J(mu) */
+    for (int a = 0; a < 3; ++a) d_mu[a] += J[a] * d_c[0] + J[3 + a] * d_c[1];
+    d_mu[0] += GJ[2] * (-cam->fx * iz * iz);
+    d_mu[1] += GJ[5] * (-cam->fy * iz * iz);
+    d_mu[2] += GJ[0] * (-cam->fx * iz * iz) + GJ[2] * (2.0 * cam->fx * mu[0] * iz * iz * iz) +
+               GJ[4] * (-cam->fy * iz * iz) + GJ[5] * (2.0 * cam->fy * mu[1] * iz * iz * iz);
+    /* Sigma = R_p S^2 R_p^T */
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0.0;
+            for (int j = 0; j < 3; ++j) acc += GS[3 * r + j] * s->Rp[3 * j + c];
+            d_Rp[3 * r + c] += 2.0 * acc * s->s[c] * s->s[c];
+        }
+    for (int k = 0; k < 3; ++k) {
+        double acc = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) acc += s->Rp[3 * a + k] * GS[3 * a + b] * s->Rp[3 * b + k];
+        d_l[k] += 2.0 * s->s[k] * s->s[k] * acc;
+    }
+}
 
 /* Chain through the eq. (17) transform.  With s0 = exp(l), o0 = sigmoid(a),
  * ml = R_p^T mu, sigma^2 the pixel area at unit distance and tau^2 = |mu|^2:
@@ -1128,7 +1198,7 @@ static double mip_chain(const double *mu, const double *Rp, const double *s0, co
 int orc_backward(const orc_scene *sc, const orc_camera *cam, const orc_options *opt, const double *dL_dC,
                  double *g_means, double *g_log_scales, double *g_quats, double *g_opacity, double *g_sh)
 {
-    if (opt->mip >= 2 || opt->divergence == 1) return -2; /* exact MIP, dilation only, D_gs: forward only */
+    if (opt->mip >= 2) return -2; /* exact MIP and dilation only: forward only */
     int64_t n = sc->n;
     const int W = cam->width, H = cam->height;
     orc_splat *sp = (orc_splat *)malloc(sizeof(orc_splat) * (n ? n : 1));
@@ -1161,8 +1231,11 @@ int orc_backward(const orc_scene *sc, const orc_camera *cam, const orc_options *
             for (int64_t k = 0; k < nc; ++k) {
                 const orc_splat *s = &sp[cand[k]];
                 if (px < s->px0 || px > s->px1) continue;
-                double tau;
-                double D = orc_divergence(s->mu, s->Rp, s->s, x, &tau, NULL);
+                double tau = 1.0, D, dgs[2];
+                if (s->gs)
+                    D = gs_divergence(s, px, py, dgs);
+                else
+                    D = orc_divergence(s->mu, s->Rp, s->s, x, &tau, NULL);
                 if (!(tau > 0.0)) continue;
                 double w = s->o * exp(-0.5 * D);
                 if (!(w >= opt->p_min)) continue;
@@ -1190,6 +1263,18 @@ int orc_backward(const orc_scene *sc, const orc_camera *cam, const orc_options *
                 double dL_dw = dL_da;
                 G->d_o += dL_dw * c->w / s->o;
                 double dL_dD = -0.5 * c->w * dL_dw;
+                if (s->gs) {
+                    /* D_gs = d^T A d with d = p - pi(mu): dD/dpi = -2 A d, dD/dA = d d^T */
+                    double d[2];
+                    gs_divergence(s, px, py, d);
+                    G->d_c[0] += dL_dD * (-2.0 * (s->gs_A[0] * d[0] + s->gs_A[1] * d[1]));
+                    G->d_c[1] += dL_dD * (-2.0 * (s->gs_A[1] * d[0] + s->gs_A[2] * d[1]));
+                    G->d_A[0] += dL_dD * d[0] * d[0];
+                    G->d_A[1] += dL_dD * d[0] * d[1];
+                    G->d_A[2] += dL_dD * d[1] * d[0];
+                    G->d_A[3] += dL_dD * d[1] * d[1];
+                    continue;
+                }
                 double e[3];
                 orc_divergence(s->mu, s->Rp, s->s, x, NULL, e);
                 double f[3], Pe[3], fs[3];
@@ -1217,7 +1302,11 @@ int orc_backward(const orc_scene *sc, const orc_camera *cam, const orc_options *
         const double o0 = 1.0 / (1.0 + exp(-sc->opacity_logits[i]));
         memcpy(d_mu, G->d_mu, sizeof d_mu);
         memcpy(d_Rp, G->d_Rp, sizeof d_Rp);
-        if (opt->mip) {
+        if (s->gs) {
+            for (int k = 0; k < 3; ++k) d_l0[k] = G->d_l[k];
+            gs_chain(s, cam, G->d_c, G->d_A, d_mu, d_Rp, d_l0);
+            Lo = G->d_o * s->o;
+        } else if (opt->mip) {
             const double s0[3] = {exp(sc->log_scales[i]), exp(sc->log_scales[n + i]), exp(sc->log_scales[2 * n + i])};
             for (int k = 0; k < 3; ++k) d_l0[k] = 0.0;
             Lo = mip_chain(s->mu, s->Rp, s0, s->s, opt->mip_sigma2_px / (cam->fx * cam->fy), G->d_l, G->d_o, s->o,

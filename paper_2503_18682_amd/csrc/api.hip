@@ -600,8 +600,6 @@ rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const r
     if (!grads) return fail(ctx, RGS_EINVAL, "grads is NULL");
     if (opts->mip == 2 || opts->mip == 3)
         return fail(ctx, RGS_EUNSUPPORTED, "mip = %d (exact MIP, dilation only) is not differentiated", opts->mip);
-    if (opts->divergence == RGS_DIVERGENCE_GS)
-        return fail(ctx, RGS_EUNSUPPORTED, "the linearised divergence is not differentiated");
     if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh))
         return fail(ctx, RGS_EINVAL, "NULL gradient pointer");
     hipStream_t s = static_cast<hipStream_t>(stream);

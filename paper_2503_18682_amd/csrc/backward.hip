@@ -60,6 +60,64 @@ __device__ void mip_chain(const double (&mu)[3], const double (&Rp)[9], const do
         for (int k = 0; k < 3; ++k) dRp[3 * r + k] += a1[k] * mu[r];
 }
 
+// Chain of the linearised divergence (Sec. 3.1): the record holds
+// pi(mu) (gradient gc) and G with G^T G = A = Sigma_pi^-1 (gradient GA as a
+// symmetric matrix), Sigma_pi = J Sigma J^T with J(mu) the pinhole Jacobian
+// and Sigma = R_p S^2 R_p^T.  dL/dSigma_pi = -A GA A; dL/dSigma =
+// J^T (dL/dSigma_pi) J; dL/dJ = 2 (dL/dSigma_pi) J Sigma; pi has Jacobian J.
+// Adds dL/dmu, dL/dR_p and dL/dlog s.
+__device__ void gs_chain(const double mu[3], const double Rp[9], const double s[3], const DevView &V,
+                         const double gc[2], const double GA[2][2], double dmu[3], double dRp[9], double dls[3])
+{
+    const double iz = 1.0 / mu[2];
+    const double J[2][3] = {{V.fx * iz, 0.0, -V.fx * mu[0] * iz * iz}, {0.0, V.fy * iz, -V.fy * mu[1] * iz * iz}};
+    double M[2][3];  // J R_p S
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 3; ++c) M[r][c] = (J[r][0] * Rp[c] + J[r][1] * Rp[3 + c] + J[r][2] * Rp[6 + c]) * s[c];
+    const double P00 = M[0][0] * M[0][0] + M[0][1] * M[0][1] + M[0][2] * M[0][2];
+    const double P01 = M[0][0] * M[1][0] + M[0][1] * M[1][1] + M[0][2] * M[1][2];
+    const double P11 = M[1][0] * M[1][0] + M[1][1] * M[1][1] + M[1][2] * M[1][2];
+    const double idet = 1.0 / (P00 * P11 - P01 * P01);
+    const double A[2][2] = {{P11 * idet, -P01 * idet}, {-P01 * idet, P00 * idet}};
+    double T[2][2], GP[2][2];
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) T[r][c] = GA[r][0] * A[0][c] + GA[r][1] * A[1][c];
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) GP[r][c] = -(A[r][0] * T[0][c] + A[r][1] * T[1][c]);
+    // Sigma = (R_p S)(R_p S)^T
+    double Sig[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k) acc += Rp[3 * a + k] * Rp[3 * b + k] * s[k] * s[k];
+            Sig[a][b] = acc;
+        }
+    double PJ[2][3];  // GP J
+    for (int r = 0; r < 2; ++r)
+        for (int a = 0; a < 3; ++a) PJ[r][a] = GP[r][0] * J[0][a] + GP[r][1] * J[1][a];
+    double GS[3][3];  // J^T GP J
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) GS[a][b] = J[0][a] * PJ[0][b] + J[1][a] * PJ[1][b];
+    double GJ[2][3];  // 2 GP J Sigma
+    for (int r = 0; r < 2; ++r)
+        for (int b = 0; b < 3; ++b) GJ[r][b] = 2.0 * (PJ[r][0] * Sig[0][b] + PJ[r][1] * Sig[1][b] + PJ[r][2] * Sig[2][b]);
+    for (int a = 0; a < 3; ++a) dmu[a] += J[0][a] * gc[0] + J[1][a] * gc[1];
+    const double iz2 = iz * iz, iz3 = iz2 * iz;
+    dmu[0] += GJ[0][2] * (-V.fx * iz2);
+    dmu[1] += GJ[1][2] * (-V.fy * iz2);
+    dmu[2] += GJ[0][0] * (-V.fx * iz2) + GJ[0][2] * (2.0 * V.fx * mu[0] * iz3) + GJ[1][1] * (-V.fy * iz2) +
+              GJ[1][2] * (2.0 * V.fy * mu[1] * iz3);
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            dRp[3 * r + c] += 2.0 * (GS[r][0] * Rp[c] + GS[r][1] * Rp[3 + c] + GS[r][2] * Rp[6 + c]) * s[c] * s[c];
+    for (int k = 0; k < 3; ++k) {
+        double acc = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) acc += Rp[3 * a + k] * GS[a][b] * Rp[3 * b + k];
+        dls[k] += 2.0 * s[k] * s[k] * acc;
+    }
+}
+
 // Geometry and opacity (the colour part is k_colour_bwd).
 __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const float *__restrict__ means, const float *__restrict__ log_scales, const float *__restrict__ quats,
@@ -105,6 +163,20 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         double Rp[9];
         for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c) Rp[3 * r + c] = W[4 * r] * R[c] + W[4 * r + 1] * R[3 + c] + W[4 * r + 2] * R[6 + c];
+        if (opt.divergence == RGS_DIVERGENCE_GS) {
+            // the record's anchor is pi(mu) and its M = G^T G is Sigma_pi^-1;
+            // den, g, 1/c^2 are constants of this divergence
+            const double gc[2] = {gu0, gv0};
+            const double GA[2][2] = {{gM00, 0.5 * gM01}, {0.5 * gM01, gM11}};
+            double dmu[3] = {0, 0, 0}, dRp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            gs_chain(mu, Rp, s, V, gc, GA, dmu, dRp, dl);
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c)
+                    dR[3 * r + c] += W[r] * dRp[c] + W[4 + r] * dRp[3 + c] + W[8 + r] * dRp[6 + c];
+            for (int c = 0; c < 3; ++c) dm[c] += W[c] * dmu[0] + W[4 + c] * dmu[1] + W[8 + c] * dmu[2];
+            da += go * o * (1.0 - o);
+            continue;
+        }
         // rendered scales and opacity: widened by the MIP transform when it is on
         double sv[3] = {s[0], s[1], s[2]}, isv[3] = {is[0], is[1], is[2]};
         double ov = o;

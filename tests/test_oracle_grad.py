@@ -81,3 +81,15 @@ def test_exact_mip_backward_is_rejected(oracle_lib):
     dl = np.ones((3, cam["height"], cam["width"]))
     with pytest.raises(ValueError):
         oracle.backward(sc, cam, opts, dl)
+
+
+def test_gs_gradient_matches_central_differences(oracle_lib):
+    """The linearised divergence of Sec. 3.1: gradients through pi(mu), the
+    Jacobian J(mu) and Sigma = R_p S^2 R_p^T."""
+    scene, cam = scenegen.fd_subcase(seed=2005)
+    opts = scenegen.default_options(divergence=1)
+    out = oracle.render(scene, cam, opts)
+    assert out["hazard"].sum() == 0
+    w = np.random.default_rng(10).normal(0, 1, (3, 32, 32))
+    worst, count = _fd_check(scene, cam, opts, w)
+    assert count == 64 * 59
