@@ -73,6 +73,11 @@ __device__ inline Centre projected_centre(const double mu[3], const DevView &V)
 }
 
 
+// Kernel variants by divergence and MIP mode, so that each carries only its
+// own code (fewer registers and instructions in the common ray-based one).
+enum PrepMode { kPrepRay = 0, kPrepMipApprox = 1, kPrepMipExact = 2, kPrepGS = 3 };
+
+template <int MODE>
 __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ means,
                                                     const float *__restrict__ log_scales,
                                                     const float *__restrict__ quats,
@@ -149,7 +154,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
             float log2o = log2o_o;
             double ml[3];  // R_p^T mu: centre in the Gaussian's own axes
             for (int c = 0; c < 3; ++c) ml[c] = Rp[c] * mu[0] + Rp[3 + c] * mu[1] + Rp[6 + c] * mu[2];
-            if (opt.divergence == RGS_DIVERGENCE_GS) {
+            if constexpr (MODE == kPrepGS) {
                 // Linearised divergence (Sec. 3.1): the pixel-space Gaussian of
                 // covariance Sigma_pi = J Sigma J^T, J the Jacobian of the
                 // projection at mu; support D_gs <= kappa, an ellipse bounded
@@ -198,7 +203,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                 break;
             }
             bool whole = false;  // exact MIP without a bounding Gaussian
-            if (opt.mip == 2) {
+            if constexpr (MODE == kPrepMipExact) {
                 // Exact MIP: the camera-inside skip applies to the Gaussian
                 // itself; the quad, box and tiles are those of the Gaussian
                 // widened by a_max = sigma^2 tau_max^2, which bounds the
@@ -245,7 +250,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                     conics[idx] = Conic{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, pc.u, pc.v};
                     break;
                 }
-            } else if (opt.mip == 1 || opt.mip == 3) {
+            } else if constexpr (MODE == kPrepMipApprox) {
                 // Approximate MIP (Sec. 5, eq. 17): add sigma^2 |mu|^2 to every
                 // variance (pixel-invariant tau = |mu|) and scale the opacity by
                 // sqrt(|Sigma| c^2 / (|Sigma^| c^^2)).
@@ -402,7 +407,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
             // holds the covered pixel rows for in-tile culling
             const uint32_t rows = (uint32_t)py0 | ((uint32_t)py1 << 16);
             const float4 col = colours[idx];
-            if (opt.mip == 2) {
+            if constexpr (MODE == kPrepMipExact) {
                 write_exact_mip_record(records + idx * (kRecordFloatsExactMip / 4), mu, Rp, s, o,
                                        opt.mip_sigma2_px / (V.fx * V.fy), V, pc.u_hi, pc.v_hi, pc.lo_bits, rows, col);
             } else {
@@ -471,8 +476,21 @@ hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n
     default: RGS_COL(3); break;
     }
 #undef RGS_COL
-    k_preprocess<<<grid, block, 0, stream>>>(g.means, g.log_scales, g.quats, g.opacity_logits, n, views, n_views, opt,
-                                             colours, records, depth_keys, order, boxes, conics, tile_counts);
+    const int mode = opt.divergence == RGS_DIVERGENCE_GS ? kPrepGS
+                     : opt.mip == 2                     ? kPrepMipExact
+                     : (opt.mip == 1 || opt.mip == 3)   ? kPrepMipApprox
+                                                        : kPrepRay;
+#define RGS_PRE(M)                                                                                              \
+    k_preprocess<M><<<grid, block, 0, stream>>>(g.means, g.log_scales, g.quats, g.opacity_logits, n, views,     \
+                                                n_views, opt, colours, records, depth_keys, order, boxes, conics, \
+                                                tile_counts)
+    switch (mode) {
+    case kPrepGS: RGS_PRE(kPrepGS); break;
+    case kPrepMipExact: RGS_PRE(kPrepMipExact); break;
+    case kPrepMipApprox: RGS_PRE(kPrepMipApprox); break;
+    default: RGS_PRE(kPrepRay); break;
+    }
+#undef RGS_PRE
     return hipGetLastError();
 }
 
