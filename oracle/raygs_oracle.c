@@ -1079,6 +1079,65 @@ typedef struct {
     double d_c[2], d_A[4]; /* D_gs: dL/d pi(mu) and dL/d Sigma_pi^-1 (2x2, row-major) */
 } splat_grad;
 
+/* Gradient of ln omega of the exact MIP weight (orc_mip_exact_weight) for the
+ * ray xbar, times g, added into d_mu, d_Rp and d_l (log-scales).  In the
+ * Gaussian's axes, with xl = R_p^T xbar, ml = R_p^T mu, the plain sums
+ * P = sum xl^2/s^2 = xbar.Sigma^-1 xbar and Lp = sum ml xl/s^2, the widening
+ * a = sigma^2 Lp^2 / (|xbar| P^2) (sigma_x^2 tau^2 of the unit ray), the
+ * widened variances v = s^2 + a and Q = sum xl^2/v, L = sum ml xl/v,
+ * tau^ = L/Q:
+ *   ln omega = ln o + (1/2)(sum ln s^2 - sum ln v + ln P - ln Q) - D/2,
+ *   dD/dml_k = 2 (ml_k - tau^ xl_k)/v_k, dD/dv_k = -(ml_k - tau^ xl_k)^2/v_k^2,
+ *   dD/dxl_k = -2 tau^ (ml_k - tau^ xl_k)/v_k,
+ * and a reaches every v_k.  Returns d ln omega / d ln o (= 1) times g. */
+static double mip_exact_grad(const double *mu, const double *Rp, const double *s, double sig2, const double *xbar,
+                             double g, double *d_mu, double *d_Rp, double *d_l)
+{
+    double xl[3], ml[3], s2[3], v[3];
+    mat3t_vec(Rp, xbar, xl);
+    mat3t_vec(Rp, mu, ml);
+    double nx = sqrt(dot3(xbar, xbar));
+    double P = 0.0, Lp = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        s2[k] = s[k] * s[k];
+        P += xl[k] * xl[k] / s2[k];
+        Lp += ml[k] * xl[k] / s2[k];
+    }
+    double tb = Lp / P;
+    double a = sig2 / nx * tb * tb;
+    double Q = 0.0, L = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        v[k] = s2[k] + a;
+        Q += xl[k] * xl[k] / v[k];
+        L += ml[k] * xl[k] / v[k];
+    }
+    double th = L / Q;
+    double gv[3], gml[3], gxl[3], gs[3], ga = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double r = ml[k] - th * xl[k];
+        gv[k] = -0.5 / v[k] + xl[k] * xl[k] / (2.0 * Q * v[k] * v[k]) + r * r / (2.0 * v[k] * v[k]);
+        gml[k] = -r / v[k];
+        gxl[k] = -xl[k] / (Q * v[k]) + th * r / v[k] + xl[k] / (P * s2[k]);
+        gs[k] = 1.0 / s[k] - xl[k] * xl[k] / (P * s2[k] * s[k]) + gv[k] * 2.0 * s[k];
+        ga += gv[k];
+    }
+    /* a = sig2 / nx * (Lp / P)^2 */
+    double da_dLp = 2.0 * sig2 / nx * tb / P, da_dP = -2.0 * sig2 / nx * tb * tb / P;
+    for (int k = 0; k < 3; ++k) {
+        gml[k] += ga * da_dLp * xl[k] / s2[k];
+        gxl[k] += ga * (da_dLp * ml[k] / s2[k] + da_dP * 2.0 * xl[k] / s2[k]);
+        gs[k] += ga * (da_dLp * (-2.0 * ml[k] * xl[k] / (s2[k] * s[k])) + da_dP * (-2.0 * xl[k] * xl[k] / (s2[k] * s[k])));
+    }
+    double dmu[3];
+    mat3_vec(Rp, gml, dmu);
+    for (int r = 0; r < 3; ++r) {
+        d_mu[r] += g * dmu[r];
+        for (int k = 0; k < 3; ++k) d_Rp[3 * r + k] += g * (mu[r] * gml[k] + xbar[r] * gxl[k]);
+    }
+    for (int k = 0; k < 3; ++k) d_l[k] += g * gs[k] * s[k];
+    return g;
+}
+
 /* D_gs (Sec. 3.1) of splat s at pixel (px, py); d receives p - pi(mu). */
 static double gs_divergence(const orc_splat *s, int px, int py, double *d)
 {
@@ -1198,7 +1257,7 @@ static double mip_chain(const double *mu, const double *Rp, const double *s0, co
 int orc_backward(const orc_scene *sc, const orc_camera *cam, const orc_options *opt, const double *dL_dC,
                  double *g_means, double *g_log_scales, double *g_quats, double *g_opacity, double *g_sh)
 {
-    if (opt->mip >= 2) return -2; /* exact MIP and dilation only: forward only */
+    if (opt->mip == 3) return -2; /* dilation only: forward only */
     int64_t n = sc->n;
     const int W = cam->width, H = cam->height;
     orc_splat *sp = (orc_splat *)malloc(sizeof(orc_splat) * (n ? n : 1));
@@ -1231,13 +1290,17 @@ int orc_backward(const orc_scene *sc, const orc_camera *cam, const orc_options *
             for (int64_t k = 0; k < nc; ++k) {
                 const orc_splat *s = &sp[cand[k]];
                 if (px < s->px0 || px > s->px1) continue;
-                double tau = 1.0, D, dgs[2];
-                if (s->gs)
-                    D = gs_divergence(s, px, py, dgs);
-                else
-                    D = orc_divergence(s->mu, s->Rp, s->s, x, &tau, NULL);
+                double tau = 1.0, D = 0.0, dgs[2], w;
+                if (s->exact) {
+                    w = orc_mip_exact_weight(s->mu, s->Rp, s->s0, s->o, s->sig2, x, &tau);
+                } else {
+                    if (s->gs)
+                        D = gs_divergence(s, px, py, dgs);
+                    else
+                        D = orc_divergence(s->mu, s->Rp, s->s, x, &tau, NULL);
+                    w = s->o * exp(-0.5 * D);
+                }
                 if (!(tau > 0.0)) continue;
-                double w = s->o * exp(-0.5 * D);
                 if (!(w >= opt->p_min)) continue;
                 double a = w < opt->alpha_max ? w : opt->alpha_max;
                 double Tn = T * (1.0 - a);
@@ -1263,6 +1326,11 @@ int orc_backward(const orc_scene *sc, const orc_camera *cam, const orc_options *
                 double dL_dw = dL_da;
                 G->d_o += dL_dw * c->w / s->o;
                 double dL_dD = -0.5 * c->w * dL_dw;
+                if (s->exact) {
+                    /* dL/d ln omega = dL/domega omega (the d_o term above is its ln o part) */
+                    mip_exact_grad(s->mu, s->Rp, s->s0, s->sig2, x, dL_dw * c->w, G->d_mu, G->d_Rp, G->d_l);
+                    continue;
+                }
                 if (s->gs) {
                     /* D_gs = d^T A d with d = p - pi(mu): dD/dpi = -2 A d, dD/dA = d d^T */
                     double d[2];
@@ -1306,7 +1374,7 @@ int orc_backward(const orc_scene *sc, const orc_camera *cam, const orc_options *
             for (int k = 0; k < 3; ++k) d_l0[k] = G->d_l[k];
             gs_chain(s, cam, G->d_c, G->d_A, d_mu, d_Rp, d_l0);
             Lo = G->d_o * s->o;
-        } else if (opt->mip) {
+        } else if (opt->mip == 1) {
             const double s0[3] = {exp(sc->log_scales[i]), exp(sc->log_scales[n + i]), exp(sc->log_scales[2 * n + i])};
             for (int k = 0; k < 3; ++k) d_l0[k] = 0.0;
             Lo = mip_chain(s->mu, s->Rp, s0, s->s, opt->mip_sigma2_px / (cam->fx * cam->fy), G->d_l, G->d_o, s->o,

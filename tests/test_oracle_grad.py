@@ -75,9 +75,24 @@ def test_mip_gradient_matches_central_differences(oracle_lib):
     assert count == 64 * 59
 
 
-def test_exact_mip_backward_is_rejected(oracle_lib):
+def test_exact_mip_gradient_matches_central_differences(oracle_lib):
+    """The exact MIP weight (mip = 2): gradients through the per-ray widening
+    (tau of the ray, the footprint) and the per-ray modulation; a footprint of
+    4 px^2 makes the widening matter everywhere."""
+    scene, cam = scenegen.fd_subcase(seed=2008)  # a seed with no pixel at a threshold (hazard)
+    opts = scenegen.default_options(mip=2, mip_sigma2_px=4.0)
+    out = oracle.render(scene, cam, opts)
+    assert out["hazard"].sum() == 0
+    plain = oracle.render(scene, cam, scenegen.default_options())
+    assert np.abs(out["rgb"] - plain["rgb"]).max() > 1e-2
+    w = np.random.default_rng(13).normal(0, 1, (3, 32, 32))
+    worst, count = _fd_check(scene, cam, opts, w)
+    assert count == 64 * 59
+
+
+def test_dilation_only_backward_is_rejected(oracle_lib):
     sc, cam = scenegen.fd_subcase(2004)
-    opts = scenegen.default_options(mip=2, mip_sigma2_px=1.0)
+    opts = scenegen.default_options(mip=3)
     dl = np.ones((3, cam["height"], cam["width"]))
     with pytest.raises(ValueError):
         oracle.backward(sc, cam, opts, dl)
