@@ -11,7 +11,8 @@ Workloads (synthetic, seeded; see scenegen/scenes.py):
   c2            3M Gaussians, 4 stereo pairs (8 views, 2064x2208 per eye x
                 {0.5,1,2} per pair), MIP on; a step renders all 8 views in one
                 graph replay.  Metric: views/s (8 single-view renders reported too).
-                --mip exact renders the same frame with the exact per-ray MIP.
+                --mip exact renders the same frame with the exact per-ray MIP
+                (and, for c3, trains through it).
   --divergence gs  c1 with the linearised divergence of 3DGS (Sec. 3.1) in the same
                 pipeline: the same-model speed comparison of GS and RayGS.
   c3            1M Gaussians, 4 views at 1600x1060; a step is forward + L1 loss
@@ -67,7 +68,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--mip", default="approx", choices=["approx", "exact"],
-                    help="c2: the approximate MIP of eq. 17 (the paper's renderer) or the exact per-ray MIP")
+                    help="c2: the approximate MIP of eq. 17 (the paper's renderer) or the exact per-ray MIP; "
+                         "c3: exact turns the exact per-ray MIP on (the workload has none)")
     ap.add_argument("--divergence", default="ray", choices=["ray", "gs"],
                     help="c1: the ray-based divergence (the paper's renderer) or the linearised one of 3DGS")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of HIP-graph replays")
@@ -294,6 +296,8 @@ def bench_c3(args, torch):
 
     w = scenegen.make_workload("c3")
     sc, cams, opts = w["scene"], w["cameras"], dict(w["options"], **tile_opts(args))
+    if args.mip == "exact":
+        opts["mip"] = 2
     n = int(sc["opacity_logits"].shape[0])
     g = to_dev(sc, torch)
     targets = [torch.from_numpy(t).cuda() for t in w["targets"]]
@@ -341,7 +345,8 @@ def bench_c3(args, torch):
         "metric": METRIC, "value": bwd / steps / len(cams), "unit": "backward ms/view", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "c3: 1M Gaussians (SH3), 4 views 1600x1060, forward + L1 + backward",
+        "config": {"workload": "c3: 1M Gaussians (SH3), 4 views 1600x1060, forward + L1 + backward"
+                   + (" (exact per-ray MIP)" if args.mip == "exact" else ""),
                    "instance_capacity": capacity},
         "roofline": roofline_for(dom, bstages[dom]),
         "stages_ms": stages,

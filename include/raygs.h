@@ -97,7 +97,7 @@ typedef struct {
     int32_t mip;           /* 0 = none (default); 1 = approximate MIP of Sec. 5, eq. 17; 2 = exact MIP of
                               Sec. 5 / App. B: per ray, Sigma + sigma_x^2 tau(x)^2 I with sigma_x^2 the
                               pixel's area at unit distance along the ray, opacity times
-                              sqrt(|Sigma| x.Sigma^-1 x / (|Sigma^_x| x.Sigma^_x^-1 x)); forward only;
+                              sqrt(|Sigma| x.Sigma^-1 x / (|Sigma^_x| x.Sigma^_x^-1 x));
                               3 = the widening of eq. 17 without its opacity modulation (the dilation-only
                               ablation of Sec. 6.2); forward only */
     double mip_sigma2_px;  /* MIP pixel variance in px^2 at the principal point (Sec. 6 uses 0.1); >= 0 */
@@ -181,8 +181,9 @@ rgs_status rgs_render_status(rgs_context *ctx, const rgs_workspace *ws, void *st
  * `ws` (which must carry RGS_WS_BACKWARD) with the same g, cams, opts and
  * outs.  Walks each pixel's list back from n_contrib starting at final_T.
  * Gradients are added into `grads`.  With opts->mip = 1 they also flow
- * through the MIP widening and opacity modulation (eq. 17); opts->mip = 2
- * or 3 returns RGS_EUNSUPPORTED.  With RGS_DIVERGENCE_GS they flow through
+ * through the MIP widening and opacity modulation (eq. 17), with opts->mip
+ * = 2 through the per-ray widening and modulation of the exact MIP; opts->mip
+ * = 3 returns RGS_EUNSUPPORTED.  With RGS_DIVERGENCE_GS they flow through
  * pi(mu), the projection's Jacobian J(mu) and Sigma_pi = J Sigma J^T.
  * Uses float atomics: results are order-nondeterministic in the last bits. */
 rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
@@ -215,7 +216,7 @@ rgs_status rgs_autotune(rgs_context *ctx, const rgs_gaussians *g, const rgs_came
 
 /* As rgs_autotune for a training step: each timed step is a render followed
  * by rgs_render_backward with the upstream gradients dL_drgb[v] (device
- * [3][H][W] per view); `ws` must carry RGS_WS_BACKWARD and opts->mip be 0 or 1.
+ * [3][H][W] per view); `ws` must carry RGS_WS_BACKWARD and opts->mip be 0, 1 or 2.
  * Every backward pass adds into `grads`, so pass scratch buffers.  *best_ms
  * is the mean forward + backward milliseconds of the chosen shape. */
 rgs_status rgs_autotune_training(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
@@ -244,7 +245,7 @@ typedef struct {
     size_t inst_ids;       /* uint32 per instance: Gaussian-view id (low 28 bits) sorted by (tile, depth, id);
                               the top 4 bits flag the tile's row bands that meet the support */
     size_t tile_ranges;    /* uint32[2] per global tile: [start, end) into the instance arrays */
-    size_t record_grads;   /* float[16] per Gaussian-view (RGS_WS_BACKWARD only, else 0) */
+    size_t record_grads;   /* float[16] per Gaussian-view (float[32] with mip = 2; RGS_WS_BACKWARD only, else 0) */
     size_t total_bytes;    /* what rgs_workspace_size reports */
     int64_t n_records;     /* n * n_views */
     int64_t capacity;      /* instances */

@@ -49,7 +49,7 @@ struct rgs_context {
     std::vector<FrameEvents> pool;
     double stage_ms[kNumStages] = {0};
     int64_t frames = 0;
-    int grid_fwd[64] = {0}, grid_fwd_exact[64] = {0}, grid_bwd[64] = {0};
+    int grid_fwd[64] = {0}, grid_fwd_exact[64] = {0}, grid_bwd[64] = {0}, grid_bwd_exact[64] = {0};
     unsigned long long *view_stamps = nullptr;  // rgs_set_view_clocks (caller-owned device memory)
     int view_stamps_views = 0;
     std::map<std::string, TileShape> tune_cache;  // autotuned tile shapes by configuration class
@@ -247,7 +247,7 @@ rgs_status compute_layout(rgs_context *ctx, int64_t n, const rgs_camera *cams, i
     L.tile_order = take((size_t)tiles * 2 * 4);  // work items: up to two per tile
     L.row_owner = take((size_t)capacity * 4);
     L.item_clock = take((size_t)tiles * 2 * 8);  // per work item, for per-view completion clocks
-    L.record_grads = (flags & RGS_WS_BACKWARD) ? take(NV * kGradFloats * sizeof(float)) : 0;
+    L.record_grads = (flags & RGS_WS_BACKWARD) ? take(NV * grad_floats(opts->mip) * sizeof(float)) : 0;
     L.total = off;
     return RGS_OK;
 }
@@ -369,7 +369,8 @@ void ensure_grids(rgs_context *ctx, TileShape s)
     const int k = shape_index(s);
     if (!ctx->grid_fwd[k]) ctx->grid_fwd[k] = blend_grid(s, false, ctx->num_cus);
     if (!ctx->grid_fwd_exact[k]) ctx->grid_fwd_exact[k] = blend_grid(s, true, ctx->num_cus);
-    if (!ctx->grid_bwd[k]) ctx->grid_bwd[k] = blend_backward_grid(s, ctx->num_cus);
+    if (!ctx->grid_bwd[k]) ctx->grid_bwd[k] = blend_backward_grid(s, false, ctx->num_cus);
+    if (!ctx->grid_bwd_exact[k]) ctx->grid_bwd_exact[k] = blend_backward_grid(s, true, ctx->num_cus);
 }
 
 // Enqueue the forward pipeline after the header copy.
@@ -598,8 +599,7 @@ rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const r
     for (int v = 0; v < n_views; ++v)
         if (!dL_drgb[v]) return fail(ctx, RGS_EINVAL, "dL_drgb[%d] is NULL", v);
     if (!grads) return fail(ctx, RGS_EINVAL, "grads is NULL");
-    if (opts->mip == 2 || opts->mip == 3)
-        return fail(ctx, RGS_EUNSUPPORTED, "mip = %d (exact MIP, dilation only) is not differentiated", opts->mip);
+    if (opts->mip == 3) return fail(ctx, RGS_EUNSUPPORTED, "mip = 3 (dilation only) is not differentiated");
     if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh))
         return fail(ctx, RGS_EINVAL, "NULL gradient pointer");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -614,14 +614,16 @@ rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const r
     uint32_t *sched = at<uint32_t>(ws->ptr, L.sched);
     float *rgrads = at<float>(ws->ptr, L.record_grads);
     Timer tm(ctx, s, true, ST_BLEND_BWD);
-    RGS_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(rgrads), 0u, L.nv_records * kGradFloats, s));
+    RGS_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(rgrads), 0u, L.nv_records * grad_floats(opts->mip), s));
     uint32_t *bwd_heads = sched + sched_backward_heads();
     RGS_HIP(ctx, launch_fill_u32(bwd_heads, 0u, (int64_t)kQueues * kQueueStride, s));
     RGS_HIP(ctx, launch_blend_backward(sh, at<uint2>(ws->ptr, L.ranges), at<uint32_t>(ws->ptr, L.tile_order),
                                        sched + sched_item_count(),
                                        at<uint32_t>(ws->ptr, L.inst_ids_a), at<float4>(ws->ptr, L.records),
                                        at<DevView>(ws->ptr, L.views), n_views, L.total_tiles, L.nv_records, dopt,
-                                       rgrads, bwd_heads, ctx->grid_bwd[shape_index(sh)], s));
+                                       rgrads, bwd_heads,
+                                       opts->mip == 2 ? ctx->grid_bwd_exact[shape_index(sh)] : ctx->grid_bwd[shape_index(sh)],
+                                       s));
     tm.mark(ST_BLEND_BWD);
     RGS_HIP(ctx, launch_preprocess_backward(*g, at<DevView>(ws->ptr, L.views), n_views, dopt,
                                             at<uint32_t>(ws->ptr, L.tile_counts), rgrads, *grads, s));

@@ -118,6 +118,52 @@ __device__ void gs_chain(const double mu[3], const double Rp[9], const double s[
     }
 }
 
+// Chain of the exact MIP record (mip = 2; written by write_exact_mip_record):
+// from the gradient of its values gr (kGradFloatsExactMip layout) to dL/dmu,
+// dL/dR_p, dL/ds (added) and dL/do (returned).  With lam = s_max^2:
+//   P0_k = R_p[0][k] / fx, P1_k = R_p[1][k] / fy,
+//   Q0_k = (R_p[1][k] mu_z - mu_y R_p[2][k]) / (fx s_max),
+//   Q1_k = (mu_x R_p[2][k] - R_p[0][k] mu_z) / (fy s_max),
+//   rho_k = (R_p^T mu)_k / mu_z, s'^2_k = s_k^2 / lam, e = sigma^2 mu_z^2 / lam,
+//   log2o = log2 o + sum_k log2 s'^2_k / 2, centre = (fx mu_x / mu_z + cx, fy mu_y / mu_z + cy).
+__device__ double exact_mip_chain(const double mu[3], const double Rp[9], const double s[3], double o,
+                                  const DevView &V, double sig2, const float *gr, double dmu[3], double dRp[9],
+                                  double ds[3])
+{
+    constexpr double kLn2 = 0.69314718055994531;
+    int m = 0;
+    for (int k = 1; k < 3; ++k)
+        if (s[k] > s[m]) m = k;
+    const double smax = s[m], ilam = 1.0 / (smax * smax), iz = 1.0 / mu[2];
+    const double ax = 1.0 / (V.fx * smax), ay = 1.0 / (V.fy * smax);
+    const double gcx = gr[0], gcy = gr[1], ge = gr[20], glog2o = gr[21];
+    double dsmax = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double gP0 = gr[2 + k], gP1 = gr[5 + k], gQ0 = gr[8 + k], gQ1 = gr[11 + k], grho = gr[14 + k];
+        const double s2 = s[k] * s[k] * ilam;
+        const double gs2 = gr[17 + k] + glog2o * 0.5 / (s2 * kLn2);
+        const double Q0 = (Rp[3 + k] * mu[2] - mu[1] * Rp[6 + k]) * ax;
+        const double Q1 = (mu[0] * Rp[6 + k] - Rp[k] * mu[2]) * ay;
+        const double rho = (Rp[k] * mu[0] + Rp[3 + k] * mu[1] + Rp[6 + k] * mu[2]) * iz;
+        dRp[k] += gP0 / V.fx - gQ1 * mu[2] * ay + grho * mu[0] * iz;
+        dRp[3 + k] += gP1 / V.fy + gQ0 * mu[2] * ax + grho * mu[1] * iz;
+        dRp[6 + k] += -gQ0 * mu[1] * ax + gQ1 * mu[0] * ay + grho * mu[2] * iz;
+        dmu[0] += gQ1 * Rp[6 + k] * ay + grho * Rp[k] * iz;
+        dmu[1] += -gQ0 * Rp[6 + k] * ax + grho * Rp[3 + k] * iz;
+        dmu[2] += gQ0 * Rp[3 + k] * ax - gQ1 * Rp[k] * ay + grho * (Rp[6 + k] - rho) * iz;
+        dsmax -= (gQ0 * Q0 + gQ1 * Q1 + gs2 * 2.0 * s2) / smax;
+        ds[k] += gs2 * 2.0 * s[k] * ilam;
+    }
+    const double e = sig2 * mu[2] * mu[2] * ilam;
+    dmu[2] += ge * 2.0 * e * iz;
+    dsmax -= ge * 2.0 * e / smax;
+    ds[m] += dsmax;
+    dmu[0] += gcx * V.fx * iz;
+    dmu[1] += gcy * V.fy * iz;
+    dmu[2] -= (gcx * V.fx * mu[0] + gcy * V.fy * mu[1]) * iz * iz;
+    return glog2o / (o * kLn2);
+}
+
 // Geometry and opacity (the colour part is k_colour_bwd).
 __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const float *__restrict__ means, const float *__restrict__ log_scales, const float *__restrict__ quats,
@@ -153,7 +199,26 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         const size_t idx = (size_t)v * n + i;
         if (tile_counts[idx] == 0) continue;
         const DevView &V = views[v];
-        const float *gr = record_grads + idx * kGradFloats;
+        const float *gr = record_grads + idx * grad_floats(opt.mip);
+        if (opt.mip == 2) {
+            const double mu[3] = {V.w2c[0] * m[0] + V.w2c[1] * m[1] + V.w2c[2] * m[2] + V.w2c[3],
+                                  V.w2c[4] * m[0] + V.w2c[5] * m[1] + V.w2c[6] * m[2] + V.w2c[7],
+                                  V.w2c[8] * m[0] + V.w2c[9] * m[1] + V.w2c[10] * m[2] + V.w2c[11]};
+            double Rp[9];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c)
+                    Rp[3 * r + c] = V.w2c[4 * r] * R[c] + V.w2c[4 * r + 1] * R[3 + c] + V.w2c[4 * r + 2] * R[6 + c];
+            double dmu[3] = {0, 0, 0}, dRp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, ds[3] = {0, 0, 0};
+            const double go = exact_mip_chain(mu, Rp, s, o, V, opt.mip_sigma2_px / (V.fx * V.fy), gr, dmu, dRp, ds);
+            const double *W = V.w2c;
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c)
+                    dR[3 * r + c] += W[r] * dRp[c] + W[4 + r] * dRp[3 + c] + W[8 + r] * dRp[6 + c];
+            for (int c = 0; c < 3; ++c) dm[c] += W[c] * dmu[0] + W[4 + c] * dmu[1] + W[8 + c] * dmu[2];
+            for (int k = 0; k < 3; ++k) dl[k] += ds[k] * s[k];
+            da += go * o * (1.0 - o);
+            continue;
+        }
         const double gu0 = gr[0], gv0 = gr[1], gM00 = gr[2], gM01 = gr[3], gM11 = gr[4], ggx = gr[5], ggy = gr[6];
         const double gk0 = gr[7], gic2 = gr[8], go = gr[9];
         const double *W = V.w2c;
@@ -290,8 +355,9 @@ template <int DEG>
 __global__ __launch_bounds__(256) void k_colour_bwd(const float *__restrict__ means, const float *__restrict__ sh,
                                                     int n, const DevView *__restrict__ views, int n_views,
                                                     const uint32_t *__restrict__ tile_counts,
-                                                    const float *__restrict__ record_grads,
-                                                    float *__restrict__ g_means, float *__restrict__ g_sh)
+                                                    const float *__restrict__ record_grads, int grad_stride,
+                                                    int rgb_offset, float *__restrict__ g_means,
+                                                    float *__restrict__ g_sh)
 {
     constexpr int NK = (DEG + 1) * (DEG + 1);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -311,7 +377,7 @@ __global__ __launch_bounds__(256) void k_colour_bwd(const float *__restrict__ me
         const size_t idx = (size_t)v * n + i;
         if (tile_counts[idx] == 0) continue;
         const DevView &V = views[v];
-        const float *gr = record_grads + idx * kGradFloats;
+        const float *gr = record_grads + idx * grad_stride;
         float dir[3];
         double dist;
         view_dir(m, V.centre, dir, &dist);
@@ -321,7 +387,7 @@ __global__ __launch_bounds__(256) void k_colour_bwd(const float *__restrict__ me
         // channels clamped at zero in the forward pass no gradient
         float gcol[3];
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) gcol[ch] = col[ch] > 0.0f ? gr[10 + ch] : 0.0f;
+        for (int ch = 0; ch < 3; ++ch) gcol[ch] = col[ch] > 0.0f ? gr[rgb_offset + ch] : 0.0f;
         float wk[NK];
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
@@ -358,7 +424,7 @@ hipError_t launch_preprocess_backward(const rgs_gaussians &g, const DevView *vie
     // after k_preprocess_bwd on the same stream: both add into gr.means
 #define RGS_BWD(D)                                                                                                  \
     k_colour_bwd<D><<<grid, block, 0, stream>>>(g.means, g.sh, n, views, n_views, tile_counts, record_grads,        \
-                                                gr.means, gr.sh)
+                                                grad_floats(opt.mip), opt.mip == 2 ? 22 : 10, gr.means, gr.sh)
     switch (g.sh_degree) {
     case 0: RGS_BWD(0); break;
     case 1: RGS_BWD(1); break;

@@ -226,8 +226,10 @@ struct XRec {
     uint32_t rows;
 };
 
+// Per-fragment values of the exact MIP weight (the backward kernel uses
+// them all; the forward only L).
 struct XFrag {
-    float L;
+    float dx, dy, r0, r1, r2, w0, w1, w2, q0, q1, q2, rB, t, S0, S1, S2, p12, p02, p01, den, num, rd, L;
 };
 
 struct ExactMipModel {
@@ -296,7 +298,8 @@ struct ExactMipModel {
         const float A = __builtin_fmaf(R.iz_, r2, __builtin_fmaf(R.iy_, r1, R.ix_ * r0));
         const float q0 = r0 * r0, q1 = r1 * r1, q2 = r2 * r2;
         const float B = __builtin_fmaf(R.isz, q2, __builtin_fmaf(R.isy, q1, R.isx * q0));
-        const float t = A * __builtin_amdgcn_rcpf(B);
+        const float rB = __builtin_amdgcn_rcpf(B);
+        const float t = A * rB;
         const float a = (R.e * inv_norm) * (t * t);
         const float S0 = R.s0 + a, S1 = R.s1 + a, S2 = R.s2 + a;
         const float p12 = S1 * S2, p02 = S0 * S2, p01 = S0 * S1;
@@ -305,6 +308,28 @@ struct ExactMipModel {
         const float th = __builtin_fmaf(R.rz * r2, p01, __builtin_fmaf(R.ry * r1, p02, (R.rx * r0) * p12));
         const float rd = __builtin_amdgcn_rcpf(den);
         f.L = __builtin_fmaf(-kHalfLog2e * num, rd, __builtin_fmaf(0.5f, __builtin_amdgcn_logf(B * rd), R.log2o));
+        f.dx = dx;
+        f.dy = dy;
+        f.r0 = r0;
+        f.r1 = r1;
+        f.r2 = r2;
+        f.w0 = w0;
+        f.w1 = w1;
+        f.w2 = w2;
+        f.q0 = q0;
+        f.q1 = q1;
+        f.q2 = q2;
+        f.rB = rB;
+        f.t = t;
+        f.S0 = S0;
+        f.S1 = S1;
+        f.S2 = S2;
+        f.p12 = p12;
+        f.p02 = p02;
+        f.p01 = p01;
+        f.den = den;
+        f.num = num;
+        f.rd = rd;
         return (th > 0.0f) & (f.L >= log2_pmin);
     }
     __device__ static float omega(const Rec &, F &f) { return __builtin_amdgcn_exp2f(f.L); }
@@ -634,6 +659,185 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
     }
 }
 
+// Backward compositing for the exact MIP weight (mip = 2).  The walk is
+// that of k_blend_bwd; per fragment, with g = dL/d ln omega (zero for lanes
+// that do not hit or whose alpha is clamped) and ln omega =
+// ln2 log2o + (ln B - ln den - num / den) / 2 (see ExactMipModel):
+//   d/dden = g (num - den) / (2 den^2), d/dnum = -g / (2 den), d/dB = g / (2 B)
+//   plus the widening a = E t^2 (E = e / |xbar|, t = A / B), which reaches
+//   every S_k = s'_k^2 + a; den = sum q_k prod_{j != k} S_j with q = r^2,
+//   num = sum S_k w_k^2, r = rho + P0 dx + P1 dy, w = Q0 dx + Q1 dy,
+//   A = sum rho_k r_k / s'_k^2, B = sum r_k^2 / s'_k^2.
+// The record gradient (kGradFloatsExactMip floats) is
+//   [0, 1] the projected centre, [2..4] P0, [5..7] P1, [8..10] Q0,
+//   [11..13] Q1, [14..16] rho, [17..19] s'^2, [20] e, [21] log2o,
+//   [22..24] colour.
+template <int TW, int TH>
+__global__ __launch_bounds__(256) void k_blend_bwd_exact(const uint2 *__restrict__ ranges,
+                                                         const uint32_t *__restrict__ work_order,
+                                                         const uint32_t *__restrict__ n_items_p,
+                                                         const uint32_t *__restrict__ inst_ids,
+                                                         const float4 *__restrict__ records,
+                                                         const DevView *__restrict__ views, BlendParams P,
+                                                         float *__restrict__ record_grads,
+                                                         unsigned int *__restrict__ queue)
+{
+    using M = ExactMipModel;
+    constexpr int LX = TW, LY = 64 / TW, PPL = TH / LY;
+    constexpr float kLn2 = 0.69314718055994531f;
+    __shared__ float4 s_rec[4][64][M::kStaged];
+    __shared__ uint32_t s_id[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lx = lane % LX, ly = lane / LX;
+    const int nq = min((int)gridDim.x, kQueues), q = (int)blockIdx.x % nq;
+    unsigned int *const head = queue + q * kQueueStride;
+    const int64_t n_items = *n_items_p;
+    for (;;) {
+        const int64_t slot = q + (int64_t)nq * wave_fetch_add(head, 1u);
+        if (slot >= n_items) break;
+        const uint32_t item = work_order[slot];
+        const int tile = (int)(item >> 2);
+        const int part = (int)(item & 3u);
+        const int k_lo = part == 2 ? PPL / 2 : 0, k_hi = part == 1 ? PPL / 2 : PPL;
+        const DevView &V = views[find_view(views, P.n_views, tile)];
+        const int local = tile - V.tile_base;
+        const int tx = local % V.tiles_x, ty = local / V.tiles_x;
+        const int px = tx * TW + lx;
+        const int ox = (tx * TW) & ~31, oy = (ty * TH) & ~31;
+        const float x0 = (float)ox, y0 = (float)oy;
+        const float pxr = (float)(px - ox) + 0.5f;
+        const size_t plane = (size_t)V.width * V.height;
+        float T[PPL], S[PPL], g0[PPL], g1[PPL], g2[PPL], pyr[PPL], aux[PPL];
+        int last[PPL];
+        int maxlast = 0;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            const int py = ty * TH + ly + k * LY;
+            pyr[k] = (float)(py - oy) + 0.5f;
+            aux[k] = M::pixel_aux(V, px, py);
+            T[k] = 1.0f;
+            S[k] = 0.0f;
+            g0[k] = g1[k] = g2[k] = 0.0f;
+            last[k] = 0;
+            if (k >= k_lo && k < k_hi && px < V.width && py < V.height) {
+                const size_t p = (size_t)py * V.width + px;
+                T[k] = V.final_T[p];
+                last[k] = V.n_contrib[p];
+                g0[k] = V.dL_drgb[p];
+                g1[k] = V.dL_drgb[plane + p];
+                g2[k] = V.dL_drgb[2 * plane + p];
+                S[k] = T[k] * (P.bg0 * g0[k] + P.bg1 * g1[k] + P.bg2 * g2[k]);
+                maxlast = max(maxlast, last[k]);
+            }
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, d, 64));
+        const uint2 rg = ranges[tile];
+        maxlast = min(maxlast, (int)(rg.y - rg.x));
+        for (int hi = maxlast; hi > 0; hi -= 64) {
+            const int lo = hi > 64 ? hi - 64 : 0;
+            const int nb = hi - lo;
+            if (lane < nb) {
+                const uint32_t v = inst_ids[rg.x + lo + lane];
+                const uint32_t id = v & kIdMask;
+                s_id[wave][lane] = id < P.n_records ? id : 0xffffffffu;
+                float4 r[M::kRaw];
+                M::fetch(r, records, v, P.n_records, PPL <= 4);
+                M::stage(s_rec[wave][lane], r, x0, y0, P.log2_pmin);
+            }
+            lds_wave_sync();
+            for (int jj = nb - 1; jj >= 0; --jj) {
+                const int j = lo + jj;
+                const XRec R = M::load(s_rec[wave][jj]);
+                const RowSpan span = row_span(R.rows, ty * TH);
+                const uint32_t bands = __builtin_amdgcn_readfirstlane(R.rows);
+                float acc[25];
+#pragma unroll
+                for (int c = 0; c < 25; ++c) acc[c] = 0.0f;
+                bool wave_hit = false;
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) {
+                    if (k < k_lo || k >= k_hi || !band_open<PPL, LY>(bands, span, k)) continue;
+                    XFrag f;
+                    const bool hit = (j < last[k]) & M::test(R, pxr, pyr[k], aux[k], P.log2_pmin, f);
+                    if (__ballot(hit) == 0) continue;
+                    wave_hit = true;
+                    const float w = hit ? M::omega(R, f) : 0.0f;
+                    const float a = fminf(w, P.alpha_max);
+                    const float rom = __builtin_amdgcn_rcpf(1.0f - a);
+                    const float Tb = T[k] * rom;
+                    const float rgd = R.r * g0[k] + R.g * g1[k] + R.b * g2[k];
+                    const float ta = Tb * a;
+                    acc[22] += ta * g0[k];
+                    acc[23] += ta * g1[k];
+                    acc[24] += ta * g2[k];
+                    const float dL_da = Tb * rgd - S[k] * rom;
+                    S[k] += ta * rgd;
+                    T[k] = Tb;
+                    // g = dL / d ln omega; a clamped alpha passes none
+                    const float g = (hit & (w < P.alpha_max)) ? dL_da * w : 0.0f;
+                    const float rd = hit ? f.rd : 0.0f;
+                    const float rB = hit ? f.rB : 0.0f;
+                    const float gden = 0.5f * g * (f.num - f.den) * (rd * rd);
+                    const float gnum = -0.5f * g * rd;
+                    const float gB0 = 0.5f * g * rB;
+                    const float gS0 = gden * (f.q1 * f.S2 + f.q2 * f.S1) + gnum * (f.w0 * f.w0);
+                    const float gS1 = gden * (f.q0 * f.S2 + f.q2 * f.S0) + gnum * (f.w1 * f.w1);
+                    const float gS2 = gden * (f.q0 * f.S1 + f.q1 * f.S0) + gnum * (f.w2 * f.w2);
+                    const float ga = gS0 + gS1 + gS2;
+                    const float E = R.e * aux[k];
+                    const float gt = ga * 2.0f * E * f.t;
+                    const float gA = gt * rB;
+                    const float gB = gB0 - gt * f.t * rB;
+                    const float gr0 = 2.0f * f.r0 * (gden * f.p12 + gB * R.isx) + gA * R.ix_;
+                    const float gr1 = 2.0f * f.r1 * (gden * f.p02 + gB * R.isy) + gA * R.iy_;
+                    const float gr2 = 2.0f * f.r2 * (gden * f.p01 + gB * R.isz) + gA * R.iz_;
+                    const float gw0 = 2.0f * gnum * f.S0 * f.w0;
+                    const float gw1 = 2.0f * gnum * f.S1 * f.w1;
+                    const float gw2 = 2.0f * gnum * f.S2 * f.w2;
+                    acc[0] -= gr0 * R.P0x + gr1 * R.P0y + gr2 * R.P0z + gw0 * R.Q0x + gw1 * R.Q0y + gw2 * R.Q0z;
+                    acc[1] -= gr0 * R.P1x + gr1 * R.P1y + gr2 * R.P1z + gw0 * R.Q1x + gw1 * R.Q1y + gw2 * R.Q1z;
+                    acc[2] += gr0 * f.dx;
+                    acc[3] += gr1 * f.dx;
+                    acc[4] += gr2 * f.dx;
+                    acc[5] += gr0 * f.dy;
+                    acc[6] += gr1 * f.dy;
+                    acc[7] += gr2 * f.dy;
+                    acc[8] += gw0 * f.dx;
+                    acc[9] += gw1 * f.dx;
+                    acc[10] += gw2 * f.dx;
+                    acc[11] += gw0 * f.dy;
+                    acc[12] += gw1 * f.dy;
+                    acc[13] += gw2 * f.dy;
+                    acc[14] += gr0 + gA * R.isx * f.r0;
+                    acc[15] += gr1 + gA * R.isy * f.r1;
+                    acc[16] += gr2 + gA * R.isz * f.r2;
+                    acc[17] += gS0 - gB * (R.isx * R.isx) * f.q0 - gA * R.rx * (R.isx * R.isx) * f.r0;
+                    acc[18] += gS1 - gB * (R.isy * R.isy) * f.q1 - gA * R.ry * (R.isy * R.isy) * f.r1;
+                    acc[19] += gS2 - gB * (R.isz * R.isz) * f.q2 - gA * R.rz * (R.isz * R.isz) * f.r2;
+                    acc[20] += ga * aux[k] * (f.t * f.t);
+                    acc[21] += g * kLn2;
+                }
+                if (!wave_hit) continue;
+                const uint32_t rid = s_id[wave][jj];
+                const int c = wave_sum16_index(lane);
+                const float lo16[16] = {acc[0], acc[1], acc[2], acc[3], acc[4], acc[5], acc[6], acc[7],
+                                        acc[8], acc[9], acc[10], acc[11], acc[12], acc[13], acc[14], acc[15]};
+                const float s_lo = wave_sum16(lo16, lane);
+                const float hi16[16] = {acc[16], acc[17], acc[18], acc[19], acc[20], acc[21], acc[22], acc[23],
+                                        acc[24], 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                const float s_hi = wave_sum16(hi16, lane);
+                if ((lane & 3) == 0 && rid != 0xffffffffu) {
+                    float *dst = record_grads + (size_t)rid * kGradFloatsExactMip;
+                    atomicAdd(dst + c, s_lo);
+                    if (c < 9) atomicAdd(dst + 16 + c, s_hi);
+                }
+            }
+            lds_wave_sync();
+        }
+    }
+}
+
 template <int TW, int TH>
 int occupancy_grid(const void *kernel, int num_cus)
 {
@@ -697,11 +901,12 @@ int blend_grid(TileShape s, bool exact_mip, int num_cus)
     return num_cus;
 }
 
-int blend_backward_grid(TileShape s, int num_cus)
+int blend_backward_grid(TileShape s, bool exact_mip, int num_cus)
 {
 #define X(W, H)                                                                                                  \
     if (s.w == W && s.h == H)                                                                                    \
-        return occupancy_grid<W, H>(reinterpret_cast<const void *>(&k_blend_bwd<W, H>), num_cus);
+        return exact_mip ? occupancy_grid<W, H>(reinterpret_cast<const void *>(&k_blend_bwd_exact<W, H>), num_cus) \
+                         : occupancy_grid<W, H>(reinterpret_cast<const void *>(&k_blend_bwd<W, H>), num_cus);
     RGS_SHAPES(X)
 #undef X
     return num_cus;
@@ -737,8 +942,12 @@ hipError_t launch_blend_backward(TileShape s, const uint2 *ranges, const uint32_
     const BlendParams P = make_params(opt, n_views, total_tiles, n_records, nullptr);
 #define X(W, H)                                                                                                  \
     if (s.w == W && s.h == H) {                                                                                  \
-        k_blend_bwd<W, H><<<grid, 256, 0, stream>>>(ranges, work_order, n_items, inst_ids, records, views, P,  \
-                                                    record_grads, queue);                                        \
+        if (opt.mip == 2)                                                                                        \
+            k_blend_bwd_exact<W, H><<<grid, 256, 0, stream>>>(ranges, work_order, n_items, inst_ids, records,    \
+                                                              views, P, record_grads, queue);                    \
+        else                                                                                                     \
+            k_blend_bwd<W, H><<<grid, 256, 0, stream>>>(ranges, work_order, n_items, inst_ids, records, views,   \
+                                                        P, record_grads, queue);                                 \
         return hipGetLastError();                                                                                \
     }
     RGS_SHAPES(X)

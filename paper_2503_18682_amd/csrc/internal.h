@@ -56,6 +56,12 @@ inline int record_floats(int mip) { return mip == 2 ? kRecordFloatsExactMip : kR
 // the single off-diagonal parameter) and do = dL / d(prior opacity).
 constexpr int kGradFloats = 16;
 
+// With exact MIP (mip = 2) the record gradient is 32 floats (layout at the
+// exact MIP backward compositing kernel in blend.hip; 25 used).
+constexpr int kGradFloatsExactMip = 32;
+
+__host__ __device__ inline int grad_floats(int mip) { return mip == 2 ? kGradFloatsExactMip : kGradFloats; }
+
 constexpr int kMaxViews = 256;
 
 struct TileShape {
@@ -166,7 +172,7 @@ hipError_t launch_blend_backward(TileShape shape, const uint2 *ranges, const uin
                                  const DevView *views, int n_views, int64_t total_tiles, int64_t n_records,
                                  const DevOptions &opt, float *record_grads, unsigned int *queue, int grid,
                                  hipStream_t stream);
-int blend_backward_grid(TileShape shape, int num_cus);
+int blend_backward_grid(TileShape shape, bool exact_mip, int num_cus);
 
 hipError_t launch_preprocess_backward(const rgs_gaussians &g, const DevView *views, int n_views,
                                       const DevOptions &opt, const uint32_t *tile_counts, const float *record_grads,

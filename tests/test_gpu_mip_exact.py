@@ -151,15 +151,54 @@ def test_exact_mip_c2_full_size_sampled_pixels(r):
     br.close()
 
 
-def test_exact_mip_backward_is_unsupported(r):
+def test_exact_mip_gradients_match_oracle(r):
+    """The backward of the exact MIP weight (per-ray widening and modulation)
+    against the oracle's analytic gradient, which central differences pin:
+    the finite-difference subcase at a 4 px^2 footprint, and two views with
+    sparse pixels at 0.5 px^2."""
+    from paper_2503_18682_amd import _lib
+    from test_gpu_grad import _compare
+
+    scene, cam = scenegen.fd_subcase(seed=2008)
+    opts = scenegen.default_options(mip=2, mip_sigma2_px=4.0)
+    say("case exact MIP grad fd-subcase 64 Gaussians 32x32")
+    g = to_dev(scene)
+    outs, (buf, ws) = r.render(g, [cam], opts, flags=_lib.RGS_WS_BACKWARD, keep_workspace=True)
+    img = outs[0]["rgb"].cpu().numpy()
+    target = np.random.default_rng(14).uniform(0, 1, img.shape)
+    dl = (np.sign(img - target) / img.size).astype(np.float32)
+    grads = r.backward(g, [cam], outs, [torch.from_numpy(dl).cuda()], ws, opts)
+    _compare(grads, oracle.backward(scene, cam, opts, dl.astype(np.float64)), "exact MIP fd-subcase")
+
+    sc = scenegen.tiny_scene(54, 20000, sh_degree=2, half_extent=1.5, log_scale_mean=-4.0, log_scale_std=0.6)
+    cams = [scenegen.pinhole(scenegen.look_at((0, 0.5, -4)), 320, 212, 50),
+            scenegen.pinhole(scenegen.look_at((2.5, 0.0, -3)), 160, 240, 60)]
+    opts = scenegen.default_options(mip=2, mip_sigma2_px=0.5)
+    say("case exact MIP grad 2 views, 20000 Gaussians, sparse pixels")
+    g = to_dev(sc)
+    outs, (buf, ws) = r.render(g, cams, opts, flags=_lib.RGS_WS_BACKWARD, keep_workspace=True)
+    rng = np.random.default_rng(15)
+    dls, ref = [], {k: 0.0 for k in ("means", "log_scales", "quats", "opacity_logits", "sh")}
+    for cam in cams:
+        H, W = cam["height"], cam["width"]
+        dl = np.zeros((3, H, W), np.float32)
+        idx = rng.choice(H * W, 400, replace=False)
+        dl.reshape(3, -1)[:, idx] = rng.normal(0, 1, (3, 400))
+        dls.append(torch.from_numpy(dl).cuda())
+        o = oracle.backward(sc, cam, opts, dl.astype(np.float64))
+        ref = {k: ref[k] + o[k] for k in ref}
+    grads = r.backward(g, cams, outs, dls, ws, opts)
+    _compare(grads, ref, "exact MIP 2 views", rel=2e-3)
+
+
+def test_dilation_only_backward_is_unsupported(r):
     from paper_2503_18682_amd import _lib
     from paper_2503_18682_amd import renderer as R
 
     sc = scenegen.tiny_scene(39, 200, sh_degree=1)
     cam = scenegen.pinhole(scenegen.look_at((0, 0, -3)), 48, 40, 60)
-    opts = scenegen.default_options(mip=2, mip_sigma2_px=0.1)
     g = to_dev(sc, requires_grad=True)
-    img = R.render(r, g, [cam], opts)[0]
+    img = R.render(r, g, [cam], scenegen.default_options(mip=3))[0]
     with pytest.raises(_lib.RayGSError) as ei:
         img.sum().backward()
     assert ei.value.status == _lib.RGS_EUNSUPPORTED
