@@ -163,9 +163,11 @@ def _mk(mus, scales, opac, rgbs, quats=None):
                 sh=sh.astype(np.float32), sh_degree=0)
 
 
-def test_edge_cases(r):
+@pytest.mark.parametrize("mode", [dict(), dict(mip=1), dict(mip=2, mip_sigma2_px=1.0), dict(mip=3), dict(divergence=1)],
+                         ids=["ray", "mip", "exact_mip", "dilation", "gs"])
+def test_edge_cases(r, mode):
     cam = scenegen.pinhole(np.concatenate([np.eye(3), np.zeros((3, 1))], 1), 48, 40, 90)
-    opts = scenegen.default_options(background=(0.1, 0.2, 0.3))
+    opts = scenegen.default_options(background=(0.1, 0.2, 0.3), **mode)
     cases = {
         "empty": _mk(np.zeros((0, 3)), np.zeros((0, 3)) + 1, np.zeros(0) + 0.5, np.zeros((0, 3))),
         "single": _mk([[0.1, 0.05, 2.0]], [[0.1, 0.2, 0.05]], [0.8], [[0.9, 0.3, 0.1]]),
@@ -181,7 +183,7 @@ def test_edge_cases(r):
     bad["sh"][0, 1, 2] = np.inf
     cases["non_finite_and_zero_quat"] = bad
     for name, sc in cases.items():
-        say(f"case edge/{name}")
+        say(f"case edge/{name} {mode}")
         outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
         assert ok
         ref = oracle.render(sc, cam, opts)
