@@ -356,6 +356,7 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
     constexpr int LX = TW, LY = 64 / TW, PPL = TH / LY;
     static_assert(64 % TW == 0 && TH % LY == 0, "tile shape");
     __shared__ float4 s_rec[4][64][M::kStaged];
+    const uint32_t amax_bits = __float_as_uint(P.alpha_max);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lx = lane % LX, ly = lane / LX;
     const int nq = min((int)gridDim.x, kQueues), q = (int)blockIdx.x % nq;
@@ -425,11 +426,13 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
                     typename M::F f;
                     const bool hit = M::test(R, pxr, pyr[k], aux[k], P.log2_pmin, f);
                     if (__ballot(hit) == 0) continue;
-                    const float a = fminf(M::omega(R, f), P.alpha_max);
+                    // omega >= 0 and alpha_max > 0: the float minimum is the
+                    // minimum of the bit patterns
+                    const float a = __uint_as_float(min(__float_as_uint(M::omega(R, f)), amax_bits));
                     const float ta = T[k] * a;
                     const float Tn = T[k] - ta;
                     const bool stop = hit & (Tn < P.t_eps);
-                    const bool take = hit & !(Tn < P.t_eps);
+                    const bool take = hit & !stop;
                     const float wt = take ? ta : 0.0f;
                     C0[k] = __builtin_fmaf(wt, R.r, C0[k]);
                     C1[k] = __builtin_fmaf(wt, R.g, C1[k]);
