@@ -295,6 +295,16 @@ const char *rgs_stage_names(void);
 rgs_status rgs_downsample_box(rgs_context *ctx, const float *src, int32_t width, int32_t height, int32_t factor,
                               int32_t planes, float *dst, void *stream);
 
+/* Measured ceilings of this device, for roofline context beside the published
+ * peaks: *fma_tflops = FP32 FMA rate of register-resident chains on every
+ * compute unit (non-packed instructions, as every kernel here is built);
+ * *exp_tops = rate of the hardware exp2 (tera-operations/s); *copy_gbs =
+ * device-to-device copy bandwidth counting bytes read plus written.  Not for
+ * use during a frame: it allocates (about 1 GiB, freed before returning) and
+ * synchronises `stream`.  RGS_EINVAL for NULL outputs, RGS_EHIP on runtime
+ * failure. */
+rgs_status rgs_calibrate(rgs_context *ctx, void *stream, double *fma_tflops, double *exp_tops, double *copy_gbs);
+
 #ifdef __cplusplus
 }
 #endif

@@ -95,6 +95,7 @@ EXPORTS = {
     "rgs_wall_clock_hz": (C.c_double, [C.c_void_p]),
     "rgs_downsample_box": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                      C.c_void_p, C.c_void_p]),
+    "rgs_calibrate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "rgs_set_stage_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "rgs_stage_times": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int64)]),
     "rgs_stage_names": (C.c_char_p, []),

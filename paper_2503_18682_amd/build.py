@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libraygs.so")
-SOURCES = ["preprocess.hip", "sort.hip", "blend.hip", "backward.hip", "aa.hip", "api.hip"]
+SOURCES = ["preprocess.hip", "sort.hip", "blend.hip", "backward.hip", "aa.hip", "calib.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("RAYGS_ARCH", "gfx950")

@@ -860,6 +860,26 @@ rgs_status rgs_downsample_box(rgs_context *ctx, const float *src, int32_t width,
     return RGS_OK;
 }
 
+}  // extern "C"
+
+namespace rgs {
+// calib.hip: FP32 FMA TFLOP/s, exp2 Top/s and device copy GB/s (read + write)
+// measured on `stream` (allocates and frees its own buffers, synchronises).
+hipError_t measure_ceilings(int num_cus, hipStream_t stream, double *fma_tflops, double *exp_tops, double *copy_gbs);
+}  // namespace rgs
+
+extern "C" {
+
+rgs_status rgs_calibrate(rgs_context *ctx, void *stream, double *fma_tflops, double *exp_tops, double *copy_gbs)
+{
+    if (!ctx) return RGS_EINVAL;
+    ctx->err.clear();
+    if (!fma_tflops || !exp_tops || !copy_gbs) return fail(ctx, RGS_EINVAL, "NULL output");
+    RGS_HIP(ctx, hipSetDevice(ctx->device));
+    RGS_HIP(ctx, measure_ceilings(ctx->num_cus, static_cast<hipStream_t>(stream), fma_tflops, exp_tops, copy_gbs));
+    return RGS_OK;
+}
+
 rgs_status rgs_set_stage_timing(rgs_context *ctx, int32_t enable)
 {
     if (!ctx) return RGS_EINVAL;

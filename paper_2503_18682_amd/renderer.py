@@ -265,6 +265,13 @@ class Renderer:
         self.lib.rgs_stage_times(self.ctx, ms, len(names), C.byref(frames))
         return dict(zip(names, list(ms))), frames.value
 
+    def calibrate(self) -> dict:
+        """Measured FP32 FMA TFLOP/s, exp2 Top/s and copy GB/s (rgs_calibrate)."""
+        f, e, c = C.c_double(), C.c_double(), C.c_double()
+        _check(self.lib, self.ctx, self.lib.rgs_calibrate(self.ctx, _stream(self.device), C.byref(f), C.byref(e),
+                                                          C.byref(c)))
+        return {"fma_tflops": f.value, "exp2_tops": e.value, "copy_gbs": c.value}
+
     def downsample(self, img: torch.Tensor, factor: int) -> torch.Tensor:
         """Box average of factor x factor blocks of a [P][H f][W f] float32
         device image (rgs_downsample_box): [P][H][W]."""

@@ -75,3 +75,14 @@ def test_aa_harness_orders_the_variants_on_thin_structures(r):
     low = res[0.5]
     assert low["msaa4"]["mae"] < low["plain"]["mae"]
     assert low["mip"]["mae"] < low["plain"]["mae"]
+
+
+def test_calibration_reports_plausible_ceilings(r):
+    """rgs_calibrate: the non-packed FP32 FMA rate lies near half the
+    published 157.3 TFLOP/s, exp2 runs at a fraction of it, and the copy
+    bandwidth below the 8 TB/s HBM peak."""
+    c = r.calibrate()
+    say(f"  calibration: {c}")
+    assert 30.0 < c["fma_tflops"] < 160.0
+    assert 1.0 < c["exp2_tops"] < c["fma_tflops"]
+    assert 1000.0 < c["copy_gbs"] < 8500.0
