@@ -12,6 +12,16 @@
 
 #include "internal.h"
 
+namespace rgs {
+// backward.hip: zeroes the record gradients of the kept Gaussian-views
+// order[0, *kept) (grad_floats_per floats each, a multiple of 4).
+hipError_t launch_zero_kept_grads(const uint32_t *order, const int64_t *kept, int64_t n_max, int grad_floats_per,
+                                  float *grads, int num_cus, hipStream_t stream);
+// calib.hip: FP32 FMA TFLOP/s, exp2 Top/s and device copy GB/s (read + write)
+// measured on `stream` (allocates and frees its own buffers, synchronises).
+hipError_t measure_ceilings(int num_cus, hipStream_t stream, double *fma_tflops, double *exp_tops, double *copy_gbs);
+}  // namespace rgs
+
 using namespace rgs;
 
 namespace {
@@ -614,7 +624,8 @@ rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const r
     uint32_t *sched = at<uint32_t>(ws->ptr, L.sched);
     float *rgrads = at<float>(ws->ptr, L.record_grads);
     Timer tm(ctx, s, true, ST_BLEND_BWD);
-    RGS_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(rgrads), 0u, L.nv_records * grad_floats(opts->mip), s));
+    RGS_HIP(ctx, launch_zero_kept_grads(at<uint32_t>(ws->ptr, L.order_a), at<int64_t>(ws->ptr, L.counters) + 4,
+                                        L.nv_records, grad_floats(opts->mip), rgrads, ctx->num_cus, s));
     uint32_t *bwd_heads = sched + sched_backward_heads();
     RGS_HIP(ctx, launch_fill_u32(bwd_heads, 0u, (int64_t)kQueues * kQueueStride, s));
     RGS_HIP(ctx, launch_blend_backward(sh, at<uint2>(ws->ptr, L.ranges), at<uint32_t>(ws->ptr, L.tile_order),
@@ -859,16 +870,6 @@ rgs_status rgs_downsample_box(rgs_context *ctx, const float *src, int32_t width,
     RGS_HIP(ctx, launch_downsample_box(src, width, height, factor, planes, dst, static_cast<hipStream_t>(stream)));
     return RGS_OK;
 }
-
-}  // extern "C"
-
-namespace rgs {
-// calib.hip: FP32 FMA TFLOP/s, exp2 Top/s and device copy GB/s (read + write)
-// measured on `stream` (allocates and frees its own buffers, synchronises).
-hipError_t measure_ceilings(int num_cus, hipStream_t stream, double *fma_tflops, double *exp_tops, double *copy_gbs);
-}  // namespace rgs
-
-extern "C" {
 
 rgs_status rgs_calibrate(rgs_context *ctx, void *stream, double *fma_tflops, double *exp_tops, double *copy_gbs)
 {

@@ -164,7 +164,28 @@ __device__ double exact_mip_chain(const double mu[3], const double Rp[9], const 
     return glog2o / (o * kLn2);
 }
 
+// Zeroes the record gradients of the kept Gaussian-views, the only ones the
+// backward kernels add into or read (the depth order lists them first:
+// order[0, *kept)).  One thread per float4, so each record's lines are
+// written whole.
+__global__ __launch_bounds__(256) void k_zero_kept_grads(const uint32_t *__restrict__ order,
+                                                         const int64_t *__restrict__ kept_p, int64_t n_max,
+                                                         int stride4, float4 *__restrict__ grads)
+{
+    const int64_t kept = min(*kept_p, n_max);
+    const int64_t total = kept * stride4;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = i / stride4;
+        grads[(size_t)order[e] * stride4 + (size_t)(i - e * stride4)] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
 // Geometry and opacity (the colour part is k_colour_bwd).
+// One instantiation per divergence and MIP mode (as the forward preprocess),
+// so that each carries only its own chain.
+enum BwdMode { kBwdRay = 0, kBwdMip = 1, kBwdMipExact = 2, kBwdGS = 3 };
+
+template <int MODE>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const float *__restrict__ means, const float *__restrict__ log_scales, const float *__restrict__ quats,
     const float *__restrict__ opacity_logits, int n, const DevView *__restrict__ views, int n_views,
@@ -199,8 +220,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         const size_t idx = (size_t)v * n + i;
         if (tile_counts[idx] == 0) continue;
         const DevView &V = views[v];
-        const float *gr = record_grads + idx * grad_floats(opt.mip);
-        if (opt.mip == 2) {
+        const float *gr = record_grads + idx * (MODE == kBwdMipExact ? kGradFloatsExactMip : kGradFloats);
+        if constexpr (MODE == kBwdMipExact) {
             const double mu[3] = {V.w2c[0] * m[0] + V.w2c[1] * m[1] + V.w2c[2] * m[2] + V.w2c[3],
                                   V.w2c[4] * m[0] + V.w2c[5] * m[1] + V.w2c[6] * m[2] + V.w2c[7],
                                   V.w2c[8] * m[0] + V.w2c[9] * m[1] + V.w2c[10] * m[2] + V.w2c[11]};
@@ -228,7 +249,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         double Rp[9];
         for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c) Rp[3 * r + c] = W[4 * r] * R[c] + W[4 * r + 1] * R[3 + c] + W[4 * r + 2] * R[6 + c];
-        if (opt.divergence == RGS_DIVERGENCE_GS) {
+        if constexpr (MODE == kBwdGS) {
             // the record's anchor is pi(mu) and its M = G^T G is Sigma_pi^-1;
             // den, g, 1/c^2 are constants of this divergence
             const double gc[2] = {gu0, gv0};
@@ -245,8 +266,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         // rendered scales and opacity: widened by the MIP transform when it is on
         double sv[3] = {s[0], s[1], s[2]}, isv[3] = {is[0], is[1], is[2]};
         double ov = o;
-        const double sig2 = opt.mip ? opt.mip_sigma2_px / (V.fx * V.fy) : 0.0;
-        if (opt.mip) {
+        const double sig2 = MODE == kBwdMip ? opt.mip_sigma2_px / (V.fx * V.fy) : 0.0;
+        if constexpr (MODE == kBwdMip) {
             const double tb2 = mu[0] * mu[0] + mu[1] * mu[1] + mu[2] * mu[2];
             double det = 1.0, deth = 1.0, c2p = 0.0, c2h = 0.0;
             for (int k = 0; k < 3; ++k) {
@@ -318,7 +339,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
             dls[k] = -acc;
         }
         // the record's opacity is ov: dL/dlog ov = go ov
-        if (opt.mip) {
+        if constexpr (MODE == kBwdMip) {
             mip_chain(mu, Rp, s, sv, sig2, dls, go * ov, dl, dmu, dRp);
         } else {
             for (int k = 0; k < 3; ++k) dl[k] += dls[k];
@@ -411,6 +432,17 @@ __global__ __launch_bounds__(256) void k_colour_bwd(const float *__restrict__ me
 
 }  // namespace
 
+hipError_t launch_zero_kept_grads(const uint32_t *order, const int64_t *kept, int64_t n_max, int grad_floats_per,
+                                  float *grads, int num_cus, hipStream_t stream)
+{
+    if (n_max == 0) return hipSuccess;
+    const int64_t want = (n_max * (grad_floats_per / 4) + 255) / 256;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cus * 16));
+    k_zero_kept_grads<<<grid, 256, 0, stream>>>(order, kept, n_max, grad_floats_per / 4,
+                                                reinterpret_cast<float4 *>(grads));
+    return hipGetLastError();
+}
+
 hipError_t launch_preprocess_backward(const rgs_gaussians &g, const DevView *views, int n_views,
                                       const DevOptions &opt, const uint32_t *tile_counts, const float *record_grads,
                                       const rgs_gaussian_grads &gr, hipStream_t stream)
@@ -418,9 +450,18 @@ hipError_t launch_preprocess_backward(const rgs_gaussians &g, const DevView *vie
     const int n = (int)g.n;
     if (n == 0) return hipSuccess;
     const dim3 grid((n + 255) / 256), block(256);
-    k_preprocess_bwd<<<grid, block, 0, stream>>>(g.means, g.log_scales, g.quats, g.opacity_logits, n, views, n_views,
-                                                 tile_counts, record_grads, opt, gr.means, gr.log_scales, gr.quats,
-                                                 gr.opacity_logits);
+    const int mode = opt.divergence == RGS_DIVERGENCE_GS ? kBwdGS : opt.mip == 2 ? kBwdMipExact : opt.mip == 1 ? kBwdMip : kBwdRay;
+#define RGS_PBWD(M)                                                                                             \
+    k_preprocess_bwd<M><<<grid, block, 0, stream>>>(g.means, g.log_scales, g.quats, g.opacity_logits, n, views, \
+                                                    n_views, tile_counts, record_grads, opt, gr.means,          \
+                                                    gr.log_scales, gr.quats, gr.opacity_logits)
+    switch (mode) {
+    case kBwdGS: RGS_PBWD(kBwdGS); break;
+    case kBwdMipExact: RGS_PBWD(kBwdMipExact); break;
+    case kBwdMip: RGS_PBWD(kBwdMip); break;
+    default: RGS_PBWD(kBwdRay); break;
+    }
+#undef RGS_PBWD
     // after k_preprocess_bwd on the same stream: both add into gr.means
 #define RGS_BWD(D)                                                                                                  \
     k_colour_bwd<D><<<grid, block, 0, stream>>>(g.means, g.sh, n, views, n_views, tile_counts, record_grads,        \
