@@ -625,7 +625,8 @@ static void preprocess_one(const orc_scene *sc, int64_t i, const orc_camera *cam
             return;
         }
         double amax = mip_exact_bound(mu, s, kappa, sp->sig2);
-        for (int k = 0; k < 3; ++k) c2b += ml0[k] * ml0[k] / (s[k] * s[k] + amax);
+        if (amax >= 0.0)
+            for (int k = 0; k < 3; ++k) c2b += ml0[k] * ml0[k] / (s[k] * s[k] + amax);
         if (amax < 0.0 || !(c2b > kappa)) {
             sp->whole = 1;
         } else {
