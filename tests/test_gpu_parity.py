@@ -329,22 +329,25 @@ def test_autotune_picks_a_supported_shape(r):
     assert ms > 0
 
 
-def test_training_autotune_picks_a_supported_shape_and_keeps_gradients_valid(r):
+@pytest.mark.parametrize("mode", [dict(), dict(mip=1), dict(mip=2, mip_sigma2_px=0.5), dict(divergence=1)],
+                         ids=["ray", "mip", "exact_mip", "gs"])
+def test_training_autotune_picks_a_supported_shape_and_keeps_gradients_valid(r, mode):
     """The render + backward autotuner returns a supported shape, and a
-    backward pass at that shape still matches the default shape's."""
+    backward pass at that shape still matches the default shape's, for every
+    differentiable divergence and MIP mode."""
     from paper_2503_18682_amd import _lib
 
     sc = scenegen.tiny_scene(37, 2000, sh_degree=1)
     cams = [scenegen.pinhole(scenegen.look_at((0, 0, -4)), 120, 100, 60)]
     g = to_dev(sc)
-    say("case training autotune")
-    opts = scenegen.default_options()
+    say(f"case training autotune {mode}")
+    opts = scenegen.default_options(**mode)
     buf, ws = r.new_workspace(2000, cams, 500000, _lib.RGS_WS_BACKWARD, opts)
     outs = r.allocate_outputs(cams)
     rng = np.random.default_rng(5)
     dl = [torch.from_numpy(rng.normal(0, 1, (3, 100, 120)).astype(np.float32)).cuda()]
     r.render_into(g, cams, outs, ws, opts)
-    best, ms = r.autotune_training(g, cams, ws, outs, dl, reps=2)
+    best, ms = r.autotune_training(g, cams, ws, outs, dl, reps=2, options=opts)
     assert best["tile_w"] in (8, 16, 32) and best["tile_h"] in (8, 16, 32) and ms > 0
     # tile (0, 0) now resolves to the tuned shape on this context
     lay = r.layout(2000, cams, 500000, _lib.RGS_WS_BACKWARD, dict(opts, tile_w=0, tile_h=0))
