@@ -462,8 +462,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: the renderer has no multi-GPU path in this build "
-              "(views would shard across GPUs with no exchange; see DESIGN.md). Run with --gpus 1.",
+        print("bench.py measures one GPU only: the renderer has no multi-GPU path "
+              "(views would shard across GPUs with no exchange). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -66,7 +66,7 @@ typedef enum {
     RGS_EOVERFLOW = -3,    /* more Gaussian-tile instances than the workspace holds */
     RGS_EHIP = -4,         /* a HIP runtime call failed */
     RGS_ECAPTURE = -5,     /* HIP graph capture or instantiation failed */
-    RGS_EUNSUPPORTED = -6  /* valid request this build does not implement */
+    RGS_EUNSUPPORTED = -6  /* a valid request the library does not implement */
 } rgs_status;
 
 typedef struct {
