@@ -162,7 +162,9 @@ rgs_status rgs_workspace_size(rgs_context *ctx, int64_t n, const rgs_camera *cam
  * of eq. 5, the quad bound of Sec. 4.1 and, with opts->mip = 1, eq. 17; with
  * opts->mip = 2 the exact MIP weight of Sec. 5 per pixel, binned by the quad
  * of a widened Gaussian that bounds its support, or by the whole view where
- * no such bound exists).
+ * no such bound exists).  A quad with a vertex at z <= 0 is drawn unclipped;
+ * its pixel box is that of the part of it inside the view frustum, and it is
+ * culled when no part is inside.
  * cams, outs: host arrays of n_views (outs entries hold device pointers);
  * opts: one struct for the whole batch.  Stream-ordered, no host
  * synchronisation.  If the frame needs
@@ -230,7 +232,9 @@ rgs_status rgs_autotune_training(rgs_context *ctx, const rgs_gaussians *g, const
 typedef struct {
     size_t counters;       /* int64[8]: [0] instances needed (tiles of all pixel boxes), [1] capacity,
                               [2] tile rows of all boxes, [3] listed instances (sorted; the rest are
-                              empty), [4] kept (not culled) Gaussian-views */
+                              empty), [4] kept (not culled) Gaussian-views, [5] quads with a vertex at
+                              z <= 0 (the first 65536 have their box clipped to the view frustum, the
+                              rest keep the whole view) */
     size_t views;          /* per-view device table */
     size_t records;        /* float[16] per Gaussian-view (float[28] with mip = 2), index v * n + i */
     size_t depth_keys;     /* uint32 per Gaussian-view: the kept views' keys, sorted, in [0, counters[4]) */

@@ -34,7 +34,8 @@
  *   omega >= p_min; compositing stops before a Gaussian whose contribution
  *   would take the transmittance below t_eps; rays with tau <= 0 get no
  *   contribution; near-plane culling of centres with mu_z <= near_z; a quad
- *   with a vertex at z <= 0 bounds the whole view; pixel centres sit at +1/2;
+ *   with a vertex at z <= 0 is clipped to the side planes of the view
+ *   frustum and its box is that of the clipped part; pixel centres sit at +1/2;
  *   colour = max(0, SH(view direction) + 0.5); depth key = bits of
  *   float32(mu_z), ties broken by Gaussian index.
  *
@@ -456,6 +457,49 @@ static void box_to_pixels(orc_splat *sp, const orc_camera *cam, double umin, dou
     sp->py1 = fy1 > H_ - 1 ? H_ - 1 : (fy1 < -1.0 ? -1 : (int)fy1);
 }
 
+/* The part of a quad (4 corners in order, camera frame) that can project into
+ * the view: the quad clipped, Sutherland-Hodgman, against the four side
+ * planes of the view frustum, which pass through the camera centre and hold
+ * the image borders (inside all four, z >= 0).  Returns 1 with the bounding
+ * box (umin, umax, vmin, vmax) of the projected clipped polygon, 0 when no
+ * part of the quad is inside, -1 when a clipped vertex has z <= 0 (only the
+ * camera centre itself can). */
+static int clip_quad_to_view(const double *quad, const orc_camera *cam, double *box)
+{
+    double P[8][3], Q[8][3];
+    int n = 4;
+    for (int k = 0; k < 4; ++k)
+        for (int c = 0; c < 3; ++c) P[k][c] = quad[3 * k + c];
+    const double planes[4][3] = {{cam->fx, 0.0, cam->cx},
+                                 {-cam->fx, 0.0, cam->width - cam->cx},
+                                 {0.0, cam->fy, cam->cy},
+                                 {0.0, -cam->fy, cam->height - cam->cy}};
+    for (int p = 0; p < 4; ++p) {
+        int m = 0;
+        for (int i = 0; i < n; ++i) {
+            const double *A = P[i], *B = P[(i + 1) % n];
+            double da = dot3(planes[p], A), db = dot3(planes[p], B);
+            if (da >= 0.0) memcpy(Q[m++], A, sizeof(double) * 3);
+            if ((da >= 0.0) != (db >= 0.0)) {
+                double t = da / (da - db);
+                for (int c = 0; c < 3; ++c) Q[m][c] = A[c] + t * (B[c] - A[c]);
+                ++m;
+            }
+        }
+        n = m;
+        if (n == 0) return 0;
+        memcpy(P, Q, sizeof(double) * 3 * n);
+    }
+    box[0] = INFINITY; box[1] = -INFINITY; box[2] = INFINITY; box[3] = -INFINITY;
+    for (int i = 0; i < n; ++i) {
+        if (!(P[i][2] > 0.0)) return -1;
+        double u = cam->fx * P[i][0] / P[i][2] + cam->cx, v = cam->fy * P[i][1] / P[i][2] + cam->cy;
+        box[0] = fmin(box[0], u); box[1] = fmax(box[1], u);
+        box[2] = fmin(box[2], v); box[3] = fmax(box[3], v);
+    }
+    return 1;
+}
+
 /* ------------------------------------------------------ per-Gaussian stage */
 static void preprocess_one(const orc_scene *sc, int64_t i, const orc_camera *cam, const orc_options *opt,
                            orc_splat *sp)
@@ -726,8 +770,10 @@ static void preprocess_one(const orc_scene *sc, int64_t i, const orc_camera *cam
     if (zmin <= 1e-12 * zscale) sp->hazard |= ORC_HZ_FRONT;
     sp->all_front = all_front;
 
-    /* Bounding box of the projected quad; no near-plane clipping of the quad
-     * (Sec. 4.1): when a vertex lies at z <= 0 the whole view is covered. */
+    /* Bounding box of the projected quad.  The quad is never clipped for
+     * drawing (Sec. 4.1): every pixel of the box is still evaluated exactly.
+     * When a vertex lies at z <= 0 only the box is bounded, by the part of
+     * the quad inside the view frustum. */
     int W_ = cam->width, H_ = cam->height;
     int px0, px1, py0, py1;
     if (all_front) {
@@ -742,8 +788,19 @@ static void preprocess_one(const orc_scene *sc, int64_t i, const orc_camera *cam
         box_to_pixels(sp, cam, umin, umax, vmin, vmax);
         px0 = sp->px0; px1 = sp->px1; py0 = sp->py0; py1 = sp->py1;
     } else {
-        sp->bbox[0] = -INFINITY; sp->bbox[1] = INFINITY; sp->bbox[2] = -INFINITY; sp->bbox[3] = INFINITY;
-        px0 = 0; px1 = W_ - 1; py0 = 0; py1 = H_ - 1;
+        /* only the box is bounded, by the part of the quad inside the view
+         * frustum; the quad is never clipped for drawing */
+        double cb[4];
+        int cr = clip_quad_to_view(sp->quad, cam, cb);
+        if (cr > 0) {
+            box_to_pixels(sp, cam, cb[0], cb[1], cb[2], cb[3]);
+            px0 = sp->px0; px1 = sp->px1; py0 = sp->py0; py1 = sp->py1;
+        } else if (cr == 0) {
+            px0 = 1; px1 = 0; py0 = 1; py1 = 0;
+        } else {
+            sp->bbox[0] = -INFINITY; sp->bbox[1] = INFINITY; sp->bbox[2] = -INFINITY; sp->bbox[3] = INFINITY;
+            px0 = 0; px1 = W_ - 1; py0 = 0; py1 = H_ - 1;
+        }
     }
     sp->px0 = px0; sp->px1 = px1; sp->py0 = py0; sp->py1 = py1;
     if (px0 > px1 || py0 > py1) {

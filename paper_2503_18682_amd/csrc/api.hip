@@ -32,10 +32,14 @@ const char *const kStageNames =
 enum Stage { ST_PRE, ST_DSORT, ST_SCAN, ST_EMIT, ST_TSORT, ST_RANGES, ST_BLEND, ST_BLEND_BWD, ST_PRE_BWD };
 
 constexpr size_t kAlign = 256;
+// Quads with a vertex at z <= 0 clipped per launch; more keep the whole view.
+constexpr int64_t kCrossingCap = 1 << 16;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t counters, views, colours, records, keys_a, keys_b, order_a, order_b, boxes, conics, tile_counts, offsets, block_sums;
+    size_t crossing;          // quads with a vertex at z <= 0, awaiting frustum clipping
+    uint32_t crossing_cap;    // entries of the crossing list
     size_t inst_tiles_a, inst_tiles_b, inst_ids_a, inst_ids_b, hist, row_total, ranges, sched, tile_order;
     size_t row_offsets, row_owner, item_clock;
     size_t record_grads, total;
@@ -243,6 +247,8 @@ rgs_status compute_layout(rgs_context *ctx, int64_t n, const rgs_camera *cams, i
     L.boxes = take(NV * 8);
     L.conics = take(NV * sizeof(Conic));
     L.tile_counts = take(NV * 4);
+    L.crossing_cap = (uint32_t)std::min<int64_t>((int64_t)NV, kCrossingCap);
+    L.crossing = take((size_t)L.crossing_cap * kCrossingDoubles * sizeof(double));
     L.offsets = take(NV * 4);
     L.row_offsets = take(NV * 4);
     L.block_sums = take(scan_block_entries((int64_t)NV) * 8);
@@ -420,9 +426,10 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
     unsigned long long *item_clock = view_stamps ? at<unsigned long long>(ws, L.item_clock) : nullptr;
     Timer tm(ctx, stream, timing, ST_PRE);
     RGS_HIP(ctx, launch_preprocess(g, views, n_views, dopt, colours, records, keys_in, ord_in, boxes, conics,
-                                   tile_counts, stream));
+                                   tile_counts, at<double>(ws, L.crossing), counters + 5, L.crossing_cap, stream));
     tm.mark(ST_PRE);
-    // counters: [0] box instances, [1] capacity, [2] tile rows, [3] listed instances, [4] kept views
+    // counters: [0] box instances, [1] capacity, [2] tile rows, [3] listed instances, [4] kept views,
+    // [5] quads with a vertex at z <= 0
     int64_t *listed = counters + 3, *kept = counters + 4;
     RGS_HIP(ctx, radix_sort(keys_in, ord_in, keys_alt, ord_alt, NV, nullptr, 32, true, 0xffffffffu, kept, hist,
                             row_total, stream));

@@ -72,10 +72,16 @@ struct TileShape {
 // Writes per Gaussian-view: the colour staging entry (colours, float4: r, g,
 // b, non-finite-coefficient flag), record, depth key (0xffffffff when
 // culled), the identity order, pixel box, support conic, and the number of
-// tiles of the box (0 when culled).
+// tiles of the box (0 when culled).  A quad with a vertex at z <= 0 is first
+// given the whole view; its parameters go to the crossing list (kCrossingDoubles
+// doubles per entry, at most crossing_cap entries, *crossing_count zero on
+// entry), and a second kernel bounds its box by the part of the quad inside
+// the view frustum.  Entries beyond the cap keep the whole view.
+constexpr int kCrossingDoubles = 12;
 hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n_views, const DevOptions &opt,
                              float4 *colours, float4 *records, uint32_t *depth_keys, uint32_t *order, uint2 *boxes,
-                             Conic *conics, uint32_t *tile_counts, hipStream_t stream);
+                             Conic *conics, uint32_t *tile_counts, double *crossing, int64_t *crossing_count,
+                             uint32_t crossing_cap, hipStream_t stream);
 
 // Stable LSD radix sort of (key, value) pairs on bits [0, bits), 8-bit digits
 // (radix_passes(bits) passes of a per-workgroup digit histogram, a scan of

@@ -87,7 +87,10 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                                                     const float4 *__restrict__ colours,
                                                     float4 *__restrict__ records, uint32_t *__restrict__ depth_keys,
                                                     uint32_t *__restrict__ order, uint2 *__restrict__ boxes,
-                                                    Conic *__restrict__ conics, uint32_t *__restrict__ tile_counts)
+                                                    Conic *__restrict__ conics, uint32_t *__restrict__ tile_counts,
+                                                    double *__restrict__ crossing,
+                                                    unsigned long long *__restrict__ crossing_count,
+                                                    uint32_t crossing_cap)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -335,13 +338,30 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
             }
             const double O0[4] = {-1.0, -1.0, 1.0, 1.0}, O1[4] = {-1.0, 1.0, 1.0, -1.0};
             bool all_front = true;
+            for (int k = 0; k < 4; ++k)
+                if (!(QU[4] * (hs * O0[k]) + QU[5] * (hs * O1[k]) + mu[2] > 0.0)) all_front = false;
+            // A vertex at z <= 0 makes the box the whole view here; the quad
+            // goes to the crossing list, whose kernel bounds the box by the
+            // part of the quad inside the view frustum.
+            if (!all_front) {
+                const unsigned long long slot = atomicAdd(crossing_count, 1ull);
+                if (slot < crossing_cap) {
+                    double *e = crossing + slot * kCrossingDoubles;
+                    e[0] = mu[0];
+                    e[1] = mu[1];
+                    e[2] = mu[2];
+                    for (int k = 0; k < 6; ++k) e[3 + k] = QU[k];
+                    e[9] = hs;
+                    e[10] = (double)idx;
+                    e[11] = 0.0;
+                }
+            }
             double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
             for (int k = 0; k < 4; ++k) {
                 const double z0 = hs * O0[k], z1 = hs * O1[k];
                 const double Vx = QU[0] * z0 + QU[1] * z1 + mu[0];
                 const double Vy = QU[2] * z0 + QU[3] * z1 + mu[1];
                 const double Vz = QU[4] * z0 + QU[5] * z1 + mu[2];
-                if (!(Vz > 0.0)) all_front = false;
                 const double iz = 1.0 / Vz;
                 const double u = V.fx * Vx * iz + V.cx;
                 const double vv = V.fy * Vy * iz + V.cy;
@@ -350,8 +370,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                 vmin = fmin(vmin, vv);
                 vmax = fmax(vmax, vv);
             }
-            // pixel centres inside the box; no near-plane clipping of the quad,
-            // so a vertex at z <= 0 makes the box the whole view
+            // pixel centres inside the box
             const int Wd = V.width, Hd = V.height;
             int px0 = 0, px1 = Wd - 1, py0 = 0, py1 = Hd - 1;
             if (all_front) {
@@ -425,6 +444,118 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
     }
 }
 
+// Box of a quad with a vertex at z <= 0 (Sec. 4.1 draws the quad unclipped;
+// only its pixel box is bounded here): the quad, rebuilt from its crossing
+// list entry with the arithmetic of the geometry kernel, is clipped
+// (Sutherland-Hodgman) against the four side planes of the view frustum,
+// which pass through the camera centre and the image borders; the box is
+// that of the projected clipped polygon.  No part inside: the Gaussian-view
+// is culled.  A clipped vertex at z <= 0 (only the camera centre can be one),
+// or a polygon beyond kClipMaxVerts vertices (rounding only), keeps the
+// whole view.  One wave per block; each lane keeps its two polygons in LDS.
+constexpr int kClipBlock = 64, kClipMaxVerts = 16, kClipGrid = 32;
+
+__global__ __launch_bounds__(kClipBlock) void k_clip_crossing(const double *__restrict__ crossing,
+                                                              const unsigned long long *__restrict__ crossing_count,
+                                                              uint32_t crossing_cap, int n,
+                                                              const DevView *__restrict__ views, DevOptions opt,
+                                                              int rec_floats, float *__restrict__ records,
+                                                              uint32_t *__restrict__ depth_keys,
+                                                              uint2 *__restrict__ boxes,
+                                                              uint32_t *__restrict__ tile_counts)
+{
+    __shared__ double poly[2][kClipMaxVerts][3][kClipBlock];
+    const unsigned long long total = min(*crossing_count, (unsigned long long)crossing_cap);
+    const int l = threadIdx.x;
+    for (unsigned long long j = (unsigned long long)blockIdx.x * kClipBlock + l; j < total;
+         j += (unsigned long long)gridDim.x * kClipBlock) {
+        const double *e = crossing + j * kCrossingDoubles;
+        const uint32_t idx = (uint32_t)e[10];
+        const DevView &V = views[idx / (uint32_t)n];
+        const double hs = e[9];
+        const double O0[4] = {-1.0, -1.0, 1.0, 1.0}, O1[4] = {-1.0, 1.0, 1.0, -1.0};
+        for (int k = 0; k < 4; ++k) {
+            const double z0 = hs * O0[k], z1 = hs * O1[k];
+            poly[0][k][0][l] = e[3] * z0 + e[4] * z1 + e[0];
+            poly[0][k][1][l] = e[5] * z0 + e[6] * z1 + e[1];
+            poly[0][k][2][l] = e[7] * z0 + e[8] * z1 + e[2];
+        }
+        // inside half-spaces: u >= 0, u <= W, v >= 0, v <= H (z > 0)
+        const double pl[4][3] = {{V.fx, 0.0, V.cx},
+                                 {-V.fx, 0.0, (double)V.width - V.cx},
+                                 {0.0, V.fy, V.cy},
+                                 {0.0, -V.fy, (double)V.height - V.cy}};
+        int m = 4, cur = 0;
+        bool bounded = true;
+        for (int p = 0; p < 4 && m > 0 && bounded; ++p) {
+            int k = 0;
+            for (int a = 0; a < m; ++a) {
+                const int bi = a + 1 == m ? 0 : a + 1;
+                double A[3], B[3];
+                for (int c = 0; c < 3; ++c) {
+                    A[c] = poly[cur][a][c][l];
+                    B[c] = poly[cur][bi][c][l];
+                }
+                const double da = pl[p][0] * A[0] + pl[p][1] * A[1] + pl[p][2] * A[2];
+                const double db = pl[p][0] * B[0] + pl[p][1] * B[1] + pl[p][2] * B[2];
+                const int emit = (da >= 0.0 ? 1 : 0) + ((da >= 0.0) != (db >= 0.0) ? 1 : 0);
+                if (k + emit > kClipMaxVerts) {
+                    bounded = false;
+                    break;
+                }
+                if (da >= 0.0) {
+                    for (int c = 0; c < 3; ++c) poly[1 - cur][k][c][l] = A[c];
+                    ++k;
+                }
+                if ((da >= 0.0) != (db >= 0.0)) {
+                    const double t = da / (da - db);
+                    for (int c = 0; c < 3; ++c) poly[1 - cur][k][c][l] = A[c] + t * (B[c] - A[c]);
+                    ++k;
+                }
+            }
+            m = k;
+            cur = 1 - cur;
+        }
+        if (!bounded) continue;
+        int px0 = 1, px1 = 0, py0 = 1, py1 = 0;
+        if (m > 0) {
+            double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+            for (int a = 0; a < m && bounded; ++a) {
+                const double z = poly[cur][a][2][l];
+                if (!(z > 0.0)) {
+                    bounded = false;
+                    break;
+                }
+                const double iz = 1.0 / z;
+                const double u = V.fx * poly[cur][a][0][l] * iz + V.cx;
+                const double vv = V.fy * poly[cur][a][1][l] * iz + V.cy;
+                umin = fmin(umin, u);
+                umax = fmax(umax, u);
+                vmin = fmin(vmin, vv);
+                vmax = fmax(vmax, vv);
+            }
+            if (!bounded) continue;
+            const int Wd = V.width, Hd = V.height;
+            const double fx0 = ceil(umin - 0.5), fx1 = floor(umax - 0.5);
+            const double fy0 = ceil(vmin - 0.5), fy1 = floor(vmax - 0.5);
+            px0 = fx0 < 0.0 ? 0 : (fx0 > Wd ? Wd : (int)fx0);
+            px1 = fx1 > Wd - 1 ? Wd - 1 : (fx1 < -1.0 ? -1 : (int)fx1);
+            py0 = fy0 < 0.0 ? 0 : (fy0 > Hd ? Hd : (int)fy0);
+            py1 = fy1 > Hd - 1 ? Hd - 1 : (fy1 < -1.0 ? -1 : (int)fy1);
+        }
+        if (px0 > px1 || py0 > py1) {
+            depth_keys[idx] = 0xffffffffu;
+            tile_counts[idx] = 0u;
+            boxes[idx] = make_uint2(0u, 0u);
+            continue;
+        }
+        boxes[idx] = make_uint2((uint32_t)px0 | ((uint32_t)px1 << 16), (uint32_t)py0 | ((uint32_t)py1 << 16));
+        tile_counts[idx] =
+            (uint32_t)((px1 / opt.tile_w - px0 / opt.tile_w + 1) * (py1 / opt.tile_h - py0 / opt.tile_h + 1));
+        records[(size_t)idx * rec_floats + 3] = __uint_as_float((uint32_t)py0 | ((uint32_t)py1 << 16));
+    }
+}
+
 // View-dependent colour of every Gaussian-view (one thread per Gaussian; its
 // coefficients are read once, coalesced across the wave), run before the
 // geometry: colours[v n + i] = (max(0, SH(direction camera centre -> mean) +
@@ -463,7 +594,8 @@ __global__ __launch_bounds__(256) void k_colour(const float *__restrict__ means,
 
 hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n_views, const DevOptions &opt,
                              float4 *colours, float4 *records, uint32_t *depth_keys, uint32_t *order, uint2 *boxes,
-                             Conic *conics, uint32_t *tile_counts, hipStream_t stream)
+                             Conic *conics, uint32_t *tile_counts, double *crossing, int64_t *crossing_count,
+                             uint32_t crossing_cap, hipStream_t stream)
 {
     const int n = (int)g.n;
     if (n == 0) return hipSuccess;
@@ -483,7 +615,8 @@ hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n
 #define RGS_PRE(M)                                                                                              \
     k_preprocess<M><<<grid, block, 0, stream>>>(g.means, g.log_scales, g.quats, g.opacity_logits, n, views,     \
                                                 n_views, opt, colours, records, depth_keys, order, boxes, conics, \
-                                                tile_counts)
+                                                tile_counts, crossing,                                            \
+                                                reinterpret_cast<unsigned long long *>(crossing_count), crossing_cap)
     switch (mode) {
     case kPrepGS: RGS_PRE(kPrepGS); break;
     case kPrepMipExact: RGS_PRE(kPrepMipExact); break;
@@ -491,6 +624,11 @@ hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n
     default: RGS_PRE(kPrepRay); break;
     }
 #undef RGS_PRE
+    // the linearised divergence has no quad, so nothing crosses
+    if (mode != kPrepGS && crossing_cap > 0)
+        k_clip_crossing<<<kClipGrid, kClipBlock, 0, stream>>>(
+            crossing, reinterpret_cast<const unsigned long long *>(crossing_count), crossing_cap, n, views, opt,
+            record_floats(opt.mip), reinterpret_cast<float *>(records), depth_keys, boxes, tile_counts);
     return hipGetLastError();
 }
 

@@ -192,6 +192,50 @@ def test_edge_cases(r, mode):
     assert np.allclose(render_with_ws(r, cases["empty"], [cam], opts)[0][0]["rgb"][2], 0.3)
 
 
+def _crossing_scene(seed, n):
+    """Large Gaussians close to a camera at the origin: many quads cross the
+    camera plane z = 0."""
+    sc = scenegen.tiny_scene(seed, n, sh_degree=1, half_extent=1.0, log_scale_mean=-1.8, log_scale_std=0.6)
+    sc["means"][2, :] = np.random.default_rng(seed).uniform(0.25, 2.5, n).astype(np.float32)
+    return sc
+
+
+@pytest.mark.parametrize("mode", [dict(), dict(mip=1), dict(mip=2, mip_sigma2_px=1.0)], ids=["ray", "mip", "exact_mip"])
+def test_crossing_quads_are_clipped_to_the_frustum(r, mode):
+    """Quads with a vertex at z <= 0: the box is that of the part of the quad
+    inside the view frustum, bit-exact against the oracle (outside its hazard
+    set), quads wholly outside the view are culled, every crossing quad is
+    counted, and the tile lists and image match the oracle."""
+    cam = scenegen.pinhole(np.concatenate([np.eye(3), np.zeros((3, 1))], 1), 97, 61, 90)
+    opts = scenegen.default_options(**mode)
+    sc = _crossing_scene(61, 300)
+    say(f"case crossing quads {mode}: 300 Gaussians near the camera, 97x61")
+    outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
+    assert ok
+    sp = oracle.preprocess(sc, cam, opts)
+    C = oracle.CULL
+    crossing = (sp["all_front"] == 0) & (sp["whole"] == 0) & np.isin(sp["cull"], [0, C["offscreen"], C["notile"]])
+    clipped_away = crossing & (sp["cull"] == C["offscreen"])
+    say(f"  {int(crossing.sum())} crossing quads, {int(clipped_away.sum())} wholly outside the view")
+    assert crossing.sum() > 20 and clipped_away.sum() > 0
+    assert int(read(buf, lay.counters, 8, np.int64)[5]) == crossing.sum()
+    n = 300
+    good = sp["hazard"] == 0
+    # a box with no listed tile (notile) still has its tiles counted
+    counts = read(buf, lay.tile_counts, n, np.uint32)
+    assert np.array_equal(counts[good] == 0, ~np.isin(sp["cull"][good], [0, C["notile"]]))
+    kept = (sp["cull"] == 0) & good
+    boxes = read(buf, lay.boxes, 2 * n, np.uint32).reshape(n, 2)
+    for f, col, sh in (("px0", 0, 0), ("px1", 0, 16), ("py0", 1, 0), ("py1", 1, 16)):
+        assert np.array_equal((boxes[kept, col] >> sh) & 0xFFFF, sp[f][kept]), f
+    assert m == oracle_box_tiles(sp)[1].sum()
+    tiles, ids = instance_lists(buf, lay)
+    ot, _, oi, bad = oracle_lists_without_hazards(sp, cam, opts)
+    keep = ~np.isin(ids, list(bad)) if bad else np.ones_like(ids, bool)
+    assert np.array_equal(tiles[keep], ot) and np.array_equal(ids[keep], oi)
+    assert_image_close(outs[0]["rgb"], outs[0]["final_T"], oracle.render(sc, cam, opts), label=f"crossing {mode}")
+
+
 def test_overflow_is_reported_and_recovers(r):
     say("case overflow: capacity 16")
     w = scenegen.make_workload("c0")

@@ -518,19 +518,56 @@ def test_culls_and_degenerate_inputs(oracle_lib):
     assert list(sp["cull"]) == [C["near"], C["near"], C["visible"], C["kappa"], C["invalid"], C["invalid"], C["offscreen"]]
 
 
-def test_quad_crossing_camera_plane_covers_view(oracle_lib):
-    """A large Gaussian just beyond the near plane whose quad crosses z <= 0
-    bounds the whole view (no near-plane clipping, Sec. 4.1); the image still
-    matches brute force."""
+def _sampled_quad_box(quad, cam, n=1201):
+    """Box (umin, umax, vmin, vmax) of the projections of a dense grid of
+    points on the quad (a rectangle: corners V0, V1, V2, V3 in order) that lie
+    in front of the camera and project into the view; None when none does."""
+    V = quad.reshape(4, 3)
+    s = np.linspace(0.0, 1.0, n)
+    S, T = np.meshgrid(s, s, indexing="ij")
+    P = V[0] + S[..., None] * (V[3] - V[0]) + T[..., None] * (V[1] - V[0])
+    z = P[..., 2]
+    front = z > 1e-9
+    u = cam["fx"] * P[..., 0] / np.where(front, z, 1.0) + cam["cx"]
+    v = cam["fy"] * P[..., 1] / np.where(front, z, 1.0) + cam["cy"]
+    inside = front & (u >= 0) & (u <= cam["width"]) & (v >= 0) & (v <= cam["height"])
+    if not inside.any():
+        return None
+    return u[inside].min(), u[inside].max(), v[inside].min(), v[inside].max()
+
+
+def test_quad_crossing_camera_plane_box_is_clipped(oracle_lib):
+    """A large Gaussian just beyond the near plane whose quad crosses z <= 0:
+    its box is that of the part of the quad inside the view frustum (the quad
+    itself is drawn unclipped, Sec. 4.1), which dense sampling of the quad's
+    surface reproduces; a second crossing quad lies wholly outside the view
+    and is culled.  The image still matches brute force, which evaluates
+    every pixel for every Gaussian, so the clipped box drops no pixel."""
     cam = _ident_cam(24, 20, 90)
     sc = _one_gaussian_scene([[0.3, 0.1, 0.6], [0, 0, 2.0]], [[0.05, 0.5, 0.05], [0.2] * 3], [0.8, 0.6], [[1, 0, 0], [0, 1, 0]])
     sc["quats"][:, 0] = np.array([0.9, 0.3, 0.2, 0.1], np.float32)
     sp = oracle.preprocess(sc, cam, OPTS)
     assert sp["cull"][0] == 0 and sp["all_front"][0] == 0
-    assert (sp["px0"][0], sp["px1"][0], sp["py0"][0], sp["py1"][0]) == (0, 23, 0, 19)
+    ref = _sampled_quad_box(sp["quad"][0], cam)
+    assert ref is not None
+    # samples lie inside the clipped polygon, and the grid spacing bounds how
+    # far inside its extreme points they can stay
+    bb = sp["bbox"][0]
+    assert bb[0] <= ref[0] + 1e-9 and bb[1] >= ref[1] - 1e-9 and bb[2] <= ref[2] + 1e-9 and bb[3] >= ref[3] - 1e-9
+    assert np.abs(bb - np.array(ref)).max() < 0.1
+    assert (sp["px0"][0], sp["px1"][0], sp["py0"][0], sp["py1"][0]) == (12, 23, 0, 19)
     out = oracle.render(sc, cam, OPTS)
     C, T = _brute_render(sc, cam, OPTS)
     np.testing.assert_allclose(out["rgb"], C, atol=1e-10)
+
+    side = _one_gaussian_scene([[2.5, 0.1, 0.6], [0, 0, 2.0]], [[0.05, 0.5, 0.05], [0.2] * 3], [0.8, 0.6],
+                               [[1, 0, 0], [0, 1, 0]])
+    side["quats"][:, 0] = np.array([0.9, 0.3, 0.2, 0.1], np.float32)
+    sp = oracle.preprocess(side, cam, OPTS)
+    assert sp["all_front"][0] == 0 and _sampled_quad_box(sp["quad"][0], cam) is None
+    assert sp["cull"][0] == oracle.CULL["offscreen"]
+    C, T = _brute_render(side, cam, OPTS)
+    np.testing.assert_allclose(oracle.render(side, cam, OPTS)["rgb"], C, atol=1e-10)
 
 
 # ----------------------------------------------------------------- MIP, eq. (17)
