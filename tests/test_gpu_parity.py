@@ -236,6 +236,38 @@ def test_crossing_quads_are_clipped_to_the_frustum(r, mode):
     assert_image_close(outs[0]["rgb"], outs[0]["final_T"], oracle.render(sc, cam, opts), label=f"crossing {mode}")
 
 
+def test_crossing_list_beyond_its_cap_keeps_the_whole_view(r):
+    """More crossing quads than the list holds (65536 per launch): every one
+    is counted, those beyond the cap keep the whole view (more instances than
+    the oracle's clipped boxes need), and the image still matches the oracle
+    on sampled pixels."""
+    n = 170000
+    sc = scenegen.tiny_scene(62, n, sh_degree=0, half_extent=1.0, log_scale_mean=-1.2, log_scale_std=0.4)
+    sc["means"][2, :] = np.random.default_rng(62).uniform(0.25, 1.5, n).astype(np.float32)
+    cam = scenegen.pinhole(np.concatenate([np.eye(3), np.zeros((3, 1))], 1), 64, 48, 90)
+    opts = scenegen.default_options()
+    say("case crossing list overflow: 170000 Gaussians near the camera, 64x48")
+    outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
+    assert ok
+    sp = oracle.preprocess(sc, cam, opts)
+    C = oracle.CULL
+    crossing = (sp["all_front"] == 0) & np.isin(sp["cull"], [0, C["offscreen"], C["notile"]])
+    got = int(read(buf, lay.counters, 8, np.int64)[5])
+    say(f"  {got} crossing quads counted, oracle {int(crossing.sum())}")
+    assert got == crossing.sum() and got > 65536
+    assert m > oracle_box_tiles(sp)[1].sum()
+    rng = np.random.default_rng(63)
+    px = rng.integers(0, 64, 300)
+    py = rng.integers(0, 48, 300)
+    rgb, T, hz = oracle.render_pixels(sc, cam, opts, px, py)
+    # every ray of this dense scene ends at the transmittance stop, so more of
+    # them sit near a decision boundary than in the other scenes (about 4%)
+    ok_ = hz == 0
+    assert (~ok_).mean() < 0.1
+    assert np.abs(outs[0]["rgb"][:, py, px].T - rgb)[ok_].max() <= 2e-4
+    assert np.abs(outs[0]["final_T"][py, px] - T)[ok_].max() <= 2e-4
+
+
 def test_overflow_is_reported_and_recovers(r):
     say("case overflow: capacity 16")
     w = scenegen.make_workload("c0")
