@@ -236,6 +236,52 @@ def test_crossing_quads_are_clipped_to_the_frustum(r, mode):
     assert_image_close(outs[0]["rgb"], outs[0]["final_T"], oracle.render(sc, cam, opts), label=f"crossing {mode}")
 
 
+def test_crossing_quads_graph_replays_and_gradients(r):
+    """The crossing list in a captured graph: its counter restarts with every
+    replay, so replays of moving cameras equal eager renders bit for bit and
+    the oracle; and the backward over the crossing scene (clipped boxes,
+    clip-culled views with no gradient) matches the oracle's gradient."""
+    from paper_2503_18682_amd import _lib
+    from paper_2503_18682_amd import renderer as R
+    from test_gpu_grad import _compare
+
+    sc = _crossing_scene(61, 300)
+    base = np.concatenate([np.eye(3), np.zeros((3, 1))], 1)
+    cams = [scenegen.pinhole(base, 97, 61, 90), scenegen.pinhole(base, 64, 80, 80)]
+    opts = scenegen.default_options()
+    g = to_dev(sc)
+    say("case crossing quads graph plan: 2 views, 3 replays")
+    br = R.BatchRenderer(r, 300, 1, cams, capacity=200000, options=opts)
+    for rep in range(3):
+        moved = []
+        for c in cams:
+            c2 = dict(c)
+            c2["w2c"] = c["w2c"].copy()
+            c2["w2c"][0, 3] += 0.03 * rep
+            moved.append(c2)
+        outs = br.launch(g, moved)
+        assert br.status()[0]
+        eager = render_with_ws(r, sc, moved, opts)[0]
+        for v in range(2):
+            assert np.array_equal(outs[v]["rgb"].cpu().numpy(), eager[v]["rgb"]), (rep, v)
+            assert np.array_equal(outs[v]["final_T"].cpu().numpy(), eager[v]["final_T"]), (rep, v)
+        if rep == 2:
+            for v in range(2):
+                assert_image_close(eager[v]["rgb"], eager[v]["final_T"], oracle.render(sc, moved[v], opts),
+                                   label=f"crossing graph view {v}")
+    br.close()
+
+    say("case crossing quads gradients: 300 Gaussians, 97x61, dense upstream gradient")
+    cam = cams[0]
+    outs, (buf, ws) = r.render(g, [cam], opts, flags=_lib.RGS_WS_BACKWARD, keep_workspace=True)
+    ref_img = oracle.render(sc, cam, opts)
+    dl = np.random.default_rng(64).normal(0, 1, (3, 61, 97))
+    dl[:, ref_img["hazard"] != 0] = 0.0  # no gradient through pixels at a decision boundary
+    dl = dl.astype(np.float32)
+    grads = r.backward(g, [cam], outs, [torch.from_numpy(dl).cuda()], ws, opts)
+    _compare(grads, oracle.backward(sc, cam, opts, dl.astype(np.float64)), "crossing", rel=2e-3)
+
+
 def test_crossing_list_beyond_its_cap_keeps_the_whole_view(r):
     """More crossing quads than the list holds (65536 per launch): every one
     is counted, those beyond the cap keep the whole view (more instances than
