@@ -233,8 +233,8 @@ typedef struct {
     size_t counters;       /* int64[8]: [0] instances needed (tiles of all pixel boxes), [1] capacity,
                               [2] tile rows of all boxes, [3] listed instances (sorted; the rest are
                               empty), [4] kept (not culled) Gaussian-views, [5] quads with a vertex at
-                              z <= 0 (the first 65536 have their box clipped to the view frustum, the
-                              rest keep the whole view) */
+                              z <= 0 (65536 of them, in no fixed order, have their box clipped to the
+                              view frustum; any others keep the whole view) */
     size_t views;          /* per-view device table */
     size_t records;        /* float[16] per Gaussian-view (float[28] with mip = 2), index v * n + i */
     size_t depth_keys;     /* uint32 per Gaussian-view: the kept views' keys, sorted, in [0, counters[4]) */
