@@ -463,10 +463,12 @@ static void box_to_pixels(orc_splat *sp, const orc_camera *cam, double umin, dou
  * the image borders (inside all four, z >= 0).  Returns 1 with the bounding
  * box (umin, umax, vmin, vmax) of the projected clipped polygon, 0 when no
  * part of the quad is inside, -1 when a clipped vertex has z <= 0 (only the
- * camera centre itself can). */
+ * camera centre itself can) or, from rounding alone, the polygon would
+ * outgrow its buffers (a convex quad gains at most one vertex per plane). */
+#define ORC_CLIP_MAX 32
 static int clip_quad_to_view(const double *quad, const orc_camera *cam, double *box)
 {
-    double P[8][3], Q[8][3];
+    double P[ORC_CLIP_MAX][3], Q[ORC_CLIP_MAX][3];
     int n = 4;
     for (int k = 0; k < 4; ++k)
         for (int c = 0; c < 3; ++c) P[k][c] = quad[3 * k + c];
@@ -479,6 +481,7 @@ static int clip_quad_to_view(const double *quad, const orc_camera *cam, double *
         for (int i = 0; i < n; ++i) {
             const double *A = P[i], *B = P[(i + 1) % n];
             double da = dot3(planes[p], A), db = dot3(planes[p], B);
+            if (m + 2 > ORC_CLIP_MAX) return -1;
             if (da >= 0.0) memcpy(Q[m++], A, sizeof(double) * 3);
             if ((da >= 0.0) != (db >= 0.0)) {
                 double t = da / (da - db);
