@@ -20,14 +20,12 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kItemsPerThread = 8;
 constexpr int kTile = kThreads * kItemsPerThread;  // items per block (scans)
 constexpr int kScanSelfPrefixBlocks = 1024;
-// radix sort: items per lane and per workgroup (a smaller tile shortens the
-// serial ranking chain of each workgroup; the digit histograms grow with the
-// number of tiles)
-#ifndef RGS_RADIX_ITEMS
-#define RGS_RADIX_ITEMS 8
-#endif
-constexpr int kRadixItems = RGS_RADIX_ITEMS;
-constexpr int kRadixTile = kThreads * kRadixItems;
+// Radix sort: the keys per thread of a pass (ITEMS: 4, 8 or 16) are chosen
+// per sort from its size.  More keys per workgroup amortise a workgroup's
+// per-digit work on large sorts; fewer give small sorts enough workgroups to
+// fill the CUs and a shorter serial ranking chain.
+constexpr int kRadixItemsMin = 4;
+constexpr int radix_tile(int items) { return kThreads * items; }
 constexpr int kBins = 256;                         // 8-bit digits
 
 // Element count of a device-sized array: a frame whose instance count
@@ -69,7 +67,8 @@ __device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t x, uint32_t *s
 // Digit histogram of one block's items; with `drop`, keys equal to drop_key
 // are left out (they leave the sort in this pass).  Blocks past the
 // device-side count write nothing: the row scan and the scatter only look at
-// the first ceil(n / kRadixTile) blocks.
+// the first ceil(n / (256 ITEMS)) blocks.
+template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restrict__ keys, int64_t n_max,
                                                          const int64_t *__restrict__ n_dev, int shift, int bits,
                                                          bool drop, uint32_t drop_key, uint32_t *__restrict__ hist,
@@ -78,7 +77,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restr
     __shared__ uint32_t cnt[kWaves][kBins];
     const int tid = threadIdx.x, wave = tid >> 6;
     const int64_t n = clamp_count(n_dev, n_max);
-    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    const int64_t base = (int64_t)blockIdx.x * radix_tile(ITEMS);
     if (base >= n) return;  // uniform per block
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) cnt[w][tid] = 0;
@@ -86,7 +85,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restr
     const uint32_t mask = (1u << bits) - 1u;
     {
 #pragma unroll
-        for (int j = 0; j < kRadixItems; ++j) {
+        for (int j = 0; j < ITEMS; ++j) {
             const int64_t idx = base + (int64_t)j * kThreads + tid;
             if (idx < n) {
                 const uint32_t key = keys[idx];
@@ -99,14 +98,14 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restr
 }
 
 // Exclusive scan of each digit's row hist[d][0..nb) (one block per digit)
-// over the nb = ceil(n / kRadixTile) blocks that hold items.
+// over the nb = ceil(n / tile) blocks that hold items (tile = keys per block).
 __global__ __launch_bounds__(kThreads) void k_radix_scan_rows(uint32_t *__restrict__ hist, int nblocks,
                                                               int64_t n_max, const int64_t *__restrict__ n_dev,
-                                                              uint32_t *__restrict__ row_total)
+                                                              int tile, uint32_t *__restrict__ row_total)
 {
     __shared__ uint32_t smem[kWaves];
     const int64_t n = clamp_count(n_dev, n_max);
-    const int nb = (int)std::min<int64_t>((n + kRadixTile - 1) / kRadixTile, nblocks);
+    const int nb = (int)std::min<int64_t>((n + tile - 1) / tile, nblocks);
     uint32_t *row = hist + (size_t)blockIdx.x * nblocks;
     uint32_t carry = 0;
     for (int base = 0; base < nb; base += kThreads) {
@@ -127,6 +126,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scan_rows(uint32_t *__restri
 // LDS in block-local sorted order and written out in runs of equal digits.
 // With `drop`, keys equal to drop_key are not written, and block 0 stores
 // the number of items kept (the sum of the digit totals) in *kept_out.
+template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
     uint32_t *__restrict__ vals_out, int64_t n_max, const int64_t *__restrict__ n_dev, int shift, int bits,
@@ -136,14 +136,14 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     __shared__ uint32_t wave_cnt[kWaves][kBins];
     __shared__ uint32_t block_start[kBins];
     __shared__ uint32_t out_base[kBins];
-    __shared__ uint32_t s_keys[kRadixTile];
-    __shared__ uint32_t s_vals[kRadixTile];
+    __shared__ uint32_t s_keys[radix_tile(ITEMS)];
+    __shared__ uint32_t s_vals[radix_tile(ITEMS)];
     __shared__ uint32_t smem[kWaves];
     __shared__ uint32_t block_valid;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t n = clamp_count(n_dev, n_max);
-    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    const int64_t base = (int64_t)blockIdx.x * radix_tile(ITEMS);
     if (base >= n) {  // uniform per block
         if (drop && blockIdx.x == 0 && tid == 0) *kept_out = 0;
         return;
@@ -159,11 +159,11 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     for (int w = 0; w < kWaves; ++w) wave_cnt[w][tid] = 0;
     __syncthreads();
 
-    uint32_t my_key[kRadixItems], my_val[kRadixItems], my_rank[kRadixItems];
+    uint32_t my_key[ITEMS], my_val[ITEMS], my_rank[ITEMS];
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
 #pragma unroll
-    for (int r = 0; r < kRadixItems; ++r) {
-        const int64_t idx = base + (int64_t)wave * (kRadixTile / kWaves) + r * 64 + lane;
+    for (int r = 0; r < ITEMS; ++r) {
+        const int64_t idx = base + (int64_t)wave * (radix_tile(ITEMS) / kWaves) + r * 64 + lane;
         const uint32_t key = idx < n ? keys_in[idx] : 0u;
         const bool valid = idx < n && !(drop && key == drop_key);
         my_key[r] = key;
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kRadixItems; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
         if (my_rank[r] == 0xffffffffu) continue;
         const uint32_t d = (my_key[r] >> shift) & mask;
         const uint32_t pos = block_start[d] + wave_cnt[wave][d] + my_rank[r];
@@ -590,15 +590,38 @@ __global__ __launch_bounds__(kThreads) void k_sched_scatter(const uint2 *__restr
 
 int radix_passes(int bits) { return bits <= 0 ? 0 : (bits + 7) / 8; }
 
-size_t radix_hist_entries(int64_t n_max) { return (size_t)kBins * (size_t)((n_max + kRadixTile - 1) / kRadixTile + 1); }
+// sized for the smallest tile, so any choice of ITEMS fits
+size_t radix_hist_entries(int64_t n_max)
+{
+    const int64_t tile = radix_tile(kRadixItemsMin);
+    return (size_t)kBins * (size_t)((n_max + tile - 1) / tile + 1);
+}
+
+namespace {
+// Keys per thread by sort size, from timings of the depth and tile sorts of a
+// 1080p frame (0.5M and 2.6M keys) and of an 8-view batch (24M and 91M).
+int radix_items_for(int64_t n_max) { return n_max <= (int64_t(1) << 20) ? 4 : n_max <= (int64_t(1) << 24) ? 8 : 16; }
+
+template <int ITEMS>
+void radix_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, int64_t n_max,
+                const int64_t *pn, int shift, int pbits, bool pdrop, uint32_t drop_key, int64_t *kept_out,
+                uint32_t *hist, uint32_t *row_total, hipStream_t stream)
+{
+    const int nblocks = (int)((n_max + radix_tile(ITEMS) - 1) / radix_tile(ITEMS));
+    k_radix_hist<ITEMS><<<nblocks, kThreads, 0, stream>>>(ki, n_max, pn, shift, pbits, pdrop, drop_key, hist, nblocks);
+    k_radix_scan_rows<<<kBins, kThreads, 0, stream>>>(hist, nblocks, n_max, pn, radix_tile(ITEMS), row_total);
+    k_radix_scatter<ITEMS><<<nblocks, kThreads, 0, stream>>>(ki, vi, ko, vo, n_max, pn, shift, pbits, pdrop, drop_key,
+                                                             kept_out, hist, row_total, nblocks);
+}
+}  // namespace
 
 hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt, int64_t n_max,
                       const int64_t *n_dev, int bits, bool drop, uint32_t drop_key, int64_t *kept_out,
                       uint32_t *hist, uint32_t *row_total, hipStream_t stream)
 {
-    const int nblocks = (int)((n_max + kRadixTile - 1) / kRadixTile);
     const int passes = radix_passes(bits);
-    if (nblocks == 0 || passes == 0) {
+    const int items = radix_items_for(n_max);
+    if (n_max <= 0 || passes == 0) {
         if (drop) k_fill_u32<<<1, kThreads, 0, stream>>>(reinterpret_cast<uint32_t *>(kept_out), 0u, 2);
         return hipGetLastError();
     }
@@ -610,10 +633,12 @@ hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32
         const int pbits = (bits - shift + (passes - p) - 1) / (passes - p);
         const bool pdrop = drop && p == 0;
         const int64_t *pn = drop && p > 0 ? kept_out : n_dev;
-        k_radix_hist<<<nblocks, kThreads, 0, stream>>>(ki, n_max, pn, shift, pbits, pdrop, drop_key, hist, nblocks);
-        k_radix_scan_rows<<<kBins, kThreads, 0, stream>>>(hist, nblocks, n_max, pn, row_total);
-        k_radix_scatter<<<nblocks, kThreads, 0, stream>>>(ki, vi, ko, vo, n_max, pn, shift, pbits, pdrop, drop_key,
-                                                          kept_out, hist, row_total, nblocks);
+        if (items == 4)
+            radix_pass<4>(ki, vi, ko, vo, n_max, pn, shift, pbits, pdrop, drop_key, kept_out, hist, row_total, stream);
+        else if (items == 8)
+            radix_pass<8>(ki, vi, ko, vo, n_max, pn, shift, pbits, pdrop, drop_key, kept_out, hist, row_total, stream);
+        else
+            radix_pass<16>(ki, vi, ko, vo, n_max, pn, shift, pbits, pdrop, drop_key, kept_out, hist, row_total, stream);
         shift += pbits;
         uint32_t *t;
         t = ki; ki = ko; ko = t;
