@@ -17,8 +17,10 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kItemsPerThread = 8;
-constexpr int kTile = kThreads * kItemsPerThread;  // items per block (scans)
+// Binning scan: items per thread (4 or 8) chosen from the item count, as for
+// the radix passes below.
+constexpr int kScanItemsMin = 4;
+constexpr int scan_tile(int items) { return kThreads * items; }
 constexpr int kScanSelfPrefixBlocks = 1024;
 // Radix sort: the keys per thread of a pass (ITEMS: 4, 8 or 16) are chosen
 // per sort from its size.  More keys per workgroup amortise a workgroup's
@@ -242,6 +244,7 @@ __device__ __forceinline__ void scan_item(const uint32_t *__restrict__ keys, con
 
 // Gathers each sorted item's two counts once (into `tiles` and `rows`, read
 // back by k_scan_apply, which scans them in place) and reduces them per block.
+template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__restrict__ keys,
                                                           const uint2 *__restrict__ boxes,
                                                           const uint32_t *__restrict__ order, int64_t n_max,
@@ -251,10 +254,10 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__rest
 {
     const int64_t n = clamp_count(n_dev, n_max);
     __shared__ unsigned long long part[2][kWaves];
-    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int64_t base = (int64_t)blockIdx.x * scan_tile(ITEMS);
     unsigned long long at = 0, ar = 0;
 #pragma unroll
-    for (int j = 0; j < kItemsPerThread; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const int64_t idx = base + (int64_t)j * kThreads + threadIdx.x;
         if (idx < n) {
             uint32_t t, r;
@@ -365,6 +368,7 @@ __device__ void block_prefix_pairs(const unsigned long long *__restrict__ block_
 // writes the totals to counters[0] and counters[2], and k_scan_top is not
 // launched.  Otherwise k_scan_top has turned block_sums into exclusive
 // prefixes and written the totals.
+template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void k_scan_apply(int64_t n_max, const int64_t *__restrict__ n_dev,
                                                          int64_t capacity,
                                                          const unsigned long long *__restrict__ block_sums,
@@ -373,21 +377,24 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(int64_t n_max, const in
                                                          uint32_t *__restrict__ row_offsets,
                                                          uint32_t *__restrict__ row_owner)
 {
-    static_assert(kItemsPerThread == 8, "two 16-byte loads per thread");
+    static_assert(ITEMS % 4 == 0, "whole 16-byte loads per thread");
     __shared__ uint32_t smem[kWaves];
     const int64_t n = clamp_count(n_dev, n_max);
-    // blocked arrangement: thread t owns items base + t*8 .. +7 (32 aligned bytes)
-    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItemsPerThread;
-    uint32_t c[kItemsPerThread], r[kItemsPerThread];
-    if (base + kItemsPerThread <= n) {
+    // blocked arrangement: thread t owns items base + t*ITEMS .. (aligned 16-byte groups)
+    const int64_t base = (int64_t)blockIdx.x * scan_tile(ITEMS) + (int64_t)threadIdx.x * ITEMS;
+    uint32_t c[ITEMS], r[ITEMS];
+    if (base + ITEMS <= n) {
         const uint4 *pc = reinterpret_cast<const uint4 *>(offsets + base);
         const uint4 *pr = reinterpret_cast<const uint4 *>(row_offsets + base);
-        const uint4 c0 = pc[0], c1 = pc[1], r0 = pr[0], r1 = pr[1];
-        c[0] = c0.x; c[1] = c0.y; c[2] = c0.z; c[3] = c0.w; c[4] = c1.x; c[5] = c1.y; c[6] = c1.z; c[7] = c1.w;
-        r[0] = r0.x; r[1] = r0.y; r[2] = r0.z; r[3] = r0.w; r[4] = r1.x; r[5] = r1.y; r[6] = r1.z; r[7] = r1.w;
+#pragma unroll
+        for (int v = 0; v < ITEMS / 4; ++v) {
+            const uint4 cv = pc[v], rv = pr[v];
+            c[4 * v] = cv.x; c[4 * v + 1] = cv.y; c[4 * v + 2] = cv.z; c[4 * v + 3] = cv.w;
+            r[4 * v] = rv.x; r[4 * v + 1] = rv.y; r[4 * v + 2] = rv.z; r[4 * v + 3] = rv.w;
+        }
     } else {
 #pragma unroll
-        for (int j = 0; j < kItemsPerThread; ++j) {
+        for (int j = 0; j < ITEMS; ++j) {
             const bool in = base + j < n;
             c[j] = in ? offsets[base + j] : 0u;
             r[j] = in ? row_offsets[base + j] : 0u;
@@ -395,7 +402,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(int64_t n_max, const in
     }
     uint32_t lt = 0, lr = 0;
 #pragma unroll
-    for (int j = 0; j < kItemsPerThread; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         lt += c[j];
         lr += r[j];
     }
@@ -418,7 +425,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(int64_t n_max, const in
     unsigned long long rt = pre[0] + bt;
     unsigned long long rr = pre[1] + br;
 #pragma unroll
-    for (int j = 0; j < kItemsPerThread; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const int64_t idx = base + j;
         if (idx < n) {
             offsets[idx] = rt > 0xffffffffull ? 0xffffffffu : (uint32_t)rt;
@@ -647,28 +654,48 @@ hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32
     return hipGetLastError();
 }
 
-size_t scan_block_entries(int64_t n) { return 2 * (size_t)((n + kTile - 1) / kTile + 1); }
+// sized for the smallest tile, so either choice of items per thread fits
+size_t scan_block_entries(int64_t n)
+{
+    const int64_t tile = scan_tile(kScanItemsMin);
+    return 2 * (size_t)((n + tile - 1) / tile + 1);
+}
+
+namespace {
+template <int ITEMS>
+void scan_launch(const uint32_t *keys, const uint2 *boxes, const uint32_t *order, int64_t n, const int64_t *n_dev,
+                 int tile_w, int tile_h, int64_t capacity, uint32_t *offsets, uint32_t *row_offsets,
+                 uint32_t *row_owner, unsigned long long *block_sums, int64_t *counters, hipStream_t stream)
+{
+    const int nb = (int)((n + scan_tile(ITEMS) - 1) / scan_tile(ITEMS));
+    k_scan_reduce<ITEMS><<<nb, kThreads, 0, stream>>>(keys, boxes, order, n, n_dev, tile_w, tile_h, offsets,
+                                                      row_offsets, block_sums);
+    // up to kScanSelfPrefixBlocks blocks, each apply block sums the block
+    // pairs before it (at most that many loads) instead of a separate scan
+    const bool self_prefix = nb <= kScanSelfPrefixBlocks;
+    if (!self_prefix) k_scan_top<<<1, 1024, 0, stream>>>(block_sums, nb, counters);
+    k_scan_apply<ITEMS><<<nb, kThreads, 0, stream>>>(n, n_dev, capacity, block_sums, counters, self_prefix, offsets,
+                                                     row_offsets, row_owner);
+}
+}  // namespace
 
 hipError_t binning_scan(const uint32_t *keys, const uint2 *boxes, const uint32_t *order, int64_t n,
                         const int64_t *n_dev, int tile_w, int tile_h, int64_t capacity, uint32_t *offsets,
                         uint32_t *row_offsets, uint32_t *row_owner, unsigned long long *block_sums,
                         int64_t *counters, hipStream_t stream)
 {
-    const int nb = (int)((n + kTile - 1) / kTile);
-    if (nb == 0) {
+    if (n <= 0) {
         // counters[0] and counters[2] (int64) = 0, counters[1] (capacity) kept
         k_fill_u32<<<1, kThreads, 0, stream>>>(reinterpret_cast<uint32_t *>(counters), 0u, 2);
         k_fill_u32<<<1, kThreads, 0, stream>>>(reinterpret_cast<uint32_t *>(counters + 2), 0u, 2);
         return hipGetLastError();
     }
-    k_scan_reduce<<<nb, kThreads, 0, stream>>>(keys, boxes, order, n, n_dev, tile_w, tile_h, offsets, row_offsets,
-                                               block_sums);
-    // up to kScanSelfPrefixBlocks blocks, each apply block sums the block
-    // pairs before it (at most that many loads) instead of a separate scan
-    const bool self_prefix = nb <= kScanSelfPrefixBlocks;
-    if (!self_prefix) k_scan_top<<<1, 1024, 0, stream>>>(block_sums, nb, counters);
-    k_scan_apply<<<nb, kThreads, 0, stream>>>(n, n_dev, capacity, block_sums, counters, self_prefix, offsets,
-                                              row_offsets, row_owner);
+    if (n <= (int64_t(1) << 20))
+        scan_launch<4>(keys, boxes, order, n, n_dev, tile_w, tile_h, capacity, offsets, row_offsets, row_owner,
+                       block_sums, counters, stream);
+    else
+        scan_launch<8>(keys, boxes, order, n, n_dev, tile_w, tile_h, capacity, offsets, row_offsets, row_owner,
+                       block_sums, counters, stream);
     return hipGetLastError();
 }
 
