@@ -9,6 +9,7 @@ from .oracle import (  # noqa: F401
     preprocess,
     render,
     render_pixels,
+    support_rows,
     backward,
     tile_lists,
     sh_basis,

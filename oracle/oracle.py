@@ -73,7 +73,8 @@ def load():
         P = C.c_void_p
         lib.orc_preprocess.argtypes = [P, P, P, P, C.c_int]
         lib.orc_render.argtypes = [P, P, P, C.c_int, C.c_int, C.c_int, P, P, P, P, P]
-        lib.orc_render_pixels.argtypes = [P, P, P, P, P, C.c_int64, C.c_int, P, P, P]
+        lib.orc_render_pixels.argtypes = [P, P, P, P, P, C.c_int64, C.c_int, P, P, P, P, P, C.c_int]
+        lib.orc_support_rows.argtypes = [P, P, P, C.c_int32, P, P, C.c_int64, P, C.c_int]
         lib.orc_backward.argtypes = [P, P, P, P, P, P, P, P, P]
         lib.orc_sh_basis.argtypes = [C.c_int, P, P, P]
         lib.orc_divergence.argtypes = [P, P, P, P, P, P]
@@ -139,9 +140,15 @@ def preprocess(scene, cam, opts, threads=None):
     return out
 
 
-def render(scene, cam, opts, rows=None, threads=None):
+# Most correct results kept per pixel (combinations of decisions taken within
+# rounding distance, see walk_pixel in raygs_oracle.c).
+MAX_LEAVES = 64
+
+
+def render(scene, cam, opts, rows=None, threads=None, branches=True):
     """Full view (or rows [a, b)): dict(rgb [3][H][W], T [H][W], hazard [H][W],
-    n_contrib [H][W], counters)."""
+    n_contrib [H][W], counters) and, with `branches`, branches = dict(px, py,
+    leaves): every correct result of each hazard pixel (see render_pixels)."""
     lib = load()
     s = _SceneF64(scene)
     H, W = int(cam["height"]), int(cam["width"])
@@ -154,13 +161,23 @@ def render(scene, cam, opts, rows=None, threads=None):
     c, o = _camera(cam), _options(opts)
     lib.orc_render(C.byref(s.struct), C.byref(c), C.byref(o), int(a), int(b), _threads(threads), _ptr(rgb), _ptr(T),
                    _ptr(hz), _ptr(nc), _ptr(cnt))
-    return dict(rgb=rgb, T=T, hazard=hz, n_contrib=nc,
-                counters=dict(visible=int(cnt[0]), instances=int(cnt[1]), fragments=int(cnt[2]),
-                              box_pairs=int(cnt[3]), contributions=int(cnt[4])))
+    out = dict(rgb=rgb, T=T, hazard=hz, n_contrib=nc,
+               counters=dict(visible=int(cnt[0]), instances=int(cnt[1]), fragments=int(cnt[2]),
+                             box_pairs=int(cnt[3]), contributions=int(cnt[4])))
+    if branches:
+        py, px = np.nonzero(hz)
+        leaves = render_pixels(scene, cam, opts, px, py, threads)["leaves"] if len(px) else []
+        out["branches"] = dict(px=px, py=py, leaves=leaves)
+    return out
 
 
 def render_pixels(scene, cam, opts, px, py, threads=None):
-    """Selected pixels: (rgb [K][3], T [K], hazard [K])."""
+    """Selected pixels: dict(rgb [K][3], T [K], hazard [K], leaves).  leaves[k]
+    is an array [n_k][4] of (r, g, b, T): every correct result of pixel k,
+    i.e. the result of every combination of outcomes of the decisions taken
+    within rounding distance (omega vs p_min, the termination test, the sign
+    of tau), the computed one first; n_k = 1 for a pixel without hazard.  A
+    pixel with more than MAX_LEAVES such results gets None."""
     lib = load()
     s = _SceneF64(scene)
     px = np.ascontiguousarray(px, np.int32)
@@ -169,10 +186,30 @@ def render_pixels(scene, cam, opts, px, py, threads=None):
     rgb = np.zeros((k, 3))
     T = np.zeros(k)
     hz = np.zeros(k, np.uint8)
+    lv = np.zeros((max(k, 1), MAX_LEAVES, 4))
+    nl = np.zeros(max(k, 1), np.int32)
     c, o = _camera(cam), _options(opts)
     lib.orc_render_pixels(C.byref(s.struct), C.byref(c), C.byref(o), _ptr(px), _ptr(py), k, _threads(threads),
-                          _ptr(rgb), _ptr(T), _ptr(hz))
-    return rgb, T, hz
+                          _ptr(rgb), _ptr(T), _ptr(hz), _ptr(lv), _ptr(nl), MAX_LEAVES)
+    leaves = [lv[i, :nl[i]].copy() if nl[i] > 0 else None for i in range(k)]
+    return dict(rgb=rgb, T=T, hazard=hz, leaves=leaves)
+
+
+def support_rows(splats, cam, opts, tiles, ids, threads=None):
+    """For each (tile, Gaussian index) pair of one view, the bit mask of the
+    tile's pixel rows (bit r = row ty * tile_h + r) that hold a pixel centre of
+    the Gaussian's support: inside its pixel box, omega >= p_min and tau > 0,
+    both clear of their rounding margins."""
+    lib = load()
+    sp = np.ascontiguousarray(splats)
+    tiles = np.ascontiguousarray(tiles, np.int64)
+    ids = np.ascontiguousarray(ids, np.int64)
+    rows = np.zeros(max(len(tiles), 1), np.uint32)
+    tiles_x = -(-int(cam["width"]) // int(opts["tile_w"]))
+    c, o = _camera(cam), _options(opts)
+    lib.orc_support_rows(_ptr(sp), C.byref(c), C.byref(o), tiles_x, _ptr(tiles), _ptr(ids), len(tiles), _ptr(rows),
+                         _threads(threads))
+    return rows[:len(tiles)]
 
 
 def backward(scene, cam, opts, dL_dC):
@@ -191,8 +228,8 @@ def backward(scene, cam, opts, dL_dC):
 
 def tile_lists(splats, cam, opts, tile_base=0):
     """Tile binning by definition: for every visible Gaussian and every listed
-    tile (a row band of the tile meets the support ellipse, see
-    raygs_oracle.c), the pair (tile id, Gaussian index), ordered by
+    tile (the rectangle of the tile's pixel centres inside the Gaussian's pixel
+    box meets the support ellipse, see raygs_oracle.c), the pair (tile id, Gaussian index), ordered by
     (tile, depth key, Gaussian index).  Returns (tile ids int64, depth keys
     uint32, Gaussian indices int64)."""
     lib = load()

@@ -358,10 +358,11 @@ static int depth_key_hazard(double z, double tol)
  * (eqs. 3, 5), a conic [p;1]^T C [p;1] <= 0 with
  * C = K^-T ((c^2 - kappa) Sigma^-1 - Sigma^-1 mu mu^T Sigma^-1) K^-1.  When its
  * 2x2 block is positive definite the region is one ellipse around pi(mu).  A
- * tile is listed when, for one of its row bands (64 / tile_w rows), the
- * rectangle spanned by the band's pixel centres inside the Gaussian's pixel
- * box meets that ellipse (every tile of the box when it is unbounded); a tile
- * that would have more than 4 such bands is tested as one band. */
+ * tile is listed when the rectangle spanned by its pixel centres inside the
+ * Gaussian's pixel box meets that ellipse (every tile of the box when the
+ * region is unbounded): every pixel centre of the support then lies in a
+ * listed tile (Sec. 4.1 bounds the support; this only drops tiles of the
+ * box that no part of it reaches). */
 static void support_conic(orc_splat *sp, const orc_camera *cam)
 {
     double Sinv[9], tmp[9], Lam[9] = {0};
@@ -414,30 +415,22 @@ static double conic_rect_min(const double *q, int x0, int x1, int y0, int y1)
     return best;
 }
 
-/* Is tile (tx, ty) listed for splat sp?  Flags a hazard when a decision is
+/* Is tile (tx, ty) listed for splat sp?  Flags a hazard when the decision is
  * within rounding of the boundary. */
 static int tile_listed(orc_splat *sp, const orc_options *opt, int tx, int ty)
 {
-    /* bands of 64 / tile_w rows, or the whole tile when that makes more than 4 */
-    int TW = opt->tile_w, TH = opt->tile_h, LY = 64 / TW;
-    if (TH / LY > 4) LY = TH;
+    int TW = opt->tile_w, TH = opt->tile_h;
     int cx0 = tx * TW > sp->px0 ? tx * TW : sp->px0;
     int cx1 = tx * TW + TW - 1 < sp->px1 ? tx * TW + TW - 1 : sp->px1;
-    if (cx0 > cx1) return 0;
+    int cy0 = ty * TH > sp->py0 ? ty * TH : sp->py0;
+    int cy1 = ty * TH + TH - 1 < sp->py1 ? ty * TH + TH - 1 : sp->py1;
+    if (cx0 > cx1 || cy0 > cy1) return 0;
     if (!sp->bounded) return 1;
     /* scale: |conic| at the projected centre = kappa c^2 / mu_z^2 (kappa for D_gs) */
     double scale = sp->gs ? sp->kappa : sp->kappa * sp->c2 / (sp->mu[2] * sp->mu[2]);
-    int listed = 0;
-    for (int b = 0; b < TH / LY; ++b) {
-        int r0 = ty * TH + b * LY, r1 = r0 + LY - 1;
-        if (r0 < sp->py0) r0 = sp->py0;
-        if (r1 > sp->py1) r1 = sp->py1;
-        if (r0 > r1) continue;
-        double m = conic_rect_min(sp->cq, cx0, cx1, r0, r1);
-        if (fabs(m) <= 1e-9 * scale) sp->hazard |= ORC_HZ_RECT;
-        if (m <= 0.0) listed = 1;
-    }
-    return listed;
+    double m = conic_rect_min(sp->cq, cx0, cx1, cy0, cy1);
+    if (fabs(m) <= 1e-9 * scale) sp->hazard |= ORC_HZ_RECT;
+    return m <= 0.0;
 }
 
 /* Pixel centres inside the bounding box [umin, umax] x [vmin, vmax] (pixel x
@@ -958,9 +951,97 @@ static int ray_hits_quad(const orc_splat *s, const double *x)
     return fabs(z0) <= hs && fabs(z1) <= hs;
 }
 
-/* Margins (relative) inside which a threshold decision is reported as a hazard. */
+/* Margins inside which a per-pixel decision is taken within rounding distance
+ * of the renderer's FP32 arithmetic (a hazard); both outcomes are then
+ * correct results (several results are correct there):
+ *   omega >= p_min: |ln omega - ln p_min| < 1e-4.  The FP32 divergence carries
+ *     a relative error of order 1e-6 of D (about 11 at the threshold), i.e.
+ *     about 6e-6 in ln omega; the margin leaves a factor of about 15;
+ *   termination T' < t_eps: |ln T' - ln t_eps| < 1e-3.  ln T' sums ln(1 - a)
+ *     over every contribution, each off by a / (1 - a) times the relative
+ *     error of omega (up to 100 times it below the clamp);
+ *   tau > 0 (Prop. A.3): the cosine between the whitened ray and the whitened
+ *     centre within 1e-5 of zero. */
 #define ORC_MARGIN_OMEGA 1e-4
 #define ORC_MARGIN_T 1e-3
+#define ORC_MARGIN_TAU 1e-5
+
+/* cosine between S^-1 R_p^T x and S^-1 R_p^T mu (its sign is that of tau) */
+static double front_cosine(const double *mu, const double *Rp, const double *s, const double *x)
+{
+    double xl[3], ml[3], xw[3], mw[3];
+    mat3t_vec(Rp, x, xl);
+    mat3t_vec(Rp, mu, ml);
+    for (int k = 0; k < 3; ++k) {
+        xw[k] = xl[k] / s[k];
+        mw[k] = ml[k] / s[k];
+    }
+    return dot3(xw, mw) / sqrt(dot3(xw, xw) * dot3(mw, mw));
+}
+
+/* Rendered opacity of splat s on the ray x through pixel (px, py): omega of
+ * eq. (2) with D_ray (eq. 5), D_gs (Sec. 3.1) or the exact MIP weight.
+ * *front: the peak of the density along the ray lies in front of the camera
+ * (tau > 0; always for D_gs); *front_hz: that sign is within ORC_MARGIN_TAU. */
+static double pixel_weight(const orc_splat *s, int px, int py, const double *x, int *front, int *front_hz)
+{
+    double tau;
+    if (s->gs) {
+        double du = px + 0.5 - s->gs_c[0], dv = py + 0.5 - s->gs_c[1];
+        double D = s->gs_A[0] * du * du + 2.0 * s->gs_A[1] * du * dv + s->gs_A[2] * dv * dv;
+        *front = 1;
+        *front_hz = 0;
+        return s->o * exp(-0.5 * D);
+    }
+    double w, cosv;
+    if (s->exact) {
+        w = orc_mip_exact_weight(s->mu, s->Rp, s->s0, s->o, s->sig2, x, &tau);
+        /* the peak of the widened density: its scales are those of the ray */
+        double nx = sqrt(dot3(x, x)), t0, sh[3];
+        orc_divergence(s->mu, s->Rp, s->s0, x, &t0, NULL);
+        double a = s->sig2 / (nx * nx * nx) * (t0 * nx) * (t0 * nx);
+        for (int k = 0; k < 3; ++k) sh[k] = sqrt(s->s0[k] * s->s0[k] + a);
+        cosv = front_cosine(s->mu, s->Rp, sh, x);
+    } else {
+        double D = orc_divergence(s->mu, s->Rp, s->s, x, &tau, NULL);
+        w = s->o * exp(-0.5 * D);
+        cosv = front_cosine(s->mu, s->Rp, s->s, x);
+    }
+    *front = tau > 0.0;
+    *front_hz = fabs(cosv) < ORC_MARGIN_TAU;
+    return w;
+}
+
+/* Outcomes of one list entry at a pixel (eqs. 1-2 with the readings of the
+ * file header): skipped (no contribution), taken, or the stop before it. */
+enum { OUT_SKIP = 1, OUT_TAKE = 2, OUT_STOP = 4 };
+
+/* The set of outcomes of entry s at transmittance T that are correct within
+ * the margins (bits OUT_*); *natural receives the outcome of the decisions
+ * as computed and *alpha the clamped opacity. */
+static int entry_outcomes(const orc_splat *s, int px, int py, const double *x, const orc_options *opt, double T,
+                          int *natural, double *alpha)
+{
+    int front, front_hz;
+    double w = pixel_weight(s, px, py, x, &front, &front_hz);
+    int pass = w >= opt->p_min;
+    int pass_hz = fabs(log(w / opt->p_min)) < ORC_MARGIN_OMEGA;
+    int can_contrib = (front || front_hz) && (pass || pass_hz);
+    int can_skip = !front || front_hz || !pass || pass_hz;
+    double a = w < opt->alpha_max ? w : opt->alpha_max;
+    int set = can_skip ? OUT_SKIP : 0;
+    *natural = OUT_SKIP;
+    *alpha = a;
+    if (can_contrib) {
+        double Tn = T * (1.0 - a);
+        int stop = Tn < opt->t_eps;
+        int stop_hz = fabs(log(Tn / opt->t_eps)) < ORC_MARGIN_T;
+        set |= stop ? OUT_STOP : OUT_TAKE;
+        if (stop_hz) set |= stop ? OUT_TAKE : OUT_STOP;
+        if (front && pass) *natural = stop ? OUT_STOP : OUT_TAKE;
+    }
+    return set;
+}
 
 typedef struct {
     double rgb[3], T;
@@ -969,52 +1050,95 @@ typedef struct {
     int64_t fragments, in_box, contributions;
 } pixel_result;
 
-/* Composite one pixel (eqs. 1-2) over the candidate list `cand[0..nc)`. */
-static void shade_pixel(const orc_splat *sp, const int64_t *cand, int64_t nc, int px, int py, const orc_camera *cam,
-                        const orc_options *opt, pixel_result *res)
+typedef struct {
+    int64_t k;      /* list position whose outcome is forced */
+    double T, C[3];
+    int32_t entry, last;
+    int32_t outcome;
+} walk_state;
+
+#define ORC_WALK_STACK 64
+
+/* Composite one pixel (eqs. 1-2) over the candidate list cand[0..nc) in
+ * depth order; an entry counts when the pixel lies in its box.  *res gets the
+ * result of the decisions as computed, with res->hazard = 1 when any of them
+ * on its path lies within its margin.  With leaves != NULL every combination
+ * of the outcomes of such decisions is followed as well, and the pixel values
+ * (r, g, b, T) of every path are written to leaves[0..) (leaves[0] is the
+ * computed one), at most cap of them; returns their number, or -1 when there
+ * are more. */
+static int walk_pixel(const orc_splat *sp, const int64_t *cand, int64_t nc, int px, int py, const orc_camera *cam,
+                      const orc_options *opt, pixel_result *res, double *leaves, int cap)
 {
-    double x[3] = {(px + 0.5 - cam->cx) / cam->fx, (py + 0.5 - cam->cy) / cam->fy, 1.0};
-    double T = 1.0, C[3] = {0, 0, 0};
-    int32_t last = 0, hz = 0;
+    const double x[3] = {(px + 0.5 - cam->cx) / cam->fx, (py + 0.5 - cam->cy) / cam->fy, 1.0};
+    walk_state stack[ORC_WALK_STACK];
+    int top = 0, n_leaves = 0, overflow = 0, primary = 1;
+    walk_state st = {0, 1.0, {0.0, 0.0, 0.0}, 0, 0, 0};
     int64_t frags = 0, inbox = 0, contrib = 0;
-    int32_t entry = 0;
-    for (int64_t k = 0; k < nc; ++k) {
-        const orc_splat *s = &sp[cand[k]];
-        if (px < s->px0 || px > s->px1 || py < s->py0 || py > s->py1) continue;
-        ++entry;
-        ++inbox;
-        frags += ray_hits_quad(s, x);
-        double tau, w;
-        if (s->gs) {
-            double du = px + 0.5 - s->gs_c[0], dv = py + 0.5 - s->gs_c[1];
-            double D = s->gs_A[0] * du * du + 2.0 * s->gs_A[1] * du * dv + s->gs_A[2] * dv * dv;
-            w = s->o * exp(-0.5 * D);
-            tau = 1.0;
-        } else if (s->exact) {
-            w = orc_mip_exact_weight(s->mu, s->Rp, s->s0, s->o, s->sig2, x, &tau);
-        } else {
-            double D = orc_divergence(s->mu, s->Rp, s->s, x, &tau, NULL);
-            w = s->o * exp(-0.5 * D);
+    int32_t hz = 0;
+    for (;;) {
+        int64_t k = st.k;
+        double T = st.T, C[3] = {st.C[0], st.C[1], st.C[2]};
+        int32_t entry = st.entry, last = st.last;
+        int forced = st.outcome;
+        for (; k < nc; ++k) {
+            const orc_splat *s = &sp[cand[k]];
+            if (px < s->px0 || px > s->px1 || py < s->py0 || py > s->py1) continue;
+            int natural, outcome;
+            double a;
+            int set = entry_outcomes(s, px, py, x, opt, T, &natural, &a);
+            if (forced) {
+                outcome = forced; /* entry k was counted when this state was saved */
+                forced = 0;
+            } else {
+                ++entry;
+                if (primary) {
+                    ++inbox;
+                    frags += ray_hits_quad(s, x);
+                }
+                if (set != natural) {
+                    if (primary) hz = 1;
+                    for (int o = OUT_SKIP; leaves && o <= OUT_STOP; o <<= 1) {
+                        if (!(set & o) || o == natural) continue;
+                        if (top == ORC_WALK_STACK) {
+                            overflow = 1;
+                            continue;
+                        }
+                        stack[top++] = (walk_state){k, T, {C[0], C[1], C[2]}, entry, last, o};
+                    }
+                }
+                outcome = natural;
+            }
+            if (outcome == OUT_STOP) break;
+            if (outcome == OUT_TAKE) {
+                for (int ch = 0; ch < 3; ++ch) C[ch] += T * a * s->rgb[ch];
+                T = T * (1.0 - a);
+                last = entry;
+                if (primary) ++contrib;
+            }
         }
-        if (!(tau > 0.0)) continue; /* peak density behind the camera */
-        if (fabs(log(w / opt->p_min)) < ORC_MARGIN_OMEGA) hz = 1;
-        if (!(w >= opt->p_min)) continue;
-        double a = w < opt->alpha_max ? w : opt->alpha_max;
-        double Tn = T * (1.0 - a);
-        if (fabs(log(Tn / opt->t_eps)) < ORC_MARGIN_T) hz = 1;
-        if (Tn < opt->t_eps) break;
-        for (int ch = 0; ch < 3; ++ch) C[ch] += T * a * s->rgb[ch];
-        T = Tn;
-        last = entry;
-        ++contrib;
+        double out[4];
+        for (int ch = 0; ch < 3; ++ch) out[ch] = C[ch] + T * opt->background[ch];
+        out[3] = T;
+        if (primary) {
+            for (int ch = 0; ch < 3; ++ch) res->rgb[ch] = out[ch];
+            res->T = T;
+            res->n_contrib = last;
+            res->hazard = hz;
+            res->fragments = frags;
+            res->in_box = inbox;
+            res->contributions = contrib;
+            primary = 0;
+        }
+        if (!leaves) break;
+        if (n_leaves < cap)
+            memcpy(leaves + 4 * n_leaves++, out, sizeof out);
+        else
+            overflow = 1;
+        if (top == 0) break;
+        st = stack[--top];
     }
-    for (int ch = 0; ch < 3; ++ch) res->rgb[ch] = C[ch] + T * opt->background[ch];
-    res->T = T;
-    res->n_contrib = last;
-    res->hazard = hz;
-    res->fragments = frags;
-    res->in_box = inbox;
-    res->contributions = contrib;
+    return leaves ? (overflow ? -1 : n_leaves) : 1;
 }
 
 typedef struct {
@@ -1038,7 +1162,7 @@ static void *render_worker(void *arg)
         int64_t nc = j->rl->start[y + 1] - j->rl->start[y];
         for (int x = 0; x < W; ++x) {
             pixel_result r;
-            shade_pixel(j->sp, cand, nc, x, y, j->cam, j->opt, &r);
+            walk_pixel(j->sp, cand, nc, x, y, j->cam, j->opt, &r, NULL, 0);
             int64_t p = (int64_t)y * W + x;
             for (int ch = 0; ch < 3; ++ch) j->rgb[(int64_t)ch * H * W + p] = r.rgb[ch];
             j->T[p] = r.T;
@@ -1098,24 +1222,144 @@ int orc_render(const orc_scene *sc, const orc_camera *cam, const orc_options *op
     return 0;
 }
 
-/* Render an arbitrary list of pixels (px[k], py[k]); rgb is [npix][3]. */
-int orc_render_pixels(const orc_scene *sc, const orc_camera *cam, const orc_options *opt, const int32_t *px,
-                      const int32_t *py, int64_t npix, int nthreads, double *rgb, double *T, uint8_t *hazard)
+typedef struct {
+    const orc_splat *sp;
+    const row_lists *rl;
+    const orc_camera *cam;
+    const orc_options *opt;
+    const int32_t *px, *py;
+    int64_t begin, end;
+    double *rgb, *T;
+    uint8_t *hazard;
+    double *leaves;
+    int32_t *n_leaves;
+    int cap;
+} pixels_job;
+
+static void *pixels_worker(void *arg)
 {
+    pixels_job *j = (pixels_job *)arg;
+    for (int64_t k = j->begin; k < j->end; ++k) {
+        int x = j->px[k], y = j->py[k];
+        pixel_result r;
+        double *lv = j->leaves ? j->leaves + 4 * (int64_t)j->cap * k : NULL;
+        int nl = 0;
+        if (x >= 0 && x < j->cam->width && y >= 0 && y < j->cam->height) {
+            const int64_t *cand = j->rl->items + j->rl->start[y];
+            nl = walk_pixel(j->sp, cand, j->rl->start[y + 1] - j->rl->start[y], x, y, j->cam, j->opt, &r, lv, j->cap);
+        } else {
+            memset(&r, 0, sizeof r);
+            r.T = 1.0;
+            for (int ch = 0; ch < 3; ++ch) r.rgb[ch] = j->opt->background[ch];
+        }
+        for (int ch = 0; ch < 3; ++ch) j->rgb[3 * k + ch] = r.rgb[ch];
+        j->T[k] = r.T;
+        if (j->hazard) j->hazard[k] = (uint8_t)r.hazard;
+        if (j->n_leaves) j->n_leaves[k] = nl;
+    }
+    return NULL;
+}
+
+/* Render an arbitrary list of pixels (px[k], py[k]); rgb is [npix][3], T and
+ * hazard [npix].  With leaves != NULL (npix x cap x 4 doubles) and n_leaves
+ * (npix int32), every correct result of each pixel (all combinations of the
+ * outcomes of decisions within their margins, see walk_pixel) is written too:
+ * leaves[k][0..n_leaves[k]) as (r, g, b, T), the computed result first;
+ * n_leaves[k] = -1 when a pixel has more than cap. */
+int orc_render_pixels(const orc_scene *sc, const orc_camera *cam, const orc_options *opt, const int32_t *px,
+                      const int32_t *py, int64_t npix, int nthreads, double *rgb, double *T, uint8_t *hazard,
+                      double *leaves, int32_t *n_leaves, int cap)
+{
+    nthreads = clamp_threads(nthreads);
     int64_t n = sc->n;
     orc_splat *sp = (orc_splat *)malloc(sizeof(orc_splat) * (n ? n : 1));
     orc_preprocess(sc, cam, opt, sp, nthreads);
     int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (n ? n : 1));
     int64_t m = depth_order(sp, n, order);
-    for (int64_t k = 0; k < npix; ++k) {
-        pixel_result r;
-        shade_pixel(sp, order, m, px[k], py[k], cam, opt, &r);
-        for (int ch = 0; ch < 3; ++ch) rgb[3 * k + ch] = r.rgb[ch];
-        T[k] = r.T;
-        if (hazard) hazard[k] = (uint8_t)r.hazard;
+    row_lists rl;
+    build_rows(sp, order, m, cam->height, &rl);
+    pthread_t th[256];
+    pixels_job jobs[256];
+    int64_t chunk = (npix + nthreads - 1) / nthreads;
+    int used = 0;
+    for (int k = 0; k < nthreads; ++k) {
+        int64_t b = k * chunk, e = (k + 1) * chunk < npix ? (k + 1) * chunk : npix;
+        if (b >= e) break;
+        jobs[k] = (pixels_job){sp, &rl, cam, opt, px, py, b, e, rgb, T, hazard, leaves, n_leaves, cap};
+        pthread_create(&th[k], NULL, pixels_worker, &jobs[k]);
+        ++used;
     }
+    for (int k = 0; k < used; ++k) pthread_join(th[k], NULL);
+    free_rows(&rl);
     free(order);
     free(sp);
+    return 0;
+}
+
+/* Rows of tile (tx, ty) holding a pixel centre of the support of splat s:
+ * inside its pixel box, with omega >= p_min and the peak in front of the
+ * camera, both decisions clear of their margins.  Bit r stands for pixel row
+ * ty * tile_h + r. */
+static uint32_t tile_support_rows(const orc_splat *s, const orc_camera *cam, const orc_options *opt, int tx, int ty)
+{
+    uint32_t rows = 0;
+    for (int r = 0; r < opt->tile_h; ++r) {
+        int py = ty * opt->tile_h + r;
+        if (py < s->py0 || py > s->py1) continue;
+        for (int c = 0; c < opt->tile_w; ++c) {
+            int px = tx * opt->tile_w + c;
+            if (px < s->px0 || px > s->px1) continue;
+            double x[3] = {(px + 0.5 - cam->cx) / cam->fx, (py + 0.5 - cam->cy) / cam->fy, 1.0};
+            int front, front_hz;
+            double w = pixel_weight(s, px, py, x, &front, &front_hz);
+            if (front && !front_hz && w >= opt->p_min * (1.0 + ORC_MARGIN_OMEGA)) {
+                rows |= 1u << r;
+                break;
+            }
+        }
+    }
+    return rows;
+}
+
+typedef struct {
+    const orc_splat *sp;
+    const orc_camera *cam;
+    const orc_options *opt;
+    const int64_t *tiles, *ids;
+    int32_t tiles_x;
+    int64_t begin, end;
+    uint32_t *rows;
+} rows_job;
+
+static void *rows_worker(void *arg)
+{
+    rows_job *j = (rows_job *)arg;
+    for (int64_t k = j->begin; k < j->end; ++k) {
+        int tx = (int)(j->tiles[k] % j->tiles_x), ty = (int)(j->tiles[k] / j->tiles_x);
+        j->rows[k] = tile_support_rows(&j->sp[j->ids[k]], j->cam, j->opt, tx, ty);
+    }
+    return NULL;
+}
+
+/* For each (tile, splat) pair k (tile = ty * tiles_x + tx of one view), the
+ * rows of the tile that hold a pixel centre of the splat's support
+ * (tile_support_rows) in rows[k].  sp is the output of orc_preprocess. */
+int orc_support_rows(const orc_splat *sp, const orc_camera *cam, const orc_options *opt, int32_t tiles_x,
+                     const int64_t *tiles, const int64_t *ids, int64_t m, uint32_t *rows, int nthreads)
+{
+    nthreads = clamp_threads(nthreads);
+    pthread_t th[256];
+    rows_job jobs[256];
+    int64_t chunk = (m + nthreads - 1) / nthreads;
+    int used = 0;
+    for (int k = 0; k < nthreads; ++k) {
+        int64_t b = k * chunk, e = (k + 1) * chunk < m ? (k + 1) * chunk : m;
+        if (b >= e) break;
+        jobs[k] = (rows_job){sp, cam, opt, tiles, ids, tiles_x, b, e, rows};
+        pthread_create(&th[k], NULL, rows_worker, &jobs[k]);
+        ++used;
+    }
+    for (int k = 0; k < used; ++k) pthread_join(th[k], NULL);
     return 0;
 }
 

@@ -452,10 +452,10 @@ def _min_D_over_rect(r, cam, x0, x1, y0, y1):
 
 
 def test_tile_lists_by_definition(oracle_lib):
-    """A tile is listed for a Gaussian iff one of its row bands (64 / tile_w
-    rows, clipped to the pixel box) meets the support: checked from below by
-    pixel centres inside the support, from above by minimising D over the band
-    rectangle; the list of a tile is ordered by (float32 depth, index)."""
+    """A tile is listed for a Gaussian iff the rectangle spanned by its pixel
+    centres inside the Gaussian's pixel box meets the support: checked from
+    below by pixel centres inside the support, from above by minimising D over
+    that rectangle; the list of a tile is ordered by (float32 depth, index)."""
     sc = scenegen.tiny_scene(17, 150, sh_degree=0, log_scale_mean=-2.5, log_scale_std=0.7)
     cam = scenegen.pinhole(scenegen.look_at((0.1, -0.2, -3.0)), 53, 41, 60)
     opts = scenegen.default_options(tile_w=16, tile_h=8)
@@ -463,7 +463,6 @@ def test_tile_lists_by_definition(oracle_lib):
     tiles, keys, idx = oracle.tile_lists(sp, cam, opts)
     tx_n = -(-53 // 16)
     listed = set(zip(tiles.tolist(), idx.tolist()))
-    LY = 64 // 16
     checked_above = 0
     for i in np.nonzero(sp["cull"] == 0)[0]:
         r = sp[i]
@@ -474,16 +473,10 @@ def test_tile_lists_by_definition(oracle_lib):
         mine = [t for (t, j) in listed if j == i]
         for t in mine[:6]:
             ty, tx = divmod(t, tx_n)
-            ok = False
-            for b in range(8 // LY):
-                r0, r1 = max(ty * 8 + b * LY, r["py0"]), min(ty * 8 + b * LY + LY - 1, r["py1"])
-                c0, c1 = max(tx * 16, r["px0"]), min(tx * 16 + 15, r["px1"])
-                if r0 > r1 or c0 > c1:
-                    continue
-                if _min_D_over_rect(r, cam, c0 + 0.5, c1 + 0.5, r0 + 0.5, r1 + 0.5) <= r["kappa"] + 1e-7:
-                    ok = True
-                    break
-            assert ok, (i, t)
+            r0, r1 = max(ty * 8, r["py0"]), min(ty * 8 + 7, r["py1"])
+            c0, c1 = max(tx * 16, r["px0"]), min(tx * 16 + 15, r["px1"])
+            assert r0 <= r1 and c0 <= c1
+            assert _min_D_over_rect(r, cam, c0 + 0.5, c1 + 0.5, r0 + 0.5, r1 + 0.5) <= r["kappa"] + 1e-7, (i, t)
             checked_above += 1
     assert checked_above > 100
     # every listed tile lies in the Gaussian's tile rectangle, lists are (depth, index) ordered
