@@ -1,7 +1,5 @@
-// Exact support-versus-tile test shared by the preprocess kernel (which
-// counts the listed tiles of each Gaussian-view) and the emission kernel
-// (which writes them): both evaluate the same double-precision code on the
-// same stored values, so they take identical decisions.
+// Exact support-versus-tile test of the emission kernel, in double precision
+// on the support conic the preprocess kernel stores per Gaussian-view.
 //
 // In pixel offsets delta = p - pi(mu) the support omega >= p_min, tau > 0 of a
 // Gaussian whose quad lies in front of the camera is the ellipse
@@ -10,10 +8,12 @@
 // (from q b^2 <= kappa den^2 with q = |G delta|^2, den = k0 + g . delta,
 // b^2 = 1 - kappa / c^2).  When P is not positive definite the support is
 // unbounded on the image plane and every tile of the bounding rectangle is
-// kept.  A row band of a tile is listed when the continuous rectangle
-// spanned by its pixel centres (clipped to the Gaussian's pixel box) meets
-// the ellipse; a tile is listed when one of its bands is.  The test is done
-// per tile row: the ellipse's x-extent over each band's heights is computed in
+// kept.  A tile is listed when the continuous rectangle spanned by its pixel
+// centres (clipped to the Gaussian's pixel box) meets the ellipse.  Its
+// culling bands, groups of pixel rows that the compositing kernel can skip
+// together, are tested the same way, and the bands that meet the ellipse
+// travel with the instance.  The tests are done per tile row: the ellipse's
+// x-extent over the row's heights and over each band's heights is computed in
 // closed form, then each tile of the row is an interval comparison.
 #pragma once
 
@@ -104,10 +104,13 @@ __device__ inline int cull_band_rows(int TW, int TH)
     return TH / LY <= kMaxBands ? LY : TH;
 }
 
-// x-extent of the ellipse over each culling band of tile row ty, in pixels.
+// x-extent of the ellipse, in pixels, over the pixel-centre heights of tile
+// row ty (clipped to the box) and over each of its culling bands.
 struct BandRanges {
+    double row_xl, row_xr;
     double xl[kMaxBands], xr[kMaxBands];
-    uint32_t valid;
+    uint32_t valid;  // bands with an extent
+    bool row_valid;  // the ellipse reaches the row's heights
 };
 
 __device__ inline void band_ranges(const Conic &C, const ConicFrame &F, const PixelBox &box, int ty, int TW, int TH,
@@ -116,15 +119,30 @@ __device__ inline void band_ranges(const Conic &C, const ConicFrame &F, const Pi
 #pragma clang fp contract(off)
     const int LY = cull_band_rows(TW, TH), nb = TH / LY;
     B.valid = 0u;
+    B.row_valid = false;
+    B.row_xl = -INFINITY;
+    B.row_xr = INFINITY;
+    const int y0 = max(ty * TH, box.y0), y1 = min(ty * TH + TH - 1, box.y1);
+    if (y0 > y1) return;
+    if (!F.bounded)
+        B.row_valid = true;
+    else
+        B.row_valid = conic_xrange(C, F, (double)y0 + 0.5 - C.v0, (double)y1 + 0.5 - C.v0, B.row_xl, B.row_xr);
 #pragma unroll
     for (int k = 0; k < kMaxBands; ++k) {
         B.xl[k] = -INFINITY;
         B.xr[k] = INFINITY;
-        if (k >= nb) continue;
+        if (k >= nb || !B.row_valid) continue;
         const int r0 = max(ty * TH + k * LY, box.y0), r1 = min(ty * TH + k * LY + LY - 1, box.y1);
         if (r0 > r1) continue;
         if (!F.bounded) {
             B.valid |= 1u << k;
+            continue;
+        }
+        if (nb == 1) {  // the band is the row
+            B.valid |= 1u;
+            B.xl[0] = B.row_xl;
+            B.xr[0] = B.row_xr;
             continue;
         }
         double xl, xr;
@@ -136,39 +154,22 @@ __device__ inline void band_ranges(const Conic &C, const ConicFrame &F, const Pi
     }
 }
 
-// Culling bands of tile (tx, .) that meet the support: the band's
-// pixel-centre rectangle (clipped to the box) overlaps the band's x-extent.
-// 0 = tile not listed.
-__device__ inline uint32_t tile_bands(const Conic &C, const BandRanges &B, const PixelBox &box, int tx, int TW)
+// Is tile (tx, .) of the row listed: does its pixel-centre rectangle (clipped
+// to the box) overlap the row's x-extent?  *bands receives the culling bands
+// whose own rectangles overlap their extents (0 for a tile not listed).
+__device__ inline bool tile_listed(const Conic &C, const BandRanges &B, const PixelBox &box, int tx, int TW,
+                                   uint32_t &bands)
 {
 #pragma clang fp contract(off)
+    bands = 0u;
     const int cx0 = max(tx * TW, box.x0), cx1 = min(tx * TW + TW - 1, box.x1);
-    if (cx0 > cx1) return 0u;
+    if (cx0 > cx1 || !B.row_valid) return false;
     const double xa = (double)cx0 + 0.5 - C.u0, xb = (double)cx1 + 0.5 - C.u0;
-    uint32_t bands = 0u;
+    if (!(xa <= B.row_xr && xb >= B.row_xl)) return false;
 #pragma unroll
     for (int k = 0; k < kMaxBands; ++k)
         if (((B.valid >> k) & 1u) && xa <= B.xr[k] && xb >= B.xl[k]) bands |= 1u << k;
-    return bands;
-}
-
-// Number of listed tiles in a tile row whose band ranges are B.
-__device__ inline uint32_t row_listed(const Conic &C, const BandRanges &B, const PixelBox &box, int TW)
-{
-    if (!B.valid) return 0u;
-    uint32_t n = 0u;
-    for (int tx = box.x0 / TW; tx <= box.x1 / TW; ++tx) n += tile_bands(C, B, box, tx, TW) != 0u;
-    return n;
-}
-
-// Boxes with at most this many tile rows and tiles are listed by one lane;
-// larger ones by a whole wave, one lane per tile row.
-constexpr int kSoloRows = 4, kSoloTiles = 16;
-
-__device__ inline bool solo_box(const PixelBox &b, int TW, int TH)
-{
-    const int rows = b.y1 / TH - b.y0 / TH + 1;
-    return rows <= kSoloRows && rows * (b.x1 / TW - b.x0 / TW + 1) <= kSoloTiles;
+    return true;
 }
 
 // Instance values carry the culling-band bits of their tile in the top 4

@@ -442,9 +442,10 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(int64_t n_max, const in
 // ---------------------------------------------------------------- emission
 // One lane per tile row of the sorted Gaussian-views (a grid-stride loop
 // over the row count the scan produced): the lane computes the support's
-// x-extent over the row's culling bands and writes every tile of the box row
-// at its scanned position, as (tile id, id | band bits) when a band meets the
-// support and as the empty marker `empty_tile` otherwise.  Instances end up
+// x-extent over the row and over its culling bands and writes every tile of
+// the box row at its scanned position, as (tile id, id | band bits) when the
+// tile's pixel-centre rectangle meets the support and as the empty marker
+// `empty_tile` otherwise.  Instances end up
 // grouped by Gaussian-view in depth order, so a stable sort on the tile id
 // alone leaves every tile's list in depth order.  The kernel also clears the
 // tile ranges and the compositing scheduling words for the stages after the
@@ -482,8 +483,9 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
         band_ranges(C, F, pb, ty, TW, TH, B);
         const uint32_t row_base = (uint32_t)views[v].tile_base + (uint32_t)(ty * views[v].tiles_x);
         for (int tx = tx0; tx <= tx1; ++tx, ++pos) {
-            const uint32_t bands = B.valid ? tile_bands(C, B, pb, tx, TW) : 0u;
-            inst_tiles[pos] = bands ? row_base + (uint32_t)tx : empty_tile;
+            uint32_t bands;
+            const bool listed = tile_listed(C, B, pb, tx, TW, bands);
+            inst_tiles[pos] = listed ? row_base + (uint32_t)tx : empty_tile;
             inst_ids[pos] = pack_instance(id, bands, TW, TH);
         }
     }

@@ -89,7 +89,8 @@ def test_workspace_size_validation(lib):
     assert _size(lib, n, arr, nv, opts, flags=8)[0] == _lib.RGS_EINVAL
     for bad in (dict(p_min=0.0), dict(p_min=1.0), dict(alpha_max=0.001), dict(alpha_max=1.0), dict(t_eps=-1.0),
                 dict(mip=4), dict(mip=-1), dict(mip_sigma2_px=-0.1), dict(divergence=2), dict(divergence=1, mip=1), dict(tile_w=12, tile_h=12), dict(tile_w=64, tile_h=64),
-                dict(near_z=float("nan")), dict(background=(0, float("inf"), 0))):
+                dict(near_z=float("nan")), dict(near_z=0.0), dict(near_z=-0.5), dict(near_z=float("inf")),
+                dict(background=(0, float("inf"), 0))):
         _, a2, _, o2 = _args(**bad)
         assert _size(lib, n, a2, nv, o2)[0] == _lib.RGS_EINVAL, bad
     # exact MIP records are 112 B instead of 64 B per Gaussian-view

@@ -7,7 +7,7 @@ import torch
 
 import oracle
 import scenegen
-from gpu_helpers import PARAM_KEYS, say, to_dev
+from gpu_helpers import PARAM_KEYS, assert_image_close, assert_pixels_close, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -201,8 +201,9 @@ def test_c3_full_size_sampled_gradients(r):
 
 def test_c4_full_size_autotuned_forward_backward(r):
     """6M Gaussians, 16 cameras of random size (256..2560 x 256..1440) and
-    FOV (40..90 deg) in one batch with the autotuned tile shape: sampled pixels
-    of two views against the oracle, then the gradients of an upstream
+    FOV (40..90 deg) in one batch with the autotuned tile shape: every pixel
+    of a 493x689 view and sampled pixels of a 2434x1264 one against the
+    oracle, then the gradients of an upstream
     gradient on 200 pixels of one view (zero on the other 15)."""
     from paper_2503_18682_amd import _lib
 
@@ -221,17 +222,16 @@ def test_c4_full_size_autotuned_forward_backward(r):
     del buf, ws
     outs, (buf, ws) = r.render(g, cams, best, flags=_lib.RGS_WS_BACKWARD, keep_workspace=True)
     rng = np.random.default_rng(10)
-    for v in (0, 7):
-        cam = cams[v]
-        px, py = rng.integers(0, cam["width"], 120), rng.integers(0, cam["height"], 120)
-        rgb, T, hz = oracle.render_pixels(sc, cam, best, px, py)
-        g_rgb = outs[v]["rgb"].cpu().numpy()[:, py, px].T
-        g_T = outs[v]["final_T"].cpu().numpy()[py, px]
-        ok_ = hz == 0
-        say(f"  c4 view {v} {cam['width']}x{cam['height']}: max|rgb-oracle|="
-            f"{np.abs(g_rgb - rgb)[ok_].max():.3e} hazard={int((~ok_).sum())}/120")
-        assert (~ok_).mean() <= 0.02
-        assert np.abs(g_rgb - rgb)[ok_].max() <= 2e-4 and np.abs(g_T - T)[ok_].max() <= 2e-4
+    # every pixel of view 0 (493x689), sampled pixels of view 7 (2434x1264)
+    host0 = {k: t.cpu().numpy() for k, t in outs[0].items()}
+    assert_image_close(host0["rgb"], host0["final_T"], oracle.render(sc, cams[0], best),
+                       label=f"c4 view 0 {cams[0]['width']}x{cams[0]['height']}, every pixel")
+    cam = cams[7]
+    px, py = rng.integers(0, cam["width"], 2000), rng.integers(0, cam["height"], 2000)
+    ref = oracle.render_pixels(sc, cam, best, px, py)
+    g_rgb = outs[7]["rgb"].cpu().numpy()[:, py, px].T
+    g_T = outs[7]["final_T"].cpu().numpy()[py, px]
+    assert_pixels_close(g_rgb, g_T, ref, label=f"c4 view 7 {cam['width']}x{cam['height']} sampled")
     v = 7
     dls = [torch.zeros_like(o["rgb"]) for o in outs]
     H, W = cams[v]["height"], cams[v]["width"]
@@ -241,3 +241,34 @@ def test_c4_full_size_autotuned_forward_backward(r):
     grads = r.backward(g, cams, outs, dls, ws, best)
     ref = oracle.backward(sc, cams[v], best, dl.astype(np.float64))
     _compare(grads, ref, "c4 view 7 sampled", rel=2e-3)
+
+
+def test_backward_takes_the_tile_shape_of_the_frame_in_its_workspace(r):
+    """The backward pass of a workspace uses the tile shape of the frame last
+    rendered into it when the options leave the shape open (0, 0), even when
+    the context would now resolve (0, 0) to another shape (here the 8x16
+    default against a 16x16 frame); an explicit shape that differs from the
+    frame's is rejected before any GPU work."""
+    from paper_2503_18682_amd import _lib
+
+    say("case backward tile shape of the workspace's frame")
+    sc = scenegen.tiny_scene(38, 1500, sh_degree=1)
+    cams = [scenegen.pinhole(scenegen.look_at((0, 0, -4)), 120, 100, 60)]
+    g = to_dev(sc)
+    o16 = scenegen.default_options(tile_w=16, tile_h=16)
+    assert (r.layout(1500, cams, 1, 0, dict(o16, tile_w=0, tile_h=0)).tile_w,
+            r.layout(1500, cams, 1, 0, dict(o16, tile_w=0, tile_h=0)).tile_h) == (8, 16)
+    buf, ws = r.new_workspace(1500, cams, 500000, _lib.RGS_WS_BACKWARD, o16)
+    outs = r.allocate_outputs(cams)
+    dl = [torch.from_numpy(np.random.default_rng(3).normal(0, 1, (3, 100, 120)).astype(np.float32)).cuda()]
+    r.render_into(g, cams, outs, ws, o16)
+    want = r.backward(g, cams, outs, dl, ws, o16)
+    r.render_into(g, cams, outs, ws, o16)
+    got = r.backward(g, cams, outs, dl, ws, dict(o16, tile_w=0, tile_h=0))
+    for k in PARAM_KEYS:
+        a, b = want[k].cpu().numpy(), got[k].cpu().numpy()
+        assert np.abs(a - b).max() <= 1e-5 * max(np.abs(a).max(), 1e-6), k
+    with pytest.raises(RuntimeError, match="differs from the 16x16"):
+        r.backward(g, cams, outs, dl, ws, dict(o16, tile_w=8, tile_h=16))
+    with pytest.raises(RuntimeError):
+        r.backward(g, cams, outs, dl, ws, dict(o16, mip=1))
