@@ -93,7 +93,7 @@ typedef struct {
     double p_min;          /* cut-off opacity of the support, eq. 3; in (0, 1); default 1/255 */
     double alpha_max;      /* opacity clamp, in (p_min, 1); default 0.99 */
     double t_eps;          /* compositing stops before T would fall below it; [0, 1); default 1e-4 */
-    double near_z;         /* centres with z <= near_z are culled (Sec. 4.1, near plane); default 0.2 */
+    double near_z;         /* centres with z <= near_z are culled (Sec. 4.1, near plane); > 0; default 0.2 */
     int32_t mip;           /* 0 = none (default); 1 = approximate MIP of Sec. 5, eq. 17; 2 = exact MIP of
                               Sec. 5 / App. B: per ray, Sigma + sigma_x^2 tau(x)^2 I with sigma_x^2 the
                               pixel's area at unit distance along the ray, opacity times
@@ -181,7 +181,12 @@ rgs_status rgs_render_status(rgs_context *ctx, const rgs_workspace *ws, void *st
 /* Gradients of a loss with respect to the Gaussian parameters, given
  * dL_drgb[v] (device [3][H][W] per view) for the frame last rendered into
  * `ws` (which must carry RGS_WS_BACKWARD) with the same g, cams, opts and
- * outs.  Walks each pixel's list back from n_contrib starting at final_T.
+ * outs.  The context remembers, per workspace address, the tile shape, MIP
+ * mode, divergence, Gaussian and view counts, capacity and flags of the last
+ * frame rendered into it (by rgs_render or rgs_batch_launch): opts->tile_w =
+ * tile_h = 0 takes that frame's tile shape (whatever the autotuners chose
+ * since), and any of these that differs from that frame is RGS_EINVAL.
+ * Walks each pixel's list back from n_contrib starting at final_T.
  * Gradients are added into `grads`.  With opts->mip = 1 they also flow
  * through the MIP widening and opacity modulation (eq. 17), with opts->mip
  * = 2 through the per-ray widening and modulation of the exact MIP; opts->mip
@@ -204,6 +209,15 @@ rgs_status rgs_batch_plan(rgs_context *ctx, int64_t n, int32_t sh_degree, const 
                           rgs_plan **out);
 rgs_status rgs_batch_launch(rgs_plan *plan, const rgs_gaussians *g, const rgs_camera *cams, const rgs_workspace *ws,
                             const rgs_view_out *outs, void *stream);
+
+/* Overflow check of a plan's last launch (eq. 1's compositing needs every
+ * Gaussian-tile instance of the frame): synchronises the stream of that
+ * launch, then writes the number of instances the frame needed to
+ * *instances_needed (may be NULL).  RGS_OK when they fit the plan's capacity,
+ * RGS_EOVERFLOW when they did not (the views were then rendered as
+ * background: make a plan with a larger capacity); RGS_EINVAL before the
+ * first launch. */
+rgs_status rgs_batch_status(rgs_plan *plan, int64_t *instances_needed);
 void rgs_plan_destroy(rgs_plan *plan);
 
 /* Times every supported tile shape on this frame (hipEvent timing, `reps`

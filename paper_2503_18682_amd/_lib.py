@@ -81,6 +81,7 @@ EXPORTS = {
                                  C.c_int64, C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_void_p)]),
     "rgs_batch_launch": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.POINTER(Camera), C.POINTER(Workspace),
                                    C.POINTER(ViewOut), C.c_void_p]),
+    "rgs_batch_status": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "rgs_plan_destroy": (None, [C.c_void_p]),
     "rgs_autotune": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.POINTER(Camera), C.c_int32, C.POINTER(Options),
                                C.POINTER(Workspace), C.POINTER(ViewOut), C.c_int32, C.c_void_p, C.POINTER(Options),

@@ -52,6 +52,14 @@ struct FrameEvents {
     int first, last;  // stages [first, last) were recorded
 };
 
+// Layout-determining parameters of a rendered frame.
+struct FrameShape {
+    TileShape tile;
+    int32_t mip, divergence, n_views;
+    int64_t n, capacity;
+    int32_t flags;
+};
+
 }  // namespace
 
 struct rgs_context {
@@ -67,6 +75,9 @@ struct rgs_context {
     unsigned long long *view_stamps = nullptr;  // rgs_set_view_clocks (caller-owned device memory)
     int view_stamps_views = 0;
     std::map<std::string, TileShape> tune_cache;  // autotuned tile shapes by configuration class
+    // What the last frame rendered into each workspace (keyed by its device
+    // address) was laid out for: the backward pass reads that frame's buffers.
+    std::map<const void *, FrameShape> ws_frames;
 };
 
 struct rgs_plan {
@@ -83,6 +94,8 @@ struct rgs_plan {
     bool captured = false;
     rgs_gaussians g{};
     void *ws_ptr = nullptr;
+    hipStream_t last_stream = nullptr;  // stream of the last launch
+    bool launched = false;
     std::vector<rgs_view_out> outs;
 };
 
@@ -191,7 +204,8 @@ rgs_status check_options(rgs_context *ctx, const rgs_options *o)
     if (!(o->alpha_max > o->p_min && o->alpha_max < 1.0))
         return fail(ctx, RGS_EINVAL, "alpha_max must lie in (p_min, 1)");
     if (!(o->t_eps >= 0.0 && o->t_eps < 1.0)) return fail(ctx, RGS_EINVAL, "t_eps must lie in [0, 1)");
-    if (!std::isfinite(o->near_z)) return fail(ctx, RGS_EINVAL, "near_z must be finite");
+    if (!(o->near_z > 0.0) || !std::isfinite(o->near_z))
+        return fail(ctx, RGS_EINVAL, "near_z must be finite and > 0");
     if (o->mip < 0 || o->mip > 3) return fail(ctx, RGS_EINVAL, "mip must be 0, 1, 2 or 3");
     if (o->divergence != RGS_DIVERGENCE_RAY && o->divergence != RGS_DIVERGENCE_GS)
         return fail(ctx, RGS_EINVAL, "divergence must be RGS_DIVERGENCE_RAY or RGS_DIVERGENCE_GS");
@@ -496,6 +510,38 @@ rgs_status check_workspace(rgs_context *ctx, const rgs_workspace *ws, const Layo
     return RGS_OK;
 }
 
+FrameShape frame_shape(const rgs_options &o, int64_t n, int32_t n_views, const rgs_workspace &ws)
+{
+    return FrameShape{shape_of(o), o.mip, o.divergence, n_views, n, ws.capacity, ws.flags};
+}
+
+// Options of the backward pass of the frame last rendered into `ws`: tile
+// (0, 0) takes that frame's tile shape; anything that would lay the
+// workspace out differently from that frame is an error.
+rgs_status backward_options(rgs_context *ctx, int64_t n, const rgs_camera *cams, int32_t n_views,
+                            const rgs_options *opts, const rgs_workspace *ws, rgs_options &out)
+{
+    const auto it = ctx->ws_frames.find(ws->ptr);
+    if (it == ctx->ws_frames.end()) {
+        out = resolve_tiles(ctx, n, cams, n_views, opts);
+        return RGS_OK;
+    }
+    const FrameShape &f = it->second;
+    out = *opts;
+    if (out.tile_w == 0 && out.tile_h == 0) {
+        out.tile_w = f.tile.w;
+        out.tile_h = f.tile.h;
+    }
+    if (out.tile_w != f.tile.w || out.tile_h != f.tile.h)
+        return fail(ctx, RGS_EINVAL, "tile %dx%d differs from the %dx%d of the frame last rendered into this workspace",
+                    out.tile_w, out.tile_h, f.tile.w, f.tile.h);
+    if (out.mip != f.mip || out.divergence != f.divergence || n != f.n || n_views != f.n_views ||
+        ws->capacity != f.capacity || ws->flags != f.flags)
+        return fail(ctx, RGS_EINVAL, "options, Gaussian count, views or workspace differ from the frame last "
+                                     "rendered into this workspace");
+    return RGS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -577,6 +623,7 @@ rgs_status rgs_render(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera
     const std::vector<unsigned char> hdr = build_header(L, cams, n_views, outs, nullptr);
     RGS_HIP(ctx, hipMemcpyAsync(ws->ptr, hdr.data(), hdr.size(), hipMemcpyHostToDevice, s));
     st = enqueue_forward(ctx, *g, n_views, *opts, L, ws->ptr, s, true, ctx->view_stamps);
+    if (st == RGS_OK) ctx->ws_frames[ws->ptr] = frame_shape(*opts, g->n, n_views, *ws);
     if (st == RGS_OK && ctx->timing) ++ctx->frames;  // frames whose stages were timed
     return st;
 }
@@ -605,7 +652,9 @@ rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const r
     if (st != RGS_OK) return st;
     if (!ws) return fail(ctx, RGS_EINVAL, "workspace is NULL");
     if (!opts) return fail(ctx, RGS_EINVAL, "opts is NULL");
-    const rgs_options ro = resolve_tiles(ctx, g->n, cams, n_views, opts);
+    if (!cams || n_views < 1) return fail(ctx, RGS_EINVAL, "no cameras");
+    rgs_options ro;
+    if ((st = backward_options(ctx, g->n, cams, n_views, opts, ws, ro)) != RGS_OK) return st;
     opts = &ro;
     Layout L;
     if ((st = compute_layout(ctx, g->n, cams, n_views, opts, ws->capacity, ws->flags, L)) != RGS_OK) return st;
@@ -747,6 +796,25 @@ rgs_status rgs_batch_launch(rgs_plan *p, const rgs_gaussians *g, const rgs_camer
     const std::vector<unsigned char> hdr = build_header(L, cams, nv, outs, nullptr);
     RGS_HIP(ctx, hipMemcpyAsync(ws->ptr, hdr.data(), hdr.size(), hipMemcpyHostToDevice, s));
     RGS_HIP(ctx, hipGraphLaunch(p->exec, s));
+    p->last_stream = s;
+    p->launched = true;
+    ctx->ws_frames[ws->ptr] = frame_shape(p->opts, p->n, nv, *ws);
+    return RGS_OK;
+}
+
+rgs_status rgs_batch_status(rgs_plan *p, int64_t *instances_needed)
+{
+    if (!p) return RGS_EINVAL;
+    rgs_context *ctx = p->ctx;
+    if (!p->launched || !p->ws_ptr) return fail(ctx, RGS_EINVAL, "the plan has not been launched");
+    RGS_HIP(ctx, hipSetDevice(ctx->device));
+    RGS_HIP(ctx, hipStreamSynchronize(p->last_stream));
+    int64_t c = 0;
+    RGS_HIP(ctx, hipMemcpy(&c, p->ws_ptr, sizeof c, hipMemcpyDeviceToHost));
+    if (instances_needed) *instances_needed = c;
+    if (c > p->capacity)
+        return fail(ctx, RGS_EOVERFLOW, "frame needed %lld instances, plan capacity %lld", (long long)c,
+                    (long long)p->capacity);
     return RGS_OK;
 }
 

@@ -331,8 +331,13 @@ class BatchRenderer:
                                                                self._outs_arr, _stream(self.r.device)))
         return self.outs
 
-    def status(self):
-        return self.r.status(self.ws)
+    def status(self) -> tuple:
+        """(fits, instances needed) of the last launch (rgs_batch_status)."""
+        inst = C.c_int64()
+        st = self.lib.rgs_batch_status(self.plan, C.byref(inst))
+        if st not in (L.RGS_OK, L.RGS_EOVERFLOW):
+            _check(self.lib, self.r.ctx, st)
+        return st == L.RGS_OK, inst.value
 
     def close(self):
         if getattr(self, "plan", None):
