@@ -1,36 +1,43 @@
 #!/usr/bin/env python3
 """Benchmark of the MI355X ray-based Gaussian splatting renderer.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c2|c3|c4]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload all|c1|c2|c3|c4]
 
-Workloads (synthetic, seeded; see scenegen/scenes.py):
-  c1 (default)  500k Gaussians (64 clusters, SH3), one 1920x1080 camera at 50 deg
-                FOV cycling over 16 orbit poses; a step renders one frame through
-                the whole hot path (preprocess, depth sort, scan, emit, tile sort,
-                ranges, compositing) replayed as one HIP graph.  Metric: frames/s.
-  c2            3M Gaussians, 4 stereo pairs (8 views, 2064x2208 per eye x
-                {0.5,1,2} per pair), MIP on; a step renders all 8 views in one
-                graph replay.  Metric: views/s (8 single-view renders reported too).
-                --mip exact renders the same frame with the exact per-ray MIP
-                (and, for c3, trains through it).
-  --divergence gs  c1 with the linearised divergence of 3DGS (Sec. 3.1) in the same
-                pipeline: the same-model speed comparison of GS and RayGS.
-  c3            1M Gaussians, 4 views at 1600x1060; a step is forward + L1 loss
-                gradient + backward.  Metric: backward ms/view.
+The default (all) prints one JSON line with the three parts of the metric:
+  value / c1    frames/s at 1080p with 500k Gaussians (64 clusters, SH3), one
+                1920x1080 camera at 50 deg FOV on a 16-pose orbit.  A step is
+                one orbit: 16 frames, one per pose, each a HIP-graph replay of
+                the whole hot path (preprocess, depth sort, scan, emit, tile
+                sort, ranges, compositing), so every timed step weights the
+                poses equally.
+  c2            batched stereo views/s: 3M Gaussians, 4 stereo pairs (8 views,
+                2064x2208 per eye x {0.5,1,2} per pair), MIP on; a step renders
+                all 8 views in one graph replay (8 plain single-view renders
+                reported beside it).
+  c3            backward ms/view: 1M Gaussians, 4 views at 1600x1060; a step is
+                forward + L1 loss gradient + backward.
+Each part carries a roofline object for its compositing kernel (forward for c1
+and c2, backward for c3); a leg that fails reports its error in place of its
+figures and the line is still printed.
+Single legs: --workload c1|c2|c3, and
   c4            6M Gaussians, 16 cameras of uneven size (256..2560 x 256..1440)
                 and FOV, autotuned tile shape; a step is forward + L1 loss gradient
                 + backward over all 16 views.  Metric: megapixels/s of the step;
                 per-view forward latency p50/p99 from device completion clocks.
+  --divergence gs  c1 with the linearised divergence of 3DGS (Sec. 3.1) in the same
+                pipeline: the same-model speed comparison of GS and RayGS.
+  --mip exact   c2 rendered with the exact per-ray MIP (c3 trains through it).
 
-Prints ONE JSON line.  Inputs are resident in HBM before the timed region.
-The roofline object covers the dominant kernel of the step, timed with HIP
-events on the stream it is launched on; its algorithmic work comes from the
-oracle's counts (tests/golden/work_counts_<workload>.json).
+Inputs are resident in HBM before the timed region.  Each roofline covers one
+kernel, timed with HIP events on the stream it is launched on; its algorithmic
+work comes from the oracle's counts of the same frames
+(tests/golden/work_counts_<workload>.json).
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -43,13 +50,22 @@ sys.path.insert(0, ROOT)
 METRIC = "frames/s at 1080p with 500k Gaussians; batched stereo views/s; backward ms/view"
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP32_TFLOPS = 157.3       # MI355X vector FP32 (published)
-# Algorithmic FP32 work of the compositing stage (FMA counts 2):
-#   per fragment (pixel centre inside a projected quad): pixel offset (4),
-#   quad-plane map (6), den (4), q (3), den^2 + q/c^2 (3), reciprocal (1),
-#   D (1), exponent (2), exp2 (1)                                  -> 25
-#   per composited fragment: clamp, 1 - a, T (1 - a), T a, colour (3 FMA) -> 10
-FLOP_PER_FRAGMENT = 25
+POSES = 16                     # c1 orbit poses per step
+# Algorithmic FP32 work of compositing (FMA counts 2, as in the published peak).
+# Forward, per fragment (pixel centre inside a projected quad), eq. 16 and eq. 2:
+#   delta = p - pi(mu) (2), n = G delta (6), den = k0 + g . delta (4), q = |n|^2 (3),
+#   den^2 + q / c^2 (3), D = q / (...) (1), omega = o exp(-D / 2) (3)      -> 22
+# per composited fragment, eq. 1: alpha = min(omega, alpha_max), 1 - alpha,
+#   T (1 - alpha), T alpha, three colour multiply-adds (6)                  -> 10
+FLOP_PER_FRAGMENT = 22
 FLOP_PER_CONTRIBUTION = 10
+# Backward, per fragment up to the pixel's stop: omega again (22); per
+# composited fragment, the adjoint of eq. 1 (T_i = T_i+1 / (1 - alpha): 2,
+# g . rgb: 5, dL/dalpha: 4, the running sum S: 2, dL/drgb: 7), through
+# alpha and omega to D and o (3), D = q / (den^2 + q / c^2) to q, den, 1/c^2 (8),
+# to n, G, g, k0 and pi(mu) (2 + 8 + 4 + 1 + 8) and the 13 record-gradient
+# accumulations (13)                                                        -> 65
+FLOP_PER_CONTRIBUTION_BWD = 65
 # Algorithmic bytes of the other stages (per unit):
 PARAM_BYTES = {0: 56, 1: 92, 2: 152, 3: 236}   # Gaussian parameters read once per batch
 RECORD_BYTES = 64 + 4 + 8 + 64 + 4             # record, depth key, pixel box, support conic, tile count per visible Gaussian-view
@@ -64,9 +80,9 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=160)
-    ap.add_argument("--warmup", type=int, default=16)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="all", choices=["all", "c1", "c2", "c3", "c4"])
     ap.add_argument("--mip", default="approx", choices=["approx", "exact"],
                     help="c2: the approximate MIP of eq. 17 (the paper's renderer) or the exact per-ray MIP; "
                          "c3: exact turns the exact per-ray MIP on (the workload has none)")
@@ -137,8 +153,17 @@ def roofline_for(stage, ms, *, flops=None, nbytes=None, traffic=None):
                 "avg_ms": ms, "algorithmic_flop": flops}
     achieved = nbytes / (ms * 1e-3) / 1e9 if nbytes else None
     return {"bound": "hbm", "kernel": stage, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": None, "avg_ms": ms,
+            "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": traffic, "avg_ms": ms,
             "algorithmic_bytes": nbytes}
+
+
+def frame_work(wc, views):
+    """Oracle fragments and composited fragments summed over `views` (indices
+    into the work-count file), or None without a file."""
+    if not wc:
+        return None
+    vs = wc["views"]
+    return (float(sum(vs[v]["fragments"] for v in views)), float(sum(vs[v]["contributions"] for v in views)))
 
 
 def cpu_baseline_c1(scene, cam, opts):
@@ -182,62 +207,58 @@ def bench_c1(args, torch):
         need = max(need, r.status(ws)[1])
         del buf
     capacity = int(need * 1.1) + 4096
-    log(f"c1: {n} Gaussians, 16 poses, max instances {need}, capacity {capacity}")
+    log(f"c1: {n} Gaussians, {POSES} poses, max instances {need}, capacity {capacity}")
     br = R.BatchRenderer(r, n, sc["sh_degree"], [cams[0]], capacity, options=opts)
 
-    def step(k):
-        if args.eager:
-            r.render_into(g, [cams[k % 16]], br.outs, br.ws, opts)
-        else:
-            br.launch(g, [cams[k % 16]])
+    def step():
+        # one orbit: a frame at each pose
+        for c in cams:
+            if args.eager:
+                r.render_into(g, [c], br.outs, br.ws, opts)
+            else:
+                br.launch(g, [c])
 
-    for k in range(args.warmup):
-        step(k)
+    for _ in range(args.warmup):
+        step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(k)
+    for _ in range(args.steps):
+        step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ok, _ = br.status()
     assert ok, "instance capacity overflow in the timed region"
     ms = (t1 - t0) * 1e3 / args.steps
-    stages, frames = stage_pass(r, g, lambda k: [cams[k % 16]], opts, br.ws, br.outs, args.stage_steps)
-    wc = work_counts("c1_gs" if gs else "c1")
+    frames = max(POSES, POSES * math.ceil(args.stage_steps / POSES))
+    stages, _ = stage_pass(r, g, lambda k: [cams[k % POSES]], opts, br.ws, br.outs, frames)
     fwd = {k: v for k, v in stages.items() if not k.endswith("backward")}
-    dom = max(fwd, key=fwd.get)
-    flops = nbytes = None
-    if wc:
-        vs = wc["views"]
-        per = [vs[k % 16] for k in range(args.stage_steps)]
-        frag = np.mean([v["fragments"] for v in per])
-        contrib = np.mean([v["contributions"] for v in per])
-        vis = np.mean([v["visible"] for v in per])
-        inst = np.mean([v["instances"] for v in per])
-        flops = FLOP_PER_FRAGMENT * frag + FLOP_PER_CONTRIBUTION * contrib
-        nbytes = {"preprocess": PARAM_BYTES[3] * n + RECORD_BYTES * vis,
-                  "tile_sort": 2 * 2 * INSTANCE_BYTES * inst}.get(dom)
+    work = frame_work(work_counts("c1_gs" if gs else "c1"), range(POSES))
+    flops = (FLOP_PER_FRAGMENT * work[0] + FLOP_PER_CONTRIBUTION * work[1]) / POSES if work else None
     tag = "c1_1080p_500k_" + args.tile + ("_gs" if gs else "")
-    roof = roofline_for(dom, fwd[dom], flops=flops, nbytes=nbytes, traffic=pmc_traffic(dom, tag))
+    roof = roofline_for("blend", fwd["blend"], flops=flops, traffic=pmc_traffic("blend", tag))
     # measured ceilings of this device (context for `peak`, which stays the published figure)
     calib = r.calibrate()
-    if roof["unit"] == "TFLOP/s" and roof["achieved"]:
+    if roof["achieved"]:
         roof["attainable_peak"] = calib["fma_tflops"]
         roof["attainable_frac"] = roof["achieved"] / calib["fma_tflops"]
     res = {
-        "metric": METRIC, "value": 1e3 / ms, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "metric": METRIC, "value": POSES * 1e3 / ms, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "c1: 500k Gaussians (64 clusters, SH3), 1920x1080, 50deg FOV, 16 orbit poses"
                    + (" (linearised GS divergence)" if gs else ""),
                    "n_gaussians": n, "width": 1920, "height": 1080, "tile": args.tile,
+                   "frames_per_step": POSES, "step": "one frame at each of the 16 orbit poses",
                    "launch": "eager" if args.eager else "hip_graph", "instance_capacity": capacity},
         "roofline": roof,
         "calibration": calib,
         "stages_ms": stages,
+        "dominant_stage": max(fwd, key=fwd.get),
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_c1(sc, cams[0], opts)
+    br.close()
+    r.close()
     return res
 
 
@@ -265,7 +286,7 @@ def bench_c2(args, torch):
         br.launch(g, cams)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    assert br.status()[0]
+    assert br.status()[0], "instance capacity overflow in the timed region"
     ms = (t1 - t0) * 1e3 / args.steps
     # 8 plain single-view renders
     singles = []
@@ -273,26 +294,34 @@ def bench_c2(args, torch):
         _, (b1, w1) = r.render(g, [c], opts, keep_workspace=True)
         singles.append((b1, w1, r.allocate_outputs([c])))
     torch.cuda.synchronize()
+    reps = max(args.steps // 4, 2)
     t0 = time.perf_counter()
-    for _ in range(max(args.steps // 4, 2)):
+    for _ in range(reps):
         for c, (b1, w1, o1) in zip(cams, singles):
             r.render_into(g, [c], o1, w1, opts)
     torch.cuda.synchronize()
-    plain_ms = (time.perf_counter() - t0) * 1e3 / max(args.steps // 4, 2)
+    plain_ms = (time.perf_counter() - t0) * 1e3 / reps
+    del singles
     stages, _ = stage_pass(r, g, lambda k: cams, opts, br.ws, br.outs, max(args.stage_steps // 4, 4))
     fwd = {k: v for k, v in stages.items() if not k.endswith("backward")}
-    dom = max(fwd, key=fwd.get)
-    return {
-        "metric": METRIC, "value": 8e3 / ms, "unit": "views/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+    work = frame_work(work_counts("c2") if args.mip != "exact" else None, range(len(cams)))
+    flops = FLOP_PER_FRAGMENT * work[0] + FLOP_PER_CONTRIBUTION * work[1] if work else None
+    res = {
+        "metric_part": "batched stereo views/s", "value": 8e3 / ms, "unit": "views/s", "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "config": {"workload": "c2: 3M Gaussians, 4 stereo pairs (8 views), MIP on, one HIP-graph replay"
                    + (" (exact per-ray MIP)" if args.mip == "exact" else ""),
-                   "views": [[c["width"], c["height"]] for c in cams], "instance_capacity": capacity},
+                   "views": [[c["width"], c["height"]] for c in cams], "tile": args.tile,
+                   "instance_capacity": capacity},
         "plain_launches_views_per_s": 8e3 / plain_ms,
-        "roofline": roofline_for(dom, fwd[dom]),
+        "roofline": roofline_for("blend", fwd["blend"], flops=flops,
+                                 traffic=pmc_traffic("blend", "c2_stereo_3m_8views_" + args.tile)),
         "stages_ms": stages,
+        "dominant_stage": max(fwd, key=fwd.get),
     }
+    br.close()
+    r.close()
+    return res
 
 
 def bench_c3(args, torch):
@@ -329,14 +358,14 @@ def bench_c3(args, torch):
         step()
     torch.cuda.synchronize()
     bwd = 0.0
-    steps = max(args.steps // 4, 4)
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for _ in range(args.steps):
         step()
         ev[2].synchronize()
         bwd += ev[1].elapsed_time(ev[2])
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    assert r.status(ws)[0], "instance capacity overflow in the timed region"
     r.stage_times()  # reset
     r.set_stage_timing(True)
     for _ in range(4):
@@ -345,18 +374,30 @@ def bench_c3(args, torch):
     stages, frames = r.stage_times()
     r.set_stage_timing(False)
     stages = {k: v / max(frames, 1) for k, v in stages.items()}
-    bstages = {k: v for k, v in stages.items() if k.endswith("backward")}
-    dom = max(bstages, key=bstages.get)
-    return {
-        "metric": METRIC, "value": bwd / steps / len(cams), "unit": "backward ms/view", "n_gpus": 1, "steps": steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+    work = frame_work(work_counts("c3") if args.mip != "exact" else None, range(len(cams)))
+    flops = FLOP_PER_FRAGMENT * work[0] + FLOP_PER_CONTRIBUTION_BWD * work[1] if work else None
+    res = {
+        "metric_part": "backward ms/view", "value": bwd / args.steps / len(cams), "unit": "backward ms/view",
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": False,
         "config": {"workload": "c3: 1M Gaussians (SH3), 4 views 1600x1060, forward + L1 + backward"
-                   + (" (exact per-ray MIP)" if args.mip == "exact" else ""),
+                   + (" (exact per-ray MIP)" if args.mip == "exact" else ""), "tile": args.tile,
                    "instance_capacity": capacity},
-        "roofline": roofline_for(dom, bstages[dom]),
+        "roofline": roofline_for("blend_backward", stages["blend_backward"], flops=flops,
+                                 traffic=pmc_traffic("blend_backward", "c3_train_1m_4views_" + args.tile)),
         "stages_ms": stages,
     }
+    r.close()
+    return res
+
+
+def line_of(part, res):
+    """A single-leg result as a full benchmark line."""
+    out = {"metric": METRIC, "value": res["value"], "unit": res["unit"], "n_gpus": 1, "steps": res["steps"],
+           "warmup": res["warmup"], "ms_per_step": res["ms_per_step"], "higher_is_better": res["higher_is_better"],
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
+    out.update({k: v for k, v in res.items() if k not in out})
+    out["metric_part"] = part
+    return out
 
 
 def bench_c4(args, torch):
@@ -477,7 +518,23 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    res = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4}[args.workload](args, torch)
+    if args.workload == "all":
+        res = bench_c1(args, torch)
+        for key, leg in (("c2", bench_c2), ("c3", bench_c3)):
+            torch.cuda.empty_cache()
+            try:
+                res[key] = leg(args, torch)
+            except Exception as e:  # the c1 line is printed whatever a later leg does
+                res[key] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"{key}: {json.dumps({k: res[key].get(k) for k in ('value', 'unit', 'error')})}")
+    elif args.workload == "c1":
+        res = bench_c1(args, torch)
+    elif args.workload == "c2":
+        res = line_of("batched stereo views/s", bench_c2(args, torch))
+    elif args.workload == "c3":
+        res = line_of("backward ms/view", bench_c3(args, torch))
+    else:
+        res = bench_c4(args, torch)
     print(json.dumps(res), flush=True)
 
 

@@ -95,7 +95,7 @@ typedef struct {
     double t_eps;          /* compositing stops before T would fall below it; [0, 1); default 1e-4 */
     double near_z;         /* centres with z <= near_z are culled (Sec. 4.1, near plane); > 0; default 0.2 */
     int32_t mip;           /* 0 = none (default); 1 = approximate MIP of Sec. 5, eq. 17; 2 = exact MIP of
-                              Sec. 5 / App. B: per ray, Sigma + sigma_x^2 tau(x)^2 I with sigma_x^2 the
+                              Sec. 5 / App. A.5: per ray, Sigma + sigma_x^2 tau(x)^2 I with sigma_x^2 the
                               pixel's area at unit distance along the ray, opacity times
                               sqrt(|Sigma| x.Sigma^-1 x / (|Sigma^_x| x.Sigma^_x^-1 x));
                               3 = the widening of eq. 17 without its opacity modulation (the dilation-only

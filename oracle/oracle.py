@@ -13,7 +13,12 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "raygs_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# RAYGS_SANITIZE=1 builds and loads a copy instrumented with AddressSanitizer
+# and UndefinedBehaviorSanitizer (load it with gcc's libasan preloaded; see
+# tests/run_sanitized.sh)
+_SANITIZE = os.environ.get("RAYGS_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
+_SAN_FLAGS = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
 
 CULL = dict(visible=0, invalid=1, near=2, kappa=3, inside=4, offscreen=5, notile=6)
 HAZARD = dict(key=1, rect=2, eigen=4, cull=8, front=16)
@@ -26,7 +31,7 @@ def build_library(force=True):
     tmp = _LIB + ".tmp"
     subprocess.check_call(
         ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC",
-         "-o", tmp, _SRC, "-lm", "-lpthread"]
+         *(_SAN_FLAGS if _SANITIZE else []), "-o", tmp, _SRC, "-lm", "-lpthread"]
     )
     os.replace(tmp, _LIB)
     return _LIB

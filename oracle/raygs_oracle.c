@@ -14,7 +14,7 @@
  *     Sigma = R_p S^2 R_p^T with R_p = W R(q / |q|), S = diag(exp(l)),
  *     o = sigmoid(a),
  *     optional MIP widening and opacity modulation (Sec. 5, eq. 17),
- *     or, for the exact MIP density of Sec. 5 / App. B, a widened Gaussian
+ *     or, for the exact MIP density of Sec. 5 / App. A.5, a widened Gaussian
  *     that bounds its support (see mip_exact_bound),
  *     kappa = -2 log(p_min / o) (eq. 3), skipped when kappa <= 0,
  *     c^2 = mu^T Sigma^-1 mu (eq. 6), skipped when c^2 <= kappa,
@@ -242,7 +242,7 @@ double orc_divergence(const double *mu, const double *Rp, const double *s, const
     return D;
 }
 
-/* Exact MIP weight of one ray (Sec. 5 and its derivation in App. B).
+/* Exact MIP weight of one ray (Sec. 5 and its derivation in App. A.5).
  * xbar = (u, v, 1) is the ray through a pixel centre in normalised camera
  * coordinates and x = xbar / |xbar| the unit ray.  With tau(x) the peak of the
  * Gaussian's own density along x (eq. 5) and sigma_x^2 the area that one pixel
@@ -253,7 +253,7 @@ double orc_divergence(const double *mu, const double *Rp, const double *s, const
  *   omega = o m(x) exp(-D_ray(x; mu, Sigma^_x) / 2),
  *   m(x)^2 = |Sigma| x^T Sigma^-1 x / (|Sigma^_x| x^T Sigma^_x^-1 x).
  * m(x) is the ratio of the ray density's normalising factor with and without
- * the widening (both written through the determinant identity of App. B), so
+ * the widening (both written through the determinant identity of App. A.5), so
  * it is 1 when sigma = 0 and equals the modulation of eq. (17) on the ray
  * through mu.  *tau_h receives the peak of the widened density along x; the
  * ray gets no contribution unless it is positive. */
@@ -284,7 +284,7 @@ double orc_mip_exact_weight(const double *mu, const double *Rp, const double *s0
 
 /* Bound of the exact MIP support.  A ray contributes only if
  * D_ray(x; mu, Sigma^_x) <= kappa (m <= 1, since det(F^T Sigma^_x F) >=
- * det(F^T Sigma F) on the tangent plane of App. B).  For such a ray, with
+ * det(F^T Sigma F) on the tangent plane of App. A.5).  For such a ray, with
  * e = mu - tau^ x (tau^ the peak of the widened density), |e|^2 <= kappa
  * (s_max^2 + a) and the plain peak differs from tau^ by at most
  * |e| s_max / s_min, so |tau| <= |mu| + sqrt(kappa) (s_max + sigma |tau|)

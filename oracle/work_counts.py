@@ -5,13 +5,18 @@ For each view of a workload it records, from a full oracle render:
   visible        Gaussians passing every cull
   instances      listed (Gaussian, tile) pairs at the recorded tile shape
   fragments      pixel centres inside a projected quad (what a rasteriser
-                 would shade for the paper's quads), before termination
-  box_pairs      pixel centres inside a Gaussian's pixel box
+                 would shade for the paper's quads), along each pixel's
+                 depth order up to the entry at which compositing stops
+  box_pairs      pixel centres inside a Gaussian's pixel box, counted the
+                 same way
   contributions  fragments that were composited (omega >= p_min, before
                  early termination)
 These are the denominators of the roofline figures (work per launch).
 
     python -m oracle.work_counts c1 [--tile 8x16] [--divergence ray|gs] [--out tests/golden/work_counts_c1.json]
+
+The benchmark's tile shape is 8x16; c2 and c3 are counted with it as well
+(python -m oracle.work_counts c2 --tile 8x16).
 
 With --divergence gs the frames are rendered with the linearised divergence
 (written to work_counts_<workload>_gs.json); its fragments are the pixel
@@ -45,7 +50,7 @@ def counts(name: str, views=None, tile=None, divergence="ray"):
         if views is not None and v not in views:
             continue
         t = time.time()
-        r = oracle.render(sc, cam, opts)
+        r = oracle.render(sc, cam, opts, branches=False)
         c = dict(r["counters"], view=v, width=cam["width"], height=cam["height"])
         out.append(c)
         print(f"{name} view {v}: {c} ({time.time() - t:.1f} s)", flush=True)

@@ -39,9 +39,21 @@ FLAGS = [
 ]
 
 
+# RAYGS_SANITIZE=1: host code instrumented with AddressSanitizer and
+# UndefinedBehaviorSanitizer (device code is not), written to libraygs_san.so
+# (load it with RAYGS_LIBRARY and clang's ASan runtime preloaded; see
+# tests/run_sanitized.sh)
+SANITIZE = os.environ.get("RAYGS_SANITIZE") == "1"
+SAN_FLAGS = ["-g", "-fno-omit-frame-pointer", "-Xarch_host", "-fsanitize=address", "-Xarch_host",
+             "-fsanitize=undefined", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+if SANITIZE:
+    LIB = os.path.join(HERE, "libraygs_san.so")
+    BUILD = os.path.join(ROOT, "_build", "san")
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *(SAN_FLAGS if SANITIZE else []), "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
@@ -54,7 +66,8 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC",
+           *(["-fsanitize=address,undefined", "-shared-libsan"] if SANITIZE else []), "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

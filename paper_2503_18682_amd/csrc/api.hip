@@ -679,11 +679,12 @@ rgs_status rgs_render_backward(rgs_context *ctx, const rgs_gaussians *g, const r
     const DevOptions dopt = dev_options(*opts);
     uint32_t *sched = at<uint32_t>(ws->ptr, L.sched);
     float *rgrads = at<float>(ws->ptr, L.record_grads);
-    Timer tm(ctx, s, true, ST_BLEND_BWD);
     RGS_HIP(ctx, launch_zero_kept_grads(at<uint32_t>(ws->ptr, L.order_a), at<int64_t>(ws->ptr, L.counters) + 4,
                                         L.nv_records, grad_floats(opts->mip), rgrads, ctx->num_cus, s));
     uint32_t *bwd_heads = sched + sched_backward_heads();
     RGS_HIP(ctx, launch_fill_u32(bwd_heads, 0u, (int64_t)kQueues * kQueueStride, s));
+    // the stage times cover the compositing backward kernel alone, then the per-Gaussian chain
+    Timer tm(ctx, s, true, ST_BLEND_BWD);
     RGS_HIP(ctx, launch_blend_backward(sh, at<uint2>(ws->ptr, L.ranges), at<uint32_t>(ws->ptr, L.tile_order),
                                        sched + sched_item_count(),
                                        at<uint32_t>(ws->ptr, L.inst_ids_a), at<float4>(ws->ptr, L.records),

@@ -44,7 +44,8 @@ import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 # translation units and headers the compositing kernels are built from
-SOURCES = {"k_blend": ["csrc/blend.hip", "csrc/internal.h", "csrc/binning.h"]}
+SOURCES = {"k_blend": ["csrc/blend.hip", "csrc/internal.h", "csrc/binning.h"],
+           "k_blend_bwd": ["csrc/blend.hip", "csrc/internal.h", "csrc/binning.h"]}
 
 
 def source_hash(kernel: str) -> str:

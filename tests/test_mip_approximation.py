@@ -1,5 +1,5 @@
 """Error of the approximate MIP of eq. (17) against the exact per-ray MIP
-weight of Sec. 5 / App. B (both from the oracle).  The paper argues that the
+weight of Sec. 5 / App. A.5 (both from the oracle).  The paper argues that the
 approximation holds for Gaussians whose rays gather near the mean and is
 least accurate for thin primitives stretched over a wide cone of rays; these
 checks measure that on single Gaussians at the paper's footprint (0.1 px^2)

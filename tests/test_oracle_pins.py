@@ -603,7 +603,7 @@ def test_mip_modulation_matches_determinant_form(oracle_lib):
     assert abs(m["o"] / p["o"] - s2 / (s2 + opts["mip_sigma2_px"] / f**2 * (p["mu"] @ p["mu"]))) < 1e-12
 
 
-# ------------------------------------------------- exact MIP (Sec. 5, App. B)
+# ------------------------------------------------- exact MIP (Sec. 5, App. A.5)
 def _tangent_frame(x):
     """Orthonormal F (3x2) with F^T x = 0, from the SVD of x^T."""
     _, _, vt = np.linalg.svd(x[None, :])
@@ -628,7 +628,7 @@ def _pixel_solid_angle(cam, px, py):
 
 
 def _mip_exact_by_tangent_plane(mu, Rp, s, o, sig2_px, cam, px, py):
-    """The per-ray MIP weight from the tangent-plane Gaussian of App. B,
+    """The per-ray MIP weight from the tangent-plane Gaussian of App. A.5,
     before any of its identities: tau(x) by brute-force minimisation along the
     unit ray, sigma_x^2 = sigma_px^2 times the pixel's solid angle (the area it
     subtends at unit distance), Sigma^ = Sigma + sigma_x^2 tau^2 I, the exponent
@@ -651,7 +651,7 @@ def _mip_exact_by_tangent_plane(mu, Rp, s, o, sig2_px, cam, px, py):
 def test_mip_exact_weight_matches_tangent_plane_form(oracle_lib):
     """The oracle's per-ray exact MIP weight (Rp^T-frame scales, D_ray of the
     widened covariance, determinant-identity modulation) equals the weight
-    written on the ray's tangent plane (App. B before equalities (a)-(d)),
+    written on the ray's tangent plane (App. A.5 before equalities (a)-(d)),
     with tau found by search and the pixel footprint as a solid angle."""
     rng = np.random.default_rng(31)
     # a long focal length keeps the pixel-centre footprint within ~1e-6 of
