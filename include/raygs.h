@@ -173,6 +173,28 @@ rgs_status rgs_workspace_size(rgs_context *ctx, int64_t n, const rgs_camera *cam
 rgs_status rgs_render(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
                       const rgs_options *opts, const rgs_workspace *ws, const rgs_view_out *outs, void *stream);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): rgs_render without a workspace argument.
+ * The frame's intermediate state lives in a scratch array the library holds
+ * on each device (256 MiB, reserved when the first context on that device is
+ * created and kept until the process ends); the call allocates nothing, on
+ * the device or the host.  The frame is laid out in the scratch with the
+ * largest instance capacity that fits.  A frame that does not fit with room
+ * for a single instance (about 180 bytes per Gaussian-view plus a few MiB)
+ * is rejected with RGS_EINVAL and a message giving both sizes.  tile_w =
+ * tile_h = 0 means 8x16 here (the autotuned shapes are not consulted).
+ * instances_needed (device, 8-byte aligned, may be NULL) receives, in stream
+ * order, the Gaussian-tile instances the frame needed; when that exceeds the
+ * capacity every view is rendered as background.  Every call on a device
+ * shares that device's scratch, which keeps the last frame's contents: calls
+ * that overlap in time on one device (other streams, other host threads)
+ * race and give wrong images.  Not for HIP graph capture: the view table is
+ * copied from host memory that the call does not keep.  No backward pass
+ * reads this scratch (use rgs_render with an RGS_WS_BACKWARD workspace). */
+rgs_status rgs_render_noalloc(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
+                              const rgs_options *opts, const rgs_view_out *outs, int64_t *instances_needed,
+                              void *stream);
+
 /* Synchronises `stream`, then reads the instance count of the last frame
  * rendered into `ws` (*instances, may be NULL).  Returns RGS_OK, or
  * RGS_EOVERFLOW when that count exceeded ws->capacity. */

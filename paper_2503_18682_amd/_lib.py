@@ -73,6 +73,8 @@ EXPORTS = {
                                      C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]),
     "rgs_render": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.POINTER(Camera), C.c_int32, C.POINTER(Options),
                              C.POINTER(Workspace), C.POINTER(ViewOut), C.c_void_p]),
+    "rgs_render_noalloc": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.POINTER(Camera), C.c_int32,
+                                     C.POINTER(Options), C.POINTER(ViewOut), C.c_void_p, C.c_void_p]),
     "rgs_render_status": (C.c_int, [C.c_void_p, C.POINTER(Workspace), C.c_void_p, C.POINTER(C.c_int64)]),
     "rgs_render_backward": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.POINTER(Camera), C.c_int32,
                                       C.POINTER(Options), C.POINTER(Workspace), C.POINTER(ViewOut),

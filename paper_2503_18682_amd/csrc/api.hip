@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -62,6 +63,45 @@ struct FrameShape {
 
 }  // namespace
 
+namespace {
+
+// Device scratch of rgs_render_noalloc: the whole frame workspace of that
+// entry point lives here instead of in caller memory.  Each device the
+// library runs on holds its own copy until the process ends.  In host code
+// `scratch` only names the symbol; its device address on each device is
+// looked up once (rgs_create, with that device current) and kept in
+// g_scratch, and only that address is ever handed to kernels or copies.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch[kMaxDevices] = {};
+hipError_t g_scratch_error[kMaxDevices] = {};
+
+// Looks up the scratch address of `device` (once per device).  Returns the
+// runtime's error when the lookup failed.
+hipError_t scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch[device] || g_scratch_error[device] != hipSuccess) return g_scratch_error[device];
+    int prev = 0;
+    hipError_t e = hipGetDevice(&prev);
+    if (e == hipSuccess) e = hipSetDevice(device);
+    void *p = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    (void)hipSetDevice(prev);
+    if (e == hipSuccess && !p) e = hipErrorInvalidSymbol;
+    if (e == hipSuccess)
+        g_scratch[device] = p;
+    else
+        g_scratch_error[device] = e;
+    return e;
+}
+
+}  // namespace
+
 struct rgs_context {
     int device = 0;
     int num_cus = 256;
@@ -78,6 +118,9 @@ struct rgs_context {
     // What the last frame rendered into each workspace (keyed by its device
     // address) was laid out for: the backward pass reads that frame's buffers.
     std::map<const void *, FrameShape> ws_frames;
+    // Host image of a frame header for rgs_render_noalloc, sized for the
+    // largest batch when the context is made, so that call allocates nothing.
+    std::vector<unsigned char> noalloc_header;
 };
 
 struct rgs_plan {
@@ -324,15 +367,18 @@ DevOptions dev_options(const rgs_options &o)
     return d;
 }
 
-// Host image of the workspace header: counters followed by the view table.
-std::vector<unsigned char> build_header(const Layout &L, const rgs_camera *cams, int n_views,
-                                        const rgs_view_out *outs, const float *const *dL)
+// Host image of the workspace header: counters followed by the view table,
+// written to buf (header_bytes(L, n_views) bytes).
+size_t header_bytes(const Layout &L, int n_views) { return L.views + sizeof(DevView) * n_views; }
+
+void write_header(unsigned char *buf, const Layout &L, const rgs_camera *cams, int n_views, const rgs_view_out *outs,
+                  const float *const *dL)
 {
-    std::vector<unsigned char> buf(L.views + sizeof(DevView) * n_views, 0);
-    int64_t *counters = reinterpret_cast<int64_t *>(buf.data() + L.counters);
+    std::memset(buf, 0, header_bytes(L, n_views));
+    int64_t *counters = reinterpret_cast<int64_t *>(buf + L.counters);
     counters[0] = 0;
     counters[1] = L.capacity;
-    DevView *views = reinterpret_cast<DevView *>(buf.data() + L.views);
+    DevView *views = reinterpret_cast<DevView *>(buf + L.views);
     int base = 0;
     for (int v = 0; v < n_views; ++v) {
         const rgs_camera &c = cams[v];
@@ -355,6 +401,13 @@ std::vector<unsigned char> build_header(const Layout &L, const rgs_camera *cams,
         d.n_contrib = outs ? outs[v].n_contrib : nullptr;
         d.dL_drgb = dL ? dL[v] : nullptr;
     }
+}
+
+std::vector<unsigned char> build_header(const Layout &L, const rgs_camera *cams, int n_views,
+                                        const rgs_view_out *outs, const float *const *dL)
+{
+    std::vector<unsigned char> buf(header_bytes(L, n_views));
+    write_header(buf.data(), L, cams, n_views, outs, dL);
     return buf;
 }
 
@@ -557,6 +610,10 @@ rgs_status rgs_create(int device, rgs_context **out)
     rgs_context *ctx = new rgs_context();
     ctx->device = device;
     ctx->num_cus = cus > 0 ? cus : 256;
+    ctx->err.reserve(512);  // error messages are at most 511 characters
+    ctx->noalloc_header.resize(align_up(8 * sizeof(int64_t)) + sizeof(DevView) * kMaxViews);
+    // the scratch of rgs_render_noalloc; a failed lookup is reported by that call
+    (void)scratch_setup(device);
     *out = ctx;
     return RGS_OK;
 }
@@ -626,6 +683,58 @@ rgs_status rgs_render(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera
     if (st == RGS_OK) ctx->ws_frames[ws->ptr] = frame_shape(*opts, g->n, n_views, *ws);
     if (st == RGS_OK && ctx->timing) ++ctx->frames;  // frames whose stages were timed
     return st;
+}
+
+rgs_status rgs_render_noalloc(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
+                              const rgs_options *opts, const rgs_view_out *outs, int64_t *instances_needed,
+                              void *stream)
+{
+    if (!ctx) return RGS_EINVAL;
+    ctx->err.clear();
+    rgs_status st = check_gaussians(ctx, g);
+    if (st != RGS_OK) return st;
+    if (!opts) return fail(ctx, RGS_EINVAL, "opts is NULL");
+    if (ctx->device < 0 || ctx->device >= kMaxDevices || !g_scratch[ctx->device])
+        return fail(ctx, RGS_EHIP, "no scratch on device %d: %s", ctx->device,
+                    hipGetErrorString(ctx->device >= 0 && ctx->device < kMaxDevices ? g_scratch_error[ctx->device]
+                                                                                     : hipErrorInvalidDevice));
+    void *const ws = g_scratch[ctx->device];
+    // tile (0, 0) is the default shape: the tuned-shape cache is not consulted
+    // (its key is built on the heap)
+    rgs_options o = *opts;
+    if (o.tile_w == 0 && o.tile_h == 0) {
+        o.tile_w = kDefaultTile.w;
+        o.tile_h = kDefaultTile.h;
+    }
+    // the largest instance capacity whose layout fits the scratch
+    Layout L;
+    if ((st = compute_layout(ctx, g->n, cams, n_views, &o, 1, 0, L)) != RGS_OK) return st;
+    if (L.total > kScratchBytes)
+        return fail(ctx, RGS_EINVAL, "the frame needs %zu bytes of scratch with room for a single instance; the "
+                                     "scratch holds %zu (fewer Gaussians or views, or rgs_render)",
+                    L.total, kScratchBytes);
+    int64_t lo = 1, hi = 0xffffffffLL;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        Layout M;
+        if (compute_layout(ctx, g->n, cams, n_views, &o, mid, 0, M) == RGS_OK && M.total <= kScratchBytes)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    ctx->err.clear();
+    if ((st = compute_layout(ctx, g->n, cams, n_views, &o, lo, 0, L)) != RGS_OK) return st;
+    if ((st = check_outs(ctx, outs, n_views)) != RGS_OK) return st;
+    if (reinterpret_cast<uintptr_t>(instances_needed) % 8)
+        return fail(ctx, RGS_EINVAL, "instances_needed must be 8-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    RGS_HIP(ctx, hipSetDevice(ctx->device));
+    unsigned char *hdr = ctx->noalloc_header.data();
+    write_header(hdr, L, cams, n_views, outs, nullptr);
+    RGS_HIP(ctx, hipMemcpyAsync(ws, hdr, header_bytes(L, n_views), hipMemcpyHostToDevice, s));
+    if ((st = enqueue_forward(ctx, *g, n_views, o, L, ws, s, false)) != RGS_OK) return st;
+    if (instances_needed) RGS_HIP(ctx, launch_copy_i64(at<int64_t>(ws, L.counters), instances_needed, s));
+    return RGS_OK;
 }
 
 rgs_status rgs_render_status(rgs_context *ctx, const rgs_workspace *ws, void *stream, int64_t *instances)

@@ -186,6 +186,9 @@ hipError_t launch_preprocess_backward(const rgs_gaussians &g, const DevView *vie
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t stream);
 
+// *dst = *src (one int64, device to device), stream-ordered.
+hipError_t launch_copy_i64(const int64_t *src, int64_t *dst, hipStream_t stream);
+
 // dst[p][y][x] = mean of src[p][y f + r][x f + c] over r, c < f (src is
 // [planes][height f][width f]).
 hipError_t launch_downsample_box(const float *src, int width, int height, int factor, int planes, float *dst,

@@ -498,6 +498,11 @@ __global__ __launch_bounds__(kThreads) void k_fill_u32(uint32_t *__restrict__ p,
     if (i < n) p[i] = value;
 }
 
+__global__ void k_copy_i64(const int64_t *__restrict__ src, int64_t *__restrict__ dst)
+{
+    if (threadIdx.x == 0) *dst = *src;
+}
+
 __global__ __launch_bounds__(kThreads) void k_tile_ranges(const uint32_t *__restrict__ inst_tiles,
                                                           const int64_t *__restrict__ counters, int64_t capacity,
                                                           int64_t total_tiles, uint2 *__restrict__ ranges)
@@ -722,6 +727,12 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t s
 {
     if (n <= 0) return hipSuccess;
     k_fill_u32<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, stream>>>(p, value, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_i64(const int64_t *src, int64_t *dst, hipStream_t stream)
+{
+    k_copy_i64<<<1, 64, 0, stream>>>(src, dst);
     return hipGetLastError();
 }
 
