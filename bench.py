@@ -15,7 +15,8 @@ The default (all) prints one JSON line with the three parts of the metric:
                 all 8 views in one graph replay (8 plain single-view renders
                 reported beside it).
   c3            backward ms/view: 1M Gaussians, 4 views at 1600x1060; a step is
-                forward + L1 loss gradient + backward.
+                forward + L1 loss gradient + backward, at the tile shape the
+                library's training autotuner picks (--no-autotune: --tile).
 Each part carries a roofline object for its compositing kernel (forward for c1
 and c2, backward for c3); a leg that fails reports its error in place of its
 figures and the line is still printed.
@@ -93,7 +94,7 @@ def parse():
     ap.add_argument("--stage-steps", type=int, default=32, help="frames of the per-stage timing pass")
     ap.add_argument("--tile", default="8x16", help="tile shape WxH, each of 8, 16, 32")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="c4: use --tile instead of the training autotuner (for profiling runs)")
+                    help="c3, c4: use --tile instead of the training autotuner (for profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference for HBM counters)")
     return ap.parse_args()
@@ -135,14 +136,16 @@ def stage_pass(r, g, cams_seq, opts, ws, outs, frames):
 
 
 def pmc_traffic(stage, workload):
-    """HBM bytes per launch of the compositing kernel from the committed
-    counter summary (profiles/), or None when there is none for this
-    workload or the kernel's sources changed since it was taken."""
-    if stage != "blend":
+    """HBM bytes per launch of a compositing kernel (stage blend: k_blend,
+    blend_backward: k_blend_bwd) from the committed counter summary
+    (profiles/<stage>_<workload>_pmc_traffic.txt), or None when there is none
+    for this workload or the kernel's sources changed since it was taken."""
+    kernel = {"blend": "k_blend", "blend_backward": "k_blend_bwd"}.get(stage)
+    if kernel is None:
         return None
     from paper_2503_18682_amd.prof_summary import read_traffic
 
-    return read_traffic(os.path.join(ROOT, "profiles", f"blend_{workload}_pmc_traffic.txt"), "k_blend")
+    return read_traffic(os.path.join(ROOT, "profiles", f"{stage}_{workload}_pmc_traffic.txt"), kernel)
 
 
 def roofline_for(stage, ms, *, flops=None, nbytes=None, traffic=None):
@@ -173,14 +176,14 @@ def cpu_baseline_c1(scene, cam, opts):
 
     threads = os.cpu_count() or 1
     t = time.perf_counter()
-    oracle.render(scene, cam, opts, rows=(0, 0), threads=threads)
+    oracle.render(scene, cam, opts, rows=(0, 0), threads=threads, branches=False)
     t_fixed = time.perf_counter() - t
     H = cam["height"]
     band, rows_done, t_rows = 6, 0, 0.0
     for b in range(8):
         a = int((b + 0.5) * H / 8) - band // 2
         t = time.perf_counter()
-        oracle.render(scene, cam, opts, rows=(a, a + band), threads=threads)
+        oracle.render(scene, cam, opts, rows=(a, a + band), threads=threads, branches=False)
         t_rows += max(time.perf_counter() - t - t_fixed, 0.0)
         rows_done += band
     frame_s = t_fixed + t_rows * H / rows_done
@@ -336,15 +339,30 @@ def bench_c3(args, torch):
     n = int(sc["opacity_logits"].shape[0])
     g = to_dev(sc, torch)
     targets = [torch.from_numpy(t).cuda() for t in w["targets"]]
+    total = sum(t.numel() for t in targets)
     r = R.Renderer(0, opts)
+    outs = r.allocate_outputs(cams)
+    tile_from = "--tile"
+    if not args.no_autotune:
+        # the tile shape of the fastest training step (render + backward), timed
+        # by the library's autotuner in a workspace with room for the finest tiles
+        fine = dict(opts, tile_w=8, tile_h=8)
+        _, (buf, ws) = r.render(g, cams, fine, keep_workspace=True)
+        need = r.status(ws)[1]
+        del buf, ws
+        buf, ws = r.new_workspace(n, cams, int(need * 1.1) + 4096, _lib.RGS_WS_BACKWARD, fine)
+        r.render_into(g, cams, outs, ws, fine)
+        dls = [torch.sign(o["rgb"] - t) / total for o, t in zip(outs, targets)]
+        opts, tune_ms = r.autotune_training(g, cams, ws, outs, dls, reps=3, options=opts)
+        tile_from = "rgs_autotune_training"
+        log(f"c3: autotuned tile {opts['tile_w']}x{opts['tile_h']} ({tune_ms:.2f} ms per render + backward)")
+        del buf, ws, dls
     _, (buf, ws) = r.render(g, cams, opts, flags=_lib.RGS_WS_BACKWARD, keep_workspace=True)
     need = r.status(ws)[1]
     del buf
     capacity = int(need * 1.1) + 4096
     buf, ws = r.new_workspace(n, cams, capacity, _lib.RGS_WS_BACKWARD, opts)
-    outs = r.allocate_outputs(cams)
     grads = {k: torch.zeros_like(g[k]) for k in R.PARAM_KEYS}
-    total = sum(t.numel() for t in targets)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
 
     def step():
@@ -380,10 +398,12 @@ def bench_c3(args, torch):
         "metric_part": "backward ms/view", "value": bwd / args.steps / len(cams), "unit": "backward ms/view",
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": False,
         "config": {"workload": "c3: 1M Gaussians (SH3), 4 views 1600x1060, forward + L1 + backward"
-                   + (" (exact per-ray MIP)" if args.mip == "exact" else ""), "tile": args.tile,
+                   + (" (exact per-ray MIP)" if args.mip == "exact" else ""),
+                   "tile": f"{opts['tile_w']}x{opts['tile_h']}", "tile_from": tile_from,
                    "instance_capacity": capacity},
         "roofline": roofline_for("blend_backward", stages["blend_backward"], flops=flops,
-                                 traffic=pmc_traffic("blend_backward", "c3_train_1m_4views_" + args.tile)),
+                                 traffic=pmc_traffic("blend_backward",
+                                                     f"c3_train_1m_4views_{opts['tile_w']}x{opts['tile_h']}")),
         "stages_ms": stages,
     }
     r.close()

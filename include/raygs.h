@@ -35,8 +35,9 @@
  *     pixel (x, y) is the ray through ((x + 1/2 - cx)/fx, (y + 1/2 - cy)/fy, 1).
  *   - Images are float32, planar: rgb[3][H][W]; final_T[H][W] is the
  *     transmittance left after compositing; n_contrib[H][W] (int32) is the
- *     1-based position, in the pixel's tile list, of the last Gaussian that
- *     contributed (0 if none).
+ *     number of entries of the pixel's tile list that compositing consumed:
+ *     the whole list, or the entries before the one at which it stopped
+ *     (the backward pass walks them back).
  *   - All work is queued on the caller's HIP stream (hipStream_t passed as
  *     void*; NULL = the null stream) and is asynchronous unless stated.
  *   - Errors are returned as rgs_status codes, never by abort; the message

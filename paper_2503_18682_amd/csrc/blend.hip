@@ -379,8 +379,12 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
         // pixel centres relative to the block corner; NaN marks a pixel that
         // is outside the image, outside the work item, or done
         const float pxr = (float)(px - ox) + 0.5f;
+        const uint2 rg = ranges[tile];
         float T[PPL], C0[PPL], C1[PPL], C2[PPL], pyr[PPL], aux[PPL];
         int last[PPL];
+        // pixel slots (row bands of 64 pixels) that hold a live pixel: a slot
+        // whose pixels have all stopped is skipped by the whole wave
+        uint32_t live = 0u;
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
             const int py = ty * TH + ly + k * LY;
@@ -389,10 +393,11 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
             aux[k] = M::pixel_aux(V, px, py);
             T[k] = 1.0f;
             C0[k] = C1[k] = C2[k] = 0.0f;
-            last[k] = 0;
+            // entries consumed: the whole list unless compositing stops
+            last[k] = (int)(rg.y - rg.x);
+            if (__ballot(on) != 0) live |= 1u << k;
         }
-        const uint2 rg = ranges[tile];
-        bool wave_live = true;
+        bool wave_live = live != 0u;
         // batch 0 goes straight to LDS; batch b+1 is fetched into registers
         // while batch b is composited
         if (rg.x + lane < rg.y) {
@@ -416,11 +421,9 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
                 const typename M::Rec R = M::load(s_rec[wave][j]);
                 const RowSpan span = row_span(R.rows, ty * TH);
                 const uint32_t bands = __builtin_amdgcn_readfirstlane(R.rows);
-                const int idx = (int)(base - rg.x + j + 1);
-                bool stopped = false;
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) {
-                    if (k < k_lo || k >= k_hi || !band_open<PPL, LY>(bands, span, k)) continue;
+                    if (!((live >> k) & 1u) || !band_open<PPL, LY>(bands, span, k)) continue;
                     // every lane evaluates the test; results are kept by selection
                     // (the values are those of a branch per lane, bit for bit)
                     typename M::F f;
@@ -438,19 +441,19 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
                     C1[k] = __builtin_fmaf(wt, R.g, C1[k]);
                     C2[k] = __builtin_fmaf(wt, R.b, C2[k]);
                     T[k] = take ? Tn : T[k];
-                    last[k] = take ? idx : last[k];
-                    pyr[k] = stop ? __builtin_nanf("") : pyr[k];
-                    stopped |= stop;
-                }
-                // a lane finished: leave the tile once no pixel is live
-                if (__ballot(stopped) != 0) {
-                    bool any = false;
-#pragma unroll
-                    for (int k = 0; k < PPL; ++k) any = any || (pyr[k] == pyr[k]);
-                    if (__ballot(any) == 0) {
-                        wave_live = false;
-                        break;
+                    if (__ballot(stop) != 0) {
+                        // some pixel of the slot stops before this entry: it has
+                        // consumed the entries before it, and it is done (a NaN
+                        // row offset fails every later test)
+                        last[k] = stop ? (int)(base - rg.x + j) : last[k];
+                        pyr[k] = stop ? __builtin_nanf("") : pyr[k];
+                        if (__ballot(pyr[k] == pyr[k]) == 0) live &= ~(1u << k);
                     }
+                }
+                // leave the tile once no pixel is live
+                if (live == 0u) {
+                    wave_live = false;
+                    break;
                 }
             }
             lds_wave_sync();
@@ -478,38 +481,59 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
 }
 
 // Sums of 16 per-lane values over the wave by transposing while reducing:
-// at each butterfly step a lane keeps one half of its values and sends the
-// other half to its partner, so the 16 sums take 8 + 4 + 2 + 1 + 1 + 1 = 17
-// exchanges instead of 16 * 6.  On return, lane l holds the sum of value
-// index ((l >> 5) & 1) * 8 + ((l >> 4) & 1) * 4 + ((l >> 3) & 1) * 2 +
+// at each step a lane keeps one half of its values and takes its partner's
+// copy of them, so 16 sums take 8 + 4 + 2 + 1 exchanges plus two for the last
+// value instead of 16 * 6.  The exchanges between the halves and quarters of
+// the wave are lane swaps (v_permlane32_swap / v_permlane16_swap: the two
+// halves of a pair of registers trade places, so the sum of the pair holds
+// one value's sum in each half); those inside 16-lane rows are DPP operands
+// (row_ror:8, row_half_mirror, quad_perm).  On return, lane l holds the sum of
+// value index ((l >> 5) & 1) * 8 + ((l >> 4) & 1) * 4 + ((l >> 3) & 1) * 2 +
 // ((l >> 2) & 1) (the same in the four lanes l & ~3 .. l | 3).
+__device__ __forceinline__ float lane_swap_sum32(float x, float y)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float lane_swap_sum16(float x, float y)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// x from the lane chosen by a DPP control word (a permutation inside each row)
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+
+constexpr int kDppRowRor8 = 0x128;        // lane i of a row takes lane (i + 8) mod 16
+constexpr int kDppRowHalfMirror = 0x141;  // lane i of an 8-lane group takes lane 7 - i
+constexpr int kDppQuadXor1 = 0xb1;        // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadXor2 = 0x4e;        // quad_perm [2, 3, 0, 1]
+
 __device__ __forceinline__ float wave_sum16(const float (&v)[16], int lane)
 {
     float a[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const bool up = lane & 32;
-        const float send = up ? v[i] : v[8 + i];
-        a[i] = (up ? v[8 + i] : v[i]) + __shfl_xor(send, 32, 64);
-    }
+    for (int i = 0; i < 8; ++i) a[i] = lane_swap_sum32(v[i], v[8 + i]);  // lanes 32..63 hold value 8 + i
     float b[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const bool up = lane & 16;
-        const float send = up ? a[i] : a[4 + i];
-        b[i] = (up ? a[4 + i] : a[i]) + __shfl_xor(send, 16, 64);
-    }
+    for (int i = 0; i < 4; ++i) b[i] = lane_swap_sum16(a[i], a[4 + i]);  // odd rows hold value 4 + i
     float c[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const bool up = lane & 8;
         const float send = up ? b[i] : b[2 + i];
-        c[i] = (up ? b[2 + i] : b[i]) + __shfl_xor(send, 8, 64);
+        c[i] = (up ? b[2 + i] : b[i]) + dpp<kDppRowRor8>(send);
     }
+    // lanes 0..3 and 4..7 of each 8-lane group pair up as i and 7 - i
     const bool up = lane & 4;
-    float x = (up ? c[1] : c[0]) + __shfl_xor(up ? c[0] : c[1], 4, 64);
-    x += __shfl_xor(x, 2, 64);
-    x += __shfl_xor(x, 1, 64);
+    float x = (up ? c[1] : c[0]) + dpp<kDppRowHalfMirror>(up ? c[0] : c[1]);
+    x += dpp<kDppQuadXor2>(x);
+    x += dpp<kDppQuadXor1>(x);
     return x;
 }
 
@@ -530,6 +554,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
     constexpr int LX = TW, LY = 64 / TW, PPL = TH / LY;
     __shared__ float4 s_rec[4][64][4];
     __shared__ uint32_t s_id[4][64];
+    const uint32_t amax_bits = __float_as_uint(P.alpha_max);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lx = lane % LX, ly = lane / LX;
     const int nq = min((int)gridDim.x, kQueues), q = (int)blockIdx.x % nq;
@@ -577,16 +602,33 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
         for (int d = 32; d >= 1; d >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, d, 64));
         const uint2 rg = ranges[tile];
         maxlast = min(maxlast, (int)(rg.y - rg.x));
-        for (int hi = maxlast; hi > 0; hi -= 64) {
-            const int lo = hi > 64 ? hi - 64 : 0;
-            const int nb = hi - lo;
-            if (lane < nb) {
+        // the last batch of the walked part of the list goes straight to LDS;
+        // each earlier batch is fetched into registers while one is walked back
+        if (maxlast > 0) {
+            const int lo = maxlast > 64 ? maxlast - 64 : 0;
+            if (lane < maxlast - lo) {
                 const uint32_t v = inst_ids[rg.x + lo + lane];
                 const uint32_t id = v & kIdMask;
                 s_id[wave][lane] = id < P.n_records ? id : 0xffffffffu;
                 float4 r[4];
                 fetch_record(r, records, v, P.n_records, PPL <= 4);
                 put_test_form(s_rec[wave][lane], r, x0, y0, P.log2_pmin);
+            }
+        }
+        for (int hi = maxlast; hi > 0; hi -= 64) {
+            const int lo = hi > 64 ? hi - 64 : 0;
+            const int nb = hi - lo;
+            const int nlo = lo > 64 ? lo - 64 : 0;
+            const bool have_next = lane < lo - nlo;
+            float4 pre[4];
+            uint32_t pre_id = 0xffffffffu;
+            if (have_next) {
+                const uint32_t v = inst_ids[rg.x + nlo + lane];
+                const uint32_t id = v & kIdMask;
+                pre_id = id < P.n_records ? id : 0xffffffffu;
+                float4 r[4];
+                fetch_record(r, records, v, P.n_records, PPL <= 4);
+                put_test_form(pre, r, x0, y0, P.log2_pmin);
             }
             lds_wave_sync();
             for (int jj = nb - 1; jj >= 0; --jj) {
@@ -595,8 +637,12 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                 const RowSpan span = row_span(R.rows, ty * TH);
                 const uint32_t bands = __builtin_amdgcn_readfirstlane(R.rows);
                 const float inv_o = __builtin_amdgcn_exp2f(-R.log2o);
-                float du0 = 0, dv0 = 0, dM00 = 0, dM01 = 0, dM11 = 0, dgx = 0, dgy = 0, dk0 = 0, dic2 = 0, dop = 0,
-                      dr = 0, dg = 0, db = 0;
+                const float dx = pxr - R.cx;  // the same in every slot of the lane
+                // sums over the lane's pixels of dL/dq, dL/dq dy, dL/dq dy^2,
+                // dL/dden and dL/dden dy (q, den, D as in frag_test); the
+                // record gradients follow from them once per record
+                float sq = -0.0f, sqy = -0.0f, syy = -0.0f, sd = -0.0f, sdy = -0.0f, dic2 = -0.0f, dop = -0.0f;
+                float dr = -0.0f, dg = -0.0f, db = -0.0f;
                 bool wave_hit = false;
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) {
@@ -611,43 +657,48 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                     frag_omega(R, f);
                     const float w = hit ? f.w : 0.0f;
                     const float rt = hit ? f.rt : 0.0f;
-                    const float a = fminf(w, P.alpha_max);
+                    // omega >= 0, alpha_max > 0: the minimum of the bit patterns
+                    const float a = __uint_as_float(min(__float_as_uint(w), amax_bits));
                     const float rom = __builtin_amdgcn_rcpf(1.0f - a);  // 1 / (1 - alpha), alpha <= alpha_max
                     const float Tb = T[k] * rom;  // transmittance in front of this Gaussian
-                    const float rgd = R.r * g0[k] + R.g * g1[k] + R.b * g2[k];
+                    const float rgd = __builtin_fmaf(R.b, g2[k], __builtin_fmaf(R.g, g1[k], R.r * g0[k]));
                     const float ta = Tb * a;
-                    dr += ta * g0[k];
-                    dg += ta * g1[k];
-                    db += ta * g2[k];
-                    const float dL_da = Tb * rgd - S[k] * rom;
-                    S[k] += ta * rgd;
+                    dr = __builtin_fmaf(ta, g0[k], dr);
+                    dg = __builtin_fmaf(ta, g1[k], dg);
+                    db = __builtin_fmaf(ta, g2[k], db);
+                    const float dL_da = __builtin_fmaf(Tb, rgd, -(S[k] * rom));
+                    S[k] = __builtin_fmaf(ta, rgd, S[k]);
                     T[k] = Tb;
                     // alpha clamped at alpha_max passes no gradient to omega
-                    const float dL_dw = w < P.alpha_max ? dL_da : 0.0f;
-                    dop += dL_dw * w * inv_o;
-                    const float dL_dD = -0.5f * w * dL_dw;
-                    const float rt2 = rt * rt;
-                    // with the test form's qs = s^2 q in place of q, dL/dden and
-                    // the sums through it (dk0, dg, du0, dv0) come out times s^2
-                    // and dic2 times s^4; they are rescaled once per record below
-                    const float dL_dq = dL_dD * (f.den * f.den) * rt2;
-                    const float dL_dden = dL_dD * (-2.0f * f.q * f.den) * rt2;
-                    dic2 += dL_dD * (-(f.q * f.q)) * rt2;
-                    dM00 += dL_dq * (f.dx * f.dx);
-                    dM01 += dL_dq * (2.0f * f.dx * f.dy);
-                    dM11 += dL_dq * (f.dy * f.dy);
-                    dk0 += dL_dden;
-                    dgx += dL_dden * f.dx;
-                    dgy += dL_dden * f.dy;
-                    // dq/ddelta = 2 G^T G delta = 2 H^T n / s^2 (the 1 / s^2 is part
-                    // of the rescaling)
-                    const float dq_ddx = 2.0f * (R.H00 * f.n0 + R.H10 * f.n1);
-                    const float dq_ddy = 2.0f * (R.H01 * f.n0 + R.H11 * f.n1);
-                    du0 -= dL_dq * dq_ddx + dL_dden * R.gx;
-                    dv0 -= dL_dq * dq_ddy + dL_dden * R.gy;
+                    const float wd = w < P.alpha_max ? w * dL_da : 0.0f;
+                    dop = __builtin_fmaf(wd, inv_o, dop);
+                    // dL/dD = -w dL/domega / 2; D = q / t with t = den^2 + q / c^2.
+                    // With the test form's qs = s^2 q in place of q, the sums
+                    // through dL/dden (dk0, dg, du0, dv0) come out times s^2 and
+                    // dic2 times s^4; they are rescaled once per record below
+                    const float e = (-0.5f * wd) * (rt * rt);
+                    const float dq = e * (f.den * f.den);
+                    const float dden = (-2.0f * e) * (f.q * f.den);
+                    dic2 = __builtin_fmaf(e, -(f.q * f.q), dic2);
+                    const float dqy = dq * f.dy;
+                    sq += dq;
+                    sqy += dqy;
+                    syy = __builtin_fmaf(dqy, f.dy, syy);
+                    sd += dden;
+                    sdy = __builtin_fmaf(dden, f.dy, sdy);
                 }
                 if (!wave_hit) continue;
-                const float vals[16] = {du0, dv0, dM00, dM01, dM11, dgx, dgy, dk0, dic2, dop, dr, dg, db, 0.f, 0.f, 0.f};
+                // q = delta^T M delta with M = H^T H: dL/dM00 = sum dq dx^2,
+                // dL/dM01 = sum dq 2 dx dy, dL/dM11 = sum dq dy^2; dq/ddelta =
+                // 2 M delta, so dL/du0 = -(2 M sum dq delta + g sum dden)
+                const float Mxx = __builtin_fmaf(R.H10, R.H10, R.H00 * R.H00);
+                const float Mxy = __builtin_fmaf(R.H10, R.H11, R.H00 * R.H01);
+                const float Myy = __builtin_fmaf(R.H11, R.H11, R.H01 * R.H01);
+                const float sqx = dx * sq;
+                const float du0 = __builtin_fmaf(-2.0f, __builtin_fmaf(Mxx, sqx, Mxy * sqy), -(R.gx * sd));
+                const float dv0 = __builtin_fmaf(-2.0f, __builtin_fmaf(Mxy, sqx, Myy * sqy), -(R.gy * sd));
+                const float vals[16] = {du0, dv0, dx * sqx, 2.0f * (dx * sqy), syy, dx * sd, sdy, sd, dic2, dop, dr,
+                                        dg, db, 0.f, 0.f, 0.f};
                 const float sum = wave_sum16(vals, lane);
                 const int c = wave_sum16_index(lane);
                 const uint32_t rid = s_id[wave][jj];
@@ -658,6 +709,11 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                     atomicAdd(record_grads + (size_t)rid * kGradFloats + c, sum * unit);
             }
             lds_wave_sync();
+            if (have_next) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) s_rec[wave][lane][c] = pre[c];
+                s_id[wave][lane] = pre_id;
+            }
         }
     }
 }
