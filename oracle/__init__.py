@@ -9,7 +9,7 @@ from .oracle import (  # noqa: F401
     preprocess,
     render,
     render_pixels,
-    support_rows,
+    support_cells,
     backward,
     tile_lists,
     sh_basis,

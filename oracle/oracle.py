@@ -79,7 +79,8 @@ def load():
         lib.orc_preprocess.argtypes = [P, P, P, P, C.c_int]
         lib.orc_render.argtypes = [P, P, P, C.c_int, C.c_int, C.c_int, P, P, P, P, P]
         lib.orc_render_pixels.argtypes = [P, P, P, P, P, C.c_int64, C.c_int, P, P, P, P, P, C.c_int]
-        lib.orc_support_rows.argtypes = [P, P, P, C.c_int32, P, P, C.c_int64, P, C.c_int]
+        lib.orc_support_cells.argtypes = [P, P, P, C.c_int32, P, P, C.c_int64, C.c_int32, C.c_int32, P, C.c_int]
+        lib.orc_support_cells.restype = C.c_int
         lib.orc_backward.argtypes = [P, P, P, P, P, P, P, P, P]
         lib.orc_sh_basis.argtypes = [C.c_int, P, P, P]
         lib.orc_divergence.argtypes = [P, P, P, P, P, P]
@@ -200,21 +201,23 @@ def render_pixels(scene, cam, opts, px, py, threads=None):
     return dict(rgb=rgb, T=T, hazard=hz, leaves=leaves)
 
 
-def support_rows(splats, cam, opts, tiles, ids, threads=None):
+def support_cells(splats, cam, opts, tiles, ids, cell_w, cell_h, threads=None):
     """For each (tile, Gaussian index) pair of one view, the bit mask of the
-    tile's pixel rows (bit r = row ty * tile_h + r) that hold a pixel centre of
-    the Gaussian's support: inside its pixel box, omega >= p_min and tau > 0,
-    both clear of their rounding margins."""
+    tile's cells of cell_w x cell_h pixels (bit cy * (tile_w / cell_w) + cx)
+    that hold a pixel centre of the Gaussian's support: inside its pixel box,
+    omega >= p_min and tau > 0, both clear of their rounding margins."""
     lib = load()
     sp = np.ascontiguousarray(splats)
     tiles = np.ascontiguousarray(tiles, np.int64)
     ids = np.ascontiguousarray(ids, np.int64)
-    rows = np.zeros(max(len(tiles), 1), np.uint32)
+    cells = np.zeros(max(len(tiles), 1), np.uint32)
     tiles_x = -(-int(cam["width"]) // int(opts["tile_w"]))
     c, o = _camera(cam), _options(opts)
-    lib.orc_support_rows(_ptr(sp), C.byref(c), C.byref(o), tiles_x, _ptr(tiles), _ptr(ids), len(tiles), _ptr(rows),
-                         _threads(threads))
-    return rows[:len(tiles)]
+    rc = lib.orc_support_cells(_ptr(sp), C.byref(c), C.byref(o), tiles_x, _ptr(tiles), _ptr(ids), len(tiles),
+                               int(cell_w), int(cell_h), _ptr(cells), _threads(threads))
+    if rc != 0:
+        raise ValueError("cells must divide the tile, at most 32 of them")
+    return cells[:len(tiles)]
 
 
 def backward(scene, cam, opts, dL_dC):

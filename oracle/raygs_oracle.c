@@ -1296,29 +1296,29 @@ int orc_render_pixels(const orc_scene *sc, const orc_camera *cam, const orc_opti
     return 0;
 }
 
-/* Rows of tile (tx, ty) holding a pixel centre of the support of splat s:
+/* Cells of tile (tx, ty) holding a pixel centre of the support of splat s:
  * inside its pixel box, with omega >= p_min and the peak in front of the
- * camera, both decisions clear of their margins.  Bit r stands for pixel row
- * ty * tile_h + r. */
-static uint32_t tile_support_rows(const orc_splat *s, const orc_camera *cam, const orc_options *opt, int tx, int ty)
+ * camera, both decisions clear of their margins.  The tile is cut into cells
+ * of cw x ch pixels; bit cy * (tile_w / cw) + cx stands for cell (cx, cy). */
+static uint32_t tile_support_cells(const orc_splat *s, const orc_camera *cam, const orc_options *opt, int tx, int ty,
+                                   int cw, int ch)
 {
-    uint32_t rows = 0;
+    uint32_t cells = 0;
+    const int ncx = opt->tile_w / cw;
     for (int r = 0; r < opt->tile_h; ++r) {
         int py = ty * opt->tile_h + r;
         if (py < s->py0 || py > s->py1) continue;
         for (int c = 0; c < opt->tile_w; ++c) {
             int px = tx * opt->tile_w + c;
-            if (px < s->px0 || px > s->px1) continue;
+            uint32_t bit = 1u << ((r / ch) * ncx + c / cw);
+            if (px < s->px0 || px > s->px1 || (cells & bit)) continue;
             double x[3] = {(px + 0.5 - cam->cx) / cam->fx, (py + 0.5 - cam->cy) / cam->fy, 1.0};
             int front, front_hz;
             double w = pixel_weight(s, px, py, x, &front, &front_hz);
-            if (front && !front_hz && w >= opt->p_min * (1.0 + ORC_MARGIN_OMEGA)) {
-                rows |= 1u << r;
-                break;
-            }
+            if (front && !front_hz && w >= opt->p_min * (1.0 + ORC_MARGIN_OMEGA)) cells |= bit;
         }
     }
-    return rows;
+    return cells;
 }
 
 typedef struct {
@@ -1326,37 +1326,41 @@ typedef struct {
     const orc_camera *cam;
     const orc_options *opt;
     const int64_t *tiles, *ids;
-    int32_t tiles_x;
+    int32_t tiles_x, cw, ch;
     int64_t begin, end;
-    uint32_t *rows;
-} rows_job;
+    uint32_t *cells;
+} cells_job;
 
-static void *rows_worker(void *arg)
+static void *cells_worker(void *arg)
 {
-    rows_job *j = (rows_job *)arg;
+    cells_job *j = (cells_job *)arg;
     for (int64_t k = j->begin; k < j->end; ++k) {
         int tx = (int)(j->tiles[k] % j->tiles_x), ty = (int)(j->tiles[k] / j->tiles_x);
-        j->rows[k] = tile_support_rows(&j->sp[j->ids[k]], j->cam, j->opt, tx, ty);
+        j->cells[k] = tile_support_cells(&j->sp[j->ids[k]], j->cam, j->opt, tx, ty, j->cw, j->ch);
     }
     return NULL;
 }
 
 /* For each (tile, splat) pair k (tile = ty * tiles_x + tx of one view), the
- * rows of the tile that hold a pixel centre of the splat's support
- * (tile_support_rows) in rows[k].  sp is the output of orc_preprocess. */
-int orc_support_rows(const orc_splat *sp, const orc_camera *cam, const orc_options *opt, int32_t tiles_x,
-                     const int64_t *tiles, const int64_t *ids, int64_t m, uint32_t *rows, int nthreads)
+ * cells of cw x ch pixels of the tile that hold a pixel centre of the splat's
+ * support (tile_support_cells) in cells[k]; at most 32 cells per tile.  sp is
+ * the output of orc_preprocess. */
+int orc_support_cells(const orc_splat *sp, const orc_camera *cam, const orc_options *opt, int32_t tiles_x,
+                      const int64_t *tiles, const int64_t *ids, int64_t m, int32_t cw, int32_t ch, uint32_t *cells,
+                      int nthreads)
 {
+    if (cw < 1 || ch < 1 || opt->tile_w % cw || opt->tile_h % ch || (opt->tile_w / cw) * (opt->tile_h / ch) > 32)
+        return -1;
     nthreads = clamp_threads(nthreads);
     pthread_t th[256];
-    rows_job jobs[256];
+    cells_job jobs[256];
     int64_t chunk = (m + nthreads - 1) / nthreads;
     int used = 0;
     for (int k = 0; k < nthreads; ++k) {
         int64_t b = k * chunk, e = (k + 1) * chunk < m ? (k + 1) * chunk : m;
         if (b >= e) break;
-        jobs[k] = (rows_job){sp, cam, opt, tiles, ids, tiles_x, b, e, rows};
-        pthread_create(&th[k], NULL, rows_worker, &jobs[k]);
+        jobs[k] = (cells_job){sp, cam, opt, tiles, ids, tiles_x, cw, ch, b, e, cells};
+        pthread_create(&th[k], NULL, cells_worker, &jobs[k]);
         ++used;
     }
     for (int k = 0; k < used; ++k) pthread_join(th[k], NULL);

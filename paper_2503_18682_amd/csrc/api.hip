@@ -519,7 +519,7 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
     tm.mark(ST_TSORT);
     const uint32_t *inst_tiles = at<uint32_t>(ws, L.inst_tiles_a);
     const uint32_t *inst_ids = at<uint32_t>(ws, L.inst_ids_a);
-    const uint32_t split_min = s.h / (64 / s.w) >= 2 ? (uint32_t)RGS_SPLIT_LEN : 0u;
+    const uint32_t split_min = slot_layout(s.w, s.h).slots >= 2 ? (uint32_t)RGS_SPLIT_LEN : 0u;
     const int blend_blocks = opts.mip == 2 ? ctx->grid_fwd_exact[shape_index(s)] : ctx->grid_fwd[shape_index(s)];
     const uint32_t waves = (uint32_t)(4 * blend_blocks);
     RGS_HIP(ctx, launch_tile_ranges(inst_tiles, listed, L.capacity, L.total_tiles, split_min, waves, ranges, sched,

@@ -93,23 +93,37 @@ __device__ inline bool conic_xrange(const Conic &C, const ConicFrame &F, double 
     return true;
 }
 
-// Row bands used for culling: rows [k*LY, (k+1)*LY) of a tile with
-// LY = 64 / TW (the rows one pixel slot of a compositing wave spans) when a
-// tile has at most 4 of them; a taller tile is tested as one band of TH rows.
-constexpr int kMaxBands = 4;
+// Pixel slots of a tile: the compositing kernels give each lane of a wave
+// one pixel of every slot, so a slot is 64 pixels that the whole wave skips
+// or evaluates together, and a tile's culling bands are its slots.  A tile
+// wider than 8 pixels that holds at most 4 blocks of 8 x 8 pixels is cut into
+// those blocks (slot k is block (k % bx, k / bx)); any other tile into row
+// bands of 64 / TW rows, the full tile width (bx = 1).  Up to 4 slots carry
+// per-instance culling bits; a tile with more is tested as one band of TH rows.
+struct SlotLayout {
+    int bx;     // slots across the tile
+    int cw;     // slot width (pixels)
+    int rh;     // slot height (pixel rows)
+    int slots;  // slots per tile
+    bool bits;  // each slot's culling bit travels with the instance
+};
 
-__device__ inline int cull_band_rows(int TW, int TH)
+__host__ __device__ constexpr SlotLayout slot_layout(int TW, int TH)
 {
-    const int LY = 64 / TW;
-    return TH / LY <= kMaxBands ? LY : TH;
+    return (TW >= 16 && (TW / 8) * (TH / 8) <= 4)
+               ? SlotLayout{TW / 8, 8, 8, (TW / 8) * (TH / 8), true}
+               : SlotLayout{1, TW, 64 / TW, TH / (64 / TW), TH / (64 / TW) <= 4};
 }
 
+constexpr int kMaxBands = 4;
+
 // x-extent of the ellipse, in pixels, over the pixel-centre heights of tile
-// row ty (clipped to the box) and over each of its culling bands.
+// row ty (clipped to the box) and over each row band of slots (the rows of
+// slot row r = k / bx).
 struct BandRanges {
     double row_xl, row_xr;
     double xl[kMaxBands], xr[kMaxBands];
-    uint32_t valid;  // bands with an extent
+    uint32_t valid;  // slot rows with an extent
     bool row_valid;  // the ellipse reaches the row's heights
 };
 
@@ -117,7 +131,8 @@ __device__ inline void band_ranges(const Conic &C, const ConicFrame &F, const Pi
                                    BandRanges &B)
 {
 #pragma clang fp contract(off)
-    const int LY = cull_band_rows(TW, TH), nb = TH / LY;
+    const SlotLayout S = slot_layout(TW, TH);
+    const int nr = S.bits ? S.slots / S.bx : 1, rh = S.bits ? S.rh : TH;  // slot rows
     B.valid = 0u;
     B.row_valid = false;
     B.row_xl = -INFINITY;
@@ -129,17 +144,17 @@ __device__ inline void band_ranges(const Conic &C, const ConicFrame &F, const Pi
     else
         B.row_valid = conic_xrange(C, F, (double)y0 + 0.5 - C.v0, (double)y1 + 0.5 - C.v0, B.row_xl, B.row_xr);
 #pragma unroll
-    for (int k = 0; k < kMaxBands; ++k) {
-        B.xl[k] = -INFINITY;
-        B.xr[k] = INFINITY;
-        if (k >= nb || !B.row_valid) continue;
-        const int r0 = max(ty * TH + k * LY, box.y0), r1 = min(ty * TH + k * LY + LY - 1, box.y1);
+    for (int r = 0; r < kMaxBands; ++r) {
+        B.xl[r] = -INFINITY;
+        B.xr[r] = INFINITY;
+        if (r >= nr || !B.row_valid) continue;
+        const int r0 = max(ty * TH + r * rh, box.y0), r1 = min(ty * TH + r * rh + rh - 1, box.y1);
         if (r0 > r1) continue;
         if (!F.bounded) {
-            B.valid |= 1u << k;
+            B.valid |= 1u << r;
             continue;
         }
-        if (nb == 1) {  // the band is the row
+        if (nr == 1) {  // the slot row is the tile row
             B.valid |= 1u;
             B.xl[0] = B.row_xl;
             B.xr[0] = B.row_xr;
@@ -147,17 +162,18 @@ __device__ inline void band_ranges(const Conic &C, const ConicFrame &F, const Pi
         }
         double xl, xr;
         if (conic_xrange(C, F, (double)r0 + 0.5 - C.v0, (double)r1 + 0.5 - C.v0, xl, xr)) {
-            B.valid |= 1u << k;
-            B.xl[k] = xl;
-            B.xr[k] = xr;
+            B.valid |= 1u << r;
+            B.xl[r] = xl;
+            B.xr[r] = xr;
         }
     }
 }
 
 // Is tile (tx, .) of the row listed: does its pixel-centre rectangle (clipped
-// to the box) overlap the row's x-extent?  *bands receives the culling bands
-// whose own rectangles overlap their extents (0 for a tile not listed).
-__device__ inline bool tile_listed(const Conic &C, const BandRanges &B, const PixelBox &box, int tx, int TW,
+// to the box) overlap the row's x-extent?  *bands receives the slots whose
+// own pixel-centre rectangles overlap their slot row's extent (0 for a tile
+// not listed).
+__device__ inline bool tile_listed(const Conic &C, const BandRanges &B, const PixelBox &box, int tx, int TW, int TH,
                                    uint32_t &bands)
 {
 #pragma clang fp contract(off)
@@ -166,21 +182,34 @@ __device__ inline bool tile_listed(const Conic &C, const BandRanges &B, const Pi
     if (cx0 > cx1 || !B.row_valid) return false;
     const double xa = (double)cx0 + 0.5 - C.u0, xb = (double)cx1 + 0.5 - C.u0;
     if (!(xa <= B.row_xr && xb >= B.row_xl)) return false;
+    const SlotLayout S = slot_layout(TW, TH);
+    const int nslots = S.bits ? S.slots : 1, bx = S.bits ? S.bx : 1, cw = S.bits ? S.cw : TW;
+    // Slot row r and column c are loop constants, so B's arrays stay in
+    // registers (a run-time index would put them in scratch memory).
 #pragma unroll
-    for (int k = 0; k < kMaxBands; ++k)
-        if (((B.valid >> k) & 1u) && xa <= B.xr[k] && xb >= B.xl[k]) bands |= 1u << k;
+    for (int r = 0; r < kMaxBands; ++r) {
+#pragma unroll
+        for (int c = 0; c < kMaxBands; ++c) {
+            const int k = r * bx + c;
+            if (c >= bx || k >= nslots) continue;
+            const int sx0 = max(tx * TW + c * cw, box.x0), sx1 = min(tx * TW + c * cw + cw - 1, box.x1);
+            if (sx0 > sx1 || !((B.valid >> r) & 1u)) continue;
+            const double sa = (double)sx0 + 0.5 - C.u0, sb = (double)sx1 + 0.5 - C.u0;
+            if (sa <= B.xr[r] && sb >= B.xl[r]) bands |= 1u << k;
+        }
+    }
     return true;
 }
 
-// Instance values carry the culling-band bits of their tile in the top 4
-// bits (a tile tested as one band carries none; its rows are then bounded by
+// Instance values carry the culling bits of their tile's slots in the top 4
+// bits (a tile with more slots carries none; its rows are then bounded by
 // the record's pixel rows).
 constexpr uint32_t kIdBits = 28;
 constexpr uint32_t kIdMask = (1u << kIdBits) - 1u;
 
 __device__ inline uint32_t pack_instance(uint32_t id, uint32_t bands, int TW, int TH)
 {
-    return cull_band_rows(TW, TH) == 64 / TW ? id | (bands << kIdBits) : id;
+    return slot_layout(TW, TH).bits ? id | (bands << kIdBits) : id;
 }
 
 }  // namespace rgs

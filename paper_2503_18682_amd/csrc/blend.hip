@@ -1,8 +1,11 @@
 // Per-pixel compositing (forward and backward).
 //
 // Work decomposition: one wavefront (64 lanes) owns one screen tile of
-// TW x TH pixels; lane l covers column l % TW and rows l / TW + k * (64 / TW),
-// k < TW * TH / 64.  Waves of a workgroup are independent: each pulls tile ids
+// TW x TH pixels, cut into TW * TH / 64 pixel slots (slot_layout in
+// binning.h: 8 x 8 blocks, or full-width row bands); lane l holds one pixel
+// of every slot, and a slot whose culling bit is clear, or whose pixels have
+// all stopped, is skipped by the whole wave.  Waves of a workgroup are
+// independent: each pulls tile ids
 // from one of kQueues atomic queues (persistent grid; the queues interleave
 // the heavy-first work order, and splitting the head keeps one memory
 // address from serialising every take), stages 64 raster records at a
@@ -335,14 +338,31 @@ struct ExactMipModel {
     __device__ static float omega(const Rec &, F &f) { return __builtin_amdgcn_exp2f(f.L); }
 };
 
-// Whether culling band k (rows [k LY, (k + 1) LY) of the tile) may hold a
-// fragment of the record: its band bit when the tile has at most 4 bands
-// (`bands` is then the record's rows word), else the record's covered rows.
-template <int PPL, int LY>
+// Whether slot k of the tile may hold a fragment of the record: its culling
+// bit when the tile's slots carry bits (`bands` is then the record's rows
+// word with the instance's bits in it), else the record's covered rows
+// against the slot's rows (the slots are then full-width row bands).
+template <int TW, int TH>
 __device__ __forceinline__ bool band_open(uint32_t bands, const RowSpan &span, int k)
 {
-    if (PPL <= 4) return (bands >> k) & 1u;
-    return !(span.r1 < k * LY || span.r0 >= (k + 1) * LY);
+    constexpr SlotLayout SL = slot_layout(TW, TH);
+    if (SL.bits) return (bands >> k) & 1u;
+    return !(span.r1 < k * SL.rh || span.r0 >= (k + 1) * SL.rh);
+}
+
+// Pixel of a lane in slot k, relative to the tile's first pixel.
+template <int TW, int TH>
+__device__ __forceinline__ int slot_x(int lane, int k)
+{
+    constexpr SlotLayout SL = slot_layout(TW, TH);
+    return SL.cw * (k % SL.bx) + lane % SL.cw;
+}
+
+template <int TW, int TH>
+__device__ __forceinline__ int slot_y(int lane, int k)
+{
+    constexpr SlotLayout SL = slot_layout(TW, TH);
+    return SL.rh * (k / SL.bx) + lane / SL.cw;
 }
 
 template <int TW, int TH, class M>
@@ -353,12 +373,11 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
                                                const float4 *__restrict__ records, const DevView *__restrict__ views,
                                                BlendParams P, unsigned int *__restrict__ queue)
 {
-    constexpr int LX = TW, LY = 64 / TW, PPL = TH / LY;
-    static_assert(64 % TW == 0 && TH % LY == 0, "tile shape");
+    constexpr int PPL = slot_layout(TW, TH).slots;
+    static_assert(64 % TW == 0 && PPL * 64 == TW * TH, "tile shape");
     __shared__ float4 s_rec[4][64][M::kStaged];
     const uint32_t amax_bits = __float_as_uint(P.alpha_max);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int lx = lane % LX, ly = lane / LX;
     const int nq = min((int)gridDim.x, kQueues), q = (int)blockIdx.x % nq;
     unsigned int *const head = queue + q * kQueueStride;
     const int64_t n_items = *n_items_p;
@@ -373,22 +392,21 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
         const DevView &V = views[find_view(views, P.n_views, tile)];
         const int local = tile - V.tile_base;
         const int tx = local % V.tiles_x, ty = local / V.tiles_x;
-        const int px = tx * TW + lx;
         const int ox = (tx * TW) & ~31, oy = (ty * TH) & ~31;
         const float x0 = (float)ox, y0 = (float)oy;
         // pixel centres relative to the block corner; NaN marks a pixel that
         // is outside the image, outside the work item, or done
-        const float pxr = (float)(px - ox) + 0.5f;
         const uint2 rg = ranges[tile];
-        float T[PPL], C0[PPL], C1[PPL], C2[PPL], pyr[PPL], aux[PPL];
+        float T[PPL], C0[PPL], C1[PPL], C2[PPL], pxr[PPL], pyr[PPL], aux[PPL];
         int last[PPL];
         // pixel slots (row bands of 64 pixels) that hold a live pixel: a slot
         // whose pixels have all stopped is skipped by the whole wave
         uint32_t live = 0u;
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
-            const int py = ty * TH + ly + k * LY;
+            const int px = tx * TW + slot_x<TW, TH>(lane, k), py = ty * TH + slot_y<TW, TH>(lane, k);
             const bool on = k >= k_lo && k < k_hi && px < V.width && py < V.height;
+            pxr[k] = (float)(px - ox) + 0.5f;
             pyr[k] = on ? (float)(py - oy) + 0.5f : __builtin_nanf("");
             aux[k] = M::pixel_aux(V, px, py);
             T[k] = 1.0f;
@@ -423,11 +441,11 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
                 const uint32_t bands = __builtin_amdgcn_readfirstlane(R.rows);
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) {
-                    if (!((live >> k) & 1u) || !band_open<PPL, LY>(bands, span, k)) continue;
+                    if (!((live >> k) & 1u) || !band_open<TW, TH>(bands, span, k)) continue;
                     // every lane evaluates the test; results are kept by selection
                     // (the values are those of a branch per lane, bit for bit)
                     typename M::F f;
-                    const bool hit = M::test(R, pxr, pyr[k], aux[k], P.log2_pmin, f);
+                    const bool hit = M::test(R, pxr[k], pyr[k], aux[k], P.log2_pmin, f);
                     if (__ballot(hit) == 0) continue;
                     // omega >= 0 and alpha_max > 0: the float minimum is the
                     // minimum of the bit patterns
@@ -465,7 +483,7 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
         const size_t plane = (size_t)V.width * V.height;
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
-            const int py = ty * TH + ly + k * LY;
+            const int px = tx * TW + slot_x<TW, TH>(lane, k), py = ty * TH + slot_y<TW, TH>(lane, k);
             if (k >= k_lo && k < k_hi && px < V.width && py < V.height) {
                 const size_t p = (size_t)py * V.width + px;
                 V.rgb[p] = C0[k] + T[k] * P.bg0;
@@ -551,12 +569,11 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                                                    const DevView *__restrict__ views, BlendParams P,
                                                    float *__restrict__ record_grads, unsigned int *__restrict__ queue)
 {
-    constexpr int LX = TW, LY = 64 / TW, PPL = TH / LY;
+    constexpr int PPL = slot_layout(TW, TH).slots;
     __shared__ float4 s_rec[4][64][4];
     __shared__ uint32_t s_id[4][64];
     const uint32_t amax_bits = __float_as_uint(P.alpha_max);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int lx = lane % LX, ly = lane / LX;
     const int nq = min((int)gridDim.x, kQueues), q = (int)blockIdx.x % nq;
     unsigned int *const head = queue + q * kQueueStride;
     const int64_t n_items = *n_items_p;
@@ -571,17 +588,16 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
         const DevView &V = views[find_view(views, P.n_views, tile)];
         const int local = tile - V.tile_base;
         const int tx = local % V.tiles_x, ty = local / V.tiles_x;
-        const int px = tx * TW + lx;
         const int ox = (tx * TW) & ~31, oy = (ty * TH) & ~31;
         const float x0 = (float)ox, y0 = (float)oy;
-        const float pxr = (float)(px - ox) + 0.5f;
         const size_t plane = (size_t)V.width * V.height;
-        float T[PPL], S[PPL], g0[PPL], g1[PPL], g2[PPL], pyr[PPL];
+        float T[PPL], S[PPL], g0[PPL], g1[PPL], g2[PPL], pxr[PPL], pyr[PPL];
         int last[PPL];
         int maxlast = 0;
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
-            const int py = ty * TH + ly + k * LY;
+            const int px = tx * TW + slot_x<TW, TH>(lane, k), py = ty * TH + slot_y<TW, TH>(lane, k);
+            pxr[k] = (float)(px - ox) + 0.5f;
             pyr[k] = (float)(py - oy) + 0.5f;
             T[k] = 1.0f;
             S[k] = 0.0f;
@@ -637,21 +653,27 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                 const RowSpan span = row_span(R.rows, ty * TH);
                 const uint32_t bands = __builtin_amdgcn_readfirstlane(R.rows);
                 const float inv_o = __builtin_amdgcn_exp2f(-R.log2o);
-                const float dx = pxr - R.cx;  // the same in every slot of the lane
-                // sums over the lane's pixels of dL/dq, dL/dq dy, dL/dq dy^2,
-                // dL/dden and dL/dden dy (q, den, D as in frag_test); the
-                // record gradients follow from them once per record
-                float sq = -0.0f, sqy = -0.0f, syy = -0.0f, sd = -0.0f, sdy = -0.0f, dic2 = -0.0f, dop = -0.0f;
+                // the slots of a lane share its pixel column when they are row
+                // bands (one slot across)
+                constexpr bool one_column = slot_layout(TW, TH).bx == 1;
+                const float dx0 = pxr[0] - R.cx;
+                // sums over the lane's pixels of dL/dq and its moments in dx
+                // and dy, of dL/dden and its moments (q, den, D as in
+                // frag_test); the record gradients follow from them once per
+                // record (with one column, the dx moments are dx times the
+                // plain sums)
+                float sq = -0.0f, sqx = -0.0f, sqy = -0.0f, sxx = -0.0f, sxy = -0.0f, syy = -0.0f;
+                float sd = -0.0f, sdx = -0.0f, sdy = -0.0f, dic2 = -0.0f, dop = -0.0f;
                 float dr = -0.0f, dg = -0.0f, db = -0.0f;
                 bool wave_hit = false;
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) {
-                    if (k < k_lo || k >= k_hi || !band_open<PPL, LY>(bands, span, k)) continue;
+                    if (k < k_lo || k >= k_hi || !band_open<TW, TH>(bands, span, k)) continue;
                     // every lane evaluates the fragment; a lane that does not hit
                     // takes omega = 0 and 1/t = 0, so every term it adds is zero
                     // and its state is unchanged (1 / (1 - 0) = 1 exactly)
                     Frag f;
-                    const bool hit = (j < last[k]) & frag_test(R, pxr, pyr[k], f);
+                    const bool hit = (j < last[k]) & frag_test(R, pxr[k], pyr[k], f);
                     if (__ballot(hit) == 0) continue;
                     wave_hit = true;
                     frag_omega(R, f);
@@ -681,23 +703,36 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                     const float dden = (-2.0f * e) * (f.q * f.den);
                     dic2 = __builtin_fmaf(e, -(f.q * f.q), dic2);
                     const float dqy = dq * f.dy;
-                    sq += dq;
                     sqy += dqy;
                     syy = __builtin_fmaf(dqy, f.dy, syy);
                     sd += dden;
                     sdy = __builtin_fmaf(dden, f.dy, sdy);
+                    if (one_column) {
+                        sq += dq;
+                    } else {
+                        const float dqx = dq * f.dx;
+                        sqx += dqx;
+                        sxx = __builtin_fmaf(dqx, f.dx, sxx);
+                        sxy = __builtin_fmaf(dqx, f.dy, sxy);
+                        sdx = __builtin_fmaf(dden, f.dx, sdx);
+                    }
                 }
                 if (!wave_hit) continue;
+                if (one_column) {
+                    sqx = dx0 * sq;
+                    sxx = dx0 * sqx;
+                    sxy = dx0 * sqy;
+                    sdx = dx0 * sd;
+                }
                 // q = delta^T M delta with M = H^T H: dL/dM00 = sum dq dx^2,
                 // dL/dM01 = sum dq 2 dx dy, dL/dM11 = sum dq dy^2; dq/ddelta =
                 // 2 M delta, so dL/du0 = -(2 M sum dq delta + g sum dden)
                 const float Mxx = __builtin_fmaf(R.H10, R.H10, R.H00 * R.H00);
                 const float Mxy = __builtin_fmaf(R.H10, R.H11, R.H00 * R.H01);
                 const float Myy = __builtin_fmaf(R.H11, R.H11, R.H01 * R.H01);
-                const float sqx = dx * sq;
                 const float du0 = __builtin_fmaf(-2.0f, __builtin_fmaf(Mxx, sqx, Mxy * sqy), -(R.gx * sd));
                 const float dv0 = __builtin_fmaf(-2.0f, __builtin_fmaf(Mxy, sqx, Myy * sqy), -(R.gy * sd));
-                const float vals[16] = {du0, dv0, dx * sqx, 2.0f * (dx * sqy), syy, dx * sd, sdy, sd, dic2, dop, dr,
+                const float vals[16] = {du0, dv0, sxx, 2.0f * sxy, syy, sdx, sdy, sd, dic2, dop, dr,
                                         dg, db, 0.f, 0.f, 0.f};
                 const float sum = wave_sum16(vals, lane);
                 const int c = wave_sum16_index(lane);
@@ -742,12 +777,11 @@ __global__ __launch_bounds__(256) void k_blend_bwd_exact(const uint2 *__restrict
                                                          unsigned int *__restrict__ queue)
 {
     using M = ExactMipModel;
-    constexpr int LX = TW, LY = 64 / TW, PPL = TH / LY;
+    constexpr int PPL = slot_layout(TW, TH).slots;
     constexpr float kLn2 = 0.69314718055994531f;
     __shared__ float4 s_rec[4][64][M::kStaged];
     __shared__ uint32_t s_id[4][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int lx = lane % LX, ly = lane / LX;
     const int nq = min((int)gridDim.x, kQueues), q = (int)blockIdx.x % nq;
     unsigned int *const head = queue + q * kQueueStride;
     const int64_t n_items = *n_items_p;
@@ -761,17 +795,16 @@ __global__ __launch_bounds__(256) void k_blend_bwd_exact(const uint2 *__restrict
         const DevView &V = views[find_view(views, P.n_views, tile)];
         const int local = tile - V.tile_base;
         const int tx = local % V.tiles_x, ty = local / V.tiles_x;
-        const int px = tx * TW + lx;
         const int ox = (tx * TW) & ~31, oy = (ty * TH) & ~31;
         const float x0 = (float)ox, y0 = (float)oy;
-        const float pxr = (float)(px - ox) + 0.5f;
         const size_t plane = (size_t)V.width * V.height;
-        float T[PPL], S[PPL], g0[PPL], g1[PPL], g2[PPL], pyr[PPL], aux[PPL];
+        float T[PPL], S[PPL], g0[PPL], g1[PPL], g2[PPL], pxr[PPL], pyr[PPL], aux[PPL];
         int last[PPL];
         int maxlast = 0;
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
-            const int py = ty * TH + ly + k * LY;
+            const int px = tx * TW + slot_x<TW, TH>(lane, k), py = ty * TH + slot_y<TW, TH>(lane, k);
+            pxr[k] = (float)(px - ox) + 0.5f;
             pyr[k] = (float)(py - oy) + 0.5f;
             aux[k] = M::pixel_aux(V, px, py);
             T[k] = 1.0f;
@@ -816,9 +849,9 @@ __global__ __launch_bounds__(256) void k_blend_bwd_exact(const uint2 *__restrict
                 bool wave_hit = false;
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) {
-                    if (k < k_lo || k >= k_hi || !band_open<PPL, LY>(bands, span, k)) continue;
+                    if (k < k_lo || k >= k_hi || !band_open<TW, TH>(bands, span, k)) continue;
                     XFrag f;
-                    const bool hit = (j < last[k]) & M::test(R, pxr, pyr[k], aux[k], P.log2_pmin, f);
+                    const bool hit = (j < last[k]) & M::test(R, pxr[k], pyr[k], aux[k], P.log2_pmin, f);
                     if (__ballot(hit) == 0) continue;
                     wave_hit = true;
                     const float w = hit ? M::omega(R, f) : 0.0f;

@@ -450,14 +450,17 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(int64_t n_max, const in
 // alone leaves every tile's list in depth order.  The kernel also clears the
 // tile ranges and the compositing scheduling words for the stages after the
 // tile sort (`clear` holds clear_words uint32 at `clear_a`, then `clear_b`).
+// Instantiated per tile shape, so the slot layout of the culling bits is
+// constant.
+template <int TW, int TH>
 __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ order,
                                                    const uint32_t *__restrict__ offsets,
                                                    const uint32_t *__restrict__ row_offsets,
                                                    const uint32_t *__restrict__ row_owner,
                                                    const uint2 *__restrict__ boxes, const Conic *__restrict__ conics,
                                                    const DevView *__restrict__ views, int64_t n,
-                                                   const int64_t *__restrict__ counters, int64_t capacity, int TW,
-                                                   int TH, uint32_t empty_tile, uint32_t *__restrict__ inst_tiles,
+                                                   const int64_t *__restrict__ counters, int64_t capacity,
+                                                   uint32_t empty_tile, uint32_t *__restrict__ inst_tiles,
                                                    uint32_t *__restrict__ inst_ids, uint32_t *__restrict__ clear_a,
                                                    int64_t clear_a_words, uint32_t *__restrict__ clear_b,
                                                    int64_t clear_b_words)
@@ -484,7 +487,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
         const uint32_t row_base = (uint32_t)views[v].tile_base + (uint32_t)(ty * views[v].tiles_x);
         for (int tx = tx0; tx <= tx1; ++tx, ++pos) {
             uint32_t bands;
-            const bool listed = tile_listed(C, B, pb, tx, TW, bands);
+            const bool listed = tile_listed(C, B, pb, tx, TW, TH, bands);
             inst_tiles[pos] = listed ? row_base + (uint32_t)tx : empty_tile;
             inst_ids[pos] = pack_instance(id, bands, TW, TH);
         }
@@ -715,12 +718,26 @@ hipError_t launch_emit(const uint32_t *order, const uint32_t *offsets, const uin
                        int64_t total_tiles, uint32_t *sched, int grid, hipStream_t stream)
 {
     // runs even with no Gaussian: it clears the ranges and scheduling words
-    k_emit<<<grid, kThreads, 0, stream>>>(order, offsets, row_offsets, row_owner, boxes, conics, views,
-                                          n > 0 ? n : 1, counters, capacity, tile_w, tile_h, empty_tile, inst_tiles,
-                                          inst_ids, reinterpret_cast<uint32_t *>(ranges), 2 * total_tiles, sched,
-                                          (int64_t)sched_words());
+#define RGS_EMIT(W, H)                                                                                               \
+    if (tile_w == W && tile_h == H) {                                                                                \
+        k_emit<W, H><<<grid, kThreads, 0, stream>>>(order, offsets, row_offsets, row_owner, boxes, conics, views,     \
+                                                    n > 0 ? n : 1, counters, capacity, empty_tile, inst_tiles,        \
+                                                    inst_ids, reinterpret_cast<uint32_t *>(ranges), 2 * total_tiles,  \
+                                                    sched, (int64_t)sched_words());                                   \
+        return hipGetLastError();                                                                                    \
+    }
+    RGS_EMIT(8, 8)
+    RGS_EMIT(8, 16)
+    RGS_EMIT(8, 32)
+    RGS_EMIT(16, 8)
+    RGS_EMIT(16, 16)
+    RGS_EMIT(16, 32)
+    RGS_EMIT(32, 8)
+    RGS_EMIT(32, 16)
+    RGS_EMIT(32, 32)
+#undef RGS_EMIT
     (void)n_views;
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t stream)

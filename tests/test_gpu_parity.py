@@ -39,27 +39,37 @@ def _check_lists(buf, lay, m, sp, cam, opts, label):
     assert np.array_equal(tiles[keep], ot) and np.array_equal(ids[keep], oi)
 
 
+def slot_layout(tw, th):
+    """The compositing kernels' pixel slots of a tw x th tile (64 pixels a
+    wave evaluates or skips together): 8 x 8 blocks for a tile wider than 8
+    pixels with at most 4 of them, else full-width row bands of 64 / tw rows.
+    Returns (slot width, slot height, slots across, slots, culling bits per
+    instance)."""
+    if tw >= 16 and (tw // 8) * (th // 8) <= 4:
+        return 8, 8, tw // 8, (tw // 8) * (th // 8), True
+    ly = 64 // tw
+    return tw, ly, 1, th // ly, th // ly <= 4
+
+
 def _check_bands(buf, lay, sp, cam, opts, label):
-    """The culling-band bits of every listed instance (top 4 bits of its id:
-    bit k for rows [k LY, (k + 1) LY) of the tile, LY = 64 / tile_w, when the
-    tile has at most 4 such bands) cover every band that holds a pixel of the
-    Gaussian's support, found pixel by pixel by the oracle."""
+    """The slot culling bits of every listed instance (top 4 bits of its id,
+    bit k for slot k) cover every slot that holds a pixel of the Gaussian's
+    support, found pixel by pixel by the oracle."""
     tw, th = int(opts["tile_w"]), int(opts["tile_h"])
-    LY = 64 // tw
-    if th // LY > 4:
+    cw, ch, bx, slots, bits = slot_layout(tw, th)
+    if not bits:
         return
     tiles, ids, bands = instance_lists(buf, lay, with_bands=True)
     keep = sp["hazard"][ids] == 0
     tiles, ids, bands = tiles[keep], ids[keep], bands[keep]
-    rows = oracle.support_rows(sp, cam, opts, tiles, ids).astype(np.int64)
-    need = np.zeros_like(bands)
-    for k in range(th // LY):
-        need |= ((rows >> (k * LY)) & ((1 << LY) - 1) != 0).astype(np.int64) << k
+    # oracle cells of the slot size are numbered row-major, as the slots are
+    need = oracle.support_cells(sp, cam, opts, tiles, ids, cw, ch).astype(np.int64)
+    assert (need >> slots).max(initial=0) == 0
     missing = (need & ~bands) != 0
     set_bits = sum(int(((bands >> k) & 1).sum()) for k in range(4))
     need_bits = sum(int(((need >> k) & 1).sum()) for k in range(4))
-    say(f"  {label}: {len(ids)} instances, {need_bits} bands hold support, {set_bits} band bits set")
-    assert not missing.any(), f"{label}: {int(missing.sum())} instances miss a band that holds support"
+    say(f"  {label}: {len(ids)} instances, {need_bits} slots hold support, {set_bits} slot bits set")
+    assert not missing.any(), f"{label}: {int(missing.sum())} instances miss a slot that holds support"
 
 
 def _check_keys_boxes_counts(buf, lay, sp, n):
@@ -133,7 +143,9 @@ def test_lists_are_consistent_with_gpu_counts_boxes_and_keys(r):
     ty, tx = tiles // tx_n, tiles % tx_n
     b = boxes[ids]
     assert np.all((tx >= b[:, 0] // 8) & (tx <= b[:, 1] // 8) & (ty >= b[:, 2] // 16) & (ty <= b[:, 3] // 16))
-    assert np.all((bands & 3) > 0)  # 2 row bands per 8x16 tile (all 4 bits for an unbounded support)
+    # 2 slots per 8x16 tile; a listed tile whose support meets only the gap
+    # between the slots' pixel rows has no slot bit (rare)
+    assert (bands >> 2).max() == 0 and (bands == 0).mean() < 0.01
     rng = read(buf, lay.tile_ranges, 2 * lay.total_tiles, np.uint32).reshape(-1, 2)
     for t in np.unique(tiles):
         idx = np.nonzero(tiles == t)[0]
