@@ -90,6 +90,9 @@ def parse():
     ap.add_argument("--divergence", default="ray", choices=["ray", "gs"],
                     help="c1: the ray-based divergence (the paper's renderer) or the linearised one of 3DGS")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of HIP-graph replays")
+    ap.add_argument("--in-flight", type=int, default=1,
+                    help="c1: frames in flight for `value` (each its own graph, workspace and stream); the line "
+                         "also reports the throughput with 2 and 3 in flight")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-steps", type=int, default=32, help="frames of the per-stage timing pass")
     ap.add_argument("--tile", default="8x16", help="tile shape WxH, each of 8, 16, 32")
@@ -212,26 +215,41 @@ def bench_c1(args, torch):
     capacity = int(need * 1.1) + 4096
     log(f"c1: {n} Gaussians, {POSES} poses, max instances {need}, capacity {capacity}")
     br = R.BatchRenderer(r, n, sc["sh_degree"], [cams[0]], capacity, options=opts)
+    # frames in flight: each its own plan (workspace, graph, outputs) on its
+    # own stream, consecutive poses round robin
+    flight = [(br, torch.cuda.current_stream())]
+    for _ in range(1, max(args.in_flight, 3)):
+        flight.append((R.BatchRenderer(r, n, sc["sh_degree"], [cams[0]], capacity, options=opts),
+                       torch.cuda.Stream()))
 
-    def step():
+    def step(f):
         # one orbit: a frame at each pose
-        for c in cams:
+        for k, c in enumerate(cams):
             if args.eager:
                 r.render_into(g, [c], br.outs, br.ws, opts)
             else:
-                br.launch(g, [c])
+                b, st = flight[k % f]
+                with torch.cuda.stream(st):
+                    b.launch(g, [c])
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ok, _ = br.status()
-    assert ok, "instance capacity overflow in the timed region"
-    ms = (t1 - t0) * 1e3 / args.steps
+    def timed(f):
+        for _ in range(args.warmup):
+            step(f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(f)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for b, _ in flight[:f]:
+            assert b.status()[0], "instance capacity overflow in the timed region"
+        return (t1 - t0) * 1e3 / args.steps
+
+    ms = timed(args.in_flight)
+    # throughput with more frames in flight (every frame still runs the whole path)
+    pipelined = {} if args.eager else {str(f): POSES * 1e3 / timed(f) for f in (2, 3) if f != args.in_flight}
+    for b, _ in flight[1:]:
+        b.close()
     frames = max(POSES, POSES * math.ceil(args.stage_steps / POSES))
     stages, _ = stage_pass(r, g, lambda k: [cams[k % POSES]], opts, br.ws, br.outs, frames)
     fwd = {k: v for k, v in stages.items() if not k.endswith("backward")}
@@ -252,11 +270,13 @@ def bench_c1(args, torch):
                    + (" (linearised GS divergence)" if gs else ""),
                    "n_gaussians": n, "width": 1920, "height": 1080, "tile": args.tile,
                    "frames_per_step": POSES, "step": "one frame at each of the 16 orbit poses",
+                   "frames_in_flight": args.in_flight,
                    "launch": "eager" if args.eager else "hip_graph", "instance_capacity": capacity},
         "roofline": roof,
         "calibration": calib,
         "stages_ms": stages,
         "dominant_stage": max(fwd, key=fwd.get),
+        "frames_per_s_in_flight": pipelined,
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_c1(sc, cams[0], opts)
