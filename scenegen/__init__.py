@@ -13,6 +13,8 @@ from .scenes import (  # noqa: F401
     make_workload,
     tiny_scene,
     thin_structure_scene,
+    wall_scene,
+    approach_cameras,
     default_options,
     fd_subcase,
 )

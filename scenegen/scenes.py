@@ -179,6 +179,36 @@ def thin_structure_scene(seed, n, *, half_extent=1.0, long_log_scale=-2.5, thin_
     return sc
 
 
+def wall_scene(seed, n, *, half_extent=2.0, depth_std=0.05, log_scale_mean=-2.0, log_scale_std=0.5, flatten=2.0):
+    """Flattened Gaussians on a wall (the plane z = 0, square of half size
+    half_extent, depths N(0, depth_std)): the third log-scale is lowered by
+    `flatten`, so most Gaussians are disks of a few centimetres, randomly
+    oriented.  A camera walking towards the wall (approach_cameras) brings
+    them close to it, where the linearised projection of Sec. 3.1 misplaces
+    their supports."""
+    rng = np.random.default_rng(seed)
+    sc = make_scene(rng, n, sh_degree=0, half_extent=half_extent, log_scale_mean=log_scale_mean,
+                    log_scale_std=log_scale_std, logit_std=1.0)
+    means = sc["means"].astype(np.float64)
+    means[2] = rng.normal(0.0, depth_std, n)
+    ls = sc["log_scales"].astype(np.float64)
+    ls[2] -= flatten
+    sc["means"] = np.ascontiguousarray(means, dtype=np.float32)
+    sc["log_scales"] = np.ascontiguousarray(ls, dtype=np.float32)
+    return sc
+
+
+def approach_cameras(distances, width, height, fov_x_deg=90.0, offset=(0.3, 0.2)):
+    """Cameras on a straight line towards the wall of wall_scene: the eye at
+    (offset, -d) for each distance d, looking along +z (OpenCV axes), so the
+    wall fills more of the view and its Gaussians come closer as d shrinks."""
+    cams = []
+    for d in distances:
+        w2c = np.array([[1.0, 0.0, 0.0, -offset[0]], [0.0, 1.0, 0.0, -offset[1]], [0.0, 0.0, 1.0, float(d)]])
+        cams.append(pinhole(w2c, width, height, fov_x_deg))
+    return cams
+
+
 def make_cameras(name, rng):
     if name == "c0":
         return [pinhole(look_at((0.0, 0.0, -4.0)), 128, 128, 60.0)]

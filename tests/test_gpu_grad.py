@@ -172,8 +172,10 @@ def test_mip_multi_view_sparse_pixels(r):
 
 
 def test_c3_full_size_sampled_gradients(r):
-    """1M Gaussians, 4 views at 1600x1060 (the training-style workload): L1
-    upstream gradient kept on 200 sampled pixels per view."""
+    """1M Gaussians, 4 views at 1600x1060 (the training-style workload): the
+    L1 upstream gradient kept on every pixel of a 64-row band of view 0
+    (102,400 pixels through the middle of the scene) and on 200 sampled pixels
+    of each view."""
     from paper_2503_18682_amd import _lib
 
     w = scenegen.make_workload("c3")
@@ -190,6 +192,8 @@ def test_c3_full_size_sampled_gradients(r):
         full = np.sign(img - w["targets"][v]) / total
         mask = np.zeros(img.shape[1:], bool)
         mask[rng.integers(0, 1060, 200), rng.integers(0, 1600, 200)] = True
+        if v == 0:
+            mask[500:564, :] = True
         dl = np.where(mask[None], full, 0).astype(np.float32)
         dls.append(torch.from_numpy(dl).cuda())
         rv = oracle.backward(sc, cam, opts, dl.astype(np.float64))
