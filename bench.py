@@ -93,6 +93,8 @@ def parse():
     ap.add_argument("--in-flight", type=int, default=1,
                     help="c1: frames in flight for `value` (each its own graph, workspace and stream); the line "
                          "also reports the throughput with 2 and 3 in flight")
+    ap.add_argument("--single-flight", action="store_true",
+                    help="c1: skip the 2 and 3 frames-in-flight timings (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-steps", type=int, default=32, help="frames of the per-stage timing pass")
     ap.add_argument("--tile", default="8x16", help="tile shape WxH, each of 8, 16, 32")
@@ -218,7 +220,7 @@ def bench_c1(args, torch):
     # frames in flight: each its own plan (workspace, graph, outputs) on its
     # own stream, consecutive poses round robin
     flight = [(br, torch.cuda.current_stream())]
-    for _ in range(1, max(args.in_flight, 3)):
+    for _ in range(1, max(args.in_flight, 1 if args.single_flight or args.eager else 3)):
         flight.append((R.BatchRenderer(r, n, sc["sh_degree"], [cams[0]], capacity, options=opts),
                        torch.cuda.Stream()))
 
@@ -247,7 +249,8 @@ def bench_c1(args, torch):
 
     ms = timed(args.in_flight)
     # throughput with more frames in flight (every frame still runs the whole path)
-    pipelined = {} if args.eager else {str(f): POSES * 1e3 / timed(f) for f in (2, 3) if f != args.in_flight}
+    pipelined = {} if args.eager or args.single_flight else \
+        {str(f): POSES * 1e3 / timed(f) for f in (2, 3) if f != args.in_flight}
     for b, _ in flight[1:]:
         b.close()
     frames = max(POSES, POSES * math.ceil(args.stage_steps / POSES))
