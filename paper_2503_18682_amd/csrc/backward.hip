@@ -386,11 +386,14 @@ __global__ __launch_bounds__(256) void k_colour_bwd(const float *__restrict__ me
     bool any = false;
     for (int v = 0; v < n_views; ++v) any = any || tile_counts[(size_t)v * n + i] != 0;
     if (!any) return;
+    // the gradient accumulators are read together with the coefficients, so
+    // both streams of loads are in flight before any arithmetic (reading them
+    // after the view loop left the final read-modify-write exposed)
     float c[NK * 3], dsh[NK * 3];
 #pragma unroll
     for (int k = 0; k < NK * 3; ++k) {
         c[k] = sh[(size_t)k * n + i];
-        dsh[k] = 0.0f;
+        dsh[k] = g_sh[(size_t)k * n + i];
     }
     const double m[3] = {means[i], means[n + i], means[2 * n + i]};
     double dm[3] = {0, 0, 0};
@@ -427,7 +430,7 @@ __global__ __launch_bounds__(256) void k_colour_bwd(const float *__restrict__ me
     }
     for (int k = 0; k < 3; ++k) g_means[(size_t)k * n + i] += (float)dm[k];
 #pragma unroll
-    for (int k = 0; k < NK * 3; ++k) g_sh[(size_t)k * n + i] += dsh[k];
+    for (int k = 0; k < NK * 3; ++k) g_sh[(size_t)k * n + i] = dsh[k];
 }
 
 }  // namespace
