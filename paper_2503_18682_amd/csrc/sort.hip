@@ -22,6 +22,8 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kScanItemsMin = 4;
 constexpr int scan_tile(int items) { return kThreads * items; }
 constexpr int kScanSelfPrefixBlocks = 1024;
+// Scans of at least this many blocks write the row owner map in row order.
+constexpr int kScanRowOrderBlocks = 4096;
 // Radix sort: the keys per thread of a pass (ITEMS: 4, 8 or 16) are chosen
 // per sort from its size.  More keys per workgroup amortise a workgroup's
 // per-digit work on large sorts; fewer give small sorts enough workgroups to
@@ -362,7 +364,11 @@ __device__ void block_prefix_pairs(const unsigned long long *__restrict__ block_
 // Offsets of every sorted item, scanned in place over the counts k_scan_reduce
 // left in `offsets` (box tiles) and `row_offsets` (tile rows), plus the owner
 // map of the tile rows (row_owner[r] = sorted position owning row r) when the
-// instances fit.
+// instances fit.  The map is written per item (each thread the rows of its
+// own items) or, with `rows_in_order`, in row order by consecutive threads,
+// each looking its row's owner up in the block's item table.  Row order
+// coalesces the stores, which pays off at tens of millions of items; with a
+// few hundred blocks the lookups' latency is exposed and per item is faster.
 // With `self_prefix` (few blocks), block_sums still holds every block's raw
 // pair: each block sums the pairs before its own and all of them, block 0
 // writes the totals to counters[0] and counters[2], and k_scan_top is not
@@ -373,7 +379,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(int64_t n_max, const in
                                                          int64_t capacity,
                                                          const unsigned long long *__restrict__ block_sums,
                                                          int64_t *__restrict__ counters, bool self_prefix,
-                                                         uint32_t *__restrict__ offsets,
+                                                         bool rows_in_order, uint32_t *__restrict__ offsets,
                                                          uint32_t *__restrict__ row_offsets,
                                                          uint32_t *__restrict__ row_owner)
 {
@@ -421,9 +427,13 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(int64_t n_max, const in
         pre[1] = block_sums[2 * blockIdx.x + 1];
         all[0] = (unsigned long long)counters[0];
     }
+    const uint32_t block_rows = tot;  // tile rows of the block's items
     const bool fits = all[0] <= (unsigned long long)capacity;
     unsigned long long rt = pre[0] + bt;
     unsigned long long rr = pre[1] + br;
+    // first row of each of the block's items, relative to the block's first row
+    __shared__ uint32_t row_start[scan_tile(ITEMS)];
+    uint32_t lr0 = br;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int64_t idx = base + j;
@@ -431,11 +441,33 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(int64_t n_max, const in
             offsets[idx] = rt > 0xffffffffull ? 0xffffffffu : (uint32_t)rt;
             row_offsets[idx] = rr > 0xffffffffull ? 0xffffffffu : (uint32_t)rr;
             // rows <= instances, so every row index lies below capacity
-            if (fits)
+            if (fits && !rows_in_order)
                 for (uint32_t q = 0; q < r[j]; ++q) row_owner[rr + q] = (uint32_t)idx;
         }
+        row_start[threadIdx.x * ITEMS + j] = lr0;
         rt += c[j];
         rr += r[j];
+        lr0 += r[j];
+    }
+    if (!fits || !rows_in_order) return;  // uniform over the grid
+    __syncthreads();
+    // owner map of the block's rows, written in row order by consecutive
+    // threads: the owner of row q is the last item whose first row is <= q
+    // (items without rows share the first row of the next item)
+    const int64_t block_base = (int64_t)blockIdx.x * scan_tile(ITEMS);
+    const int nvalid = (int)min((int64_t)scan_tile(ITEMS), n - block_base);
+    const unsigned long long row0 = pre[1];
+    for (uint32_t q = threadIdx.x; q < block_rows; q += kThreads) {
+        int lo = 0, hi = nvalid;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (row_start[mid] <= q)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        // rows <= instances, so every row index lies below capacity
+        row_owner[row0 + q] = (uint32_t)(block_base + lo);
     }
 }
 
@@ -506,17 +538,39 @@ __global__ void k_copy_i64(const int64_t *__restrict__ src, int64_t *__restrict_
     if (threadIdx.x == 0) *dst = *src;
 }
 
+// Each thread takes four consecutive positions per step (one 16-byte load and
+// the two neighbours), so the grid-stride loop keeps four times as many loads
+// in flight per step as one position per thread would.
 __global__ __launch_bounds__(kThreads) void k_tile_ranges(const uint32_t *__restrict__ inst_tiles,
                                                           const int64_t *__restrict__ counters, int64_t capacity,
                                                           int64_t total_tiles, uint2 *__restrict__ ranges)
 {
     const int64_t m = clamp_count(counters, capacity);
+    const int64_t groups = (m + 3) / 4;
     const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < m; p += stride) {
-        const uint32_t t = inst_tiles[p];
-        if (t >= total_tiles) continue;
-        if (p == 0 || inst_tiles[p - 1] != t) ranges[t].x = (uint32_t)p;
-        if (p == m - 1 || inst_tiles[p + 1] != t) ranges[t].y = (uint32_t)(p + 1);
+    constexpr uint32_t kNone = 0xffffffffu;  // no neighbour (never a tile id)
+    for (int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x; g < groups; g += stride) {
+        const int64_t p0 = 4 * g;
+        uint32_t t[6];  // tiles at positions p0 - 1 .. p0 + 4
+        if (p0 + 4 <= m) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(inst_tiles + p0);
+            t[1] = v.x;
+            t[2] = v.y;
+            t[3] = v.z;
+            t[4] = v.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) t[1 + j] = p0 + j < m ? inst_tiles[p0 + j] : kNone;
+        }
+        t[0] = p0 > 0 ? inst_tiles[p0 - 1] : kNone;
+        t[5] = p0 + 4 < m ? inst_tiles[p0 + 4] : kNone;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t tj = t[1 + j];
+            if (tj >= total_tiles) continue;  // also past the end (kNone)
+            if (t[j] != tj) ranges[tj].x = (uint32_t)(p0 + j);
+            if (t[j + 2] != tj) ranges[tj].y = (uint32_t)(p0 + j + 1);
+        }
     }
 }
 
@@ -684,8 +738,8 @@ void scan_launch(const uint32_t *keys, const uint2 *boxes, const uint32_t *order
     // pairs before it (at most that many loads) instead of a separate scan
     const bool self_prefix = nb <= kScanSelfPrefixBlocks;
     if (!self_prefix) k_scan_top<<<1, 1024, 0, stream>>>(block_sums, nb, counters);
-    k_scan_apply<ITEMS><<<nb, kThreads, 0, stream>>>(n, n_dev, capacity, block_sums, counters, self_prefix, offsets,
-                                                     row_offsets, row_owner);
+    k_scan_apply<ITEMS><<<nb, kThreads, 0, stream>>>(n, n_dev, capacity, block_sums, counters, self_prefix,
+                                                     nb >= kScanRowOrderBlocks, offsets, row_offsets, row_owner);
 }
 }  // namespace
 
@@ -765,7 +819,7 @@ hipError_t launch_tile_ranges(const uint32_t *inst_tiles, const int64_t *counter
     // a grid-stride loop over the listed instances (a grid sized for the whole
     // capacity would mostly launch idle workgroups)
     if (capacity > 0) {
-        const unsigned grid = (unsigned)std::min<int64_t>((capacity + kThreads - 1) / kThreads, kRangeBlocks);
+        const unsigned grid = (unsigned)std::min<int64_t>((capacity + 4 * kThreads - 1) / (4 * kThreads), kRangeBlocks);
         k_tile_ranges<<<grid, kThreads, 0, stream>>>(inst_tiles, counters, capacity, total_tiles, ranges);
     }
     const unsigned nb = (unsigned)((total_tiles + kThreads - 1) / kThreads);
