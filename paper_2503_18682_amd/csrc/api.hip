@@ -38,7 +38,8 @@ constexpr int64_t kCrossingCap = 1 << 16;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t counters, views, colours, records, keys_a, keys_b, order_a, order_b, boxes, conics, tile_counts, offsets, block_sums;
+    size_t counters, views, colours, records, keys_a, keys_b, order_a, order_b, boxes, sorted_boxes, conics, tile_counts,
+        offsets, block_sums;
     size_t crossing;          // quads with a vertex at z <= 0, awaiting frustum clipping
     uint32_t crossing_cap;    // entries of the crossing list
     size_t inst_tiles_a, inst_tiles_b, inst_ids_a, inst_ids_b, hist, row_total, ranges, sched, tile_order;
@@ -302,6 +303,7 @@ rgs_status compute_layout(rgs_context *ctx, int64_t n, const rgs_camera *cams, i
     L.order_a = take(NV * 4);
     L.order_b = take(NV * 4);
     L.boxes = take(NV * 8);
+    L.sorted_boxes = take(NV * 8);
     L.conics = take(NV * sizeof(Conic));
     L.tile_counts = take(NV * 4);
     L.crossing_cap = (uint32_t)std::min<int64_t>((int64_t)NV, kCrossingCap);
@@ -505,12 +507,13 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
     uint32_t *offsets = at<uint32_t>(ws, L.offsets);
     uint32_t *row_offsets = at<uint32_t>(ws, L.row_offsets);
     uint32_t *row_owner = at<uint32_t>(ws, L.row_owner);
+    uint2 *sorted_boxes = at<uint2>(ws, L.sorted_boxes);
     RGS_HIP(ctx, binning_scan(at<uint32_t>(ws, L.keys_a), boxes, order, NV, kept, s.w, s.h, L.capacity, offsets,
-                              row_offsets, row_owner,
+                              row_offsets, row_owner, sorted_boxes,
                               at<unsigned long long>(ws, L.block_sums), counters, stream));
     tm.mark(ST_SCAN);
     const uint32_t empty_tile = (uint32_t)((int64_t(1) << L.tile_bits) - 1);
-    RGS_HIP(ctx, launch_emit(order, offsets, row_offsets, row_owner, boxes, conics, views, g.n, n_views, counters,
+    RGS_HIP(ctx, launch_emit(order, offsets, row_offsets, row_owner, sorted_boxes, conics, views, g.n, n_views, counters,
                              L.capacity, s.w, s.h, empty_tile, tiles_in, ids_in, ranges, L.total_tiles, sched,
                              emit_grid(ctx->num_cus), stream));
     tm.mark(ST_EMIT);

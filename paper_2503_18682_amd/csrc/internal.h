@@ -104,12 +104,13 @@ size_t radix_hist_entries(int64_t n_max);
 // row_offsets[k] = box tile rows of the positions before k; counters[0] =
 // all box tiles (instances), counters[2] = all tile rows (int64);
 // row_owner[r] = k for each tile row r of position k, written when the
-// instances fit `capacity` (row_owner holds capacity entries).  block_sums
-// holds scan_block_entries(n) uint64.
+// instances fit `capacity` (row_owner holds capacity entries);
+// sorted_boxes[k] = boxes[order[k]] (n entries).  block_sums holds
+// scan_block_entries(n) uint64.
 hipError_t binning_scan(const uint32_t *keys, const uint2 *boxes, const uint32_t *order, int64_t n,
                         const int64_t *n_dev, int tile_w, int tile_h, int64_t capacity, uint32_t *offsets,
-                        uint32_t *row_offsets, uint32_t *row_owner, unsigned long long *block_sums,
-                        int64_t *counters, hipStream_t stream);
+                        uint32_t *row_offsets, uint32_t *row_owner, uint2 *sorted_boxes,
+                        unsigned long long *block_sums, int64_t *counters, hipStream_t stream);
 size_t scan_block_entries(int64_t n);
 
 // Instances of every tile row (one lane per row, `grid` workgroups looping
@@ -119,7 +120,7 @@ size_t scan_block_entries(int64_t n);
 // tile sort; always launched, also for an empty scene.
 int emit_grid(int num_cus);
 hipError_t launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *row_offsets,
-                       const uint32_t *row_owner, const uint2 *boxes, const Conic *conics, const DevView *views,
+                       const uint32_t *row_owner, const uint2 *sorted_boxes, const Conic *conics, const DevView *views,
                        int64_t n, int n_views, const int64_t *counters, int64_t capacity, int tile_w, int tile_h,
                        uint32_t empty_tile, uint32_t *inst_tiles, uint32_t *inst_ids, uint2 *ranges,
                        int64_t total_tiles, uint32_t *sched, int grid, hipStream_t stream);

@@ -234,11 +234,13 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
 // costs no gather; a kept one reads its box.
 __device__ __forceinline__ void scan_item(const uint32_t *__restrict__ keys, const uint2 *__restrict__ boxes,
                                           const uint32_t *__restrict__ order, int64_t idx, int TW, int TH,
-                                          uint32_t &tiles, uint32_t &rows)
+                                          uint32_t &tiles, uint32_t &rows, uint2 &box)
 {
     tiles = rows = 0u;
+    box = make_uint2(0u, 0u);
     if (keys[idx] != 0xffffffffu) {
-        const PixelBox pb = unpack_box(boxes[order[idx]]);
+        box = boxes[order[idx]];
+        const PixelBox pb = unpack_box(box);
         rows = (uint32_t)(pb.y1 / TH - pb.y0 / TH + 1);
         tiles = rows * (uint32_t)(pb.x1 / TW - pb.x0 / TW + 1);
     }
@@ -246,12 +248,15 @@ __device__ __forceinline__ void scan_item(const uint32_t *__restrict__ keys, con
 
 // Gathers each sorted item's two counts once (into `tiles` and `rows`, read
 // back by k_scan_apply, which scans them in place) and reduces them per block.
+// The gathered pixel box is also stored in depth order (`sorted_boxes`), so
+// the emission kernel reads it coalesced instead of gathering it again.
 template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__restrict__ keys,
                                                           const uint2 *__restrict__ boxes,
                                                           const uint32_t *__restrict__ order, int64_t n_max,
                                                           const int64_t *__restrict__ n_dev, int TW, int TH,
                                                           uint32_t *__restrict__ tiles, uint32_t *__restrict__ rows,
+                                                          uint2 *__restrict__ sorted_boxes,
                                                           unsigned long long *__restrict__ block_sums)
 {
     const int64_t n = clamp_count(n_dev, n_max);
@@ -263,9 +268,11 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__rest
         const int64_t idx = base + (int64_t)j * kThreads + threadIdx.x;
         if (idx < n) {
             uint32_t t, r;
-            scan_item(keys, boxes, order, idx, TW, TH, t, r);
+            uint2 box;
+            scan_item(keys, boxes, order, idx, TW, TH, t, r, box);
             tiles[idx] = t;
             rows[idx] = r;
+            sorted_boxes[idx] = box;
             at += t;
             ar += r;
         }
@@ -489,7 +496,8 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
                                                    const uint32_t *__restrict__ offsets,
                                                    const uint32_t *__restrict__ row_offsets,
                                                    const uint32_t *__restrict__ row_owner,
-                                                   const uint2 *__restrict__ boxes, const Conic *__restrict__ conics,
+                                                   const uint2 *__restrict__ sorted_boxes,
+                                                   const Conic *__restrict__ conics,
                                                    const DevView *__restrict__ views, int64_t n,
                                                    const int64_t *__restrict__ counters, int64_t capacity,
                                                    uint32_t empty_tile, uint32_t *__restrict__ inst_tiles,
@@ -506,7 +514,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
     for (int64_t r = tid; r < rows; r += stride) {
         const uint32_t k = row_owner[r];
         const uint32_t id = order[k];
-        const PixelBox pb = unpack_box(boxes[id]);
+        const PixelBox pb = unpack_box(sorted_boxes[k]);
         const int v = (int)(id / (uint32_t)n);
         const int row = (int)(r - row_offsets[k]);
         const int ty = pb.y0 / TH + row;
@@ -729,11 +737,12 @@ namespace {
 template <int ITEMS>
 void scan_launch(const uint32_t *keys, const uint2 *boxes, const uint32_t *order, int64_t n, const int64_t *n_dev,
                  int tile_w, int tile_h, int64_t capacity, uint32_t *offsets, uint32_t *row_offsets,
-                 uint32_t *row_owner, unsigned long long *block_sums, int64_t *counters, hipStream_t stream)
+                 uint32_t *row_owner, uint2 *sorted_boxes, unsigned long long *block_sums, int64_t *counters,
+                 hipStream_t stream)
 {
     const int nb = (int)((n + scan_tile(ITEMS) - 1) / scan_tile(ITEMS));
     k_scan_reduce<ITEMS><<<nb, kThreads, 0, stream>>>(keys, boxes, order, n, n_dev, tile_w, tile_h, offsets,
-                                                      row_offsets, block_sums);
+                                                      row_offsets, sorted_boxes, block_sums);
     // up to kScanSelfPrefixBlocks blocks, each apply block sums the block
     // pairs before it (at most that many loads) instead of a separate scan
     const bool self_prefix = nb <= kScanSelfPrefixBlocks;
@@ -745,8 +754,8 @@ void scan_launch(const uint32_t *keys, const uint2 *boxes, const uint32_t *order
 
 hipError_t binning_scan(const uint32_t *keys, const uint2 *boxes, const uint32_t *order, int64_t n,
                         const int64_t *n_dev, int tile_w, int tile_h, int64_t capacity, uint32_t *offsets,
-                        uint32_t *row_offsets, uint32_t *row_owner, unsigned long long *block_sums,
-                        int64_t *counters, hipStream_t stream)
+                        uint32_t *row_offsets, uint32_t *row_owner, uint2 *sorted_boxes,
+                        unsigned long long *block_sums, int64_t *counters, hipStream_t stream)
 {
     if (n <= 0) {
         // counters[0] and counters[2] (int64) = 0, counters[1] (capacity) kept
@@ -756,17 +765,17 @@ hipError_t binning_scan(const uint32_t *keys, const uint2 *boxes, const uint32_t
     }
     if (n <= (int64_t(1) << 20))
         scan_launch<4>(keys, boxes, order, n, n_dev, tile_w, tile_h, capacity, offsets, row_offsets, row_owner,
-                       block_sums, counters, stream);
+                       sorted_boxes, block_sums, counters, stream);
     else
         scan_launch<8>(keys, boxes, order, n, n_dev, tile_w, tile_h, capacity, offsets, row_offsets, row_owner,
-                       block_sums, counters, stream);
+                       sorted_boxes, block_sums, counters, stream);
     return hipGetLastError();
 }
 
 int emit_grid(int num_cus) { return 8 * num_cus; }
 
 hipError_t launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *row_offsets,
-                       const uint32_t *row_owner, const uint2 *boxes, const Conic *conics, const DevView *views,
+                       const uint32_t *row_owner, const uint2 *sorted_boxes, const Conic *conics, const DevView *views,
                        int64_t n, int n_views, const int64_t *counters, int64_t capacity, int tile_w, int tile_h,
                        uint32_t empty_tile, uint32_t *inst_tiles, uint32_t *inst_ids, uint2 *ranges,
                        int64_t total_tiles, uint32_t *sched, int grid, hipStream_t stream)
@@ -774,8 +783,8 @@ hipError_t launch_emit(const uint32_t *order, const uint32_t *offsets, const uin
     // runs even with no Gaussian: it clears the ranges and scheduling words
 #define RGS_EMIT(W, H)                                                                                               \
     if (tile_w == W && tile_h == H) {                                                                                \
-        k_emit<W, H><<<grid, kThreads, 0, stream>>>(order, offsets, row_offsets, row_owner, boxes, conics, views,     \
-                                                    n > 0 ? n : 1, counters, capacity, empty_tile, inst_tiles,        \
+        k_emit<W, H><<<grid, kThreads, 0, stream>>>(order, offsets, row_offsets, row_owner, sorted_boxes, conics,     \
+                                                    views, n > 0 ? n : 1, counters, capacity, empty_tile, inst_tiles, \
                                                     inst_ids, reinterpret_cast<uint32_t *>(ranges), 2 * total_tiles,  \
                                                     sched, (int64_t)sched_words());                                   \
         return hipGetLastError();                                                                                    \
