@@ -365,6 +365,8 @@ DevOptions dev_options(const rgs_options &o)
     const TileShape s = shape_of(o);
     d.tile_w = s.w;
     d.tile_h = s.h;
+    d.tile_wshift = __builtin_ctz((unsigned)s.w);
+    d.tile_hshift = __builtin_ctz((unsigned)s.h);
     for (int k = 0; k < 3; ++k) d.bg[k] = (float)o.background[k];
     return d;
 }
@@ -388,6 +390,8 @@ void write_header(unsigned char *buf, const Layout &L, const rgs_camera *cams, i
         std::memcpy(d.w2c, c.world_to_cam, sizeof d.w2c);
         d.fx = c.fx;
         d.fy = c.fy;
+        d.ifx = 1.0 / c.fx;  // correctly rounded, as the same division on the device
+        d.ify = 1.0 / c.fy;
         d.cx = c.cx;
         d.cy = c.cy;
         const double *W = c.world_to_cam;
@@ -494,14 +498,15 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
     if (view_stamps) RGS_HIP(ctx, launch_view_clock_start(view_stamps, n_views, stream));
     unsigned long long *item_clock = view_stamps ? at<unsigned long long>(ws, L.item_clock) : nullptr;
     Timer tm(ctx, stream, timing, ST_PRE);
-    RGS_HIP(ctx, launch_preprocess(g, views, n_views, dopt, colours, records, keys_in, ord_in, boxes, conics,
+    RGS_HIP(ctx, launch_preprocess(g, views, n_views, dopt, colours, records, keys_in, boxes, conics,
                                    tile_counts, at<double>(ws, L.crossing), counters + 5, L.crossing_cap, stream));
     tm.mark(ST_PRE);
     // counters: [0] box instances, [1] capacity, [2] tile rows, [3] listed instances, [4] kept views,
     // [5] quads with a vertex at z <= 0
     int64_t *listed = counters + 3, *kept = counters + 4;
+    // the values of the first pass are the Gaussian-view ids, not read
     RGS_HIP(ctx, radix_sort(keys_in, ord_in, keys_alt, ord_alt, NV, nullptr, 32, true, 0xffffffffu, kept, hist,
-                            row_total, stream));
+                            row_total, stream, true));
     tm.mark(ST_DSORT);
     const uint32_t *order = at<uint32_t>(ws, L.order_a);
     uint32_t *offsets = at<uint32_t>(ws, L.offsets);

@@ -15,6 +15,7 @@ namespace rgs {
 struct DevView {
     double w2c[12];        // row-major [R | t]
     double fx, fy, cx, cy;
+    double ifx, ify;       // 1 / fx, 1 / fy
     double centre[3];      // camera centre in world coordinates, -R^T t
     int32_t width, height;
     int32_t tiles_x, tiles_y;
@@ -30,6 +31,7 @@ struct DevOptions {
     double p_min, alpha_max, t_eps, near_z, mip_sigma2_px;
     int32_t mip;
     int32_t tile_w, tile_h;
+    int32_t tile_wshift, tile_hshift;  // log2 of the tile shape (powers of two)
     int32_t divergence;  // RGS_DIVERGENCE_*
     float bg[3];
 };
@@ -71,7 +73,7 @@ struct TileShape {
 // ---- launchers (each enqueues on `stream`, returns hipError_t) -----------
 // Writes per Gaussian-view: the colour staging entry (colours, float4: r, g,
 // b, non-finite-coefficient flag), record, depth key (0xffffffff when
-// culled), the identity order, pixel box, support conic, and the number of
+// culled), pixel box, support conic, and the number of
 // tiles of the box (0 when culled).  A quad with a vertex at z <= 0 is first
 // given the whole view; its parameters go to the crossing list (kCrossingDoubles
 // doubles per entry, at most crossing_cap entries, *crossing_count zero on
@@ -79,11 +81,13 @@ struct TileShape {
 // the view frustum.  Entries beyond the cap keep the whole view.
 constexpr int kCrossingDoubles = 12;
 hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n_views, const DevOptions &opt,
-                             float4 *colours, float4 *records, uint32_t *depth_keys, uint32_t *order, uint2 *boxes,
+                             float4 *colours, float4 *records, uint32_t *depth_keys, uint2 *boxes,
                              Conic *conics, uint32_t *tile_counts, double *crossing, int64_t *crossing_count,
                              uint32_t crossing_cap, hipStream_t stream);
 
 // Stable LSD radix sort of (key, value) pairs on bits [0, bits), 8-bit digits
+// (with `iota` the input values are not read: they are the positions 0, 1,
+// 2, ...)
 // (radix_passes(bits) passes of a per-workgroup digit histogram, a scan of
 // each digit's row over the workgroups, and a stable scatter).  n_dev (may
 // be null) holds a device-side element count, clamped to n_max.  With
@@ -95,7 +99,7 @@ hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n
 int radix_passes(int bits);
 hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt, int64_t n_max,
                       const int64_t *n_dev, int bits, bool drop, uint32_t drop_key, int64_t *kept_out,
-                      uint32_t *hist, uint32_t *row_total, hipStream_t stream);
+                      uint32_t *hist, uint32_t *row_total, hipStream_t stream, bool iota = false);
 size_t radix_hist_entries(int64_t n_max);
 
 // Binning scan over the depth order (Gaussian-view order[k] at position k,

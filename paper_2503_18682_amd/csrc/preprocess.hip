@@ -29,7 +29,7 @@ __device__ void write_exact_mip_record(float4 *rec, const double mu[3], const do
     const double ilam = 1.0 / (smax * smax), iz = 1.0 / mu[2];
     const double u0 = mu[0] * iz, v0 = mu[1] * iz;
     const double qx = mu[2] / (V.fx * smax), qy = mu[2] / (V.fy * smax);
-    const double ifx = 1.0 / V.fx, ify = 1.0 / V.fy;
+    const double ifx = V.ifx, ify = V.ify;
     double P0[3], P1[3], Q0[3], Q1[3], rho[3], s2[3];
     for (int k = 0; k < 3; ++k) {
         // (R_p^T e_r)_k = R_p[r][k]
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                                                     const DevView *__restrict__ views, int n_views, DevOptions opt,
                                                     const float4 *__restrict__ colours,
                                                     float4 *__restrict__ records, uint32_t *__restrict__ depth_keys,
-                                                    uint32_t *__restrict__ order, uint2 *__restrict__ boxes,
+                                                    uint2 *__restrict__ boxes,
                                                     Conic *__restrict__ conics, uint32_t *__restrict__ tile_counts,
                                                     double *__restrict__ crossing,
                                                     unsigned long long *__restrict__ crossing_count,
@@ -138,7 +138,6 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
     for (int v = 0; v < n_views; ++v) {
         const DevView &V = views[v];
         const size_t idx = (size_t)v * n + i;
-        order[idx] = (uint32_t)idx;
         uint32_t key = 0xffffffffu, cnt = 0;
         uint2 box = make_uint2(0u, 0u);
         const double *W = V.w2c;
@@ -193,7 +192,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                 if (px0 > px1 || py0 > py1) break;
                 box = make_uint2((uint32_t)px0 | ((uint32_t)px1 << 16), (uint32_t)py0 | ((uint32_t)py1 << 16));
                 key = __float_as_uint((float)mu[2]);
-                cnt = (uint32_t)((px1 / opt.tile_w - px0 / opt.tile_w + 1) * (py1 / opt.tile_h - py0 / opt.tile_h + 1));
+                cnt = (uint32_t)(((px1 >> opt.tile_wshift) - (px0 >> opt.tile_wshift) + 1) * ((py1 >> opt.tile_hshift) - (py0 >> opt.tile_hshift) + 1));
                 const double G00 = sqrt(A00), G01 = A01 / G00, G11 = sqrt(A11 - G01 * G01);
                 float4 *rec = records + idx * 4;
                 rec[0] = make_float4(pc.u_hi, pc.v_hi, __uint_as_float(pc.lo_bits),
@@ -245,7 +244,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                     const int Wd = V.width, Hd = V.height;
                     box = make_uint2((uint32_t)(Wd - 1) << 16, (uint32_t)(Hd - 1) << 16);
                     key = __float_as_uint((float)mu[2]);
-                    cnt = (uint32_t)(((Wd - 1) / opt.tile_w + 1) * ((Hd - 1) / opt.tile_h + 1));
+                    cnt = (uint32_t)((((Wd - 1) >> opt.tile_wshift) + 1) * (((Hd - 1) >> opt.tile_hshift) + 1));
                     const Centre pc = projected_centre(mu, V);
                     write_exact_mip_record(records + idx * (kRecordFloatsExactMip / 4), mu, Rp, s, o, sig2, V,
                                            pc.u_hi, pc.v_hi, pc.lo_bits, (uint32_t)(Hd - 1) << 16, colours[idx]);
@@ -392,7 +391,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
             // A2 = (S^-1 R_p^T)[:, 0:2] diag(1/fx, 1/fy): a pixel offset delta moves
             // the whitened ray direction by A2 delta.
             double A2[3][2];
-            const double ifx = 1.0 / V.fx, ify = 1.0 / V.fy;
+            const double ifx = V.ifx, ify = V.ify;
             for (int k = 0; k < 3; ++k) {
                 A2[k][0] = Rp[k] * isv[k] * ifx;
                 A2[k][1] = Rp[3 + k] * isv[k] * ify;
@@ -421,7 +420,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
             }
             // tiles of the box; the emission kernel lists those whose row bands
             // meet the support and marks the others empty
-            cnt = (uint32_t)((px1 / opt.tile_w - px0 / opt.tile_w + 1) * (py1 / opt.tile_h - py0 / opt.tile_h + 1));
+            cnt = (uint32_t)(((px1 >> opt.tile_wshift) - (px0 >> opt.tile_wshift) + 1) * ((py1 >> opt.tile_hshift) - (py0 >> opt.tile_hshift) + 1));
             // the residuals of the centre go into one fp16 pair; the freed slot
             // holds the covered pixel rows for in-tile culling
             const uint32_t rows = (uint32_t)py0 | ((uint32_t)py1 << 16);
@@ -551,7 +550,7 @@ __global__ __launch_bounds__(kClipBlock) void k_clip_crossing(const double *__re
         }
         boxes[idx] = make_uint2((uint32_t)px0 | ((uint32_t)px1 << 16), (uint32_t)py0 | ((uint32_t)py1 << 16));
         tile_counts[idx] =
-            (uint32_t)((px1 / opt.tile_w - px0 / opt.tile_w + 1) * (py1 / opt.tile_h - py0 / opt.tile_h + 1));
+            (uint32_t)(((px1 >> opt.tile_wshift) - (px0 >> opt.tile_wshift) + 1) * ((py1 >> opt.tile_hshift) - (py0 >> opt.tile_hshift) + 1));
         records[(size_t)idx * rec_floats + 3] = __uint_as_float((uint32_t)py0 | ((uint32_t)py1 << 16));
     }
 }
@@ -593,7 +592,7 @@ __global__ __launch_bounds__(256) void k_colour(const float *__restrict__ means,
 }  // namespace
 
 hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n_views, const DevOptions &opt,
-                             float4 *colours, float4 *records, uint32_t *depth_keys, uint32_t *order, uint2 *boxes,
+                             float4 *colours, float4 *records, uint32_t *depth_keys, uint2 *boxes,
                              Conic *conics, uint32_t *tile_counts, double *crossing, int64_t *crossing_count,
                              uint32_t crossing_cap, hipStream_t stream)
 {
@@ -614,7 +613,7 @@ hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n
                                                         : kPrepRay;
 #define RGS_PRE(M)                                                                                              \
     k_preprocess<M><<<grid, block, 0, stream>>>(g.means, g.log_scales, g.quats, g.opacity_logits, n, views,     \
-                                                n_views, opt, colours, records, depth_keys, order, boxes, conics, \
+                                                n_views, opt, colours, records, depth_keys, boxes, conics,        \
                                                 tile_counts, crossing,                                            \
                                                 reinterpret_cast<unsigned long long *>(crossing_count), crossing_cap)
     switch (mode) {

@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
         const uint32_t key = idx < n ? keys_in[idx] : 0u;
         const bool valid = idx < n && !(drop && key == drop_key);
         my_key[r] = key;
-        my_val[r] = valid ? vals_in[idx] : 0u;
+        my_val[r] = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;
         const uint32_t d = (key >> shift) & mask;
         unsigned long long peers = __ballot(valid);
         for (int b = 0; b < bits; ++b) {
@@ -696,7 +696,7 @@ void radix_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *
 
 hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt, int64_t n_max,
                       const int64_t *n_dev, int bits, bool drop, uint32_t drop_key, int64_t *kept_out,
-                      uint32_t *hist, uint32_t *row_total, hipStream_t stream)
+                      uint32_t *hist, uint32_t *row_total, hipStream_t stream, bool iota)
 {
     const int passes = radix_passes(bits);
     const int items = radix_items_for(n_max);
@@ -712,12 +712,13 @@ hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32
         const int pbits = (bits - shift + (passes - p) - 1) / (passes - p);
         const bool pdrop = drop && p == 0;
         const int64_t *pn = drop && p > 0 ? kept_out : n_dev;
+        const uint32_t *pvi = iota && p == 0 ? nullptr : vi;
         if (items == 4)
-            radix_pass<4>(ki, vi, ko, vo, n_max, pn, shift, pbits, pdrop, drop_key, kept_out, hist, row_total, stream);
+            radix_pass<4>(ki, pvi, ko, vo, n_max, pn, shift, pbits, pdrop, drop_key, kept_out, hist, row_total, stream);
         else if (items == 8)
-            radix_pass<8>(ki, vi, ko, vo, n_max, pn, shift, pbits, pdrop, drop_key, kept_out, hist, row_total, stream);
+            radix_pass<8>(ki, pvi, ko, vo, n_max, pn, shift, pbits, pdrop, drop_key, kept_out, hist, row_total, stream);
         else
-            radix_pass<16>(ki, vi, ko, vo, n_max, pn, shift, pbits, pdrop, drop_key, kept_out, hist, row_total, stream);
+            radix_pass<16>(ki, pvi, ko, vo, n_max, pn, shift, pbits, pdrop, drop_key, kept_out, hist, row_total, stream);
         shift += pbits;
         uint32_t *t;
         t = ki; ki = ko; ko = t;
