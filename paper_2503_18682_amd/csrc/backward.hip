@@ -172,11 +172,15 @@ __global__ __launch_bounds__(256) void k_zero_kept_grads(const uint32_t *__restr
                                                          const int64_t *__restrict__ kept_p, int64_t n_max,
                                                          int stride4, float4 *__restrict__ grads)
 {
-    // one kept entry (a whole record gradient) per thread and step
+    // consecutive threads clear consecutive float4 of one record gradient, so
+    // each record's line is written whole by one store instruction (stride4 is
+    // a power of two: the entry and part are a shift and a mask)
     const int64_t kept = min(*kept_p, n_max);
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < kept; e += (int64_t)gridDim.x * blockDim.x) {
-        float4 *dst = grads + (size_t)order[e] * stride4;
-        for (int c = 0; c < stride4; ++c) dst[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int sh = __builtin_ctz((unsigned)stride4);
+    const int64_t total = kept << sh;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = i >> sh;
+        grads[((size_t)order[e] << sh) + (size_t)(i & (stride4 - 1))] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
 }
 
@@ -439,7 +443,7 @@ hipError_t launch_zero_kept_grads(const uint32_t *order, const int64_t *kept, in
                                   float *grads, int num_cus, hipStream_t stream)
 {
     if (n_max == 0) return hipSuccess;
-    const int64_t want = (n_max + 255) / 256;
+    const int64_t want = (n_max * (grad_floats_per / 4) + 255) / 256;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cus * 16));
     k_zero_kept_grads<<<grid, 256, 0, stream>>>(order, kept, n_max, grad_floats_per / 4,
                                                 reinterpret_cast<float4 *>(grads));
