@@ -180,9 +180,15 @@ def cpu_baseline_c1(scene, cam, opts):
     import oracle
 
     threads = os.cpu_count() or 1
-    t = time.perf_counter()
+    # the per-Gaussian stage alone (no rows), after one untimed call that pays
+    # the one-time costs (library load, first touch of the scene's pages);
+    # the faster of two calls, so that its noise is not subtracted from the rows
     oracle.render(scene, cam, opts, rows=(0, 0), threads=threads, branches=False)
-    t_fixed = time.perf_counter() - t
+    t_fixed = float("inf")
+    for _ in range(2):
+        t = time.perf_counter()
+        oracle.render(scene, cam, opts, rows=(0, 0), threads=threads, branches=False)
+        t_fixed = min(t_fixed, time.perf_counter() - t)
     H = cam["height"]
     band, rows_done, t_rows = 6, 0, 0.0
     for b in range(8):
