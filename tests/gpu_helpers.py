@@ -31,9 +31,10 @@ def read(buf, offset, count, dtype):
     return raw.view(dtype)
 
 
-def render_with_ws(r, scene, cams, opts, capacity=None, flags=0):
+def render_with_ws(r, scene, cams, opts, capacity=None, flags=0, to_host=True):
     """Render through the C ABI with an explicit workspace; returns
-    (outs as numpy dicts, workspace buffer, ws struct, layout, status)."""
+    (outs as numpy dicts (device tensors with to_host=False), workspace
+    buffer, ws struct, layout, status)."""
     g = to_dev(scene)
     n = int(scene["opacity_logits"].shape[0])
     cap = capacity or r.default_capacity(n, len(cams))
@@ -47,7 +48,7 @@ def render_with_ws(r, scene, cams, opts, capacity=None, flags=0):
         r.render_into(g, cams, outs, ws, opts)
         ok, need = r.status(ws)
     lay = r.layout(n, cams, cap, flags, opts)
-    host = [{k: v.cpu().numpy() for k, v in o.items()} for o in outs]
+    host = [{k: v.cpu().numpy() for k, v in o.items()} for o in outs] if to_host else outs
     return host, buf, ws, lay, (ok, need)
 
 

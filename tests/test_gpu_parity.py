@@ -410,6 +410,41 @@ def test_c1_full_frame(r, pose):
     assert_image_close(outs[0]["rgb"], outs[0]["final_T"], oracle.render(sc, cam, opts), label=f"c1 pose {pose}")
 
 
+def test_maximum_view_size(r):
+    """The largest view the ABI takes (16384 x 16384) at the finest tiles
+    (8 x 8: 4.2M tiles, 23-bit tile ids): keys, boxes, box tile counts, the
+    full tile list and slot bits bit-exact, and 6000 sampled pixels against
+    the oracle; then a 16384 x 40 view (widest, ragged last tile row) on
+    every pixel."""
+    sc = scenegen.tiny_scene(57, 3000, sh_degree=1, half_extent=1.5, log_scale_mean=-4.5, log_scale_std=0.6)
+    cam = scenegen.pinhole(scenegen.look_at((0.3, -0.2, -3.0)), 16384, 16384, 90)
+    opts = scenegen.default_options(tile_w=8, tile_h=8)
+    say("case maximum view size: 3000 Gaussians, 16384x16384, 8x8 tiles")
+    outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts, to_host=False)
+    assert ok
+    assert int(lay.total_tiles) == 2048 * 2048
+    sp = oracle.preprocess(sc, cam, opts)
+    assert m == oracle_box_tiles(sp)[1].sum()
+    _check_keys_boxes_counts(buf, lay, sp, sc["opacity_logits"].shape[0])
+    _check_lists(buf, lay, m, sp, cam, opts, "16384x16384 lists")
+    _check_bands(buf, lay, sp, cam, opts, "16384x16384 slot bits")
+    rng = np.random.default_rng(12)
+    px = torch.from_numpy(rng.integers(0, 16384, 6000))
+    py = torch.from_numpy(rng.integers(0, 16384, 6000))
+    o = outs[0]
+    g_rgb = o["rgb"][:, py.cuda(), px.cuda()].T.cpu().numpy()
+    g_T = o["final_T"][py.cuda(), px.cuda()].cpu().numpy()
+    del outs, o, buf, ws
+    ref = oracle.render_pixels(sc, cam, opts, px.numpy(), py.numpy())
+    assert_pixels_close(g_rgb, g_T, ref, label="16384x16384 sampled")
+    cam = scenegen.pinhole(scenegen.look_at((0.3, -0.2, -3.0)), 16384, 40, 90)
+    say("case maximum view width: 3000 Gaussians, 16384x40, 8x8 tiles")
+    outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
+    assert ok
+    _check_lists(buf, lay, m, oracle.preprocess(sc, cam, opts), cam, opts, "16384x40 lists")
+    assert_image_close(outs[0]["rgb"], outs[0]["final_T"], oracle.render(sc, cam, opts), label="16384x40")
+
+
 def _sampled_pixels(outs_v, sc, cam, opts, n_px, rng, label):
     """GPU pixels against the oracle's per-pixel evaluation at n_px random pixels."""
     px = rng.integers(0, cam["width"], n_px)
