@@ -390,21 +390,38 @@ def test_batch_plan_overflow_is_reported_by_batch_status(r):
     assert_image_close(host["rgb"], host["final_T"], oracle.render(sc, cam, opts), label="batch after regrow")
 
 
-@pytest.mark.parametrize("pose", [0, 8])
-def test_c1_full_frame(r, pose):
+@pytest.mark.parametrize("pose,tile,graph", [(0, (8, 16), True), (8, (16, 16), False)],
+                         ids=["pose0-8x16-graph", "pose8-16x16-eager"])
+def test_c1_full_frame(r, pose, tile, graph):
     """500k Gaussians at 1920x1080 (the benchmark frame), two of its 16 orbit
     poses: every pixel against the oracle, depth keys, order, pixel boxes and
     box tile counts of every Gaussian, the full tile list bit-exact and the
-    band bits of every listed instance."""
-    say(f"case c1 full frame: 500k Gaussians, 1920x1080, pose {pose}")
+    slot bits of every listed instance.  Pose 0 runs in the benchmark's launch
+    configuration (8x16 tiles, one HIP-graph replay of a batch plan); pose 8
+    as an eager render at 16x16 tiles."""
+    from paper_2503_18682_amd import renderer as R
+
+    say(f"case c1 full frame: 500k Gaussians, 1920x1080, pose {pose}, tile {tile}, {'graph' if graph else 'eager'}")
     w = scenegen.make_workload("c1")
-    sc, cam, opts = w["scene"], w["cameras"][pose], w["options"]
+    sc, cam = w["scene"], w["cameras"][pose]
+    opts = dict(w["options"], tile_w=tile[0], tile_h=tile[1])
+    n = int(sc["opacity_logits"].shape[0])
     outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
     assert ok
+    if graph:
+        br = R.BatchRenderer(r, n, sc["sh_degree"], [cam], int(ws.capacity), options=opts)
+        g = to_dev(sc)
+        for _ in range(2):  # the capture, then a replay
+            gouts = br.launch(g, [cam])
+        assert br.status()[0]
+        for k in ("rgb", "final_T", "n_contrib"):
+            assert np.array_equal(gouts[0][k].cpu().numpy(), outs[0][k]), k
+        buf = br.buf
+        br.close()
     sp = oracle.preprocess(sc, cam, opts)
     assert (sp["hazard"] & oracle.HAZARD["cull"]).sum() == 0
     assert m == oracle_box_tiles(sp)[1].sum()
-    _check_keys_boxes_counts(buf, lay, sp, sc["opacity_logits"].shape[0])
+    _check_keys_boxes_counts(buf, lay, sp, n)
     _check_lists(buf, lay, m, sp, cam, opts, "c1 lists")
     _check_bands(buf, lay, sp, cam, opts, "c1 bands")
     assert_image_close(outs[0]["rgb"], outs[0]["final_T"], oracle.render(sc, cam, opts), label=f"c1 pose {pose}")
