@@ -67,7 +67,7 @@ __device__ void mip_chain(const double (&mu)[3], const double (&Rp)[9], const do
 // J^T (dL/dSigma_pi) J; dL/dJ = 2 (dL/dSigma_pi) J Sigma; pi has Jacobian J.
 // Adds dL/dmu, dL/dR_p and dL/dlog s.
 __device__ void gs_chain(const double mu[3], const double Rp[9], const double s[3], const DevView &V,
-                         const double gc[2], const double GA[2][2], double dmu[3], double dRp[9], double dls[3])
+                         const double sq[2], const double GA[2][2], double dmu[3], double dRp[9], double dls[3])
 {
     const double iz = 1.0 / mu[2];
     const double J[2][3] = {{V.fx * iz, 0.0, -V.fx * mu[0] * iz * iz}, {0.0, V.fy * iz, -V.fy * mu[1] * iz * iz}};
@@ -79,6 +79,8 @@ __device__ void gs_chain(const double mu[3], const double Rp[9], const double s[
     const double P11 = M[1][0] * M[1][0] + M[1][1] * M[1][1] + M[1][2] * M[1][2];
     const double idet = 1.0 / (P00 * P11 - P01 * P01);
     const double A[2][2] = {{P11 * idet, -P01 * idet}, {-P01 * idet, P00 * idet}};
+    // the anchor's gradient from the record's raw q sums (its M is A, g = 0)
+    const double gc[2] = {A[0][0] * sq[0] + A[0][1] * sq[1], A[1][0] * sq[0] + A[1][1] * sq[1]};
     double T[2][2], GP[2][2];
     for (int r = 0; r < 2; ++r)
         for (int c = 0; c < 2; ++c) T[r][c] = GA[r][0] * A[0][c] + GA[r][1] * A[1][c];
@@ -244,8 +246,13 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
             da += go * o * (1.0 - o);
             continue;
         }
-        const double gu0 = gr[0], gv0 = gr[1], gM00 = gr[2], gM01 = gr[3], gM11 = gr[4], ggx = gr[5], ggy = gr[6];
-        const double gk0 = gr[7], gic2 = gr[8], go = gr[9];
+        // the record's gradient from the raw sums of the backward compositing
+        // kernel (layout at kGradFloats): the q moments are -2 dL/dM sums
+        // (dM01 counts the off-diagonal twice), the dic2 sum 2 dL/d(1/c^2) in
+        // the test form's units, which scale by 1 / s^2 = 2 ln 2 K per power of
+        // den (dk0, dg, du0, dv0) and by 1 / s^4 for 1/c^2
+        const double gM00 = -0.5 * (double)gr[2], gM01 = -(double)gr[3], gM11 = -0.5 * (double)gr[4];
+        const double sqx = gr[0], sqy = gr[1], sd = gr[7], go = gr[9];
         const double *W = V.w2c;
         const double mu[3] = {W[0] * m[0] + W[1] * m[1] + W[2] * m[2] + W[3],
                               W[4] * m[0] + W[5] * m[1] + W[6] * m[2] + W[7],
@@ -256,10 +263,10 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         if constexpr (MODE == kBwdGS) {
             // the record's anchor is pi(mu) and its M = G^T G is Sigma_pi^-1;
             // den, g, 1/c^2 are constants of this divergence
-            const double gc[2] = {gu0, gv0};
+            const double sq[2] = {sqx, sqy};
             const double GA[2][2] = {{gM00, 0.5 * gM01}, {0.5 * gM01, gM11}};
             double dmu[3] = {0, 0, 0}, dRp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-            gs_chain(mu, Rp, s, V, gc, GA, dmu, dRp, dl);
+            gs_chain(mu, Rp, s, V, sq, GA, dmu, dRp, dl);
             for (int r = 0; r < 3; ++r)
                 for (int c = 0; c < 3; ++c)
                     dR[3 * r + c] += W[r] * dRp[c] + W[4 + r] * dRp[3 + c] + W[8 + r] * dRp[6 + c];
@@ -301,6 +308,20 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         }
         double wv[2];
         for (int c = 0; c < 2; ++c) wv[c] = A2[0][c] * mw[0] + A2[1][c] * mw[1] + A2[2][c] * mw[2];
+        // the record's M = G^T G = A2^T A2 - w w^T / c^2 and g = w / c^2, and the
+        // test form's 1 / s^2 = 2 ln 2 K with K = log2(ov / p_min)
+        double Mg[3] = {-wv[0] * wv[0] * ic2, -wv[0] * wv[1] * ic2, -wv[1] * wv[1] * ic2};
+        for (int k = 0; k < 3; ++k) {
+            Mg[0] += A2[k][0] * A2[k][0];
+            Mg[1] += A2[k][0] * A2[k][1];
+            Mg[2] += A2[k][1] * A2[k][1];
+        }
+        // (single precision, as the record's own log2 of its opacity)
+        const double is2 = 1.38629436111989061 * (double)(__log2f((float)ov) - __log2f((float)opt.p_min));
+        const double ggx = is2 * gr[5], ggy = is2 * gr[6], gk0 = is2 * sd;
+        const double gic2 = 0.5 * is2 * is2 * gr[8];
+        const double gu0 = Mg[0] * sqx + Mg[1] * sqy - is2 * (wv[0] * ic2) * sd;
+        const double gv0 = Mg[1] * sqx + Mg[2] * sqy - is2 * (wv[1] * ic2) * sd;
         // symmetric matrix gradient of M (the off-diagonal parameter appears twice)
         const double Gm[2][2] = {{gM00, 0.5 * gM01}, {0.5 * gM01, gM11}};
         double dA2[3][2], dw[2], dc2;

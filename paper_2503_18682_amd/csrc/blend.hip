@@ -572,11 +572,6 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
     constexpr int PPL = slot_layout(TW, TH).slots;
     __shared__ float4 s_rec[4][64][4];
     __shared__ uint32_t s_id[4][64];
-    // constant factor of the record-gradient component this lane adds: the q
-    // moment sums are -2 dL/dM (dM01 counts the off-diagonal twice: -1), the
-    // dic2 sum is 2 dL/d(1/c^2)
-    const int cl = wave_sum16_index((int)(threadIdx.x & 63));
-    const float c_factor = (cl == 2 || cl == 4) ? -0.5f : cl == 3 ? -1.0f : cl == 8 ? 0.5f : 1.0f;
     const uint32_t amax_bits = __float_as_uint(P.alpha_max);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nq = min((int)gridDim.x, kQueues), q = (int)blockIdx.x % nq;
@@ -703,9 +698,8 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                     // so with ew = w dL/domega / t^2: dL/dq = -ew den^2 / 2,
                     // dL/dden = ew q den, dL/d(1/c^2) = ew q^2 / 2.  The sums
                     // below leave out the constant factors (-1/2 for the q
-                    // moments, 1/2 for dic2), which are applied once per record
-                    // with the rescaling from the test form's qs = s^2 q (the
-                    // sums through dL/dden come out times s^2, dic2 times s^4)
+                    // moments, 1/2 for dic2) and are in the test form's units
+                    // (qs = s^2 q): both are applied by the per-Gaussian backward
                     const float ew = wd * (rt * rt);
                     const float dq = ew * (f.den * f.den);
                     const float dden = ew * (f.q * f.den);
@@ -732,25 +726,18 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                     sxy = dx0 * sqy;
                     sdx = dx0 * sd;
                 }
-                // q = delta^T M delta with M = H^T H: dL/dM00 = sum dq dx^2,
-                // dL/dM01 = sum dq 2 dx dy, dL/dM11 = sum dq dy^2; dq/ddelta =
-                // 2 M delta, so dL/du0 = -(2 M sum dq delta + g sum dden)
-                // (the q sums here are -2 dL/dq sums: du0 takes them as they are)
-                const float Mxx = __builtin_fmaf(R.H10, R.H10, R.H00 * R.H00);
-                const float Mxy = __builtin_fmaf(R.H10, R.H11, R.H00 * R.H01);
-                const float Myy = __builtin_fmaf(R.H11, R.H11, R.H01 * R.H01);
-                const float du0 = __builtin_fmaf(Mxx, sqx, __builtin_fmaf(Mxy, sqy, -(R.gx * sd)));
-                const float dv0 = __builtin_fmaf(Mxy, sqx, __builtin_fmaf(Myy, sqy, -(R.gy * sd)));
-                const float vals[16] = {du0, dv0, sxx, sxy, syy, sdx, sdy, sd, dic2, dop, dr,
+                // the record's gradient as raw sums (layout at kGradFloats);
+                // the per-Gaussian backward turns them into dL/d(record) once
+                // per Gaussian-view, in double precision, rather than once per
+                // (record, tile) here
+                const float vals[16] = {sqx, sqy, sxx, sxy, syy, sdx, sdy, sd, dic2, dop, dr,
                                         dg, db, 0.f, 0.f, 0.f};
                 const float sum = wave_sum16(vals, lane);
                 const int c = wave_sum16_index(lane);
                 const uint32_t rid = s_id[wave][jj];
-                const float is2 = R.K * kTwoLn2;  // 1 / s^2
-                const float unit = c_factor * (c == 8 ? is2 * is2 : (c <= 1 || (c >= 5 && c <= 7)) ? is2 : 1.0f);
-                // one lane per gradient component adds it to the record's accumulators
+                // one lane per component adds it to the record's accumulators
                 if ((lane & 3) == 0 && c < 13 && rid != 0xffffffffu)
-                    atomicAdd(record_grads + (size_t)rid * kGradFloats + c, sum * unit);
+                    atomicAdd(record_grads + (size_t)rid * kGradFloats + c, sum);
             }
             lds_wave_sync();
             if (have_next) {
