@@ -252,7 +252,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         // the test form's units, which scale by 1 / s^2 = 2 ln 2 K per power of
         // den (dk0, dg, du0, dv0) and by 1 / s^4 for 1/c^2
         const double gM00 = -0.5 * (double)gr[2], gM01 = -(double)gr[3], gM11 = -0.5 * (double)gr[4];
-        const double sqx = gr[0], sqy = gr[1], sd = gr[7], go = gr[9];
+        // gr[9] = sum of w dL/dw = the record opacity ov times dL/dov
+        const double sqx = gr[0], sqy = gr[1], sd = gr[7], gw = gr[9];
         const double *W = V.w2c;
         const double mu[3] = {W[0] * m[0] + W[1] * m[1] + W[2] * m[2] + W[3],
                               W[4] * m[0] + W[5] * m[1] + W[6] * m[2] + W[7],
@@ -271,7 +272,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
                 for (int c = 0; c < 3; ++c)
                     dR[3 * r + c] += W[r] * dRp[c] + W[4 + r] * dRp[3 + c] + W[8 + r] * dRp[6 + c];
             for (int c = 0; c < 3; ++c) dm[c] += W[c] * dmu[0] + W[4 + c] * dmu[1] + W[8 + c] * dmu[2];
-            da += go * o * (1.0 - o);
+            da += gw * (1.0 - o);
             continue;
         }
         // rendered scales and opacity: widened by the MIP transform when it is on
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         }
         // the record's opacity is ov: dL/dlog ov = go ov
         if constexpr (MODE == kBwdMip) {
-            mip_chain(mu, Rp, s, sv, sig2, dls, go * ov, dl, dmu, dRp);
+            mip_chain(mu, Rp, s, sv, sig2, dls, gw, dl, dmu, dRp);
         } else {
             for (int k = 0; k < 3; ++k) dl[k] += dls[k];
         }
@@ -374,7 +375,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
             for (int c = 0; c < 3; ++c) dR[3 * r + c] += W[r] * dRp[c] + W[4 + r] * dRp[3 + c] + W[8 + r] * dRp[6 + c];
         for (int c = 0; c < 3; ++c) dm[c] += W[c] * dmu[0] + W[4 + c] * dmu[1] + W[8 + c] * dmu[2];
         // prior opacity: dlog o / da = 1 - o
-        da += go * ov * (1.0 - o);
+        da += gw * (1.0 - o);
     }
     // quaternion: dR/d(w,x,y,z) of the unit quaternion, then the normalisation
     const double J[9][4] = {{0, 0, -4 * y, -4 * z},       {-2 * z, 2 * y, 2 * x, -2 * w}, {2 * y, 2 * z, 2 * w, 2 * x},

@@ -652,7 +652,6 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                 const TRec R = load_trec(s_rec[wave][jj]);
                 const RowSpan span = row_span(R.rows, ty * TH);
                 const uint32_t bands = __builtin_amdgcn_readfirstlane(R.rows);
-                const float inv_o = __builtin_amdgcn_exp2f(-R.log2o);
                 // the slots of a lane share its pixel column when they are row
                 // bands (one slot across)
                 constexpr bool one_column = slot_layout(TW, TH).bx == 1;
@@ -693,7 +692,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                     T[k] = Tb;
                     // alpha clamped at alpha_max passes no gradient to omega
                     const float wd = w < P.alpha_max ? w * dL_da : 0.0f;
-                    dop = __builtin_fmaf(wd, inv_o, dop);
+                    dop += wd;  // sum of w dL/dw: the record opacity times dL/d(opacity)
                     // dL/dD = -w dL/domega / 2; D = q / t with t = den^2 + q / c^2,
                     // so with ew = w dL/domega / t^2: dL/dq = -ew den^2 / 2,
                     // dL/dden = ew q den, dL/d(1/c^2) = ew q^2 / 2.  The sums

@@ -56,14 +56,15 @@ inline int record_floats(int mip) { return mip == 2 ? kRecordFloatsExactMip : kR
 // as sums over its fragments (13 used):
 //   [0, 1]  sum e dx, sum e dy          [2, 3, 4]  sum e dx^2, e dx dy, e dy^2
 //   [5, 6]  sum f dx, sum f dy          [7]        sum f
-//   [8]     sum ew q^2                  [9]        dL/d(record opacity)
+//   [8]     sum ew q^2                  [9]        sum w dL/dw
 //   [10..12] dL/d(colour)
 // with (dx, dy) the pixel offset from the projected centre, q and den the
 // fragment's quadratic and denominator in the test form (q_s = s^2 q, 1 / s^2
 // = 2 ln 2 K, K = log2(record opacity / p_min)), ew = w dL/dw / t^2, e = ew
-// den^2 and f = ew q_s den.  The per-Gaussian backward turns them into the
+// den^2 and f = ew q_s den (sum w dL/dw is the record opacity times the
+// derivative with respect to it).  The per-Gaussian backward turns them into the
 // derivatives with respect to the record's u0, v0, M = G^T G, g, k0 and 1/c^2
-// (see record_gradient in backward.hip).
+// (k_preprocess_bwd in backward.hip).
 constexpr int kGradFloats = 16;
 
 // With exact MIP (mip = 2) the record gradient is 32 floats (layout at the
