@@ -282,9 +282,10 @@ typedef struct {
                               [0, counters[4]) */
     size_t offsets;        /* uint32 per Gaussian-view: first instance of each sorted entry */
     size_t inst_tiles;     /* uint32 per instance: global tile id, sorted, [0, counters[3]) (box tiles
-                              whose row bands all miss the support are dropped by the sort) */
+                              whose pixel-centre rectangle misses the support are dropped by the sort) */
     size_t inst_ids;       /* uint32 per instance: Gaussian-view id (low 28 bits) sorted by (tile, depth, id);
-                              the top 4 bits flag the tile's row bands that meet the support */
+                              with tile shapes of at most 4 pixel slots of 64 pixels, the top 4 bits
+                              flag the slots that the support reaches (0 with more slots) */
     size_t tile_ranges;    /* uint32[2] per global tile: [start, end) into the instance arrays */
     size_t record_grads;   /* float[16] per Gaussian-view (float[32] with mip = 2; RGS_WS_BACKWARD only, else 0) */
     size_t total_bytes;    /* what rgs_workspace_size reports */

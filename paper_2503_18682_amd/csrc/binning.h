@@ -10,11 +10,12 @@
 // unbounded on the image plane and every tile of the bounding rectangle is
 // kept.  A tile is listed when the continuous rectangle spanned by its pixel
 // centres (clipped to the Gaussian's pixel box) meets the ellipse.  Its
-// culling bands, groups of pixel rows that the compositing kernel can skip
-// together, are tested the same way, and the bands that meet the ellipse
-// travel with the instance.  The tests are done per tile row: the ellipse's
-// x-extent over the row's heights and over each band's heights is computed in
-// closed form, then each tile of the row is an interval comparison.
+// pixel slots, the 64-pixel groups that a compositing wave tests or skips
+// together (slot_layout below), are tested the same way, and the bits of the
+// slots that meet the ellipse travel with the instance.  The tests are done
+// per tile row: the ellipse's x-extent over the row's heights and over each
+// slot row's heights is computed in closed form, then each tile and slot of
+// the row is an interval comparison.
 #pragma once
 
 #include <hip/hip_runtime.h>

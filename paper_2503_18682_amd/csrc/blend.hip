@@ -44,13 +44,13 @@ namespace {
 // pixel gets the same arithmetic whatever the tile shape, and offsets from
 // the corner are small exact integers.
 //   [0] cx, cy, K, rows   projected centre minus the block corner;
-//                          K = log2(o / p_min); covered rows or band bits
+//                          K = log2(o / p_min); covered rows or slot bits
 //   [1] H00 H01 H10 H11   H = s G
 //   [2] gx, gy, k0, j     j = ic2 / s^2
 //   [3] log2o, r, g, b
 struct TRec {
     float cx, cy, K, H00, H01, H10, H11, gx, gy, k0, j, log2o, r, g, b;
-    uint32_t rows;  // first | last << 16 covered pixel row, or band bits
+    uint32_t rows;  // first | last << 16 covered pixel row, or the instance's slot bits
 };
 
 struct Frag {
@@ -92,8 +92,8 @@ __device__ __forceinline__ void frag_omega(const TRec &R, Frag &f)
 }
 
 // Rows of the tile covered by a record, relative to the tile's first row, as
-// wave-uniform (scalar) values: lane l's pixel k lies in row band
-// [k * LY, k * LY + LY), so a band outside [r0, r1] is skipped by the whole wave.
+// wave-uniform (scalar) values: where the tile's slots carry no bits, a slot
+// whose rows lie outside [r0, r1] is skipped by the whole wave.
 struct RowSpan {
     int r0, r1;
 };
@@ -125,11 +125,11 @@ struct BlendParams {
     unsigned long long *item_clock;  // per work-order slot: wall clock at the item's end (may be null)
 };
 
-// Raw record (four float4) of instance value `inst` (id | band bits),
+// Raw record (four float4) of instance value `inst` (id | slot bits),
 // fetched ahead of its conversion.  An id outside the record array (never
 // produced by the binning) gets a placeholder that cannot reach p_min.  When
-// a tile has at most 4 culling bands the covered-rows word is not needed,
-// and the instance's band bits take its place.
+// the tile's slots carry bits the covered-rows word is not needed, and the
+// instance's slot bits take its place.
 __device__ __forceinline__ void fetch_record(float4 (&r)[4], const float4 *__restrict__ records, uint32_t inst,
                                              uint32_t n_records, bool bands_in_rows)
 {
@@ -399,7 +399,7 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
         const uint2 rg = ranges[tile];
         float T[PPL], C0[PPL], C1[PPL], C2[PPL], pxr[PPL], pyr[PPL], aux[PPL];
         int last[PPL];
-        // pixel slots (row bands of 64 pixels) that hold a live pixel: a slot
+        // pixel slots (64 pixels each) that hold a live pixel: a slot
         // whose pixels have all stopped is skipped by the whole wave
         uint32_t live = 0u;
 #pragma unroll

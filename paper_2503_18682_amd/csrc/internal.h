@@ -127,7 +127,7 @@ hipError_t binning_scan(const uint32_t *keys, const uint2 *boxes, const uint32_t
 size_t scan_block_entries(int64_t n);
 
 // Instances of every tile row (one lane per row, `grid` workgroups looping
-// over counters[2] rows): (tile id, id | band bits) for listed tiles and
+// over counters[2] rows): (tile id, id | slot bits) for listed tiles and
 // (empty_tile, id) for the other tiles of the box.  Also zeroes `ranges`
 // (total_tiles entries) and `sched` (sched_words()) for the stages after the
 // tile sort; always launched, also for an empty scene.

@@ -403,7 +403,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                     G[r][cc] = Rv[r] * A2[0][cc] + Rv[3 + r] * A2[1][cc] + Rv[6 + r] * A2[2][cc];
             const double gx = (A2[0][0] * mw[0] + A2[1][0] * mw[1] + A2[2][0] * mw[2]) * ic2;
             const double gy = (A2[0][1] * mw[0] + A2[1][1] * mw[1] + A2[2][1] * mw[2]) * ic2;
-            // support ellipse in pixel offsets; list the tiles whose row bands meet it
+            // support ellipse in pixel offsets; the emission lists the tiles it meets
             Conic C;
             {
                 const double M00 = G[0][0] * G[0][0] + G[1][0] * G[1][0];
@@ -418,8 +418,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                 C.u0 = u_c;
                 C.v0 = v_c;
             }
-            // tiles of the box; the emission kernel lists those whose row bands
-            // meet the support and marks the others empty
+            // tiles of the box; the emission kernel lists those whose pixel-centre
+            // rectangle meets the support and marks the others empty
             cnt = (uint32_t)(((px1 >> opt.tile_wshift) - (px0 >> opt.tile_wshift) + 1) * ((py1 >> opt.tile_hshift) - (py0 >> opt.tile_hshift) + 1));
             // the residuals of the centre go into one fp16 pair; the freed slot
             // holds the covered pixel rows for in-tile culling

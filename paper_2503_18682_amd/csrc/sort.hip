@@ -481,10 +481,10 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(int64_t n_max, const in
 // ---------------------------------------------------------------- emission
 // One lane per tile row of the sorted Gaussian-views (a grid-stride loop
 // over the row count the scan produced): the lane computes the support's
-// x-extent over the row and over its culling bands and writes every tile of
-// the box row at its scanned position, as (tile id, id | band bits) when the
-// tile's pixel-centre rectangle meets the support and as the empty marker
-// `empty_tile` otherwise.  Instances end up
+// x-extent over the row and over its rows of pixel slots and writes every
+// tile of the box row at its scanned position, as (tile id, id | slot bits)
+// when the tile's pixel-centre rectangle meets the support and as the empty
+// marker `empty_tile` otherwise.  Instances end up
 // grouped by Gaussian-view in depth order, so a stable sort on the tile id
 // alone leaves every tile's list in depth order.  The kernel also clears the
 // tile ranges and the compositing scheduling words for the stages after the

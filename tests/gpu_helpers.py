@@ -56,13 +56,13 @@ ID_MASK = (1 << 28) - 1
 
 
 def listed_count(buf, lay):
-    """Instances left after the tile sort (box tiles whose row bands all miss
-    the support leave the sort)."""
+    """Instances left after the tile sort (box tiles whose pixel-centre
+    rectangle misses the support leave the sort)."""
     return int(read(buf, lay.counters, 8, np.int64)[3])
 
 
 def instance_lists(buf, lay, with_bands=False):
-    """Sorted listed instances (tile ids, Gaussian-view ids[, band bits])."""
+    """Sorted listed instances (tile ids, Gaussian-view ids[, slot bits])."""
     m = listed_count(buf, lay)
     tiles = read(buf, lay.inst_tiles, m, np.uint32).astype(np.int64)
     raw = read(buf, lay.inst_ids, m, np.uint32).astype(np.int64)

@@ -5,8 +5,8 @@ a decision (omega vs p_min, the termination test, the sign of tau) lies within
 rounding distance within 2e-4 of one of its correct results, which the oracle
 enumerates.  Depth keys, pixel boxes, box tile counts and tile lists:
 bit-exact, excluding Gaussians the oracle flags as hazards (expected count
-~0).  The culling-band bits of each listed instance: a superset of the bands
-that hold a pixel of the Gaussian's support."""
+~0).  The slot bits of each listed instance: a superset of the tile's pixel
+slots that hold a pixel of the Gaussian's support."""
 import numpy as np
 import pytest
 import torch
@@ -111,7 +111,7 @@ def test_c0_image_keys_and_lists(r):
 def test_lists_are_consistent_with_gpu_counts_boxes_and_keys(r):
     """The integer stages are exact functions of the GPU's own outputs: every
     Gaussian is listed in at most its counted number of box tiles, all inside
-    its box's tile rectangle and each with band bits; the kept views and the
+    its box's tile rectangle and each with slot bits; the kept views and the
     listed instances are counted right; re-sorting the GPU's instances on the
     host by (tile, depth key, id) reproduces its order; tile ranges bracket
     exactly the runs of each tile."""
