@@ -38,7 +38,7 @@ constexpr int64_t kCrossingCap = 1 << 16;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t counters, views, colours, records, keys_a, keys_b, order_a, order_b, boxes, sorted_boxes, conics, tile_counts,
+    size_t counters, views, records, keys_a, keys_b, order_a, order_b, boxes, sorted_boxes, conics, tile_counts,
         offsets, block_sums;
     size_t crossing;          // quads with a vertex at z <= 0, awaiting frustum clipping
     uint32_t crossing_cap;    // entries of the crossing list
@@ -296,7 +296,6 @@ rgs_status compute_layout(rgs_context *ctx, int64_t n, const rgs_camera *cams, i
     };
     L.counters = take(8 * sizeof(int64_t));
     L.views = take(sizeof(DevView) * n_views);
-    L.colours = take(NV * sizeof(float4));
     L.records = take(NV * record_floats(opts->mip) * sizeof(float));
     L.keys_a = take(NV * 4);
     L.keys_b = take(NV * 4);
@@ -484,7 +483,6 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
     uint32_t *tiles_alt = at<uint32_t>(ws, tpasses % 2 ? L.inst_tiles_a : L.inst_tiles_b);
     uint32_t *ids_in = at<uint32_t>(ws, tpasses % 2 ? L.inst_ids_b : L.inst_ids_a);
     uint32_t *ids_alt = at<uint32_t>(ws, tpasses % 2 ? L.inst_ids_a : L.inst_ids_b);
-    float4 *colours = at<float4>(ws, L.colours);
     float4 *records = at<float4>(ws, L.records);
     uint2 *boxes = at<uint2>(ws, L.boxes);
     Conic *conics = at<Conic>(ws, L.conics);
@@ -498,8 +496,8 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
     if (view_stamps) RGS_HIP(ctx, launch_view_clock_start(view_stamps, n_views, stream));
     unsigned long long *item_clock = view_stamps ? at<unsigned long long>(ws, L.item_clock) : nullptr;
     Timer tm(ctx, stream, timing, ST_PRE);
-    RGS_HIP(ctx, launch_preprocess(g, views, n_views, dopt, colours, records, keys_in, boxes, conics,
-                                   tile_counts, at<double>(ws, L.crossing), counters + 5, L.crossing_cap, stream));
+    RGS_HIP(ctx, launch_preprocess(g, views, n_views, dopt, records, keys_in, boxes, conics, tile_counts,
+                                   at<double>(ws, L.crossing), counters + 5, L.crossing_cap, stream));
     tm.mark(ST_PRE);
     // counters: [0] box instances, [1] capacity, [2] tile rows, [3] listed instances, [4] kept views,
     // [5] quads with a vertex at z <= 0

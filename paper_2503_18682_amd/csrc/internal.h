@@ -52,6 +52,13 @@ constexpr int kRecordFloatsExactMip = 28;
 
 inline int record_floats(int mip) { return mip == 2 ? kRecordFloatsExactMip : kRecordFloats; }
 
+// Where r, g, b sit in a record: floats first, first + step, first + 2 step
+// (13, 14, 15; with exact MIP 15, 19, 23).
+struct ColourSlot {
+    int first, step;
+};
+__host__ __device__ constexpr ColourSlot colour_slot(int mip) { return mip == 2 ? ColourSlot{15, 4} : ColourSlot{13, 1}; }
+
 // Gradient of one record as accumulated by the backward compositing kernel,
 // as sums over its fragments (13 used):
 //   [0, 1]  sum e dx, sum e dy          [2, 3, 4]  sum e dx^2, e dx dy, e dy^2
@@ -80,18 +87,17 @@ struct TileShape {
 };
 
 // ---- launchers (each enqueues on `stream`, returns hipError_t) -----------
-// Writes per Gaussian-view: the colour staging entry (colours, float4: r, g,
-// b, non-finite-coefficient flag), record, depth key (0xffffffff when
-// culled), pixel box, support conic, and the number of
-// tiles of the box (0 when culled).  A quad with a vertex at z <= 0 is first
+// Writes per Gaussian-view: the record (its colour for every view, culled or
+// not), depth key (0xffffffff when culled), pixel box, support conic, and
+// the number of tiles of the box (0 when culled).  A quad with a vertex at z <= 0 is first
 // given the whole view; its parameters go to the crossing list (kCrossingDoubles
 // doubles per entry, at most crossing_cap entries, *crossing_count zero on
 // entry), and a second kernel bounds its box by the part of the quad inside
 // the view frustum.  Entries beyond the cap keep the whole view.
 constexpr int kCrossingDoubles = 12;
 hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n_views, const DevOptions &opt,
-                             float4 *colours, float4 *records, uint32_t *depth_keys, uint2 *boxes,
-                             Conic *conics, uint32_t *tile_counts, double *crossing, int64_t *crossing_count,
+                             float4 *records, uint32_t *depth_keys, uint2 *boxes, Conic *conics,
+                             uint32_t *tile_counts, double *crossing, int64_t *crossing_count,
                              uint32_t crossing_cap, hipStream_t stream);
 
 // Stable LSD radix sort of (key, value) pairs on bits [0, bits), 8-bit digits

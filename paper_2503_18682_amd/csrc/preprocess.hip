@@ -23,7 +23,7 @@ namespace {
 // the Gaussian in its own axes with its variances divided by lam = s_max^2.
 __device__ void write_exact_mip_record(float4 *rec, const double mu[3], const double Rp[9], const double s[3],
                                        double o, double sig2, const DevView &V, float u_hi, float v_hi,
-                                       uint32_t lo_bits, uint32_t rows, float4 col)
+                                       uint32_t lo_bits, uint32_t rows)
 {
     const double smax = fmax(s[0], fmax(s[1], s[2]));
     const double ilam = 1.0 / (smax * smax), iz = 1.0 / mu[2];
@@ -45,9 +45,13 @@ __device__ void write_exact_mip_record(float4 *rec, const double mu[3], const do
     rec[0] = make_float4(u_hi, v_hi, __uint_as_float(lo_bits), __uint_as_float(rows));
     rec[1] = make_float4((float)P0[0], (float)P0[1], (float)P0[2], (float)e);
     rec[2] = make_float4((float)P1[0], (float)P1[1], (float)P1[2], (float)log2o);
-    rec[3] = make_float4((float)Q0[0], (float)Q0[1], (float)Q0[2], col.x);
-    rec[4] = make_float4((float)Q1[0], (float)Q1[1], (float)Q1[2], col.y);
-    rec[5] = make_float4((float)rho[0], (float)rho[1], (float)rho[2], col.z);
+    // the fourth floats of rows 3..5 hold the colour (written by the colour phase)
+    float *f = reinterpret_cast<float *>(rec);
+    for (int k = 0; k < 3; ++k) {
+        f[12 + k] = (float)Q0[k];
+        f[16 + k] = (float)Q1[k];
+        f[20 + k] = (float)rho[k];
+    }
     rec[6] = make_float4((float)s2[0], (float)s2[1], (float)s2[2], 0.0f);
 }
 
@@ -77,14 +81,47 @@ __device__ inline Centre projected_centre(const double mu[3], const DevView &V)
 // own code (fewer registers and instructions in the common ray-based one).
 enum PrepMode { kPrepRay = 0, kPrepMipApprox = 1, kPrepMipExact = 2, kPrepGS = 3 };
 
-template <int MODE>
+// View-dependent colour of Gaussian i in every view, max(0, SH(direction
+// camera centre -> mean) + 1/2), written into the record's colour floats
+// (also of views where the Gaussian is culled).  Returns whether every
+// coefficient is finite (if not, the Gaussian is culled in every view).
+// Run by the preprocess thread before its geometry: the coefficients' loads
+// are the HBM-bound part of the kernel and the geometry the FP64-bound one,
+// and the waves of a SIMD are in either phase at any time, so the two
+// overlap; the coefficient registers are dead before the geometry starts.
+template <int DEG>
+__device__ __forceinline__ bool colour_phase(const float *__restrict__ sh, int n, int i, const double (&m)[3],
+                                             const DevView *__restrict__ views, int n_views,
+                                             float *__restrict__ records, int rec_floats, ColourSlot slot)
+{
+    constexpr int NK = (DEG + 1) * (DEG + 1);
+    float c[NK * 3];
+    bool sh_ok = true;
+#pragma unroll
+    for (int k = 0; k < NK * 3; ++k) {
+        c[k] = sh[(size_t)k * n + i];
+        sh_ok = sh_ok && isfinite(c[k]);
+    }
+    for (int v = 0; v < n_views; ++v) {
+        float dir[3], Y[NK], col[3];
+        double dist;
+        view_dir(m, views[v].centre, dir, &dist);
+        sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
+        sh_colour<DEG>(Y, c, col);
+        float *rc = records + ((size_t)v * n + i) * rec_floats + slot.first;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) rc[k * slot.step] = fmaxf(col[k], 0.0f);
+    }
+    return sh_ok;
+}
+
+template <int MODE, int DEG>
 __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ means,
                                                     const float *__restrict__ log_scales,
                                                     const float *__restrict__ quats,
                                                     const float *__restrict__ opacity_logits,
-                                                    int n,
+                                                    const float *__restrict__ sh, int n,
                                                     const DevView *__restrict__ views, int n_views, DevOptions opt,
-                                                    const float4 *__restrict__ colours,
                                                     float4 *__restrict__ records, uint32_t *__restrict__ depth_keys,
                                                     uint2 *__restrict__ boxes,
                                                     Conic *__restrict__ conics, uint32_t *__restrict__ tile_counts,
@@ -96,17 +133,17 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
     if (i >= n) return;
 
     const double m[3] = {means[i], means[n + i], means[2 * n + i]};
+    const bool sh_ok = colour_phase<DEG>(sh, n, i, m, views, n_views, reinterpret_cast<float *>(records),
+                                         MODE == kPrepMipExact ? kRecordFloatsExactMip : kRecordFloats,
+                                         colour_slot(MODE == kPrepMipExact ? 2 : 0));
     const float lf[3] = {log_scales[i], log_scales[n + i], log_scales[2 * n + i]};
     const float qf[4] = {quats[i], quats[n + i], quats[2 * n + i], quats[3 * n + i]};
     const float af = opacity_logits[i];
-    bool ok = isfinite(af);
+    bool ok = sh_ok && isfinite(af);
 #pragma unroll
     for (int k = 0; k < 3; ++k) ok = ok && isfinite((float)m[k]) && isfinite(lf[k]);
 #pragma unroll
     for (int k = 0; k < 4; ++k) ok = ok && isfinite(qf[k]);
-    // the colour kernel flags a non-finite colour coefficient (culled in
-    // every view)
-    ok = ok && colours[i].w == 0.0f;
     const double q[4] = {qf[0], qf[1], qf[2], qf[3]};
     const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     ok = ok && qn > 0.0;
@@ -199,8 +236,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                                      __uint_as_float((uint32_t)py0 | ((uint32_t)py1 << 16)));
                 rec[1] = make_float4((float)G00, (float)G01, 0.0f, (float)G11);
                 rec[2] = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
-                const float4 col = colours[idx];
-                rec[3] = make_float4(log2o, col.x, col.y, col.z);
+                reinterpret_cast<float *>(rec)[12] = log2o;  // floats 13..15: the colour phase's
                 conics[idx] = Conic{A00, A01, A11, 0.0, 0.0, kappa, pc.u, pc.v};
                 break;
             }
@@ -247,7 +283,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                     cnt = (uint32_t)((((Wd - 1) >> opt.tile_wshift) + 1) * (((Hd - 1) >> opt.tile_hshift) + 1));
                     const Centre pc = projected_centre(mu, V);
                     write_exact_mip_record(records + idx * (kRecordFloatsExactMip / 4), mu, Rp, s, o, sig2, V,
-                                           pc.u_hi, pc.v_hi, pc.lo_bits, (uint32_t)(Hd - 1) << 16, colours[idx]);
+                                           pc.u_hi, pc.v_hi, pc.lo_bits, (uint32_t)(Hd - 1) << 16);
                     // P00 = 0: not an ellipse, so every tile of the box is listed
                     conics[idx] = Conic{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, pc.u, pc.v};
                     break;
@@ -424,16 +460,15 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
             // the residuals of the centre go into one fp16 pair; the freed slot
             // holds the covered pixel rows for in-tile culling
             const uint32_t rows = (uint32_t)py0 | ((uint32_t)py1 << 16);
-            const float4 col = colours[idx];
             if constexpr (MODE == kPrepMipExact) {
                 write_exact_mip_record(records + idx * (kRecordFloatsExactMip / 4), mu, Rp, s, o,
-                                       opt.mip_sigma2_px / (V.fx * V.fy), V, pc.u_hi, pc.v_hi, pc.lo_bits, rows, col);
+                                       opt.mip_sigma2_px / (V.fx * V.fy), V, pc.u_hi, pc.v_hi, pc.lo_bits, rows);
             } else {
                 float4 *rec = records + idx * 4;
                 rec[0] = make_float4(pc.u_hi, pc.v_hi, __uint_as_float(pc.lo_bits), __uint_as_float(rows));
                 rec[1] = make_float4((float)G[0][0], (float)G[0][1], (float)G[1][0], (float)G[1][1]);
                 rec[2] = make_float4((float)gx, (float)gy, (float)k0, (float)ic2);
-                rec[3] = make_float4(log2o, col.x, col.y, col.z);
+                reinterpret_cast<float *>(rec)[12] = log2o;  // floats 13..15: the colour phase's
             }
             conics[idx] = C;
         } while (false);
@@ -555,73 +590,39 @@ __global__ __launch_bounds__(kClipBlock) void k_clip_crossing(const double *__re
     }
 }
 
-// View-dependent colour of every Gaussian-view (one thread per Gaussian; its
-// coefficients are read once, coalesced across the wave), run before the
-// geometry: colours[v n + i] = (max(0, SH(direction camera centre -> mean) +
-// 1/2), flag) with flag 0, or NaN when a coefficient is not finite (the
-// Gaussian is then culled in every view).  The geometry kernel copies the
-// colour of each kept view into its record, so every record is written as
-// whole 64-byte lines.
-template <int DEG>
-__global__ __launch_bounds__(256) void k_colour(const float *__restrict__ means, const float *__restrict__ sh, int n,
-                                                const DevView *__restrict__ views, int n_views,
-                                                float4 *__restrict__ colours)
-{
-    constexpr int NK = (DEG + 1) * (DEG + 1);
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float c[NK * 3];
-    bool sh_ok = true;
-#pragma unroll
-    for (int k = 0; k < NK * 3; ++k) {
-        c[k] = sh[(size_t)k * n + i];
-        sh_ok = sh_ok && isfinite(c[k]);
-    }
-    const float flag = sh_ok ? 0.0f : __builtin_nanf("");
-    const double m[3] = {means[i], means[n + i], means[2 * n + i]};
-    for (int v = 0; v < n_views; ++v) {
-        float dir[3], Y[NK], col[3];
-        double dist;
-        view_dir(m, views[v].centre, dir, &dist);
-        sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
-        sh_colour<DEG>(Y, c, col);
-        colours[(size_t)v * n + i] = make_float4(fmaxf(col[0], 0.0f), fmaxf(col[1], 0.0f), fmaxf(col[2], 0.0f), flag);
-    }
-}
-
 }  // namespace
 
 hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n_views, const DevOptions &opt,
-                             float4 *colours, float4 *records, uint32_t *depth_keys, uint2 *boxes,
-                             Conic *conics, uint32_t *tile_counts, double *crossing, int64_t *crossing_count,
+                             float4 *records, uint32_t *depth_keys, uint2 *boxes, Conic *conics,
+                             uint32_t *tile_counts, double *crossing, int64_t *crossing_count,
                              uint32_t crossing_cap, hipStream_t stream)
 {
     const int n = (int)g.n;
     if (n == 0) return hipSuccess;
     const dim3 grid((n + 255) / 256), block(256);
-#define RGS_COL(D) k_colour<D><<<grid, block, 0, stream>>>(g.means, g.sh, n, views, n_views, colours)
-    switch (g.sh_degree) {
-    case 0: RGS_COL(0); break;
-    case 1: RGS_COL(1); break;
-    case 2: RGS_COL(2); break;
-    default: RGS_COL(3); break;
-    }
-#undef RGS_COL
     const int mode = opt.divergence == RGS_DIVERGENCE_GS ? kPrepGS
                      : opt.mip == 2                     ? kPrepMipExact
                      : (opt.mip == 1 || opt.mip == 3)   ? kPrepMipApprox
                                                         : kPrepRay;
-#define RGS_PRE(M)                                                                                              \
-    k_preprocess<M><<<grid, block, 0, stream>>>(g.means, g.log_scales, g.quats, g.opacity_logits, n, views,     \
-                                                n_views, opt, colours, records, depth_keys, boxes, conics,        \
-                                                tile_counts, crossing,                                            \
-                                                reinterpret_cast<unsigned long long *>(crossing_count), crossing_cap)
-    switch (mode) {
-    case kPrepGS: RGS_PRE(kPrepGS); break;
-    case kPrepMipExact: RGS_PRE(kPrepMipExact); break;
-    case kPrepMipApprox: RGS_PRE(kPrepMipApprox); break;
-    default: RGS_PRE(kPrepRay); break;
+#define RGS_PRE(M, D)                                                                                            \
+    k_preprocess<M, D><<<grid, block, 0, stream>>>(g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, n,    \
+                                                   views, n_views, opt, records, depth_keys, boxes, conics,       \
+                                                   tile_counts, crossing,                                         \
+                                                   reinterpret_cast<unsigned long long *>(crossing_count), crossing_cap)
+#define RGS_PRE_DEG(M)                    \
+    switch (g.sh_degree) {                \
+    case 0: RGS_PRE(M, 0); break;         \
+    case 1: RGS_PRE(M, 1); break;         \
+    case 2: RGS_PRE(M, 2); break;         \
+    default: RGS_PRE(M, 3); break;        \
     }
+    switch (mode) {
+    case kPrepGS: RGS_PRE_DEG(kPrepGS); break;
+    case kPrepMipExact: RGS_PRE_DEG(kPrepMipExact); break;
+    case kPrepMipApprox: RGS_PRE_DEG(kPrepMipApprox); break;
+    default: RGS_PRE_DEG(kPrepRay); break;
+    }
+#undef RGS_PRE_DEG
 #undef RGS_PRE
     // the linearised divergence has no quad, so nothing crosses
     if (mode != kPrepGS && crossing_cap > 0)

@@ -1,5 +1,6 @@
-// Real spherical-harmonic colour shared by the forward colour kernel and its
-// backward (float32, contraction off, so both take the same clamp decision).
+// Real spherical-harmonic colour shared by the preprocess kernel's colour
+// phase and the colour backward (float32, contraction off, so both take the
+// same clamp decision).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,7 +9,8 @@ namespace rgs {
 
 // Unit view direction camera centre -> mean as float32 (difference and norm
 // in double, one reciprocal); *dist receives the distance.  Shared by the
-// colour kernel and its backward so both evaluate the same colour.
+// forward colour phase and the colour backward so both evaluate the same
+// colour.
 __device__ __forceinline__ void view_dir(const double (&m)[3], const double (&centre)[3], float (&dir)[3],
                                          double *dist)
 {

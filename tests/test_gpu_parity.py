@@ -224,9 +224,10 @@ def test_edge_cases(r, mode):
                                           [[1, 0, 0], [0, 1, 0]], quats=[[0.9, 0.3, 0.2, 0.1], [1, 0, 0, 0]]),
         "offscreen": _mk([[30.0, 0.0, 2.0]], [[0.1] * 3], [0.9], [[1, 1, 1]]),
     }
-    bad = _mk([[0.0, 0.0, 2.0], [0.1, 0.0, 2.5], [0.0, 0.1, 3.0]], [[0.2] * 3] * 3, [0.7] * 3, [[1, 0, 0]] * 3)
+    bad = _mk([[0.0, 0.0, 2.0], [0.1, 0.0, 2.5], [0.0, 0.1, 3.0], [-0.1, -0.05, 2.2]], [[0.2] * 3] * 4, [0.7] * 4,
+              [[1, 0, 0]] * 4)
     bad["means"][0, 0] = np.nan
-    bad["quats"][:, 1] = 0.0
+    bad["quats"][:, 1] = 0.0  # the fourth Gaussian stays valid
     bad["sh"][0, 1, 2] = np.inf
     cases["non_finite_and_zero_quat"] = bad
     for name, sc in cases.items():
@@ -234,8 +235,17 @@ def test_edge_cases(r, mode):
         outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
         assert ok
         ref = oracle.render(sc, cam, opts)
-        assert m == oracle_box_tiles(oracle.preprocess(sc, cam, opts))[1].sum(), name
+        kept, box_tiles = oracle_box_tiles(oracle.preprocess(sc, cam, opts))
+        assert m == box_tiles.sum(), name
         assert_image_close(outs[0]["rgb"], outs[0]["final_T"], ref, label=name)
+        if name == "non_finite_and_zero_quat":
+            # a non-finite colour coefficient culls like any other cull: no
+            # depth position, tile count 0, not counted as kept
+            n = sc["opacity_logits"].shape[0]
+            assert list(np.nonzero(kept)[0]) == [3]
+            assert read(buf, lay.counters, 8, np.int64)[4] == 1
+            assert np.array_equal(read(buf, lay.tile_counts, n, np.uint32), box_tiles)
+            assert read(buf, lay.order, 1, np.uint32)[0] == 3
     assert np.allclose(render_with_ws(r, cases["empty"], [cam], opts)[0][0]["rgb"][2], 0.3)
 
 
