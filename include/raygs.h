@@ -165,7 +165,10 @@ rgs_status rgs_workspace_size(rgs_context *ctx, int64_t n, const rgs_camera *cam
  * of a widened Gaussian that bounds its support, or by the whole view where
  * no such bound exists).  A quad with a vertex at z <= 0 is drawn unclipped;
  * its pixel box is that of the part of it inside the view frustum, and it is
- * culled when no part is inside.
+ * culled when no part is inside.  Tiles are binned from the part of the
+ * pixel box whose pixel centres lie in the support ellipse's bounding box
+ * (no other pixel can hold support); a Gaussian-view with no such pixel is
+ * culled.
  * cams, outs: host arrays of n_views (outs entries hold device pointers);
  * opts: one struct for the whole batch.  Stream-ordered, no host
  * synchronisation.  If the frame needs
@@ -267,8 +270,8 @@ rgs_status rgs_autotune_training(rgs_context *ctx, const rgs_gaussians *g, const
  * profiling tools).  Counts are element counts.  Pure host arithmetic; ctx
  * may be NULL. */
 typedef struct {
-    size_t counters;       /* int64[8]: [0] instances needed (tiles of all pixel boxes), [1] capacity,
-                              [2] tile rows of all boxes, [3] listed instances (sorted; the rest are
+    size_t counters;       /* int64[8]: [0] instances needed (tiles of all binning boxes), [1] capacity,
+                              [2] tile rows of all binning boxes, [3] listed instances (sorted; the rest are
                               empty), [4] kept (not culled) Gaussian-views, [5] quads with a vertex at
                               z <= 0 (65536 of them, in no fixed order, have their box clipped to the
                               view frustum; any others keep the whole view) */
@@ -276,12 +279,15 @@ typedef struct {
     size_t records;        /* float[16] per Gaussian-view (float[28] with mip = 2), index v * n + i */
     size_t depth_keys;     /* uint32 per Gaussian-view: the kept views' keys, sorted, in [0, counters[4]) */
     size_t boxes;          /* uint16[4] per Gaussian-view: pixel box x0, x1, y0, y1 (inclusive) */
+    size_t bin_boxes;      /* uint16[4] per Gaussian-view: binning box, the pixels of the pixel box whose
+                              centres lie in the support ellipse's bounding box (the whole pixel box when
+                              the support is unbounded; tiles are listed from it) */
     size_t conics;         /* double[8] per Gaussian-view: support ellipse P00, P01, P11, h0, h1, f0, u0, v0 */
-    size_t tile_counts;    /* uint32 per Gaussian-view: tiles of its pixel box (0 = culled) */
+    size_t tile_counts;    /* uint32 per Gaussian-view: tiles of its binning box (0 = culled) */
     size_t order;          /* uint32 per Gaussian-view: the kept views' ids sorted by (depth key, id), in
                               [0, counters[4]) */
     size_t offsets;        /* uint32 per Gaussian-view: first instance of each sorted entry */
-    size_t inst_tiles;     /* uint32 per instance: global tile id, sorted, [0, counters[3]) (box tiles
+    size_t inst_tiles;     /* uint32 per instance: global tile id, sorted, [0, counters[3]) (binning box tiles
                               whose pixel-centre rectangle misses the support are dropped by the sort) */
     size_t inst_ids;       /* uint32 per instance: Gaussian-view id (low 28 bits) sorted by (tile, depth, id);
                               with tile shapes of at most 4 pixel slots of 64 pixels, the top 4 bits

@@ -20,7 +20,7 @@ _SANITIZE = os.environ.get("RAYGS_SANITIZE") == "1"
 _LIB = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
 _SAN_FLAGS = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
 
-CULL = dict(visible=0, invalid=1, near=2, kappa=3, inside=4, offscreen=5, notile=6)
+CULL = dict(visible=0, invalid=1, near=2, kappa=3, inside=4, offscreen=5, notile=6, nobin=7)
 HAZARD = dict(key=1, rect=2, eigen=4, cull=8, front=16)
 
 
@@ -57,7 +57,9 @@ SPLAT_DTYPE = np.dtype(
     [("cull", np.int32), ("hazard", np.int32), ("mu", np.float64, 3), ("Rp", np.float64, 9), ("s", np.float64, 3),
      ("o", np.float64), ("kappa", np.float64), ("c2", np.float64), ("mu_w", np.float64, 3), ("b", np.float64),
      ("Rv", np.float64, 9), ("U", np.float64, 4), ("quad", np.float64, 12), ("bbox", np.float64, 4),
+     ("ebox", np.float64, 4),
      ("all_front", np.int32), ("px0", np.int32), ("px1", np.int32), ("py0", np.int32), ("py1", np.int32),
+     ("bx0", np.int32), ("bx1", np.int32), ("by0", np.int32), ("by1", np.int32),
      ("tx0", np.int32), ("tx1", np.int32), ("ty0", np.int32), ("ty1", np.int32), ("depth_key", np.uint32),
      ("pad", np.int32), ("rgb", np.float64, 3), ("rgb_raw", np.float64, 3), ("dir", np.float64, 3),
      ("dist", np.float64), ("cq", np.float64, 6), ("bounded", np.int32), ("listed", np.int32),

@@ -81,7 +81,8 @@ enum {
     ORC_CULL_KAPPA = 3,
     ORC_CULL_INSIDE = 4,
     ORC_CULL_OFFSCREEN = 5,
-    ORC_CULL_NOTILE = 6
+    ORC_CULL_NOTILE = 6,
+    ORC_CULL_NOBIN = 7   /* no pixel centre of the box lies in the support's bounding box */
 };
 
 enum { /* hazard bits: a decision taken within rounding distance */
@@ -106,9 +107,11 @@ typedef struct {
     double U[4];      /* U_ray = (u0, u1) as columns, row-major 2x2 */
     double quad[12];  /* 4 vertices x (x, y, z), camera frame */
     double bbox[4];   /* umin, umax, vmin, vmax of the projected quad */
+    double ebox[4];   /* umin, umax, vmin, vmax of the support ellipse (infinite when unbounded) */
     int32_t all_front;
-    int32_t px0, px1, py0, py1; /* covered pixel centres (inclusive) */
-    int32_t tx0, tx1, ty0, ty1; /* covered tiles (inclusive) */
+    int32_t px0, px1, py0, py1; /* pixel box: pixel centres inside bbox (inclusive) */
+    int32_t bx0, bx1, by0, by1; /* binning box: pixels of the pixel box with centres inside ebox */
+    int32_t tx0, tx1, ty0, ty1; /* tiles of the binning box (inclusive) */
     uint32_t depth_key;
     int32_t pad;
     double rgb[3], rgb_raw[3];
@@ -420,10 +423,10 @@ static double conic_rect_min(const double *q, int x0, int x1, int y0, int y1)
 static int tile_listed(orc_splat *sp, const orc_options *opt, int tx, int ty)
 {
     int TW = opt->tile_w, TH = opt->tile_h;
-    int cx0 = tx * TW > sp->px0 ? tx * TW : sp->px0;
-    int cx1 = tx * TW + TW - 1 < sp->px1 ? tx * TW + TW - 1 : sp->px1;
-    int cy0 = ty * TH > sp->py0 ? ty * TH : sp->py0;
-    int cy1 = ty * TH + TH - 1 < sp->py1 ? ty * TH + TH - 1 : sp->py1;
+    int cx0 = tx * TW > sp->bx0 ? tx * TW : sp->bx0;
+    int cx1 = tx * TW + TW - 1 < sp->bx1 ? tx * TW + TW - 1 : sp->bx1;
+    int cy0 = ty * TH > sp->by0 ? ty * TH : sp->by0;
+    int cy1 = ty * TH + TH - 1 < sp->by1 ? ty * TH + TH - 1 : sp->by1;
     if (cx0 > cx1 || cy0 > cy1) return 0;
     if (!sp->bounded) return 1;
     /* scale: |conic| at the projected centre = kappa c^2 / mu_z^2 (kappa for D_gs) */
@@ -448,6 +451,46 @@ static void box_to_pixels(orc_splat *sp, const orc_camera *cam, double umin, dou
     sp->px1 = fx1 > W_ - 1 ? W_ - 1 : (fx1 < -1.0 ? -1 : (int)fx1);
     sp->py0 = fy0 < 0.0 ? 0 : (fy0 > H_ ? H_ : (int)fy0);
     sp->py1 = fy1 > H_ - 1 ? H_ - 1 : (fy1 < -1.0 ? -1 : (int)fy1);
+}
+
+/* Binning box (tighter binning than the quad's box; the pixel box stays the
+ * set of pixels evaluated): the pixels of the pixel box whose centres lie in
+ * the bounding box of the support ellipse when the support conic is bounded,
+ * else the pixel box itself.  No pixel centre outside it can hold support,
+ * so no tile outside it can be listed.  The ellipse is
+ * (x - c)^T A (x - c) <= r2 with c = -A^-1 b and r2 = -Q(c); its half widths
+ * are sqrt(r2 (A^-1)_00) and sqrt(r2 (A^-1)_11).  Sets the tile range of the
+ * box; returns 0 (culled, ORC_CULL_NOBIN) when it holds no pixel. */
+static int binning_box(orc_splat *sp, const orc_options *opt)
+{
+    sp->bx0 = sp->px0; sp->bx1 = sp->px1; sp->by0 = sp->py0; sp->by1 = sp->py1;
+    sp->ebox[0] = -INFINITY; sp->ebox[1] = INFINITY; sp->ebox[2] = -INFINITY; sp->ebox[3] = INFINITY;
+    if (sp->bounded && !sp->gs) {
+        const double *q = sp->cq;
+        const double det = q[0] * q[2] - q[1] * q[1];
+        const double cx = (q[1] * q[4] - q[2] * q[3]) / det, cy = (q[1] * q[3] - q[0] * q[4]) / det;
+        const double r2 = -conic_at(q, cx, cy);
+        const double hx = sqrt(r2 * q[2] / det), hy = sqrt(r2 * q[0] / det);
+        sp->ebox[0] = cx - hx; sp->ebox[1] = cx + hx; sp->ebox[2] = cy - hy; sp->ebox[3] = cy + hy;
+        const double fx0 = ceil(sp->ebox[0] - 0.5), fx1 = floor(sp->ebox[1] - 0.5);
+        const double fy0 = ceil(sp->ebox[2] - 0.5), fy1 = floor(sp->ebox[3] - 0.5);
+        int hz = 0;
+        for (int k = 0; k < 4; ++k) hz |= near_integer(sp->ebox[k] - 0.5, 1e-9);
+        if (hz) sp->hazard |= ORC_HZ_RECT;
+        if (fx0 > sp->bx0) sp->bx0 = fx0 > sp->px1 + 1 ? sp->px1 + 1 : (int)fx0;
+        if (fx1 < sp->bx1) sp->bx1 = fx1 < sp->px0 - 1 ? sp->px0 - 1 : (int)fx1;
+        if (fy0 > sp->by0) sp->by0 = fy0 > sp->py1 + 1 ? sp->py1 + 1 : (int)fy0;
+        if (fy1 < sp->by1) sp->by1 = fy1 < sp->py0 - 1 ? sp->py0 - 1 : (int)fy1;
+        /* an edge within rounding can decide whether the box is empty */
+        if (hz && (sp->bx1 - sp->bx0 <= 0 || sp->by1 - sp->by0 <= 0)) sp->hazard |= ORC_HZ_CULL;
+    }
+    if (sp->bx0 > sp->bx1 || sp->by0 > sp->by1) {
+        sp->cull = ORC_CULL_NOBIN;
+        return 0;
+    }
+    sp->tx0 = sp->bx0 / opt->tile_w; sp->tx1 = sp->bx1 / opt->tile_w;
+    sp->ty0 = sp->by0 / opt->tile_h; sp->ty1 = sp->by1 / opt->tile_h;
+    return 1;
 }
 
 /* The part of a quad (4 corners in order, camera frame) that can project into
@@ -595,14 +638,14 @@ static void preprocess_one(const orc_scene *sc, int64_t i, const orc_camera *cam
             sp->cull = ORC_CULL_OFFSCREEN;
             return;
         }
-        sp->tx0 = sp->px0 / opt->tile_w; sp->tx1 = sp->px1 / opt->tile_w;
-        sp->ty0 = sp->py0 / opt->tile_h; sp->ty1 = sp->py1 / opt->tile_h;
         const double *A = sp->gs_A;
         sp->cq[0] = A[0]; sp->cq[1] = A[1]; sp->cq[2] = A[2];
         sp->cq[3] = -(A[0] * uc + A[1] * vc);
         sp->cq[4] = -(A[1] * uc + A[2] * vc);
         sp->cq[5] = A[0] * uc * uc + 2.0 * A[1] * uc * vc + A[2] * vc * vc - kappa;
         sp->bounded = 1;
+        /* the pixel box is already the ellipse's box: the binning box is the same */
+        if (!binning_box(sp, opt)) return;
         sp->listed = 0;
         for (int ty = sp->ty0; ty <= sp->ty1; ++ty)
             for (int tx = sp->tx0; tx <= sp->tx1; ++tx) sp->listed += tile_listed(sp, opt, tx, ty);
@@ -692,9 +735,8 @@ static void preprocess_one(const orc_scene *sc, int64_t i, const orc_camera *cam
         sp->all_front = 0;
         sp->bbox[0] = -INFINITY; sp->bbox[1] = INFINITY; sp->bbox[2] = -INFINITY; sp->bbox[3] = INFINITY;
         sp->px0 = 0; sp->px1 = cam->width - 1; sp->py0 = 0; sp->py1 = cam->height - 1;
-        sp->tx0 = 0; sp->tx1 = sp->px1 / opt->tile_w;
-        sp->ty0 = 0; sp->ty1 = sp->py1 / opt->tile_h;
         sp->bounded = 0;
+        (void)binning_box(sp, opt); /* unbounded: the whole view */
         sp->listed = (sp->tx1 + 1) * (sp->ty1 + 1);
         goto colour;
     }
@@ -803,9 +845,8 @@ static void preprocess_one(const orc_scene *sc, int64_t i, const orc_camera *cam
         sp->cull = ORC_CULL_OFFSCREEN;
         return;
     }
-    sp->tx0 = px0 / opt->tile_w; sp->tx1 = px1 / opt->tile_w;
-    sp->ty0 = py0 / opt->tile_h; sp->ty1 = py1 / opt->tile_h;
     support_conic(sp, cam);
+    if (!binning_box(sp, opt)) return;
     sp->listed = 0;
     for (int ty = sp->ty0; ty <= sp->ty1; ++ty)
         for (int tx = sp->tx0; tx <= sp->tx1; ++tx) sp->listed += tile_listed(sp, opt, tx, ty);

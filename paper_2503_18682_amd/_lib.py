@@ -57,7 +57,7 @@ class Workspace(C.Structure):
 
 
 class WorkspaceLayout(C.Structure):
-    _fields_ = [(k, C.c_size_t) for k in ("counters", "views", "records", "depth_keys", "boxes", "conics",
+    _fields_ = [(k, C.c_size_t) for k in ("counters", "views", "records", "depth_keys", "boxes", "bin_boxes", "conics",
                                           "tile_counts", "order", "offsets", "inst_tiles", "inst_ids", "tile_ranges",
                                           "record_grads", "total_bytes")] + [
         ("n_records", C.c_int64), ("capacity", C.c_int64), ("total_tiles", C.c_int64), ("tile_w", C.c_int32),

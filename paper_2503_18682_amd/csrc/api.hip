@@ -38,7 +38,8 @@ constexpr int64_t kCrossingCap = 1 << 16;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t counters, views, records, keys_a, keys_b, order_a, order_b, boxes, sorted_boxes, conics, tile_counts,
+    size_t counters, views, records, keys_a, keys_b, order_a, order_b, boxes, bin_boxes, sorted_boxes, conics,
+        tile_counts,
         offsets, block_sums;
     size_t crossing;          // quads with a vertex at z <= 0, awaiting frustum clipping
     uint32_t crossing_cap;    // entries of the crossing list
@@ -302,6 +303,7 @@ rgs_status compute_layout(rgs_context *ctx, int64_t n, const rgs_camera *cams, i
     L.order_a = take(NV * 4);
     L.order_b = take(NV * 4);
     L.boxes = take(NV * 8);
+    L.bin_boxes = take(NV * 8);
     L.sorted_boxes = take(NV * 8);
     L.conics = take(NV * sizeof(Conic));
     L.tile_counts = take(NV * 4);
@@ -334,6 +336,7 @@ void fill_public_layout(const Layout &L, rgs_workspace_layout *o)
     o->records = L.records;
     o->depth_keys = L.keys_a;
     o->boxes = L.boxes;
+    o->bin_boxes = L.bin_boxes;
     o->conics = L.conics;
     o->tile_counts = L.tile_counts;
     o->order = L.order_a;
@@ -496,7 +499,8 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
     if (view_stamps) RGS_HIP(ctx, launch_view_clock_start(view_stamps, n_views, stream));
     unsigned long long *item_clock = view_stamps ? at<unsigned long long>(ws, L.item_clock) : nullptr;
     Timer tm(ctx, stream, timing, ST_PRE);
-    RGS_HIP(ctx, launch_preprocess(g, views, n_views, dopt, records, keys_in, boxes, conics, tile_counts,
+    uint2 *bin_boxes = at<uint2>(ws, L.bin_boxes);
+    RGS_HIP(ctx, launch_preprocess(g, views, n_views, dopt, records, keys_in, boxes, bin_boxes, conics, tile_counts,
                                    at<double>(ws, L.crossing), counters + 5, L.crossing_cap, stream));
     tm.mark(ST_PRE);
     // counters: [0] box instances, [1] capacity, [2] tile rows, [3] listed instances, [4] kept views,
@@ -511,7 +515,7 @@ rgs_status enqueue_forward(rgs_context *ctx, const rgs_gaussians &g, int n_views
     uint32_t *row_offsets = at<uint32_t>(ws, L.row_offsets);
     uint32_t *row_owner = at<uint32_t>(ws, L.row_owner);
     uint2 *sorted_boxes = at<uint2>(ws, L.sorted_boxes);
-    RGS_HIP(ctx, binning_scan(at<uint32_t>(ws, L.keys_a), boxes, order, NV, kept, s.w, s.h, L.capacity, offsets,
+    RGS_HIP(ctx, binning_scan(at<uint32_t>(ws, L.keys_a), bin_boxes, order, NV, kept, s.w, s.h, L.capacity, offsets,
                               row_offsets, row_owner, sorted_boxes,
                               at<unsigned long long>(ws, L.block_sums), counters, stream));
     tm.mark(ST_SCAN);

@@ -8,8 +8,10 @@
 // (from q b^2 <= kappa den^2 with q = |G delta|^2, den = k0 + g . delta,
 // b^2 = 1 - kappa / c^2).  When P is not positive definite the support is
 // unbounded on the image plane and every tile of the bounding rectangle is
-// kept.  A tile is listed when the continuous rectangle spanned by its pixel
-// centres (clipped to the Gaussian's pixel box) meets the ellipse.  Its
+// kept.  Tiles are binned from the Gaussian's binning box (binning_clip
+// below: the pixels of its pixel box whose centres lie in the ellipse's
+// bounding box), and a tile is listed when the continuous rectangle spanned
+// by its pixel centres inside the binning box meets the ellipse.  Its
 // pixel slots, the 64-pixel groups that a compositing wave tests or skips
 // together (slot_layout below), are tested the same way, and the bits of the
 // slots that meet the ellipse travel with the instance.  The tests are done
@@ -67,6 +69,31 @@ __device__ inline ConicFrame conic_frame(const Conic &C)
     F.yright = F.cy - sy;
     F.inv_p00 = 1.0 / C.P00;
     return F;
+}
+
+// Binning box of a Gaussian-view: the pixels [x0, x1] x [y0, y1] of its pixel
+// box [px0, px1] x [py0, py1] whose centres lie in the bounding box of the
+// support ellipse, or the pixel box itself when the support is unbounded.
+// No pixel centre outside it can hold support, so no tile outside it can be
+// listed.  Returns false when it holds no pixel.
+__device__ inline bool binning_clip(const Conic &C, int px0, int px1, int py0, int py1, int &x0, int &x1, int &y0,
+                                    int &y1)
+{
+#pragma clang fp contract(off)
+    x0 = px0;
+    x1 = px1;
+    y0 = py0;
+    y1 = py1;
+    const ConicFrame F = conic_frame(C);
+    if (F.bounded) {
+        const double ex0 = ceil(C.u0 + F.xmin - 0.5), ex1 = floor(C.u0 + F.xmax - 0.5);
+        const double ey0 = ceil(C.v0 + F.ymin - 0.5), ey1 = floor(C.v0 + F.ymax - 0.5);
+        if (ex0 > x0) x0 = ex0 > px1 + 1 ? px1 + 1 : (int)ex0;
+        if (ex1 < x1) x1 = ex1 < px0 - 1 ? px0 - 1 : (int)ex1;
+        if (ey0 > y0) y0 = ey0 > py1 + 1 ? py1 + 1 : (int)ey0;
+        if (ey1 < y1) y1 = ey1 < py0 - 1 ? py0 - 1 : (int)ey1;
+    }
+    return x0 <= x1 && y0 <= y1;
 }
 
 // x-extent [xl, xr] of the ellipse over heights y in [ya, yb]; false if the

@@ -88,15 +88,17 @@ struct TileShape {
 
 // ---- launchers (each enqueues on `stream`, returns hipError_t) -----------
 // Writes per Gaussian-view: the record (its colour for every view, culled or
-// not), depth key (0xffffffff when culled), pixel box, support conic, and
-// the number of tiles of the box (0 when culled).  A quad with a vertex at z <= 0 is first
+// not), depth key (0xffffffff when culled), pixel box, binning box (the
+// pixels of the pixel box whose centres lie in the support ellipse's bounding
+// box; culled when there are none), support conic, and the number of tiles
+// of the binning box (0 when culled).  A quad with a vertex at z <= 0 is first
 // given the whole view; its parameters go to the crossing list (kCrossingDoubles
 // doubles per entry, at most crossing_cap entries, *crossing_count zero on
 // entry), and a second kernel bounds its box by the part of the quad inside
 // the view frustum.  Entries beyond the cap keep the whole view.
 constexpr int kCrossingDoubles = 12;
 hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n_views, const DevOptions &opt,
-                             float4 *records, uint32_t *depth_keys, uint2 *boxes, Conic *conics,
+                             float4 *records, uint32_t *depth_keys, uint2 *boxes, uint2 *bin_boxes, Conic *conics,
                              uint32_t *tile_counts, double *crossing, int64_t *crossing_count,
                              uint32_t crossing_cap, hipStream_t stream);
 

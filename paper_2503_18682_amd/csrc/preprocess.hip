@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                                                     const float *__restrict__ sh, int n,
                                                     const DevView *__restrict__ views, int n_views, DevOptions opt,
                                                     float4 *__restrict__ records, uint32_t *__restrict__ depth_keys,
-                                                    uint2 *__restrict__ boxes,
+                                                    uint2 *__restrict__ boxes, uint2 *__restrict__ bin_boxes,
                                                     Conic *__restrict__ conics, uint32_t *__restrict__ tile_counts,
                                                     double *__restrict__ crossing,
                                                     unsigned long long *__restrict__ crossing_count,
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
         const DevView &V = views[v];
         const size_t idx = (size_t)v * n + i;
         uint32_t key = 0xffffffffu, cnt = 0;
-        uint2 box = make_uint2(0u, 0u);
+        uint2 box = make_uint2(0u, 0u), bin = make_uint2(0u, 0u);
         const double *W = V.w2c;
         // camera-frame centre
         const double mu[3] = {W[0] * m[0] + W[1] * m[1] + W[2] * m[2] + W[3],
@@ -228,6 +228,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                 const int py1 = fy1 > Hd - 1 ? Hd - 1 : (fy1 < -1.0 ? -1 : (int)fy1);
                 if (px0 > px1 || py0 > py1) break;
                 box = make_uint2((uint32_t)px0 | ((uint32_t)px1 << 16), (uint32_t)py0 | ((uint32_t)py1 << 16));
+                bin = box;  // the box is already the support ellipse's
                 key = __float_as_uint((float)mu[2]);
                 cnt = (uint32_t)(((px1 >> opt.tile_wshift) - (px0 >> opt.tile_wshift) + 1) * ((py1 >> opt.tile_hshift) - (py0 >> opt.tile_hshift) + 1));
                 const double G00 = sqrt(A00), G01 = A01 / G00, G11 = sqrt(A11 - G01 * G01);
@@ -279,6 +280,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                 if (whole) {
                     const int Wd = V.width, Hd = V.height;
                     box = make_uint2((uint32_t)(Wd - 1) << 16, (uint32_t)(Hd - 1) << 16);
+                    bin = box;
                     key = __float_as_uint((float)mu[2]);
                     cnt = (uint32_t)((((Wd - 1) >> opt.tile_wshift) + 1) * (((Hd - 1) >> opt.tile_hshift) + 1));
                     const Centre pc = projected_centre(mu, V);
@@ -454,12 +456,19 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                 C.u0 = u_c;
                 C.v0 = v_c;
             }
-            // tiles of the box; the emission kernel lists those whose pixel-centre
-            // rectangle meets the support and marks the others empty
-            cnt = (uint32_t)(((px1 >> opt.tile_wshift) - (px0 >> opt.tile_wshift) + 1) * ((py1 >> opt.tile_hshift) - (py0 >> opt.tile_hshift) + 1));
+            // (written before any cull below: the crossing kernel reads it)
+            conics[idx] = C;
+            // binning box: the pixels of the box whose centres lie in the
+            // support ellipse's bounding box (no tile outside it can be listed)
+            int bx0 = px0, bx1 = px1, by0 = py0, by1 = py1;
+            if (!binning_clip(C, px0, px1, py0, py1, bx0, bx1, by0, by1)) break;
+            bin = make_uint2((uint32_t)bx0 | ((uint32_t)bx1 << 16), (uint32_t)by0 | ((uint32_t)by1 << 16));
+            // tiles of the binning box; the emission kernel lists those whose
+            // pixel-centre rectangle meets the support and marks the others empty
+            cnt = (uint32_t)(((bx1 >> opt.tile_wshift) - (bx0 >> opt.tile_wshift) + 1) * ((by1 >> opt.tile_hshift) - (by0 >> opt.tile_hshift) + 1));
             // the residuals of the centre go into one fp16 pair; the freed slot
-            // holds the covered pixel rows for in-tile culling
-            const uint32_t rows = (uint32_t)py0 | ((uint32_t)py1 << 16);
+            // holds the binning box's pixel rows for in-tile culling
+            const uint32_t rows = (uint32_t)by0 | ((uint32_t)by1 << 16);
             if constexpr (MODE == kPrepMipExact) {
                 write_exact_mip_record(records + idx * (kRecordFloatsExactMip / 4), mu, Rp, s, o,
                                        opt.mip_sigma2_px / (V.fx * V.fy), V, pc.u_hi, pc.v_hi, pc.lo_bits, rows);
@@ -470,11 +479,11 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                 rec[2] = make_float4((float)gx, (float)gy, (float)k0, (float)ic2);
                 reinterpret_cast<float *>(rec)[12] = log2o;  // floats 13..15: the colour phase's
             }
-            conics[idx] = C;
         } while (false);
         depth_keys[idx] = cnt ? key : 0xffffffffu;
         tile_counts[idx] = cnt;
         boxes[idx] = box;
+        bin_boxes[idx] = bin;
     }
 }
 
@@ -495,7 +504,8 @@ __global__ __launch_bounds__(kClipBlock) void k_clip_crossing(const double *__re
                                                               const DevView *__restrict__ views, DevOptions opt,
                                                               int rec_floats, float *__restrict__ records,
                                                               uint32_t *__restrict__ depth_keys,
-                                                              uint2 *__restrict__ boxes,
+                                                              uint2 *__restrict__ boxes, uint2 *__restrict__ bin_boxes,
+                                                              const Conic *__restrict__ conics,
                                                               uint32_t *__restrict__ tile_counts)
 {
     __shared__ double poly[2][kClipMaxVerts][3][kClipBlock];
@@ -577,23 +587,26 @@ __global__ __launch_bounds__(kClipBlock) void k_clip_crossing(const double *__re
             py0 = fy0 < 0.0 ? 0 : (fy0 > Hd ? Hd : (int)fy0);
             py1 = fy1 > Hd - 1 ? Hd - 1 : (fy1 < -1.0 ? -1 : (int)fy1);
         }
-        if (px0 > px1 || py0 > py1) {
+        int bx0 = px0, bx1 = px1, by0 = py0, by1 = py1;
+        if (px0 > px1 || py0 > py1 || !binning_clip(conics[idx], px0, px1, py0, py1, bx0, bx1, by0, by1)) {
             depth_keys[idx] = 0xffffffffu;
             tile_counts[idx] = 0u;
             boxes[idx] = make_uint2(0u, 0u);
+            bin_boxes[idx] = make_uint2(0u, 0u);
             continue;
         }
         boxes[idx] = make_uint2((uint32_t)px0 | ((uint32_t)px1 << 16), (uint32_t)py0 | ((uint32_t)py1 << 16));
+        bin_boxes[idx] = make_uint2((uint32_t)bx0 | ((uint32_t)bx1 << 16), (uint32_t)by0 | ((uint32_t)by1 << 16));
         tile_counts[idx] =
-            (uint32_t)(((px1 >> opt.tile_wshift) - (px0 >> opt.tile_wshift) + 1) * ((py1 >> opt.tile_hshift) - (py0 >> opt.tile_hshift) + 1));
-        records[(size_t)idx * rec_floats + 3] = __uint_as_float((uint32_t)py0 | ((uint32_t)py1 << 16));
+            (uint32_t)(((bx1 >> opt.tile_wshift) - (bx0 >> opt.tile_wshift) + 1) * ((by1 >> opt.tile_hshift) - (by0 >> opt.tile_hshift) + 1));
+        records[(size_t)idx * rec_floats + 3] = __uint_as_float((uint32_t)by0 | ((uint32_t)by1 << 16));
     }
 }
 
 }  // namespace
 
 hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n_views, const DevOptions &opt,
-                             float4 *records, uint32_t *depth_keys, uint2 *boxes, Conic *conics,
+                             float4 *records, uint32_t *depth_keys, uint2 *boxes, uint2 *bin_boxes, Conic *conics,
                              uint32_t *tile_counts, double *crossing, int64_t *crossing_count,
                              uint32_t crossing_cap, hipStream_t stream)
 {
@@ -606,7 +619,8 @@ hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n
                                                         : kPrepRay;
 #define RGS_PRE(M, D)                                                                                            \
     k_preprocess<M, D><<<grid, block, 0, stream>>>(g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, n,    \
-                                                   views, n_views, opt, records, depth_keys, boxes, conics,       \
+                                                   views, n_views, opt, records, depth_keys, boxes, bin_boxes,    \
+                                                   conics,                                                        \
                                                    tile_counts, crossing,                                         \
                                                    reinterpret_cast<unsigned long long *>(crossing_count), crossing_cap)
 #define RGS_PRE_DEG(M)                    \
@@ -628,7 +642,8 @@ hipError_t launch_preprocess(const rgs_gaussians &g, const DevView *views, int n
     if (mode != kPrepGS && crossing_cap > 0)
         k_clip_crossing<<<kClipGrid, kClipBlock, 0, stream>>>(
             crossing, reinterpret_cast<const unsigned long long *>(crossing_count), crossing_cap, n, views, opt,
-            record_floats(opt.mip), reinterpret_cast<float *>(records), depth_keys, boxes, tile_counts);
+            record_floats(opt.mip), reinterpret_cast<float *>(records), depth_keys, boxes, bin_boxes, conics,
+            tile_counts);
     return hipGetLastError();
 }
 

@@ -228,7 +228,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
 
 // ---------------------------------------------------------------------- scan
 // Binning scan over the depth-sorted Gaussian-views: each item carries two
-// counts, the tiles of its pixel box (instances) and the tile rows of that
+// counts, the tiles of its binning box (instances) and the tile rows of that
 // box; both are scanned at once (block sums hold the pair as two uint64).
 // A culled view (sorted key 0xffffffff, all at the end) counts nothing and
 // costs no gather; a kept one reads its box.
@@ -248,7 +248,7 @@ __device__ __forceinline__ void scan_item(const uint32_t *__restrict__ keys, con
 
 // Gathers each sorted item's two counts once (into `tiles` and `rows`, read
 // back by k_scan_apply, which scans them in place) and reduces them per block.
-// The gathered pixel box is also stored in depth order (`sorted_boxes`), so
+// The gathered binning box is also stored in depth order (`sorted_boxes`), so
 // the emission kernel reads it coalesced instead of gathering it again.
 template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__restrict__ keys,

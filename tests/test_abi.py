@@ -125,7 +125,8 @@ def test_workspace_layout(lib):
     assert lay.n_records == 2000 and lay.capacity == 5000
     assert lay.total_tiles == 9 * 5 + 3 * 3 and lay.tile_bits == 6
     assert lay.record_grads == 0
-    offs = [getattr(lay, k) for k in ("counters", "views", "records", "depth_keys", "boxes", "conics", "tile_counts",
+    offs = [getattr(lay, k) for k in ("counters", "views", "records", "depth_keys", "boxes", "bin_boxes", "conics",
+                                      "tile_counts",
                                       "order", "offsets", "inst_tiles", "inst_ids", "tile_ranges")]
     assert all(o % 256 == 0 for o in offs) and len(set(offs)) == len(offs)
     assert max(offs) < lay.total_bytes

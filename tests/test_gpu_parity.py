@@ -73,8 +73,8 @@ def _check_bands(buf, lay, sp, cam, opts, label):
 
 
 def _check_keys_boxes_counts(buf, lay, sp, n):
-    """Depth keys and order (kept views, sorted), pixel boxes and box tile
-    counts, bit-exact outside the oracle's hazard set."""
+    """Depth keys and order (kept views, sorted), pixel boxes, binning boxes
+    and their tile counts, bit-exact outside the oracle's hazard set."""
     kept, box_tiles = oracle_box_tiles(sp)
     n_kept = int(kept.sum())  # culled views sort last (key 0xffffffff)
     keys = read(buf, lay.depth_keys, n_kept, np.uint32)
@@ -84,11 +84,16 @@ def _check_keys_boxes_counts(buf, lay, sp, n):
     assert np.array_equal(order, want) and np.array_equal(keys, sp["depth_key"][want])
     boxes = read(buf, lay.boxes, 4 * n, np.uint16).reshape(n, 4)
     good = kept & (sp["hazard"] == 0)
+    bins = read(buf, lay.bin_boxes, 4 * n, np.uint16).reshape(n, 4)
     for f, col in (("px0", 0), ("px1", 1), ("py0", 2), ("py1", 3)):
         assert np.array_equal(boxes[good, col], sp[f][good])
+    for f, col in (("bx0", 0), ("bx1", 1), ("by0", 2), ("by1", 3)):
+        assert np.array_equal(bins[good, col], sp[f][good])
     counts = read(buf, lay.tile_counts, n, np.uint32)
     assert np.array_equal(counts[good], box_tiles[good])
-    say(f"  keys, order, boxes and tile counts of {n_kept} kept Gaussians bit-exact "
+    tighter = int(((sp["bx1"] - sp["bx0"] < sp["px1"] - sp["px0"]) | (sp["by1"] - sp["by0"] < sp["py1"] - sp["py0"]))[good].sum())
+    say(f"  keys, order, boxes, binning boxes ({tighter} tighter than the box) and tile counts of {n_kept} kept "
+        f"Gaussians bit-exact "
         f"({int((kept & ~good).sum())} hazard Gaussians excluded from boxes)")
 
 
@@ -127,6 +132,13 @@ def test_lists_are_consistent_with_gpu_counts_boxes_and_keys(r):
     keys = read(buf, lay.depth_keys, n_kept, np.uint32)
     order = read(buf, lay.order, n_kept, np.uint32).astype(np.int64)
     boxes = read(buf, lay.boxes, 4 * n, np.uint16).reshape(n, 4).astype(np.int64)
+    bins = read(buf, lay.bin_boxes, 4 * n, np.uint16).reshape(n, 4).astype(np.int64)
+    kept_ids = order
+    # the binning box lies in the pixel box, and the tile count is its tiles
+    assert np.all((bins[kept_ids, 0] >= boxes[kept_ids, 0]) & (bins[kept_ids, 1] <= boxes[kept_ids, 1]) &
+                  (bins[kept_ids, 2] >= boxes[kept_ids, 2]) & (bins[kept_ids, 3] <= boxes[kept_ids, 3]))
+    assert np.array_equal(counts[kept_ids], (bins[kept_ids, 1] // 8 - bins[kept_ids, 0] // 8 + 1) *
+                          (bins[kept_ids, 3] // 16 - bins[kept_ids, 2] // 16 + 1))
     assert np.all(counts[order] > 0)
     assert np.all(np.diff(keys.astype(np.int64)) >= 0)
     key_of = np.zeros(n, np.uint32)
@@ -138,10 +150,10 @@ def test_lists_are_consistent_with_gpu_counts_boxes_and_keys(r):
     assert np.all(tiles < lay.total_tiles)
     srt = np.lexsort((ids, key_of[ids], tiles))
     assert np.array_equal(srt, np.arange(len(ids)))
-    say(f"  {m} box instances, {len(ids)} listed")
+    say(f"  {m} binning-box instances, {len(ids)} listed")
     tx_n = -(-200 // 8)
     ty, tx = tiles // tx_n, tiles % tx_n
-    b = boxes[ids]
+    b = bins[ids]
     assert np.all((tx >= b[:, 0] // 8) & (tx <= b[:, 1] // 8) & (ty >= b[:, 2] // 16) & (ty <= b[:, 3] // 16))
     # 2 slots per 8x16 tile; a listed tile whose support meets only the gap
     # between the slots' pixel rows has no slot bit (rare)
@@ -271,7 +283,8 @@ def test_crossing_quads_are_clipped_to_the_frustum(r, mode):
     assert ok
     sp = oracle.preprocess(sc, cam, opts)
     C = oracle.CULL
-    crossing = (sp["all_front"] == 0) & (sp["whole"] == 0) & np.isin(sp["cull"], [0, C["offscreen"], C["notile"]])
+    crossing = (sp["all_front"] == 0) & (sp["whole"] == 0) & np.isin(sp["cull"], [0, C["offscreen"], C["notile"],
+                                                                                   C["nobin"]])
     clipped_away = crossing & (sp["cull"] == C["offscreen"])
     say(f"  {int(crossing.sum())} crossing quads, {int(clipped_away.sum())} wholly outside the view")
     assert crossing.sum() > 20 and clipped_away.sum() > 0
@@ -283,8 +296,11 @@ def test_crossing_quads_are_clipped_to_the_frustum(r, mode):
     assert np.array_equal(counts[good] == 0, ~np.isin(sp["cull"][good], [0, C["notile"]]))
     kept = (sp["cull"] == 0) & good
     boxes = read(buf, lay.boxes, 2 * n, np.uint32).reshape(n, 2)
+    bins = read(buf, lay.bin_boxes, 2 * n, np.uint32).reshape(n, 2)
     for f, col, sh in (("px0", 0, 0), ("px1", 0, 16), ("py0", 1, 0), ("py1", 1, 16)):
         assert np.array_equal((boxes[kept, col] >> sh) & 0xFFFF, sp[f][kept]), f
+    for f, col, sh in (("bx0", 0, 0), ("bx1", 0, 16), ("by0", 1, 0), ("by1", 1, 16)):
+        assert np.array_equal((bins[kept, col] >> sh) & 0xFFFF, sp[f][kept]), f
     assert m == oracle_box_tiles(sp)[1].sum()
     tiles, ids = instance_lists(buf, lay)
     ot, _, oi, bad = oracle_lists_without_hazards(sp, cam, opts)

@@ -204,6 +204,29 @@ def test_box_edge_on_a_pixel_centre_is_flagged():
             assert sp["px0"] == px0
 
 
+def test_binning_box_edge_on_a_pixel_centre_is_flagged():
+    """A binning-box edge (the pixels of the box whose centres lie in the
+    support ellipse's bounding box) within rounding of a pixel centre is
+    flagged; moved 1e-6 px off it, it is not, and the binning box takes or
+    leaves that pixel column by the pixel-centre rule."""
+    cam = _cam(40, 40, 60.0)
+    sc = _scene([[0.0, 0.0, 4.0]], [[0.3, 0.1, 0.1]], [0.8], [[0.5, 0.5, 0.5]])
+    c, h = math.cos(math.pi / 8), math.sin(math.pi / 8)  # 45 degrees about the optical axis
+    sc["quats"][:, 0] = [c, 0.0, 0.0, h]
+    sp0 = oracle.preprocess(sc, cam, OPTS)[0]
+    umin = sp0["ebox"][0]
+    assert umin > sp0["bbox"][0] + 1.0  # the quad's box is wider than the ellipse's
+    target = math.floor(umin - 0.5) + 0.5
+    col = int(round(target - 0.5))
+    for shift, flagged, bx0 in ((0.0, True, None), (1e-6, False, col + 1), (-1e-6, False, col)):
+        c = dict(cam, cx=cam["cx"] + (target - umin) + shift)
+        sp = oracle.preprocess(sc, c, OPTS)[0]
+        assert abs(sp["ebox"][0] - (target + shift)) < 1e-9
+        assert bool(sp["hazard"] & oracle.HAZARD["rect"]) == flagged, shift
+        if bx0 is not None:
+            assert sp["bx0"] == bx0 and sp["px0"] < bx0
+
+
 def test_fragment_count_equals_pixel_centres_inside_projected_quads():
     """The fragment counter (pixel centres whose ray hits a Gaussian's 3D quad
     in front of the camera: what a rasteriser shades for the quad, Sec. 4)

@@ -499,6 +499,60 @@ def test_pixel_box_is_centres_inside_bbox(oracle_lib):
         assert inside.min() == r["px0"] and inside.max() == r["px1"]
 
 
+def _support_extent(r, cam, axis):
+    """Extent of the support D <= kappa along image axis `axis` (0: u, 1: v)
+    by the discriminant route: in homogeneous pixel coordinates the support is
+    p^T M p <= 0 with M = (c^2 - kappa) K^T Sinv K - (K^T Sinv mu)(K^T Sinv mu)^T
+    (Sinv inverted numerically, K: pixel -> ray); at an extreme value of one
+    coordinate the quadratic in the other has a double root, a quadratic
+    condition whose two roots are the extent (no centre or radius used)."""
+    Sinv = _sigma_inv(r["Rp"].reshape(3, 3), r["s"])
+    K = np.array([[1 / cam["fx"], 0, -cam["cx"] / cam["fx"]], [0, 1 / cam["fy"], -cam["cy"] / cam["fy"]], [0, 0, 1.0]])
+    a = K.T @ Sinv @ r["mu"]
+    M = (r["c2"] - r["kappa"]) * (K.T @ Sinv @ K) - np.outer(a, a)
+    i, j = (0, 1) if axis == 0 else (1, 0)
+    # row j of the quadratic in the other coordinate: M_jj t^2 + 2 (M_ij s + M_j2) t + (M_ii s^2 + 2 M_i2 s + M_22)
+    A2 = M[i, j] ** 2 - M[j, j] * M[i, i]
+    A1 = 2 * (M[i, j] * M[j, 2] - M[j, j] * M[i, 2])
+    A0 = M[j, 2] ** 2 - M[j, j] * M[2, 2]
+    roots = np.sort(np.roots([A2, A1, A0]).real)
+    return roots[0], roots[1]
+
+
+def test_binning_box_is_centres_inside_the_support_ellipse_box(oracle_lib):
+    """The binning box holds exactly the pixel-box pixels whose centres lie in
+    the support ellipse's bounding box; that box equals the extent of D <=
+    kappa found by an independent route; every support pixel lies in the
+    binning box, and a Gaussian whose box holds no such centre is culled
+    (nobin), with no support pixel."""
+    checked = 0
+    for seed in (18, 19):
+        sc = scenegen.tiny_scene(seed, 300, sh_degree=0, log_scale_mean=-2.5, log_scale_std=0.8)
+        cam = scenegen.pinhole(scenegen.look_at((0, 0, -3.5)), 96, 80, 70)
+        sp = oracle.preprocess(sc, cam, OPTS)
+        tighter = 0
+        for r in sp[(sp["cull"] == 0) & (sp["bounded"] == 1)]:
+            for axis, (k0, k1) in enumerate(((0, 1), (2, 3))):
+                lo, hi = _support_extent(r, cam, axis)
+                np.testing.assert_allclose([r["ebox"][k0], r["ebox"][k1]], [lo, hi], rtol=1e-9, atol=1e-9)
+            xs = np.arange(r["px0"], r["px1"] + 1)
+            ys = np.arange(r["py0"], r["py1"] + 1)
+            bx = xs[(xs + 0.5 >= r["ebox"][0]) & (xs + 0.5 <= r["ebox"][1])]
+            by = ys[(ys + 0.5 >= r["ebox"][2]) & (ys + 0.5 <= r["ebox"][3])]
+            assert (bx.min(), bx.max(), by.min(), by.max()) == (r["bx0"], r["bx1"], r["by0"], r["by1"])
+            assert (r["tx0"], r["tx1"], r["ty0"], r["ty1"]) == (r["bx0"] // 16, r["bx1"] // 16, r["by0"] // 16, r["by1"] // 16)
+            yy, xx = np.mgrid[r["py0"]:r["py1"] + 1, r["px0"]:r["px1"] + 1]
+            sup, _ = _support_mask(r, cam, xx + 0.5, yy + 0.5)
+            assert np.all((xx[sup] >= r["bx0"]) & (xx[sup] <= r["bx1"]) & (yy[sup] >= r["by0"]) & (yy[sup] <= r["by1"]))
+            tighter += (r["bx1"] - r["bx0"] < r["px1"] - r["px0"]) or (r["by1"] - r["by0"] < r["py1"] - r["py0"])
+            checked += 1
+        assert tighter > 20
+        for r in sp[sp["cull"] == oracle.CULL["nobin"]]:
+            yy, xx = np.mgrid[r["py0"]:r["py1"] + 1, r["px0"]:r["px1"] + 1]
+            assert not _support_mask(r, cam, xx + 0.5, yy + 0.5)[0].any()
+    assert checked > 200
+
+
 # --------------------------------------------------------------------- culls
 def test_culls_and_degenerate_inputs(oracle_lib):
     cam = _ident_cam()
