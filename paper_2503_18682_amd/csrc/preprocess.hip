@@ -45,7 +45,7 @@ __device__ void write_exact_mip_record(float4 *rec, const double mu[3], const do
     rec[0] = make_float4(u_hi, v_hi, __uint_as_float(lo_bits), __uint_as_float(rows));
     rec[1] = make_float4((float)P0[0], (float)P0[1], (float)P0[2], (float)e);
     rec[2] = make_float4((float)P1[0], (float)P1[1], (float)P1[2], (float)log2o);
-    // the fourth floats of rows 3..5 hold the colour (written by the colour phase)
+    // the fourth floats of rows 3..5 hold the colour (written by colour_view)
     float *f = reinterpret_cast<float *>(rec);
     for (int k = 0; k < 3; ++k) {
         f[12 + k] = (float)Q0[k];
@@ -81,38 +81,49 @@ __device__ inline Centre projected_centre(const double mu[3], const DevView &V)
 // own code (fewer registers and instructions in the common ray-based one).
 enum PrepMode { kPrepRay = 0, kPrepMipApprox = 1, kPrepMipExact = 2, kPrepGS = 3 };
 
-// View-dependent colour of Gaussian i in every view, max(0, SH(direction
-// camera centre -> mean) + 1/2), written into the record's colour floats
-// (also of views where the Gaussian is culled).  Returns whether every
-// coefficient is finite (if not, the Gaussian is culled in every view).
-// Run by the preprocess thread before its geometry: the coefficients' loads
-// are the HBM-bound part of the kernel and the geometry the FP64-bound one,
-// and the waves of a SIMD are in either phase at any time, so the two
-// overlap; the coefficient registers are dead before the geometry starts.
+// View-dependent colour, max(0, SH(direction camera centre -> mean) + 1/2),
+// in two steps.  sh_load keeps Gaussian i's coefficients in the block's LDS
+// (coefficient k of thread t at lds[k][t]: each thread only touches its own
+// column, and consecutive threads hit consecutive banks) and returns whether
+// they are all finite (if not, the Gaussian is culled in every view).
+// colour_view then evaluates one view's colour from them into the record's
+// colour floats next to the geometry of that view, which writes the rest of
+// the record: the two partial writes of a record line follow each other
+// closely and merge in L2.  Views that end up culled mostly cost no colour
+// (see the view loop of k_preprocess).  The
+// coefficients are read from HBM once per batch; they are not held in
+// registers across the FP64 geometry, which keeps its occupancy.
 template <int DEG>
-__device__ __forceinline__ bool colour_phase(const float *__restrict__ sh, int n, int i, const double (&m)[3],
-                                             const DevView *__restrict__ views, int n_views,
-                                             float *__restrict__ records, int rec_floats, ColourSlot slot)
+__device__ __forceinline__ bool sh_load(const float *__restrict__ sh, int n, int i, float (*lds)[256])
 {
     constexpr int NK = (DEG + 1) * (DEG + 1);
-    float c[NK * 3];
     bool sh_ok = true;
 #pragma unroll
     for (int k = 0; k < NK * 3; ++k) {
-        c[k] = sh[(size_t)k * n + i];
-        sh_ok = sh_ok && isfinite(c[k]);
-    }
-    for (int v = 0; v < n_views; ++v) {
-        float dir[3], Y[NK], col[3];
-        double dist;
-        view_dir(m, views[v].centre, dir, &dist);
-        sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
-        sh_colour<DEG>(Y, c, col);
-        float *rc = records + ((size_t)v * n + i) * rec_floats + slot.first;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) rc[k * slot.step] = fmaxf(col[k], 0.0f);
+        const float c = sh[(size_t)k * n + i];
+        lds[k][threadIdx.x] = c;
+        sh_ok = sh_ok && isfinite(c);
     }
     return sh_ok;
+}
+
+template <int DEG>
+__device__ __forceinline__ void colour_view(const float (*lds)[256], const double (&m)[3], const DevView &V,
+                                            float *__restrict__ rc, ColourSlot slot)
+{
+    constexpr int NK = (DEG + 1) * (DEG + 1);
+    float c[NK * 3], dir[3], Y[NK], col[3];
+#pragma unroll
+    for (int k = 0; k < NK * 3; ++k) c[k] = lds[k][threadIdx.x];
+    double dist;
+    view_dir(m, V.centre, dir, &dist);
+    sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
+    sh_colour<DEG>(Y, c, col);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) rc[k * slot.step] = fmaxf(col[k], 0.0f);
+    // keep the scheduler from interleaving this with the view's geometry:
+    // the colour's temporaries then die before the FP64 registers are needed
+    __builtin_amdgcn_sched_barrier(0);
 }
 
 template <int MODE, int DEG>
@@ -132,10 +143,11 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
 
+    __shared__ float sh_lds[(DEG + 1) * (DEG + 1) * 3][256];
     const double m[3] = {means[i], means[n + i], means[2 * n + i]};
-    const bool sh_ok = colour_phase<DEG>(sh, n, i, m, views, n_views, reinterpret_cast<float *>(records),
-                                         MODE == kPrepMipExact ? kRecordFloatsExactMip : kRecordFloats,
-                                         colour_slot(MODE == kPrepMipExact ? 2 : 0));
+    const bool sh_ok = sh_load<DEG>(sh, n, i, sh_lds);
+    constexpr int rec_floats = MODE == kPrepMipExact ? kRecordFloatsExactMip : kRecordFloats;
+    constexpr ColourSlot slot = colour_slot(MODE == kPrepMipExact ? 2 : 0);
     const float lf[3] = {log_scales[i], log_scales[n + i], log_scales[2 * n + i]};
     const float qf[4] = {quats[i], quats[n + i], quats[2 * n + i], quats[3 * n + i]};
     const float af = opacity_logits[i];
@@ -182,6 +194,18 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
         const double mu[3] = {W[0] * m[0] + W[1] * m[1] + W[2] * m[2] + W[3],
                               W[4] * m[0] + W[5] * m[1] + W[6] * m[2] + W[7],
                               W[8] * m[0] + W[9] * m[1] + W[10] * m[2] + W[11]};
+        float *const rc = reinterpret_cast<float *>(records) + idx * rec_floats + slot.first;
+        // A view whose centre projects inside the image is almost always
+        // kept: its colour is evaluated before the geometry (the scheduler
+        // then overlaps it best); any other kept view gets it afterwards.
+        bool coloured = false;
+        if (ok && mu[2] > opt.near_z) {
+            const double ux = V.fx * mu[0] + V.cx * mu[2], vy = V.fy * mu[1] + V.cy * mu[2];
+            if (ux >= 0.0 && ux <= V.width * mu[2] && vy >= 0.0 && vy <= V.height * mu[2]) {
+                colour_view<DEG>(sh_lds, m, V, rc, slot);
+                coloured = true;
+            }
+        }
         do {
             if (!ok || !(mu[2] > opt.near_z)) break;
             double Rp[9];  // R_p = W_rot R
@@ -237,7 +261,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                                      __uint_as_float((uint32_t)py0 | ((uint32_t)py1 << 16)));
                 rec[1] = make_float4((float)G00, (float)G01, 0.0f, (float)G11);
                 rec[2] = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
-                reinterpret_cast<float *>(rec)[12] = log2o;  // floats 13..15: the colour phase's
+                reinterpret_cast<float *>(rec)[12] = log2o;  // floats 13..15: colour_view's
                 conics[idx] = Conic{A00, A01, A11, 0.0, 0.0, kappa, pc.u, pc.v};
                 break;
             }
@@ -477,9 +501,11 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ me
                 rec[0] = make_float4(pc.u_hi, pc.v_hi, __uint_as_float(pc.lo_bits), __uint_as_float(rows));
                 rec[1] = make_float4((float)G[0][0], (float)G[0][1], (float)G[1][0], (float)G[1][1]);
                 rec[2] = make_float4((float)gx, (float)gy, (float)k0, (float)ic2);
-                reinterpret_cast<float *>(rec)[12] = log2o;  // floats 13..15: the colour phase's
+                reinterpret_cast<float *>(rec)[12] = log2o;  // floats 13..15: colour_view's
             }
         } while (false);
+        // culled views' records are never read
+        if (cnt && !coloured) colour_view<DEG>(sh_lds, m, V, rc, slot);
         depth_keys[idx] = cnt ? key : 0xffffffffu;
         tile_counts[idx] = cnt;
         boxes[idx] = box;
