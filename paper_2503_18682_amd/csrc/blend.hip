@@ -184,6 +184,25 @@ struct PlainModel {
     {
         fetch_record(r, records, inst, n_records, bands_in_rows);
     }
+    // the same in two steps: loads with no branch (the id clamped into the
+    // record array, n_records >= 1), then what fetch decides by branching
+    __device__ static void load_raw(float4 (&r)[kRaw], const float4 *__restrict__ records, uint32_t inst,
+                                    uint32_t n_records)
+    {
+        const float4 *src = records + (size_t)min(inst & kIdMask, n_records - 1u) * kRaw;
+#pragma unroll
+        for (int c = 0; c < kRaw; ++c) r[c] = src[c];
+    }
+    __device__ static void settle(float4 (&r)[kRaw], uint32_t inst, uint32_t n_records, bool bands_in_rows)
+    {
+        if ((inst & kIdMask) >= n_records) {
+            r[0] = make_float4(0.f, 0.f, 0.f, __uint_as_float(1u));
+            r[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            r[2] = make_float4(0.f, 0.f, -1.f, 0.f);
+            r[3] = make_float4(-126.f, 0.f, 0.f, 0.f);
+        }
+        if (bands_in_rows) r[0].w = __uint_as_float(inst >> kIdBits);
+    }
     __device__ static void stage(float4 *dst, const float4 (&r)[kRaw], float x0, float y0, float log2_pmin)
     {
         put_test_form(dst, r, x0, y0, log2_pmin);
@@ -256,6 +275,26 @@ struct ExactMipModel {
             for (int c = 0; c < kRaw; ++c) r[c] = src[c];
         } else {
             // rows [1, 0]: empty; a ray in front with omega = 2^-126
+            r[0] = make_float4(0.f, 0.f, 0.f, __uint_as_float(1u));
+            r[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            r[2] = make_float4(0.f, 0.f, 0.f, -126.f);
+            r[3] = make_float4(0.f, 0.f, 0.f, 0.f);
+            r[4] = make_float4(0.f, 0.f, 0.f, 0.f);
+            r[5] = make_float4(0.f, 0.f, 1.f, 0.f);
+            r[6] = make_float4(1.f, 1.f, 1.f, 0.f);
+        }
+        if (bands_in_rows) r[0].w = __uint_as_float(inst >> kIdBits);
+    }
+    __device__ static void load_raw(float4 (&r)[kRaw], const float4 *__restrict__ records, uint32_t inst,
+                                    uint32_t n_records)
+    {
+        const float4 *src = records + (size_t)min(inst & kIdMask, n_records - 1u) * kRaw;
+#pragma unroll
+        for (int c = 0; c < kRaw; ++c) r[c] = src[c];
+    }
+    __device__ static void settle(float4 (&r)[kRaw], uint32_t inst, uint32_t n_records, bool bands_in_rows)
+    {
+        if ((inst & kIdMask) >= n_records) {
             r[0] = make_float4(0.f, 0.f, 0.f, __uint_as_float(1u));
             r[1] = make_float4(0.f, 0.f, 0.f, 0.f);
             r[2] = make_float4(0.f, 0.f, 0.f, -126.f);
@@ -416,24 +455,26 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
             if (__ballot(on) != 0) live |= 1u << k;
         }
         bool wave_live = live != 0u;
-        // batch 0 goes straight to LDS; batch b+1 is fetched into registers
-        // while batch b is composited
+        // Batch 0 goes straight to LDS.  While batch b is composited, the
+        // raw records of batch b + 1 and the ids of batch b + 2 are in
+        // flight: their loads carry no branch (indices clamped into the
+        // list, ids into the record array), so the wait for them falls after
+        // the batch, where they are converted and staged.
+        if (rg.x < rg.y) {
         if (rg.x + lane < rg.y) {
             const uint32_t inst = inst_ids[rg.x + lane];
             float4 r[M::kRaw];
             M::fetch(r, records, inst, P.n_records, PPL <= 4);
             M::stage(s_rec[wave][lane], r, x0, y0, P.log2_pmin);
         }
+        uint32_t nid = inst_ids[min(rg.x + 64 + lane, rg.y - 1u)];
         for (uint32_t base = rg.x; base < rg.y && wave_live; base += 64) {
             const uint32_t nb = min(64u, rg.y - base);
-            const uint32_t next = base + 64 + lane;
-            const bool have_next = next < rg.y;
-            float4 pre[M::kStaged];
-            if (have_next) {
-                float4 r[M::kRaw];
-                M::fetch(r, records, inst_ids[next], P.n_records, PPL <= 4);
-                M::stage(pre, r, x0, y0, P.log2_pmin);
-            }
+            const bool have_next = base + 64 + lane < rg.y;
+            const uint32_t cid = nid;
+            float4 raw[M::kRaw];
+            M::load_raw(raw, records, cid, P.n_records);
+            nid = inst_ids[min(base + 128 + lane, rg.y - 1u)];
             lds_wave_sync();
             for (uint32_t j = 0; j < nb; ++j) {
                 const typename M::Rec R = M::load(s_rec[wave][j]);
@@ -476,9 +517,10 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
             }
             lds_wave_sync();
             if (have_next) {
-#pragma unroll
-                for (int c = 0; c < M::kStaged; ++c) s_rec[wave][lane][c] = pre[c];
+                M::settle(raw, cid, P.n_records, PPL <= 4);
+                M::stage(s_rec[wave][lane], raw, x0, y0, P.log2_pmin);
             }
+        }
         }
         const size_t plane = (size_t)V.width * V.height;
 #pragma unroll
@@ -618,8 +660,12 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
         for (int d = 32; d >= 1; d >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, d, 64));
         const uint2 rg = ranges[tile];
         maxlast = min(maxlast, (int)(rg.y - rg.x));
-        // the last batch of the walked part of the list goes straight to LDS;
-        // each earlier batch is fetched into registers while one is walked back
+        // The last batch of the walked part of the list goes straight to LDS.
+        // While a batch is walked back, the raw records of the batch before
+        // it and the ids of the one before that are in flight, with no branch
+        // around their loads (indices clamped into the list, ids into the
+        // record array), so the wait for them falls after the batch.
+        uint32_t nid = 0u;
         if (maxlast > 0) {
             const int lo = maxlast > 64 ? maxlast - 64 : 0;
             if (lane < maxlast - lo) {
@@ -630,22 +676,19 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
                 fetch_record(r, records, v, P.n_records, PPL <= 4);
                 put_test_form(s_rec[wave][lane], r, x0, y0, P.log2_pmin);
             }
+            const int nlo = lo > 64 ? lo - 64 : 0;
+            nid = inst_ids[rg.x + min(nlo + lane, maxlast - 1)];
         }
         for (int hi = maxlast; hi > 0; hi -= 64) {
             const int lo = hi > 64 ? hi - 64 : 0;
             const int nb = hi - lo;
             const int nlo = lo > 64 ? lo - 64 : 0;
             const bool have_next = lane < lo - nlo;
-            float4 pre[4];
-            uint32_t pre_id = 0xffffffffu;
-            if (have_next) {
-                const uint32_t v = inst_ids[rg.x + nlo + lane];
-                const uint32_t id = v & kIdMask;
-                pre_id = id < P.n_records ? id : 0xffffffffu;
-                float4 r[4];
-                fetch_record(r, records, v, P.n_records, PPL <= 4);
-                put_test_form(pre, r, x0, y0, P.log2_pmin);
-            }
+            const uint32_t cid = nid;
+            float4 raw[4];
+            PlainModel::load_raw(raw, records, cid, P.n_records);
+            const int nnlo = nlo > 64 ? nlo - 64 : 0;
+            nid = inst_ids[rg.x + min(nnlo + lane, maxlast - 1)];
             lds_wave_sync();
             for (int jj = nb - 1; jj >= 0; --jj) {
                 const int j = lo + jj;
@@ -740,9 +783,10 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint2 *__restrict__ ran
             }
             lds_wave_sync();
             if (have_next) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) s_rec[wave][lane][c] = pre[c];
-                s_id[wave][lane] = pre_id;
+                PlainModel::settle(raw, cid, P.n_records, PPL <= 4);
+                put_test_form(s_rec[wave][lane], raw, x0, y0, P.log2_pmin);
+                const uint32_t id = cid & kIdMask;
+                s_id[wave][lane] = id < P.n_records ? id : 0xffffffffu;
             }
         }
     }
