@@ -90,9 +90,9 @@ enum PrepMode { kPrepRay = 0, kPrepMipApprox = 1, kPrepMipExact = 2, kPrepGS = 3
 // colour floats next to the geometry of that view, which writes the rest of
 // the record: the two partial writes of a record line follow each other
 // closely and merge in L2.  Views that end up culled mostly cost no colour
-// (see the view loop of k_preprocess).  The
-// coefficients are read from HBM once per batch; they are not held in
-// registers across the FP64 geometry, which keeps its occupancy.
+// (see the view loop of k_preprocess).  The coefficients are read from HBM
+// once per batch; they are not held in registers across the FP64 geometry,
+// which keeps its occupancy.
 template <int DEG>
 __device__ __forceinline__ bool sh_load(const float *__restrict__ sh, int n, int i, float (*lds)[256])
 {
