@@ -235,6 +235,11 @@ def test_edge_cases(r, mode):
         "quad_crossing_camera_plane": _mk([[0.3, 0.1, 0.6], [0, 0, 2.0]], [[0.05, 0.5, 0.05], [0.2] * 3], [0.8, 0.6],
                                           [[1, 0, 0], [0, 1, 0]], quats=[[0.9, 0.3, 0.2, 0.1], [1, 0, 0, 0]]),
         "offscreen": _mk([[30.0, 0.0, 2.0]], [[0.1] * 3], [0.9], [[1, 1, 1]]),
+        # centres outside the image whose supports reach into it (their
+        # colour is evaluated after the geometry, the others' before it)
+        "centre_outside_support_inside": _mk([[2.5, 0.0, 2.0], [-0.2, -2.3, 2.0], [0.1, 0.0, 2.2]],
+                                             [[0.5, 0.4, 0.3], [0.3, 0.6, 0.4], [0.2] * 3], [0.8, 0.7, 0.6],
+                                             [[0.9, 0.2, 0.1], [0.1, 0.8, 0.3], [0.2, 0.3, 0.9]]),
     }
     bad = _mk([[0.0, 0.0, 2.0], [0.1, 0.0, 2.5], [0.0, 0.1, 3.0], [-0.1, -0.05, 2.2]], [[0.2] * 3] * 4, [0.7] * 4,
               [[1, 0, 0]] * 4)
