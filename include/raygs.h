@@ -184,7 +184,7 @@ rgs_status rgs_render(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera
  * created and kept until the process ends); the call allocates nothing, on
  * the device or the host.  The frame is laid out in the scratch with the
  * largest instance capacity that fits.  A frame that does not fit with room
- * for a single instance (about 175 bytes per Gaussian-view plus a few MiB)
+ * for a single instance (about 180 bytes per Gaussian-view plus a few MiB)
  * is rejected with RGS_EINVAL and a message giving both sizes.  tile_w =
  * tile_h = 0 means 8x16 here (the autotuned shapes are not consulted).
  * instances_needed (device, 8-byte aligned, may be NULL) receives, in stream
