@@ -519,17 +519,21 @@ def _support_extent(r, cam, axis):
     return roots[0], roots[1]
 
 
-def test_binning_box_is_centres_inside_the_support_ellipse_box(oracle_lib):
+@pytest.mark.parametrize("mip", [0, 1, 2])
+def test_binning_box_is_centres_inside_the_support_ellipse_box(oracle_lib, mip):
     """The binning box holds exactly the pixel-box pixels whose centres lie in
     the support ellipse's bounding box; that box equals the extent of D <=
     kappa found by an independent route; every support pixel lies in the
     binning box, and a Gaussian whose box holds no such centre is culled
-    (nobin), with no support pixel."""
+    (nobin), with no support pixel.  With eq. (17) the ellipse is the widened
+    Gaussian's, with the exact MIP the bounding Gaussian's (the splat's s,
+    kappa and c2 are those)."""
+    opts = dict(OPTS, mip=mip, mip_sigma2_px=1.0)
     checked = 0
     for seed in (18, 19):
         sc = scenegen.tiny_scene(seed, 300, sh_degree=0, log_scale_mean=-2.5, log_scale_std=0.8)
         cam = scenegen.pinhole(scenegen.look_at((0, 0, -3.5)), 96, 80, 70)
-        sp = oracle.preprocess(sc, cam, OPTS)
+        sp = oracle.preprocess(sc, cam, opts)
         tighter = 0
         for r in sp[(sp["cull"] == 0) & (sp["bounded"] == 1)]:
             for axis, (k0, k1) in enumerate(((0, 1), (2, 3))):
@@ -542,14 +546,15 @@ def test_binning_box_is_centres_inside_the_support_ellipse_box(oracle_lib):
             assert (bx.min(), bx.max(), by.min(), by.max()) == (r["bx0"], r["bx1"], r["by0"], r["by1"])
             assert (r["tx0"], r["tx1"], r["ty0"], r["ty1"]) == (r["bx0"] // 16, r["bx1"] // 16, r["by0"] // 16, r["by1"] // 16)
             yy, xx = np.mgrid[r["py0"]:r["py1"] + 1, r["px0"]:r["px1"] + 1]
-            sup, _ = _support_mask(r, cam, xx + 0.5, yy + 0.5)
+            sup = _support_mask(r, cam, xx + 0.5, yy + 0.5)[0] if mip == 0 else \
+                (_support_mask(r, cam, xx + 0.5, yy + 0.5)[1] <= r["kappa"])
             assert np.all((xx[sup] >= r["bx0"]) & (xx[sup] <= r["bx1"]) & (yy[sup] >= r["by0"]) & (yy[sup] <= r["by1"]))
             tighter += (r["bx1"] - r["bx0"] < r["px1"] - r["px0"]) or (r["by1"] - r["by0"] < r["py1"] - r["py0"])
             checked += 1
         assert tighter > 20
         for r in sp[sp["cull"] == oracle.CULL["nobin"]]:
             yy, xx = np.mgrid[r["py0"]:r["py1"] + 1, r["px0"]:r["px1"] + 1]
-            assert not _support_mask(r, cam, xx + 0.5, yy + 0.5)[0].any()
+            assert not (_support_mask(r, cam, xx + 0.5, yy + 0.5)[1] <= r["kappa"]).any()
     assert checked > 200
 
 
