@@ -489,17 +489,20 @@ __global__ __launch_bounds__(256) void k_blend(const uint2 *__restrict__ ranges,
                     const bool hit = M::test(R, pxr[k], pyr[k], aux[k], P.log2_pmin, f);
                     if (__ballot(hit) == 0) continue;
                     // omega >= 0 and alpha_max > 0: the float minimum is the
-                    // minimum of the bit patterns
-                    const float a = __uint_as_float(min(__float_as_uint(M::omega(R, f)), amax_bits));
+                    // minimum of the bit patterns.  A lane without a hit takes
+                    // alpha = 0, which leaves T and C as they are; since T >=
+                    // t_eps holds for every pixel (a stopped one keeps the T
+                    // from before its stop), only a hit can stop a pixel.
+                    const float w = M::omega(R, f);
+                    const float a = hit ? __uint_as_float(min(__float_as_uint(w), amax_bits)) : 0.0f;
                     const float ta = T[k] * a;
                     const float Tn = T[k] - ta;
-                    const bool stop = hit & (Tn < P.t_eps);
-                    const bool take = hit & !stop;
-                    const float wt = take ? ta : 0.0f;
+                    const bool stop = Tn < P.t_eps;
+                    const float wt = stop ? 0.0f : ta;
                     C0[k] = __builtin_fmaf(wt, R.r, C0[k]);
                     C1[k] = __builtin_fmaf(wt, R.g, C1[k]);
                     C2[k] = __builtin_fmaf(wt, R.b, C2[k]);
-                    T[k] = take ? Tn : T[k];
+                    T[k] = stop ? T[k] : Tn;
                     if (__ballot(stop) != 0) {
                         // some pixel of the slot stops before this entry: it has
                         // consumed the entries before it, and it is done (a NaN
