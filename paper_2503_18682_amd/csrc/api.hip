@@ -146,6 +146,30 @@ struct rgs_plan {
 
 namespace {
 
+// A small host block (the workspace header: counters and view table) goes to
+// the device as the argument of a one-block kernel rather than through a
+// host-to-device copy, whose staging and copy kernel take longer per frame.
+// Larger blocks, and sizes that are not whole words, are copied.
+constexpr size_t kArgBlockBytes = 3072;
+struct ArgBlock {
+    uint32_t w[kArgBlockBytes / 4];
+};
+
+__global__ __launch_bounds__(256) void k_put_words(uint32_t *__restrict__ dst, ArgBlock b, int n_words)
+{
+    for (int i = threadIdx.x; i < n_words; i += 256) dst[i] = b.w[i];
+}
+
+hipError_t put_bytes(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    if (bytes > kArgBlockBytes || bytes % 4 != 0 || reinterpret_cast<uintptr_t>(dst) % 4 != 0)
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    ArgBlock b;
+    std::memcpy(b.w, src, bytes);
+    k_put_words<<<1, 256, 0, s>>>(static_cast<uint32_t *>(dst), b, (int)(bytes / 4));
+    return hipGetLastError();
+}
+
 rgs_status fail(rgs_context *ctx, rgs_status st, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
 rgs_status fail(rgs_context *ctx, rgs_status st, const char *fmt, ...)
 {
@@ -688,7 +712,7 @@ rgs_status rgs_render(rgs_context *ctx, const rgs_gaussians *g, const rgs_camera
     hipStream_t s = static_cast<hipStream_t>(stream);
     RGS_HIP(ctx, hipSetDevice(ctx->device));
     const std::vector<unsigned char> hdr = build_header(L, cams, n_views, outs, nullptr);
-    RGS_HIP(ctx, hipMemcpyAsync(ws->ptr, hdr.data(), hdr.size(), hipMemcpyHostToDevice, s));
+    RGS_HIP(ctx, put_bytes(ws->ptr, hdr.data(), hdr.size(), s));
     st = enqueue_forward(ctx, *g, n_views, *opts, L, ws->ptr, s, true, ctx->view_stamps);
     if (st == RGS_OK) ctx->ws_frames[ws->ptr] = frame_shape(*opts, g->n, n_views, *ws);
     if (st == RGS_OK && ctx->timing) ++ctx->frames;  // frames whose stages were timed
@@ -914,7 +938,7 @@ rgs_status rgs_batch_launch(rgs_plan *p, const rgs_gaussians *g, const rgs_camer
         p->outs.assign(outs, outs + nv);
     }
     const std::vector<unsigned char> hdr = build_header(L, cams, nv, outs, nullptr);
-    RGS_HIP(ctx, hipMemcpyAsync(ws->ptr, hdr.data(), hdr.size(), hipMemcpyHostToDevice, s));
+    RGS_HIP(ctx, put_bytes(ws->ptr, hdr.data(), hdr.size(), s));
     RGS_HIP(ctx, hipGraphLaunch(p->exec, s));
     p->last_stream = s;
     p->launched = true;
