@@ -548,6 +548,27 @@ def test_batched_views_match_single_views_and_oracle(r):
         assert_image_close(outs[v]["rgb"], outs[v]["final_T"], oracle.render(sc, cam, opts), label=f"batch view {v}")
 
 
+@pytest.mark.parametrize("n_views", [12, 14])
+def test_many_view_batches_match_single_views(r, n_views):
+    """A batch whose workspace header (counters and a 224-byte entry per
+    view) goes to the device as kernel arguments (12 views) or by a copy (14
+    views) renders every view as a single-view render does, bit for bit."""
+    sc = scenegen.tiny_scene(34, 1500, sh_degree=1, half_extent=1.5, log_scale_mean=-3.0, log_scale_std=0.5)
+    rng = np.random.default_rng(35)
+    cams = [scenegen.pinhole(scenegen.look_at((rng.uniform(-2, 2), rng.uniform(-1, 1), -4.0)),
+                             int(rng.integers(24, 72)), int(rng.integers(24, 72)), 55) for _ in range(n_views)]
+    opts = scenegen.default_options()
+    say(f"case batch of {n_views} small views")
+    outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, cams, opts)
+    assert ok
+    header = lay.views + 224 * n_views
+    assert (header <= 3072) == (n_views == 12), header
+    for v, cam in enumerate(cams):
+        single = render_with_ws(r, sc, [cam], opts)[0][0]
+        assert np.array_equal(outs[v]["rgb"], single["rgb"]), v
+        assert np.array_equal(outs[v]["n_contrib"], single["n_contrib"]), v
+
+
 def test_graph_plan_replays_match_eager(r):
     from paper_2503_18682_amd import renderer as R
 
