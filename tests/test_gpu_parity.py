@@ -266,6 +266,28 @@ def test_edge_cases(r, mode):
     assert np.allclose(render_with_ws(r, cases["empty"], [cam], opts)[0][0]["rgb"][2], 0.3)
 
 
+@pytest.mark.parametrize("t_eps", [0.0, 0.5, 0.99999999])
+def test_termination_threshold_extremes(r, t_eps):
+    """Early termination (eq. 1) at the ends of its range: never (t_eps 0),
+    after about half the light is absorbed, and at the first composited
+    Gaussian (0.99999999, which is 1 in FP32: no pixel takes a colour), in
+    every compositing mode, against the oracle.  A pixel's transmittance
+    never falls below t_eps before it stops, so a Gaussian that misses the
+    pixel cannot stop it."""
+    sc = scenegen.tiny_scene(36, 2000, sh_degree=1, half_extent=1.2, log_scale_mean=-2.6, log_scale_std=0.5,
+                             logit_std=2.0)
+    cam = scenegen.pinhole(scenegen.look_at((0.3, 0.2, -3.5)), 96, 80, 60)
+    for mode in (dict(), dict(mip=1), dict(mip=2, mip_sigma2_px=1.0)):
+        opts = scenegen.default_options(t_eps=t_eps, background=(0.2, 0.1, 0.3), **mode)
+        say(f"case t_eps {t_eps} {mode}")
+        outs, buf, ws, lay, (ok, m) = render_with_ws(r, sc, [cam], opts)
+        assert ok
+        assert_image_close(outs[0]["rgb"], outs[0]["final_T"], oracle.render(sc, cam, opts),
+                           label=f"t_eps {t_eps} {mode}")
+        if t_eps > 0.9:
+            assert np.all(outs[0]["final_T"] == 1.0)
+
+
 def _crossing_scene(seed, n):
     """Large Gaussians close to a camera at the origin: many quads cross the
     camera plane z = 0."""
