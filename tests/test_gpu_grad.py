@@ -56,6 +56,28 @@ def test_fd_subcase_l1(r):
     _compare(grads, ref, "fd-subcase")
 
 
+@pytest.mark.parametrize("extra", [dict(alpha_max=0.3), dict(p_min=0.05)], ids=["alpha_max_0.3", "p_min_0.05"])
+def test_clamp_and_support_threshold_extremes(r, extra):
+    """The FD subcase with most fragments clamped at alpha_max (which then
+    pass no gradient to omega), and with a support threshold p_min 13 times
+    the default (eqs. 2-3): image and gradients against the oracle."""
+    from paper_2503_18682_amd import _lib
+
+    scene, cam = scenegen.fd_subcase()
+    opts = scenegen.default_options(**extra)
+    say(f"case grad fd-subcase {extra}")
+    g = to_dev(scene)
+    outs, (buf, ws) = r.render(g, [cam], opts, flags=_lib.RGS_WS_BACKWARD, keep_workspace=True)
+    assert_image_close(outs[0]["rgb"].cpu().numpy(), outs[0]["final_T"].cpu().numpy(),
+                       oracle.render(scene, cam, opts), label=str(extra))
+    img = outs[0]["rgb"].cpu().numpy()
+    target = np.random.default_rng(4).uniform(0, 1, img.shape)
+    dl = _l1_grad(img, target, img.size).astype(np.float32)
+    grads = r.backward(g, [cam], outs, [torch.from_numpy(dl).cuda()], ws, opts)
+    ref = oracle.backward(scene, cam, opts, dl.astype(np.float64))
+    _compare(grads, ref, f"fd-subcase {extra}")
+
+
 def test_multi_view_sparse_pixels(r):
     """Two views in one batch; dL/dC nonzero on sampled pixels only."""
     from paper_2503_18682_amd import _lib
