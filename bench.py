@@ -12,8 +12,8 @@ The default (all) prints one JSON line with the three parts of the metric:
                 poses equally.
   c2            batched stereo views/s: 3M Gaussians, 4 stereo pairs (8 views,
                 2064x2208 per eye x {0.5,1,2} per pair), MIP on; a step renders
-                all 8 views in one graph replay (8 plain single-view renders
-                reported beside it).
+                all 8 views in one graph replay at 16x8 tiles (8 plain
+                single-view renders reported beside it).
   c3            backward ms/view: 1M Gaussians, 4 views at 1600x1060; a step is
                 forward + L1 loss gradient + backward, at the tile shape the
                 library's training autotuner picks (--no-autotune: --tile).
@@ -97,7 +97,9 @@ def parse():
                     help="c1: skip the 2 and 3 frames-in-flight timings (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-steps", type=int, default=32, help="frames of the per-stage timing pass")
-    ap.add_argument("--tile", default="8x16", help="tile shape WxH, each of 8, 16, 32")
+    ap.add_argument("--tile", default=None,
+                    help="tile shape WxH, each of 8, 16, 32 (default: 8x16 for c1, 16x8 for c2, the autotuner's "
+                         "for c3 and c4, 8x16 there with --no-autotune)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="c3, c4: use --tile instead of the training autotuner (for profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -105,8 +107,19 @@ def parse():
     return ap.parse_args()
 
 
-def tile_opts(args):
-    tw, th = (int(v) for v in args.tile.lower().split("x"))
+# Tile shape of each workload when --tile is not given, from sweeps of the
+# nine shapes on the benchmark itself: the 1080p frame is fastest at 8x16,
+# the stereo batch (views of 1-18 MP) at 16x8 (849 against 823 views/s at
+# 8x16).  The training workloads take the autotuner's shape.
+DEFAULT_TILE = {"c1": "8x16", "c2": "16x8"}
+
+
+def tile_of(args, workload):
+    return args.tile or DEFAULT_TILE.get(workload, "8x16")
+
+
+def tile_opts(args, workload):
+    tw, th = (int(v) for v in tile_of(args, workload).lower().split("x"))
     return dict(tile_w=tw, tile_h=th)
 
 
@@ -207,7 +220,7 @@ def bench_c1(args, torch):
     from paper_2503_18682_amd import renderer as R
 
     w = scenegen.make_workload("c1")
-    sc, cams, opts = w["scene"], w["cameras"], dict(w["options"], **tile_opts(args))
+    sc, cams, opts = w["scene"], w["cameras"], dict(w["options"], **tile_opts(args, "c1"))
     gs = args.divergence == "gs"
     if gs:
         opts["divergence"] = 1
@@ -264,7 +277,7 @@ def bench_c1(args, torch):
     fwd = {k: v for k, v in stages.items() if not k.endswith("backward")}
     work = frame_work(work_counts("c1_gs" if gs else "c1"), range(POSES))
     flops = (FLOP_PER_FRAGMENT * work[0] + FLOP_PER_CONTRIBUTION * work[1]) / POSES if work else None
-    tag = "c1_1080p_500k_" + args.tile + ("_gs" if gs else "")
+    tag = "c1_1080p_500k_" + tile_of(args, "c1") + ("_gs" if gs else "")
     roof = roofline_for("blend", fwd["blend"], flops=flops, traffic=pmc_traffic("blend", tag))
     # measured ceilings of this device (context for `peak`, which stays the published figure)
     calib = r.calibrate()
@@ -277,7 +290,7 @@ def bench_c1(args, torch):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "c1: 500k Gaussians (64 clusters, SH3), 1920x1080, 50deg FOV, 16 orbit poses"
                    + (" (linearised GS divergence)" if gs else ""),
-                   "n_gaussians": n, "width": 1920, "height": 1080, "tile": args.tile,
+                   "n_gaussians": n, "width": 1920, "height": 1080, "tile": tile_of(args, "c1"),
                    "frames_per_step": POSES, "step": "one frame at each of the 16 orbit poses",
                    "frames_in_flight": args.in_flight,
                    "launch": "eager" if args.eager else "hip_graph", "instance_capacity": capacity},
@@ -299,7 +312,7 @@ def bench_c2(args, torch):
     from paper_2503_18682_amd import renderer as R
 
     w = scenegen.make_workload("c2")
-    sc, cams, opts = w["scene"], w["cameras"], dict(w["options"], **tile_opts(args))
+    sc, cams, opts = w["scene"], w["cameras"], dict(w["options"], **tile_opts(args, "c2"))
     if args.mip == "exact":
         opts["mip"] = 2
     n = int(sc["opacity_logits"].shape[0])
@@ -343,11 +356,11 @@ def bench_c2(args, torch):
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "config": {"workload": "c2: 3M Gaussians, 4 stereo pairs (8 views), MIP on, one HIP-graph replay"
                    + (" (exact per-ray MIP)" if args.mip == "exact" else ""),
-                   "views": [[c["width"], c["height"]] for c in cams], "tile": args.tile,
+                   "views": [[c["width"], c["height"]] for c in cams], "tile": tile_of(args, "c2"),
                    "instance_capacity": capacity},
         "plain_launches_views_per_s": 8e3 / plain_ms,
         "roofline": roofline_for("blend", fwd["blend"], flops=flops,
-                                 traffic=pmc_traffic("blend", "c2_stereo_3m_8views_" + args.tile)),
+                                 traffic=pmc_traffic("blend", "c2_stereo_3m_8views_" + tile_of(args, "c2"))),
         "stages_ms": stages,
         "dominant_stage": max(fwd, key=fwd.get),
     }
@@ -362,7 +375,7 @@ def bench_c3(args, torch):
     from paper_2503_18682_amd import renderer as R
 
     w = scenegen.make_workload("c3")
-    sc, cams, opts = w["scene"], w["cameras"], dict(w["options"], **tile_opts(args))
+    sc, cams, opts = w["scene"], w["cameras"], dict(w["options"], **tile_opts(args, "c3"))
     if args.mip == "exact":
         opts["mip"] = 2
     n = int(sc["opacity_logits"].shape[0])
@@ -469,7 +482,7 @@ def bench_c4(args, torch):
     buf, ws = r.new_workspace(n, cams, int(need * 1.1) + 4096, _lib.RGS_WS_BACKWARD, fine)
     outs = r.allocate_outputs(cams)
     if args.no_autotune:
-        opts, tile_from = dict(opts0, **tile_opts(args)), "--tile"
+        opts, tile_from = dict(opts0, **tile_opts(args, "c4")), "--tile"
     else:
         r.render_into(g, cams, outs, ws, fine)
         dls = [torch.sign(o["rgb"] - t) / sum(t.numel() for t in targets) for o, t in zip(outs, targets)]
